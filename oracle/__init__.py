@@ -1,0 +1,10 @@
+"""CPU oracle for CG on the unscaled 5-point Laplacian (test infrastructure).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg use
+this package.  The GPU library never imports, links or executes it.
+"""
+from .oracle import (  # noqa: F401
+    MODE_CANONICAL, MODE_SEQUENTIAL, VARIANT_CLASSIC, VARIANT_PIPELINED,
+    OR_OK, OR_NOT_CONVERGED, OR_BREAKDOWN, OR_E_INVALID,
+    Order, csr, spmv, dot, cg, refine, lib_path,
+)

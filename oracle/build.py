@@ -1,0 +1,28 @@
+"""Builds the CPU oracle (test infrastructure) into oracle/libcg_oracle.so.
+
+Plain gcc, -O2 with floating-point contraction off and no fast-math, so that
+every arithmetic operation in cg_oracle.c is one correctly rounded IEEE
+operation.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cg_oracle.c")
+LIB = os.path.join(HERE, "libcg_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

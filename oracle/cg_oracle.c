@@ -1,0 +1,580 @@
+/*
+ * cg_oracle.c - CPU oracle for conjugate gradients on the 2D Laplace problem.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links, loads or calls this
+ * file; only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header or table with the GPU library.
+ *
+ * What it computes (paper: "Efficient FPGA Implementation of Conjugate Gradient
+ * Methods for Laplacian System using HLS", arXiv 1803.03797):
+ *   - the system A x = b of Section II: the Laplacian on an nx-by-ny interior
+ *     grid with zero Dirichlet boundary, discretised by the 5-point stencil
+ *     whose 3x3 form the paper prints in Section II-B (centre 4, the four
+ *     compass neighbours -1, corners 0).  A is used unscaled (no 1/h^2).
+ *   - A is ASSEMBLED EXPLICITLY as a CSR matrix (the paper applies it
+ *     matrix-free; the oracle deliberately does not).
+ *   - classic CG = Algorithm 1 (stdCG), with a general starting vector x0;
+ *   - the modified CG = Algorithm 2 (newCG, the pipelined CG of Ghysels and
+ *     Vanroose, unpreconditioned), with the sign/parenthesis readings listed
+ *     in the design notes: r <- r - alpha*q, w <- w - alpha*z,
+ *     alpha_i = 1 / (delta_i/gamma_i - beta_i/alpha_{i-1});
+ *   - FP32-inner / FP64-outer iterative refinement around classic CG.
+ *
+ * Unknown (i, j), 0 <= i < nx, 0 <= j < ny, has index k = j*nx + i.
+ * Build with -O2 -ffp-contract=off (no fast-math): every operation below is
+ * one correctly rounded IEEE binary64 (or binary32) operation, and fma() is
+ * the correctly rounded fused multiply-add of C99.
+ *
+ * Two summation/rounding "modes", both valid FP64 CG runs:
+ *   MODE_SEQUENTIAL  textbook: dot = sum over k ascending of a[k]*b[k]
+ *                    (product rounded, then added); axpy y + a*x rounded
+ *                    twice; CSR rows sorted by column.
+ *   MODE_CANONICAL   the documented arithmetic contract of the GPU library
+ *                    (written out again here from that contract, not shared):
+ *                    axpys are fma(a, x, y); CSR row entries are stored in the
+ *                    order centre, west, east, south, north so that the plain
+ *                    CSR loop evaluates (((4uC - uW) - uE) - uS) - uN;
+ *                    dots follow the tile / lane / butterfly order described
+ *                    at dot_canonical() below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 2, OR_BREAKDOWN = 3,
+       OR_E_INVALID = -1, OR_E_NOMEM = -2 };
+enum { MODE_SEQUENTIAL = 0, MODE_CANONICAL = 1 };
+enum { VARIANT_CLASSIC = 0, VARIANT_PIPELINED = 1 };
+
+/* Reduction order of the canonical mode (see dot_canonical). */
+typedef struct {
+  int32_t cols_per_lane; /* consecutive columns owned by one lane            */
+  int32_t lanes;         /* lanes per wavefront                              */
+  int32_t waves;         /* wavefronts stacked vertically in one tile        */
+  int32_t rows;          /* rows per wavefront strip                         */
+  int32_t threads2;      /* threads of the cross-tile sum (multiple of lanes) */
+} oracle_order;
+
+typedef struct {
+  int32_t status;
+  int32_t iterations;        /* x-updates (inner iterations for refinement) */
+  int32_t outer_iterations;  /* refinement only                             */
+  int32_t pad_;
+  double rel_res_recursive;  /* sqrt(gamma / (b,b)) at exit                  */
+  double rel_res_true;       /* ||b - A x|| / ||b|| recomputed at exit       */
+} oracle_result;
+
+/* Optional per-iteration records for the invariant tests.  Any pointer may be
+ * NULL.  gamma has room for max_hist entries; r, p, x have room for max_hist
+ * vectors of n entries each, entry m holding the vector after m updates. */
+typedef struct {
+  int32_t max_hist;
+  int32_t count;   /* out: entries written */
+  double* gamma;
+  double* r;
+  double* p;
+  double* x;
+} oracle_history;
+
+/* ------------------------------------------------------------------ CSR -- */
+
+int64_t oracle_csr_nnz(int32_t nx, int32_t ny) {
+  if (nx < 1 || ny < 1) return -1;
+  int64_t n = (int64_t)nx * ny;
+  /* every unknown has itself plus the in-range compass neighbours */
+  return n + 2 * (int64_t)(nx - 1) * ny + 2 * (int64_t)nx * (ny - 1);
+}
+
+/* Assemble A.  order 0: entries of a row sorted by column.  order 1: centre,
+ * west (i-1), east (i+1), south (j-1), north (j+1).  Returns nnz or <0. */
+int64_t oracle_csr_assemble(int32_t nx, int32_t ny, int32_t order,
+                            int64_t* row_ptr, int32_t* col, double* val) {
+  if (nx < 1 || ny < 1) return OR_E_INVALID;
+  int64_t e = 0;
+  for (int32_t j = 0; j < ny; ++j) {
+    for (int32_t i = 0; i < nx; ++i) {
+      int64_t k = (int64_t)j * nx + i;
+      row_ptr[k] = e;
+      if (order == 0) {
+        if (j > 0)      { col[e] = (int32_t)(k - nx); val[e++] = -1.0; }
+        if (i > 0)      { col[e] = (int32_t)(k - 1);  val[e++] = -1.0; }
+        col[e] = (int32_t)k; val[e++] = 4.0;
+        if (i < nx - 1) { col[e] = (int32_t)(k + 1);  val[e++] = -1.0; }
+        if (j < ny - 1) { col[e] = (int32_t)(k + nx); val[e++] = -1.0; }
+      } else {
+        col[e] = (int32_t)k; val[e++] = 4.0;
+        if (i > 0)      { col[e] = (int32_t)(k - 1);  val[e++] = -1.0; }
+        if (i < nx - 1) { col[e] = (int32_t)(k + 1);  val[e++] = -1.0; }
+        if (j > 0)      { col[e] = (int32_t)(k - nx); val[e++] = -1.0; }
+        if (j < ny - 1) { col[e] = (int32_t)(k + nx); val[e++] = -1.0; }
+      }
+    }
+  }
+  row_ptr[(int64_t)nx * ny] = e;
+  return e;
+}
+
+typedef struct {
+  int32_t nx, ny;
+  int64_t n;
+  int64_t* row_ptr;
+  int32_t* col;
+  double* val;
+  float* valf;
+} csr_t;
+
+static void csr_free(csr_t* A) {
+  free(A->row_ptr); free(A->col); free(A->val); free(A->valf);
+  memset(A, 0, sizeof(*A));
+}
+
+static int csr_build(csr_t* A, int32_t nx, int32_t ny, int32_t order, int want_float) {
+  memset(A, 0, sizeof(*A));
+  int64_t nnz = oracle_csr_nnz(nx, ny);
+  if (nnz < 0) return OR_E_INVALID;
+  A->nx = nx; A->ny = ny; A->n = (int64_t)nx * ny;
+  A->row_ptr = (int64_t*)malloc((size_t)(A->n + 1) * sizeof(int64_t));
+  A->col = (int32_t*)malloc((size_t)nnz * sizeof(int32_t));
+  A->val = (double*)malloc((size_t)nnz * sizeof(double));
+  if (want_float) A->valf = (float*)malloc((size_t)nnz * sizeof(float));
+  if (!A->row_ptr || !A->col || !A->val || (want_float && !A->valf)) {
+    csr_free(A); return OR_E_NOMEM;
+  }
+  oracle_csr_assemble(nx, ny, order, A->row_ptr, A->col, A->val);
+  if (want_float)
+    for (int64_t e = 0; e < nnz; ++e) A->valf[e] = (float)A->val[e];
+  return OR_OK;
+}
+
+/* y = A u, each row summed in the stored entry order, starting from +0. */
+static void spmv(const csr_t* A, const double* u, double* y) {
+  for (int64_t k = 0; k < A->n; ++k) {
+    double acc = 0.0;
+    for (int64_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e)
+      acc = acc + A->val[e] * u[A->col[e]];
+    y[k] = acc;
+  }
+}
+
+static void spmv_f32(const csr_t* A, const float* u, float* y) {
+  for (int64_t k = 0; k < A->n; ++k) {
+    float acc = 0.0f;
+    for (int64_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e)
+      acc = acc + A->valf[e] * u[A->col[e]];
+    y[k] = acc;
+  }
+}
+
+/* Exported y = A u for the tests. */
+int oracle_spmv(int32_t nx, int32_t ny, int32_t order, const double* u, double* y) {
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, order, 0);
+  if (rc) return rc;
+  spmv(&A, u, y);
+  csr_free(&A);
+  return OR_OK;
+}
+
+/* ----------------------------------------------------------------- dots -- */
+
+static double dot_sequential(int64_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s = s + a[k] * b[k];
+  return s;
+}
+
+/* In-place xor butterfly over one wavefront: for m = lanes/2, ..., 1 every
+ * lane l takes v[l] + v[l ^ m] (both partners form the same sum, since IEEE
+ * addition is commutative).  Returns lane 0. */
+static double butterfly(double* v, int32_t lanes) {
+  double tmp[256];
+  for (int32_t m = lanes / 2; m >= 1; m /= 2) {
+    for (int32_t l = 0; l < lanes; ++l) tmp[l] = v[l] + v[l ^ m];
+    for (int32_t l = 0; l < lanes; ++l) v[l] = tmp[l];
+  }
+  return v[0];
+}
+
+/* Canonical order of the GPU library's deterministic dot product over the
+ * nx-by-ny grid (vectors here are dense, k = j*nx + i):
+ *   tile width  TW = cols_per_lane * lanes   columns,
+ *   tile height TH = waves * rows            rows,
+ *   tiles numbered t = ty * ceil(nx/TW) + tx (row-major).
+ *   In tile (tx, ty), wavefront w covers rows ty*TH + w*rows + [0, rows) and
+ *   lane l covers columns tx*TW + l*cols_per_lane + e, e < cols_per_lane.
+ *   Lane: one accumulator per owned column, starting at +0, updated as
+ *     acc_e = fma(a, b, acc_e) over its in-range rows in ascending order
+ *     (out-of-range rows/columns are skipped); lane value
+ *     ((acc_0 + acc_1) + acc_2) + ...
+ *   Wavefront: xor butterfly (see butterfly()).
+ *   Tile partial: ((wave_0 + wave_1) + wave_2) + ...
+ *   Cross-tile: thread t of threads2 sums partial[t], partial[t+threads2], ...
+ *     in that order starting at +0; then each group of `lanes` threads is
+ *     butterflied and the group values are added in group order.
+ */
+static double dot_canonical(int32_t nx, int32_t ny, const double* a, const double* b,
+                            const oracle_order* o) {
+  const int32_t cpl = o->cols_per_lane, L = o->lanes, W = o->waves, R = o->rows;
+  const int32_t TW = cpl * L, TH = W * R;
+  const int64_t ntx = (nx + TW - 1) / TW, nty = (ny + TH - 1) / TH;
+  const int64_t T = ntx * nty;
+  double* part = (double*)malloc((size_t)T * sizeof(double));
+  double lane[256], accs[16];
+  for (int64_t ty = 0; ty < nty; ++ty) {
+    for (int64_t tx = 0; tx < ntx; ++tx) {
+      double tile = 0.0;
+      for (int32_t w = 0; w < W; ++w) {
+        int64_t j0 = ty * TH + (int64_t)w * R;
+        for (int32_t l = 0; l < L; ++l) {
+          for (int32_t e = 0; e < cpl; ++e) accs[e] = 0.0;
+          for (int64_t j = j0; j < j0 + R && j < ny; ++j) {
+            for (int32_t e = 0; e < cpl; ++e) {
+              int64_t c = tx * TW + (int64_t)l * cpl + e;
+              if (c < nx) accs[e] = fma(a[j * nx + c], b[j * nx + c], accs[e]);
+            }
+          }
+          double v = accs[0];
+          for (int32_t e = 1; e < cpl; ++e) v = v + accs[e];
+          lane[l] = v;
+        }
+        double wv = butterfly(lane, L);
+        tile = (w == 0) ? wv : tile + wv;
+      }
+      part[ty * ntx + tx] = tile;
+    }
+  }
+  const int32_t T2 = o->threads2;
+  double* th = (double*)malloc((size_t)T2 * sizeof(double));
+  for (int32_t t = 0; t < T2; ++t) {
+    double s = 0.0;
+    for (int64_t k = t; k < T; k += T2) s = s + part[k];
+    th[t] = s;
+  }
+  double total = 0.0;
+  for (int32_t g = 0; g < T2 / L; ++g) {
+    double gv = butterfly(th + (int64_t)g * L, L);
+    total = (g == 0) ? gv : total + gv;
+  }
+  free(th);
+  free(part);
+  return total;
+}
+
+/* Exported dot for the tests. */
+double oracle_dot(int32_t nx, int32_t ny, int32_t mode, const oracle_order* o,
+                  const double* a, const double* b) {
+  if (mode == MODE_CANONICAL) return dot_canonical(nx, ny, a, b, o);
+  return dot_sequential((int64_t)nx * ny, a, b);
+}
+
+/* --------------------------------------------------------- CG context -- */
+
+typedef struct {
+  int32_t nx, ny, mode;
+  const oracle_order* ord;
+} ctx_t;
+
+static double dot(const ctx_t* c, const double* a, const double* b) {
+  return oracle_dot(c->nx, c->ny, c->mode, c->ord, a, b);
+}
+
+/* y <- y + a*x */
+static void axpy(const ctx_t* c, int64_t n, double a, const double* x, double* y) {
+  if (c->mode == MODE_CANONICAL) for (int64_t k = 0; k < n; ++k) y[k] = fma(a, x[k], y[k]);
+  else                           for (int64_t k = 0; k < n; ++k) y[k] = y[k] + a * x[k];
+}
+
+/* y <- x + a*y */
+static void xpay(const ctx_t* c, int64_t n, const double* x, double a, double* y) {
+  if (c->mode == MODE_CANONICAL) for (int64_t k = 0; k < n; ++k) y[k] = fma(a, y[k], x[k]);
+  else                           for (int64_t k = 0; k < n; ++k) y[k] = x[k] + a * y[k];
+}
+
+static void record(oracle_history* h, int64_t n, double gamma, const double* r,
+                   const double* p, const double* x) {
+  if (!h || h->count >= h->max_hist) return;
+  int64_t m = h->count;
+  if (h->gamma) h->gamma[m] = gamma;
+  if (h->r) memcpy(h->r + m * n, r, (size_t)n * sizeof(double));
+  if (h->p) memcpy(h->p + m * n, p, (size_t)n * sizeof(double));
+  if (h->x) memcpy(h->x + m * n, x, (size_t)n * sizeof(double));
+  h->count++;
+}
+
+/* Stopping and failure rules shared by both variants (readings of "until
+ * convergence", which the paper leaves open):
+ *   ||r||_2 <= tol ||b||_2 is evaluated as gamma <= (tol*tol)*(b,b);
+ *   a non-finite gamma, or a non-positive / non-finite curvature term, is a
+ *   breakdown; reaching maxit is NOT_CONVERGED, except that tol == 0 asks for
+ *   exactly maxit iterations and then reports OK. */
+static int stop_rule(double gamma, double thr, int32_t k, int32_t maxit, double tol) {
+  if (!isfinite(gamma)) return OR_BREAKDOWN;
+  if (gamma <= thr) return OR_OK;
+  if (k >= maxit) return tol == 0.0 ? OR_OK : OR_NOT_CONVERGED;
+  return -100; /* keep iterating */
+}
+
+static void finish(const csr_t* A, const ctx_t* c, const double* b, const double* x,
+                   double bb, double gamma, oracle_result* res) {
+  int64_t n = A->n;
+  double* t = (double*)malloc((size_t)n * sizeof(double));
+  spmv(A, x, t);
+  for (int64_t k = 0; k < n; ++k) t[k] = b[k] - t[k];
+  double rr = dot(c, t, t);
+  free(t);
+  res->rel_res_recursive = sqrt(gamma / bb);
+  res->rel_res_true = sqrt(rr / bb);
+}
+
+/* Classic CG (Algorithm 1, stdCG) with starting vector x0 (NULL = zeros):
+ *   r = b - A x0; p = r; gamma = (r,r)
+ *   repeat: s = A p; pi = (p,s); alpha = gamma/pi; x += alpha p;
+ *           r -= alpha s; gamma' = (r,r); beta = gamma'/gamma; p = r + beta p */
+static int cg_classic(const csr_t* A, const ctx_t* c, const double* b, const double* x0,
+                      double* x, double tol, int32_t maxit, oracle_result* res,
+                      oracle_history* h) {
+  const int64_t n = A->n;
+  double* r = (double*)malloc((size_t)n * sizeof(double));
+  double* p = (double*)malloc((size_t)n * sizeof(double));
+  double* s = (double*)malloc((size_t)n * sizeof(double));
+  if (!r || !p || !s) { free(r); free(p); free(s); return OR_E_NOMEM; }
+
+  const double bb = dot(c, b, b);
+  int32_t k = 0;
+  int st;
+  if (bb == 0.0) {  /* zero right-hand side: x = 0 solves it exactly */
+    memset(x, 0, (size_t)n * sizeof(double));
+    res->rel_res_recursive = res->rel_res_true = 0.0;
+    st = OR_OK;
+    goto done;
+  }
+  if (x0) memcpy(x, x0, (size_t)n * sizeof(double));
+  else    memset(x, 0, (size_t)n * sizeof(double));
+  spmv(A, x, s);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - s[i];
+  memcpy(p, r, (size_t)n * sizeof(double));
+  const double thr = (tol * tol) * bb;
+  double gamma = dot(c, r, r);
+  record(h, n, gamma, r, p, x);
+  for (;;) {
+    st = stop_rule(gamma, thr, k, maxit, tol);
+    if (st != -100) break;
+    spmv(A, p, s);
+    double pi = dot(c, p, s);
+    if (!(pi > 0.0) || !isfinite(pi)) { st = OR_BREAKDOWN; break; }
+    double alpha = gamma / pi;
+    axpy(c, n, alpha, p, x);
+    axpy(c, n, -alpha, s, r);
+    double gnew = dot(c, r, r);
+    double beta = gnew / gamma;
+    xpay(c, n, r, beta, p);
+    gamma = gnew;
+    ++k;
+    record(h, n, gamma, r, p, x);
+  }
+  finish(A, c, b, x, bb, gamma, res);
+done:
+  res->status = st;
+  res->iterations = k;
+  res->outer_iterations = 0;
+  free(r); free(p); free(s);
+  return st;
+}
+
+/* Modified CG (Algorithm 2, newCG), readings as in the file header:
+ *   r = b - A x0; w = A r; gamma = (r,r); delta = (w,r)
+ *   nvec = A w; beta = 0; alpha = gamma/delta; z = nvec; q = w; p = r
+ *   x += alpha p; r -= alpha q; w -= alpha z                      (k = 1)
+ *   repeat: gamma_old = gamma; gamma = (r,r); delta = (w,r); nvec = A w;
+ *           beta = gamma/gamma_old; alpha = 1/(delta/gamma - beta/alpha);
+ *           z = nvec + beta z; q = w + beta q; p = r + beta p;
+ *           x += alpha p; r -= alpha q; w -= alpha z
+ * The vector called n in the paper is nvec here (n is also the size). */
+static int cg_pipelined(const csr_t* A, const ctx_t* c, const double* b, const double* x0,
+                        double* x, double tol, int32_t maxit, oracle_result* res,
+                        oracle_history* h) {
+  const int64_t n = A->n;
+  double* r = (double*)malloc((size_t)n * sizeof(double));
+  double* w = (double*)malloc((size_t)n * sizeof(double));
+  double* nv = (double*)malloc((size_t)n * sizeof(double));
+  double* z = (double*)malloc((size_t)n * sizeof(double));
+  double* q = (double*)malloc((size_t)n * sizeof(double));
+  double* p = (double*)malloc((size_t)n * sizeof(double));
+  if (!r || !w || !nv || !z || !q || !p) {
+    free(r); free(w); free(nv); free(z); free(q); free(p); return OR_E_NOMEM;
+  }
+  const double bb = dot(c, b, b);
+  int32_t k = 0;
+  int st;
+  double gamma = 0.0;
+  if (bb == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    res->rel_res_recursive = res->rel_res_true = 0.0;
+    st = OR_OK;
+    goto done;
+  }
+  if (x0) memcpy(x, x0, (size_t)n * sizeof(double));
+  else    memset(x, 0, (size_t)n * sizeof(double));
+  spmv(A, x, nv);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - nv[i];
+  spmv(A, r, w);
+  const double thr = (tol * tol) * bb;
+  gamma = dot(c, r, r);
+  double delta = dot(c, w, r);
+  record(h, n, gamma, r, r, x);
+  st = stop_rule(gamma, thr, k, maxit, tol);
+  if (st != -100) goto fin;
+  if (!(delta > 0.0) || !isfinite(delta)) { st = OR_BREAKDOWN; goto fin; }
+  spmv(A, w, nv);
+  double alpha = gamma / delta;
+  memcpy(z, nv, (size_t)n * sizeof(double));
+  memcpy(q, w, (size_t)n * sizeof(double));
+  memcpy(p, r, (size_t)n * sizeof(double));
+  axpy(c, n, alpha, p, x);
+  axpy(c, n, -alpha, q, r);
+  axpy(c, n, -alpha, z, w);
+  k = 1;
+  for (;;) {
+    double gamma_old = gamma;
+    gamma = dot(c, r, r);
+    delta = dot(c, w, r);
+    record(h, n, gamma, r, p, x);
+    st = stop_rule(gamma, thr, k, maxit, tol);
+    if (st != -100) break;
+    spmv(A, w, nv);
+    double beta = gamma / gamma_old;
+    double den = delta / gamma - beta / alpha;
+    if (!(den > 0.0) || !isfinite(den)) { st = OR_BREAKDOWN; break; }
+    alpha = 1.0 / den;
+    xpay(c, n, nv, beta, z);
+    xpay(c, n, w, beta, q);
+    xpay(c, n, r, beta, p);
+    axpy(c, n, alpha, p, x);
+    axpy(c, n, -alpha, q, r);
+    axpy(c, n, -alpha, z, w);
+    ++k;
+  }
+fin:
+  finish(A, c, b, x, bb, gamma, res);
+done:
+  res->status = st;
+  res->iterations = k;
+  res->outer_iterations = 0;
+  free(r); free(w); free(nv); free(z); free(q); free(p);
+  return st;
+}
+
+/* Solve A x = b.  variant: 0 classic, 1 pipelined.  mode: 0 sequential,
+ * 1 canonical (then ord must describe the order).  x0 may be NULL.
+ * Returns the status (also in res). */
+int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
+              int32_t ny, const double* b, const double* x0, double* x, double tol,
+              int32_t maxit, oracle_result* res, oracle_history* hist) {
+  if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0)
+    return OR_E_INVALID;
+  if (mode == MODE_CANONICAL &&
+      (!ord || ord->cols_per_lane < 1 || ord->cols_per_lane > 16 || ord->lanes < 1 ||
+       ord->lanes > 256 || (ord->lanes & (ord->lanes - 1)) || ord->waves < 1 ||
+       ord->rows < 1 || ord->threads2 < ord->lanes || ord->threads2 % ord->lanes))
+    return OR_E_INVALID;
+  if (hist) hist->count = 0;
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
+  if (rc) return rc;
+  ctx_t c = {nx, ny, mode, ord};
+  memset(res, 0, sizeof(*res));
+  rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, hist)
+                                      : cg_classic(&A, &c, b, x0, x, tol, maxit, res, hist);
+  csr_free(&A);
+  return rc;
+}
+
+/* ---------------------------------------------------------- refinement -- */
+
+static double dot_f32_in_f64(int64_t n, const float* a, const float* b) {
+  /* each product of two binary32 values is exact in binary64 */
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s = s + (double)a[k] * (double)b[k];
+  return s;
+}
+
+/* FP32-inner / FP64-outer iterative refinement around classic CG:
+ *   outer: r = b - A x (FP64); stop when (r,r) <= tol^2 (b,b);
+ *          s = ||r||; rho = fp32(r * (1/s));
+ *   inner: classic CG on A d = rho with FP32 vectors and FP32 stencil/axpy
+ *          arithmetic, FP64 dot products, scalars alpha/beta computed in FP64
+ *          and rounded to FP32 once; stop when (ri,ri) <= inner_tol^2 (rho,rho);
+ *          a breakdown of the inner solve ends it early;
+ *   update: x += s * fp64(d).
+ * maxit caps the total number of inner iterations; an outer step whose inner
+ * solve made no iteration is a breakdown. */
+int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, double* x,
+                  double tol, double inner_tol, int32_t maxit, oracle_result* res) {
+  if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
+      !(inner_tol > 0.0) || inner_tol >= 1.0)
+    return OR_E_INVALID;
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, 0, 1);
+  if (rc) return rc;
+  const int64_t n = A.n;
+  double* r = (double*)malloc((size_t)n * sizeof(double));
+  float* ri = (float*)malloc((size_t)n * sizeof(float));
+  float* d = (float*)malloc((size_t)n * sizeof(float));
+  float* p = (float*)malloc((size_t)n * sizeof(float));
+  float* s = (float*)malloc((size_t)n * sizeof(float));
+  memset(res, 0, sizeof(*res));
+  int st = OR_OK;
+  int32_t total = 0, outer = 0;
+  const double bb = dot_sequential(n, b, b);
+  double g = 0.0;
+  if (!r || !ri || !d || !p || !s) { st = OR_E_NOMEM; goto out; }
+  if (bb == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    goto out;
+  }
+  if (x0) memcpy(x, x0, (size_t)n * sizeof(double));
+  else    memset(x, 0, (size_t)n * sizeof(double));
+  const double thr = (tol * tol) * bb;
+  for (;;) {
+    spmv(&A, x, r);
+    for (int64_t k = 0; k < n; ++k) r[k] = b[k] - r[k];
+    g = dot_sequential(n, r, r);
+    if (!isfinite(g)) { st = OR_BREAKDOWN; break; }
+    if (g <= thr) { st = OR_OK; break; }
+    if (total >= maxit) { st = OR_NOT_CONVERGED; break; }
+    const double sc = sqrt(g), inv = 1.0 / sc;
+    for (int64_t k = 0; k < n; ++k) {
+      ri[k] = (float)(r[k] * inv);
+      d[k] = 0.0f;
+      p[k] = ri[k];
+    }
+    double gamma = dot_f32_in_f64(n, ri, ri);
+    const double thr_in = (inner_tol * inner_tol) * gamma;
+    int32_t kin = 0;
+    while (!(gamma <= thr_in) && total < maxit) {
+      spmv_f32(&A, p, s);
+      double pi = dot_f32_in_f64(n, p, s);
+      if (!(pi > 0.0) || !isfinite(pi)) break;
+      double alpha = gamma / pi;
+      float af = (float)alpha;
+      for (int64_t k = 0; k < n; ++k) { d[k] = d[k] + af * p[k]; ri[k] = ri[k] - af * s[k]; }
+      double gnew = dot_f32_in_f64(n, ri, ri);
+      float bf = (float)(gnew / gamma);
+      for (int64_t k = 0; k < n; ++k) p[k] = ri[k] + bf * p[k];
+      gamma = gnew;
+      ++kin; ++total;
+    }
+    if (kin == 0) { st = OR_BREAKDOWN; break; }
+    for (int64_t k = 0; k < n; ++k) x[k] = x[k] + sc * (double)d[k];
+    ++outer;
+  }
+  res->rel_res_recursive = res->rel_res_true = sqrt(g / bb);
+out:
+  res->status = st;
+  res->iterations = total;
+  res->outer_iterations = outer;
+  free(r); free(ri); free(d); free(p); free(s);
+  csr_free(&A);
+  return st;
+}

@@ -1,0 +1,159 @@
+"""ctypes front end of cg_oracle.c (test infrastructure; see the C file header).
+
+Vectors are dense float64 arrays of shape (ny, nx), C order, so that unknown
+(i, j) sits at [j, i], i.e. flat index k = j*nx + i.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+MODE_SEQUENTIAL, MODE_CANONICAL = 0, 1
+VARIANT_CLASSIC, VARIANT_PIPELINED = 0, 1
+OR_OK, OR_NOT_CONVERGED, OR_BREAKDOWN, OR_E_INVALID, OR_E_NOMEM = 0, 2, 3, -1, -2
+
+
+class Order(C.Structure):
+    """Reduction order of the canonical mode (see dot_canonical in the C file)."""
+    _fields_ = [("cols_per_lane", C.c_int32), ("lanes", C.c_int32), ("waves", C.c_int32),
+                ("rows", C.c_int32), ("threads2", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32),
+                ("outer_iterations", C.c_int32), ("pad_", C.c_int32),
+                ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double)]
+
+
+class _History(C.Structure):
+    _fields_ = [("max_hist", C.c_int32), ("count", C.c_int32),
+                ("gamma", C.c_void_p), ("r", C.c_void_p), ("p", C.c_void_p), ("x", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib_path():
+    return _build.LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB) or (
+            os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+        _build.build()
+    lib = C.CDLL(_build.LIB)
+    P = C.c_void_p
+    lib.oracle_csr_nnz.restype = C.c_int64
+    lib.oracle_csr_nnz.argtypes = [C.c_int32, C.c_int32]
+    lib.oracle_csr_assemble.restype = C.c_int64
+    lib.oracle_csr_assemble.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
+    lib.oracle_spmv.restype = C.c_int
+    lib.oracle_spmv.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+    lib.oracle_dot.restype = C.c_double
+    lib.oracle_dot.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Order), P, P]
+    lib.oracle_cg.restype = C.c_int
+    lib.oracle_cg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
+                              P, P, P, C.c_double, C.c_int32, C.POINTER(_Result),
+                              C.POINTER(_History)]
+    lib.oracle_refine.restype = C.c_int
+    lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
+                                  C.c_int32, C.POINTER(_Result)]
+    _lib = lib
+    return lib
+
+
+def _vec(a, nx, ny):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != nx * ny:
+        raise ValueError("vector has %d entries, grid %dx%d needs %d" % (a.size, nx, ny, nx * ny))
+    return a.reshape(ny, nx)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def csr(nx, ny, order=0):
+    """The matrix A as (row_ptr int64, col int32, val float64)."""
+    lib = _load()
+    nnz = lib.oracle_csr_nnz(nx, ny)
+    if nnz < 0:
+        raise ValueError("bad grid")
+    rp = np.zeros(nx * ny + 1, np.int64)
+    col = np.zeros(nnz, np.int32)
+    val = np.zeros(nnz, np.float64)
+    got = lib.oracle_csr_assemble(nx, ny, order, _ptr(rp), _ptr(col), _ptr(val))
+    assert got == nnz
+    return rp, col, val
+
+
+def spmv(u, nx, ny, order=0):
+    u = _vec(u, nx, ny)
+    y = np.zeros_like(u)
+    rc = _load().oracle_spmv(nx, ny, order, _ptr(u), _ptr(y))
+    if rc:
+        raise RuntimeError("oracle_spmv failed: %d" % rc)
+    return y
+
+
+def dot(a, b, nx, ny, mode=MODE_SEQUENTIAL, order=None):
+    a, b = _vec(a, nx, ny), _vec(b, nx, ny)
+    o = C.byref(order) if order is not None else None
+    if mode == MODE_CANONICAL and order is None:
+        raise ValueError("canonical mode needs an Order")
+    return _load().oracle_dot(nx, ny, mode, o, _ptr(a), _ptr(b))
+
+
+class Result(dict):
+    __getattr__ = dict.__getitem__
+
+
+def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
+       mode=MODE_SEQUENTIAL, order=None, history=0):
+    """Solve A x = b.  Returns (x, Result); with history=m also returns a dict of
+    the first m records (gamma, r, p, x after 0, 1, ... updates)."""
+    b = _vec(b, nx, ny)
+    x0a = _vec(x0, nx, ny) if x0 is not None else None
+    x = np.zeros_like(b)
+    res = _Result()
+    o = C.byref(order) if order is not None else None
+    hist = None
+    h = None
+    if history:
+        n = nx * ny
+        hist = dict(gamma=np.zeros(history), r=np.zeros((history, n)),
+                    p=np.zeros((history, n)), x=np.zeros((history, n)))
+        h = _History(history, 0, _ptr(hist["gamma"]), _ptr(hist["r"]), _ptr(hist["p"]),
+                     _ptr(hist["x"]))
+    rc = _load().oracle_cg(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, maxit,
+                           C.byref(res), C.byref(h) if h is not None else None)
+    if rc < 0:
+        raise ValueError("oracle_cg rejected the call: %d" % rc)
+    out = Result(status=res.status, iterations=res.iterations,
+                 outer_iterations=res.outer_iterations,
+                 rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
+    if history:
+        c = h.count
+        hist = {k: v[:c] for k, v in hist.items()}
+        return x, out, hist
+    return x, out
+
+
+def refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, maxit=200000, x0=None):
+    """FP32-inner / FP64-outer iterative refinement (see oracle_refine)."""
+    b = _vec(b, nx, ny)
+    x0a = _vec(x0, nx, ny) if x0 is not None else None
+    x = np.zeros_like(b)
+    res = _Result()
+    rc = _load().oracle_refine(nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, inner_tol, maxit,
+                               C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle_refine rejected the call: %d" % rc)
+    return x, Result(status=res.status, iterations=res.iterations,
+                     outer_iterations=res.outer_iterations,
+                     rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)

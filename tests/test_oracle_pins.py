@@ -1,0 +1,325 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests compares the oracle with itself: each checks it against a
+closed form (eigenvalues/eigenvectors of the 5-point Laplacian), a library
+routine (dense Cholesky, dense eigensolver, scipy sparse products), an exact
+integer computation, an invariant of CG, or the stencil the paper prints.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle
+from oracle import MODE_CANONICAL, MODE_SEQUENTIAL, VARIANT_CLASSIC, VARIANT_PIPELINED
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+VARIANTS = (VARIANT_CLASSIC, VARIANT_PIPELINED)
+GPU_LIKE = oracle.Order(2, 64, 4, 16, 256)
+
+
+def dense_A(nx, ny, order=0):
+    rp, col, val = oracle.csr(nx, ny, order)
+    return sp.csr_matrix((val, col, rp), shape=(nx * ny, nx * ny)).toarray()
+
+
+def sparse_A(nx, ny):
+    rp, col, val = oracle.csr(nx, ny, 0)
+    return sp.csr_matrix((val, col, rp), shape=(nx * ny, nx * ny))
+
+
+def closed_form_eigs(nx, ny):
+    a = np.arange(1, nx + 1)[None, :]
+    b = np.arange(1, ny + 1)[:, None]
+    return 4 - 2 * np.cos(a * np.pi / (nx + 1)) - 2 * np.cos(b * np.pi / (ny + 1))
+
+
+def mode(nx, ny, a, b):
+    """Eigenvector phi_ab on the (ny, nx) grid, unknown (i, j) at [j, i]."""
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    return np.sin(a * np.pi * (i + 1) / (nx + 1)) * np.sin(b * np.pi * (j + 1) / (ny + 1))
+
+
+def mode_eig(nx, ny, a, b):
+    return 4 - 2 * math.cos(a * math.pi / (nx + 1)) - 2 * math.cos(b * math.pi / (ny + 1))
+
+
+# ------------------------------------------------------------ the operator --
+
+def test_golden_stencil_from_paper():
+    """Interior row of A equals the 3x3 stencil printed in Section II-B."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "stencil_3x3.txt"))
+            if l.strip() and not l.startswith("#")]
+    st = np.array(rows, dtype=float)
+    assert st.shape == (3, 3)
+    nx, ny = 7, 6
+    for order in (0, 1):
+        A = dense_A(nx, ny, order)
+        i, j = 3, 2
+        row = A[j * nx + i].reshape(ny, nx)
+        # window centred on (i, j): rows j+1, j, j-1 (north first), columns i-1..i+1
+        win = row[[j + 1, j, j - 1]][:, i - 1:i + 2]
+        np.testing.assert_array_equal(win, st)
+        assert np.count_nonzero(row) == 5
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 5), (5, 7), (16, 16), (9, 4), (13, 11)])
+def test_eigenvalues_closed_form(nx, ny):
+    """Dense eigvalsh of the assembled A equals 4-2cos(a pi/(nx+1))-2cos(b pi/(ny+1))."""
+    A = dense_A(nx, ny)
+    got = np.sort(np.linalg.eigvalsh(A))
+    want = np.sort(closed_form_eigs(nx, ny).ravel())
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("nx,ny", [(5, 7), (12, 12), (3, 1)])
+def test_matrix_structure(nx, ny):
+    for order in (0, 1):
+        A = dense_A(nx, ny, order)
+        np.testing.assert_array_equal(A, A.T)
+        np.testing.assert_array_equal(A, dense_A(nx, ny, 1 - order))
+        # a row sums to the number of that node's neighbours on the Dirichlet ring
+        g = np.zeros((ny, nx))
+        g[0, :] += 1; g[-1, :] += 1; g[:, 0] += 1; g[:, -1] += 1
+        np.testing.assert_array_equal(A.sum(axis=1), g.ravel())
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (64, 1), (100, 100)])
+def test_eigenvector_identity(nx, ny):
+    for (a, b) in [(1, 1), (2, 1), (nx, ny), (max(1, nx // 3), max(1, ny // 2))]:
+        phi = mode(nx, ny, a, b)
+        lam = mode_eig(nx, ny, a, b)
+        for order in (0, 1):
+            y = oracle.spmv(phi, nx, ny, order)
+            np.testing.assert_allclose(y, lam * phi, rtol=0, atol=1e-14 * 8)
+
+
+def test_spmv_matches_scipy():
+    nx, ny = 31, 17
+    u = np.random.default_rng(0).standard_normal((ny, nx))
+    want = sparse_A(nx, ny) @ u.ravel()
+    for order in (0, 1):
+        np.testing.assert_allclose(oracle.spmv(u, nx, ny, order).ravel(), want, rtol=0,
+                                   atol=1e-14)
+
+
+# ------------------------------------------------------------------- dots --
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (127, 1), (129, 65), (300, 77), (1000, 3)])
+@pytest.mark.parametrize("order", [GPU_LIKE, oracle.Order(4, 64, 4, 8, 256),
+                                   oracle.Order(1, 4, 3, 5, 8)])
+def test_canonical_dot_exact_on_integers(nx, ny, order):
+    """Integer data: every partial sum is exact, so any correct order returns the
+    exact sum; a dropped, repeated or misplaced term would not."""
+    rng = np.random.default_rng(nx * 1000 + ny)
+    a = rng.integers(-8, 9, size=(ny, nx)).astype(float)
+    b = rng.integers(-8, 9, size=(ny, nx)).astype(float)
+    exact = float(np.sum(a.astype(np.int64) * b.astype(np.int64)))
+    assert oracle.dot(a, b, nx, ny, MODE_CANONICAL, order) == exact
+    assert oracle.dot(a, b, nx, ny, MODE_SEQUENTIAL) == exact
+    # weights that identify every position: term k gets weight k+1
+    w = np.arange(1, nx * ny + 1, dtype=float).reshape(ny, nx)
+    one = np.ones((ny, nx))
+    assert oracle.dot(w, one, nx, ny, MODE_CANONICAL, order) == (nx * ny) * (nx * ny + 1) / 2
+
+
+@pytest.mark.parametrize("nx,ny", [(300, 77), (513, 129)])
+def test_canonical_dot_error_bound(nx, ny):
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((ny, nx))
+    b = rng.standard_normal((ny, nx))
+    exact = math.fsum((a * b).ravel())  # products rounded, then summed exactly
+    mag = float(np.sum(np.abs(a * b)))
+    u = 2.0 ** -53
+    o = GPU_LIKE
+    T = math.ceil(nx / (o.cols_per_lane * o.lanes)) * math.ceil(ny / (o.waves * o.rows))
+    depth = o.rows + o.cols_per_lane + 6 + o.waves + math.ceil(T / o.threads2) + 6 + 4 + 2
+    got = oracle.dot(a, b, nx, ny, MODE_CANONICAL, o)
+    # fma rounds once per term, so the product rounding of fsum adds n*u*mag at most
+    assert abs(got - exact) <= 2 * depth * u * mag + 1e-300
+    assert abs(oracle.dot(a, b, nx, ny, MODE_SEQUENTIAL) - exact) <= nx * ny * u * mag
+
+
+# -------------------------------------------------------------- CG solves --
+
+def kappa(nx, ny):
+    e = closed_form_eigs(nx, ny)
+    return e.max() / e.min()
+
+
+@pytest.mark.parametrize("nx,ny", [(6, 5), (16, 16), (11, 3)])
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("mode_", [MODE_SEQUENTIAL, MODE_CANONICAL])
+def test_solve_vs_dense_cholesky(nx, ny, variant, mode_):
+    b = np.random.default_rng(nx + 31 * ny).uniform(-1, 1, (ny, nx))
+    c = sla.cho_factor(dense_A(nx, ny))
+    xc = sla.cho_solve(c, b.ravel())
+    tol = 1e-12
+    x, r = oracle.cg(b, nx, ny, variant=variant, tol=tol, maxit=1000, mode=mode_,
+                     order=GPU_LIKE)
+    assert r.status == oracle.OR_OK
+    assert r.rel_res_recursive <= tol
+    err = np.linalg.norm(x.ravel() - xc) / np.linalg.norm(xc)
+    assert err <= 2 * tol * kappa(nx, ny)
+    # the reported true residual matches a scipy recomputation
+    rt = np.linalg.norm(b.ravel() - sparse_A(nx, ny) @ x.ravel()) / np.linalg.norm(b)
+    assert abs(rt - r.rel_res_true) <= 1e-3 * rt + 1e-16
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_single_eigenvector_one_iteration(variant):
+    nx, ny = 13, 9
+    phi = mode(nx, ny, 3, 2)
+    lam = mode_eig(nx, ny, 3, 2)
+    x, r = oracle.cg(phi, nx, ny, variant=variant, tol=1e-12, maxit=50)
+    assert r.status == oracle.OR_OK and r.iterations == 1
+    np.testing.assert_allclose(x, phi / lam, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("K", [2, 3, 5])
+def test_finite_termination(variant, K):
+    """b spanning K eigenvectors with distinct eigenvalues: CG ends after K
+    iterations in exact arithmetic (K or K+1 in FP64)."""
+    nx, ny = 13, 7
+    modes = [(1, 1), (4, 2), (7, 5), (2, 6), (12, 3)][:K]
+    lams = [mode_eig(nx, ny, a, b) for a, b in modes]
+    assert min(abs(x - y) for i, x in enumerate(lams) for y in lams[i + 1:]) > 1e-2
+    coef = [1.0, -0.7, 0.45, 0.9, -0.3][:K]
+    b = sum(c * mode(nx, ny, a, bb) for c, (a, bb) in zip(coef, modes))
+    x, r = oracle.cg(b, nx, ny, variant=variant, tol=1e-10, maxit=100)
+    assert r.status == oracle.OR_OK
+    assert r.iterations in (K, K + 1)
+    want = sum(c / l * mode(nx, ny, a, bb) for c, l, (a, bb) in zip(coef, lams, modes))
+    np.testing.assert_allclose(x, want, rtol=0, atol=1e-9)
+
+
+def test_one_by_one_and_two_by_one_brute_force():
+    x, r = oracle.cg(np.array([[3.0]]), 1, 1, tol=1e-14)
+    assert r.iterations == 1 and x[0, 0] == 0.75
+    b = np.array([[1.0, 2.0]])
+    want = np.linalg.solve(np.array([[4.0, -1.0], [-1.0, 4.0]]), b.ravel())
+    for v in VARIANTS:
+        x, r = oracle.cg(b, 2, 1, variant=v, tol=1e-14)
+        assert r.status == oracle.OR_OK and r.iterations <= 2
+        np.testing.assert_allclose(x.ravel(), want, rtol=1e-15, atol=1e-15)
+
+
+def test_classic_invariants():
+    """Residuals mutually orthogonal, directions A-conjugate, A-norm error
+    non-increasing (first 20 iterations)."""
+    nx, ny = 12, 12
+    b = np.random.default_rng(3).uniform(-1, 1, (ny, nx))
+    m = 21
+    x, r, h = oracle.cg(b, nx, ny, tol=0.0, maxit=m - 1, history=m)
+    assert h["r"].shape[0] == m
+    R, P, X = h["r"], h["p"], h["x"]
+    A = sparse_A(nx, ny)
+    G = R @ R.T
+    d = np.sqrt(np.diag(G))
+    off = np.abs(G / np.outer(d, d) - np.eye(m))
+    assert off.max() <= 1e-10
+    AP = (A @ P.T).T
+    H = P @ AP.T
+    dh = np.sqrt(np.diag(H))
+    assert np.abs(H / np.outer(dh, dh) - np.eye(m)).max() <= 1e-10
+    xs = sla.cho_solve(sla.cho_factor(dense_A(nx, ny)), b.ravel())
+    E = X - xs
+    anorm = np.sqrt(np.einsum("ij,ij->i", E, (A @ E.T).T))
+    assert np.all(np.diff(anorm) <= 1e-12 * anorm[0])
+    # recorded gamma is (r, r)
+    np.testing.assert_allclose(h["gamma"], np.einsum("ij,ij->i", R, R), rtol=1e-14)
+
+
+@pytest.mark.parametrize("nx,ny", [(6, 5), (16, 16), (9, 14)])
+def test_variant_agreement(nx, ny):
+    """Classic and modified CG produce the same iterates in exact arithmetic;
+    a wrong sign or a misplaced parenthesis in the modified recurrences breaks this."""
+    b = np.random.default_rng(nx * ny).uniform(-1, 1, (ny, nx))
+    for m in (1, 2, 5, 10, 20):
+        xc, rc = oracle.cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=0.0, maxit=m)
+        xp, rp = oracle.cg(b, nx, ny, variant=VARIANT_PIPELINED, tol=0.0, maxit=m)
+        assert rc.iterations == rp.iterations == m
+        assert np.linalg.norm(xc - xp) / np.linalg.norm(xc) <= 1e-12
+    xc, rc = oracle.cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8)
+    xp, rp = oracle.cg(b, nx, ny, variant=VARIANT_PIPELINED, tol=1e-8)
+    assert abs(rc.iterations - rp.iterations) <= 1
+
+
+def test_modes_agree_on_workload_shape():
+    """Sequential and canonical orders are two valid FP64 runs of the same method."""
+    nx, ny = 100, 100
+    b = np.random.default_rng(11).uniform(-1, 1, (ny, nx))
+    for v, lim in ((VARIANT_CLASSIC, 1e-13), (VARIANT_PIPELINED, 1e-9)):
+        xs, rs = oracle.cg(b, nx, ny, variant=v, tol=1e-8)
+        xk, rk = oracle.cg(b, nx, ny, variant=v, tol=1e-8, mode=MODE_CANONICAL, order=GPU_LIKE)
+        assert abs(rs.iterations - rk.iterations) <= 1
+        assert np.linalg.norm(xs - xk) / np.linalg.norm(xs) <= lim
+
+
+# ------------------------------------------------------------- edge cases --
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_zero_rhs(variant):
+    x, r = oracle.cg(np.zeros((4, 5)), 5, 4, variant=variant, x0=np.ones((4, 5)))
+    assert r.status == oracle.OR_OK and r.iterations == 0
+    assert not x.any()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_fixed_iterations_and_maxit(variant):
+    b = np.random.default_rng(5).uniform(-1, 1, (20, 30))
+    x, r = oracle.cg(b, 30, 20, variant=variant, tol=0.0, maxit=7)
+    assert r.status == oracle.OR_OK and r.iterations == 7
+    x, r = oracle.cg(b, 30, 20, variant=variant, tol=1e-12, maxit=7)
+    assert r.status == oracle.OR_NOT_CONVERGED and r.iterations == 7
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_exact_start_takes_no_iteration(variant):
+    nx, ny = 8, 6
+    b = np.random.default_rng(2).uniform(-1, 1, (ny, nx))
+    xs = sla.cho_solve(sla.cho_factor(dense_A(nx, ny)), b.ravel()).reshape(ny, nx)
+    x, r = oracle.cg(b, nx, ny, variant=variant, tol=1e-8, x0=xs)
+    assert r.iterations == 0 and r.status == oracle.OR_OK
+    np.testing.assert_array_equal(x, xs)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_nonfinite_rhs_is_breakdown(variant):
+    b = np.ones((3, 3)); b[1, 1] = np.nan
+    x, r = oracle.cg(b, 3, 3, variant=variant)
+    assert r.status == oracle.OR_BREAKDOWN and r.iterations == 0
+
+
+def test_rejects_invalid():
+    with pytest.raises(ValueError):
+        oracle.cg(np.ones((2, 2)), 2, 2, tol=1.5)
+    with pytest.raises(ValueError):
+        oracle.cg(np.ones((2, 2)), 2, 2, maxit=0)
+
+
+# ------------------------------------------------------------- refinement --
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (40, 25)])
+def test_refinement_reaches_fp64_accuracy(nx, ny):
+    b = np.random.default_rng(9).standard_normal((ny, nx))
+    tol = 1e-10
+    x, r = oracle.refine(b, nx, ny, tol=tol, inner_tol=1e-4)
+    assert r.status == oracle.OR_OK and r.outer_iterations >= 2
+    rt = np.linalg.norm(b.ravel() - sparse_A(nx, ny) @ x.ravel()) / np.linalg.norm(b)
+    assert rt <= tol
+    xc = sla.cho_solve(sla.cho_factor(dense_A(nx, ny)), b.ravel())
+    assert np.linalg.norm(x.ravel() - xc) / np.linalg.norm(xc) <= 2 * tol * kappa(nx, ny)
+
+
+def test_refinement_inner_cap_and_zero():
+    b = np.random.default_rng(4).standard_normal((30, 30))
+    x, r = oracle.refine(b, 30, 30, tol=1e-12, inner_tol=1e-4, maxit=10)
+    assert r.status == oracle.OR_NOT_CONVERGED and r.iterations == 10
+    x, r = oracle.refine(np.zeros((3, 3)), 3, 3)
+    assert r.status == oracle.OR_OK and r.iterations == 0 and not x.any()
