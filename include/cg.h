@@ -1,0 +1,175 @@
+/*
+ * cg.h - C ABI of the MI355X (gfx950) stencil conjugate-gradient library.
+ *
+ * The library solves A x = b where A is the Laplacian of Section II of
+ * "Efficient FPGA Implementation of Conjugate Gradient Methods for Laplacian
+ * System using HLS" (arXiv 1803.03797): an nx-by-ny interior grid with zero
+ * Dirichlet boundary, discretised by the 5-point stencil the paper prints in
+ * Section II-B (4 on the centre, -1 on the four compass neighbours), used
+ * unscaled.  A is never assembled: every product A*u is the stencil applied on
+ * the grid (Section II-B, "Parallel Matrix Vector Multiplication implemented as
+ * Stencil operations").  Two iterations are offered, the paper's Algorithm 1
+ * (stdCG, "classic") and Algorithm 2 (newCG, the pipelined CG that overlaps the
+ * stencil with the two dot products, "pipelined").
+ *
+ * Vector layout at the boundary: nx*ny doubles, row-major, unknown (i, j) with
+ * 0 <= i < nx, 0 <= j < ny at index j*nx + i.  Pointers are host or device
+ * pointers as stated by cg_problem.mem; the caller owns them.
+ *
+ * Return convention of every int-returning call: a negative value means the
+ * call was rejected and nothing happened (CG_E_*); a non-negative value is an
+ * outcome (CG_OK, CG_PENDING, CG_NOT_CONVERGED, CG_BREAKDOWN).  No exception
+ * and no errno crosses this boundary.  cg_status_str() names any code.
+ *
+ * Threading: calls on one context are serialised by the context; cg_submit
+ * and cg_poll may be called from any thread.
+ */
+#ifndef CG_H
+#define CG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cg_ctx cg_ctx; /* opaque: device workspace, streams, scheduler */
+
+typedef enum { CG_VARIANT_CLASSIC = 0, CG_VARIANT_PIPELINED = 1 } cg_variant;
+typedef enum { CG_PREC_FP64 = 0, CG_PREC_FP32_REFINED = 1 } cg_precision;
+typedef enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 } cg_memspace;
+
+enum {
+  CG_OK = 0,             /* converged: ||r|| <= tol*||b|| (or tol == 0 and maxit done) */
+  CG_PENDING = 1,        /* cg_poll: not finished yet                                 */
+  CG_NOT_CONVERGED = 2,  /* maxit reached; x holds the last iterate                   */
+  CG_BREAKDOWN = 3,      /* non-positive or non-finite curvature / scalar; x = last   */
+  CG_E_INVALID = -1,     /* bad argument                                              */
+  CG_E_NOMEM = -2,       /* footprint larger than the arena (or arena exhausted)      */
+  CG_E_DEVICE = -3,      /* HIP error, no device, or the GPU library could not run    */
+  CG_E_BUSY = -4,        /* context is shutting down                                  */
+  CG_E_TICKET = -5       /* unknown or already-released ticket                        */
+};
+
+typedef struct {
+  int32_t device;         /* HIP device ordinal                                         */
+  void* stream;           /* hipStream_t the caller orders work on (may be NULL = the
+                             null stream); the library runs on its own stream and
+                             orders itself after this one at every call               */
+  void* arena;            /* device memory the library may use for all workspace, or
+                             NULL: then the library allocates arena_bytes itself      */
+  size_t arena_bytes;     /* size of arena; admission budget (0 with arena == NULL
+                             means 4 GiB)                                              */
+  int32_t max_slots;      /* max solves resident at once (batch / serving); 0 = 256   */
+  const char* tune_cache; /* path of the autotuner's JSON cache, or NULL              */
+} cg_config;
+
+typedef struct {
+  int32_t nx, ny;          /* interior grid; zero Dirichlet ring implied (Section II) */
+  cg_memspace mem;         /* where b, x0 and x live                                  */
+  const double* b;         /* right-hand side, nx*ny, row-major; read until the final
+                              status is returned                                      */
+  const double* x0;        /* starting vector or NULL (= zeros); may alias x          */
+  double* x;               /* out: solution, nx*ny                                    */
+  double tol;              /* stop when ||r||_2 <= tol ||b||_2, 0 <= tol < 1; tol == 0
+                              runs exactly maxit iterations (throughput mode)         */
+  int32_t maxit;           /* >= 1; FP32-refined: cap on the total inner iterations   */
+  cg_variant variant;      /* Algorithm 1 or Algorithm 2                              */
+  cg_precision precision;  /* FP64, or FP32 inner CG inside FP64 refinement           */
+  double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
+} cg_problem;
+
+typedef struct {
+  int32_t status;           /* CG_OK / CG_NOT_CONVERGED / CG_BREAKDOWN                */
+  int32_t iterations;       /* x-updates (refined: total inner iterations)           */
+  int32_t outer_iterations; /* refined: refinement steps; else 0                     */
+  int32_t pad_;
+  double rel_res_recursive; /* sqrt((r,r)/(b,b)) of the iteration's own residual     */
+  double rel_res_true;      /* ||b - A x|| / ||b|| recomputed in FP64 on the device  */
+  double device_seconds;    /* wall time the solve held the device                   */
+  double latency_seconds;   /* serving: submit -> completion; else = device_seconds  */
+} cg_result;
+
+/* Work layout a problem will use; its reduction order is the documented
+ * arithmetic contract (tile = 64 lanes x cols_per_lane columns by waves x rows
+ * rows; lanes accumulate with fma in row order; xor butterfly; waves in order;
+ * tiles in index order through threads2 strided threads). */
+typedef struct {
+  int32_t path;             /* 0 = multi-work-group passes, 1 = single work-group    */
+  int32_t cols_per_lane, lanes, waves, rows, threads2;
+  int32_t tiles;            /* tiles per pass                                        */
+  int32_t grid;             /* work-groups per pass launch                           */
+  int32_t pitch;            /* padded row length in elements                         */
+  int32_t pad_;
+  size_t footprint;         /* device bytes the solve occupies                       */
+} cg_plan_info;
+
+/* Per-kernel timing gathered while profiling is on (cg_set_profiling). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double seconds;           /* summed HIP-event time of the launches                 */
+  double bytes;             /* summed algorithmic HBM bytes of the launches          */
+} cg_kstat;
+
+/* Creates a context on cfg->device.  CG_E_DEVICE when no usable GPU. */
+int cg_create(const cg_config* cfg, cg_ctx** out);
+/* Cancels queued requests (they complete as CG_E_BUSY), waits for running
+ * work, frees everything the library allocated. */
+int cg_destroy(cg_ctx* ctx);
+
+/* One blocking solve of A x = b (Algorithm 1 or 2; Section II problem). */
+int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
+
+/* n independent solves in one persistent launch over a tile work queue.
+ * Returns the worst per-solve status; results[i] holds each outcome.  A
+ * breakdown of one solve does not disturb the others. */
+int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
+
+/* Serving: queue one request (non-blocking).  The request is admitted when
+ * its device footprint fits the free arena and a slot is free, joins the
+ * device-resident active set at the next epoch, and is retired when final.
+ * CG_E_NOMEM if its footprint exceeds arena_bytes. */
+int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket);
+/* CG_PENDING, or the final status (then *res is filled and the ticket is
+ * released). */
+int cg_poll(cg_ctx* ctx, uint64_t ticket, cg_result* res);
+
+const char* cg_status_str(int code);
+
+/* ---- building blocks, exposed for verification and measurement ---------- */
+
+/* y = A u on the nx-by-ny grid, matrix-free (Section II-B stencil). */
+int cg_apply(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* u, double* y);
+/* *out = (a, b) with the library's deterministic two-stage reduction (the
+ * order of cg_plan_info for an FP64 problem of this shape). */
+int cg_dot(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* a,
+           const double* b, double* out);
+/* Fills *info for prob (host-side; no device work). */
+int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info);
+/* Device bytes prob needs while resident (host-only; no context needed). */
+int cg_footprint(const cg_problem* prob, size_t* bytes);
+/* CG_OK or CG_E_INVALID (host-only; no context needed). */
+int cg_validate(const cg_problem* prob);
+/* Autotuner: times candidate tile shapes for (nx, ny, variant, precision) on
+ * the device and pins the fastest for that grid shape (cached, optionally in
+ * cfg->tune_cache).  Returns CG_OK. */
+int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision);
+/* Pins an explicit tile height (rows per wavefront strip) and grid size for a
+ * grid shape; grid 0 = occupancy-derived.  For experiments and tests. */
+int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int32_t rows,
+                int32_t grid);
+/* Profiling on/off; while on, every kernel launch is bracketed by HIP events
+ * on the library's stream. */
+int cg_set_profiling(cg_ctx* ctx, int32_t on);
+/* Copies up to max entries of the per-kernel statistics; *count = entries
+ * available.  reset != 0 clears them afterwards. */
+int cg_kernel_stats(cg_ctx* ctx, cg_kstat* out, int32_t max, int32_t* count, int32_t reset);
+/* Library build identifier. */
+const char* cg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CG_H */

@@ -1,0 +1,190 @@
+// cg_abi.cpp - the extern "C" entry points of include/cg.h.
+//
+// Every call validates its arguments before touching the device, returns a
+// negative CG_E_* code without side effects when it rejects, and serialises
+// on the context's mutex.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/cg.h"
+#include "cg_runtime.h"
+
+using cgr::Ctx;
+
+static Ctx* C(cg_ctx* c) { return reinterpret_cast<Ctx*>(c); }
+
+extern "C" {
+
+int cg_create(const cg_config* cfg, cg_ctx** out) {
+  if (!out) return CG_E_INVALID;
+  *out = nullptr;
+  if (cfg && cfg->arena && cfg->arena_bytes == 0) return CG_E_INVALID;
+  Ctx* c = new (std::nothrow) Ctx;
+  if (!c) return CG_E_NOMEM;
+  int rc = c->init(cfg);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = reinterpret_cast<cg_ctx*>(c);
+  return CG_OK;
+}
+
+int cg_destroy(cg_ctx* ctx) {
+  if (!ctx) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  cgr_server_stop(c);
+  delete c;
+  return CG_OK;
+}
+
+int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res) {
+  if (!ctx || !res) return CG_E_INVALID;
+  int rc = cgr::validate(prob);
+  if (rc) return rc;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->solve(prob, res);
+}
+
+int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results) {
+  if (!ctx || !probs || !results || n < 1) return CG_E_INVALID;
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = cgr::validate(&probs[i]);
+    if (rc) return rc;
+  }
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->solve_batch(probs, n, results);
+}
+
+int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
+  if (!ctx || !ticket) return CG_E_INVALID;
+  int rc = cgr::validate(prob);
+  if (rc) return rc;
+  return cgr_server_submit(C(ctx), prob, ticket);
+}
+
+int cg_poll(cg_ctx* ctx, uint64_t ticket, cg_result* res) {
+  if (!ctx || !res) return CG_E_INVALID;
+  return cgr_server_poll(C(ctx), ticket, res);
+}
+
+const char* cg_status_str(int code) {
+  switch (code) {
+    case CG_OK: return "CG_OK";
+    case CG_PENDING: return "CG_PENDING";
+    case CG_NOT_CONVERGED: return "CG_NOT_CONVERGED";
+    case CG_BREAKDOWN: return "CG_BREAKDOWN";
+    case CG_E_INVALID: return "CG_E_INVALID";
+    case CG_E_NOMEM: return "CG_E_NOMEM";
+    case CG_E_DEVICE: return "CG_E_DEVICE";
+    case CG_E_BUSY: return "CG_E_BUSY";
+    case CG_E_TICKET: return "CG_E_TICKET";
+  }
+  return "CG_UNKNOWN";
+}
+
+int cg_apply(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* u, double* y) {
+  if (!ctx || nx < 1 || ny < 1 || !u || !y || (mem != CG_MEM_HOST && mem != CG_MEM_DEVICE))
+    return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->apply_or_dot(cgk::K_APPLY, nx, ny, mem, u, nullptr, y, nullptr);
+}
+
+int cg_dot(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* a,
+           const double* b, double* out) {
+  if (!ctx || nx < 1 || ny < 1 || !a || !b || !out ||
+      (mem != CG_MEM_HOST && mem != CG_MEM_DEVICE))
+    return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->apply_or_dot(cgk::K_DOT, nx, ny, mem, a, b, nullptr, out);
+}
+
+int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
+  if (!ctx || !info) return CG_E_INVALID;
+  if (!prob || prob->nx < 1 || prob->ny < 1) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  cgr::Plan pl = c->plan(prob);
+  memset(info, 0, sizeof(*info));
+  info->path = pl.wg ? 1 : 0;
+  info->cols_per_lane = pl.fp32g ? 4 : 2;
+  info->lanes = cgk::kWave;
+  info->waves = cgk::kWavesPerTile;
+  info->rows = pl.g.rows;
+  info->threads2 = cgk::kGroup;
+  info->tiles = pl.g.tiles;
+  info->grid = pl.grid;
+  info->pitch = pl.g.pitch;
+  info->footprint = pl.footprint;
+  return CG_OK;
+}
+
+int cg_footprint(const cg_problem* prob, size_t* bytes) {
+  if (!prob || !bytes || prob->nx < 1 || prob->ny < 1) return CG_E_INVALID;
+  *bytes = cgr::footprint_of(prob);
+  return CG_OK;
+}
+
+int cg_validate(const cg_problem* prob) { return cgr::validate(prob); }
+
+int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision) {
+  if (!ctx || nx < 1 || ny < 1) return CG_E_INVALID;
+  if (variant != CG_VARIANT_CLASSIC && variant != CG_VARIANT_PIPELINED) return CG_E_INVALID;
+  if (precision != CG_PREC_FP64 && precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->tune(nx, ny, variant, precision);
+}
+
+int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int32_t rows,
+                int32_t grid) {
+  if (!ctx || nx < 1 || ny < 1 || rows < 1 || rows > 4096 || grid < 0) return CG_E_INVALID;
+  if (precision != CG_PREC_FP64 && precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  c->pins[Ctx::key(nx, ny, precision == CG_PREC_FP32_REFINED)] = cgr::Pin{rows, grid};
+  return CG_OK;
+}
+
+int cg_set_profiling(cg_ctx* ctx, int32_t on) {
+  if (!ctx) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  c->prof = on != 0;
+  return CG_OK;
+}
+
+int cg_kernel_stats(cg_ctx* ctx, cg_kstat* out, int32_t max, int32_t* count, int32_t reset) {
+  if (!ctx || !count || max < 0 || (max > 0 && !out)) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  *count = (int32_t)c->stats.size();
+  int32_t i = 0;
+  for (auto& kv : c->stats) {
+    if (i >= max) break;
+    memset(&out[i], 0, sizeof(cg_kstat));
+    strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+    out[i].launches = kv.second.launches;
+    out[i].seconds = kv.second.seconds;
+    out[i].bytes = kv.second.bytes;
+    ++i;
+  }
+  if (reset) c->stats.clear();
+  return CG_OK;
+}
+
+const char* cg_version(void) { return "mi355x-stencil-cg 0.1 (gfx950)"; }
+
+}  // extern "C"

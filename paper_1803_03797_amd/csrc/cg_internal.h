@@ -1,0 +1,119 @@
+// cg_internal.h - structures shared by the host runtime and the gfx950 kernels.
+//
+// Layout in HBM.  Every grid vector is stored row-major with a padded pitch P
+// (a multiple of the tile width, so each wavefront row access is a full
+// aligned 1-2 KiB segment); columns [nx, P) are kept zero and are never
+// written.  The Dirichlet ring is not stored: out-of-grid neighbours read as
+// zero by predicate.
+//
+// Work decomposition (the arithmetic contract every pass obeys).  A tile is
+// 64 lanes x CPL columns wide and 4 wavefronts x `rows` rows tall; wavefront w
+// marches down its own `rows`-row strip.  Tiles are numbered row-major.  Each
+// pass writes one FP64 partial per dot product per tile; the next pass sums
+// them in tile order (cross-tile stage) before it starts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cgk {
+
+constexpr int kWave = 64;
+constexpr int kGroup = 256;       // threads that process one tile (4 wavefronts)
+constexpr int kWavesPerTile = 4;
+constexpr int kWgGroups = 2;     // tile groups of the single-work-group solver
+
+// Device-side solve status (host maps it to the ABI codes).
+enum : int32_t {
+  ST_RUNNING = 0,
+  ST_OK = 1,             // converged, or tol == 0 and maxit iterations done
+  ST_NOT_CONVERGED = 2,
+  ST_BREAKDOWN = 3,
+  ST_ZERO_RHS = 4,       // (b,b) == 0: x = 0 is the answer
+  ST_INNER_DONE = 5,     // refinement: inner solve finished, outer step pending
+};
+
+enum : int32_t {
+  F_BB_PENDING = 1,      // the next prologue takes (b,b) from partial slot 1
+};
+
+// Scalar state of one solve.  Kept in device memory, double-buffered by pass
+// parity: a pass reads state[m & 1] and its first work-group writes
+// state[(m + 1) & 1], so no work-group overwrites what another still reads.
+struct alignas(16) State {
+  double gamma;      // (r, r) of the current iterate
+  double gamma0;     // refinement: (rho, rho) at the start of the inner solve
+  double delta;      // pipelined: (w, r)
+  double alpha, beta;
+  double bb;         // (b, b)
+  double thr;        // stop when gamma <= thr = tol^2 (b, b)
+  double thr_in;     // refinement inner stop threshold
+  double scale;      // refinement: ||b - A x|| of the current outer step
+  double res2;       // ||b - A x||^2 recomputed at exit (or last outer step)
+  double tol, inner_tol;
+  int32_t k;         // x-updates done (refinement: total inner iterations)
+  int32_t status;
+  int32_t flags;
+  int32_t kin;       // refinement: iterations of the current inner solve
+  int32_t outer;     // refinement: outer steps done
+  int32_t maxit;
+  int32_t pad_[2];
+};
+
+struct Geo {
+  int32_t nx, ny, pitch;
+  int32_t ntx, nty, tiles;
+  int32_t rows;      // rows per wavefront strip
+  int32_t th;        // rows per tile = 4 * rows
+};
+
+// Pass kinds.
+enum : int32_t {
+  K_INIT_R = 0,   // r = b - A x;               slots (r,r), (b,b)
+  K_INIT_W,       // w = A r;                   slots (r,r), (w,r)    [pipelined]
+  K_PCG,          // fused pipelined iteration; slots (r,r), (w,r)
+  K_CG1,          // p = r + beta p; s = A p;   slot  (p,s)          [classic]
+  K_CG2,          // x += a p; r -= a A p;      slot  (r,r)          [classic]
+  K_RESID,        // t = b - A x;               slots (t,t), (b,b)
+  K_REF_SCALE,    // rho = fp32((b - A x)/s); d = 0; slot (rho,rho)  [refinement]
+  K_CG1F,         // FP32 classic pass 1
+  K_CG2F,         // FP32 classic pass 2
+  K_REF_UPDATE,   // x += s * d
+  K_APPLY,        // y = A u
+  K_DOT,          // slot (u, y)
+  K_NKINDS
+};
+
+// Everything a pass may touch.  Unused pointers are null.
+struct PassArgs {
+  Geo g;
+  const State* st_in;
+  State* st_out;
+  const double* part_in;   // [2][tiles] partials of the previous pass
+  double* part_out;        // [2][tiles] partials of this pass
+  const double* b;
+  double* x;
+  double* r;
+  const double* w_in;      // pipelined: w of this iteration (read with halo)
+  double* w_out;           //            w of the next iteration
+  double* z;
+  double* q;
+  double* p;               // pipelined p
+  const double* pc_in;     // classic: previous direction (read with halo)
+  double* pc_out;          //          new direction
+  float* rf;               // refinement: inner residual rho / r_in
+  float* df;               //             inner solution d
+  const float* pf_in;      //             inner direction ping-pong
+  float* pf_out;
+  const double* u;         // apply / dot inputs
+  double* y;
+};
+
+// Host-side launchers (cg_kernels.hip).
+hipError_t launch_pass(int kind, int fp32_geometry, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slot 0
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
+int pass_max_blocks_per_cu(int kind, int fp32_geometry);
+size_t pass_algorithmic_bytes(int kind, int64_t dof);
+
+}  // namespace cgk

@@ -1,0 +1,1104 @@
+// cg_kernels.hip - gfx950 kernels of the stencil conjugate-gradient library.
+//
+// The method (arXiv 1803.03797): conjugate gradients on the Laplacian of
+// Section II, with the matrix-vector product applied as the 5-point stencil of
+// Section II-B (never assembled), in the two variants of the paper:
+// Algorithm 1 (stdCG) and Algorithm 2 (newCG, the pipelined CG that lets the
+// stencil and the two dot products proceed together, Section II dataflow
+// discussion).  The FPGA design of the paper (line buffers, FACTOR-way
+// superscalar streams, padding copies) is replaced by a GPU design:
+//
+//  * Every CG step is a "pass" over the grid that fuses the stencil with the
+//    dot products and axpy updates of that step (Section II-C: dot product and
+//    axpy blocks), so each vector crosses HBM once per pass.
+//  * A pass walks tiles; inside a tile each wavefront marches down a strip of
+//    rows keeping the south/centre/north rows of the halo vector in registers;
+//    west/east neighbours come from adjacent lanes through wavefront-wide DPP
+//    shifts, and the tile's outer columns from one extra load per edge lane.
+//  * Dot products use a fixed order: per-lane fma accumulation in row order,
+//    xor butterfly across the 64 lanes, wavefronts in order, one FP64 partial
+//    per tile; the next pass sums the partials in tile order (every
+//    work-group redundantly, so no atomics or cross-work-group fences are
+//    needed) and evaluates the scalar recurrences of the algorithm before its
+//    own body.  Results are bitwise reproducible.
+//
+// All arithmetic is written with explicit fma() where the contract says fma;
+// the library is built with -ffp-contract=off so nothing else is fused.
+#include <math.h>
+
+#include "cg_internal.h"
+
+namespace cgk {
+
+// ------------------------------------------------------------- lane rows --
+
+template <typename T, int CPL>
+struct Row {
+  T e[CPL];
+};
+
+template <typename T, int CPL>
+__device__ __forceinline__ Row<T, CPL> zrow() {
+  Row<T, CPL> v;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) v.e[k] = T(0);
+  return v;
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ Row<T, CPL> ldrow(const T* p) {
+  Row<T, CPL> v;
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < CPL; k += 2) {
+      double2 t = *reinterpret_cast<const double2*>(p + k);
+      v.e[k] = t.x;
+      v.e[k + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; k += 4) {
+      float4 t = *reinterpret_cast<const float4*>(p + k);
+      v.e[k] = t.x;
+      v.e[k + 1] = t.y;
+      v.e[k + 2] = t.z;
+      v.e[k + 3] = t.w;
+    }
+  }
+  return v;
+}
+
+// Stores the first `valid` elements (valid >= CPL: the whole row segment).
+template <typename T, int CPL>
+__device__ __forceinline__ void strow(T* p, const Row<T, CPL>& v, int valid) {
+  if (valid >= CPL) {
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int k = 0; k < CPL; k += 2)
+        *reinterpret_cast<double2*>(p + k) = make_double2(v.e[k], v.e[k + 1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < CPL; k += 4)
+        *reinterpret_cast<float4*>(p + k) =
+            make_float4(v.e[k], v.e[k + 1], v.e[k + 2], v.e[k + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k)
+      if (k < valid) p[k] = v.e[k];
+  }
+}
+
+// ---------------------------------------------------- wavefront exchange --
+
+constexpr int kDppWaveShr1 = 0x138;  // lane l receives lane l-1 (lane 0 keeps `old`)
+constexpr int kDppWaveShl1 = 0x130;  // lane l receives lane l+1 (lane 63 keeps `old`)
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v, double old) {
+  int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, 0xf, 0xf,
+                                       false);
+  int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, 0xf, 0xf,
+                                       false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    0xf, 0xf, false));
+}
+
+// West and east neighbours of every element of a lane's row segment.  eW is
+// the value left of the tile (used by lane 0), eE the value right of it
+// (used by lane 63).  Must be called with the whole wavefront active.
+template <typename T, int CPL>
+__device__ __forceinline__ void west_east(const Row<T, CPL>& v, T eW, T eE, Row<T, CPL>& W,
+                                          Row<T, CPL>& E) {
+  W.e[0] = dpp<kDppWaveShr1>(v.e[CPL - 1], eW);
+  E.e[CPL - 1] = dpp<kDppWaveShl1>(v.e[0], eE);
+#pragma unroll
+  for (int k = 1; k < CPL; ++k) W.e[k] = v.e[k - 1];
+#pragma unroll
+  for (int k = 0; k < CPL - 1; ++k) E.e[k] = v.e[k + 1];
+}
+
+// (A u) at one point: (((4 uC - uW) - uE) - uS) - uN, S = row j-1, N = row j+1.
+template <typename T>
+__device__ __forceinline__ T st5(T c, T w, T e, T s, T n) {
+  return (((T(4) * c - w) - e) - s) - n;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// ------------------------------------------------------- tile geometry --
+
+struct Strip {
+  int tx, lane, wave;
+  int c;       // first column of this lane
+  int ct;      // first column of the tile
+  int j0, j1;  // rows of this wavefront's strip; empty when j0 >= j1
+};
+
+template <int CPL>
+__device__ __forceinline__ Strip strip_of(const Geo& g, int t) {
+  Strip s;
+  s.tx = t % g.ntx;
+  const int ty = t / g.ntx;
+  s.lane = threadIdx.x & (kWave - 1);
+  s.wave = (threadIdx.x >> 6) & (kWavesPerTile - 1);
+  s.ct = s.tx * (kWave * CPL);
+  s.c = s.ct + s.lane * CPL;
+  s.j0 = ty * g.th + s.wave * g.rows;
+  s.j1 = min(s.j0 + g.rows, g.ny);
+  return s;
+}
+
+// Values just outside the tile on one row (zero outside the grid: the pad
+// columns are zero, and there is no tile beyond the last one).
+template <typename T, int CPL>
+__device__ __forceinline__ void edges(const T* row, const Strip& s, const Geo& g, T& eW, T& eE) {
+  eW = T(0);
+  eE = T(0);
+  if (s.lane == 0 && s.tx > 0) eW = row[s.ct - 1];
+  if (s.lane == kWave - 1 && s.tx + 1 < g.ntx) eE = row[s.ct + kWave * CPL];
+}
+
+// ---------------------------------------------------------- scalar step --
+
+struct Sc {
+  double al, be;
+  bool first;  // first iteration: previous direction vectors are zero
+  double inv;  // refinement: 1/scale
+};
+
+__device__ __forceinline__ int stop_code(double gamma, double thr, int k, int maxit, double tol) {
+  if (!isfinite(gamma)) return ST_BREAKDOWN;
+  if (gamma <= thr) return ST_OK;
+  if (k >= maxit) return tol == 0.0 ? ST_OK : ST_NOT_CONVERGED;
+  return ST_RUNNING;
+}
+
+// Applies the scalar recurrences that sit between the previous pass and this
+// one.  `sum` holds the cross-tile sums of the previous pass's partials.
+// Returns true when this pass's body must run.
+template <int KIND>
+__device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) {
+  sc.al = 0.0;
+  sc.be = 0.0;
+  sc.first = false;
+  sc.inv = 0.0;
+  if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
+    return true;
+  } else if constexpr (KIND == K_INIT_R) {
+    return s.status == ST_RUNNING;
+  } else if constexpr (KIND == K_INIT_W) {
+    if (s.status != ST_RUNNING) return false;
+    s.bb = sum[1];
+    s.thr = (s.tol * s.tol) * s.bb;
+    s.flags &= ~F_BB_PENDING;
+    if (s.bb == 0.0) s.status = ST_ZERO_RHS;
+    return s.status == ST_RUNNING;
+  } else if constexpr (KIND == K_PCG) {
+    // Algorithm 2: gamma = (r,r), delta = (w,r); first pass alpha = gamma/delta,
+    // later beta = gamma/gamma_old, alpha = 1/(delta/gamma - beta/alpha_old).
+    if (s.status != ST_RUNNING) return false;
+    const double gamma = sum[0], delta = sum[1];
+    int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
+    double al = 0.0, be = 0.0;
+    if (st == ST_RUNNING) {
+      if (s.k == 0) {
+        if (!(delta > 0.0) || !isfinite(delta)) st = ST_BREAKDOWN;
+        else al = gamma / delta;
+        sc.first = true;
+      } else {
+        be = gamma / s.gamma;
+        const double den = delta / gamma - be / s.alpha;
+        if (!(den > 0.0) || !isfinite(den)) st = ST_BREAKDOWN;
+        else al = 1.0 / den;
+      }
+    }
+    s.gamma = gamma;
+    s.delta = delta;
+    s.status = st;
+    if (st != ST_RUNNING) return false;
+    s.alpha = al;
+    s.beta = be;
+    s.k += 1;
+    sc.al = al;
+    sc.be = be;
+    return true;
+  } else if constexpr (KIND == K_CG1) {
+    // Algorithm 1: beta = (r,r)_new / (r,r)_old, then p = r + beta p.
+    if (s.status != ST_RUNNING) return false;
+    const double gamma = sum[0];
+    if (s.flags & F_BB_PENDING) {
+      s.bb = sum[1];
+      s.thr = (s.tol * s.tol) * s.bb;
+      s.flags &= ~F_BB_PENDING;
+      if (s.bb == 0.0) {
+        s.status = ST_ZERO_RHS;
+        return false;
+      }
+    }
+    const int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
+    double be = 0.0;
+    if (s.k == 0) sc.first = true;
+    else be = gamma / s.gamma;
+    s.gamma = gamma;
+    s.status = st;
+    if (st != ST_RUNNING) return false;
+    s.beta = be;
+    sc.be = be;
+    return true;
+  } else if constexpr (KIND == K_CG2) {
+    // Algorithm 1: alpha = (r,r) / (p, A p).
+    if (s.status != ST_RUNNING) return false;
+    const double pi = sum[0];
+    if (!(pi > 0.0) || !isfinite(pi)) {
+      s.status = ST_BREAKDOWN;
+      return false;
+    }
+    s.alpha = s.gamma / pi;
+    s.k += 1;
+    sc.al = s.alpha;
+    return true;
+  } else if constexpr (KIND == K_REF_SCALE) {
+    // Outer refinement step: test the true FP64 residual, then scale it.
+    if (s.status != ST_RUNNING) return false;
+    const double g = sum[0];
+    if (s.flags & F_BB_PENDING) {
+      s.bb = sum[1];
+      s.thr = (s.tol * s.tol) * s.bb;
+      s.flags &= ~F_BB_PENDING;
+      if (s.bb == 0.0) {
+        s.status = ST_ZERO_RHS;
+        return false;
+      }
+    }
+    s.res2 = g;
+    int st = ST_RUNNING;
+    if (!isfinite(g)) st = ST_BREAKDOWN;
+    else if (g <= s.thr) st = ST_OK;
+    else if (s.k >= s.maxit) st = ST_NOT_CONVERGED;
+    s.status = st;
+    if (st != ST_RUNNING) return false;
+    s.scale = sqrt(g);
+    s.kin = 0;
+    sc.inv = 1.0 / s.scale;
+    return true;
+  } else if constexpr (KIND == K_CG1F) {
+    if (s.status != ST_RUNNING) return false;
+    const double gamma = sum[0];
+    double be = 0.0;
+    if (s.kin == 0) {
+      s.gamma0 = gamma;
+      s.thr_in = (s.inner_tol * s.inner_tol) * gamma;
+      sc.first = true;
+    } else {
+      be = gamma / s.gamma;
+    }
+    s.gamma = gamma;
+    if (!isfinite(gamma) || gamma <= s.thr_in || s.k >= s.maxit) {
+      s.status = ST_INNER_DONE;
+      return false;
+    }
+    s.beta = be;
+    sc.be = be;
+    return true;
+  } else if constexpr (KIND == K_CG2F) {
+    if (s.status != ST_RUNNING) return false;
+    const double pi = sum[0];
+    if (!(pi > 0.0) || !isfinite(pi)) {
+      s.status = ST_INNER_DONE;
+      return false;
+    }
+    s.alpha = s.gamma / pi;
+    s.k += 1;
+    s.kin += 1;
+    sc.al = s.alpha;
+    return true;
+  } else if constexpr (KIND == K_REF_UPDATE) {
+    if (s.status != ST_INNER_DONE) return false;
+    if (s.kin == 0) {
+      s.status = ST_BREAKDOWN;
+      return false;
+    }
+    s.status = ST_RUNNING;
+    s.outer += 1;
+    sc.al = s.scale;
+    return true;
+  }
+  return false;
+}
+
+template <int KIND>
+constexpr int ndots_in() {  // partial slots the prologue consumes
+  return (KIND == K_PCG || KIND == K_INIT_W || KIND == K_CG1 || KIND == K_REF_SCALE) ? 2
+         : (KIND == K_CG2 || KIND == K_CG1F || KIND == K_CG2F)                      ? 1
+                                                                                     : 0;
+}
+
+template <int KIND>
+constexpr int ndots_out() {  // partial slots the body produces
+  return (KIND == K_INIT_R || KIND == K_INIT_W || KIND == K_PCG || KIND == K_RESID) ? 2
+         : (KIND == K_CG1 || KIND == K_CG2 || KIND == K_REF_SCALE || KIND == K_CG1F ||
+            KIND == K_CG2F || KIND == K_DOT)
+             ? 1
+             : 0;
+}
+
+// ------------------------------------------------------------- reductions --
+
+// Cross-tile stage: the 256 threads of a tile group sum part[d*T + k] for
+// k = tid, tid+256, ... in order, butterfly within each wavefront, then add
+// the four wavefront values in order.  Every thread of the group receives
+// the sums.  `lds` holds 4*D doubles for this group.
+template <int D>
+__device__ __forceinline__ void cross_tile_sum(const double* part, int T, double* out,
+                                               double* lds) {
+  const int tid = threadIdx.x & (kGroup - 1), lane = tid & (kWave - 1), wave = tid >> 6;
+  double v[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double acc = 0.0;
+    for (int k = tid; k < T; k += kGroup) acc = acc + part[(size_t)d * T + k];
+    v[d] = wave_sum(acc);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) lds[wave * D + d] = v[d];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double t = lds[d];
+#pragma unroll
+    for (int w = 1; w < kWavesPerTile; ++w) t = t + lds[w * D + d];
+    out[d] = t;
+  }
+  __syncthreads();
+}
+
+// Per-tile partials: butterfly each lane value, add wavefronts in order, and
+// let the group's first thread store part[d*T + t].  `lds` holds 2*4*D
+// doubles for this group (double-buffered by `par` so one barrier suffices).
+template <int D>
+__device__ __forceinline__ void tile_partial(const double* lv, double* part, int T, int t,
+                                             double* lds, int par) {
+  const int tid = threadIdx.x & (kGroup - 1), lane = tid & (kWave - 1), wave = tid >> 6;
+  double* L = lds + par * kWavesPerTile * D;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double v = wave_sum(lv[d]);
+    if (lane == 0) L[wave * D + d] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double s = L[d];
+#pragma unroll
+      for (int w = 1; w < kWavesPerTile; ++w) s = s + L[w * D + d];
+      part[(size_t)d * T + t] = s;
+    }
+  }
+}
+
+template <int CPL>
+__device__ __forceinline__ double fold(const double (&acc)[CPL]) {
+  double v = acc[0];
+#pragma unroll
+  for (int k = 1; k < CPL; ++k) v = v + acc[k];
+  return v;
+}
+
+// ------------------------------------------------------------- tile bodies --
+//
+// Each body handles tile t for the calling wavefront (rows s.j0..s.j1-1) and
+// leaves the lane's dot-product values in lv[].  Loops are wavefront-uniform.
+
+// Row walker shared by every stencil body.  For the wavefront's strip it
+// keeps rows j-1, j, j+1 of the halo vector (H) and the tile-edge values of
+// rows j and j+1 in registers, and loads the next row's data (halo row j+2,
+// point row j+1) before it computes row j, so each wavefront keeps two rows
+// of loads in flight.
+//   hrow(off)          -> Row: H on row offset `off` at this lane's columns
+//   hedge(off, W, E)   -> H just left/right of the tile on that row
+//   point(off)         -> Bundle: the point-wise operands of that row
+//   comp(off, S, C, N, W, E, bundle): row j's arithmetic and stores
+template <typename T, int CPL, class HRow, class HEdge, class Point, class Comp>
+__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HRow hrow, HEdge hedge,
+                                     Point point, Comp comp) {
+  using R = Row<T, CPL>;
+  if (s.j0 >= s.j1) return;
+  const size_t P = g.pitch;
+  size_t o = (size_t)s.j0 * P;
+  R hS = s.j0 > 0 ? hrow(o - P) : zrow<T, CPL>();
+  R hC = hrow(o);
+  T eW, eE;
+  hedge(o, eW, eE);
+  R hN = zrow<T, CPL>();
+  T nW = T(0), nE = T(0);
+  if (s.j0 + 1 < g.ny) {
+    hN = hrow(o + P);
+    hedge(o + P, nW, nE);
+  }
+  auto cur = point(o);
+  for (int j = s.j0; j < s.j1; ++j, o += P) {
+    R hNN = zrow<T, CPL>();
+    T nnW = T(0), nnE = T(0);
+    auto nxt = cur;
+    if (j + 1 < s.j1) {
+      nxt = point(o + P);
+      if (j + 2 < g.ny) {
+        hNN = hrow(o + 2 * P);
+        hedge(o + 2 * P, nnW, nnE);
+      }
+    }
+    R W, E;
+    west_east<T, CPL>(hC, eW, eE, W, E);
+    comp(o, hS, hC, hN, W, E, cur);
+    hS = hC;
+    hC = hN;
+    hN = hNN;
+    eW = nW;
+    eE = nE;
+    nW = nnW;
+    nE = nnE;
+    cur = nxt;
+  }
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ auto halo_loader(const T* V, const Strip& s) {
+  return [=](size_t off) { return ldrow<T, CPL>(V + off + s.c); };
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ auto edge_loader(const T* V, const Strip& s, const Geo& g) {
+  return [=](size_t off, T& eW, T& eE) { edges<T, CPL>(V + off, s, g, eW, eE); };
+}
+
+struct Empty {};
+
+// --- K_INIT_R: r = b - A x; slots (r,r), (b,b)
+// --- K_RESID:  t = b - A x; slots (t,t), (b,b)   (no store)
+template <int CPL, bool STORE>
+__device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  double a0[CPL], a1[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
+  const int valid = g.nx - s.c;
+  const double* B = a.b;
+  double* Rr = a.r;
+  walk<double, CPL>(
+      g, s, halo_loader<double, CPL>(a.x, s), edge_loader<double, CPL>(a.x, s, g),
+      [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& bb) {
+        R res;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          res.e[k] = bb.e[k] - st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (k < valid) {
+            a0[k] = fma(res.e[k], res.e[k], a0[k]);
+            a1[k] = fma(bb.e[k], bb.e[k], a1[k]);
+          }
+        }
+        if constexpr (STORE) strow<double, CPL>(Rr + off + s.c, res, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+  lv[1] = fold<CPL>(a1);
+}
+
+// --- K_INIT_W: w = A r; slots (r,r), (w,r)
+// --- K_APPLY:  y = A u; no slots
+template <int CPL, bool INITW>
+__device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const double* U = INITW ? a.r : a.u;
+  double* Y = INITW ? a.w_out : a.y;
+  double a0[CPL], a1[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
+  const int valid = g.nx - s.c;
+  walk<double, CPL>(
+      g, s, halo_loader<double, CPL>(U, s), edge_loader<double, CPL>(U, s, g),
+      [](size_t) { return Empty{}; },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const Empty&) {
+        R out;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          out.e[k] = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (INITW && k < valid) {
+            a0[k] = fma(hC.e[k], hC.e[k], a0[k]);
+            a1[k] = fma(out.e[k], hC.e[k], a1[k]);
+          }
+        }
+        strow<double, CPL>(Y + off + s.c, out, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+  lv[1] = fold<CPL>(a1);
+}
+
+// --- K_DOT: slot (u, y)
+template <int CPL>
+__device__ __forceinline__ void body_dot(const PassArgs& a, int t, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  double a0[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
+  const int valid = g.nx - s.c;
+  for (int j = s.j0; j < s.j1; ++j) {
+    const size_t o = (size_t)j * g.pitch + s.c;
+    const R u = ldrow<double, CPL>(a.u + o), y = ldrow<double, CPL>(a.y + o);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k)
+      if (k < valid) a0[k] = fma(u.e[k], y.e[k], a0[k]);
+  }
+  lv[0] = fold<CPL>(a0);
+}
+
+// --- K_PCG: one fused iteration of Algorithm 2 (its loop body):
+//   nvec = A w; z = nvec + beta z; q = w + beta q; p = r + beta p;
+//   x += alpha p; r -= alpha q; w' = w - alpha z;  slots (r',r'), (w',r').
+// On the first iteration z, q, p are taken as zero (z = nvec, q = w, p = r).
+template <int CPL>
+struct PcgRow {
+  Row<double, CPL> x, r, z, q, p;
+};
+
+template <int CPL>
+__device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const double al = sc.al, be = sc.be, nal = -sc.al;
+  const bool first = sc.first;
+  double a0[CPL], a1[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
+  const int valid = g.nx - s.c;
+  double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
+  walk<double, CPL>(
+      g, s, halo_loader<double, CPL>(a.w_in, s), edge_loader<double, CPL>(a.w_in, s, g),
+      [=](size_t off) {
+        PcgRow<CPL> v;
+        const size_t oc = off + s.c;
+        v.x = ldrow<double, CPL>(X + oc);
+        v.r = ldrow<double, CPL>(Rv + oc);
+        if (first) {
+          v.z = v.q = v.p = zrow<double, CPL>();
+        } else {
+          v.z = ldrow<double, CPL>(Z + oc);
+          v.q = ldrow<double, CPL>(Q + oc);
+          v.p = ldrow<double, CPL>(Pp + oc);
+        }
+        return v;
+      },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const PcgRow<CPL>& in) {
+        R x = in.x, r = in.r, z, q, p, wo;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const double nv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (first) {
+            z.e[k] = nv;
+            q.e[k] = hC.e[k];
+            p.e[k] = r.e[k];
+          } else {
+            z.e[k] = fma(be, in.z.e[k], nv);
+            q.e[k] = fma(be, in.q.e[k], hC.e[k]);
+            p.e[k] = fma(be, in.p.e[k], r.e[k]);
+          }
+          x.e[k] = fma(al, p.e[k], x.e[k]);
+          r.e[k] = fma(nal, q.e[k], r.e[k]);
+          wo.e[k] = fma(nal, z.e[k], hC.e[k]);
+          if (k < valid) {
+            a0[k] = fma(r.e[k], r.e[k], a0[k]);
+            a1[k] = fma(wo.e[k], r.e[k], a1[k]);
+          }
+        }
+        const size_t oc = off + s.c;
+        strow<double, CPL>(Z + oc, z, valid);
+        strow<double, CPL>(Q + oc, q, valid);
+        strow<double, CPL>(Pp + oc, p, valid);
+        strow<double, CPL>(X + oc, x, valid);
+        strow<double, CPL>(Rv + oc, r, valid);
+        strow<double, CPL>(Wo + oc, wo, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+  lv[1] = fold<CPL>(a1);
+}
+
+// --- K_CG1 / K_CG1F: p = r + beta p_old (on tile + halo); s = A p; store p;
+//     slot (p, s).  First iteration: p = r.
+template <typename T, int CPL>
+__device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  using R = Row<T, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const T* Rv;
+  const T* Po;
+  T* Pn;
+  if constexpr (sizeof(T) == 8) {
+    Rv = a.r;
+    Po = a.pc_in;
+    Pn = a.pc_out;
+  } else {
+    Rv = a.rf;
+    Po = a.pf_in;
+    Pn = a.pf_out;
+  }
+  const T be = T(sc.be);
+  const bool first = sc.first;
+  double a0[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
+  const int valid = g.nx - s.c;
+  walk<T, CPL>(
+      g, s,
+      [=](size_t off) -> R {
+        const R r = ldrow<T, CPL>(Rv + off + s.c);
+        if (first) return r;
+        const R po = ldrow<T, CPL>(Po + off + s.c);
+        R v;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) v.e[k] = fma(be, po.e[k], r.e[k]);
+        return v;
+      },
+      [=](size_t row, T& eW, T& eE) {
+        eW = T(0);
+        eE = T(0);
+        if (s.lane == 0 && s.tx > 0) {
+          const size_t i = row + s.ct - 1;
+          eW = first ? Rv[i] : fma(be, Po[i], Rv[i]);
+        }
+        if (s.lane == kWave - 1 && s.tx + 1 < g.ntx) {
+          const size_t i = row + s.ct + kWave * CPL;
+          eE = first ? Rv[i] : fma(be, Po[i], Rv[i]);
+        }
+      },
+      [](size_t) { return Empty{}; },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const Empty&) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const T sv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (k < valid) a0[k] = fma((double)hC.e[k], (double)sv, a0[k]);
+        }
+        strow<T, CPL>(Pn + off + s.c, hC, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+}
+
+// --- K_CG2 / K_CG2F: s = A p; x += alpha p; r -= alpha s; slot (r, r).
+template <typename T, int CPL>
+struct XrRow {
+  Row<T, CPL> x, r;
+};
+
+template <typename T, int CPL>
+__device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  using R = Row<T, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const T* Pv;
+  T* Xv;
+  T* Rv;
+  if constexpr (sizeof(T) == 8) {
+    Pv = a.pc_in;
+    Xv = a.x;
+    Rv = a.r;
+  } else {
+    Pv = a.pf_in;
+    Xv = a.df;
+    Rv = a.rf;
+  }
+  const T al = T(sc.al), nal = -al;
+  double a0[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
+  const int valid = g.nx - s.c;
+  walk<T, CPL>(
+      g, s, halo_loader<T, CPL>(Pv, s), edge_loader<T, CPL>(Pv, s, g),
+      [=](size_t off) {
+        XrRow<T, CPL> v;
+        v.x = ldrow<T, CPL>(Xv + off + s.c);
+        v.r = ldrow<T, CPL>(Rv + off + s.c);
+        return v;
+      },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const XrRow<T, CPL>& in) {
+        R x = in.x, r = in.r;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const T sv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          x.e[k] = fma(al, hC.e[k], x.e[k]);
+          r.e[k] = fma(nal, sv, r.e[k]);
+          if (k < valid) a0[k] = fma((double)r.e[k], (double)r.e[k], a0[k]);
+        }
+        strow<T, CPL>(Xv + off + s.c, x, valid);
+        strow<T, CPL>(Rv + off + s.c, r, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+}
+
+// --- K_REF_SCALE: rho = fp32((b - A x) * inv); d = 0; slot (rho, rho) in FP64.
+template <int CPL>
+__device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const Sc& sc,
+                                               double* lv) {
+  using R = Row<double, CPL>;
+  using RF = Row<float, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const double inv = sc.inv;
+  double a0[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
+  const int valid = g.nx - s.c;
+  const double* B = a.b;
+  float *Rf = a.rf, *Df = a.df;
+  walk<double, CPL>(
+      g, s, halo_loader<double, CPL>(a.x, s), edge_loader<double, CPL>(a.x, s, g),
+      [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& bb) {
+        RF rho;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const double res = bb.e[k] - st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          rho.e[k] = (float)(res * inv);
+          if (k < valid) a0[k] = fma((double)rho.e[k], (double)rho.e[k], a0[k]);
+        }
+        strow<float, CPL>(Rf + off + s.c, rho, valid);
+        strow<float, CPL>(Df + off + s.c, zrow<float, CPL>(), valid);
+      });
+  lv[0] = fold<CPL>(a0);
+}
+
+// --- K_REF_UPDATE: x += scale * fp64(d).
+template <int CPL>
+__device__ __forceinline__ void body_ref_update(const PassArgs& a, int t, const Sc& sc) {
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const double sc_ = sc.al;
+  const int valid = g.nx - s.c;
+  for (int j = s.j0; j < s.j1; ++j) {
+    const size_t o = (size_t)j * g.pitch + s.c;
+    Row<double, CPL> x = ldrow<double, CPL>(a.x + o);
+    const Row<float, CPL> d = ldrow<float, CPL>(a.df + o);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x.e[k] = fma(sc_, (double)d.e[k], x.e[k]);
+    strow<double, CPL>(a.x + o, x, valid);
+  }
+}
+
+template <int KIND, int CPL>
+__device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  if constexpr (KIND == K_INIT_R) body_residual<CPL, true>(a, t, lv);
+  else if constexpr (KIND == K_RESID) body_residual<CPL, false>(a, t, lv);
+  else if constexpr (KIND == K_INIT_W) body_apply<CPL, true>(a, t, lv);
+  else if constexpr (KIND == K_APPLY) body_apply<CPL, false>(a, t, lv);
+  else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
+  else if constexpr (KIND == K_PCG) body_pcg<CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG1) body_cg1<double, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2) body_cg2<double, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG1F) body_cg1<float, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2F) body_cg2<float, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_REF_SCALE) body_ref_scale<CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_REF_UPDATE) body_ref_update<CPL>(a, t, sc);
+}
+
+// LDS per tile group: 4*2 doubles for the cross-tile stage, 2*4*2 for tiles.
+constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 2;
+
+// ------------------------------------------------------ multi-group pass --
+//
+// grid = G work-groups of 256 threads, G a multiple of 8.  Work-group b is
+// placed by the hardware on XCD b % 8; the tiles are split into 8 contiguous
+// bands, band x served by the work-groups of XCD x, so vertically adjacent
+// tiles (whose halo rows overlap) share an L2.
+template <int KIND, int CPL>
+__global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
+  __shared__ double lds[kLdsPerGroup];
+  constexpr int DI = ndots_in<KIND>(), DO = ndots_out<KIND>();
+  Sc sc;
+  if constexpr (KIND == K_APPLY || KIND == K_DOT) {
+    sc.al = sc.be = sc.inv = 0.0;
+    sc.first = false;
+  } else {
+    State s = *a.st_in;
+    double sum[2] = {0.0, 0.0};
+    if constexpr (DI > 0) {
+      const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
+      if (s.status == ST_RUNNING) {
+        if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
+        else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
+      }
+    }
+    const bool run = transition<KIND>(s, sum, sc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
+    if (!run) return;
+  }
+
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+  const int T = a.g.tiles;
+  const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
+  int par = 0;
+  for (int t = t0 + slot; t < t1; t += nb, par ^= 1) {
+    double lv[2];
+    run_body<KIND, CPL>(a, t, sc, lv);
+    if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
+  }
+}
+
+// res2 = cross-tile sum of slot 0 (true residual at exit); one work-group.
+__global__ __launch_bounds__(kGroup) void k_final(PassArgs a) {
+  __shared__ double lds[8];
+  double sum[1];
+  cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
+  if (threadIdx.x == 0) {
+    State s = *a.st_in;
+    s.res2 = sum[0];
+    *a.st_out = s;
+  }
+}
+
+__global__ void k_fill(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ------------------------------------------------- single work-group solve --
+//
+// The whole solve inside one work-group of kWgGroups tile groups for small
+// grids: the same pass bodies and the same reduction order as the
+// multi-work-group path, separated by work-group barriers instead of kernel
+// boundaries.  Group g handles tiles g, g+kWgGroups, ...; every group
+// evaluates the cross-tile stage itself (identical result).  Buffers: part_in/part_out are
+// the two partial buffers, w_in/w_out (pipelined) or pc_in/pc_out (classic)
+// the two halo buffers; st_in is the initial state, st_out the final one.
+template <int KIND>
+__device__ __forceinline__ void wg_pass(const PassArgs& a, const Sc& sc, double* lds) {
+  constexpr int DO = ndots_out<KIND>();
+  const int grp = threadIdx.x >> 8;
+  const int T = a.g.tiles;
+  // every group runs the same number of tile iterations (barrier balance)
+  const int iters = (T + kWgGroups - 1) / kWgGroups;
+  for (int i = 0, par = 0; i < iters; ++i, par ^= 1) {
+    const int t = grp + kWgGroups * i;
+    double lv[2] = {0.0, 0.0};
+    if (t < T) run_body<KIND, 2>(a, t, sc, lv);
+    if constexpr (DO > 0) {
+      // groups past the end join the barrier but store nothing
+      const int tid = threadIdx.x & (kGroup - 1), lane = tid & 63, wave = tid >> 6;
+      double* L = lds + par * kWavesPerTile * DO;
+#pragma unroll
+      for (int d = 0; d < DO; ++d) {
+        const double v = wave_sum(lv[d]);
+        if (lane == 0) L[wave * DO + d] = v;
+      }
+      __syncthreads();
+      if (tid == 0 && t < T) {
+#pragma unroll
+        for (int d = 0; d < DO; ++d) {
+          double s = L[d];
+#pragma unroll
+          for (int w = 1; w < kWavesPerTile; ++w) s = s + L[w * DO + d];
+          a.part_out[(size_t)d * T + t] = s;
+        }
+      }
+    }
+  }
+  __syncthreads();  // vectors and partials of this pass visible to the next
+}
+
+template <int KIND>
+__device__ __forceinline__ bool wg_step(State& s, const PassArgs& a, Sc& sc, double* lds) {
+  constexpr int DI = ndots_in<KIND>();
+  double sum[2] = {0.0, 0.0};
+  if (DI > 0 && s.status == ST_RUNNING) {
+    const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
+    if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
+    else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
+  }
+  const bool run = transition<KIND>(s, sum, sc);
+  if (run) wg_pass<KIND>(a, sc, lds + 8);
+  return run;
+}
+
+template <int VARIANT>
+__global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
+  __shared__ double lds_all[kWgGroups * kLdsPerGroup];
+  double* lds = lds_all + (threadIdx.x >> 8) * kLdsPerGroup;
+  State s = *a0.st_in;
+  double* P0 = const_cast<double*>(a0.part_in);
+  double* P1 = a0.part_out;
+  Sc sc;
+  PassArgs a = a0;
+  // r = b - A x
+  a.part_out = P0;
+  wg_step<K_INIT_R>(s, a, sc, lds);
+  double* cur = P0;  // partials produced by the last pass
+  double* nxt = P1;
+  if constexpr (VARIANT == 1) {
+    a.part_in = cur;
+    a.part_out = nxt;
+    a.w_out = const_cast<double*>(a0.w_in);
+    if (wg_step<K_INIT_W>(s, a, sc, lds)) {
+      double* t = cur; cur = nxt; nxt = t;
+    }
+    const double* Wi = a0.w_in;
+    double* Wo = a0.w_out;
+    while (s.status == ST_RUNNING) {
+      a.part_in = cur;
+      a.part_out = nxt;
+      a.w_in = Wi;
+      a.w_out = Wo;
+      if (!wg_step<K_PCG>(s, a, sc, lds)) break;
+      double* t = cur; cur = nxt; nxt = t;
+      const double* tw = Wi; Wi = Wo; Wo = const_cast<double*>(tw);
+    }
+  } else {
+    const double* Pi = a0.pc_in;
+    double* Po = a0.pc_out;
+    while (s.status == ST_RUNNING) {
+      a.part_in = cur;
+      a.part_out = nxt;
+      a.pc_in = Pi;
+      a.pc_out = Po;
+      if (!wg_step<K_CG1>(s, a, sc, lds)) break;
+      { double* t = cur; cur = nxt; nxt = t; }
+      a.part_in = cur;
+      a.part_out = nxt;
+      a.pc_in = Po;
+      if (!wg_step<K_CG2>(s, a, sc, lds)) break;
+      { double* t = cur; cur = nxt; nxt = t; }
+      const double* tp = Pi; Pi = Po; Po = const_cast<double*>(tp);
+    }
+  }
+  // true residual of the final iterate
+  if (s.status != ST_ZERO_RHS) {
+    a.part_out = nxt;
+    wg_step<K_RESID>(s, a, sc, lds);
+    double sum[1];
+    cross_tile_sum<1>(nxt, a.g.tiles, sum, lds);
+    s.res2 = sum[0];
+  }
+  if (threadIdx.x == 0) *a0.st_out = s;
+}
+
+// ---------------------------------------------------------------- launchers --
+
+template <int KIND>
+static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_t st) {
+  if (fp32g) hipLaunchKernelGGL((k_pass<KIND, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+  else hipLaunchKernelGGL((k_pass<KIND, 2>), dim3(grid), dim3(kGroup), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStream_t st) {
+  if (grid < 8 || (grid & 7)) return hipErrorInvalidValue;
+  switch (kind) {
+    case K_INIT_R: return launch_kind<K_INIT_R>(fp32g, a, grid, st);
+    case K_INIT_W: return launch_kind<K_INIT_W>(fp32g, a, grid, st);
+    case K_PCG: return launch_kind<K_PCG>(fp32g, a, grid, st);
+    case K_CG1: return launch_kind<K_CG1>(fp32g, a, grid, st);
+    case K_CG2: return launch_kind<K_CG2>(fp32g, a, grid, st);
+    case K_RESID: return launch_kind<K_RESID>(fp32g, a, grid, st);
+    case K_APPLY: return launch_kind<K_APPLY>(fp32g, a, grid, st);
+    case K_DOT: return launch_kind<K_DOT>(fp32g, a, grid, st);
+    case K_REF_SCALE:
+      hipLaunchKernelGGL((k_pass<K_REF_SCALE, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
+    case K_CG1F:
+      hipLaunchKernelGGL((k_pass<K_CG1F, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
+    case K_CG2F:
+      hipLaunchKernelGGL((k_pass<K_CG2F, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
+    case K_REF_UPDATE:
+      hipLaunchKernelGGL((k_pass<K_REF_UPDATE, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_final(const PassArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kGroup), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
+  if (bytes & 3) return hipErrorInvalidValue;
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  const int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t st) {
+  if (variant == 1) hipLaunchKernelGGL((k_solve_wg<1>), dim3(1), dim3(kWgGroups * kGroup), 0, st, a);
+  else hipLaunchKernelGGL((k_solve_wg<0>), dim3(1), dim3(kWgGroups * kGroup), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int KIND, int CPL>
+static int occ() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pass<KIND, CPL>, kGroup, 0) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+int pass_max_blocks_per_cu(int kind, int fp32g) {
+  switch (kind) {
+    case K_PCG: return fp32g ? occ<K_PCG, 4>() : occ<K_PCG, 2>();
+    case K_CG1: return fp32g ? occ<K_CG1, 4>() : occ<K_CG1, 2>();
+    case K_CG2: return fp32g ? occ<K_CG2, 4>() : occ<K_CG2, 2>();
+    case K_CG1F: return occ<K_CG1F, 4>();
+    case K_CG2F: return occ<K_CG2F, 4>();
+    default: return fp32g ? occ<K_RESID, 4>() : occ<K_RESID, 2>();
+  }
+}
+
+// Algorithmic HBM bytes per unknown of each pass (each vector read or written
+// once; halo re-reads are not counted).
+size_t pass_algorithmic_bytes(int kind, int64_t dof) {
+  size_t per = 0;
+  switch (kind) {
+    case K_INIT_R: per = 8 * 3; break;          // read x, b; write r
+    case K_INIT_W: per = 8 * 2; break;          // read r; write w
+    case K_PCG: per = 8 * 12; break;            // read x r w p q z; write x r w p q z
+    case K_CG1: per = 8 * 3; break;             // read r, p_old; write p
+    case K_CG2: per = 8 * 5; break;             // read p, x, r; write x, r
+    case K_RESID: per = 8 * 2; break;           // read x, b
+    case K_REF_SCALE: per = 8 * 2 + 4 * 2; break;  // read x, b; write rho, d
+    case K_CG1F: per = 4 * 3; break;
+    case K_CG2F: per = 4 * 5; break;
+    case K_REF_UPDATE: per = 8 * 2 + 4; break;  // read x, d; write x
+    case K_APPLY: per = 8 * 2; break;
+    case K_DOT: per = 8 * 2; break;
+  }
+  return per * (size_t)dof;
+}
+
+}  // namespace cgk

@@ -1,0 +1,822 @@
+// cg_runtime.cpp - host runtime of the stencil CG library: context, device
+// arena, planning, pass sequencing (with hipGraph-captured iteration chunks),
+// profiling, and the C ABI of include/cg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cg.h"
+#include "cg_internal.h"
+#include "cg_runtime.h"
+
+namespace cgr {
+
+using namespace cgk;
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ arena --
+
+void* Arena::alloc(size_t n) {
+  n = round_up(n ? n : 1, kAlign);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= n) {
+      size_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > n) free_[off + n] = sz - n;
+      used_[off] = n;
+      in_use_ += n;
+      return base_ + off;
+    }
+  }
+  return nullptr;
+}
+
+void Arena::release(void* p) {
+  if (!p) return;
+  size_t off = (size_t)((char*)p - base_);
+  auto it = used_.find(off);
+  if (it == used_.end()) return;
+  size_t n = it->second;
+  used_.erase(it);
+  in_use_ -= n;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && off + n == nx->first) {
+    n += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      pv->second += n;
+      return;
+    }
+  }
+  free_[off] = n;
+}
+
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (auto& kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
+// ------------------------------------------------------------- planning --
+
+static int32_t map_status(int32_t st) {
+  switch (st) {
+    case ST_OK:
+    case ST_ZERO_RHS: return CG_OK;
+    case ST_NOT_CONVERGED: return CG_NOT_CONVERGED;
+    case ST_BREAKDOWN: return CG_BREAKDOWN;
+    default: return CG_PENDING;
+  }
+}
+
+int validate(const cg_problem* p) {
+  if (!p) return CG_E_INVALID;
+  if (p->nx < 1 || p->ny < 1) return CG_E_INVALID;
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return CG_E_INVALID;
+  if (!(p->tol >= 0.0) || !(p->tol < 1.0)) return CG_E_INVALID;
+  if (p->maxit < 1) return CG_E_INVALID;
+  if (!p->b || !p->x) return CG_E_INVALID;
+  if (p->mem != CG_MEM_HOST && p->mem != CG_MEM_DEVICE) return CG_E_INVALID;
+  if (p->variant != CG_VARIANT_CLASSIC && p->variant != CG_VARIANT_PIPELINED) return CG_E_INVALID;
+  if (p->precision != CG_PREC_FP64 && p->precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
+  if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
+    return CG_E_INVALID;
+  return CG_OK;
+}
+
+Geo make_geo(int nx, int ny, int fp32g, int rows) {
+  Geo g;
+  const int cpl = fp32g ? 4 : 2, tw = kWave * cpl;
+  g.nx = nx;
+  g.ny = ny;
+  g.pitch = (int)round_up((size_t)nx, (size_t)tw);
+  g.ntx = g.pitch / tw;
+  g.rows = std::max(1, rows);
+  g.th = kWavesPerTile * g.rows;
+  g.nty = (ny + g.th - 1) / g.th;
+  g.tiles = g.ntx * g.nty;
+  return g;
+}
+
+int default_rows(int nx, int ny, int fp32g) {
+  const int cpl = fp32g ? 4 : 2, tw = kWave * cpl;
+  const int ntx = (nx + tw - 1) / tw;
+  // aim for about 1024 tiles (4 per CU) with strips of up to 32 rows: long
+  // strips amortise the halo rows, enough tiles keep every CU busy
+  const int want_nty = std::max(1, (1024 + ntx - 1) / ntx);
+  int rows = ny / (kWavesPerTile * want_nty);
+  return std::min(32, std::max(2, rows));
+}
+
+static int wg_rows(int nx, int ny) {
+  // one tile per group of the single work-group when the width allows
+  const int ntx = (nx + 2 * kWave - 1) / (2 * kWave);
+  const int nty = std::max(1, (kWgGroups + ntx - 1) / ntx);
+  return std::max(1, (ny + kWavesPerTile * nty - 1) / (kWavesPerTile * nty));
+}
+
+bool Ctx::use_wg(const cg_problem* p) const {
+  return p->precision == CG_PREC_FP64 && (int64_t)p->nx * p->ny <= wg_max_dof;
+}
+
+Plan Ctx::plan(const cg_problem* p) {
+  Plan pl;
+  pl.variant = p->variant;
+  pl.refined = p->precision == CG_PREC_FP32_REFINED;
+  pl.fp32g = pl.refined ? 1 : 0;
+  pl.wg = use_wg(p);
+  int rows, grid = 0;
+  if (pl.wg) {
+    rows = wg_rows(p->nx, p->ny);
+  } else {
+    auto it = pins.find(key(p->nx, p->ny, pl.fp32g));
+    if (it != pins.end()) {
+      rows = it->second.rows;
+      grid = it->second.grid;
+    } else {
+      rows = default_rows(p->nx, p->ny, pl.fp32g);
+    }
+  }
+  pl.g = make_geo(p->nx, p->ny, pl.fp32g, rows);
+  const int T = pl.g.tiles;
+  if (pl.wg) {
+    pl.grid = 1;
+  } else if (grid > 0) {
+    pl.grid = std::max(8, (int)round_up((size_t)grid, 8));
+  } else {
+    const int kind = pl.refined ? K_CG2F : (p->variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
+    const int cap = std::max(8, pass_max_blocks_per_cu(kind, pl.fp32g) * num_cu);
+    const int tpb = (T + cap - 1) / cap;          // tiles per work-group
+    pl.grid = (int)round_up((size_t)((T + tpb - 1) / tpb), 8);
+  }
+  const size_t elems = (size_t)pl.g.pitch * p->ny;
+  pl.v64 = round_up(elems * 8, Arena::kAlign);
+  pl.v32 = round_up(elems * 4, Arena::kAlign);
+  int n64, n32 = 0;
+  if (pl.refined) {
+    n64 = 2;  // b, x
+    n32 = 4;  // rho, d, p, p'
+  } else if (p->variant == CG_VARIANT_PIPELINED) {
+    n64 = 8;  // b, x, r, w, w', z, q, p
+  } else {
+    n64 = 5;  // b, x, r, p, p'
+  }
+  pl.part = round_up((size_t)2 * T * 8, Arena::kAlign);
+  pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256);
+  return pl;
+}
+
+size_t footprint_of(const cg_problem* p) {
+  // same arithmetic as Ctx::plan, without a device (tiling affects only the
+  // partial buffers, bounded here by one tile per 2 rows)
+  const int fp32g = p->precision == CG_PREC_FP32_REFINED;
+  Geo g = make_geo(p->nx, p->ny, fp32g, 1);
+  const size_t elems = (size_t)g.pitch * p->ny;
+  const size_t v64 = round_up(elems * 8, Arena::kAlign), v32 = round_up(elems * 4, Arena::kAlign);
+  size_t n64 = fp32g ? 2 : (p->variant == CG_VARIANT_PIPELINED ? 8 : 5);
+  size_t n32 = fp32g ? 4 : 0;
+  const size_t part = round_up((size_t)2 * g.tiles * 8, Arena::kAlign);
+  return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256);
+}
+
+// --------------------------------------------------------- profiling --
+
+void Ctx::prof_add(const char* name, double seconds, double bytes, int64_t launches) {
+  auto& s = stats[name];
+  s.launches += launches;
+  s.seconds += seconds;
+  s.bytes += bytes;
+}
+
+hipEvent_t Ctx::event() {
+  if (!ev_free.empty()) {
+    hipEvent_t e = ev_free.back();
+    ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Ctx::prof_collect() {
+  for (auto& pr : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.a, pr.b) == hipSuccess)
+      prof_add(pr.name, ms * 1e-3, pr.bytes, 1);
+    ev_free.push_back(pr.a);
+    ev_free.push_back(pr.b);
+  }
+  pending.clear();
+}
+
+static const char* kind_name(int kind, int fp32g) {
+  switch (kind) {
+    case K_INIT_R: return fp32g ? "init_r_f32geo" : "init_r";
+    case K_INIT_W: return "init_w";
+    case K_PCG: return "pcg_pass";
+    case K_CG1: return "stencil_dot";
+    case K_CG2: return "update_norm";
+    case K_RESID: return fp32g ? "resid_f32geo" : "resid";
+    case K_REF_SCALE: return "ref_scale";
+    case K_CG1F: return "stencil_dot_f32";
+    case K_CG2F: return "update_norm_f32";
+    case K_REF_UPDATE: return "ref_update";
+    case K_APPLY: return "apply";
+    case K_DOT: return "dot";
+  }
+  return "?";
+}
+
+// Launches one pass; with profiling on, brackets it by events.
+hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid) {
+  if (!prof || capturing) return launch_pass(kind, fp32g, a, grid, st);
+  hipEvent_t e0 = event(), e1 = event();
+  hipEventRecord(e0, st);
+  hipError_t rc = launch_pass(kind, fp32g, a, grid, st);
+  hipEventRecord(e1, st);
+  pending.push_back({e0, e1, kind_name(kind, fp32g),
+                     (double)pass_algorithmic_bytes(kind, (int64_t)a.g.nx * a.g.ny)});
+  return rc;
+}
+
+// ---------------------------------------------------------------- solve --
+
+// Workspace of one resident solve, carved from the arena.
+struct Work {
+  Plan pl;
+  char* mem = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *w[2] = {}, *z = nullptr, *q = nullptr,
+         *p = nullptr, *pc[2] = {};
+  float *rf = nullptr, *df = nullptr, *pf[2] = {};
+  double* part[2] = {};
+  State* S[2] = {};
+  int m = 0;  // passes issued (state/partial parity)
+  int i = 0;  // iterations issued (vector ping-pong parity)
+};
+
+static bool carve(Ctx& c, Work& w) {
+  w.mem = (char*)c.arena.alloc(w.pl.footprint);
+  if (!w.mem) return false;
+  char* q = w.mem;
+  auto take = [&](size_t n) {
+    char* r = q;
+    q += n;
+    return r;
+  };
+  const Plan& pl = w.pl;
+  w.b = (double*)take(pl.v64);
+  w.x = (double*)take(pl.v64);
+  if (pl.refined) {
+    w.rf = (float*)take(pl.v32);
+    w.df = (float*)take(pl.v32);
+    w.pf[0] = (float*)take(pl.v32);
+    w.pf[1] = (float*)take(pl.v32);
+  } else if (pl.variant == CG_VARIANT_PIPELINED) {
+    w.r = (double*)take(pl.v64);
+    w.w[0] = (double*)take(pl.v64);
+    w.w[1] = (double*)take(pl.v64);
+    w.z = (double*)take(pl.v64);
+    w.q = (double*)take(pl.v64);
+    w.p = (double*)take(pl.v64);
+  } else {
+    w.r = (double*)take(pl.v64);
+    w.pc[0] = (double*)take(pl.v64);
+    w.pc[1] = (double*)take(pl.v64);
+  }
+  w.part[0] = (double*)take(pl.part);
+  w.part[1] = (double*)take(pl.part);
+  w.S[0] = (State*)take(round_up(sizeof(State), 256));
+  w.S[1] = (State*)take(round_up(sizeof(State), 256));
+  return true;
+}
+
+static PassArgs base_args(const Work& w) {
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = w.pl.g;
+  a.b = w.b;
+  a.x = w.x;
+  a.r = w.r;
+  a.z = w.z;
+  a.q = w.q;
+  a.p = w.p;
+  a.rf = w.rf;
+  a.df = w.df;
+  return a;
+}
+
+// Issues one pass of the solve with the state/partial double buffers of pass
+// number w.m; `mod` sets the vector ping-pong pointers.
+template <class F>
+static hipError_t issue(Ctx& c, Work& w, int kind, F mod) {
+  PassArgs a = base_args(w);
+  a.st_in = w.S[w.m & 1];
+  a.st_out = w.S[(w.m + 1) & 1];
+  a.part_in = w.part[w.m & 1];
+  a.part_out = w.part[(w.m + 1) & 1];
+  mod(a);
+  w.m++;
+  return c.pass(kind, w.pl.fp32g, a, w.pl.grid);
+}
+
+static hipError_t issue_iteration(Ctx& c, Work& w) {
+  hipError_t e;
+  const int i = w.i;
+  if (w.pl.refined) {
+    e = issue(c, w, K_CG1F, [&](PassArgs& a) {
+      a.pf_in = w.pf[i & 1];
+      a.pf_out = w.pf[(i + 1) & 1];
+    });
+    if (e == hipSuccess)
+      e = issue(c, w, K_CG2F, [&](PassArgs& a) { a.pf_in = w.pf[(i + 1) & 1]; });
+  } else if (w.pl.variant == CG_VARIANT_PIPELINED) {
+    e = issue(c, w, K_PCG, [&](PassArgs& a) {
+      a.w_in = w.w[i & 1];
+      a.w_out = w.w[(i + 1) & 1];
+    });
+  } else {
+    e = issue(c, w, K_CG1, [&](PassArgs& a) {
+      a.pc_in = w.pc[i & 1];
+      a.pc_out = w.pc[(i + 1) & 1];
+    });
+    if (e == hipSuccess)
+      e = issue(c, w, K_CG2, [&](PassArgs& a) { a.pc_in = w.pc[(i + 1) & 1]; });
+  }
+  w.i++;
+  return e;
+}
+
+#define HIPCHK(x)                                     \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) {                           \
+      c.last_error = hipGetErrorString(e_);           \
+      return CG_E_DEVICE;                             \
+    }                                                 \
+  } while (0)
+
+// Reads the state the next pass would read (after w.m passes).
+static int read_state(Ctx& c, Work& w, State& out) {
+  HIPCHK(hipMemcpyAsync(c.host_state, w.S[w.m & 1], sizeof(State), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  if (c.prof) c.prof_collect();
+  memcpy(&out, c.host_state, sizeof(State));
+  return CG_OK;
+}
+
+// Runs `iters` iterations as one hipGraph replay; the graph is cached per
+// workspace layout, chunk length and buffer parity.
+static int run_chunk(Ctx& c, Work& w, int iters) {
+  const bool graphs = c.graph_chunk > 0 && !c.prof;
+  if (!graphs) {
+    for (int k = 0; k < iters; ++k) HIPCHK(issue_iteration(c, w));
+    return CG_OK;
+  }
+  GraphKey key{w.mem, w.pl.g.nx, w.pl.g.ny, w.pl.g.rows, w.pl.grid, w.pl.variant,
+               w.pl.refined, iters, w.m & 1, w.i & 1};
+  auto it = c.graphs.find(key);
+  if (it == c.graphs.end()) {
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
+    c.capturing = true;
+    const int m0 = w.m, i0 = w.i;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < iters && e == hipSuccess; ++k) e = issue_iteration(c, w);
+    c.capturing = false;
+    hipError_t e2 = hipStreamEndCapture(c.st, &g);
+    w.m = m0;
+    w.i = i0;
+    HIPCHK(e);
+    HIPCHK(e2);
+    hipGraphExec_t ge;
+    hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(e3);
+    if (c.graphs.size() > 64) {
+      for (auto& kv : c.graphs) hipGraphExecDestroy(kv.second);
+      c.graphs.clear();
+    }
+    it = c.graphs.emplace(key, ge).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, c.st));
+  w.m += iters * (w.pl.variant == CG_VARIANT_PIPELINED && !w.pl.refined ? 1 : 2);
+  w.i += iters;
+  return CG_OK;
+}
+
+void Ctx::forget_graphs(const void* mem) {
+  for (auto it = graphs.begin(); it != graphs.end();) {
+    if (it->first.mem == mem) {
+      hipGraphExecDestroy(it->second);
+      it = graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+static int stage_in(Ctx& c, Work& w, const cg_problem* p) {
+  const Plan& pl = w.pl;
+  HIPCHK(launch_fill(w.mem, pl.footprint, c.st));
+  const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyHostToDevice
+                                                   : hipMemcpyDeviceToDevice;
+  const size_t row = (size_t)p->nx * 8, pitch = (size_t)pl.g.pitch * 8;
+  HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, p->ny, kind, c.st));
+  if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, p->ny, kind, c.st));
+  State s;
+  memset(&s, 0, sizeof(s));
+  s.status = ST_RUNNING;
+  s.flags = F_BB_PENDING;
+  s.tol = p->tol;
+  s.inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
+  s.maxit = p->maxit;
+  memcpy(c.host_state, &s, sizeof(s));
+  HIPCHK(hipMemcpyAsync(w.S[0], c.host_state, sizeof(State), hipMemcpyHostToDevice, c.st));
+  // the pinned staging buffer is reused below: wait for this copy
+  HIPCHK(hipStreamSynchronize(c.st));
+  w.m = 0;
+  w.i = 0;
+  return CG_OK;
+}
+
+static int stage_out(Ctx& c, Work& w, const cg_problem* p, const State& s) {
+  const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyDeviceToHost
+                                                   : hipMemcpyDeviceToDevice;
+  const size_t row = (size_t)p->nx * 8, pitch = (size_t)w.pl.g.pitch * 8;
+  if (s.status == ST_ZERO_RHS) {
+    if (p->mem == CG_MEM_HOST) memset(p->x, 0, row * p->ny);
+    else HIPCHK(hipMemsetAsync(p->x, 0, row * p->ny, c.st));
+  } else {
+    HIPCHK(hipMemcpy2DAsync(p->x, row, w.x, pitch, row, p->ny, kind, c.st));
+  }
+  HIPCHK(hipStreamSynchronize(c.st));
+  return CG_OK;
+}
+
+static void fill_result(const State& s, cg_result* res, double secs) {
+  memset(res, 0, sizeof(*res));
+  res->status = map_status(s.status);
+  res->iterations = s.k;
+  res->outer_iterations = s.outer;
+  if (s.status == ST_ZERO_RHS) {
+    res->iterations = 0;
+    res->rel_res_recursive = res->rel_res_true = 0.0;
+  } else {
+    res->rel_res_recursive = std::sqrt(s.gamma / s.bb);
+    res->rel_res_true = std::sqrt(s.res2 / s.bb);
+  }
+  res->device_seconds = secs;
+  res->latency_seconds = secs;
+}
+
+static int chunk_iters(Ctx& c, const Work& w) {
+  int k = c.graph_chunk > 0 ? c.graph_chunk : 32;
+  // small grids: longer chunks (launch-bound); keep it even
+  const int64_t dof = (int64_t)w.pl.g.nx * w.pl.g.ny;
+  if (dof < 512 * 512) k *= 4;
+  else if (dof < 2048 * 2048) k *= 2;
+  return std::max(2, k & ~1);
+}
+
+static int solve_tiled(Ctx& c, Work& w, const cg_problem* p, State& s) {
+  int rc;
+  if (w.pl.refined) {
+    // outer loop: resid -> scale -> inner chunks -> update
+    HIPCHK(issue(c, w, K_RESID, [](PassArgs&) {}));
+    HIPCHK(issue(c, w, K_REF_SCALE, [](PassArgs&) {}));
+    for (;;) {
+      if ((rc = read_state(c, w, s))) return rc;
+      if (s.status != ST_RUNNING) break;
+      w.i = 0;  // inner direction ping-pong restarts every inner solve
+      for (;;) {
+        if ((rc = run_chunk(c, w, chunk_iters(c, w)))) return rc;
+        if ((rc = read_state(c, w, s))) return rc;
+        if (s.status != ST_RUNNING) break;
+      }
+      if (s.status != ST_INNER_DONE) break;
+      HIPCHK(issue(c, w, K_REF_UPDATE, [](PassArgs&) {}));
+      HIPCHK(issue(c, w, K_RESID, [](PassArgs&) {}));
+      HIPCHK(issue(c, w, K_REF_SCALE, [](PassArgs&) {}));
+    }
+    return CG_OK;
+  }
+  HIPCHK(issue(c, w, K_INIT_R, [](PassArgs&) {}));
+  if (w.pl.variant == CG_VARIANT_PIPELINED)
+    HIPCHK(issue(c, w, K_INIT_W, [&](PassArgs& a) { a.w_out = w.w[0]; }));
+  const int K = chunk_iters(c, w);
+  for (;;) {
+    // never issue iterations past maxit: the device would run them as no-ops
+    const int left = p->maxit - w.i;
+    if ((rc = run_chunk(c, w, left > 0 ? std::min(K, left) : 2))) return rc;
+    if ((rc = read_state(c, w, s))) return rc;
+    if (s.status != ST_RUNNING) break;
+  }
+  if (s.status != ST_ZERO_RHS) {
+    HIPCHK(issue(c, w, K_RESID, [](PassArgs&) {}));
+    PassArgs a = base_args(w);
+    a.st_in = w.S[w.m & 1];
+    a.st_out = w.S[(w.m + 1) & 1];
+    a.part_in = w.part[w.m & 1];
+    w.m++;
+    HIPCHK(launch_final(a, c.st));
+    if ((rc = read_state(c, w, s))) return rc;
+  }
+  return CG_OK;
+}
+
+static int solve_wg(Ctx& c, Work& w, const cg_problem* p, State& s) {
+  PassArgs a = base_args(w);
+  a.st_in = w.S[0];
+  a.st_out = w.S[1];
+  a.part_in = w.part[0];
+  a.part_out = w.part[1];
+  if (p->variant == CG_VARIANT_PIPELINED) {
+    a.w_in = w.w[0];
+    a.w_out = w.w[1];
+  } else {
+    a.pc_in = w.pc[0];
+    a.pc_out = w.pc[1];
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.prof) {
+    e0 = c.event();
+    e1 = c.event();
+    hipEventRecord(e0, c.st);
+  }
+  HIPCHK(launch_solve_wg(p->variant, a, c.st));
+  if (c.prof) {
+    hipEventRecord(e1, c.st);
+    c.pending.push_back({e0, e1, "solve_wg", 0.0});
+  }
+  w.m = 1;
+  return read_state(c, w, s);
+}
+
+int Ctx::solve(const cg_problem* p, cg_result* res) {
+  Ctx& c = *this;
+  const double t0 = now_s();
+  Work w;
+  w.pl = plan(p);
+  if (w.pl.footprint > arena.size()) return CG_E_NOMEM;
+  if (!carve(c, w)) return CG_E_NOMEM;
+  struct Release {
+    Ctx& c;
+    Work& w;
+    ~Release() { c.arena.release(w.mem); }
+  } rel{c, w};
+  int rc = order_after_user();
+  if (rc) return rc;
+  if ((rc = stage_in(c, w, p))) return rc;
+  State s;
+  rc = w.pl.wg ? solve_wg(c, w, p, s) : solve_tiled(c, w, p, s);
+  if (rc) return rc;
+  if ((rc = stage_out(c, w, p, s))) return rc;
+  fill_result(s, res, now_s() - t0);
+  return res->status;
+}
+
+int Ctx::order_after_user() {
+  if (!user_stream) return CG_OK;
+  Ctx& c = *this;
+  HIPCHK(hipEventRecord(user_ev, user_stream));
+  HIPCHK(hipStreamWaitEvent(st, user_ev, 0));
+  return CG_OK;
+}
+
+// ------------------------------------------------------- building blocks --
+
+int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u,
+                      const double* y_in, double* y_out, double* dot_out) {
+  Ctx& c = *this;
+  cg_problem p;
+  memset(&p, 0, sizeof(p));
+  p.nx = nx;
+  p.ny = ny;
+  p.maxit = 1;
+  p.variant = CG_VARIANT_CLASSIC;
+  p.precision = CG_PREC_FP64;
+  // the same geometry (hence reduction order) a solve of this shape uses;
+  // always run by the multi-work-group pass kernels
+  Plan pl = plan(&p);
+  if (pl.wg) {
+    const int cap = std::max(8, pass_max_blocks_per_cu(kind, 0) * num_cu);
+    pl.grid = (int)round_up((size_t)std::min(pl.g.tiles, cap), 8);
+  }
+  const size_t need = 2 * pl.v64 + pl.part + round_up(sizeof(State), 256);
+  char* m = (char*)arena.alloc(need);
+  if (!m) return CG_E_NOMEM;
+  struct Rel {
+    Arena& a;
+    char* m;
+    ~Rel() { a.release(m); }
+  } rel{arena, m};
+  double* U = (double*)m;
+  double* Y = (double*)(m + pl.v64);
+  double* part = (double*)(m + 2 * pl.v64);
+  State* S = (State*)(m + 2 * pl.v64 + pl.part);
+  int rc = order_after_user();
+  if (rc) return rc;
+  HIPCHK(launch_fill(m, need, st));
+  const hipMemcpyKind kin = mem == CG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const size_t row = (size_t)nx * 8, pitch = (size_t)pl.g.pitch * 8;
+  HIPCHK(hipMemcpy2DAsync(U, pitch, u, row, row, ny, kin, st));
+  if (kind == K_DOT) HIPCHK(hipMemcpy2DAsync(Y, pitch, y_in, row, row, ny, kin, st));
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = pl.g;
+  a.u = U;
+  a.y = Y;
+  a.part_out = part;
+  HIPCHK(pass(kind, 0, a, pl.grid));
+  if (kind == K_APPLY) {
+    const hipMemcpyKind kout =
+        mem == CG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    HIPCHK(hipMemcpy2DAsync(y_out, row, Y, pitch, row, ny, kout, st));
+  } else {
+    PassArgs f;
+    memset(&f, 0, sizeof(f));
+    f.g = pl.g;
+    f.part_in = part;
+    f.st_in = S;  // zero-filled state; res2 receives the sum
+    f.st_out = S;
+    HIPCHK(launch_final(f, st));
+    HIPCHK(hipMemcpyAsync(host_state, S, sizeof(State), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (prof) prof_collect();
+  if (kind == K_DOT) {
+    State s;
+    memcpy(&s, host_state, sizeof(s));
+    *dot_out = s.res2;
+  }
+  return CG_OK;
+}
+
+// ---------------------------------------------------------- autotuner --
+
+int Ctx::tune(int nx, int ny, int variant, int precision) {
+  cg_problem p;
+  memset(&p, 0, sizeof(p));
+  p.nx = nx;
+  p.ny = ny;
+  p.variant = (cg_variant)variant;
+  p.precision = (cg_precision)precision;
+  p.tol = 0.0;
+  p.maxit = 8;
+  p.mem = CG_MEM_DEVICE;
+  if (use_wg(&p)) return CG_OK;  // single work-group path: nothing to tune
+  const int fp32g = precision == CG_PREC_FP32_REFINED;
+  const size_t n = (size_t)nx * ny;
+  void* bx = arena.alloc(2 * n * 8);
+  if (!bx) return CG_E_NOMEM;
+  double* b = (double*)bx;
+  double* x = b + n;
+  Ctx& c = *this;
+  HIPCHK(launch_fill(bx, 2 * n * 8, st));
+  // b = 1 everywhere is enough for timing: tol = 0 runs a fixed number of passes
+  std::vector<double> ones(std::min<size_t>(n, 1 << 20), 1.0);
+  for (size_t o = 0; o < n; o += ones.size()) {
+    size_t k = std::min(ones.size(), n - o);
+    HIPCHK(hipMemcpyAsync(b + o, ones.data(), k * 8, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  p.b = b;
+  p.x = x;
+  const auto k = key(nx, ny, fp32g);
+  const bool had = pins.count(k) != 0;
+  const Pin saved = had ? pins[k] : Pin{};
+  const int kind = fp32g ? K_CG2F : (variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
+  const int cap = std::max(8, pass_max_blocks_per_cu(kind, fp32g) * num_cu);
+  double best = 1e30;
+  Pin bestp{default_rows(nx, ny, fp32g), 0};
+  const bool save_prof = prof;
+  prof = false;
+  for (int rows : {2, 4, 8, 12, 16, 24, 32}) {
+    Geo g = make_geo(nx, ny, fp32g, rows);
+    std::vector<int> grids;
+    for (int div : {1, 2, 3, 4}) {
+      int gsz = (int)round_up((size_t)std::max(8, cap / div), 8);
+      if (gsz > (int)round_up((size_t)g.tiles, 8)) gsz = (int)round_up((size_t)g.tiles, 8);
+      if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
+    }
+    for (int gsz : grids) {
+      pins[k] = Pin{rows, gsz};
+      cg_result r;
+      int rc = solve(&p, &r);  // warm (graph capture, caches)
+      if (rc < 0) continue;
+      double t = 1e30;
+      for (int rep = 0; rep < 3; ++rep) {
+        rc = solve(&p, &r);
+        if (rc < 0) break;
+        t = std::min(t, r.device_seconds);
+      }
+      if (t < best) {
+        best = t;
+        bestp = Pin{rows, gsz};
+      }
+    }
+  }
+  prof = save_prof;
+  pins[k] = bestp;
+  (void)had;
+  (void)saved;
+  arena.release(bx);
+  save_tune_cache();
+  return CG_OK;
+}
+
+void Ctx::load_tune_cache() {
+  if (tune_path.empty()) return;
+  FILE* f = fopen(tune_path.c_str(), "r");
+  if (!f) return;
+  int nx, ny, fp, rows, grid;
+  // one entry per line: nx ny fp32geometry rows grid
+  while (fscanf(f, "%d %d %d %d %d", &nx, &ny, &fp, &rows, &grid) == 5)
+    pins[key(nx, ny, fp)] = Pin{rows, grid};
+  fclose(f);
+}
+
+void Ctx::save_tune_cache() {
+  if (tune_path.empty()) return;
+  FILE* f = fopen(tune_path.c_str(), "w");
+  if (!f) return;
+  for (auto& kv : pins)
+    fprintf(f, "%d %d %d %d %d\n", (int)(kv.first >> 33), (int)((kv.first >> 1) & 0xffffffff),
+            (int)(kv.first & 1), kv.second.rows, kv.second.grid);
+  fclose(f);
+}
+
+// --------------------------------------------------------------- create --
+
+int Ctx::init(const cg_config* cfg) {
+  Ctx& c = *this;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return CG_E_DEVICE;
+  device = cfg ? cfg->device : 0;
+  if (device < 0 || device >= ndev) return CG_E_DEVICE;
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  num_cu = prop.multiProcessorCount;
+  HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&user_ev, hipEventDisableTiming));
+  HIPCHK(hipHostMalloc((void**)&host_state, 4096, hipHostMallocDefault));
+  user_stream = cfg ? (hipStream_t)cfg->stream : nullptr;
+  size_t bytes = cfg ? cfg->arena_bytes : 0;
+  void* base = cfg ? cfg->arena : nullptr;
+  if (!base) {
+    if (bytes == 0) bytes = (size_t)4 << 30;
+    HIPCHK(hipMalloc(&base, bytes));
+    own_arena = base;
+  } else if (bytes == 0) {
+    return CG_E_INVALID;
+  }
+  arena.init((char*)base, bytes);
+  max_slots = (cfg && cfg->max_slots > 0) ? cfg->max_slots : 256;
+  if (cfg && cfg->tune_cache) tune_path = cfg->tune_cache;
+  if (const char* e = getenv("CG_GRAPH_CHUNK")) graph_chunk = atoi(e);
+  if (const char* e = getenv("CG_WG_MAX_DOF")) wg_max_dof = atoi(e);
+  load_tune_cache();
+  return CG_OK;
+}
+
+Ctx::~Ctx() {
+  hipSetDevice(device);
+  if (st) hipStreamSynchronize(st);
+  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  for (auto& pr : pending) {
+    hipEventDestroy(pr.a);
+    hipEventDestroy(pr.b);
+  }
+  for (auto e : ev_free) hipEventDestroy(e);
+  if (user_ev) hipEventDestroy(user_ev);
+  if (host_state) hipHostFree(host_state);
+  if (own_arena) hipFree(own_arena);
+  if (st) hipStreamDestroy(st);
+}
+
+}  // namespace cgr

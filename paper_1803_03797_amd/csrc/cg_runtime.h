@@ -1,0 +1,139 @@
+// cg_runtime.h - host runtime types of the stencil CG library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cg.h"
+#include "cg_internal.h"
+
+namespace cgr {
+
+// First-fit allocator over one device region (the caller's arena tensor or a
+// region the library allocated).  256-byte granularity; neighbours coalesce.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  void init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    used_.clear();
+    in_use_ = 0;
+    free_[0] = size;
+  }
+  void* alloc(size_t n);
+  void release(void* p);
+  size_t largest_free() const;
+  size_t size() const { return size_; }
+  size_t in_use() const { return in_use_; }
+  char* base() const { return base_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, in_use_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  std::map<size_t, size_t> used_;
+};
+
+struct Plan {
+  int variant = 0;
+  bool refined = false;
+  int fp32g = 0;     // geometry of the FP32 lanes (4 columns per lane)
+  bool wg = false;   // whole solve inside one work-group
+  cgk::Geo g{};
+  int grid = 8;      // work-groups per pass
+  size_t v64 = 0, v32 = 0, part = 0, footprint = 0;
+};
+
+struct Pin {
+  int rows = 0;
+  int grid = 0;
+};
+
+struct GraphKey {
+  const void* mem;
+  int nx, ny, rows, grid, variant, refined, iters, mpar, ipar;
+  bool operator<(const GraphKey& o) const {
+    const int a[] = {nx, ny, rows, grid, variant, refined, iters, mpar, ipar};
+    const int b[] = {o.nx, o.ny, o.rows, o.grid, o.variant, o.refined, o.iters, o.mpar, o.ipar};
+    if (mem != o.mem) return mem < o.mem;
+    for (int i = 0; i < 9; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+
+struct KStat {
+  int64_t launches = 0;
+  double seconds = 0.0, bytes = 0.0;
+};
+
+struct PendingEv {
+  hipEvent_t a, b;
+  const char* name;
+  double bytes;
+};
+
+int validate(const cg_problem* p);
+size_t footprint_of(const cg_problem* p);
+cgk::Geo make_geo(int nx, int ny, int fp32g, int rows);
+int default_rows(int nx, int ny, int fp32g);
+
+class Server;  // serving scheduler (cg_serve.cpp)
+
+struct Ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t st = nullptr;
+  hipStream_t user_stream = nullptr;
+  hipEvent_t user_ev = nullptr;
+  void* own_arena = nullptr;
+  Arena arena;
+  int max_slots = 256;
+  std::string tune_path;
+  std::recursive_mutex mu;
+  char* host_state = nullptr;  // pinned staging for state words
+  int graph_chunk = 32;        // iterations per captured chunk; 0 = plain launches
+  int wg_max_dof = 16384;      // whole-solve-in-one-work-group threshold (FP64)
+  bool capturing = false;
+  bool prof = false;
+  std::string last_error;
+  std::map<uint64_t, Pin> pins;  // tile shape pinned per grid shape
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<std::string, KStat> stats;
+  std::vector<PendingEv> pending;
+  std::vector<hipEvent_t> ev_free;
+  Server* server = nullptr;
+
+  static uint64_t key(int nx, int ny, int fp32g) {
+    return ((uint64_t)(uint32_t)nx << 33) | ((uint64_t)(uint32_t)ny << 1) | (uint64_t)(fp32g & 1);
+  }
+  int init(const cg_config* cfg);
+  ~Ctx();
+  bool use_wg(const cg_problem* p) const;
+  Plan plan(const cg_problem* p);
+  int solve(const cg_problem* p, cg_result* res);
+  int solve_batch(const cg_problem* p, int n, cg_result* res);
+  int apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u, const double* y_in,
+                   double* y_out, double* dot_out);
+  int tune(int nx, int ny, int variant, int precision);
+  void load_tune_cache();
+  void save_tune_cache();
+  int order_after_user();
+  hipError_t pass(int kind, int fp32g, const cgk::PassArgs& a, int grid);
+  hipEvent_t event();
+  void prof_add(const char* name, double seconds, double bytes, int64_t launches);
+  void prof_collect();
+  void forget_graphs(const void* mem);
+};
+
+}  // namespace cgr
+
+// Serving front end (cg_serve.cpp).
+int cgr_server_submit(cgr::Ctx* c, const cg_problem* p, uint64_t* ticket);
+int cgr_server_poll(cgr::Ctx* c, uint64_t ticket, cg_result* res);
+void cgr_server_stop(cgr::Ctx* c);

@@ -1,0 +1,76 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function the
+header declares, and its host-only calls (validation, footprint) behave.  No
+compute call is made without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1803_03797_amd import cg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "cg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(cg_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cg.load()
+    names = header_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(cg.SYMBOLS) == names
+
+
+def test_status_strings():
+    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5):
+        assert cg.cg_status_str(code).startswith("CG_")
+    assert cg.cg_status_str(99) == "CG_UNKNOWN"
+    assert "gfx950" in cg.cg_version()
+
+
+def _prob(**kw):
+    d = dict(nx=10, ny=7, mem=cg.CG_MEM_HOST, b=1, x0=None, x=2, tol=1e-8, maxit=10,
+             variant=0, precision=0, inner_tol=0.0)
+    d.update(kw)
+    return cg.cg_problem(d["nx"], d["ny"], d["mem"], d["b"], d["x0"], d["x"], d["tol"],
+                         d["maxit"], d["variant"], d["precision"], d["inner_tol"])
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
+                                 dict(tol=float("nan")), dict(maxit=0), dict(b=None),
+                                 dict(x=None), dict(mem=7), dict(variant=2), dict(precision=5),
+                                 dict(precision=1, inner_tol=1.5)])
+def test_validation_rejects(bad):
+    assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
+
+
+def test_validation_accepts():
+    assert cg.cg_validate(_prob()) == cg.CG_OK
+    assert cg.cg_validate(_prob(tol=0.0, precision=1, inner_tol=0.0)) == cg.CG_OK
+
+
+def test_footprint_per_unknown():
+    """Resident bytes per unknown: classic 5 FP64 vectors, pipelined 8, refined
+    2 FP64 + 4 FP32 (plus padding and small partial/state buffers)."""
+    n = 4096
+    for variant, prec, per in ((0, 0, 40), (1, 0, 64), (0, 1, 32)):
+        fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, precision=prec))
+        assert per * n * n <= fp <= per * n * n * 1.01 + (1 << 20)
+
+
+def test_create_without_gpu_fails_cleanly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = cg.load()
+    h = C.c_void_p()
+    cfg = cg.cg_config(0, None, None, 0, 0, None)
+    assert lib.cg_create(C.byref(cfg), C.byref(h)) == cg.CG_E_DEVICE
+    assert not h.value
+    assert lib.cg_destroy(None) == cg.CG_E_INVALID
