@@ -70,6 +70,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libcg.so is not built: run paper_1803_03797_amd/build.py "
                            "(or __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's; load it
+    # first so that a process using both has exactly one runtime (torch's).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P, I, D = C.c_void_p, C.c_int32, C.c_double
     sig = {

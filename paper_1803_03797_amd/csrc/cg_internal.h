@@ -108,12 +108,56 @@ struct PassArgs {
   double* y;
 };
 
+// Scalars a pass body needs, chosen by the preceding transition.
+struct Sc {
+  double al, be;
+  int32_t first;   // first iteration: previous direction vectors are zero
+  int32_t pad_;
+  double inv;      // refinement: 1 / scale
+};
+
+// One resident solve of the persistent batch kernel.  Static fields are
+// written by the host at admission; the dynamic ones by the work-group that
+// completes the last tile of a pass (the "closer").
+struct alignas(64) Slot {
+  Geo g;
+  int32_t variant, refined;
+  double* b;
+  double* x;
+  double* r;
+  double* z;
+  double* q;
+  double* p;
+  double* W[2];      // pipelined w ping-pong
+  double* PC[2];     // classic direction ping-pong
+  float* rf;
+  float* df;
+  float* PF[2];      // refinement inner direction ping-pong
+  double* part[2];   // per-tile partials, by pass parity
+  State* st;
+  // dynamic
+  int32_t active;    // 1 while the solve has passes left
+  int32_t kind;      // pass kind of the current epoch
+  int32_t iter;      // iteration counter (vector ping-pong parity)
+  int32_t pad_;
+  Sc sc;             // scalars of the current epoch
+  unsigned long long claim;  // (epoch << 32) | next unclaimed tile
+  unsigned int done;         // tiles completed in the current epoch
+  unsigned int pad2_;
+};
+
 // Host-side launchers (cg_kernels.hip).
 hipError_t launch_pass(int kind, int fp32_geometry, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slot 0
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
+// Persistent batch kernel over nslots slots; returns when no solve is left,
+// when budget_ticks of the device wall clock have passed, or after idle_ticks
+// without claimable work.  *remaining counts the unfinished active slots.
+hipError_t launch_batch(Slot* slots, int nslots, int* remaining, long long budget_ticks,
+                        long long idle_ticks, int grid, hipStream_t s);
+int batch_max_blocks_per_cu();
 size_t pass_algorithmic_bytes(int kind, int64_t dof);
 
 }  // namespace cgk

@@ -170,11 +170,6 @@ __device__ __forceinline__ void edges(const T* row, const Strip& s, const Geo& g
 
 // ---------------------------------------------------------- scalar step --
 
-struct Sc {
-  double al, be;
-  bool first;  // first iteration: previous direction vectors are zero
-  double inv;  // refinement: 1/scale
-};
 
 __device__ __forceinline__ int stop_code(double gamma, double thr, int k, int maxit, double tol) {
   if (!isfinite(gamma)) return ST_BREAKDOWN;
@@ -190,7 +185,8 @@ template <int KIND>
 __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) {
   sc.al = 0.0;
   sc.be = 0.0;
-  sc.first = false;
+  sc.first = 0;
+  sc.pad_ = 0;
   sc.inv = 0.0;
   if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
     return true;
@@ -214,7 +210,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
       if (s.k == 0) {
         if (!(delta > 0.0) || !isfinite(delta)) st = ST_BREAKDOWN;
         else al = gamma / delta;
-        sc.first = true;
+        sc.first = 1;
       } else {
         be = gamma / s.gamma;
         const double den = delta / gamma - be / s.alpha;
@@ -247,7 +243,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     }
     const int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
     double be = 0.0;
-    if (s.k == 0) sc.first = true;
+    if (s.k == 0) sc.first = 1;
     else be = gamma / s.gamma;
     s.gamma = gamma;
     s.status = st;
@@ -298,7 +294,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     if (s.kin == 0) {
       s.gamma0 = gamma;
       s.thr_in = (s.inner_tol * s.inner_tol) * gamma;
-      sc.first = true;
+      sc.first = 1;
     } else {
       be = gamma / s.gamma;
     }
@@ -839,7 +835,8 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   Sc sc;
   if constexpr (KIND == K_APPLY || KIND == K_DOT) {
     sc.al = sc.be = sc.inv = 0.0;
-    sc.first = false;
+    sc.first = 0;
+    sc.pad_ = 0;
   } else {
     State s = *a.st_in;
     double sum[2] = {0.0, 0.0};
@@ -1002,6 +999,253 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
     s.res2 = sum[0];
   }
   if (threadIdx.x == 0) *a0.st_out = s;
+}
+
+// ------------------------------------------------------ persistent batch --
+//
+// One launch serves many solves.  Every solve is a sequence of passes (the
+// same passes, bodies and transitions as a single solve); a pass of solve s is
+// "epoch" e of that solve and consists of its tiles.  Work-groups claim
+// (solve, tile) items with one 64-bit atomic per claim (epoch in the high
+// word, next tile in the low word), process the tile, and count it done.  The
+// work-group completing the last tile of an epoch (the closer) sums the
+// epoch's partials, applies the scalar transition of the next pass, picks the
+// next pass kind and publishes the next epoch.  A work-group never waits while
+// it holds work, so progress needs no co-residency; it leaves when every solve
+// is finished, when the launch's time budget is spent (the host relaunches;
+// claimed-but-unfinished work never exists outside a running work-group), or
+// after idle_ticks without claimable work.
+//
+// Cross-XCD visibility: agent-scope fences (L2 write-back / invalidate on
+// gfx950) separate a tile's stores from the done-count, the closer's reads from
+// the done-count, the closer's stores from the publish, and a claim from the
+// tile's loads.
+
+constexpr unsigned kClaimClosed = 0x80000000u;  // low word of a finished solve
+
+__device__ __forceinline__ int ndots_out_rt(int kind) {
+  switch (kind) {
+    case K_INIT_R: case K_INIT_W: case K_PCG: case K_RESID: return 2;
+    case K_CG1: case K_CG2: case K_REF_SCALE: case K_CG1F: case K_CG2F: return 1;
+  }
+  return 0;
+}
+
+template <int KIND, int CPL>
+__device__ __forceinline__ void batch_body(const PassArgs& a, int t, const Sc& sc, double* part,
+                                           double* lds, int par) {
+  constexpr int DO = ndots_out<KIND>();
+  double lv[2] = {0.0, 0.0};
+  run_body<KIND, CPL>(a, t, sc, lv);
+  if constexpr (DO > 0) {
+    tile_partial<DO>(lv, part, a.g.tiles, t, lds, par);
+  }
+}
+
+__device__ __forceinline__ void batch_tile(const Slot& S, int kind, int iter, const Sc& sc, int t,
+                                           double* part, double* lds, int par) {
+  PassArgs a;
+  a.g = S.g;
+  a.st_in = nullptr;
+  a.st_out = nullptr;
+  a.part_in = nullptr;
+  a.part_out = part;
+  a.b = S.b;
+  a.x = S.x;
+  a.r = S.r;
+  a.z = S.z;
+  a.q = S.q;
+  a.p = S.p;
+  a.w_in = S.W[iter & 1];
+  a.w_out = S.W[(iter + 1) & 1];
+  a.pc_in = S.PC[iter & 1];
+  a.pc_out = S.PC[(iter + 1) & 1];
+  a.rf = S.rf;
+  a.df = S.df;
+  a.pf_in = S.PF[iter & 1];
+  a.pf_out = S.PF[(iter + 1) & 1];
+  a.u = nullptr;
+  a.y = nullptr;
+  if (S.refined) {
+    switch (kind) {
+      case K_RESID: batch_body<K_RESID, 4>(a, t, sc, part, lds, par); break;
+      case K_REF_SCALE: batch_body<K_REF_SCALE, 4>(a, t, sc, part, lds, par); break;
+      case K_CG1F: batch_body<K_CG1F, 4>(a, t, sc, part, lds, par); break;
+      case K_CG2F:
+        a.pf_in = S.PF[(iter + 1) & 1];
+        batch_body<K_CG2F, 4>(a, t, sc, part, lds, par);
+        break;
+      case K_REF_UPDATE: batch_body<K_REF_UPDATE, 4>(a, t, sc, part, lds, par); break;
+    }
+  } else {
+    switch (kind) {
+      case K_INIT_R: batch_body<K_INIT_R, 2>(a, t, sc, part, lds, par); break;
+      case K_INIT_W:
+        a.w_out = S.W[0];
+        batch_body<K_INIT_W, 2>(a, t, sc, part, lds, par);
+        break;
+      case K_PCG: batch_body<K_PCG, 2>(a, t, sc, part, lds, par); break;
+      case K_CG1: batch_body<K_CG1, 2>(a, t, sc, part, lds, par); break;
+      case K_CG2:
+        a.pc_in = S.PC[(iter + 1) & 1];
+        batch_body<K_CG2, 2>(a, t, sc, part, lds, par);
+        break;
+      case K_RESID: batch_body<K_RESID, 2>(a, t, sc, part, lds, par); break;
+    }
+  }
+}
+
+// The closer: the same sequence of transitions a single solve's prologues run.
+// Returns with S (in global memory) describing the next epoch; thread 0 writes.
+__device__ __forceinline__ void batch_close(Slot* Sp, int epoch, double* lds) {
+  const int kind = Sp->kind;
+  const int T = Sp->g.tiles;
+  const double* part = Sp->part[epoch & 1];
+  double sum[2] = {0.0, 0.0};
+  const int D = ndots_out_rt(kind);
+  if (D == 2) cross_tile_sum<2>(part, T, sum, lds);
+  else if (D == 1) cross_tile_sum<1>(part, T, sum, lds);
+  State s = *Sp->st;
+  Sc sc;
+  sc.al = sc.be = sc.inv = 0.0;
+  sc.first = 0;
+  sc.pad_ = 0;
+  int iter = Sp->iter;
+  int next = -1;  // -1: solve finished
+  auto fin = [&]() { return s.status == ST_ZERO_RHS ? -1 : (int)K_RESID; };
+  auto upd = [&]() { return transition<K_REF_UPDATE>(s, sum, sc) ? (int)K_REF_UPDATE : -1; };
+  switch (kind) {
+    case K_INIT_R:
+      if (Sp->variant == 1) next = transition<K_INIT_W>(s, sum, sc) ? (int)K_INIT_W : -1;
+      else next = transition<K_CG1>(s, sum, sc) ? (int)K_CG1 : fin();
+      break;
+    case K_INIT_W: next = transition<K_PCG>(s, sum, sc) ? (int)K_PCG : fin(); break;
+    case K_PCG:
+      ++iter;
+      next = transition<K_PCG>(s, sum, sc) ? (int)K_PCG : fin();
+      break;
+    case K_CG1: next = transition<K_CG2>(s, sum, sc) ? (int)K_CG2 : fin(); break;
+    case K_CG2:
+      ++iter;
+      next = transition<K_CG1>(s, sum, sc) ? (int)K_CG1 : fin();
+      break;
+    case K_RESID:
+      if (Sp->refined) {
+        next = transition<K_REF_SCALE>(s, sum, sc) ? (int)K_REF_SCALE : -1;
+      } else {
+        s.res2 = sum[0];
+        next = -1;
+      }
+      break;
+    case K_REF_SCALE:
+      iter = 0;
+      next = transition<K_CG1F>(s, sum, sc) ? (int)K_CG1F : upd();
+      break;
+    case K_CG1F: next = transition<K_CG2F>(s, sum, sc) ? (int)K_CG2F : upd(); break;
+    case K_CG2F:
+      ++iter;
+      next = transition<K_CG1F>(s, sum, sc) ? (int)K_CG1F : upd();
+      break;
+    case K_REF_UPDATE: next = K_RESID; break;
+  }
+  if (threadIdx.x == 0) {
+    *Sp->st = s;
+    Sp->sc = sc;
+    Sp->iter = iter;
+    if (next >= 0) Sp->kind = next;
+    else Sp->active = 0;
+    Sp->done = 0;
+  }
+}
+
+__global__ __launch_bounds__(kGroup) void k_batch(Slot* slots, int nslots, int* remaining,
+                                                 long long budget_ticks, long long idle_ticks) {
+  __shared__ double lds[kLdsPerGroup];
+  __shared__ int sh_slot, sh_tile, sh_epoch, sh_close;
+  const long long t_start = wall_clock64();
+  long long t_idle = t_start;
+  int scan = blockIdx.x % nslots;
+  int par = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int found = -1;
+      const long long now = wall_clock64();
+      if (__hip_atomic_load(remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
+          now - t_start > budget_ticks || now - t_idle > idle_ticks) {
+        found = -2;
+      } else {
+        for (int k = 0; k < nslots && found < 0; ++k) {
+          const int si = (scan + k) % nslots;
+          Slot* S = slots + si;
+          if (!__hip_atomic_load(&S->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            continue;
+          const unsigned long long c =
+              __hip_atomic_load(&S->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned T = (unsigned)S->g.tiles;
+          if ((unsigned)(c & 0xffffffffu) >= T) continue;
+          const unsigned long long old = atomicAdd(&S->claim, 1ull);
+          if ((unsigned)(old & 0xffffffffu) >= T) continue;
+          found = si;
+          sh_tile = (int)(old & 0xffffffffu);
+          sh_epoch = (int)(old >> 32);
+          scan = si;
+        }
+      }
+      sh_slot = found;
+    }
+    __syncthreads();
+    const int si = sh_slot;
+    if (si == -2) break;
+    if (si < 0) {
+      if (threadIdx.x == 0) __builtin_amdgcn_s_sleep(8);
+      __syncthreads();
+      continue;
+    }
+    t_idle = wall_clock64();
+    const int t = sh_tile, epoch = sh_epoch;
+    __threadfence();  // acquire: the epoch's scalars and the previous epoch's vectors
+    Slot* S = slots + si;
+    const int kind = S->kind, iter = S->iter;
+    const Sc sc = S->sc;
+    batch_tile(*S, kind, iter, sc, t, S->part[epoch & 1], lds + 8, par);
+    par ^= 1;
+    __threadfence();  // release this tile's vectors and partial
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned prev = atomicAdd(&S->done, 1u);
+      sh_close = (prev + 1 == (unsigned)S->g.tiles);
+    }
+    __syncthreads();
+    if (sh_close) {
+      __threadfence();  // acquire every tile's partial
+      batch_close(S, epoch, lds);
+      __threadfence();  // release the new scalars
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const unsigned long long nxt = (unsigned long long)(unsigned)(epoch + 1) << 32;
+        if (S->active) {
+          atomicExch(&S->claim, nxt);
+        } else {
+          atomicExch(&S->claim, nxt | kClaimClosed);
+          atomicSub(remaining, 1);
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_batch(Slot* slots, int nslots, int* remaining, long long budget_ticks,
+                        long long idle_ticks, int grid, hipStream_t st) {
+  if (nslots < 1 || grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kGroup), 0, st, slots, nslots, remaining,
+                     budget_ticks, idle_ticks);
+  return hipGetLastError();
+}
+
+int batch_max_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, kGroup, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 // ---------------------------------------------------------------- launchers --

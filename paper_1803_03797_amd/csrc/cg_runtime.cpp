@@ -27,7 +27,7 @@ namespace cgr {
 
 using namespace cgk;
 
-static double now_s() {
+double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
 }
@@ -265,20 +265,7 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid) {
 
 // ---------------------------------------------------------------- solve --
 
-// Workspace of one resident solve, carved from the arena.
-struct Work {
-  Plan pl;
-  char* mem = nullptr;
-  double *b = nullptr, *x = nullptr, *r = nullptr, *w[2] = {}, *z = nullptr, *q = nullptr,
-         *p = nullptr, *pc[2] = {};
-  float *rf = nullptr, *df = nullptr, *pf[2] = {};
-  double* part[2] = {};
-  State* S[2] = {};
-  int m = 0;  // passes issued (state/partial parity)
-  int i = 0;  // iterations issued (vector ping-pong parity)
-};
-
-static bool carve(Ctx& c, Work& w) {
+bool carve(Ctx& c, Work& w) {
   w.mem = (char*)c.arena.alloc(w.pl.footprint);
   if (!w.mem) return false;
   char* q = w.mem;
@@ -439,7 +426,7 @@ void Ctx::forget_graphs(const void* mem) {
   }
 }
 
-static int stage_in(Ctx& c, Work& w, const cg_problem* p) {
+int stage_in(Ctx& c, Work& w, const cg_problem* p) {
   const Plan& pl = w.pl;
   HIPCHK(launch_fill(w.mem, pl.footprint, c.st));
   const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyHostToDevice
@@ -463,7 +450,7 @@ static int stage_in(Ctx& c, Work& w, const cg_problem* p) {
   return CG_OK;
 }
 
-static int stage_out(Ctx& c, Work& w, const cg_problem* p, const State& s) {
+int stage_out(Ctx& c, Work& w, const cg_problem* p, const State& s) {
   const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyDeviceToHost
                                                    : hipMemcpyDeviceToDevice;
   const size_t row = (size_t)p->nx * 8, pitch = (size_t)w.pl.g.pitch * 8;
@@ -477,7 +464,7 @@ static int stage_out(Ctx& c, Work& w, const cg_problem* p, const State& s) {
   return CG_OK;
 }
 
-static void fill_result(const State& s, cg_result* res, double secs) {
+void fill_result(const State& s, cg_result* res, double secs, bool refined) {
   memset(res, 0, sizeof(*res));
   res->status = map_status(s.status);
   res->iterations = s.k;
@@ -486,7 +473,8 @@ static void fill_result(const State& s, cg_result* res, double secs) {
     res->iterations = 0;
     res->rel_res_recursive = res->rel_res_true = 0.0;
   } else {
-    res->rel_res_recursive = std::sqrt(s.gamma / s.bb);
+    // refinement: the outer residual is the true FP64 residual itself
+    res->rel_res_recursive = std::sqrt((refined ? s.res2 : s.gamma) / s.bb);
     res->rel_res_true = std::sqrt(s.res2 / s.bb);
   }
   res->device_seconds = secs;
@@ -595,7 +583,7 @@ int Ctx::solve(const cg_problem* p, cg_result* res) {
   rc = w.pl.wg ? solve_wg(c, w, p, s) : solve_tiled(c, w, p, s);
   if (rc) return rc;
   if ((rc = stage_out(c, w, p, s))) return rc;
-  fill_result(s, res, now_s() - t0);
+  fill_result(s, res, now_s() - t0, w.pl.refined);
   return res->status;
 }
 

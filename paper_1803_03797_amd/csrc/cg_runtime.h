@@ -78,6 +78,26 @@ struct PendingEv {
   double bytes;
 };
 
+// Workspace of one resident solve, carved from the arena.
+struct Work {
+  Plan pl;
+  char* mem = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *w[2] = {}, *z = nullptr, *q = nullptr,
+         *p = nullptr, *pc[2] = {};
+  float *rf = nullptr, *df = nullptr, *pf[2] = {};
+  double* part[2] = {};
+  cgk::State* S[2] = {};
+  int m = 0;  // passes issued (state/partial parity)
+  int i = 0;  // iterations issued (vector ping-pong parity)
+};
+
+struct Ctx;
+double now_s();
+bool carve(Ctx& c, Work& w);
+int stage_in(Ctx& c, Work& w, const cg_problem* p);
+int stage_out(Ctx& c, Work& w, const cg_problem* p, const cgk::State& s);
+void fill_result(const cgk::State& s, cg_result* res, double secs, bool refined);
+
 int validate(const cg_problem* p);
 size_t footprint_of(const cg_problem* p);
 cgk::Geo make_geo(int nx, int ny, int fp32g, int rows);

@@ -1,10 +1,451 @@
-// cg_serve.cpp - batched persistent solves and the serving loop.
+// cg_serve.cpp - many solves on one GPU: the persistent batch engine behind
+// cg_solve_batch, and the continuous-batching request server behind
+// cg_submit / cg_poll.
+//
+// Engine: a fixed array of device slots (cgk::Slot).  A solve is admitted
+// into a free slot when its device footprint fits the arena (its workspace is
+// carved from the arena, its inputs staged, its state initialised); then
+// every launch of the persistent kernel advances all resident solves
+// together, for at most a time budget; between launches finished solves are
+// harvested (solution copied out, memory returned) and new ones admitted.
+// Each solve keeps its x/r/p... vectors resident on the device from
+// admission to retirement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "cg_runtime.h"
 
 namespace cgr {
-int Ctx::solve_batch(const cg_problem*, int, cg_result*) { return CG_E_DEVICE; }
+
+using namespace cgk;
+
+struct Job {
+  cg_problem p;
+  uint64_t ticket = 0;
+  double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+  Work w;
+  int slot = -1;
+  bool finished = false;
+  int rc = CG_PENDING;  // final status (or a negative error)
+  cg_result res{};
+};
+
+class Engine {
+ public:
+  explicit Engine(Ctx& c, int nslots) : c_(c), n_(std::max(1, nslots)) {}
+  ~Engine() {
+    for (Job* j : slot_job_)
+      if (j) c_.arena.release(j->w.mem);
+    if (ctrl_) c_.arena.release(ctrl_);
+    if (h_slots_) hipHostFree(h_slots_);
+    if (h_rem_) hipHostFree(h_rem_);
+  }
+
+  int init() {
+    const size_t bytes = (size_t)n_ * sizeof(Slot) + 256;
+    ctrl_ = (char*)c_.arena.alloc(bytes);
+    if (!ctrl_) return CG_E_NOMEM;
+    d_slots_ = (Slot*)ctrl_;
+    d_rem_ = (int*)(ctrl_ + (size_t)n_ * sizeof(Slot));
+    if (hipHostMalloc((void**)&h_slots_, (size_t)n_ * sizeof(Slot), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&h_rem_, 256, hipHostMallocDefault) != hipSuccess)
+      return CG_E_DEVICE;
+    memset(h_slots_, 0, (size_t)n_ * sizeof(Slot));
+    if (hipMemcpyAsync(d_slots_, h_slots_, (size_t)n_ * sizeof(Slot), hipMemcpyHostToDevice,
+                       c_.st) != hipSuccess)
+      return CG_E_DEVICE;
+    slot_job_.assign(n_, nullptr);
+    grid_ = std::max(8, batch_max_blocks_per_cu() * c_.num_cu);
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c_.device) != hipSuccess ||
+        khz <= 0)
+      return CG_E_DEVICE;
+    ticks_per_s_ = (double)khz * 1e3;
+    return hipStreamSynchronize(c_.st) == hipSuccess ? CG_OK : CG_E_DEVICE;
+  }
+
+  int active() const { return active_; }
+  bool has_free() const { return active_ < n_; }
+
+  // CG_OK when admitted, CG_E_NOMEM when the arena has no room right now.
+  int admit(Job* j) {
+    int slot = -1;
+    for (int i = 0; i < n_; ++i)
+      if (!slot_job_[i]) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) return CG_E_BUSY;
+    j->w = Work();
+    j->w.pl = c_.plan(&j->p);
+    if (!carve(c_, j->w)) return CG_E_NOMEM;
+    int rc = stage_in(c_, j->w, &j->p);
+    if (rc) {
+      c_.arena.release(j->w.mem);
+      return rc;
+    }
+    Slot& S = h_slots_[slot];
+    memset(&S, 0, sizeof(S));
+    const Work& w = j->w;
+    S.g = w.pl.g;
+    S.variant = j->p.variant;
+    S.refined = w.pl.refined ? 1 : 0;
+    S.b = w.b;
+    S.x = w.x;
+    S.r = w.r;
+    S.z = w.z;
+    S.q = w.q;
+    S.p = w.p;
+    S.W[0] = w.w[0];
+    S.W[1] = w.w[1];
+    S.PC[0] = w.pc[0];
+    S.PC[1] = w.pc[1];
+    S.rf = w.rf;
+    S.df = w.df;
+    S.PF[0] = w.pf[0];
+    S.PF[1] = w.pf[1];
+    S.part[0] = w.part[0];
+    S.part[1] = w.part[1];
+    S.st = w.S[0];
+    S.active = 1;
+    S.kind = w.pl.refined ? K_RESID : K_INIT_R;
+    S.iter = 0;
+    S.claim = 0;
+    S.done = 0;
+    if (hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st) !=
+        hipSuccess) {
+      c_.arena.release(j->w.mem);
+      return CG_E_DEVICE;
+    }
+    slot_job_[slot] = j;
+    j->slot = slot;
+    j->t_admit = now_s();
+    ++active_;
+    return CG_OK;
+  }
+
+  // One launch of the persistent kernel over every resident solve.
+  int run(double budget_s) {
+    if (!active_) return CG_OK;
+    *h_rem_ = active_;
+    if (hipMemcpyAsync(d_rem_, h_rem_, sizeof(int), hipMemcpyHostToDevice, c_.st) != hipSuccess)
+      return CG_E_DEVICE;
+    const long long budget = (long long)(budget_s * ticks_per_s_);
+    const long long idle = (long long)(std::max(budget_s, 0.05) * ticks_per_s_);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c_.prof) {
+      e0 = c_.event();
+      e1 = c_.event();
+      hipEventRecord(e0, c_.st);
+    }
+    if (launch_batch(d_slots_, n_, d_rem_, budget, idle, grid_, c_.st) != hipSuccess)
+      return CG_E_DEVICE;
+    if (c_.prof) {
+      hipEventRecord(e1, c_.st);
+      c_.pending.push_back({e0, e1, "batch_persistent", 0.0});
+    }
+    if (hipStreamSynchronize(c_.st) != hipSuccess) return CG_E_DEVICE;
+    if (c_.prof) c_.prof_collect();
+    ++launches_;
+    return CG_OK;
+  }
+
+  // Moves finished solves out: copies x back, fills the result, frees memory.
+  int harvest(std::vector<Job*>& done) {
+    if (!active_) return CG_OK;
+    if (hipMemcpyAsync(h_slots_, d_slots_, (size_t)n_ * sizeof(Slot), hipMemcpyDeviceToHost,
+                       c_.st) != hipSuccess ||
+        hipStreamSynchronize(c_.st) != hipSuccess)
+      return CG_E_DEVICE;
+    unsigned long long progress = 0;
+    for (int i = 0; i < n_; ++i) {
+      Job* j = slot_job_[i];
+      if (!j) continue;
+      progress += (h_slots_[i].claim >> 32) + (h_slots_[i].claim & 0xffffffffu) +
+                  h_slots_[i].done;
+      if (h_slots_[i].active) continue;
+      State s;
+      if (hipMemcpyAsync(c_.host_state, j->w.S[0], sizeof(State), hipMemcpyDeviceToHost,
+                         c_.st) != hipSuccess ||
+          hipStreamSynchronize(c_.st) != hipSuccess)
+        return CG_E_DEVICE;
+      memcpy(&s, c_.host_state, sizeof(s));
+      int rc = stage_out(c_, j->w, &j->p, s);
+      j->t_done = now_s();
+      if (rc) {
+        j->rc = rc;
+      } else {
+        fill_result(s, &j->res, j->t_done - j->t_admit, j->w.pl.refined);
+        j->rc = j->res.status;
+      }
+      c_.arena.release(j->w.mem);
+      j->w.mem = nullptr;
+      slot_job_[i] = nullptr;
+      j->slot = -1;
+      --active_;
+      done.push_back(j);
+    }
+    // A launch that moved no solve at all means the kernel cannot progress.
+    if (progress == last_progress_ && active_ > 0) {
+      if (++stalls_ >= 3) return CG_E_DEVICE;
+    } else {
+      stalls_ = 0;
+    }
+    last_progress_ = progress;
+    return CG_OK;
+  }
+
+  // Fails every resident solve (used after a device error).
+  void abandon(std::vector<Job*>& done, int rc) {
+    for (int i = 0; i < n_; ++i) {
+      Job* j = slot_job_[i];
+      if (!j) continue;
+      c_.arena.release(j->w.mem);
+      j->w.mem = nullptr;
+      j->rc = rc;
+      j->t_done = now_s();
+      slot_job_[i] = nullptr;
+      done.push_back(j);
+    }
+    active_ = 0;
+  }
+
+  int launches() const { return launches_; }
+
+ private:
+  Ctx& c_;
+  int n_;
+  char* ctrl_ = nullptr;
+  Slot* d_slots_ = nullptr;
+  int* d_rem_ = nullptr;
+  Slot* h_slots_ = nullptr;
+  int* h_rem_ = nullptr;
+  std::vector<Job*> slot_job_;
+  int active_ = 0;
+  int grid_ = 8;
+  double ticks_per_s_ = 1e8;
+  unsigned long long last_progress_ = ~0ull;
+  int stalls_ = 0;
+  int launches_ = 0;
+};
+
+static int worse(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  auto rank = [](int s) { return s == CG_BREAKDOWN ? 3 : s == CG_NOT_CONVERGED ? 2 : 0; };
+  return rank(a) >= rank(b) ? a : b;
+}
+
+int Ctx::solve_batch(const cg_problem* probs, int n, cg_result* results) {
+  for (int i = 0; i < n; ++i)
+    if (plan(&probs[i]).footprint + (size_t)max_slots * sizeof(Slot) + 256 > arena.size())
+      return CG_E_NOMEM;
+  int rc = order_after_user();
+  if (rc) return rc;
+  Engine eng(*this, std::min(n, max_slots));
+  if ((rc = eng.init())) return rc;
+  std::vector<Job> jobs(n);
+  std::deque<int> pending;
+  for (int i = 0; i < n; ++i) {
+    jobs[i].p = probs[i];
+    jobs[i].t_submit = now_s();
+    pending.push_back(i);
+  }
+  std::vector<Job*> done;
+  int worst = CG_OK;
+  while (!pending.empty() || eng.active() > 0) {
+    while (!pending.empty() && eng.has_free()) {
+      int a = eng.admit(&jobs[pending.front()]);
+      if (a == CG_E_NOMEM && eng.active() > 0) break;  // wait for memory to free up
+      if (a != CG_OK) {
+        std::vector<Job*> tmp;
+        eng.abandon(tmp, a);
+        return a;
+      }
+      pending.pop_front();
+    }
+    if ((rc = eng.run(1.0)) || (rc = eng.harvest(done))) {
+      eng.abandon(done, rc);
+      return rc;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    results[i] = jobs[i].res;
+    results[i].latency_seconds = jobs[i].t_done - jobs[i].t_submit;
+    worst = worse(worst, jobs[i].rc);
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------- server --
+
+class Server {
+ public:
+  explicit Server(Ctx& c) : c_(c) {}
+  ~Server() { stop(); }
+
+  int submit(const cg_problem* p, uint64_t* ticket) {
+    if (footprint_of(p) + (size_t)c_.max_slots * sizeof(Slot) + 256 > c_.arena.size())
+      return CG_E_NOMEM;
+    Job* j = new Job;
+    j->p = *p;
+    j->t_submit = now_s();
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      if (stopping_) {
+        delete j;
+        return CG_E_BUSY;
+      }
+      j->ticket = next_ticket_++;
+      jobs_[j->ticket] = j;
+      queue_.push_back(j);
+      if (!th_.joinable()) th_ = std::thread([this] { loop(); });
+    }
+    cv_.notify_one();
+    *ticket = j->ticket;
+    return CG_OK;
+  }
+
+  int poll(uint64_t t, cg_result* r) {
+    std::lock_guard<std::mutex> lk(m_);
+    auto it = jobs_.find(t);
+    if (it == jobs_.end()) return CG_E_TICKET;
+    Job* j = it->second;
+    if (!j->finished) return CG_PENDING;
+    *r = j->res;
+    r->latency_seconds = j->t_done - j->t_submit;
+    const int rc = j->rc;
+    jobs_.erase(it);
+    delete j;
+    return rc;
+  }
+
+  void stop() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stopping_ = true;
+    }
+    cv_.notify_all();
+    if (th_.joinable()) th_.join();
+    std::lock_guard<std::mutex> lk(m_);
+    for (auto& kv : jobs_) delete kv.second;
+    jobs_.clear();
+    queue_.clear();
+  }
+
+  // serving knobs
+  double budget_s = 0.002;
+
+ private:
+  void loop() {
+    std::unique_ptr<Engine> eng;
+    std::vector<Job*> done;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] {
+          return stopping_ || !queue_.empty() || (eng && eng->active() > 0);
+        });
+        if (stopping_ && (!eng || eng->active() == 0)) {
+          for (Job* j : queue_) {  // cancelled before admission
+            j->rc = CG_E_BUSY;
+            j->finished = true;
+            j->t_done = now_s();
+          }
+          queue_.clear();
+          break;
+        }
+      }
+      done.clear();
+      {
+        std::lock_guard<std::recursive_mutex> ck(c_.mu);
+        if (hipSetDevice(c_.device) != hipSuccess) break;
+        int rc = CG_OK;
+        if (!eng) {
+          eng.reset(new Engine(c_, c_.max_slots));
+          rc = eng->init();
+        }
+        // admission: FIFO while a slot is free and the footprint fits
+        while (rc == CG_OK) {
+          Job* j = nullptr;
+          {
+            std::lock_guard<std::mutex> lk(m_);
+            if (stopping_ || queue_.empty() || !eng->has_free()) break;
+            j = queue_.front();
+          }
+          const int a = eng->admit(j);
+          if (a == CG_E_NOMEM && eng->active() > 0) break;
+          std::lock_guard<std::mutex> lk(m_);
+          queue_.pop_front();
+          if (a != CG_OK) {
+            j->rc = a;
+            j->finished = true;
+            j->t_done = now_s();
+          }
+        }
+        if (rc == CG_OK) rc = eng->run(budget_s);
+        if (rc == CG_OK) rc = eng->harvest(done);
+        if (rc != CG_OK) eng->abandon(done, rc);
+      }
+      {
+        std::lock_guard<std::mutex> lk(m_);
+        for (Job* j : done) j->finished = true;
+      }
+    }
+    if (eng) {
+      std::lock_guard<std::recursive_mutex> ck(c_.mu);
+      eng.reset();
+    }
+  }
+
+  Ctx& c_;
+  std::thread th_;
+  std::mutex m_;
+  std::condition_variable cv_;
+  std::deque<Job*> queue_;
+  std::unordered_map<uint64_t, Job*> jobs_;
+  bool stopping_ = false;
+  uint64_t next_ticket_ = 1;
+};
+
 }  // namespace cgr
 
-int cgr_server_submit(cgr::Ctx*, const cg_problem*, uint64_t*) { return CG_E_DEVICE; }
-int cgr_server_poll(cgr::Ctx*, uint64_t, cg_result*) { return CG_E_TICKET; }
-void cgr_server_stop(cgr::Ctx*) {}
+using cgr::Ctx;
+using cgr::Server;
+
+int cgr_server_submit(Ctx* c, const cg_problem* p, uint64_t* ticket) {
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!c->server) c->server = new Server(*c);
+  }
+  return c->server->submit(p, ticket);
+}
+
+int cgr_server_poll(Ctx* c, uint64_t ticket, cg_result* res) {
+  Server* s;
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    s = c->server;
+  }
+  if (!s) return CG_E_TICKET;
+  return s->poll(ticket, res);
+}
+
+void cgr_server_stop(Ctx* c) {
+  Server* s;
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    s = c->server;
+    c->server = nullptr;
+  }
+  delete s;
+}
