@@ -156,10 +156,22 @@ int cg_validate(const cg_problem* prob);
  * the device and pins the fastest for that grid shape (cached, optionally in
  * cfg->tune_cache).  Returns CG_OK. */
 int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision);
-/* Pins an explicit tile height (rows per wavefront strip) and grid size for a
- * grid shape; grid 0 = occupancy-derived.  For experiments and tests. */
+/* Pins the tile shape for a grid shape: tile height (rows per wavefront
+ * strip), grid size (0 = occupancy-derived) and columns per lane (0 = default:
+ * 2 for FP64, 4 for FP32-refined; classic FP64 may also use 4).  The reduction
+ * order follows the pinned shape (cg_plan reports it).  For the autotuner,
+ * experiments and tests. */
 int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int32_t rows,
-                int32_t grid);
+                int32_t grid, int32_t cols_per_lane);
+/* HBM probe, for measurement only: runs a plain streaming kernel over
+ * device buffers carved from the arena, `elems` doubles per vector, reps + 1
+ * times (the first warms up) and returns the best time and the bytes it moves.
+ * pattern 0: read one vector; 1: copy one vector to another (the known-size
+ * copy that calibrates hardware traffic counters); 2: two reads, one write;
+ * 3: three reads, two writes; 4: six vectors read and written in place (the
+ * traffic mix of a pipelined CG pass).  CG_E_NOMEM if the arena is too small. */
+int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
+                    double* bytes);
 /* Profiling on/off; while on, every kernel launch is bracketed by HIP events
  * on the library's stream. */
 int cg_set_profiling(cg_ctx* ctx, int32_t on);

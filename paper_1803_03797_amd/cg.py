@@ -57,7 +57,8 @@ class cg_kstat(C.Structure):
 
 SYMBOLS = ["cg_create", "cg_destroy", "cg_solve", "cg_solve_batch", "cg_submit", "cg_poll",
            "cg_status_str", "cg_apply", "cg_dot", "cg_plan", "cg_footprint", "cg_validate",
-           "cg_tune", "cg_pin_tile", "cg_set_profiling", "cg_kernel_stats", "cg_version"]
+           "cg_tune", "cg_pin_tile", "cg_set_profiling", "cg_kernel_stats", "cg_version",
+           "cg_stream_probe"]
 
 _lib = None
 
@@ -92,7 +93,8 @@ def load():
         "cg_footprint": (C.c_int, [C.POINTER(cg_problem), C.POINTER(C.c_size_t)]),
         "cg_validate": (C.c_int, [C.POINTER(cg_problem)]),
         "cg_tune": (C.c_int, [P, I, I, I, I]),
-        "cg_pin_tile": (C.c_int, [P, I, I, I, I, I]),
+        "cg_pin_tile": (C.c_int, [P, I, I, I, I, I, I]),
+        "cg_stream_probe": (C.c_int, [P, I, C.c_size_t, I, C.POINTER(D), C.POINTER(D)]),
         "cg_set_profiling": (C.c_int, [P, I]),
         "cg_kernel_stats": (C.c_int, [P, C.POINTER(cg_kstat), I, C.POINTER(I), I]),
         "cg_version": (C.c_char_p, []),
@@ -245,8 +247,15 @@ class Context:
     def cg_tune(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64):
         return _check("cg_tune", self.lib.cg_tune(self.h, nx, ny, variant, precision))
 
-    def cg_pin_tile(self, nx, ny, rows, grid=0, precision=CG_PREC_FP64):
-        return _check("cg_pin_tile", self.lib.cg_pin_tile(self.h, nx, ny, precision, rows, grid))
+    def cg_pin_tile(self, nx, ny, rows, grid=0, precision=CG_PREC_FP64, cols_per_lane=0):
+        return _check("cg_pin_tile", self.lib.cg_pin_tile(self.h, nx, ny, precision, rows, grid,
+                                                          cols_per_lane))
+
+    def cg_stream_probe(self, pattern, elems, reps=5):
+        sec, nbytes = C.c_double(), C.c_double()
+        _check("cg_stream_probe", self.lib.cg_stream_probe(self.h, pattern, elems, reps,
+                                                           C.byref(sec), C.byref(nbytes)))
+        return sec.value, nbytes.value
 
     def cg_set_profiling(self, on):
         return _check("cg_set_profiling", self.lib.cg_set_profiling(self.h, 1 if on else 0))

@@ -149,13 +149,26 @@ int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precisio
 }
 
 int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int32_t rows,
-                int32_t grid) {
+                int32_t grid, int32_t cols_per_lane) {
   if (!ctx || nx < 1 || ny < 1 || rows < 1 || rows > 4096 || grid < 0) return CG_E_INVALID;
   if (precision != CG_PREC_FP64 && precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
+  if (cols_per_lane != 0 && cols_per_lane != 2 && cols_per_lane != 4) return CG_E_INVALID;
+  if (precision == CG_PREC_FP32_REFINED && cols_per_lane == 2) return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
-  c->pins[Ctx::key(nx, ny, precision == CG_PREC_FP32_REFINED)] = cgr::Pin{rows, grid};
+  c->pins[Ctx::key(nx, ny, precision == CG_PREC_FP32_REFINED)] =
+      cgr::Pin{rows, grid, cols_per_lane};
   return CG_OK;
+}
+
+int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
+                    double* bytes) {
+  if (!ctx || !seconds || !bytes || pattern < 0 || pattern > 4 || elems < 2 || reps < 1)
+    return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->stream_probe(pattern, elems, reps, seconds, bytes);
 }
 
 int cg_set_profiling(cg_ctx* ctx, int32_t on) {

@@ -122,6 +122,8 @@ struct Sc {
 struct alignas(64) Slot {
   Geo g;
   int32_t variant, refined;
+  int32_t cpl4;      // 4 columns per lane (refined, or pinned classic FP64)
+  int32_t pad0_;
   double* b;
   double* x;
   double* r;
@@ -158,6 +160,8 @@ int pass_max_blocks_per_cu(int kind, int fp32_geometry);
 hipError_t launch_batch(Slot* slots, int nslots, int* remaining, long long budget_ticks,
                         long long idle_ticks, int grid, hipStream_t s);
 int batch_max_blocks_per_cu();
+hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
+                         hipStream_t s);
 size_t pass_algorithmic_bytes(int kind, int64_t dof);
 
 }  // namespace cgk

@@ -129,6 +129,33 @@ __device__ __forceinline__ T st5(T c, T w, T e, T s, T n) {
   return (((T(4) * c - w) - e) - s) - n;
 }
 
+// Reads a State every lane needs with the same value into scalar registers
+// (readfirstlane), so the solve's scalars do not hold vector registers (which
+// the compiler would otherwise spill across the prologue's barriers).
+__device__ __forceinline__ State load_state_uniform(const State* p) {
+  static_assert(sizeof(State) % 16 == 0, "State is loaded as uint4");
+  constexpr int N = sizeof(State) / 4;
+  uint32_t u[N];
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+  for (int i = 0; i < N / 4; ++i) {
+    const uint4 v = q[i];
+    u[4 * i + 0] = __builtin_amdgcn_readfirstlane(v.x);
+    u[4 * i + 1] = __builtin_amdgcn_readfirstlane(v.y);
+    u[4 * i + 2] = __builtin_amdgcn_readfirstlane(v.z);
+    u[4 * i + 3] = __builtin_amdgcn_readfirstlane(v.w);
+  }
+  State s;
+  __builtin_memcpy(&s, u, sizeof(State));
+  return s;
+}
+
+__device__ __forceinline__ double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m, kWave);
@@ -418,66 +445,130 @@ __device__ __forceinline__ double fold(const double (&acc)[CPL]) {
 // Each body handles tile t for the calling wavefront (rows s.j0..s.j1-1) and
 // leaves the lane's dot-product values in lv[].  Loops are wavefront-uniform.
 
+// Tile-edge addressing: lane 0 reads the value left of the tile, lane 63 the
+// value right of it, every other lane re-reads its own first element (an L1
+// hit), so the edge values come from one load of the whole wavefront with no
+// divergent branch.  `emask` is set on the lanes whose edge value is inside the
+// grid; elsewhere the edge reads as zero.
+struct EdgeAddr {
+  int off;     // column offset of this lane's edge load within a row
+  bool emask;  // this lane supplies a real neighbour value
+};
+
+template <int CPL>
+__device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
+  EdgeAddr e;
+  e.off = s.c;
+  e.emask = false;
+  if (s.lane == 0 && s.tx > 0) {
+    e.off = s.ct - 1;
+    e.emask = true;
+  }
+  if (s.lane == kWave - 1 && s.tx + 1 < g.ntx) {
+    e.off = s.ct + kWave * CPL;
+    e.emask = true;
+  }
+  return e;
+}
+
 // Row walker shared by every stencil body.  For the wavefront's strip it
-// keeps rows j-1, j, j+1 of the halo vector (H) and the tile-edge values of
-// rows j and j+1 in registers, and loads the next row's data (halo row j+2,
-// point row j+1) before it computes row j, so each wavefront keeps two rows
-// of loads in flight.
-//   hrow(off)          -> Row: H on row offset `off` at this lane's columns
-//   hedge(off, W, E)   -> H just left/right of the tile on that row
-//   point(off)         -> Bundle: the point-wise operands of that row
+// keeps rows j-1, j, j+1 of the halo vector H and the point data of row j in
+// registers, and issues the loads of halo row j+PD+1 and point row j+PD
+// before it computes row j, so each wavefront keeps PD+1 rows of loads in
+// flight.  Loads and arithmetic are separate stages (hload/eload load only;
+// hmake/emake combine the loaded values when the row enters the window), and
+// every prefetch load is unconditional: a row outside the grid or past the
+// strip's north halo is replaced by a valid row whose value is then ignored.
+// That keeps the number of loads in flight static, so the compiler waits only
+// for the row it is about to use.
+//   hload(off) -> raw halo data of the row at offset `off`
+//   hmake(raw) -> Row: H at this lane's columns
+//   eload(off) -> raw tile-edge data of that row (one load per vector)
+//   emake(raw) -> H just outside the tile for lanes 0 / 63 (zero elsewhere)
+//   point(off) -> Bundle: the point-wise operands of that row
 //   comp(off, S, C, N, W, E, bundle): row j's arithmetic and stores
-template <typename T, int CPL, class HRow, class HEdge, class Point, class Comp>
-__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HRow hrow, HEdge hedge,
-                                     Point point, Comp comp) {
+template <typename T, int CPL, int PD, class HLoad, class HMake, class ELoad, class EMake,
+          class Point, class Comp>
+__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
+                                     ELoad eload, EMake emake, Point point, Comp comp) {
   using R = Row<T, CPL>;
+  using RawH = decltype(hload((size_t)0));
+  using RawE = decltype(eload((size_t)0));
+  using B = decltype(point((size_t)0));
   if (s.j0 >= s.j1) return;
   const size_t P = g.pitch;
-  size_t o = (size_t)s.j0 * P;
-  R hS = s.j0 > 0 ? hrow(o - P) : zrow<T, CPL>();
-  R hC = hrow(o);
-  T eW, eE;
-  hedge(o, eW, eE);
-  R hN = zrow<T, CPL>();
-  T nW = T(0), nE = T(0);
-  if (s.j0 + 1 < g.ny) {
-    hN = hrow(o + P);
-    hedge(o + P, nW, nE);
+  const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
+  const size_t o0 = (size_t)s.j0 * P;
+  R hS = zrow<T, CPL>();
+  {
+    const R v = hmake(hload((size_t)max(s.j0 - 1, 0) * P));
+    if (s.j0 > 0) hS = v;
   }
-  auto cur = point(o);
+  R hC = hmake(hload(o0));
+  T eC = emake(eload(o0));
+  RawH q[PD];   // raw halo rows j+1 .. j+PD
+  RawE qe[PD];
+  bool qv[PD];  // the row exists (inside the grid, not past the strip's north halo)
+  B pt[PD];     // point data of rows j .. j+PD-1
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    const int r = s.j0 + 1 + k;
+    qv[k] = r <= hmax;
+    const size_t ro = (size_t)min(r, hmax) * P;
+    q[k] = hload(ro);
+    qe[k] = eload(ro);
+    pt[k] = point((size_t)min(s.j0 + k, s.j1 - 1) * P);
+  }
+  size_t o = o0;
   for (int j = s.j0; j < s.j1; ++j, o += P) {
-    R hNN = zrow<T, CPL>();
-    T nnW = T(0), nnE = T(0);
-    auto nxt = cur;
-    if (j + 1 < s.j1) {
-      nxt = point(o + P);
-      if (j + 2 < g.ny) {
-        hNN = hrow(o + 2 * P);
-        hedge(o + 2 * P, nnW, nnE);
-      }
+    // loads of the rows needed PD iterations from now
+    const int rh = j + PD + 1;
+    const bool nv = rh <= hmax;
+    const size_t ho = (size_t)min(rh, hmax) * P;
+    const RawH hn = hload(ho);
+    const RawE en = eload(ho);
+    const B pn = point((size_t)min(j + PD, s.j1 - 1) * P);
+    // row j+1 enters the window
+    R hN = hmake(q[0]);
+    T eN = emake(qe[0]);
+    if (!qv[0]) {
+      hN = zrow<T, CPL>();
+      eN = T(0);
     }
     R W, E;
-    west_east<T, CPL>(hC, eW, eE, W, E);
-    comp(o, hS, hC, hN, W, E, cur);
+    west_east<T, CPL>(hC, eC, eC, W, E);
+    comp(o, hS, hC, hN, W, E, pt[0]);
     hS = hC;
     hC = hN;
-    hN = hNN;
-    eW = nW;
-    eE = nE;
-    nW = nnW;
-    nE = nnE;
-    cur = nxt;
+    eC = eN;
+#pragma unroll
+    for (int k = 0; k + 1 < PD; ++k) {
+      q[k] = q[k + 1];
+      qe[k] = qe[k + 1];
+      qv[k] = qv[k + 1];
+      pt[k] = pt[k + 1];
+    }
+    q[PD - 1] = hn;
+    qe[PD - 1] = en;
+    qv[PD - 1] = nv;
+    pt[PD - 1] = pn;
   }
 }
 
-template <typename T, int CPL>
-__device__ __forceinline__ auto halo_loader(const T* V, const Strip& s) {
-  return [=](size_t off) { return ldrow<T, CPL>(V + off + s.c); };
-}
+#ifndef CG1_PREFETCH
+#define CG1_PREFETCH 1
+#endif
 
-template <typename T, int CPL>
-__device__ __forceinline__ auto edge_loader(const T* V, const Strip& s, const Geo& g) {
-  return [=](size_t off, T& eW, T& eE) { edges<T, CPL>(V + off, s, g, eW, eE); };
+// Loaders for a halo vector that is stored as is.
+template <typename T, int CPL, class Point, class Comp>
+__device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
+                                           Comp comp) {
+  const EdgeAddr ea = edge_addr<CPL>(s, g);
+  const int c = s.c;
+  walk<T, CPL, 1>(
+      g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
+      [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
+      [=](T v) { return ea.emask ? v : T(0); }, point, comp);
 }
 
 struct Empty {};
@@ -495,9 +586,8 @@ __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* 
   const int valid = g.nx - s.c;
   const double* B = a.b;
   double* Rr = a.r;
-  walk<double, CPL>(
-      g, s, halo_loader<double, CPL>(a.x, s), edge_loader<double, CPL>(a.x, s, g),
-      [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
+  walk_plain<double, CPL>(
+      g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const R& bb) {
         R res;
@@ -528,9 +618,8 @@ __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv)
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk<double, CPL>(
-      g, s, halo_loader<double, CPL>(U, s), edge_loader<double, CPL>(U, s, g),
-      [](size_t) { return Empty{}; },
+  walk_plain<double, CPL>(
+      g, s, U, [](size_t) { return Empty{}; },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const Empty&) {
         R out;
@@ -589,20 +678,17 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk<double, CPL>(
-      g, s, halo_loader<double, CPL>(a.w_in, s), edge_loader<double, CPL>(a.w_in, s, g),
+  walk_plain<double, CPL>(
+      g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
         const size_t oc = off + s.c;
         v.x = ldrow<double, CPL>(X + oc);
         v.r = ldrow<double, CPL>(Rv + oc);
-        if (first) {
-          v.z = v.q = v.p = zrow<double, CPL>();
-        } else {
-          v.z = ldrow<double, CPL>(Z + oc);
-          v.q = ldrow<double, CPL>(Q + oc);
-          v.p = ldrow<double, CPL>(Pp + oc);
-        }
+        // z, q, p are ignored on the first iteration (taken as zero)
+        v.z = ldrow<double, CPL>(Z + oc);
+        v.q = ldrow<double, CPL>(Q + oc);
+        v.p = ldrow<double, CPL>(Pp + oc);
         return v;
       },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
@@ -665,29 +751,36 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk<T, CPL>(
+  // the halo vector p = r + beta p_old is formed from the raw loads of r and
+  // p_old when a row enters the window; on the first iteration p = r
+  struct Raw {
+    R r, po;
+  };
+  struct RawE {
+    T r, po;
+  };
+  const EdgeAddr ea = edge_addr<CPL>(s, g);
+  walk<T, CPL, CG1_PREFETCH>(
       g, s,
-      [=](size_t off) -> R {
-        const R r = ldrow<T, CPL>(Rv + off + s.c);
-        if (first) return r;
-        const R po = ldrow<T, CPL>(Po + off + s.c);
-        R v;
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) v.e[k] = fma(be, po.e[k], r.e[k]);
+      [=](size_t off) {
+        Raw v;
+        v.r = ldrow<T, CPL>(Rv + off + s.c);
+        v.po = ldrow<T, CPL>(Po + off + s.c);  // ignored on the first iteration
         return v;
       },
-      [=](size_t row, T& eW, T& eE) {
-        eW = T(0);
-        eE = T(0);
-        if (s.lane == 0 && s.tx > 0) {
-          const size_t i = row + s.ct - 1;
-          eW = first ? Rv[i] : fma(be, Po[i], Rv[i]);
-        }
-        if (s.lane == kWave - 1 && s.tx + 1 < g.ntx) {
-          const size_t i = row + s.ct + kWave * CPL;
-          eE = first ? Rv[i] : fma(be, Po[i], Rv[i]);
-        }
+      [=](const Raw& v) {
+        R h;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) h.e[k] = first ? v.r.e[k] : fma(be, v.po.e[k], v.r.e[k]);
+        return h;
       },
+      [=](size_t off) {
+        RawE v;
+        v.r = Rv[off + ea.off];
+        v.po = Po[off + ea.off];
+        return v;
+      },
+      [=](const RawE& v) { return ea.emask ? (first ? v.r : fma(be, v.po, v.r)) : T(0); },
       [](size_t) { return Empty{}; },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const Empty&) {
@@ -729,8 +822,8 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk<T, CPL>(
-      g, s, halo_loader<T, CPL>(Pv, s), edge_loader<T, CPL>(Pv, s, g),
+  walk_plain<T, CPL>(
+      g, s, Pv,
       [=](size_t off) {
         XrRow<T, CPL> v;
         v.x = ldrow<T, CPL>(Xv + off + s.c);
@@ -768,9 +861,8 @@ __device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const S
   const int valid = g.nx - s.c;
   const double* B = a.b;
   float *Rf = a.rf, *Df = a.df;
-  walk<double, CPL>(
-      g, s, halo_loader<double, CPL>(a.x, s), edge_loader<double, CPL>(a.x, s, g),
-      [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
+  walk_plain<double, CPL>(
+      g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const R& bb) {
         RF rho;
@@ -838,7 +930,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
     sc.first = 0;
     sc.pad_ = 0;
   } else {
-    State s = *a.st_in;
+    State s = load_state_uniform(a.st_in);
     double sum[2] = {0.0, 0.0};
     if constexpr (DI > 0) {
       const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
@@ -846,6 +938,8 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
         if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
         else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
       }
+      sum[0] = uniform(sum[0]);
+      sum[1] = uniform(sum[1]);
     }
     const bool run = transition<KIND>(s, sum, sc);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
@@ -1066,8 +1160,14 @@ __device__ __forceinline__ void batch_tile(const Slot& S, int kind, int iter, co
   a.pf_out = S.PF[(iter + 1) & 1];
   a.u = nullptr;
   a.y = nullptr;
-  if (S.refined) {
+  if (S.cpl4) {
     switch (kind) {
+      case K_INIT_R: batch_body<K_INIT_R, 4>(a, t, sc, part, lds, par); break;
+      case K_CG1: batch_body<K_CG1, 4>(a, t, sc, part, lds, par); break;
+      case K_CG2:
+        a.pc_in = S.PC[(iter + 1) & 1];
+        batch_body<K_CG2, 4>(a, t, sc, part, lds, par);
+        break;
       case K_RESID: batch_body<K_RESID, 4>(a, t, sc, part, lds, par); break;
       case K_REF_SCALE: batch_body<K_REF_SCALE, 4>(a, t, sc, part, lds, par); break;
       case K_CG1F: batch_body<K_CG1F, 4>(a, t, sc, part, lds, par); break;
@@ -1105,7 +1205,9 @@ __device__ __forceinline__ void batch_close(Slot* Sp, int epoch, double* lds) {
   const int D = ndots_out_rt(kind);
   if (D == 2) cross_tile_sum<2>(part, T, sum, lds);
   else if (D == 1) cross_tile_sum<1>(part, T, sum, lds);
-  State s = *Sp->st;
+  sum[0] = uniform(sum[0]);
+  sum[1] = uniform(sum[1]);
+  State s = load_state_uniform(Sp->st);
   Sc sc;
   sc.al = sc.be = sc.inv = 0.0;
   sc.first = 0;
@@ -1246,6 +1348,51 @@ int batch_max_blocks_per_cu() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, kGroup, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
+}
+
+// ------------------------------------------------------------ HBM probes --
+//
+// Plain streaming kernels over `nv` device vectors of n doubles (16 B per
+// lane access, grid-stride): the attainable bandwidth of a read/write mix,
+// and the copy kernel of known size that calibrates the traffic counters.
+// pattern 0: read 1; 1: copy (1R 1W); 2: 2R 1W; 3: 3R 2W; 4: 6R 6W in place.
+__global__ __launch_bounds__(256) void k_stream(int pattern, double2* v0, double2* v1,
+                                                double2* v2, double2* v3, double2* v4,
+                                                double2* v5, size_t n2, double* sink) {
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (pattern == 0) {
+      const double2 a = v0[i];
+      acc += a.x + a.y;
+    } else if (pattern == 1) {
+      v1[i] = v0[i];
+    } else if (pattern == 2) {
+      const double2 a = v0[i], b = v1[i];
+      v2[i] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
+    } else if (pattern == 3) {
+      const double2 a = v0[i], b = v1[i], c = v2[i];
+      v3[i] = make_double2(a.x + b.x, a.y + b.y);
+      v4[i] = make_double2(b.x - c.x, b.y - c.y);
+    } else {
+      const double2 a = v0[i], b = v1[i], c = v2[i], d = v3[i], e = v4[i], f = v5[i];
+      v0[i] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
+      v1[i] = make_double2(b.x - 0.25 * c.x, b.y - 0.25 * c.y);
+      v2[i] = make_double2(c.x + d.x, c.y + d.y);
+      v3[i] = make_double2(d.x * 0.75, d.y * 0.75);
+      v4[i] = make_double2(e.x + f.x, e.y + f.y);
+      v5[i] = make_double2(f.x - a.x, f.y - a.y);
+    }
+  }
+  if (pattern == 0 && acc == 1.2345678e300) sink[0] = acc;  // keeps the reads alive
+}
+
+hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_stream, dim3(grid), dim3(256), 0, st, pattern, (double2*)v[0],
+                     (double2*)v[1], (double2*)v[2], (double2*)v[3], (double2*)v[4],
+                     (double2*)v[5], n / 2, sink);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launchers --

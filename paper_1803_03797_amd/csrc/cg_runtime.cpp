@@ -156,6 +156,8 @@ Plan Ctx::plan(const cg_problem* p) {
     if (it != pins.end()) {
       rows = it->second.rows;
       grid = it->second.grid;
+      // classic FP64 may run with 4 columns (32 B) per lane
+      if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4) pl.fp32g = 1;
     } else {
       rows = default_rows(p->nx, p->ny, pl.fp32g);
     }
@@ -252,14 +254,17 @@ static const char* kind_name(int kind, int fp32g) {
 }
 
 // Launches one pass; with profiling on, brackets it by events.
-hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid) {
+// A `check` pass only classifies the state reached by the previous pass (its
+// body never runs); it is recorded under "final_check" with no bytes.
+hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool check) {
   if (!prof || capturing) return launch_pass(kind, fp32g, a, grid, st);
   hipEvent_t e0 = event(), e1 = event();
   hipEventRecord(e0, st);
   hipError_t rc = launch_pass(kind, fp32g, a, grid, st);
   hipEventRecord(e1, st);
-  pending.push_back({e0, e1, kind_name(kind, fp32g),
-                     (double)pass_algorithmic_bytes(kind, (int64_t)a.g.nx * a.g.ny)});
+  pending.push_back({e0, e1, check ? "final_check" : kind_name(kind, fp32g),
+                     check ? 0.0
+                           : (double)pass_algorithmic_bytes(kind, (int64_t)a.g.nx * a.g.ny)});
   return rc;
 }
 
@@ -327,7 +332,7 @@ static hipError_t issue(Ctx& c, Work& w, int kind, F mod) {
   a.part_out = w.part[(w.m + 1) & 1];
   mod(a);
   w.m++;
-  return c.pass(kind, w.pl.fp32g, a, w.pl.grid);
+  return c.pass(kind, w.pl.fp32g, a, w.pl.grid, w.check);
 }
 
 static hipError_t issue_iteration(Ctx& c, Work& w) {
@@ -447,6 +452,8 @@ int stage_in(Ctx& c, Work& w, const cg_problem* p) {
   HIPCHK(hipStreamSynchronize(c.st));
   w.m = 0;
   w.i = 0;
+  w.maxit = p->maxit;
+  w.check = false;
   return CG_OK;
 }
 
@@ -501,7 +508,9 @@ static int solve_tiled(Ctx& c, Work& w, const cg_problem* p, State& s) {
       if (s.status != ST_RUNNING) break;
       w.i = 0;  // inner direction ping-pong restarts every inner solve
       for (;;) {
-        if ((rc = run_chunk(c, w, chunk_iters(c, w)))) return rc;
+        // while profiling, one iteration per chunk so that at most one no-op
+        // pass pair per inner solve enters the statistics
+        if ((rc = run_chunk(c, w, c.prof ? 1 : chunk_iters(c, w)))) return rc;
         if ((rc = read_state(c, w, s))) return rc;
         if (s.status != ST_RUNNING) break;
       }
@@ -517,9 +526,12 @@ static int solve_tiled(Ctx& c, Work& w, const cg_problem* p, State& s) {
     HIPCHK(issue(c, w, K_INIT_W, [&](PassArgs& a) { a.w_out = w.w[0]; }));
   const int K = chunk_iters(c, w);
   for (;;) {
-    // never issue iterations past maxit: the device would run them as no-ops
+    // never issue iterations past maxit: after maxit iterations one more
+    // pass only classifies the final state
     const int left = p->maxit - w.i;
-    if ((rc = run_chunk(c, w, left > 0 ? std::min(K, left) : 2))) return rc;
+    w.check = left <= 0;
+    if ((rc = run_chunk(c, w, left > 0 ? std::min(K, left) : 1))) return rc;
+    w.check = false;
     if ((rc = read_state(c, w, s))) return rc;
     if (s.status != ST_RUNNING) break;
   }
@@ -661,6 +673,45 @@ int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u
     memcpy(&s, host_state, sizeof(s));
     *dot_out = s.res2;
   }
+  return CG_OK;
+}
+
+// ------------------------------------------------------------ HBM probe --
+
+int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, double* bytes) {
+  Ctx& c = *this;
+  static const int nv[] = {1, 2, 3, 5, 6};
+  static const int moved[] = {1, 2, 3, 5, 12};
+  if (pattern < 0 || pattern > 4 || elems < 2 || reps < 1) return CG_E_INVALID;
+  elems &= ~(size_t)1;
+  const size_t vb = round_up(elems * 8, Arena::kAlign);
+  char* m = (char*)arena.alloc(nv[pattern] * vb + 256);
+  if (!m) return CG_E_NOMEM;
+  struct Rel {
+    Arena& a;
+    char* m;
+    ~Rel() { a.release(m); }
+  } rel{arena, m};
+  double* v[6];
+  for (int k = 0; k < 6; ++k) v[k] = (double*)(m + (k < nv[pattern] ? k : 0) * vb);
+  double* sink = (double*)(m + nv[pattern] * vb);
+  HIPCHK(launch_fill(m, nv[pattern] * vb + 256, st));
+  const int grid = 8 * num_cu;
+  hipEvent_t e0 = event(), e1 = event();
+  double best = 1e30;
+  for (int r = 0; r < reps + 1; ++r) {
+    HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(launch_stream(pattern, v, elems, sink, grid, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (r > 0) best = std::min(best, ms * 1e-3);  // the first launch warms up
+  }
+  ev_free.push_back(e0);
+  ev_free.push_back(e1);
+  *seconds = best;
+  *bytes = (double)moved[pattern] * elems * 8.0;
   return CG_OK;
 }
 

@@ -52,6 +52,7 @@ struct Plan {
 struct Pin {
   int rows = 0;
   int grid = 0;
+  int cpl = 0;  // columns per lane; 0 = default (2 for FP64, 4 for refined)
 };
 
 struct GraphKey {
@@ -89,6 +90,8 @@ struct Work {
   cgk::State* S[2] = {};
   int m = 0;  // passes issued (state/partial parity)
   int i = 0;  // iterations issued (vector ping-pong parity)
+  int maxit = 0;
+  bool check = false;  // the passes being issued only classify the final state
 };
 
 struct Ctx;
@@ -144,7 +147,8 @@ struct Ctx {
   void load_tune_cache();
   void save_tune_cache();
   int order_after_user();
-  hipError_t pass(int kind, int fp32g, const cgk::PassArgs& a, int grid);
+  hipError_t pass(int kind, int fp32g, const cgk::PassArgs& a, int grid, bool check = false);
+  int stream_probe(int pattern, size_t elems, int reps, double* seconds, double* bytes);
   hipEvent_t event();
   void prof_add(const char* name, double seconds, double bytes, int64_t launches);
   void prof_collect();

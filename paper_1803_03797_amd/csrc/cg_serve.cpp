@@ -100,6 +100,7 @@ class Engine {
     S.g = w.pl.g;
     S.variant = j->p.variant;
     S.refined = w.pl.refined ? 1 : 0;
+    S.cpl4 = w.pl.fp32g;
     S.b = w.b;
     S.x = w.x;
     S.r = w.r;
