@@ -56,8 +56,12 @@ struct alignas(16) State {
   int32_t kin;       // refinement: iterations of the current inner solve
   int32_t outer;     // refinement: outer steps done
   int32_t maxit;
-  int32_t pad_[2];
+  int32_t kind;      // step engine: pass kind the solve runs at its next step
+  int32_t pad_;
 };
+
+constexpr int32_t K_FINAL = 100;  // step engine: sum the true residual, then done
+constexpr int32_t K_DONE = -1;    // step engine: nothing left to run
 
 struct Geo {
   int32_t nx, ny, pitch;
@@ -116,14 +120,15 @@ struct Sc {
   double inv;      // refinement: 1 / scale
 };
 
-// One resident solve of the persistent batch kernel.  Static fields are
-// written by the host at admission; the dynamic ones by the work-group that
-// completes the last tile of a pass (the "closer").
+// One resident solve of the multi-solve step kernel (batch and serving),
+// written by the host at admission.  The solve's progress lives in its
+// double-buffered State (which holds the kind of the next pass); a solve
+// admitted at step a runs its pass number (step - a) at every step.
 struct alignas(64) Slot {
   Geo g;
   int32_t variant, refined;
   int32_t cpl4;      // 4 columns per lane (refined, or pinned classic FP64)
-  int32_t pad0_;
+  int32_t admit_step;
   double* b;
   double* x;
   double* r;
@@ -136,16 +141,12 @@ struct alignas(64) Slot {
   float* df;
   float* PF[2];      // refinement inner direction ping-pong
   double* part[2];   // per-tile partials, by pass parity
-  State* st;
-  // dynamic
-  int32_t active;    // 1 while the solve has passes left
-  int32_t kind;      // pass kind of the current epoch
-  int32_t iter;      // iteration counter (vector ping-pong parity)
-  int32_t pad_;
-  Sc sc;             // scalars of the current epoch
-  unsigned long long claim;  // (epoch << 32) | next unclaimed tile
-  unsigned int done;         // tiles completed in the current epoch
-  unsigned int pad2_;
+  State* S[2];       // state, by pass parity
+};
+
+// A unit of work of one step: tiles [t0, t1) of one resident solve.
+struct Item {
+  int32_t slot, t0, t1, pad_;
 };
 
 // Host-side launchers (cg_kernels.hip).
@@ -154,12 +155,14 @@ hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slo
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
-// Persistent batch kernel over nslots slots; returns when no solve is left,
-// when budget_ticks of the device wall clock have passed, or after idle_ticks
-// without claimable work.  *remaining counts the unfinished active slots.
-hipError_t launch_batch(Slot* slots, int nslots, int* remaining, long long budget_ticks,
-                        long long idle_ticks, int grid, hipStream_t s);
-int batch_max_blocks_per_cu();
+// One step of every resident solve: work-groups stride over the *n_items
+// items; grid is any positive size.
+hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items, int step,
+                       int grid, hipStream_t s);
+// Copies each listed slot's current state (pass parity of `step`) to out[i].
+hipError_t launch_gather(const Slot* slots, const int* idx, int n, int step, State* out,
+                         hipStream_t s);
+int step_max_blocks_per_cu();
 hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
                          hipStream_t s);
 size_t pass_algorithmic_bytes(int kind, int64_t dof);

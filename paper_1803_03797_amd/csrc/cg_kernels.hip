@@ -1034,13 +1034,19 @@ __device__ __forceinline__ bool wg_step(State& s, const PassArgs& a, Sc& sc, dou
   return run;
 }
 
+constexpr int kWgMaxLdsTiles = 64;  // up to this many tiles the partials stay in LDS
+
 template <int VARIANT>
 __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
   __shared__ double lds_all[kWgGroups * kLdsPerGroup];
+  __shared__ double lds_part[2][2 * kWgMaxLdsTiles];
   double* lds = lds_all + (threadIdx.x >> 8) * kLdsPerGroup;
   State s = *a0.st_in;
-  double* P0 = const_cast<double*>(a0.part_in);
-  double* P1 = a0.part_out;
+  // the per-tile partials of a pass live in LDS for small grids (the same
+  // values and order as in global memory, one L2 round trip less per pass)
+  const bool in_lds = a0.g.tiles <= kWgMaxLdsTiles;
+  double* P0 = in_lds ? lds_part[0] : const_cast<double*>(a0.part_in);
+  double* P1 = in_lds ? lds_part[1] : a0.part_out;
   Sc sc;
   PassArgs a = a0;
   // r = b - A x
@@ -1095,258 +1101,171 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
   if (threadIdx.x == 0) *a0.st_out = s;
 }
 
-// ------------------------------------------------------ persistent batch --
+// ---------------------------------------------------- multi-solve step --
 //
-// One launch serves many solves.  Every solve is a sequence of passes (the
-// same passes, bodies and transitions as a single solve); a pass of solve s is
-// "epoch" e of that solve and consists of its tiles.  Work-groups claim
-// (solve, tile) items with one 64-bit atomic per claim (epoch in the high
-// word, next tile in the low word), process the tile, and count it done.  The
-// work-group completing the last tile of an epoch (the closer) sums the
-// epoch's partials, applies the scalar transition of the next pass, picks the
-// next pass kind and publishes the next epoch.  A work-group never waits while
-// it holds work, so progress needs no co-residency; it leaves when every solve
-// is finished, when the launch's time budget is spent (the host relaunches;
-// claimed-but-unfinished work never exists outside a running work-group), or
-// after idle_ticks without claimable work.
-//
-// Cross-XCD visibility: agent-scope fences (L2 write-back / invalidate on
-// gfx950) separate a tile's stores from the done-count, the closer's reads from
-// the done-count, the closer's stores from the publish, and a claim from the
-// tile's loads.
+// One launch advances every resident solve by one pass.  The work is a table
+// of items (tiles [t0, t1) of one solve); work-groups stride over it.  For
+// each item a work-group reads its solve's state for this pass, sums the
+// previous pass's tile partials, applies the transition of the pass kind the
+// state names (exactly the prologue of a single-solve pass, hence the same
+// bits), records the kind of the solve's next pass, and processes its tiles.
+// The work-group holding tile 0 of a solve writes the solve's next state.
+// Kernel boundaries order the steps: no atomics, no fences, no waiting.
 
-constexpr unsigned kClaimClosed = 0x80000000u;  // low word of a finished solve
-
-__device__ __forceinline__ int ndots_out_rt(int kind) {
-  switch (kind) {
-    case K_INIT_R: case K_INIT_W: case K_PCG: case K_RESID: return 2;
-    case K_CG1: case K_CG2: case K_REF_SCALE: case K_CG1F: case K_CG2F: return 1;
+template <int KIND>
+__device__ __forceinline__ bool step_transition(State& s, const double* sum, Sc& sc) {
+  if constexpr (KIND == K_FINAL) {
+    sc.al = sc.be = sc.inv = 0.0;
+    sc.first = 0;
+    sc.pad_ = 0;
+    s.res2 = sum[0];
+    return false;
+  } else {
+    return transition<KIND>(s, sum, sc);
   }
-  return 0;
+}
+
+// Kind of the pass after `kind`, given whether its body ran.
+__device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int variant,
+                                         int refined) {
+  switch (kind) {
+    case K_INIT_R: return variant == 1 ? K_INIT_W : K_CG1;
+    case K_INIT_W: return ran ? K_PCG : K_DONE;
+    case K_PCG: return ran ? K_PCG : (s.status == ST_ZERO_RHS ? K_DONE : K_RESID);
+    case K_CG1: return ran ? K_CG2 : (s.status == ST_ZERO_RHS ? K_DONE : K_RESID);
+    case K_CG2: return ran ? K_CG1 : K_RESID;
+    case K_RESID: return refined ? K_REF_SCALE : K_FINAL;
+    case K_FINAL: return K_DONE;
+    case K_REF_SCALE: return ran ? K_CG1F : K_DONE;
+    case K_CG1F: return ran ? K_CG2F : K_REF_UPDATE;
+    case K_CG2F: return ran ? K_CG1F : K_REF_UPDATE;
+    case K_REF_UPDATE: return ran ? K_RESID : K_DONE;
+  }
+  return K_DONE;
 }
 
 template <int KIND, int CPL>
-__device__ __forceinline__ void batch_body(const PassArgs& a, int t, const Sc& sc, double* part,
-                                           double* lds, int par) {
-  constexpr int DO = ndots_out<KIND>();
-  double lv[2] = {0.0, 0.0};
-  run_body<KIND, CPL>(a, t, sc, lv);
-  if constexpr (DO > 0) {
-    tile_partial<DO>(lv, part, a.g.tiles, t, lds, par);
+__device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, State s,
+                                          double* lds) {
+  constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
+  constexpr int DO = (KIND == K_FINAL) ? 0 : ndots_out<KIND>();
+  const int T = S.g.tiles;
+  double sum[2] = {0.0, 0.0};
+  if constexpr (DI > 0) {
+    const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
+    if (s.status == ST_RUNNING || KIND == K_FINAL) {
+      if (din == 2) cross_tile_sum<2>(S.part[m & 1], T, sum, lds);
+      else cross_tile_sum<1>(S.part[m & 1], T, sum, lds);
+    }
+    sum[0] = uniform(sum[0]);
+    sum[1] = uniform(sum[1]);
   }
-}
-
-__device__ __forceinline__ void batch_tile(const Slot& S, int kind, int iter, const Sc& sc, int t,
-                                           double* part, double* lds, int par) {
+  // ping-pong parities come from the iteration counters before the transition
+  const int k0 = s.k, kin0 = s.kin;
+  Sc sc;
+  const bool run = step_transition<KIND>(s, sum, sc);
+  if (it.t0 == 0 && threadIdx.x == 0) {
+    State o = s;
+    o.kind = next_kind(KIND, run, s, S.variant, S.refined);
+    *S.S[(m + 1) & 1] = o;
+  }
+  if (!run) return;
   PassArgs a;
   a.g = S.g;
   a.st_in = nullptr;
   a.st_out = nullptr;
   a.part_in = nullptr;
-  a.part_out = part;
+  a.part_out = S.part[(m + 1) & 1];
   a.b = S.b;
   a.x = S.x;
   a.r = S.r;
   a.z = S.z;
   a.q = S.q;
   a.p = S.p;
-  a.w_in = S.W[iter & 1];
-  a.w_out = S.W[(iter + 1) & 1];
-  a.pc_in = S.PC[iter & 1];
-  a.pc_out = S.PC[(iter + 1) & 1];
+  a.w_in = S.W[k0 & 1];
+  a.w_out = (KIND == K_INIT_W) ? S.W[0] : S.W[(k0 + 1) & 1];
+  a.pc_in = (KIND == K_CG2) ? S.PC[(k0 + 1) & 1] : S.PC[k0 & 1];
+  a.pc_out = S.PC[(k0 + 1) & 1];
   a.rf = S.rf;
   a.df = S.df;
-  a.pf_in = S.PF[iter & 1];
-  a.pf_out = S.PF[(iter + 1) & 1];
+  a.pf_in = (KIND == K_CG2F) ? S.PF[(kin0 + 1) & 1] : S.PF[kin0 & 1];
+  a.pf_out = S.PF[(kin0 + 1) & 1];
   a.u = nullptr;
   a.y = nullptr;
-  if (S.cpl4) {
-    switch (kind) {
-      case K_INIT_R: batch_body<K_INIT_R, 4>(a, t, sc, part, lds, par); break;
-      case K_CG1: batch_body<K_CG1, 4>(a, t, sc, part, lds, par); break;
-      case K_CG2:
-        a.pc_in = S.PC[(iter + 1) & 1];
-        batch_body<K_CG2, 4>(a, t, sc, part, lds, par);
-        break;
-      case K_RESID: batch_body<K_RESID, 4>(a, t, sc, part, lds, par); break;
-      case K_REF_SCALE: batch_body<K_REF_SCALE, 4>(a, t, sc, part, lds, par); break;
-      case K_CG1F: batch_body<K_CG1F, 4>(a, t, sc, part, lds, par); break;
-      case K_CG2F:
-        a.pf_in = S.PF[(iter + 1) & 1];
-        batch_body<K_CG2F, 4>(a, t, sc, part, lds, par);
-        break;
-      case K_REF_UPDATE: batch_body<K_REF_UPDATE, 4>(a, t, sc, part, lds, par); break;
-    }
-  } else {
-    switch (kind) {
-      case K_INIT_R: batch_body<K_INIT_R, 2>(a, t, sc, part, lds, par); break;
-      case K_INIT_W:
-        a.w_out = S.W[0];
-        batch_body<K_INIT_W, 2>(a, t, sc, part, lds, par);
-        break;
-      case K_PCG: batch_body<K_PCG, 2>(a, t, sc, part, lds, par); break;
-      case K_CG1: batch_body<K_CG1, 2>(a, t, sc, part, lds, par); break;
-      case K_CG2:
-        a.pc_in = S.PC[(iter + 1) & 1];
-        batch_body<K_CG2, 2>(a, t, sc, part, lds, par);
-        break;
-      case K_RESID: batch_body<K_RESID, 2>(a, t, sc, part, lds, par); break;
-    }
-  }
-}
-
-// The closer: the same sequence of transitions a single solve's prologues run.
-// Returns with S (in global memory) describing the next epoch; thread 0 writes.
-__device__ __forceinline__ void batch_close(Slot* Sp, int epoch, double* lds) {
-  const int kind = Sp->kind;
-  const int T = Sp->g.tiles;
-  const double* part = Sp->part[epoch & 1];
-  double sum[2] = {0.0, 0.0};
-  const int D = ndots_out_rt(kind);
-  if (D == 2) cross_tile_sum<2>(part, T, sum, lds);
-  else if (D == 1) cross_tile_sum<1>(part, T, sum, lds);
-  sum[0] = uniform(sum[0]);
-  sum[1] = uniform(sum[1]);
-  State s = load_state_uniform(Sp->st);
-  Sc sc;
-  sc.al = sc.be = sc.inv = 0.0;
-  sc.first = 0;
-  sc.pad_ = 0;
-  int iter = Sp->iter;
-  int next = -1;  // -1: solve finished
-  auto fin = [&]() { return s.status == ST_ZERO_RHS ? -1 : (int)K_RESID; };
-  auto upd = [&]() { return transition<K_REF_UPDATE>(s, sum, sc) ? (int)K_REF_UPDATE : -1; };
-  switch (kind) {
-    case K_INIT_R:
-      if (Sp->variant == 1) next = transition<K_INIT_W>(s, sum, sc) ? (int)K_INIT_W : -1;
-      else next = transition<K_CG1>(s, sum, sc) ? (int)K_CG1 : fin();
-      break;
-    case K_INIT_W: next = transition<K_PCG>(s, sum, sc) ? (int)K_PCG : fin(); break;
-    case K_PCG:
-      ++iter;
-      next = transition<K_PCG>(s, sum, sc) ? (int)K_PCG : fin();
-      break;
-    case K_CG1: next = transition<K_CG2>(s, sum, sc) ? (int)K_CG2 : fin(); break;
-    case K_CG2:
-      ++iter;
-      next = transition<K_CG1>(s, sum, sc) ? (int)K_CG1 : fin();
-      break;
-    case K_RESID:
-      if (Sp->refined) {
-        next = transition<K_REF_SCALE>(s, sum, sc) ? (int)K_REF_SCALE : -1;
-      } else {
-        s.res2 = sum[0];
-        next = -1;
-      }
-      break;
-    case K_REF_SCALE:
-      iter = 0;
-      next = transition<K_CG1F>(s, sum, sc) ? (int)K_CG1F : upd();
-      break;
-    case K_CG1F: next = transition<K_CG2F>(s, sum, sc) ? (int)K_CG2F : upd(); break;
-    case K_CG2F:
-      ++iter;
-      next = transition<K_CG1F>(s, sum, sc) ? (int)K_CG1F : upd();
-      break;
-    case K_REF_UPDATE: next = K_RESID; break;
-  }
-  if (threadIdx.x == 0) {
-    *Sp->st = s;
-    Sp->sc = sc;
-    Sp->iter = iter;
-    if (next >= 0) Sp->kind = next;
-    else Sp->active = 0;
-    Sp->done = 0;
-  }
-}
-
-__global__ __launch_bounds__(kGroup) void k_batch(Slot* slots, int nslots, int* remaining,
-                                                 long long budget_ticks, long long idle_ticks) {
-  __shared__ double lds[kLdsPerGroup];
-  __shared__ int sh_slot, sh_tile, sh_epoch, sh_close;
-  const long long t_start = wall_clock64();
-  long long t_idle = t_start;
-  int scan = blockIdx.x % nslots;
   int par = 0;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      int found = -1;
-      const long long now = wall_clock64();
-      if (__hip_atomic_load(remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0 ||
-          now - t_start > budget_ticks || now - t_idle > idle_ticks) {
-        found = -2;
-      } else {
-        for (int k = 0; k < nslots && found < 0; ++k) {
-          const int si = (scan + k) % nslots;
-          Slot* S = slots + si;
-          if (!__hip_atomic_load(&S->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            continue;
-          const unsigned long long c =
-              __hip_atomic_load(&S->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const unsigned T = (unsigned)S->g.tiles;
-          if ((unsigned)(c & 0xffffffffu) >= T) continue;
-          const unsigned long long old = atomicAdd(&S->claim, 1ull);
-          if ((unsigned)(old & 0xffffffffu) >= T) continue;
-          found = si;
-          sh_tile = (int)(old & 0xffffffffu);
-          sh_epoch = (int)(old >> 32);
-          scan = si;
-        }
-      }
-      sh_slot = found;
-    }
-    __syncthreads();
-    const int si = sh_slot;
-    if (si == -2) break;
-    if (si < 0) {
-      if (threadIdx.x == 0) __builtin_amdgcn_s_sleep(8);
-      __syncthreads();
+  for (int t = it.t0; t < it.t1; ++t, par ^= 1) {
+    double lv[2] = {0.0, 0.0};
+    run_body<KIND, CPL>(a, t, sc, lv);
+    if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
+  }
+}
+
+__global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* items,
+                                                const int* n_items, int step) {
+  __shared__ double lds[kLdsPerGroup];
+  const int n = __builtin_amdgcn_readfirstlane(*n_items);
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const Item it = items[i];
+    const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
+    const int m = step - S.admit_step;
+    const State s = load_state_uniform(S.S[m & 1]);
+    const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+    if (kind == K_DONE) {
+      if (it.t0 == 0 && threadIdx.x == 0) *S.S[(m + 1) & 1] = s;
       continue;
     }
-    t_idle = wall_clock64();
-    const int t = sh_tile, epoch = sh_epoch;
-    __threadfence();  // acquire: the epoch's scalars and the previous epoch's vectors
-    Slot* S = slots + si;
-    const int kind = S->kind, iter = S->iter;
-    const Sc sc = S->sc;
-    batch_tile(*S, kind, iter, sc, t, S->part[epoch & 1], lds + 8, par);
-    par ^= 1;
-    __threadfence();  // release this tile's vectors and partial
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned prev = atomicAdd(&S->done, 1u);
-      sh_close = (prev + 1 == (unsigned)S->g.tiles);
-    }
-    __syncthreads();
-    if (sh_close) {
-      __threadfence();  // acquire every tile's partial
-      batch_close(S, epoch, lds);
-      __threadfence();  // release the new scalars
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const unsigned long long nxt = (unsigned long long)(unsigned)(epoch + 1) << 32;
-        if (S->active) {
-          atomicExch(&S->claim, nxt);
-        } else {
-          atomicExch(&S->claim, nxt | kClaimClosed);
-          atomicSub(remaining, 1);
-        }
+    if (S.cpl4) {
+      switch (kind) {
+        case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds); break;
+        case K_CG1: step_item<K_CG1, 4>(S, it, m, s, lds); break;
+        case K_CG2: step_item<K_CG2, 4>(S, it, m, s, lds); break;
+        case K_RESID: step_item<K_RESID, 4>(S, it, m, s, lds); break;
+        case K_FINAL: step_item<K_FINAL, 4>(S, it, m, s, lds); break;
+        case K_REF_SCALE: step_item<K_REF_SCALE, 4>(S, it, m, s, lds); break;
+        case K_CG1F: step_item<K_CG1F, 4>(S, it, m, s, lds); break;
+        case K_CG2F: step_item<K_CG2F, 4>(S, it, m, s, lds); break;
+        case K_REF_UPDATE: step_item<K_REF_UPDATE, 4>(S, it, m, s, lds); break;
+      }
+    } else {
+      switch (kind) {
+        case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds); break;
+        case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds); break;
+        case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds); break;
+        case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds); break;
+        case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds); break;
+        case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds); break;
+        case K_FINAL: step_item<K_FINAL, 2>(S, it, m, s, lds); break;
       }
     }
+    __syncthreads();  // LDS reuse by the next item
   }
 }
 
-hipError_t launch_batch(Slot* slots, int nslots, int* remaining, long long budget_ticks,
-                        long long idle_ticks, int grid, hipStream_t st) {
-  if (nslots < 1 || grid < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kGroup), 0, st, slots, nslots, remaining,
-                     budget_ticks, idle_ticks);
+__global__ void k_gather(const Slot* slots, const int* idx, int n, int step, State* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const Slot& S = slots[idx[i]];
+    out[i] = *S.S[(step - S.admit_step) & 1];
+  }
+}
+
+hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items, int step,
+                       int grid, hipStream_t st) {
+  if (grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items, step);
   return hipGetLastError();
 }
 
-int batch_max_blocks_per_cu() {
+hipError_t launch_gather(const Slot* slots, const int* idx, int n, int step, State* out,
+                         hipStream_t st) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((n + 63) / 64), dim3(64), 0, st, slots, idx, n, step, out);
+  return hipGetLastError();
+}
+
+int step_max_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch, kGroup, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step, kGroup, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 

@@ -717,7 +717,14 @@ int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, doub
 
 // ---------------------------------------------------------- autotuner --
 
+// Times candidate tile shapes for one grid shape on the device and pins the
+// fastest.  Candidates: rows per wavefront strip x work-groups per pass (the
+// occupancy limit and 1/2, 1/3, 1/4 of it, capped by the tile count) x
+// columns per lane (2 or 4 for classic FP64).  Each candidate runs a short
+// fixed-iteration solve (tol = 0) twice; the score is the HIP-event time of
+// the iteration kernels of the second run per iteration.
 int Ctx::tune(int nx, int ny, int variant, int precision) {
+  Ctx& c = *this;
   cg_problem p;
   memset(&p, 0, sizeof(p));
   p.nx = nx;
@@ -725,77 +732,101 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
   p.variant = (cg_variant)variant;
   p.precision = (cg_precision)precision;
   p.tol = 0.0;
-  p.maxit = 8;
+  p.maxit = 24;
   p.mem = CG_MEM_DEVICE;
   if (use_wg(&p)) return CG_OK;  // single work-group path: nothing to tune
   const int fp32g = precision == CG_PREC_FP32_REFINED;
   const size_t n = (size_t)nx * ny;
-  void* bx = arena.alloc(2 * n * 8);
+  char* bx = (char*)arena.alloc(2 * n * 8);
   if (!bx) return CG_E_NOMEM;
+  struct Rel {
+    Arena& a;
+    char* m;
+    ~Rel() { a.release(m); }
+  } rel{arena, bx};
   double* b = (double*)bx;
   double* x = b + n;
-  Ctx& c = *this;
   HIPCHK(launch_fill(bx, 2 * n * 8, st));
-  // b = 1 everywhere is enough for timing: tol = 0 runs a fixed number of passes
+  // b = 1 everywhere: the timing does not depend on the values
   std::vector<double> ones(std::min<size_t>(n, 1 << 20), 1.0);
   for (size_t o = 0; o < n; o += ones.size()) {
-    size_t k = std::min(ones.size(), n - o);
+    const size_t k = std::min(ones.size(), n - o);
     HIPCHK(hipMemcpyAsync(b + o, ones.data(), k * 8, hipMemcpyHostToDevice, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   p.b = b;
   p.x = x;
-  const auto k = key(nx, ny, fp32g);
-  const bool had = pins.count(k) != 0;
-  const Pin saved = had ? pins[k] : Pin{};
-  const int kind = fp32g ? K_CG2F : (variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
-  const int cap = std::max(8, pass_max_blocks_per_cu(kind, fp32g) * num_cu);
-  double best = 1e30;
-  Pin bestp{default_rows(nx, ny, fp32g), 0};
+  const uint64_t k = key(nx, ny, fp32g);
+  std::vector<const char*> names;
+  if (fp32g) names = {"stencil_dot_f32", "update_norm_f32"};
+  else if (variant == CG_VARIANT_PIPELINED) names = {"pcg_pass"};
+  else names = {"stencil_dot", "update_norm"};
+  std::vector<int> cpls = {0};
+  if (!fp32g && variant == CG_VARIANT_CLASSIC) cpls = {2, 4};
   const bool save_prof = prof;
-  prof = false;
-  for (int rows : {2, 4, 8, 12, 16, 24, 32}) {
-    Geo g = make_geo(nx, ny, fp32g, rows);
-    std::vector<int> grids;
-    for (int div : {1, 2, 3, 4}) {
-      int gsz = (int)round_up((size_t)std::max(8, cap / div), 8);
-      if (gsz > (int)round_up((size_t)g.tiles, 8)) gsz = (int)round_up((size_t)g.tiles, 8);
-      if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
-    }
-    for (int gsz : grids) {
-      pins[k] = Pin{rows, gsz};
-      cg_result r;
-      int rc = solve(&p, &r);  // warm (graph capture, caches)
-      if (rc < 0) continue;
-      double t = 1e30;
-      for (int rep = 0; rep < 3; ++rep) {
-        rc = solve(&p, &r);
-        if (rc < 0) break;
-        t = std::min(t, r.device_seconds);
+  const auto save_stats = stats;
+  prof = true;
+  double best = 1e30;
+  Pin bestp{default_rows(nx, ny, fp32g), 0, 0};
+  for (int cpl : cpls) {
+    const int geo4 = fp32g || cpl == 4;
+    const int kind = fp32g ? K_CG2F : (variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
+    const int cap = std::max(8, pass_max_blocks_per_cu(kind, geo4) * num_cu);
+    for (int rows : {2, 4, 8, 16, 32, 64}) {
+      const Geo g = make_geo(nx, ny, geo4, rows);
+      if (rows > 4 * ((ny + 3) / 4)) continue;
+      std::vector<int> grids;
+      for (int div : {1, 2, 3, 4}) {
+        int gsz = (int)round_up((size_t)std::max(8, cap / div), 8);
+        gsz = std::min(gsz, (int)round_up((size_t)g.tiles, 8));
+        if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
       }
-      if (t < best) {
-        best = t;
-        bestp = Pin{rows, gsz};
+      for (int gsz : grids) {
+        pins[k] = Pin{rows, gsz, cpl};
+        cg_result r;
+        if (solve(&p, &r) < 0) continue;  // warms graphs and caches
+        stats.clear();
+        if (solve(&p, &r) < 0) continue;
+        double t = 0.0;
+        int64_t launches = 0;
+        for (const char* nm : names) {
+          auto it = stats.find(nm);
+          if (it != stats.end()) {
+            t += it->second.seconds;
+            launches = std::max(launches, it->second.launches);
+          }
+        }
+        if (launches == 0) continue;
+        t /= (double)launches;  // per iteration
+        if (t < best) {
+          best = t;
+          bestp = Pin{rows, gsz, cpl};
+        }
       }
     }
   }
   prof = save_prof;
+  stats = save_stats;
   pins[k] = bestp;
-  (void)had;
-  (void)saved;
-  arena.release(bx);
   save_tune_cache();
   return CG_OK;
 }
 
+// The tune cache is one JSON object per line:
+//   {"nx": 4096, "ny": 4096, "fp32": 0, "rows": 32, "grid": 1024, "cpl": 2}
 void Ctx::load_tune_cache() {
   if (tune_path.empty()) return;
   FILE* f = fopen(tune_path.c_str(), "r");
   if (!f) return;
-  int nx, ny, fp, rows, grid;
-  // one entry per line: nx ny fp32geometry rows grid
-  while (fscanf(f, "%d %d %d %d %d", &nx, &ny, &fp, &rows, &grid) == 5)
-    pins[key(nx, ny, fp)] = Pin{rows, grid};
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    int nx, ny, fp, rows, grid, cpl;
+    if (sscanf(line,
+               " {\"nx\": %d, \"ny\": %d, \"fp32\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}",
+               &nx, &ny, &fp, &rows, &grid, &cpl) == 6 &&
+        nx > 0 && ny > 0 && rows > 0 && grid >= 0 && (cpl == 0 || cpl == 2 || cpl == 4))
+      pins[key(nx, ny, fp)] = Pin{rows, grid, cpl};
+  }
   fclose(f);
 }
 
@@ -804,8 +835,9 @@ void Ctx::save_tune_cache() {
   FILE* f = fopen(tune_path.c_str(), "w");
   if (!f) return;
   for (auto& kv : pins)
-    fprintf(f, "%d %d %d %d %d\n", (int)(kv.first >> 33), (int)((kv.first >> 1) & 0xffffffff),
-            (int)(kv.first & 1), kv.second.rows, kv.second.grid);
+    fprintf(f, "{\"nx\": %d, \"ny\": %d, \"fp32\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}\n",
+            (int)(kv.first >> 33), (int)((kv.first >> 1) & 0xffffffff), (int)(kv.first & 1),
+            kv.second.rows, kv.second.grid, kv.second.cpl);
   fclose(f);
 }
 
@@ -839,6 +871,8 @@ int Ctx::init(const cg_config* cfg) {
   if (cfg && cfg->tune_cache) tune_path = cfg->tune_cache;
   if (const char* e = getenv("CG_GRAPH_CHUNK")) graph_chunk = atoi(e);
   if (const char* e = getenv("CG_WG_MAX_DOF")) wg_max_dof = atoi(e);
+  if (const char* e = getenv("CG_STEP_CHUNK")) step_chunk = std::max(1, atoi(e));
+  if (const char* e = getenv("CG_SERVE_CHUNK")) serve_chunk = std::max(1, atoi(e));
   load_tune_cache();
   return CG_OK;
 }

@@ -122,6 +122,12 @@ struct Ctx {
   char* host_state = nullptr;  // pinned staging for state words
   int graph_chunk = 32;        // iterations per captured chunk; 0 = plain launches
   int wg_max_dof = 16384;      // whole-solve-in-one-work-group threshold (FP64)
+  int step_chunk = 32;         // batch: steps between harvests
+  int serve_chunk = 8;         // serving: steps between admissions
+  size_t engine_bytes() const {  // control block of the multi-solve engine
+    return (size_t)max_slots * (sizeof(cgk::Slot) + 256 * sizeof(cgk::Item) + sizeof(int) +
+                                sizeof(cgk::State)) + 4096;
+  }
   bool capturing = false;
   bool prof = false;
   std::string last_error;
@@ -131,6 +137,7 @@ struct Ctx {
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_free;
   Server* server = nullptr;
+  std::mutex server_mu;  // guards `server` only (submit/poll never wait for an epoch)
 
   static uint64_t key(int nx, int ny, int fp32g) {
     return ((uint64_t)(uint32_t)nx << 33) | ((uint64_t)(uint32_t)ny << 1) | (uint64_t)(fp32g & 1);

@@ -1,15 +1,15 @@
-// cg_serve.cpp - many solves on one GPU: the persistent batch engine behind
+// cg_serve.cpp - many solves on one GPU: the multi-solve step engine behind
 // cg_solve_batch, and the continuous-batching request server behind
 // cg_submit / cg_poll.
 //
 // Engine: a fixed array of device slots (cgk::Slot).  A solve is admitted
 // into a free slot when its device footprint fits the arena (its workspace is
-// carved from the arena, its inputs staged, its state initialised); then
-// every launch of the persistent kernel advances all resident solves
-// together, for at most a time budget; between launches finished solves are
-// harvested (solution copied out, memory returned) and new ones admitted.
-// Each solve keeps its x/r/p... vectors resident on the device from
-// admission to retirement.
+// carved from the arena, its inputs staged, its state initialised).  Every
+// launch of the step kernel then advances all resident solves by one pass,
+// over a table of (solve, tile range) items; chunks of steps run back to
+// back, and between chunks finished solves are harvested (solution copied
+// out, memory returned) and new ones admitted.  Each solve keeps its vectors
+// and scalars resident on the device from admission to retirement.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +34,7 @@ struct Job {
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   Work w;
   int slot = -1;
+  int steps_cap = 0;
   bool finished = false;
   int rc = CG_PENDING;  // final status (or a negative error)
   cg_result res{};
@@ -41,41 +42,47 @@ struct Job {
 
 class Engine {
  public:
+  static constexpr int kMaxItemsPerSolve = 256;
+
   explicit Engine(Ctx& c, int nslots) : c_(c), n_(std::max(1, nslots)) {}
   ~Engine() {
     for (Job* j : slot_job_)
       if (j) c_.arena.release(j->w.mem);
     if (ctrl_) c_.arena.release(ctrl_);
     if (h_slots_) hipHostFree(h_slots_);
-    if (h_rem_) hipHostFree(h_rem_);
+    if (h_items_) hipHostFree(h_items_);
+    if (h_idx_) hipHostFree(h_idx_);
+    if (h_states_) hipHostFree(h_states_);
   }
 
   int init() {
-    const size_t bytes = (size_t)n_ * sizeof(Slot) + 256;
-    ctrl_ = (char*)c_.arena.alloc(bytes);
+    max_items_ = n_ * kMaxItemsPerSolve;
+    const size_t b_slots = round256((size_t)n_ * sizeof(Slot));
+    const size_t b_items = round256((size_t)max_items_ * sizeof(Item));
+    const size_t b_idx = round256((size_t)n_ * sizeof(int) + sizeof(int));
+    const size_t b_states = round256((size_t)n_ * sizeof(State));
+    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states);
     if (!ctrl_) return CG_E_NOMEM;
     d_slots_ = (Slot*)ctrl_;
-    d_rem_ = (int*)(ctrl_ + (size_t)n_ * sizeof(Slot));
-    if (hipHostMalloc((void**)&h_slots_, (size_t)n_ * sizeof(Slot), hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void**)&h_rem_, 256, hipHostMallocDefault) != hipSuccess)
+    d_items_ = (Item*)(ctrl_ + b_slots);
+    d_idx_ = (int*)(ctrl_ + b_slots + b_items);
+    d_nitems_ = d_idx_ + n_;
+    d_states_ = (State*)(ctrl_ + b_slots + b_items + b_idx);
+    if (hipHostMalloc((void**)&h_slots_, (size_t)n_ * sizeof(Slot), hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_items_, (size_t)max_items_ * sizeof(Item) + 256,
+                      hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_idx_, (size_t)n_ * sizeof(int) + 256, hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_states_, (size_t)n_ * sizeof(State), hipHostMallocDefault))
       return CG_E_DEVICE;
     memset(h_slots_, 0, (size_t)n_ * sizeof(Slot));
-    if (hipMemcpyAsync(d_slots_, h_slots_, (size_t)n_ * sizeof(Slot), hipMemcpyHostToDevice,
-                       c_.st) != hipSuccess)
-      return CG_E_DEVICE;
     slot_job_.assign(n_, nullptr);
-    grid_ = std::max(8, batch_max_blocks_per_cu() * c_.num_cu);
-    int khz = 0;
-    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c_.device) != hipSuccess ||
-        khz <= 0)
-      return CG_E_DEVICE;
-    ticks_per_s_ = (double)khz * 1e3;
-    return hipStreamSynchronize(c_.st) == hipSuccess ? CG_OK : CG_E_DEVICE;
+    grid_ = std::max(8, step_max_blocks_per_cu() * c_.num_cu);
+    return upload_items();
   }
 
   int active() const { return active_; }
   bool has_free() const { return active_ < n_; }
+  int step() const { return step_; }
 
   // CG_OK when admitted, CG_E_NOMEM when the arena has no room right now.
   int admit(Job* j) {
@@ -94,6 +101,15 @@ class Engine {
       c_.arena.release(j->w.mem);
       return rc;
     }
+    // the first pass: r = b - A x (FP64) or the first outer residual (refined)
+    State s;
+    memset(&s, 0, sizeof(s));
+    s.status = ST_RUNNING;
+    s.flags = F_BB_PENDING;
+    s.tol = j->p.tol;
+    s.inner_tol = j->p.inner_tol > 0.0 ? j->p.inner_tol : 1e-4;
+    s.maxit = j->p.maxit;
+    s.kind = j->w.pl.refined ? K_RESID : K_INIT_R;
     Slot& S = h_slots_[slot];
     memset(&S, 0, sizeof(S));
     const Work& w = j->w;
@@ -101,6 +117,8 @@ class Engine {
     S.variant = j->p.variant;
     S.refined = w.pl.refined ? 1 : 0;
     S.cpl4 = w.pl.fp32g;
+    // pass m of this solve runs at step admit_step + m; its state is S[m & 1]
+    S.admit_step = step_;
     S.b = w.b;
     S.x = w.x;
     S.r = w.r;
@@ -117,70 +135,68 @@ class Engine {
     S.PF[1] = w.pf[1];
     S.part[0] = w.part[0];
     S.part[1] = w.part[1];
-    S.st = w.S[0];
-    S.active = 1;
-    S.kind = w.pl.refined ? K_RESID : K_INIT_R;
-    S.iter = 0;
-    S.claim = 0;
-    S.done = 0;
-    if (hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st) !=
-        hipSuccess) {
+    S.S[0] = w.S[0];
+    S.S[1] = w.S[1];
+    memcpy(c_.host_state, &s, sizeof(s));
+    if (hipMemcpyAsync(w.S[0], c_.host_state, sizeof(State), hipMemcpyHostToDevice, c_.st) ||
+        hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st) ||
+        hipStreamSynchronize(c_.st)) {
       c_.arena.release(j->w.mem);
       return CG_E_DEVICE;
     }
     slot_job_[slot] = j;
     j->slot = slot;
     j->t_admit = now_s();
+    // a solve finishes within 5 maxit + 16 passes: 2 per inner iteration and
+    // at most 3 per outer step, each outer step taking an inner iteration
+    j->steps_cap = step_ + 5 * j->p.maxit + 16;
     ++active_;
+    dirty_ = true;
     return CG_OK;
   }
 
-  // One launch of the persistent kernel over every resident solve.
-  int run(double budget_s) {
+  // Launches `steps` steps of every resident solve.
+  int run(int steps) {
     if (!active_) return CG_OK;
-    *h_rem_ = active_;
-    if (hipMemcpyAsync(d_rem_, h_rem_, sizeof(int), hipMemcpyHostToDevice, c_.st) != hipSuccess)
-      return CG_E_DEVICE;
-    const long long budget = (long long)(budget_s * ticks_per_s_);
-    const long long idle = (long long)(std::max(budget_s, 0.05) * ticks_per_s_);
+    if (dirty_ && upload_items()) return CG_E_DEVICE;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c_.prof) {
       e0 = c_.event();
       e1 = c_.event();
       hipEventRecord(e0, c_.st);
     }
-    if (launch_batch(d_slots_, n_, d_rem_, budget, idle, grid_, c_.st) != hipSuccess)
-      return CG_E_DEVICE;
+    for (int k = 0; k < steps; ++k)
+      if (launch_step(d_slots_, d_items_, d_nitems_, step_ + k, grid_, c_.st) != hipSuccess)
+        return CG_E_DEVICE;
     if (c_.prof) {
       hipEventRecord(e1, c_.st);
-      c_.pending.push_back({e0, e1, "batch_persistent", 0.0});
+      c_.pending.push_back({e0, e1, "batch_steps", 0.0});
     }
-    if (hipStreamSynchronize(c_.st) != hipSuccess) return CG_E_DEVICE;
-    if (c_.prof) c_.prof_collect();
-    ++launches_;
+    step_ += steps;
     return CG_OK;
   }
 
   // Moves finished solves out: copies x back, fills the result, frees memory.
   int harvest(std::vector<Job*>& done) {
     if (!active_) return CG_OK;
-    if (hipMemcpyAsync(h_slots_, d_slots_, (size_t)n_ * sizeof(Slot), hipMemcpyDeviceToHost,
-                       c_.st) != hipSuccess ||
-        hipStreamSynchronize(c_.st) != hipSuccess)
+    int n = 0;
+    for (int i = 0; i < n_; ++i)
+      if (slot_job_[i]) h_idx_[n++] = i;
+    if (hipMemcpyAsync(d_idx_, h_idx_, (size_t)n * sizeof(int), hipMemcpyHostToDevice, c_.st) ||
+        launch_gather(d_slots_, d_idx_, n, step_, d_states_, c_.st) ||
+        hipMemcpyAsync(h_states_, d_states_, (size_t)n * sizeof(State), hipMemcpyDeviceToHost,
+                       c_.st) ||
+        hipStreamSynchronize(c_.st))
       return CG_E_DEVICE;
-    unsigned long long progress = 0;
-    for (int i = 0; i < n_; ++i) {
+    if (c_.prof) c_.prof_collect();
+    for (int k = 0; k < n; ++k) {
+      const int i = h_idx_[k];
       Job* j = slot_job_[i];
-      if (!j) continue;
-      progress += (h_slots_[i].claim >> 32) + (h_slots_[i].claim & 0xffffffffu) +
-                  h_slots_[i].done;
-      if (h_slots_[i].active) continue;
-      State s;
-      if (hipMemcpyAsync(c_.host_state, j->w.S[0], sizeof(State), hipMemcpyDeviceToHost,
-                         c_.st) != hipSuccess ||
-          hipStreamSynchronize(c_.st) != hipSuccess)
-        return CG_E_DEVICE;
-      memcpy(&s, c_.host_state, sizeof(s));
+      const State& s = h_states_[k];
+      if (s.kind != K_DONE) {
+        if (step_ > j->steps_cap) return CG_E_DEVICE;  // cannot happen: passes are bounded
+        continue;
+      }
       int rc = stage_out(c_, j->w, &j->p, s);
       j->t_done = now_s();
       if (rc) {
@@ -194,15 +210,9 @@ class Engine {
       slot_job_[i] = nullptr;
       j->slot = -1;
       --active_;
+      dirty_ = true;
       done.push_back(j);
     }
-    // A launch that moved no solve at all means the kernel cannot progress.
-    if (progress == last_progress_ && active_ > 0) {
-      if (++stalls_ >= 3) return CG_E_DEVICE;
-    } else {
-      stalls_ = 0;
-    }
-    last_progress_ = progress;
     return CG_OK;
   }
 
@@ -219,25 +229,52 @@ class Engine {
       done.push_back(j);
     }
     active_ = 0;
+    dirty_ = true;
   }
 
-  int launches() const { return launches_; }
-
  private:
+  static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+  // Rebuilds the item table: each resident solve contributes up to
+  // kMaxItemsPerSolve items of consecutive tiles.
+  int upload_items() {
+    int n = 0;
+    for (int i = 0; i < n_; ++i) {
+      Job* j = slot_job_[i];
+      if (!j) continue;
+      const int T = j->w.pl.g.tiles;
+      const int per = (T + kMaxItemsPerSolve - 1) / kMaxItemsPerSolve;
+      for (int t = 0; t < T; t += per) h_items_[n++] = Item{i, t, std::min(T, t + per), 0};
+    }
+    int* nn = (int*)(h_items_ + max_items_);
+    *nn = n;
+    if (hipMemcpyAsync(d_items_, h_items_, (size_t)std::max(n, 1) * sizeof(Item),
+                       hipMemcpyHostToDevice, c_.st) ||
+        hipMemcpyAsync(d_nitems_, nn, sizeof(int), hipMemcpyHostToDevice, c_.st) ||
+        hipStreamSynchronize(c_.st))
+      return CG_E_DEVICE;
+    dirty_ = false;
+    return CG_OK;
+  }
+
   Ctx& c_;
   int n_;
+  int max_items_ = 0;
   char* ctrl_ = nullptr;
   Slot* d_slots_ = nullptr;
-  int* d_rem_ = nullptr;
+  Item* d_items_ = nullptr;
+  int* d_idx_ = nullptr;
+  int* d_nitems_ = nullptr;
+  State* d_states_ = nullptr;
   Slot* h_slots_ = nullptr;
-  int* h_rem_ = nullptr;
+  Item* h_items_ = nullptr;
+  int* h_idx_ = nullptr;
+  State* h_states_ = nullptr;
   std::vector<Job*> slot_job_;
   int active_ = 0;
   int grid_ = 8;
-  double ticks_per_s_ = 1e8;
-  unsigned long long last_progress_ = ~0ull;
-  int stalls_ = 0;
-  int launches_ = 0;
+  int step_ = 0;
+  bool dirty_ = true;
 };
 
 static int worse(int a, int b) {
@@ -248,11 +285,12 @@ static int worse(int a, int b) {
 
 int Ctx::solve_batch(const cg_problem* probs, int n, cg_result* results) {
   for (int i = 0; i < n; ++i)
-    if (plan(&probs[i]).footprint + (size_t)max_slots * sizeof(Slot) + 256 > arena.size())
+    if (plan(&probs[i]).footprint + engine_bytes() > arena.size())
       return CG_E_NOMEM;
   int rc = order_after_user();
   if (rc) return rc;
   Engine eng(*this, std::min(n, max_slots));
+  const int chunk = step_chunk;
   if ((rc = eng.init())) return rc;
   std::vector<Job> jobs(n);
   std::deque<int> pending;
@@ -274,7 +312,7 @@ int Ctx::solve_batch(const cg_problem* probs, int n, cg_result* results) {
       }
       pending.pop_front();
     }
-    if ((rc = eng.run(1.0)) || (rc = eng.harvest(done))) {
+    if ((rc = eng.run(chunk)) || (rc = eng.harvest(done))) {
       eng.abandon(done, rc);
       return rc;
     }
@@ -295,7 +333,7 @@ class Server {
   ~Server() { stop(); }
 
   int submit(const cg_problem* p, uint64_t* ticket) {
-    if (footprint_of(p) + (size_t)c_.max_slots * sizeof(Slot) + 256 > c_.arena.size())
+    if (footprint_of(p) + c_.engine_bytes() > c_.arena.size())
       return CG_E_NOMEM;
     Job* j = new Job;
     j->p = *p;
@@ -342,9 +380,6 @@ class Server {
     jobs_.clear();
     queue_.clear();
   }
-
-  // serving knobs
-  double budget_s = 0.002;
 
  private:
   void loop() {
@@ -393,7 +428,7 @@ class Server {
             j->t_done = now_s();
           }
         }
-        if (rc == CG_OK) rc = eng->run(budget_s);
+        if (rc == CG_OK) rc = eng->run(c_.serve_chunk);
         if (rc == CG_OK) rc = eng->harvest(done);
         if (rc != CG_OK) eng->abandon(done, rc);
       }
@@ -424,17 +459,19 @@ using cgr::Ctx;
 using cgr::Server;
 
 int cgr_server_submit(Ctx* c, const cg_problem* p, uint64_t* ticket) {
+  Server* s;
   {
-    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    std::lock_guard<std::mutex> lk(c->server_mu);
     if (!c->server) c->server = new Server(*c);
+    s = c->server;
   }
-  return c->server->submit(p, ticket);
+  return s->submit(p, ticket);
 }
 
 int cgr_server_poll(Ctx* c, uint64_t ticket, cg_result* res) {
   Server* s;
   {
-    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    std::lock_guard<std::mutex> lk(c->server_mu);
     s = c->server;
   }
   if (!s) return CG_E_TICKET;
@@ -444,7 +481,7 @@ int cgr_server_poll(Ctx* c, uint64_t ticket, cg_result* res) {
 void cgr_server_stop(Ctx* c) {
   Server* s;
   {
-    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    std::lock_guard<std::mutex> lk(c->server_mu);
     s = c->server;
     c->server = nullptr;
   }

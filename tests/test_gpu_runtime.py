@@ -1,0 +1,138 @@
+"""GPU tests of the runtime around the kernels: autotuner and its cache, pinned
+tile shapes (the reduction order follows the shape), profiling statistics,
+the HBM probe, and a caller-provided arena tensor and stream."""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import MODE_CANONICAL
+from paper_1803_03797_amd import cg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def order_of(ctx, nx, ny, variant=0, precision=0):
+    info = ctx.cg_plan(nx, ny, variant, precision)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2), info
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_tune_cache_and_parity(tmp_path, variant):
+    nx, ny = 700, 300
+    cache = str(tmp_path / "tune.json")
+    with cg.Context(device=0, arena_bytes=1 << 30, tune_cache=cache) as ctx:
+        say("tune", nx, ny, variant)
+        ctx.cg_tune(nx, ny, variant)
+        o, info = order_of(ctx, nx, ny, variant)
+        lines = [json.loads(l) for l in open(cache)]
+        assert any(d["nx"] == nx and d["ny"] == ny and d["rows"] == info.rows for d in lines)
+        b = np.random.default_rng(1).uniform(-1, 1, (ny, nx))
+        x = np.zeros_like(b)
+        rc, r = ctx.solve(b, x, nx, ny, tol=0.0, maxit=30, variant=variant)
+        xo, ro = oracle.cg(b, nx, ny, variant=variant, tol=0.0, maxit=30, mode=MODE_CANONICAL,
+                           order=o)
+        np.testing.assert_array_equal(x, xo)
+    with cg.Context(device=0, arena_bytes=1 << 30, tune_cache=cache) as ctx2:
+        info2 = ctx2.cg_plan(nx, ny, variant)
+        assert (info2.rows, info2.cols_per_lane, info2.grid) == (info.rows, info.cols_per_lane,
+                                                                info.grid)
+
+
+@pytest.mark.parametrize("rows", [1, 3, 32])
+def test_pinned_wide_lanes_classic_bitwise(rows):
+    """Classic FP64 with 4 columns per lane: the canonical order with
+    cols_per_lane = 4 reproduces it bitwise, alone and in a batch."""
+    nx, ny = 513, 130
+    with cg.Context(device=0, arena_bytes=1 << 30) as ctx:
+        ctx.cg_pin_tile(nx, ny, rows, 0, cg.CG_PREC_FP64, 4)
+        o, info = order_of(ctx, nx, ny, 0)
+        assert info.cols_per_lane == 4 and info.rows == rows
+        b = np.random.default_rng(rows).uniform(-1, 1, (ny, nx))
+        x = np.zeros_like(b)
+        say("wide lanes rows", rows)
+        rc, r = ctx.solve(b, x, nx, ny, tol=1e-8, maxit=5000, variant=0)
+        xo, ro = oracle.cg(b, nx, ny, variant=0, tol=1e-8, maxit=5000, mode=MODE_CANONICAL,
+                           order=o)
+        assert r.iterations == ro.iterations
+        np.testing.assert_array_equal(x, xo)
+        xb = np.zeros_like(b)
+        rc, res = ctx.cg_solve_batch([cg.make_problem(b, xb, nx, ny, tol=1e-8, maxit=5000)])
+        np.testing.assert_array_equal(xb, xo)
+
+
+def test_pin_rejects_bad_shapes():
+    with cg.Context(device=0, arena_bytes=64 << 20) as ctx:
+        for args in ((10, 10, 0, 0, 0, 3), (10, 10, 0, 0, 0, 0), (10, 10, 4, -1, 0, 0),
+                     (10, 10, 4, 0, cg.CG_PREC_FP32_REFINED, 2)):
+            nx, ny, rows, grid, prec, cpl = args
+            assert ctx.lib.cg_pin_tile(ctx.h, nx, ny, prec, rows, grid, cpl) == cg.CG_E_INVALID
+
+
+def test_profiling_statistics(torch):
+    n = 1024
+    with cg.Context(device=0, arena_bytes=1 << 30) as ctx:
+        b = torch.rand(n * n, dtype=torch.float64, device="cuda")
+        x = torch.zeros_like(b)
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        say("profiling stats")
+        rc, r = ctx.solve(b, x, n, n, tol=0.0, maxit=37, variant=1)
+        st = ctx.cg_kernel_stats(reset=True)
+        assert st["pcg_pass"]["launches"] == 37
+        assert st["final_check"]["launches"] == 1 and st["final_check"]["bytes"] == 0
+        assert st["pcg_pass"]["bytes"] == 37 * 96 * n * n
+        rc, r = ctx.solve(b, x, n, n, tol=0.0, maxit=12, variant=0)
+        st = ctx.cg_kernel_stats(reset=False)
+        assert st["stencil_dot"]["launches"] == 12 and st["update_norm"]["launches"] == 12
+        assert ctx.cg_kernel_stats(reset=True) == st
+        assert ctx.cg_kernel_stats() == {}
+
+
+def test_stream_probe():
+    with cg.Context(device=0, arena_bytes=2 << 30) as ctx:
+        for pat, moved in ((0, 1), (1, 2), (2, 3), (3, 5), (4, 12)):
+            t, nbytes = ctx.cg_stream_probe(pat, 1 << 22, 2)
+            assert nbytes == moved * (1 << 22) * 8 and t > 0
+            say("probe", pat, "%.0f GB/s" % (nbytes / t / 1e9))
+        with pytest.raises(cg.CGError):
+            ctx.cg_stream_probe(5, 1 << 20, 1)
+
+
+def test_caller_arena_and_stream(torch):
+    """Workspace carved from a caller's uint8 tensor; work ordered after the
+    caller's stream."""
+    nx, ny = 300, 200
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    rng = np.random.default_rng(2)
+    bh = rng.uniform(-1, 1, (ny, nx))
+    with cg.Context(device=0, stream=stream, arena=arena) as ctx:
+        with torch.cuda.stream(stream):
+            b = torch.from_numpy(bh).cuda()
+            b.mul_(2.0)  # pending work on the caller's stream
+            x = torch.zeros_like(b)
+        rc, r = ctx.solve(b, x, nx, ny, tol=1e-9, maxit=5000, variant=1)
+        o, _ = order_of(ctx, nx, ny, 1)
+        xo, ro = oracle.cg(2.0 * bh, nx, ny, variant=1, tol=1e-9, maxit=5000,
+                           mode=MODE_CANONICAL, order=o)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(x.cpu().numpy(), xo)
+    # an arena pointer without a size is rejected
+    import ctypes as C
+    h = C.c_void_p()
+    cfg = cg.cg_config(0, None, arena.data_ptr(), 0, 0, None)
+    assert cg.load().cg_create(C.byref(cfg), C.byref(h)) == cg.CG_E_INVALID
