@@ -38,10 +38,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_DOF = {"pcg_pass": 96, "stencil_dot": 24, "update_norm": 40}
-# HBM bytes per pcg_pass launch at 4096 x 4096 from rocprofv3 counters
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 134 MB copy kernel
-# gives); None until measured for the current kernel.
-PCG_TRAFFIC_BYTES = None
+# HBM bytes per pcg_pass launch at 4096 x 4096 from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors the library's 134 MB
+# copy kernel gives for the same counters); set to None whenever pcg_pass
+# changes, until the counters are taken again.
+PCG_TRAFFIC_BYTES = 1641154582
 
 
 def log(*a):
@@ -305,7 +306,7 @@ def bench_batch(args):
                "sample": "the %d smallest of the solves, pipelined CG, explicit CSR, single "
                          "thread (%.1f s)" % (len(order), ct),
                "extrapolated_batch_seconds": round(work / (cw / ct), 1)}
-    emit({"metric": "batch solves/s (pipelined FP64, tol 1e-8, one persistent launch)",
+    emit({"metric": "batch solves/s (pipelined FP64, tol 1e-8, multi-solve step kernel)",
           "workload": "batch",
           "config": {"workload": "%d solves, sides i.i.d. from {64..1024} per axis, b~U[-1,1]"
                                  % len(shapes), "total_dof": int(dof.sum())},
@@ -401,7 +402,11 @@ def bench_serve(args):
         return cg.make_problem(bs[m], x, nx, ny, tol=tol, maxit=200000, variant=0,
                                precision=precision, inner_tol=1e-4)
 
-    # 1. per-request FP64, everything queued at t = 0: service times, capacity
+    def met(rc, r, m):
+        # equal accuracy: every result's true FP64 residual meets its tolerance
+        return int(rc == cg.CG_OK and r.rel_res_true <= reqs[m][2] * 1.0000001)
+
+    # per-request FP64: one cg_solve after another, all queued at t = 0
     x64 = [torch.zeros_like(b) for b in bs]
     for m in range(min(4, len(reqs))):
         ctx.cg_solve(prob(m, torch.zeros_like(bs[m]), 0))
@@ -412,23 +417,20 @@ def bench_serve(args):
         t = time.perf_counter()
         rc, r = ctx.cg_solve(prob(m, x64[m], 0))
         svc[m] = time.perf_counter() - t
-        ok64 += int(rc == cg.CG_OK and r.rel_res_true <= reqs[m][2] * 1.0000001)
-    cap = len(reqs) / (time.perf_counter() - t0)
-    rate = args.load * cap
-    arrivals = workloads.poisson_arrivals(len(reqs), rate)
-    log("per-request FP64 capacity %.1f solves/s; arrival rate %.1f/s" % (cap, rate))
+        ok64 += met(rc, r, m)
+    cap64 = len(reqs) / (time.perf_counter() - t0)
+    log("per-request FP64: %.1f solves/s" % cap64)
 
-    # per-request FP64 at that arrival process: one server, FIFO, measured
-    # service times (the queue is replayed from the measured times)
-    done = 0.0
-    lat64 = np.zeros(len(reqs))
-    for m in range(len(reqs)):
-        start = max(done, arrivals[m])
-        done = start + svc[m]
-        lat64[m] = done - arrivals[m]
-    make64 = done
+    def fifo(arrivals):
+        # one server, FIFO, the measured service times
+        done = 0.0
+        lat = np.zeros(len(reqs))
+        for m in range(len(reqs)):
+            done = max(done, arrivals[m]) + svc[m]
+            lat[m] = done - arrivals[m]
+        return lat, done
 
-    def served(precision):
+    def served(precision, arrivals):
         xs = [torch.zeros_like(b) for b in bs]
         tickets = [None] * len(reqs)
         results = {}
@@ -436,10 +438,11 @@ def bench_serve(args):
 
         def submitter():
             for m in range(len(reqs)):
-                dt = arrivals[m] - (time.perf_counter() - start)
-                if dt > 0:
-                    time.sleep(dt)
-                tickets[m] = (ctx.cg_submit(prob(m, xs[m], precision)), time.perf_counter())
+                if arrivals is not None:
+                    dt = arrivals[m] - (time.perf_counter() - start)
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets[m] = ctx.cg_submit(prob(m, xs[m], precision))
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -447,39 +450,52 @@ def bench_serve(args):
             for m in range(len(reqs)):
                 if m in results or tickets[m] is None:
                     continue
-                rc, r = ctx.cg_poll(tickets[m][0])
+                rc, r = ctx.cg_poll(tickets[m])
                 if rc != cg.CG_PENDING:
-                    results[m] = (rc, r.rel_res_true, r.iterations, r.latency_seconds,
-                                  time.perf_counter() - start)
+                    results[m] = (rc, cg.cg_result.from_buffer_copy(r), time.perf_counter() - start)
             time.sleep(0.0005)
         th.join()
-        makespan = max(v[4] for v in results.values())
-        lat = np.array([results[m][3] for m in range(len(reqs))])
-        ok = sum(int(results[m][0] == cg.CG_OK and results[m][1] <= reqs[m][2] * 1.0000001)
-                 for m in range(len(reqs)))
-        return xs, dict(solves_per_s=round(len(reqs) / makespan, 2), makespan_s=round(makespan, 3),
+        makespan = max(v[2] for v in results.values())
+        lat = np.array([results[m][1].latency_seconds for m in range(len(reqs))])
+        ok = sum(met(results[m][0], results[m][1], m) for m in range(len(reqs)))
+        return xs, dict(solves_per_s=round(len(reqs) / makespan, 2),
+                        makespan_s=round(makespan, 3),
                         p50_ms=round(float(np.median(lat)) * 1e3, 3),
                         p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),
                         met_tolerance=ok)
 
-    xs_ref, served_ref = served(cg.CG_PREC_FP32_REFINED)
-    log("served refined", json.dumps(served_ref))
-    xs_64, served_64 = served(cg.CG_PREC_FP64)
-    log("served fp64", json.dumps(served_64))
+    # saturated throughput: every request submitted at t = 0
+    xs_ref, sat_ref = served(cg.CG_PREC_FP32_REFINED, None)
+    log("served FP32-refined, saturated", json.dumps(sat_ref))
+    xs_64, sat_64 = served(cg.CG_PREC_FP64, None)
+    log("served FP64, saturated", json.dumps(sat_64))
     same = sum(int(torch.equal(a, c)) for a, c in zip(xs_64, x64))
+    # latency under Poisson arrivals at fractions of the per-request capacity
+    loads = {}
+    for frac in args.loads:
+        arr = workloads.poisson_arrivals(len(reqs), frac * cap64, seed_item=int(frac * 100))
+        lat64, make64 = fifo(arr)
+        entry = {"arrival_rate_per_s": round(frac * cap64, 2),
+                 "per_request_fp64": dict(solves_per_s=round(len(reqs) / make64, 2),
+                                          p50_ms=round(float(np.median(lat64)) * 1e3, 3),
+                                          p99_ms=round(float(np.percentile(lat64, 99)) * 1e3,
+                                                       3))}
+        _, entry["served_fp32_refined"] = served(cg.CG_PREC_FP32_REFINED, arr)
+        _, entry["served_fp64"] = served(cg.CG_PREC_FP64, arr)
+        loads["%.2f" % frac] = entry
+        log("load %.2f:" % frac, json.dumps(entry))
     emit({"metric": "served solves/s and p50/p99 latency (FP32-refined vs per-request FP64)",
           "workload": "serve",
           "config": {"workload": "%d requests, sides log-uniform [32,2048] per axis, tol 1e-6 or "
-                                 "1e-8, b~U[-1,1], Poisson arrivals at %.2f x the per-request "
-                                 "FP64 capacity" % (len(reqs), args.load),
-                     "arrival_rate_per_s": round(rate, 2), "total_dof": int(dof.sum())},
-          "per_request_fp64": {"capacity_solves_per_s": round(cap, 2),
-                               "solves_per_s_at_rate": round(len(reqs) / make64, 2),
-                               "p50_ms": round(float(np.median(lat64)) * 1e3, 3),
-                               "p99_ms": round(float(np.percentile(lat64, 99)) * 1e3, 3),
-                               "met_tolerance": ok64,
-                               "latency_model": "FIFO replay of measured service times"},
-          "served_fp32_refined": served_ref, "served_fp64": served_64,
+                                 "1e-8, b~U[-1,1]" % len(reqs), "total_dof": int(dof.sum()),
+                     "classic CG; refined: inner tol 1e-4": True},
+          "saturated_solves_per_s": {"per_request_fp64": round(cap64, 2),
+                                     "served_fp32_refined": sat_ref["solves_per_s"],
+                                     "served_fp64": sat_64["solves_per_s"]},
+          "saturated": {"served_fp32_refined": sat_ref, "served_fp64": sat_64,
+                        "per_request_fp64_met_tolerance": ok64},
+          "poisson_loads_x_per_request_capacity": loads,
+          "per_request_latency_model": "FIFO replay of the measured per-request service times",
           "served_fp64_equals_alone_bitwise": same, "of": len(reqs)})
     ctx.close()
 
@@ -523,7 +539,7 @@ def main():
     ap.add_argument("--count", type=int, default=None)
     ap.add_argument("--cpu-solves", type=int, default=16)
     ap.add_argument("--n-huge", type=int, default=8192)
-    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.5])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
