@@ -155,10 +155,11 @@ hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slo
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
-// One step of every resident solve: work-groups stride over the *n_items
-// items; grid is any positive size.
-hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items, int step,
-                       int grid, hipStream_t s);
+// Step *step_base + k of every resident solve: work-groups stride over the
+// *n_items items; grid is any positive size.  The base step is read on the
+// device so that a captured chunk of launches can be replayed.
+hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
+                       const int* step_base, int k, int grid, hipStream_t s);
 // Copies each listed slot's current state (pass parity of `step`) to out[i].
 hipError_t launch_gather(const Slot* slots, const int* idx, int n, int step, State* out,
                          hipStream_t s);

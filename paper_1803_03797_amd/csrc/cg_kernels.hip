@@ -1201,9 +1201,11 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
 }
 
 __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* items,
-                                                const int* n_items, int step) {
+                                                const int* n_items, const int* step_base,
+                                                int k) {
   __shared__ double lds[kLdsPerGroup];
   const int n = __builtin_amdgcn_readfirstlane(*n_items);
+  const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const Item it = items[i];
     const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
@@ -1249,10 +1251,11 @@ __global__ void k_gather(const Slot* slots, const int* idx, int n, int step, Sta
   }
 }
 
-hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items, int step,
-                       int grid, hipStream_t st) {
+hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
+                       const int* step_base, int k, int grid, hipStream_t st) {
   if (grid < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_step, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items, step);
+  hipLaunchKernelGGL(k_step, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items, step_base,
+                     k);
   return hipGetLastError();
 }
 

@@ -124,6 +124,7 @@ struct Ctx {
   int wg_max_dof = 16384;      // whole-solve-in-one-work-group threshold (FP64)
   int step_chunk = 32;         // batch: steps between harvests
   int serve_chunk = 8;         // serving: steps between admissions
+  int step_chunk_for(bool serving) const { return serving ? serve_chunk : step_chunk; }
   size_t engine_bytes() const {  // control block of the multi-solve engine
     return (size_t)max_slots * (sizeof(cgk::Slot) + 256 * sizeof(cgk::Item) + sizeof(int) +
                                 sizeof(cgk::State)) + 4096;

@@ -46,6 +46,7 @@ class Engine {
 
   explicit Engine(Ctx& c, int nslots) : c_(c), n_(std::max(1, nslots)) {}
   ~Engine() {
+    if (graph_) hipGraphExecDestroy(graph_);
     for (Job* j : slot_job_)
       if (j) c_.arena.release(j->w.mem);
     if (ctrl_) c_.arena.release(ctrl_);
@@ -53,6 +54,7 @@ class Engine {
     if (h_items_) hipHostFree(h_items_);
     if (h_idx_) hipHostFree(h_idx_);
     if (h_states_) hipHostFree(h_states_);
+    if (h_step_) hipHostFree(h_step_);
   }
 
   int init() {
@@ -61,18 +63,20 @@ class Engine {
     const size_t b_items = round256((size_t)max_items_ * sizeof(Item));
     const size_t b_idx = round256((size_t)n_ * sizeof(int) + sizeof(int));
     const size_t b_states = round256((size_t)n_ * sizeof(State));
-    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states);
+    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states + 256);
     if (!ctrl_) return CG_E_NOMEM;
     d_slots_ = (Slot*)ctrl_;
     d_items_ = (Item*)(ctrl_ + b_slots);
     d_idx_ = (int*)(ctrl_ + b_slots + b_items);
     d_nitems_ = d_idx_ + n_;
     d_states_ = (State*)(ctrl_ + b_slots + b_items + b_idx);
+    d_step_ = (int*)(ctrl_ + b_slots + b_items + b_idx + b_states);
     if (hipHostMalloc((void**)&h_slots_, (size_t)n_ * sizeof(Slot), hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_items_, (size_t)max_items_ * sizeof(Item) + 256,
                       hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_idx_, (size_t)n_ * sizeof(int) + 256, hipHostMallocDefault) ||
-        hipHostMalloc((void**)&h_states_, (size_t)n_ * sizeof(State), hipHostMallocDefault))
+        hipHostMalloc((void**)&h_states_, (size_t)n_ * sizeof(State), hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_step_, kStepRing * sizeof(int), hipHostMallocDefault))
       return CG_E_DEVICE;
     memset(h_slots_, 0, (size_t)n_ * sizeof(Slot));
     slot_job_.assign(n_, nullptr);
@@ -155,7 +159,8 @@ class Engine {
     return CG_OK;
   }
 
-  // Launches `steps` steps of every resident solve.
+  // Launches `steps` steps of every resident solve: a replay of the captured
+  // chunk when `steps` is the chunk length, plain launches otherwise.
   int run(int steps) {
     if (!active_) return CG_OK;
     if (dirty_ && upload_items()) return CG_E_DEVICE;
@@ -165,9 +170,36 @@ class Engine {
       e1 = c_.event();
       hipEventRecord(e0, c_.st);
     }
-    for (int k = 0; k < steps; ++k)
-      if (launch_step(d_slots_, d_items_, d_nitems_, step_ + k, grid_, c_.st) != hipSuccess)
+    // the chunk's base step, read by every launch of the chunk on the device
+    int* hs = h_step_ + (ring_++ % kStepRing);
+    *hs = step_;
+    if (hipMemcpyAsync(d_step_, hs, sizeof(int), hipMemcpyHostToDevice, c_.st)) return CG_E_DEVICE;
+    const bool use_graph = c_.graph_chunk > 0 && steps == c_.step_chunk_for(this_is_serving_);
+    if (use_graph && (!graph_ || graph_steps_ != steps)) {
+      if (graph_) hipGraphExecDestroy(graph_);
+      graph_ = nullptr;
+      hipGraph_t g;
+      if (hipStreamBeginCapture(c_.st, hipStreamCaptureModeThreadLocal)) return CG_E_DEVICE;
+      hipError_t e = hipSuccess;
+      for (int k = 0; k < steps && e == hipSuccess; ++k)
+        e = launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st);
+      hipError_t e2 = hipStreamEndCapture(c_.st, &g);
+      if (e || e2) return CG_E_DEVICE;
+      e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e) {
+        graph_ = nullptr;
         return CG_E_DEVICE;
+      }
+      graph_steps_ = steps;
+    }
+    if (use_graph) {
+      if (hipGraphLaunch(graph_, c_.st)) return CG_E_DEVICE;
+    } else {
+      for (int k = 0; k < steps; ++k)
+        if (launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st) != hipSuccess)
+          return CG_E_DEVICE;
+    }
     if (c_.prof) {
       hipEventRecord(e1, c_.st);
       c_.pending.push_back({e0, e1, "batch_steps", 0.0});
@@ -257,9 +289,20 @@ class Engine {
     return CG_OK;
   }
 
+  static constexpr int kStepRing = 64;
   Ctx& c_;
   int n_;
   int max_items_ = 0;
+  int* d_step_ = nullptr;
+  int* h_step_ = nullptr;
+  unsigned ring_ = 0;
+  hipGraphExec_t graph_ = nullptr;
+  int graph_steps_ = 0;
+
+ public:
+  bool this_is_serving_ = false;
+
+ private:
   char* ctrl_ = nullptr;
   Slot* d_slots_ = nullptr;
   Item* d_items_ = nullptr;
@@ -408,6 +451,7 @@ class Server {
         int rc = CG_OK;
         if (!eng) {
           eng.reset(new Engine(c_, c_.max_slots));
+          eng->this_is_serving_ = true;
           rc = eng->init();
         }
         // admission: FIFO while a slot is free and the footprint fits
