@@ -35,7 +35,8 @@
  *                    order centre, west, east, south, north so that the plain
  *                    CSR loop evaluates (((4uC - uW) - uE) - uS) - uN;
  *                    dots follow the tile / lane / butterfly order described
- *                    at dot_canonical() below.
+ *                    at dot_canonical() below, or, for the column-segment
+ *                    layout of the small-grid solver, dot_segments().
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +55,8 @@ typedef struct {
   int32_t waves;         /* wavefronts stacked vertically in one tile        */
   int32_t rows;          /* rows per wavefront strip                         */
   int32_t threads2;      /* threads of the cross-tile sum (multiple of lanes) */
+  int32_t layout;        /* 0: tiles (dot_canonical); 1: column segments
+                            (dot_segments: rows, lanes, waves are used)       */
 } oracle_order;
 
 typedef struct {
@@ -261,10 +264,46 @@ static double dot_canonical(int32_t nx, int32_t ny, const double* a, const doubl
   return total;
 }
 
+/* Canonical order of the column-segment layout, used by a solver that keeps
+ * one small grid in a single work-group of waves*lanes threads, each thread
+ * owning a short piece of one grid column:
+ *   E = rows;  segments per column S = ceil(ny / E);
+ *   thread t = w*lanes + l (wavefront w, lane l) owns column c = t mod nx and
+ *   rows s*E .. s*E + E - 1 (those < ny) of segment s = t div nx; threads with
+ *   s >= S own nothing (their lane value is +0).
+ *   Lane: one accumulator from +0, acc = fma(a, b, acc) over its rows in
+ *     ascending order.
+ *   Wavefront: xor butterfly (see butterfly()).
+ *   Total: ((wave_0 + wave_1) + wave_2) + ...
+ * The layout must cover the grid: waves*lanes >= nx*S (else NaN). */
+static double dot_segments(int32_t nx, int32_t ny, const double* a, const double* b,
+                           const oracle_order* o) {
+  const int32_t E = o->rows, L = o->lanes, W = o->waves;
+  const int64_t S = (ny + E - 1) / E;
+  if ((int64_t)W * L < (int64_t)nx * S) return NAN;
+  double lane[256];
+  double total = 0.0;
+  for (int32_t w = 0; w < W; ++w) {
+    for (int32_t l = 0; l < L; ++l) {
+      const int64_t t = (int64_t)w * L + l;
+      const int64_t c = t % nx, s = t / nx;
+      double acc = 0.0;
+      if (s < S)
+        for (int64_t j = s * E; j < s * E + E && j < ny; ++j)
+          acc = fma(a[j * nx + c], b[j * nx + c], acc);
+      lane[l] = acc;
+    }
+    const double wv = butterfly(lane, L);
+    total = (w == 0) ? wv : total + wv;
+  }
+  return total;
+}
+
 /* Exported dot for the tests. */
 double oracle_dot(int32_t nx, int32_t ny, int32_t mode, const oracle_order* o,
                   const double* a, const double* b) {
-  if (mode == MODE_CANONICAL) return dot_canonical(nx, ny, a, b, o);
+  if (mode == MODE_CANONICAL)
+    return o->layout == 1 ? dot_segments(nx, ny, a, b, o) : dot_canonical(nx, ny, a, b, o);
   return dot_sequential((int64_t)nx * ny, a, b);
 }
 
@@ -465,6 +504,16 @@ done:
   return st;
 }
 
+static int order_valid(const oracle_order* o, int32_t nx, int32_t ny) {
+  if (!o || o->lanes < 1 || o->lanes > 256 || (o->lanes & (o->lanes - 1)) || o->waves < 1 ||
+      o->rows < 1)
+    return 0;
+  if (o->layout == 1)
+    return (int64_t)o->waves * o->lanes >= (int64_t)nx * ((ny + o->rows - 1) / o->rows);
+  return o->layout == 0 && o->cols_per_lane >= 1 && o->cols_per_lane <= 16 &&
+         o->threads2 >= o->lanes && o->threads2 % o->lanes == 0;
+}
+
 /* Solve A x = b.  variant: 0 classic, 1 pipelined.  mode: 0 sequential,
  * 1 canonical (then ord must describe the order).  x0 may be NULL.
  * Returns the status (also in res). */
@@ -473,11 +522,7 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
               int32_t maxit, oracle_result* res, oracle_history* hist) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0)
     return OR_E_INVALID;
-  if (mode == MODE_CANONICAL &&
-      (!ord || ord->cols_per_lane < 1 || ord->cols_per_lane > 16 || ord->lanes < 1 ||
-       ord->lanes > 256 || (ord->lanes & (ord->lanes - 1)) || ord->waves < 1 ||
-       ord->rows < 1 || ord->threads2 < ord->lanes || ord->threads2 % ord->lanes))
-    return OR_E_INVALID;
+  if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
   if (hist) hist->count = 0;
   csr_t A;
   int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);

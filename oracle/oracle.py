@@ -16,9 +16,15 @@ OR_OK, OR_NOT_CONVERGED, OR_BREAKDOWN, OR_E_INVALID, OR_E_NOMEM = 0, 2, 3, -1, -
 
 
 class Order(C.Structure):
-    """Reduction order of the canonical mode (see dot_canonical in the C file)."""
+    """Reduction order of the canonical mode: layout 0 = tiles (dot_canonical in
+    the C file), layout 1 = column segments (dot_segments)."""
     _fields_ = [("cols_per_lane", C.c_int32), ("lanes", C.c_int32), ("waves", C.c_int32),
-                ("rows", C.c_int32), ("threads2", C.c_int32)]
+                ("rows", C.c_int32), ("threads2", C.c_int32), ("layout", C.c_int32)]
+
+    @classmethod
+    def segments(cls, rows, lanes, waves):
+        """Column-segment order: waves*lanes threads, `rows` rows per thread."""
+        return cls(1, lanes, waves, rows, 0, 1)
 
 
 class _Result(C.Structure):

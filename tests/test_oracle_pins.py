@@ -127,6 +127,56 @@ def test_canonical_dot_exact_on_integers(nx, ny, order):
     assert oracle.dot(w, one, nx, ny, MODE_CANONICAL, order) == (nx * ny) * (nx * ny + 1) / 2
 
 
+def seg_order(nx, ny, rows, lanes, spare_waves=1):
+    """Column-segment order covering the grid, with idle threads in spare waves."""
+    need = nx * -(-ny // rows)
+    return oracle.Order.segments(rows, lanes, -(-need // lanes) + spare_waves)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 37), (37, 1), (100, 100), (129, 65), (1000, 3)])
+@pytest.mark.parametrize("rows,lanes", [(10, 64), (1, 64), (3, 4), (7, 16)])
+def test_segment_dot_exact_on_integers(nx, ny, rows, lanes):
+    """The column-segment order counts every term exactly once: exact on
+    integer data, and the position-weighted sum identifies every term."""
+    order = seg_order(nx, ny, rows, lanes)
+    rng = np.random.default_rng(nx * 7 + ny)
+    a = rng.integers(-8, 9, size=(ny, nx)).astype(float)
+    b = rng.integers(-8, 9, size=(ny, nx)).astype(float)
+    exact = float(np.sum(a.astype(np.int64) * b.astype(np.int64)))
+    assert oracle.dot(a, b, nx, ny, MODE_CANONICAL, order) == exact
+    w = np.arange(1, nx * ny + 1, dtype=float).reshape(ny, nx)
+    assert oracle.dot(w, np.ones((ny, nx)), nx, ny, MODE_CANONICAL, order) == \
+        (nx * ny) * (nx * ny + 1) / 2
+    # squares of the position weights: a term counted twice or dropped changes it
+    assert oracle.dot(w, w, nx, ny, MODE_CANONICAL, order) == \
+        sum(k * k for k in range(1, nx * ny + 1))
+
+
+def test_segment_order_must_cover_the_grid():
+    short = oracle.Order.segments(10, 64, 15)  # 960 threads < 100 * 10 segments
+    assert math.isnan(oracle.dot(np.ones((100, 100)), np.ones((100, 100)), 100, 100,
+                                 MODE_CANONICAL, short))
+    with pytest.raises(ValueError):
+        oracle.cg(np.ones((100, 100)), 100, 100, mode=MODE_CANONICAL, order=short)
+    ok = oracle.Order.segments(10, 64, 16)
+    assert oracle.dot(np.ones((100, 100)), np.ones((100, 100)), 100, 100, MODE_CANONICAL,
+                      ok) == 1e4
+
+
+def test_segment_dot_error_bound():
+    nx, ny, rows = 100, 100, 10
+    o = seg_order(nx, ny, rows, 64)
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((ny, nx))
+    b = rng.standard_normal((ny, nx))
+    exact = math.fsum((a * b).ravel())
+    mag = float(np.sum(np.abs(a * b)))
+    u = 2.0 ** -53
+    depth = rows + 6 + o.waves + 2
+    got = oracle.dot(a, b, nx, ny, MODE_CANONICAL, o)
+    assert abs(got - exact) <= 2 * depth * u * mag + 1e-300
+
+
 @pytest.mark.parametrize("nx,ny", [(300, 77), (513, 129)])
 def test_canonical_dot_error_bound(nx, ny):
     rng = np.random.default_rng(7)
@@ -153,14 +203,17 @@ def kappa(nx, ny):
 
 @pytest.mark.parametrize("nx,ny", [(6, 5), (16, 16), (11, 3)])
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("mode_", [MODE_SEQUENTIAL, MODE_CANONICAL])
+@pytest.mark.parametrize("mode_", [MODE_SEQUENTIAL, MODE_CANONICAL, "segments"])
 def test_solve_vs_dense_cholesky(nx, ny, variant, mode_):
     b = np.random.default_rng(nx + 31 * ny).uniform(-1, 1, (ny, nx))
     c = sla.cho_factor(dense_A(nx, ny))
     xc = sla.cho_solve(c, b.ravel())
     tol = 1e-12
+    order = GPU_LIKE
+    if mode_ == "segments":
+        mode_, order = MODE_CANONICAL, seg_order(nx, ny, 3, 4)
     x, r = oracle.cg(b, nx, ny, variant=variant, tol=tol, maxit=1000, mode=mode_,
-                     order=GPU_LIKE)
+                     order=order)
     assert r.status == oracle.OR_OK
     assert r.rel_res_recursive <= tol
     err = np.linalg.norm(x.ravel() - xc) / np.linalg.norm(xc)
