@@ -91,16 +91,24 @@ typedef struct {
   double latency_seconds;   /* serving: submit -> completion; else = device_seconds  */
 } cg_result;
 
-/* Work layout a problem will use; its reduction order is the documented
- * arithmetic contract (tile = 64 lanes x cols_per_lane columns by waves x rows
- * rows; lanes accumulate with fma in row order; xor butterfly; waves in order;
- * tiles in index order through threads2 strided threads). */
+/* Work layout a problem will use.  Its reduction order is the documented
+ * arithmetic contract.  Tile order (paths 0 and 1; cg_dot; an FP64 problem of
+ * path 0 or 1 in a batch): tile = 64 lanes x cols_per_lane columns by waves x
+ * rows rows; lanes accumulate with fma in row order; xor butterfly; waves in
+ * order; tiles in index order through threads2 strided threads.  Column-
+ * segment order (path 2, alone and in a batch): thread t of seg_waves*64
+ * owns column t mod nx and seg_rows rows of segment t div nx; fma in row
+ * order; xor butterfly; waves in order.  The tile fields always describe the
+ * tile geometry of the shape (cg_dot and cg_apply use it on every path). */
 typedef struct {
-  int32_t path;             /* 0 = multi-work-group passes, 1 = single work-group    */
+  int32_t path;             /* 0 = multi-work-group passes, 1 = single work-group,
+                               2 = single work-group with the vectors on chip       */
   int32_t cols_per_lane, lanes, waves, rows, threads2;
   int32_t tiles;            /* tiles per pass                                        */
   int32_t grid;             /* work-groups per pass launch                           */
   int32_t pitch;            /* padded row length in elements                         */
+  int32_t seg_rows;         /* path 2: rows per thread; else 0                       */
+  int32_t seg_waves;        /* path 2: wavefronts of the work-group; else 0          */
   int32_t pad_;
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
@@ -122,14 +130,20 @@ int cg_destroy(cg_ctx* ctx);
 /* One blocking solve of A x = b (Algorithm 1 or 2; Section II problem). */
 int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
 
-/* n independent solves in one persistent launch over a tile work queue.
- * Returns the worst per-solve status; results[i] holds each outcome.  A
- * breakdown of one solve does not disturb the others. */
+/* n independent solves on the device at once.  Every resident solve advances
+ * by one CG pass per launch of a multi-solve step kernel (chunks of launches
+ * replayed from a HIP graph); problems small enough for the on-chip solver
+ * (cg_plan_info.path 2) run whole, one work-group each, beside the steps.
+ * Solves are admitted in order while their footprint fits the arena and a
+ * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
+ * worst per-solve status; results[i] holds each outcome.  A breakdown of one
+ * solve does not disturb the others. */
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
 
-/* Serving: queue one request (non-blocking).  The request is admitted when
- * its device footprint fits the free arena and a slot is free, joins the
- * device-resident active set at the next epoch, and is retired when final.
+/* Serving: queue one request (non-blocking).  A scheduler thread admits
+ * queued requests in order when the device footprint fits the free arena and
+ * a slot is free; admitted requests join the resident set at the next chunk
+ * of steps (or run whole on the on-chip solver) and are retired when final.
  * CG_E_NOMEM if its footprint exceeds arena_bytes. */
 int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket);
 /* CG_PENDING, or the final status (then *res is filled and the ticket is

@@ -117,7 +117,9 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   cgr::Plan pl = c->plan(prob);
   memset(info, 0, sizeof(*info));
-  info->path = pl.wg ? 1 : 0;
+  info->path = pl.rr ? 2 : pl.wg ? 1 : 0;
+  info->seg_rows = pl.rr ? cgk::kRrRows : 0;
+  info->seg_waves = pl.rr ? pl.rr_threads / cgk::kWave : 0;
   info->cols_per_lane = pl.fp32g ? 4 : 2;
   info->lanes = cgk::kWave;
   info->waves = cgk::kWavesPerTile;

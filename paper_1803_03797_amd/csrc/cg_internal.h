@@ -21,6 +21,8 @@ constexpr int kWave = 64;
 constexpr int kGroup = 256;       // threads that process one tile (4 wavefronts)
 constexpr int kWavesPerTile = 4;
 constexpr int kWgGroups = 2;     // tile groups of the single-work-group solver
+constexpr int kRrRows = 20;       // rows per thread of the register-resident solver
+constexpr int kRrThreads = 512;   // its largest work-group
 
 // Device-side solve status (host maps it to the ABI codes).
 enum : int32_t {
@@ -154,6 +156,12 @@ hipError_t launch_pass(int kind, int fp32_geometry, const PassArgs& a, int grid,
 hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slot 0
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
+// Whole solve in one work-group of `threads` threads with the vectors on chip;
+// needs nx * ceil(ny / kRrRows) <= threads <= kRrThreads.
+hipError_t launch_solve_rr(int variant, const PassArgs& a, int threads, hipStream_t s);
+// One register-resident solve per listed slot (slots[idx[i]], i < n), each
+// fitting the solver; final states land in both state buffers, kind K_DONE.
+hipError_t launch_solve_rr_many(const Slot* slots, const int* idx, int n, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the

@@ -150,6 +150,19 @@ __device__ __forceinline__ State load_state_uniform(const State* p) {
   return s;
 }
 
+// The same for a State held in registers whose fields are uniform (all
+// threads computed them from the same sums).
+__device__ __forceinline__ State uniform_state(const State& in) {
+  constexpr int N = sizeof(State) / 4;
+  uint32_t u[N];
+  __builtin_memcpy(u, &in, sizeof(State));
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] = __builtin_amdgcn_readfirstlane(u[i]);
+  State s;
+  __builtin_memcpy(&s, u, sizeof(State));
+  return s;
+}
+
 __device__ __forceinline__ double uniform(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
@@ -159,6 +172,27 @@ __device__ __forceinline__ double uniform(double v) {
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// The same butterfly (stage order 32, 16, ..., 1; every lane adds its xor
+// partner) with the stages inside 32-lane halves done by ds_swizzle, whose
+// lane pattern is an immediate: no per-lane address registers are needed.
+template <int M>
+__device__ __forceinline__ double swz_xor(double v) {
+  constexpr int pat = 0x1f | (M << 10);  // bitmask mode: lane ^ M within 32 lanes
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_swz(double v) {
+  v = v + __shfl_xor(v, 32, kWave);
+  v = v + swz_xor<16>(v);
+  v = v + swz_xor<8>(v);
+  v = v + swz_xor<4>(v);
+  v = v + swz_xor<2>(v);
+  v = v + swz_xor<1>(v);
   return v;
 }
 
@@ -1101,6 +1135,428 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
   if (threadIdx.x == 0) *a0.st_out = s;
 }
 
+// ------------------------------------------ register-resident small solve --
+//
+// For a grid with nx * ceil(ny / kRrRows) <= kRrThreads the whole solve runs
+// in one work-group with every vector on chip.  Thread t owns column
+// c = t mod nx and the kRrRows rows of segment t div nx (rows past ny are held
+// as zero); threads past the last segment own nothing.  Along a column the
+// stencil's south/north neighbours are the thread's own registers; west/east
+// neighbours come from the adjacent lanes by DPP.  What crosses a thread's
+// boundary (the first and last element of every segment, the whole segment of
+// lanes 0 and 63 of each wavefront) goes through LDS, together with the
+// wavefront sums of the dot products, with one barrier per exchange and the
+// LDS buffers double-buffered by phase parity.  Pipelined CG keeps x in LDS
+// (six vectors do not fit the register file), classic CG keeps all four of
+// its vectors (x, r, p, A p) in registers.
+//
+// Dot products follow the column-segment order: fma per thread over its rows
+// in ascending order, xor butterfly, wavefronts in order.  The scalar
+// recurrences are the transitions of the pass kernels, and every vector
+// update is the same expression as in the pass bodies.
+
+constexpr int kRrWaves = kRrThreads / kWave;
+
+struct RrXchg {  // one exchanged vector
+  double first[kRrThreads];           // element 0 of each thread's segment
+  double last[kRrThreads];            // element kRrRows-1
+  double edge[kRrWaves][2][kRrRows];  // segments of lanes 0 and 63 of each wavefront
+};
+
+struct RrLdsPcg {
+  RrXchg x[2];                   // by phase parity
+  double tot[2][kRrWaves][2];    // wavefront sums, by phase parity
+  double xs[kRrRows][kRrThreads];  // the iterate x
+};
+
+struct RrLdsCg {
+  RrXchg x[2][2];                // [parity][r, p]
+  double tot[2][kRrWaves][2];
+};
+
+constexpr size_t kRrLdsBytes =
+    sizeof(RrLdsPcg) > sizeof(RrLdsCg) ? sizeof(RrLdsPcg) : sizeof(RrLdsCg);
+
+struct RrSeg {
+  int t, lane, wave, nw, nx;
+  int nv;             // rows of the segment inside the grid (0: idle thread)
+  bool west, east;    // a west / east neighbour column exists
+  bool south, north;  // the segment below / above exists
+  size_t off;         // element offset of the segment's first row (padded pitch)
+  int pitch;
+};
+
+__device__ __forceinline__ RrSeg rr_seg(const Geo& g) {
+  RrSeg s;
+  s.t = threadIdx.x;
+  s.lane = s.t & (kWave - 1);
+  s.wave = s.t >> 6;
+  s.nw = blockDim.x >> 6;
+  s.nx = g.nx;
+  const int nseg = (g.ny + kRrRows - 1) / kRrRows;
+  const int c = s.t % g.nx, sg = s.t / g.nx;
+  const bool act = sg < nseg;
+  s.nv = act ? min(kRrRows, g.ny - sg * kRrRows) : 0;
+  s.west = act && c > 0;
+  s.east = act && c + 1 < g.nx;
+  s.south = act && sg > 0;
+  s.north = act && sg + 1 < nseg;
+  s.pitch = g.pitch;
+  s.off = act ? (size_t)sg * kRrRows * g.pitch + c : 0;
+  return s;
+}
+
+using RrVec = double[kRrRows];
+
+// The segment's addresses are recomputed at every use (the empty asm hides
+// the offset from common-subexpression elimination), so the addresses of the
+// first load are not kept in registers across the whole solve.
+__device__ __forceinline__ void rr_load(const double* G, const RrSeg& s, RrVec& v) {
+  size_t off = s.off;
+  asm volatile("" : "+v"(off));
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) v[e] = e < s.nv ? G[off + (size_t)e * s.pitch] : 0.0;
+}
+
+__device__ __forceinline__ void rr_store(double* G, const RrSeg& s, const RrVec& v) {
+  size_t off = s.off;
+  asm volatile("" : "+v"(off));
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e)
+    if (e < s.nv) G[off + (size_t)e * s.pitch] = v[e];
+}
+
+// After a transition: the state and the pass scalars back in scalar registers.
+__device__ __forceinline__ void rr_uniform(State& st, Sc& sc) {
+  st = uniform_state(st);
+  sc.al = uniform(sc.al);
+  sc.be = uniform(sc.be);
+}
+
+__device__ __forceinline__ void rr_publish(const RrVec& v, const RrSeg& s, RrXchg& X) {
+  X.first[s.t] = v[0];
+  X.last[s.t] = v[kRrRows - 1];
+  if (s.lane == 0 || s.lane == kWave - 1) {
+    double* d = X.edge[s.wave][s.lane == 0 ? 0 : 1];
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) d[e] = v[e];
+  }
+}
+
+// Neighbour values of a published vector just outside this thread's segment:
+// south of element 0 and north of element kRrRows-1 (from the segments below
+// and above), and for lanes 0 / 63 the west / east neighbours from the
+// adjacent wavefront.  `f` maps the published values to the vector the
+// stencil is applied to (identity, or the classic direction update); X2 is a
+// second published vector that f combines with the first.
+template <class F>
+struct RrHalo {
+  double S, N;
+  const double* e1;  // this lane's edge segment (used by lanes 0 and 63 only)
+  const double* e2;
+  F f;
+};
+
+template <class F>
+__device__ __forceinline__ RrHalo<F> rr_halo(const RrSeg& s, const RrXchg& X, const RrXchg* X2,
+                                             F f) {
+  const int ts = s.south ? s.t - s.nx : s.t, tn = s.north ? s.t + s.nx : s.t;
+  const double S = f(X.last[ts], X2 ? X2->last[ts] : 0.0);
+  const double N = f(X.first[tn], X2 ? X2->first[tn] : 0.0);
+  // lane 0 takes lane 63 of the previous wavefront, lane 63 lane 0 of the next
+  const int ww = s.wave > 0 ? s.wave - 1 : 0, we = s.wave + 1 < s.nw ? s.wave + 1 : s.wave;
+  const int wsel = s.lane == 0 ? ww : we, side = s.lane == 0 ? 1 : 0;
+  return RrHalo<F>{s.south ? S : 0.0, s.north ? N : 0.0, X.edge[wsel][side],
+                   X2 ? X2->edge[wsel][side] : nullptr, f};
+}
+
+// (A v) at element e of the segment; zero for rows outside the grid.  vs is
+// v[e-1] as it was before any update of this pass (the caller may have
+// overwritten v[e-1] already); unused for e == 0.
+template <class F>
+__device__ __forceinline__ double rr_st5(const RrVec& v, double vs, const RrSeg& s,
+                                         const RrHalo<F>& h, int e) {
+  const double ev = h.f(h.e1[e], h.e2 ? h.e2[e] : 0.0);
+  double w = dpp<kDppWaveShr1>(v[e], ev);   // lane 0 keeps ev: its west edge
+  double ea = dpp<kDppWaveShl1>(v[e], ev);  // lane 63 keeps ev: its east edge
+  w = s.west ? w : 0.0;
+  ea = s.east ? ea : 0.0;
+  const double so = e > 0 ? vs : h.S;
+  const double no = e + 1 < kRrRows ? v[e + 1] : h.N;
+  return e < s.nv ? st5(v[e], w, ea, so, no) : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void rr_publish_sums(const double* acc, const RrSeg& s,
+                                                double (*tot)[2]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double v = wave_sum_swz(acc[d]);
+    if (s.lane == 0) tot[s.wave][d] = v;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void rr_read_sums(const RrSeg& s, const double (*tot)[2],
+                                             double* sum) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double v = tot[0][d];
+    for (int w = 1; w < s.nw; ++w) v = v + tot[w][d];
+    sum[d] = uniform(v);
+  }
+}
+
+struct RrId {
+  __device__ double operator()(double a, double) const { return a; }
+};
+
+// Classic direction update p = r + beta p_old (p = r on the first iteration).
+struct RrDir {
+  double be;
+  bool first;
+  __device__ double operator()(double rv, double pv) const {
+    return first ? rv : fma(be, pv, rv);
+  }
+};
+
+// Pipelined CG (Algorithm 2) on one grid, x in LDS.
+__device__ __forceinline__ void rr_solve_pcg(const PassArgs& a, State& st, char* raw) {
+  RrLdsPcg& L = *reinterpret_cast<RrLdsPcg*>(raw);
+  const RrSeg s = rr_seg(a.g);
+  RrVec r, w, p, q, z;
+  Sc sc;
+  int par = 0;
+  double sum[2] = {0.0, 0.0};
+  {
+    RrVec x;
+    rr_load(a.x, s, x);
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) L.xs[e][s.t] = x[e];
+    rr_publish(x, s, L.x[par]);
+    __syncthreads();
+    // r = b - A x; slots (r,r), (b,b)
+    transition<K_INIT_R>(st, sum, sc);
+    RrVec b;
+    rr_load(a.b, s, b);
+    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      r[e] = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
+      if (e < s.nv) {
+        acc[0] = fma(r[e], r[e], acc[0]);
+        acc[1] = fma(b[e], b[e], acc[1]);
+      }
+    }
+    par ^= 1;
+    rr_publish(r, s, L.x[par]);
+    rr_publish_sums<2>(acc, s, L.tot[par]);
+    __syncthreads();
+  }
+  rr_read_sums<2>(s, L.tot[par], sum);
+  if (transition<K_INIT_W>(st, sum, sc)) {
+    // w = A r; slots (r,r), (w,r)
+    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      w[e] = rr_st5(r, e > 0 ? r[e - 1] : 0.0, s, h, e);
+      if (e < s.nv) {
+        acc[0] = fma(r[e], r[e], acc[0]);
+        acc[1] = fma(w[e], r[e], acc[1]);
+      }
+      p[e] = q[e] = z[e] = 0.0;
+    }
+    par ^= 1;
+    rr_publish(w, s, L.x[par]);
+    rr_publish_sums<2>(acc, s, L.tot[par]);
+    __syncthreads();
+    for (;;) {
+      rr_read_sums<2>(s, L.tot[par], sum);
+      if (!transition<K_PCG>(st, sum, sc)) break;
+      rr_uniform(st, sc);
+      const double al = sc.al, be = sc.be, nal = -sc.al;
+      const bool first = sc.first;
+      const RrHalo h2 = rr_halo(s, L.x[par], nullptr, RrId());
+      double ac[2] = {0.0, 0.0};
+      double wprev = 0.0;  // w[e-1] of this iteration (w is updated in place)
+#pragma unroll
+      for (int e = 0; e < kRrRows; ++e) {
+        const double nv = rr_st5(w, wprev, s, h2, e);
+        wprev = w[e];
+        // selects rather than branches: both forms are computed
+        const double zf = fma(be, z[e], nv), qf = fma(be, q[e], w[e]), pf = fma(be, p[e], r[e]);
+        z[e] = first ? nv : zf;
+        q[e] = first ? w[e] : qf;
+        p[e] = first ? r[e] : pf;
+        L.xs[e][s.t] = fma(al, p[e], L.xs[e][s.t]);
+        r[e] = fma(nal, q[e], r[e]);
+        const bool in = e < s.nv;
+        w[e] = in ? fma(nal, z[e], w[e]) : 0.0;
+        const double a0 = fma(r[e], r[e], ac[0]), a1 = fma(w[e], r[e], ac[1]);
+        ac[0] = in ? a0 : ac[0];
+        ac[1] = in ? a1 : ac[1];
+      }
+      par ^= 1;
+      rr_publish(w, s, L.x[par]);
+      rr_publish_sums<2>(ac, s, L.tot[par]);
+      __syncthreads();
+    }
+  }
+  RrVec x;
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) x[e] = e < s.nv ? L.xs[e][s.t] : 0.0;
+  if (st.status != ST_ZERO_RHS) {
+    // true residual of the final iterate: slots (t,t), (b,b)
+    par ^= 1;
+    rr_publish(x, s, L.x[par]);
+    __syncthreads();
+    RrVec b;
+    rr_load(a.b, s, b);
+    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      const double t = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
+      if (e < s.nv) acc[0] = fma(t, t, acc[0]);
+    }
+    par ^= 1;
+    rr_publish_sums<1>(acc, s, L.tot[par]);
+    __syncthreads();
+    rr_read_sums<1>(s, L.tot[par], sum);
+    st.res2 = sum[0];
+  }
+  rr_store(a.x, s, x);
+}
+
+// Classic CG (Algorithm 1) on one grid, every vector in registers.
+__device__ __forceinline__ void rr_solve_cg(const PassArgs& a, State& st, char* raw) {
+  RrLdsCg& L = *reinterpret_cast<RrLdsCg*>(raw);
+  const RrSeg s = rr_seg(a.g);
+  RrVec x, r, p, sv;
+  Sc sc;
+  int par = 0;
+  double sum[2] = {0.0, 0.0};
+  rr_load(a.x, s, x);
+  rr_publish(x, s, L.x[par][0]);
+  __syncthreads();
+  {
+    // r = b - A x; slots (r,r), (b,b)
+    transition<K_INIT_R>(st, sum, sc);
+    RrVec b;
+    rr_load(a.b, s, b);
+    const RrHalo h = rr_halo(s, L.x[par][0], nullptr, RrId());
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      r[e] = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
+      if (e < s.nv) {
+        acc[0] = fma(r[e], r[e], acc[0]);
+        acc[1] = fma(b[e], b[e], acc[1]);
+      }
+      p[e] = 0.0;
+    }
+    par ^= 1;
+    rr_publish(r, s, L.x[par][0]);
+    rr_publish(p, s, L.x[par][1]);
+    rr_publish_sums<2>(acc, s, L.tot[par]);
+    __syncthreads();
+  }
+  for (;;) {
+    // pass 1: beta; p = r + beta p (also on the halo); s = A p; slot (p, s)
+    if (st.flags & F_BB_PENDING) rr_read_sums<2>(s, L.tot[par], sum);
+    else rr_read_sums<1>(s, L.tot[par], sum);
+    if (!transition<K_CG1>(st, sum, sc)) break;
+    rr_uniform(st, sc);
+    const double be = sc.be;
+    const bool first = sc.first;
+    const RrDir dir{be, first};
+    const RrHalo h = rr_halo(s, L.x[par][0], &L.x[par][1], dir);
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) p[e] = e < s.nv ? dir(r[e], p[e]) : 0.0;
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      sv[e] = rr_st5(p, e > 0 ? p[e - 1] : 0.0, s, h, e);
+      const double a0 = fma(p[e], sv[e], acc[0]);
+      acc[0] = e < s.nv ? a0 : acc[0];
+    }
+    par ^= 1;
+    rr_publish_sums<1>(acc, s, L.tot[par]);
+    __syncthreads();
+    // pass 2: alpha; x += alpha p; r -= alpha s; slot (r, r)
+    rr_read_sums<1>(s, L.tot[par], sum);
+    if (!transition<K_CG2>(st, sum, sc)) break;
+    rr_uniform(st, sc);
+    const double al = sc.al, nal = -sc.al;
+    double ac2[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      x[e] = fma(al, p[e], x[e]);
+      r[e] = fma(nal, sv[e], r[e]);
+      if (e < s.nv) ac2[0] = fma(r[e], r[e], ac2[0]);
+    }
+    par ^= 1;
+    rr_publish(r, s, L.x[par][0]);
+    rr_publish(p, s, L.x[par][1]);
+    rr_publish_sums<1>(ac2, s, L.tot[par]);
+    __syncthreads();
+  }
+  if (st.status != ST_ZERO_RHS) {
+    par ^= 1;
+    rr_publish(x, s, L.x[par][0]);
+    __syncthreads();
+    RrVec b;
+    rr_load(a.b, s, b);
+    const RrHalo h = rr_halo(s, L.x[par][0], nullptr, RrId());
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < kRrRows; ++e) {
+      const double t = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
+      if (e < s.nv) acc[0] = fma(t, t, acc[0]);
+    }
+    par ^= 1;
+    rr_publish_sums<1>(acc, s, L.tot[par]);
+    __syncthreads();
+    rr_read_sums<1>(s, L.tot[par], sum);
+    st.res2 = sum[0];
+  }
+  rr_store(a.x, s, x);
+}
+
+template <int VARIANT>
+__global__ __launch_bounds__(kRrThreads) void k_solve_rr(PassArgs a) {
+  __shared__ __attribute__((aligned(16))) char raw[kRrLdsBytes];
+  State st = load_state_uniform(a.st_in);
+  if constexpr (VARIANT == 1) rr_solve_pcg(a, st, raw);
+  else rr_solve_cg(a, st, raw);
+  if (threadIdx.x == 0) *a.st_out = st;
+}
+
+// Many register-resident solves, one per work-group: work-group i solves the
+// resident solve in slot idx[i] (initial state in S[0]) and leaves its final
+// state, marked done for the step engine, in both S[0] and S[1].  A wider
+// work-group than the solve needs only adds idle wavefronts, whose zero sums
+// leave every dot product unchanged.
+__global__ __launch_bounds__(kRrThreads) void k_solve_rr_many(const Slot* slots,
+                                                              const int* idx) {
+  __shared__ __attribute__((aligned(16))) char raw[kRrLdsBytes];
+  const Slot& S = slots[__builtin_amdgcn_readfirstlane(idx[blockIdx.x])];
+  PassArgs a = {};
+  a.g = S.g;
+  a.b = S.b;
+  a.x = S.x;
+  State st = load_state_uniform(S.S[0]);
+  if (S.variant == 1) rr_solve_pcg(a, st, raw);
+  else rr_solve_cg(a, st, raw);
+  st.kind = K_DONE;
+  if (threadIdx.x == 0) {
+    *S.S[0] = st;
+    *S.S[1] = st;
+  }
+}
+
 // ---------------------------------------------------- multi-solve step --
 //
 // One launch advances every resident solve by one pass.  The work is a table
@@ -1364,6 +1820,21 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_rr_many(const Slot* slots, const int* idx, int n, hipStream_t st) {
+  if (n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_solve_rr_many, dim3(n), dim3(kRrThreads), 0, st, slots, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_rr(int variant, const PassArgs& a, int threads, hipStream_t st) {
+  const int64_t need = (int64_t)a.g.nx * ((a.g.ny + kRrRows - 1) / kRrRows);
+  if (threads < kWave || threads > kRrThreads || threads % kWave || need > threads)
+    return hipErrorInvalidValue;
+  if (variant == 1) hipLaunchKernelGGL((k_solve_rr<1>), dim3(1), dim3(threads), 0, st, a);
+  else hipLaunchKernelGGL((k_solve_rr<0>), dim3(1), dim3(threads), 0, st, a);
   return hipGetLastError();
 }
 

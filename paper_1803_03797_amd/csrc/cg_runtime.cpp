@@ -142,12 +142,26 @@ bool Ctx::use_wg(const cg_problem* p) const {
   return p->precision == CG_PREC_FP64 && (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
-Plan Ctx::plan(const cg_problem* p) {
+static int64_t rr_threads_needed(int nx, int ny) {
+  return (int64_t)nx * ((ny + kRrRows - 1) / kRrRows);
+}
+
+bool Ctx::use_rr(const cg_problem* p) const {
+  return rr_enabled && p->precision == CG_PREC_FP64 &&
+         rr_threads_needed(p->nx, p->ny) <= kRrThreads;
+}
+
+Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   Plan pl;
   pl.variant = p->variant;
   pl.refined = p->precision == CG_PREC_FP32_REFINED;
   pl.fp32g = pl.refined ? 1 : 0;
   pl.wg = use_wg(p);
+  pl.rr = allow_rr && use_rr(p);
+  if (pl.rr) {
+    pl.wg = true;
+    pl.rr_threads = (int)round_up((size_t)rr_threads_needed(p->nx, p->ny), (size_t)kWave);
+  }
   int rows, grid = 0;
   if (pl.wg) {
     rows = wg_rows(p->nx, p->ny);
@@ -576,6 +590,25 @@ static int solve_wg(Ctx& c, Work& w, const cg_problem* p, State& s) {
   return read_state(c, w, s);
 }
 
+static int solve_rr(Ctx& c, Work& w, const cg_problem* p, State& s) {
+  PassArgs a = base_args(w);
+  a.st_in = w.S[0];
+  a.st_out = w.S[1];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.prof) {
+    e0 = c.event();
+    e1 = c.event();
+    hipEventRecord(e0, c.st);
+  }
+  HIPCHK(launch_solve_rr(p->variant, a, w.pl.rr_threads, c.st));
+  if (c.prof) {
+    hipEventRecord(e1, c.st);
+    c.pending.push_back({e0, e1, "solve_rr", 0.0});
+  }
+  w.m = 1;
+  return read_state(c, w, s);
+}
+
 int Ctx::solve(const cg_problem* p, cg_result* res) {
   Ctx& c = *this;
   const double t0 = now_s();
@@ -592,7 +625,7 @@ int Ctx::solve(const cg_problem* p, cg_result* res) {
   if (rc) return rc;
   if ((rc = stage_in(c, w, p))) return rc;
   State s;
-  rc = w.pl.wg ? solve_wg(c, w, p, s) : solve_tiled(c, w, p, s);
+  rc = w.pl.rr ? solve_rr(c, w, p, s) : w.pl.wg ? solve_wg(c, w, p, s) : solve_tiled(c, w, p, s);
   if (rc) return rc;
   if ((rc = stage_out(c, w, p, s))) return rc;
   fill_result(s, res, now_s() - t0, w.pl.refined);
@@ -619,9 +652,9 @@ int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u
   p.maxit = 1;
   p.variant = CG_VARIANT_CLASSIC;
   p.precision = CG_PREC_FP64;
-  // the same geometry (hence reduction order) a solve of this shape uses;
-  // always run by the multi-work-group pass kernels
-  Plan pl = plan(&p);
+  // the tile geometry (hence reduction order) of this shape; always run by
+  // the multi-work-group pass kernels
+  Plan pl = plan(&p, false);
   if (pl.wg) {
     const int cap = std::max(8, pass_max_blocks_per_cu(kind, 0) * num_cu);
     pl.grid = (int)round_up((size_t)std::min(pl.g.tiles, cap), 8);
@@ -854,6 +887,7 @@ int Ctx::init(const cg_config* cfg) {
   HIPCHK(hipGetDeviceProperties(&prop, device));
   num_cu = prop.multiProcessorCount;
   HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&user_ev, hipEventDisableTiming));
   HIPCHK(hipHostMalloc((void**)&host_state, 4096, hipHostMallocDefault));
   user_stream = cfg ? (hipStream_t)cfg->stream : nullptr;
@@ -871,6 +905,7 @@ int Ctx::init(const cg_config* cfg) {
   if (cfg && cfg->tune_cache) tune_path = cfg->tune_cache;
   if (const char* e = getenv("CG_GRAPH_CHUNK")) graph_chunk = atoi(e);
   if (const char* e = getenv("CG_WG_MAX_DOF")) wg_max_dof = atoi(e);
+  if (const char* e = getenv("CG_RR")) rr_enabled = atoi(e) != 0;
   if (const char* e = getenv("CG_STEP_CHUNK")) step_chunk = std::max(1, atoi(e));
   if (const char* e = getenv("CG_SERVE_CHUNK")) serve_chunk = std::max(1, atoi(e));
   load_tune_cache();
@@ -880,6 +915,7 @@ int Ctx::init(const cg_config* cfg) {
 Ctx::~Ctx() {
   hipSetDevice(device);
   if (st) hipStreamSynchronize(st);
+  if (side) hipStreamSynchronize(side);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
   for (auto& pr : pending) {
     hipEventDestroy(pr.a);
@@ -889,6 +925,7 @@ Ctx::~Ctx() {
   if (user_ev) hipEventDestroy(user_ev);
   if (host_state) hipHostFree(host_state);
   if (own_arena) hipFree(own_arena);
+  if (side) hipStreamDestroy(side);
   if (st) hipStreamDestroy(st);
 }
 

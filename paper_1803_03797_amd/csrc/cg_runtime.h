@@ -44,6 +44,8 @@ struct Plan {
   bool refined = false;
   int fp32g = 0;     // geometry of the FP32 lanes (4 columns per lane)
   bool wg = false;   // whole solve inside one work-group
+  bool rr = false;   // ... with the vectors on chip (register-resident solver)
+  int rr_threads = 0;
   cgk::Geo g{};
   int grid = 8;      // work-groups per pass
   size_t v64 = 0, v32 = 0, part = 0, footprint = 0;
@@ -112,6 +114,7 @@ struct Ctx {
   int device = 0;
   int num_cu = 256;
   hipStream_t st = nullptr;
+  hipStream_t side = nullptr;  // register-resident solves of a batch, beside the steps
   hipStream_t user_stream = nullptr;
   hipEvent_t user_ev = nullptr;
   void* own_arena = nullptr;
@@ -122,11 +125,12 @@ struct Ctx {
   char* host_state = nullptr;  // pinned staging for state words
   int graph_chunk = 32;        // iterations per captured chunk; 0 = plain launches
   int wg_max_dof = 16384;      // whole-solve-in-one-work-group threshold (FP64)
+  bool rr_enabled = true;      // register-resident solver for grids that fit it
   int step_chunk = 32;         // batch: steps between harvests
   int serve_chunk = 8;         // serving: steps between admissions
   int step_chunk_for(bool serving) const { return serving ? serve_chunk : step_chunk; }
   size_t engine_bytes() const {  // control block of the multi-solve engine
-    return (size_t)max_slots * (sizeof(cgk::Slot) + 256 * sizeof(cgk::Item) + sizeof(int) +
+    return (size_t)max_slots * (sizeof(cgk::Slot) + 256 * sizeof(cgk::Item) + 2 * sizeof(int) +
                                 sizeof(cgk::State)) + 4096;
   }
   bool capturing = false;
@@ -146,7 +150,10 @@ struct Ctx {
   int init(const cg_config* cfg);
   ~Ctx();
   bool use_wg(const cg_problem* p) const;
-  Plan plan(const cg_problem* p);
+  bool use_rr(const cg_problem* p) const;
+  // allow_rr = false: the tile geometry even where the register-resident
+  // solver would run the problem (building blocks use tiles)
+  Plan plan(const cg_problem* p, bool allow_rr = true);
   int solve(const cg_problem* p, cg_result* res);
   int solve_batch(const cg_problem* p, int n, cg_result* res);
   int apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u, const double* y_in,

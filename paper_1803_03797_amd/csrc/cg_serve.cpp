@@ -9,7 +9,10 @@
 // over a table of (solve, tile range) items; chunks of steps run back to
 // back, and between chunks finished solves are harvested (solution copied
 // out, memory returned) and new ones admitted.  Each solve keeps its vectors
-// and scalars resident on the device from admission to retirement.
+// and scalars resident on the device from admission to retirement.  Solves
+// small enough for the register-resident solver take no step items: the
+// chunk that follows their admission also launches them, one work-group
+// each, on a side stream, and the next harvest waits for them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +49,10 @@ class Engine {
 
   explicit Engine(Ctx& c, int nslots) : c_(c), n_(std::max(1, nslots)) {}
   ~Engine() {
+    if (rr_pending_) hipStreamSynchronize(c_.side);
+    if (rr_ev_) hipEventDestroy(rr_ev_);
+    if (stage_ev_) hipEventDestroy(stage_ev_);
+    if (h_rr_idx_) hipHostFree(h_rr_idx_);
     if (graph_) hipGraphExecDestroy(graph_);
     for (Job* j : slot_job_)
       if (j) c_.arena.release(j->w.mem);
@@ -63,14 +70,20 @@ class Engine {
     const size_t b_items = round256((size_t)max_items_ * sizeof(Item));
     const size_t b_idx = round256((size_t)n_ * sizeof(int) + sizeof(int));
     const size_t b_states = round256((size_t)n_ * sizeof(State));
-    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states + 256);
+    const size_t b_rr = round256((size_t)n_ * sizeof(int));
+    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states + b_rr + 256);
     if (!ctrl_) return CG_E_NOMEM;
     d_slots_ = (Slot*)ctrl_;
     d_items_ = (Item*)(ctrl_ + b_slots);
     d_idx_ = (int*)(ctrl_ + b_slots + b_items);
     d_nitems_ = d_idx_ + n_;
     d_states_ = (State*)(ctrl_ + b_slots + b_items + b_idx);
-    d_step_ = (int*)(ctrl_ + b_slots + b_items + b_idx + b_states);
+    d_rr_idx_ = (int*)(ctrl_ + b_slots + b_items + b_idx + b_states);
+    d_step_ = (int*)(ctrl_ + b_slots + b_items + b_idx + b_states + b_rr);
+    if (hipEventCreateWithFlags(&rr_ev_, hipEventDisableTiming) ||
+        hipEventCreateWithFlags(&stage_ev_, hipEventDisableTiming) ||
+        hipHostMalloc((void**)&h_rr_idx_, (size_t)n_ * sizeof(int), hipHostMallocDefault))
+      return CG_E_DEVICE;
     if (hipHostMalloc((void**)&h_slots_, (size_t)n_ * sizeof(Slot), hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_items_, (size_t)max_items_ * sizeof(Item) + 256,
                       hipHostMallocDefault) ||
@@ -151,6 +164,8 @@ class Engine {
     slot_job_[slot] = j;
     j->slot = slot;
     j->t_admit = now_s();
+    if (w.pl.rr) rr_new_.push_back(slot);
+    else ++step_jobs_;
     // a solve finishes within 5 maxit + 16 passes: 2 per inner iteration and
     // at most 3 per outer step, each outer step taking an inner iteration
     j->steps_cap = step_ + 5 * j->p.maxit + 16;
@@ -164,6 +179,21 @@ class Engine {
   int run(int steps) {
     if (!active_) return CG_OK;
     if (dirty_ && upload_items()) return CG_E_DEVICE;
+    if (!rr_new_.empty()) {
+      // newly admitted small solves: whole solves on the side stream, after
+      // their staging on the main stream
+      const int n = (int)rr_new_.size();
+      memcpy(h_rr_idx_, rr_new_.data(), (size_t)n * sizeof(int));
+      if (hipMemcpyAsync(d_rr_idx_, h_rr_idx_, (size_t)n * sizeof(int), hipMemcpyHostToDevice,
+                         c_.st) ||
+          hipEventRecord(stage_ev_, c_.st) || hipStreamWaitEvent(c_.side, stage_ev_, 0) ||
+          launch_solve_rr_many(d_slots_, d_rr_idx_, n, c_.side) ||
+          hipEventRecord(rr_ev_, c_.side))
+        return CG_E_DEVICE;
+      rr_new_.clear();
+      rr_pending_ = true;
+    }
+    if (!step_jobs_) return CG_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c_.prof) {
       e0 = c_.event();
@@ -211,6 +241,10 @@ class Engine {
   // Moves finished solves out: copies x back, fills the result, frees memory.
   int harvest(std::vector<Job*>& done) {
     if (!active_) return CG_OK;
+    if (rr_pending_) {
+      if (hipStreamWaitEvent(c_.st, rr_ev_, 0)) return CG_E_DEVICE;
+      rr_pending_ = false;
+    }
     int n = 0;
     for (int i = 0; i < n_; ++i)
       if (slot_job_[i]) h_idx_[n++] = i;
@@ -237,6 +271,7 @@ class Engine {
         fill_result(s, &j->res, j->t_done - j->t_admit, j->w.pl.refined);
         j->rc = j->res.status;
       }
+      if (!j->w.pl.rr) --step_jobs_;
       c_.arena.release(j->w.mem);
       j->w.mem = nullptr;
       slot_job_[i] = nullptr;
@@ -250,6 +285,10 @@ class Engine {
 
   // Fails every resident solve (used after a device error).
   void abandon(std::vector<Job*>& done, int rc) {
+    if (rr_pending_) hipStreamSynchronize(c_.side);
+    rr_pending_ = false;
+    rr_new_.clear();
+    step_jobs_ = 0;
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
       if (!j) continue;
@@ -273,7 +312,7 @@ class Engine {
     int n = 0;
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
-      if (!j) continue;
+      if (!j || j->w.pl.rr) continue;
       const int T = j->w.pl.g.tiles;
       const int per = (T + kMaxItemsPerSolve - 1) / kMaxItemsPerSolve;
       for (int t = 0; t < T; t += per) h_items_[n++] = Item{i, t, std::min(T, t + per), 0};
@@ -314,6 +353,12 @@ class Engine {
   int* h_idx_ = nullptr;
   State* h_states_ = nullptr;
   std::vector<Job*> slot_job_;
+  std::vector<int> rr_new_;  // slots of register-resident solves not yet launched
+  int* d_rr_idx_ = nullptr;
+  int* h_rr_idx_ = nullptr;
+  hipEvent_t rr_ev_ = nullptr, stage_ev_ = nullptr;
+  bool rr_pending_ = false;  // launched, not yet joined by a harvest
+  int step_jobs_ = 0;        // resident solves that take step items
   int active_ = 0;
   int grid_ = 8;
   int step_ = 0;

@@ -74,3 +74,32 @@ def test_create_without_gpu_fails_cleanly():
     assert lib.cg_create(C.byref(cfg), C.byref(h)) == cg.CG_E_DEVICE
     assert not h.value
     assert lib.cg_destroy(None) == cg.CG_E_INVALID
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    the C compiler gives the header's structures."""
+    structs = {"cg_config": cg.cg_config, "cg_problem": cg.cg_problem,
+               "cg_result": cg.cg_result, "cg_plan_info": cg.cg_plan_info,
+               "cg_kstat": cg.cg_kstat}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "cg.h"', 'int main(void) {']
+    for name, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for name, py in structs.items():
+        assert got[(name, "size")] == C.sizeof(py), name
+        for f in py._fields_:
+            assert got[(name, f[0])] == getattr(py, f[0]).offset, (name, f[0])

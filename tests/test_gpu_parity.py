@@ -40,8 +40,16 @@ def ctx(torch):
 
 
 def order_of(ctx, nx, ny, variant=0):
+    """The reduction order a solve of this shape uses, and the plan."""
     info = ctx.cg_plan(nx, ny, variant)
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2), info
+    if info.path == 2:
+        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves), info
+    return tile_order(info), info
+
+
+def tile_order(info):
+    """The tile order of the shape (cg_dot and cg_apply use it on every path)."""
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
 
 
 def rel(a, b):
@@ -83,7 +91,7 @@ def test_dot_matches_canonical_order(ctx, nx, ny):
     rng = np.random.default_rng(nx + 13 * ny)
     a = rng.standard_normal((ny, nx))
     b = rng.standard_normal((ny, nx))
-    o, _ = order_of(ctx, nx, ny)
+    o = tile_order(ctx.cg_plan(nx, ny))
     got = ctx.cg_dot(a, b, nx, ny)
     assert got == oracle.dot(a, b, nx, ny, MODE_CANONICAL, o)
     exact = math.fsum((a * b).ravel())
@@ -149,7 +157,7 @@ def test_natural_stop(ctx, nx, ny, variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_small_workload_device_memory(ctx, torch, variant):
-    """The 100x100 workload through device pointers (single work-group path)."""
+    """The 100x100 workload through device pointers (on-chip solver)."""
     nx, ny = workloads.SMALL["nx"], workloads.SMALL["ny"]
     b = workloads.small_problem()
     say("small workload device", variant)
@@ -157,7 +165,7 @@ def test_small_workload_device_memory(ctx, torch, variant):
     xd = torch.zeros_like(bd)
     rc, res = ctx.solve(bd, xd, nx, ny, tol=1e-8, maxit=2000, variant=variant)
     o, info = order_of(ctx, nx, ny, variant)
-    assert info.path == 1
+    assert info.path == 2 and info.seg_rows * info.seg_waves * info.lanes >= nx * ny
     xk, rk = oracle.cg(b, nx, ny, variant=variant, tol=1e-8, maxit=2000, mode=MODE_CANONICAL,
                        order=o)
     xs, rs = oracle.cg(b, nx, ny, variant=variant, tol=1e-8, maxit=2000)
