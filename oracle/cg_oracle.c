@@ -56,7 +56,9 @@ typedef struct {
   int32_t rows;          /* rows per wavefront strip                         */
   int32_t threads2;      /* threads of the cross-tile sum (multiple of lanes) */
   int32_t layout;        /* 0: tiles (dot_canonical); 1: column segments
-                            (dot_segments: rows, lanes, waves are used)       */
+                            (dot_segments: rows, lanes, waves, seg_cols)      */
+  int32_t seg_cols;      /* layout 1: threads per row of segments (>= nx; the
+                            threads of columns >= nx own nothing)             */
 } oracle_order;
 
 typedef struct {
@@ -267,28 +269,29 @@ static double dot_canonical(int32_t nx, int32_t ny, const double* a, const doubl
 /* Canonical order of the column-segment layout, used by a solver that keeps
  * one small grid in a single work-group of waves*lanes threads, each thread
  * owning a short piece of one grid column:
- *   E = rows;  segments per column S = ceil(ny / E);
- *   thread t = w*lanes + l (wavefront w, lane l) owns column c = t mod nx and
- *   rows s*E .. s*E + E - 1 (those < ny) of segment s = t div nx; threads with
- *   s >= S own nothing (their lane value is +0).
+ *   E = rows;  segments per column S = ceil(ny / E);  C = seg_cols >= nx;
+ *   thread t = w*lanes + l (wavefront w, lane l) owns column c = t mod C and
+ *   rows s*E .. s*E + E - 1 (those < ny) of segment s = t div C; threads with
+ *   c >= nx or s >= S own nothing (their lane value is +0).
  *   Lane: one accumulator from +0, acc = fma(a, b, acc) over its rows in
  *     ascending order.
  *   Wavefront: xor butterfly (see butterfly()).
  *   Total: ((wave_0 + wave_1) + wave_2) + ...
- * The layout must cover the grid: waves*lanes >= nx*S (else NaN). */
+ * The layout must cover the grid: seg_cols >= nx and waves*lanes >= C*S
+ * (else NaN). */
 static double dot_segments(int32_t nx, int32_t ny, const double* a, const double* b,
                            const oracle_order* o) {
-  const int32_t E = o->rows, L = o->lanes, W = o->waves;
+  const int32_t E = o->rows, L = o->lanes, W = o->waves, C = o->seg_cols;
   const int64_t S = (ny + E - 1) / E;
-  if ((int64_t)W * L < (int64_t)nx * S) return NAN;
+  if (C < nx || (int64_t)W * L < (int64_t)C * S) return NAN;
   double lane[256];
   double total = 0.0;
   for (int32_t w = 0; w < W; ++w) {
     for (int32_t l = 0; l < L; ++l) {
       const int64_t t = (int64_t)w * L + l;
-      const int64_t c = t % nx, s = t / nx;
+      const int64_t c = t % C, s = t / C;
       double acc = 0.0;
-      if (s < S)
+      if (s < S && c < nx)
         for (int64_t j = s * E; j < s * E + E && j < ny; ++j)
           acc = fma(a[j * nx + c], b[j * nx + c], acc);
       lane[l] = acc;
@@ -509,7 +512,8 @@ static int order_valid(const oracle_order* o, int32_t nx, int32_t ny) {
       o->rows < 1)
     return 0;
   if (o->layout == 1)
-    return (int64_t)o->waves * o->lanes >= (int64_t)nx * ((ny + o->rows - 1) / o->rows);
+    return o->seg_cols >= nx &&
+           (int64_t)o->waves * o->lanes >= (int64_t)o->seg_cols * ((ny + o->rows - 1) / o->rows);
   return o->layout == 0 && o->cols_per_lane >= 1 && o->cols_per_lane <= 16 &&
          o->threads2 >= o->lanes && o->threads2 % o->lanes == 0;
 }

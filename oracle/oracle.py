@@ -19,12 +19,14 @@ class Order(C.Structure):
     """Reduction order of the canonical mode: layout 0 = tiles (dot_canonical in
     the C file), layout 1 = column segments (dot_segments)."""
     _fields_ = [("cols_per_lane", C.c_int32), ("lanes", C.c_int32), ("waves", C.c_int32),
-                ("rows", C.c_int32), ("threads2", C.c_int32), ("layout", C.c_int32)]
+                ("rows", C.c_int32), ("threads2", C.c_int32), ("layout", C.c_int32),
+                ("seg_cols", C.c_int32)]
 
     @classmethod
-    def segments(cls, rows, lanes, waves):
-        """Column-segment order: waves*lanes threads, `rows` rows per thread."""
-        return cls(1, lanes, waves, rows, 0, 1)
+    def segments(cls, rows, lanes, waves, seg_cols):
+        """Column-segment order: waves*lanes threads, `rows` rows per thread,
+        seg_cols threads per row of segments (those of columns >= nx idle)."""
+        return cls(1, lanes, waves, rows, 0, 1, seg_cols)
 
 
 class _Result(C.Structure):

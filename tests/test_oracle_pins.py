@@ -127,18 +127,20 @@ def test_canonical_dot_exact_on_integers(nx, ny, order):
     assert oracle.dot(w, one, nx, ny, MODE_CANONICAL, order) == (nx * ny) * (nx * ny + 1) / 2
 
 
-def seg_order(nx, ny, rows, lanes, spare_waves=1):
-    """Column-segment order covering the grid, with idle threads in spare waves."""
-    need = nx * -(-ny // rows)
-    return oracle.Order.segments(rows, lanes, -(-need // lanes) + spare_waves)
+def seg_order(nx, ny, rows, lanes, spare_waves=1, ghosts=1):
+    """Column-segment order covering the grid, with `ghosts` idle threads per
+    row of segments and idle threads in spare waves."""
+    cols = nx + ghosts
+    need = cols * -(-ny // rows)
+    return oracle.Order.segments(rows, lanes, -(-need // lanes) + spare_waves, cols)
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 37), (37, 1), (100, 100), (129, 65), (1000, 3)])
-@pytest.mark.parametrize("rows,lanes", [(10, 64), (1, 64), (3, 4), (7, 16)])
-def test_segment_dot_exact_on_integers(nx, ny, rows, lanes):
+@pytest.mark.parametrize("rows,lanes,ghosts", [(10, 64, 1), (1, 64, 0), (3, 4, 2), (7, 16, 1)])
+def test_segment_dot_exact_on_integers(nx, ny, rows, lanes, ghosts):
     """The column-segment order counts every term exactly once: exact on
     integer data, and the position-weighted sum identifies every term."""
-    order = seg_order(nx, ny, rows, lanes)
+    order = seg_order(nx, ny, rows, lanes, ghosts=ghosts)
     rng = np.random.default_rng(nx * 7 + ny)
     a = rng.integers(-8, 9, size=(ny, nx)).astype(float)
     b = rng.integers(-8, 9, size=(ny, nx)).astype(float)
@@ -153,14 +155,15 @@ def test_segment_dot_exact_on_integers(nx, ny, rows, lanes):
 
 
 def test_segment_order_must_cover_the_grid():
-    short = oracle.Order.segments(10, 64, 15)  # 960 threads < 100 * 10 segments
-    assert math.isnan(oracle.dot(np.ones((100, 100)), np.ones((100, 100)), 100, 100,
-                                 MODE_CANONICAL, short))
-    with pytest.raises(ValueError):
-        oracle.cg(np.ones((100, 100)), 100, 100, mode=MODE_CANONICAL, order=short)
-    ok = oracle.Order.segments(10, 64, 16)
-    assert oracle.dot(np.ones((100, 100)), np.ones((100, 100)), 100, 100, MODE_CANONICAL,
-                      ok) == 1e4
+    one = np.ones((100, 100))
+    short = oracle.Order.segments(10, 64, 15, 100)  # 960 threads < 100 * 10 segments
+    narrow = oracle.Order.segments(10, 64, 20, 99)  # fewer threads per row than columns
+    for o in (short, narrow):
+        assert math.isnan(oracle.dot(one, one, 100, 100, MODE_CANONICAL, o))
+        with pytest.raises(ValueError):
+            oracle.cg(one, 100, 100, mode=MODE_CANONICAL, order=o)
+    for o in (oracle.Order.segments(10, 64, 16, 100), oracle.Order.segments(20, 64, 8, 101)):
+        assert oracle.dot(one, one, 100, 100, MODE_CANONICAL, o) == 1e4
 
 
 def test_segment_dot_error_bound():
