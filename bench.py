@@ -504,8 +504,10 @@ def bench_serve(args):
 
 def bench_probe(args):
     torch, cg = setup()
-    ctx = cg.Context(device=0, arena_bytes=6 << 30)
-    names = ["read", "copy", "2R1W", "3R2W", "6R6W"]
+    ctx = cg.Context(device=0, arena_bytes=8 << 30)
+    # 6R6W: in place (the traffic of pcg_pass); 6R6W_out: six other vectors
+    # written; 6R6W_nt: in place with non-temporal stores
+    names = ["read", "copy", "2R1W", "3R2W", "6R6W", "6R6W_out", "6R6W_nt"]
     out = {}
     if args.copy_only:
         # the known-size copy that calibrates the traffic counters: one

@@ -97,8 +97,9 @@ typedef struct {
  * rows rows; lanes accumulate with fma in row order; xor butterfly; waves in
  * order; tiles in index order through threads2 strided threads.  Column-
  * segment order (path 2, alone and in a batch): thread t of seg_waves*64
- * owns column t mod nx and seg_rows rows of segment t div nx; fma in row
- * order; xor butterfly; waves in order.  The tile fields always describe the
+ * owns column t mod seg_cols and seg_rows rows of segment t div seg_cols
+ * (threads of columns >= nx own nothing); fma in row order; xor butterfly;
+ * waves in order.  The tile fields always describe the
  * tile geometry of the shape (cg_dot and cg_apply use it on every path). */
 typedef struct {
   int32_t path;             /* 0 = multi-work-group passes, 1 = single work-group,
@@ -109,7 +110,7 @@ typedef struct {
   int32_t pitch;            /* padded row length in elements                         */
   int32_t seg_rows;         /* path 2: rows per thread; else 0                       */
   int32_t seg_waves;        /* path 2: wavefronts of the work-group; else 0          */
-  int32_t pad_;
+  int32_t seg_cols;         /* path 2: threads per row of segments (nx + 1); else 0  */
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 
@@ -179,11 +180,14 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
                 int32_t grid, int32_t cols_per_lane);
 /* HBM probe, for measurement only: runs a plain streaming kernel over
  * device buffers carved from the arena, `elems` doubles per vector, reps + 1
- * times (the first warms up) and returns the best time and the bytes it moves.
+ * times (the first warms up) for each of the grids of 1, 2, 4 and 8
+ * work-groups per CU, and returns the best time and the bytes it moves.
  * pattern 0: read one vector; 1: copy one vector to another (the known-size
  * copy that calibrates hardware traffic counters); 2: two reads, one write;
  * 3: three reads, two writes; 4: six vectors read and written in place (the
- * traffic mix of a pipelined CG pass).  CG_E_NOMEM if the arena is too small. */
+ * traffic mix of a pipelined CG pass); 5: six vectors read, six others
+ * written; 6: as 4 with non-temporal stores.  CG_E_NOMEM if the arena is too
+ * small. */
 int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
                     double* bytes);
 /* Profiling on/off; while on, every kernel launch is bracketed by HIP events

@@ -47,7 +47,7 @@ class cg_plan_info(C.Structure):
     _fields_ = [("path", C.c_int32), ("cols_per_lane", C.c_int32), ("lanes", C.c_int32),
                 ("waves", C.c_int32), ("rows", C.c_int32), ("threads2", C.c_int32),
                 ("tiles", C.c_int32), ("grid", C.c_int32), ("pitch", C.c_int32),
-                ("seg_rows", C.c_int32), ("seg_waves", C.c_int32), ("pad_", C.c_int32),
+                ("seg_rows", C.c_int32), ("seg_waves", C.c_int32), ("seg_cols", C.c_int32),
                 ("footprint", C.c_size_t)]
 
 

@@ -120,6 +120,7 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   info->path = pl.rr ? 2 : pl.wg ? 1 : 0;
   info->seg_rows = pl.rr ? cgk::kRrRows : 0;
   info->seg_waves = pl.rr ? pl.rr_threads / cgk::kWave : 0;
+  info->seg_cols = pl.rr ? prob->nx + 1 : 0;
   info->cols_per_lane = pl.fp32g ? 4 : 2;
   info->lanes = cgk::kWave;
   info->waves = cgk::kWavesPerTile;
@@ -165,7 +166,7 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
 
 int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
                     double* bytes) {
-  if (!ctx || !seconds || !bytes || pattern < 0 || pattern > 4 || elems < 2 || reps < 1)
+  if (!ctx || !seconds || !bytes || pattern < 0 || pattern > 6 || elems < 2 || reps < 1)
     return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);

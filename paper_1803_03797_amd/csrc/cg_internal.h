@@ -157,7 +157,7 @@ hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slo
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_solve_wg(int variant, const PassArgs& a, hipStream_t s);
 // Whole solve in one work-group of `threads` threads with the vectors on chip;
-// needs nx * ceil(ny / kRrRows) <= threads <= kRrThreads.
+// needs (nx + 1) * ceil(ny / kRrRows) <= threads <= kRrThreads.
 hipError_t launch_solve_rr(int variant, const PassArgs& a, int threads, hipStream_t s);
 // One register-resident solve per listed slot (slots[idx[i]], i < n), each
 // fitting the solver; final states land in both state buffers, kind K_DONE.

@@ -176,8 +176,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // The same butterfly (stage order 32, 16, ..., 1; every lane adds its xor
-// partner) with the stages inside 32-lane halves done by ds_swizzle, whose
-// lane pattern is an immediate: no per-lane address registers are needed.
+// partner) with the stages inside 32-lane halves done by DPP row/quad
+// permutations (xor 8, 2, 1) or ds_swizzle (xor 16, 4), whose lane patterns
+// are immediates: no per-lane address registers, half the LDS round trips.
 template <int M>
 __device__ __forceinline__ double swz_xor(double v) {
   constexpr int pat = 0x1f | (M << 10);  // bitmask mode: lane ^ M within 32 lanes
@@ -186,13 +187,18 @@ __device__ __forceinline__ double swz_xor(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// DPP controls that are xor permutations inside 16-lane rows.
+constexpr int kDppXor8 = 0x128;  // row_ror:8: lane l of a 16-lane row gets lane l ^ 8
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2,3,0,1]: lane l gets lane l ^ 2
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1,0,3,2]: lane l gets lane l ^ 1
+
 __device__ __forceinline__ double wave_sum_swz(double v) {
   v = v + __shfl_xor(v, 32, kWave);
   v = v + swz_xor<16>(v);
-  v = v + swz_xor<8>(v);
+  v = v + dpp<kDppXor8>(v, v);
   v = v + swz_xor<4>(v);
-  v = v + swz_xor<2>(v);
-  v = v + swz_xor<1>(v);
+  v = v + dpp<kDppXor2>(v, v);
+  v = v + dpp<kDppXor1>(v, v);
   return v;
 }
 
@@ -1137,18 +1143,25 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
 
 // ------------------------------------------ register-resident small solve --
 //
-// For a grid with nx * ceil(ny / kRrRows) <= kRrThreads the whole solve runs
-// in one work-group with every vector on chip.  Thread t owns column
-// c = t mod nx and the kRrRows rows of segment t div nx (rows past ny are held
-// as zero); threads past the last segment own nothing.  Along a column the
-// stencil's south/north neighbours are the thread's own registers; west/east
-// neighbours come from the adjacent lanes by DPP.  What crosses a thread's
-// boundary (the first and last element of every segment, the whole segment of
-// lanes 0 and 63 of each wavefront) goes through LDS, together with the
-// wavefront sums of the dot products, with one barrier per exchange and the
-// LDS buffers double-buffered by phase parity.  Pipelined CG keeps x in LDS
-// (six vectors do not fit the register file), classic CG keeps all four of
-// its vectors (x, r, p, A p) in registers.
+// For a grid with (nx + 1) * ceil(ny / kRrRows) <= kRrThreads the whole solve
+// runs in one work-group with every vector on chip.  Threads are laid out in
+// rows of nx + 1: thread t owns column c = t mod (nx + 1) and the kRrRows rows
+// of segment t div (nx + 1) (rows past ny are held as zero); the last thread
+// of each row (c == nx) and the threads past the last segment own nothing and
+// hold zeros, so the west neighbour of column 0 and the east neighbour of
+// column nx-1 read as zero without a test.  Along a column the stencil's
+// south/north neighbours are the thread's own registers; west/east neighbours
+// come from the adjacent lanes by DPP.  What crosses a thread's boundary (the
+// first and last element of every segment, the whole segment of lanes 0 and
+// 63 of each wavefront) goes through LDS, together with the wavefront sums of
+// the dot products, with one barrier per exchange and the LDS buffers
+// double-buffered by phase parity.  Pipelined CG keeps x in LDS (six vectors
+// do not fit the register file), classic CG keeps all four of its vectors
+// (x, r, p, A p) in registers.
+//
+// Rows outside the grid hold exact zeros through every update (the stencil
+// result is forced to zero there, and every other update maps zeros to +0),
+// so the dot products accumulate them without a test: fma(0, 0, acc) == acc.
 //
 // Dot products follow the column-segment order: fma per thread over its rows
 // in ascending order, xor butterfly, wavefronts in order.  The scalar
@@ -1158,19 +1171,21 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
 constexpr int kRrWaves = kRrThreads / kWave;
 
 struct RrXchg {  // one exchanged vector
-  double first[kRrThreads];           // element 0 of each thread's segment
-  double last[kRrThreads];            // element kRrRows-1
-  double edge[kRrWaves][2][kRrRows];  // segments of lanes 0 and 63 of each wavefront
+  double first[kRrThreads];  // element 0 of each thread's segment
+  double last[kRrThreads];   // element kRrRows-1
+  // segments of lanes 0 and 63 of wavefront w at [w + 1]; [0] stays zero (the
+  // west neighbour of thread 0)
+  double edge[kRrWaves + 1][2][kRrRows];
 };
 
 struct RrLdsPcg {
-  RrXchg x[2];                   // by phase parity
-  double tot[2][kRrWaves][2];    // wavefront sums, by phase parity
+  RrXchg x[2];                     // by phase parity
+  double tot[2][kRrWaves][2];      // wavefront sums, by phase parity
   double xs[kRrRows][kRrThreads];  // the iterate x
 };
 
 struct RrLdsCg {
-  RrXchg x[2][2];                // [parity][r, p]
+  RrXchg x[2][2];  // [parity][r, p]
   double tot[2][kRrWaves][2];
 };
 
@@ -1178,9 +1193,9 @@ constexpr size_t kRrLdsBytes =
     sizeof(RrLdsPcg) > sizeof(RrLdsCg) ? sizeof(RrLdsPcg) : sizeof(RrLdsCg);
 
 struct RrSeg {
-  int t, lane, wave, nw, nx;
+  int t, lane, wave, nw;
+  int stride;         // threads per row of segments (nx + 1)
   int nv;             // rows of the segment inside the grid (0: idle thread)
-  bool west, east;    // a west / east neighbour column exists
   bool south, north;  // the segment below / above exists
   size_t off;         // element offset of the segment's first row (padded pitch)
   int pitch;
@@ -1192,18 +1207,22 @@ __device__ __forceinline__ RrSeg rr_seg(const Geo& g) {
   s.lane = s.t & (kWave - 1);
   s.wave = s.t >> 6;
   s.nw = blockDim.x >> 6;
-  s.nx = g.nx;
+  s.stride = g.nx + 1;
   const int nseg = (g.ny + kRrRows - 1) / kRrRows;
-  const int c = s.t % g.nx, sg = s.t / g.nx;
-  const bool act = sg < nseg;
+  const int c = s.t % s.stride, sg = s.t / s.stride;
+  const bool act = sg < nseg && c < g.nx;
   s.nv = act ? min(kRrRows, g.ny - sg * kRrRows) : 0;
-  s.west = act && c > 0;
-  s.east = act && c + 1 < g.nx;
   s.south = act && sg > 0;
   s.north = act && sg + 1 < nseg;
   s.pitch = g.pitch;
   s.off = act ? (size_t)sg * kRrRows * g.pitch + c : 0;
   return s;
+}
+
+// Zeroes the never-written edge entry of both parities of an exchange buffer.
+__device__ __forceinline__ void rr_clear_edge0(RrXchg& X) {
+  const int t = threadIdx.x;
+  if (t < 2 * kRrRows) X.edge[0][t / kRrRows][t % kRrRows] = 0.0;
 }
 
 using RrVec = double[kRrRows];
@@ -1237,7 +1256,7 @@ __device__ __forceinline__ void rr_publish(const RrVec& v, const RrSeg& s, RrXch
   X.first[s.t] = v[0];
   X.last[s.t] = v[kRrRows - 1];
   if (s.lane == 0 || s.lane == kWave - 1) {
-    double* d = X.edge[s.wave][s.lane == 0 ? 0 : 1];
+    double* d = X.edge[s.wave + 1][s.lane == 0 ? 0 : 1];
 #pragma unroll
     for (int e = 0; e < kRrRows; ++e) d[e] = v[e];
   }
@@ -1252,22 +1271,29 @@ __device__ __forceinline__ void rr_publish(const RrVec& v, const RrSeg& s, RrXch
 template <class F>
 struct RrHalo {
   double S, N;
-  const double* e1;  // this lane's edge segment (used by lanes 0 and 63 only)
-  const double* e2;
+  // the wavefront's west edge (used by lane 0) and east edge (used by lane
+  // 63); wavefront-uniform addresses, so every lane reads the same entry
+  const double *eW, *eE;
+  const double *eW2, *eE2;
   F f;
 };
 
 template <class F>
 __device__ __forceinline__ RrHalo<F> rr_halo(const RrSeg& s, const RrXchg& X, const RrXchg* X2,
                                              F f) {
-  const int ts = s.south ? s.t - s.nx : s.t, tn = s.north ? s.t + s.nx : s.t;
+  const int ts = s.south ? s.t - s.stride : s.t, tn = s.north ? s.t + s.stride : s.t;
   const double S = f(X.last[ts], X2 ? X2->last[ts] : 0.0);
   const double N = f(X.first[tn], X2 ? X2->first[tn] : 0.0);
-  // lane 0 takes lane 63 of the previous wavefront, lane 63 lane 0 of the next
-  const int ww = s.wave > 0 ? s.wave - 1 : 0, we = s.wave + 1 < s.nw ? s.wave + 1 : s.wave;
-  const int wsel = s.lane == 0 ? ww : we, side = s.lane == 0 ? 1 : 0;
-  return RrHalo<F>{s.south ? S : 0.0, s.north ? N : 0.0, X.edge[wsel][side],
-                   X2 ? X2->edge[wsel][side] : nullptr, f};
+  // west: lane 63 of the previous wavefront (the zero entry for wavefront 0);
+  // east: lane 0 of the next (for the last wavefront an entry nobody uses)
+  const int ww = s.wave, we = min(s.wave + 2, s.nw);
+  return RrHalo<F>{s.south ? S : 0.0,
+                   s.north ? N : 0.0,
+                   X.edge[ww][1],
+                   X.edge[we][0],
+                   X2 ? X2->edge[ww][1] : nullptr,
+                   X2 ? X2->edge[we][0] : nullptr,
+                   f};
 }
 
 // (A v) at element e of the segment; zero for rows outside the grid.  vs is
@@ -1276,11 +1302,10 @@ __device__ __forceinline__ RrHalo<F> rr_halo(const RrSeg& s, const RrXchg& X, co
 template <class F>
 __device__ __forceinline__ double rr_st5(const RrVec& v, double vs, const RrSeg& s,
                                          const RrHalo<F>& h, int e) {
-  const double ev = h.f(h.e1[e], h.e2 ? h.e2[e] : 0.0);
-  double w = dpp<kDppWaveShr1>(v[e], ev);   // lane 0 keeps ev: its west edge
-  double ea = dpp<kDppWaveShl1>(v[e], ev);  // lane 63 keeps ev: its east edge
-  w = s.west ? w : 0.0;
-  ea = s.east ? ea : 0.0;
+  const double evW = h.f(h.eW[e], h.eW2 ? h.eW2[e] : 0.0);
+  const double evE = h.f(h.eE[e], h.eE2 ? h.eE2[e] : 0.0);
+  const double w = dpp<kDppWaveShr1>(v[e], evW);   // lane 0 keeps its west edge
+  const double ea = dpp<kDppWaveShl1>(v[e], evE);  // lane 63 keeps its east edge
   const double so = e > 0 ? vs : h.S;
   const double no = e + 1 < kRrRows ? v[e + 1] : h.N;
   return e < s.nv ? st5(v[e], w, ea, so, no) : 0.0;
@@ -1296,15 +1321,23 @@ __device__ __forceinline__ void rr_publish_sums(const double* acc, const RrSeg& 
   }
 }
 
+// Sums of the wavefront totals in wavefront order.  All kRrWaves entries are
+// loaded at once (entries of absent wavefronts are read but not added).
 template <int D>
 __device__ __forceinline__ void rr_read_sums(const RrSeg& s, const double (*tot)[2],
                                              double* sum) {
+  double2 t[kRrWaves];
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    double v = tot[0][d];
-    for (int w = 1; w < s.nw; ++w) v = v + tot[w][d];
-    sum[d] = uniform(v);
+  for (int w = 0; w < kRrWaves; ++w) t[w] = *reinterpret_cast<const double2*>(tot[w]);
+  double v0 = t[0].x, v1 = t[0].y;
+#pragma unroll
+  for (int w = 1; w < kRrWaves; ++w) {
+    const double a0 = v0 + t[w].x, a1 = v1 + t[w].y;
+    v0 = w < s.nw ? a0 : v0;
+    v1 = w < s.nw ? a1 : v1;
   }
+  sum[0] = uniform(v0);
+  if (D > 1) sum[1] = uniform(v1);
 }
 
 struct RrId {
@@ -1320,6 +1353,70 @@ struct RrDir {
   }
 };
 
+// true residual b - A x of the final iterate: slot (t,t); res2 = its sum
+__device__ __forceinline__ void rr_final_residual(const PassArgs& a, const RrSeg& s, State& st,
+                                                  const RrVec& x, RrXchg& X,
+                                                  double (*tot_out)[2]) {
+  rr_publish(x, s, X);
+  __syncthreads();
+  RrVec b;
+  rr_load(a.b, s, b);
+  const auto h = rr_halo(s, X, nullptr, RrId());
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) {
+    const double t = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
+    acc[0] = fma(t, t, acc[0]);
+  }
+  rr_publish_sums<1>(acc, s, tot_out);
+  __syncthreads();
+  double sum[1];
+  rr_read_sums<1>(s, tot_out, sum);
+  st.res2 = sum[0];
+}
+
+// One pass of Algorithm 2's loop (the K_PCG pass): sums of the previous
+// pass, transition, then nvec = A w and the z, q, p, x, r, w recurrences with
+// slots (r,r), (w,r).  FIRST: the first loop pass (z = nvec, q = w, p = r).
+// Returns false when the solve stops.
+template <bool FIRST>
+__device__ __forceinline__ bool rr_pcg_pass(const RrSeg& s, RrLdsPcg& L, int& par, State& st,
+                                            RrVec& r, RrVec& w, RrVec& p, RrVec& q, RrVec& z) {
+  double sum[2];
+  Sc sc;
+  rr_read_sums<2>(s, L.tot[par], sum);
+  if (!transition<K_PCG>(st, sum, sc)) return false;
+  rr_uniform(st, sc);
+  const double al = sc.al, be = sc.be, nal = -sc.al;
+  const auto h = rr_halo(s, L.x[par], nullptr, RrId());
+  double ac[2] = {0.0, 0.0};
+  double wprev = 0.0;  // w[e-1] of this pass (w is updated in place)
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) {
+    const double nv = rr_st5(w, wprev, s, h, e);
+    wprev = w[e];
+    if (FIRST) {
+      z[e] = nv;
+      q[e] = w[e];
+      p[e] = r[e];
+    } else {
+      z[e] = fma(be, z[e], nv);
+      q[e] = fma(be, q[e], w[e]);
+      p[e] = fma(be, p[e], r[e]);
+    }
+    L.xs[e][s.t] = fma(al, p[e], L.xs[e][s.t]);
+    r[e] = fma(nal, q[e], r[e]);
+    w[e] = fma(nal, z[e], w[e]);
+    ac[0] = fma(r[e], r[e], ac[0]);
+    ac[1] = fma(w[e], r[e], ac[1]);
+  }
+  par ^= 1;
+  rr_publish(w, s, L.x[par]);
+  rr_publish_sums<2>(ac, s, L.tot[par]);
+  __syncthreads();
+  return true;
+}
+
 // Pipelined CG (Algorithm 2) on one grid, x in LDS.
 __device__ __forceinline__ void rr_solve_pcg(const PassArgs& a, State& st, char* raw) {
   RrLdsPcg& L = *reinterpret_cast<RrLdsPcg*>(raw);
@@ -1328,6 +1425,8 @@ __device__ __forceinline__ void rr_solve_pcg(const PassArgs& a, State& st, char*
   Sc sc;
   int par = 0;
   double sum[2] = {0.0, 0.0};
+  rr_clear_edge0(L.x[0]);
+  rr_clear_edge0(L.x[1]);
   {
     RrVec x;
     rr_load(a.x, s, x);
@@ -1339,15 +1438,13 @@ __device__ __forceinline__ void rr_solve_pcg(const PassArgs& a, State& st, char*
     transition<K_INIT_R>(st, sum, sc);
     RrVec b;
     rr_load(a.b, s, b);
-    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
+    const auto h = rr_halo(s, L.x[par], nullptr, RrId());
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < kRrRows; ++e) {
       r[e] = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
-      if (e < s.nv) {
-        acc[0] = fma(r[e], r[e], acc[0]);
-        acc[1] = fma(b[e], b[e], acc[1]);
-      }
+      acc[0] = fma(r[e], r[e], acc[0]);
+      acc[1] = fma(b[e], b[e], acc[1]);
     }
     par ^= 1;
     rr_publish(r, s, L.x[par]);
@@ -1357,77 +1454,82 @@ __device__ __forceinline__ void rr_solve_pcg(const PassArgs& a, State& st, char*
   rr_read_sums<2>(s, L.tot[par], sum);
   if (transition<K_INIT_W>(st, sum, sc)) {
     // w = A r; slots (r,r), (w,r)
-    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
+    const auto h = rr_halo(s, L.x[par], nullptr, RrId());
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < kRrRows; ++e) {
       w[e] = rr_st5(r, e > 0 ? r[e - 1] : 0.0, s, h, e);
-      if (e < s.nv) {
-        acc[0] = fma(r[e], r[e], acc[0]);
-        acc[1] = fma(w[e], r[e], acc[1]);
-      }
-      p[e] = q[e] = z[e] = 0.0;
+      acc[0] = fma(r[e], r[e], acc[0]);
+      acc[1] = fma(w[e], r[e], acc[1]);
     }
     par ^= 1;
     rr_publish(w, s, L.x[par]);
     rr_publish_sums<2>(acc, s, L.tot[par]);
     __syncthreads();
-    for (;;) {
-      rr_read_sums<2>(s, L.tot[par], sum);
-      if (!transition<K_PCG>(st, sum, sc)) break;
-      rr_uniform(st, sc);
-      const double al = sc.al, be = sc.be, nal = -sc.al;
-      const bool first = sc.first;
-      const RrHalo h2 = rr_halo(s, L.x[par], nullptr, RrId());
-      double ac[2] = {0.0, 0.0};
-      double wprev = 0.0;  // w[e-1] of this iteration (w is updated in place)
-#pragma unroll
-      for (int e = 0; e < kRrRows; ++e) {
-        const double nv = rr_st5(w, wprev, s, h2, e);
-        wprev = w[e];
-        // selects rather than branches: both forms are computed
-        const double zf = fma(be, z[e], nv), qf = fma(be, q[e], w[e]), pf = fma(be, p[e], r[e]);
-        z[e] = first ? nv : zf;
-        q[e] = first ? w[e] : qf;
-        p[e] = first ? r[e] : pf;
-        L.xs[e][s.t] = fma(al, p[e], L.xs[e][s.t]);
-        r[e] = fma(nal, q[e], r[e]);
-        const bool in = e < s.nv;
-        w[e] = in ? fma(nal, z[e], w[e]) : 0.0;
-        const double a0 = fma(r[e], r[e], ac[0]), a1 = fma(w[e], r[e], ac[1]);
-        ac[0] = in ? a0 : ac[0];
-        ac[1] = in ? a1 : ac[1];
-      }
-      par ^= 1;
-      rr_publish(w, s, L.x[par]);
-      rr_publish_sums<2>(ac, s, L.tot[par]);
-      __syncthreads();
-    }
+    bool go = rr_pcg_pass<true>(s, L, par, st, r, w, p, q, z);
+    while (go) go = rr_pcg_pass<false>(s, L, par, st, r, w, p, q, z);
   }
   RrVec x;
 #pragma unroll
-  for (int e = 0; e < kRrRows; ++e) x[e] = e < s.nv ? L.xs[e][s.t] : 0.0;
+  for (int e = 0; e < kRrRows; ++e) x[e] = L.xs[e][s.t];
   if (st.status != ST_ZERO_RHS) {
-    // true residual of the final iterate: slots (t,t), (b,b)
     par ^= 1;
-    rr_publish(x, s, L.x[par]);
-    __syncthreads();
-    RrVec b;
-    rr_load(a.b, s, b);
-    const RrHalo h = rr_halo(s, L.x[par], nullptr, RrId());
-    double acc[1] = {0.0};
-#pragma unroll
-    for (int e = 0; e < kRrRows; ++e) {
-      const double t = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
-      if (e < s.nv) acc[0] = fma(t, t, acc[0]);
-    }
-    par ^= 1;
-    rr_publish_sums<1>(acc, s, L.tot[par]);
-    __syncthreads();
-    rr_read_sums<1>(s, L.tot[par], sum);
-    st.res2 = sum[0];
+    rr_final_residual(a, s, st, x, L.x[par], L.tot[par ^ 1]);
   }
   rr_store(a.x, s, x);
+}
+
+// Algorithm 1, first pass of an iteration (the K_CG1 pass): beta; p = r +
+// beta p, also on the halo; s = A p; slot (p, s).  FIRST: p = r.
+template <bool FIRST>
+__device__ __forceinline__ bool rr_cg1_pass(const RrSeg& s, RrLdsCg& L, int& par, State& st,
+                                            const RrVec& r, RrVec& p, RrVec& sv) {
+  double sum[2];
+  Sc sc;
+  if (st.flags & F_BB_PENDING) rr_read_sums<2>(s, L.tot[par], sum);
+  else rr_read_sums<1>(s, L.tot[par], sum);
+  if (!transition<K_CG1>(st, sum, sc)) return false;
+  rr_uniform(st, sc);
+  const RrDir dir{sc.be, FIRST};
+  const auto h = rr_halo(s, L.x[par][0], &L.x[par][1], dir);
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) p[e] = dir(r[e], p[e]);
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) {
+    sv[e] = rr_st5(p, e > 0 ? p[e - 1] : 0.0, s, h, e);
+    acc[0] = fma(p[e], sv[e], acc[0]);
+  }
+  par ^= 1;
+  rr_publish_sums<1>(acc, s, L.tot[par]);
+  __syncthreads();
+  return true;
+}
+
+// Algorithm 1, second pass (the K_CG2 pass): alpha; x += alpha p;
+// r -= alpha s; slot (r, r).
+__device__ __forceinline__ bool rr_cg2_pass(const RrSeg& s, RrLdsCg& L, int& par, State& st,
+                                            RrVec& x, RrVec& r, const RrVec& p,
+                                            const RrVec& sv) {
+  double sum[1];
+  Sc sc;
+  rr_read_sums<1>(s, L.tot[par], sum);
+  if (!transition<K_CG2>(st, sum, sc)) return false;
+  rr_uniform(st, sc);
+  const double al = sc.al, nal = -sc.al;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < kRrRows; ++e) {
+    x[e] = fma(al, p[e], x[e]);
+    r[e] = fma(nal, sv[e], r[e]);
+    acc[0] = fma(r[e], r[e], acc[0]);
+  }
+  par ^= 1;
+  rr_publish(r, s, L.x[par][0]);
+  rr_publish(p, s, L.x[par][1]);
+  rr_publish_sums<1>(acc, s, L.tot[par]);
+  __syncthreads();
+  return true;
 }
 
 // Classic CG (Algorithm 1) on one grid, every vector in registers.
@@ -1438,6 +1540,10 @@ __device__ __forceinline__ void rr_solve_cg(const PassArgs& a, State& st, char* 
   Sc sc;
   int par = 0;
   double sum[2] = {0.0, 0.0};
+  rr_clear_edge0(L.x[0][0]);
+  rr_clear_edge0(L.x[0][1]);
+  rr_clear_edge0(L.x[1][0]);
+  rr_clear_edge0(L.x[1][1]);
   rr_load(a.x, s, x);
   rr_publish(x, s, L.x[par][0]);
   __syncthreads();
@@ -1446,15 +1552,13 @@ __device__ __forceinline__ void rr_solve_cg(const PassArgs& a, State& st, char* 
     transition<K_INIT_R>(st, sum, sc);
     RrVec b;
     rr_load(a.b, s, b);
-    const RrHalo h = rr_halo(s, L.x[par][0], nullptr, RrId());
+    const auto h = rr_halo(s, L.x[par][0], nullptr, RrId());
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < kRrRows; ++e) {
       r[e] = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
-      if (e < s.nv) {
-        acc[0] = fma(r[e], r[e], acc[0]);
-        acc[1] = fma(b[e], b[e], acc[1]);
-      }
+      acc[0] = fma(r[e], r[e], acc[0]);
+      acc[1] = fma(b[e], b[e], acc[1]);
       p[e] = 0.0;
     }
     par ^= 1;
@@ -1463,64 +1567,12 @@ __device__ __forceinline__ void rr_solve_cg(const PassArgs& a, State& st, char* 
     rr_publish_sums<2>(acc, s, L.tot[par]);
     __syncthreads();
   }
-  for (;;) {
-    // pass 1: beta; p = r + beta p (also on the halo); s = A p; slot (p, s)
-    if (st.flags & F_BB_PENDING) rr_read_sums<2>(s, L.tot[par], sum);
-    else rr_read_sums<1>(s, L.tot[par], sum);
-    if (!transition<K_CG1>(st, sum, sc)) break;
-    rr_uniform(st, sc);
-    const double be = sc.be;
-    const bool first = sc.first;
-    const RrDir dir{be, first};
-    const RrHalo h = rr_halo(s, L.x[par][0], &L.x[par][1], dir);
-    double acc[1] = {0.0};
-#pragma unroll
-    for (int e = 0; e < kRrRows; ++e) p[e] = e < s.nv ? dir(r[e], p[e]) : 0.0;
-#pragma unroll
-    for (int e = 0; e < kRrRows; ++e) {
-      sv[e] = rr_st5(p, e > 0 ? p[e - 1] : 0.0, s, h, e);
-      const double a0 = fma(p[e], sv[e], acc[0]);
-      acc[0] = e < s.nv ? a0 : acc[0];
-    }
-    par ^= 1;
-    rr_publish_sums<1>(acc, s, L.tot[par]);
-    __syncthreads();
-    // pass 2: alpha; x += alpha p; r -= alpha s; slot (r, r)
-    rr_read_sums<1>(s, L.tot[par], sum);
-    if (!transition<K_CG2>(st, sum, sc)) break;
-    rr_uniform(st, sc);
-    const double al = sc.al, nal = -sc.al;
-    double ac2[1] = {0.0};
-#pragma unroll
-    for (int e = 0; e < kRrRows; ++e) {
-      x[e] = fma(al, p[e], x[e]);
-      r[e] = fma(nal, sv[e], r[e]);
-      if (e < s.nv) ac2[0] = fma(r[e], r[e], ac2[0]);
-    }
-    par ^= 1;
-    rr_publish(r, s, L.x[par][0]);
-    rr_publish(p, s, L.x[par][1]);
-    rr_publish_sums<1>(ac2, s, L.tot[par]);
-    __syncthreads();
-  }
+  bool go = rr_cg1_pass<true>(s, L, par, st, r, p, sv) && rr_cg2_pass(s, L, par, st, x, r, p, sv);
+  while (go)
+    go = rr_cg1_pass<false>(s, L, par, st, r, p, sv) && rr_cg2_pass(s, L, par, st, x, r, p, sv);
   if (st.status != ST_ZERO_RHS) {
     par ^= 1;
-    rr_publish(x, s, L.x[par][0]);
-    __syncthreads();
-    RrVec b;
-    rr_load(a.b, s, b);
-    const RrHalo h = rr_halo(s, L.x[par][0], nullptr, RrId());
-    double acc[1] = {0.0};
-#pragma unroll
-    for (int e = 0; e < kRrRows; ++e) {
-      const double t = b[e] - rr_st5(x, e > 0 ? x[e - 1] : 0.0, s, h, e);
-      if (e < s.nv) acc[0] = fma(t, t, acc[0]);
-    }
-    par ^= 1;
-    rr_publish_sums<1>(acc, s, L.tot[par]);
-    __syncthreads();
-    rr_read_sums<1>(s, L.tot[par], sum);
-    st.res2 = sum[0];
+    rr_final_residual(a, s, st, x, L.x[par][0], L.tot[par ^ 1]);
   }
   rr_store(a.x, s, x);
 }
@@ -1734,42 +1786,72 @@ int step_max_blocks_per_cu() {
 // lane access, grid-stride): the attainable bandwidth of a read/write mix,
 // and the copy kernel of known size that calibrates the traffic counters.
 // pattern 0: read 1; 1: copy (1R 1W); 2: 2R 1W; 3: 3R 2W; 4: 6R 6W in place.
-__global__ __launch_bounds__(256) void k_stream(int pattern, double2* v0, double2* v1,
-                                                double2* v2, double2* v3, double2* v4,
-                                                double2* v5, size_t n2, double* sink) {
+struct StreamArgs {
+  double2* v[12];
+  size_t n2;
+  double* sink;
+};
+
+__device__ __forceinline__ void st_nt(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
+template <int PATTERN>
+__global__ __launch_bounds__(256) void k_stream(StreamArgs s) {
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+  double2* const* v = s.v;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n2;
        i += (size_t)gridDim.x * blockDim.x) {
-    if (pattern == 0) {
-      const double2 a = v0[i];
+    if constexpr (PATTERN == 0) {
+      const double2 a = v[0][i];
       acc += a.x + a.y;
-    } else if (pattern == 1) {
-      v1[i] = v0[i];
-    } else if (pattern == 2) {
-      const double2 a = v0[i], b = v1[i];
-      v2[i] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
-    } else if (pattern == 3) {
-      const double2 a = v0[i], b = v1[i], c = v2[i];
-      v3[i] = make_double2(a.x + b.x, a.y + b.y);
-      v4[i] = make_double2(b.x - c.x, b.y - c.y);
+    } else if constexpr (PATTERN == 1) {
+      v[1][i] = v[0][i];
+    } else if constexpr (PATTERN == 2) {
+      const double2 a = v[0][i], b = v[1][i];
+      v[2][i] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
+    } else if constexpr (PATTERN == 3) {
+      const double2 a = v[0][i], b = v[1][i], c = v[2][i];
+      v[3][i] = make_double2(a.x + b.x, a.y + b.y);
+      v[4][i] = make_double2(b.x - c.x, b.y - c.y);
     } else {
-      const double2 a = v0[i], b = v1[i], c = v2[i], d = v3[i], e = v4[i], f = v5[i];
-      v0[i] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
-      v1[i] = make_double2(b.x - 0.25 * c.x, b.y - 0.25 * c.y);
-      v2[i] = make_double2(c.x + d.x, c.y + d.y);
-      v3[i] = make_double2(d.x * 0.75, d.y * 0.75);
-      v4[i] = make_double2(e.x + f.x, e.y + f.y);
-      v5[i] = make_double2(f.x - a.x, f.y - a.y);
+      // six vectors in; six out: in place (4), to six other vectors (5), or
+      // in place with non-temporal stores (6)
+      const double2 a = v[0][i], b = v[1][i], c = v[2][i], d = v[3][i], e = v[4][i], f = v[5][i];
+      const double2 o[6] = {make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y),
+                            make_double2(b.x - 0.25 * c.x, b.y - 0.25 * c.y),
+                            make_double2(c.x + d.x, c.y + d.y),
+                            make_double2(d.x * 0.75, d.y * 0.75),
+                            make_double2(e.x + f.x, e.y + f.y),
+                            make_double2(f.x - a.x, f.y - a.y)};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if constexpr (PATTERN == 5) v[6 + k][i] = o[k];
+        else if constexpr (PATTERN == 6) st_nt(v[k] + i, o[k]);
+        else v[k][i] = o[k];
+      }
     }
   }
-  if (pattern == 0 && acc == 1.2345678e300) sink[0] = acc;  // keeps the reads alive
+  if (PATTERN == 0 && acc == 1.2345678e300) s.sink[0] = acc;  // keeps the reads alive
 }
 
 hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_stream, dim3(grid), dim3(256), 0, st, pattern, (double2*)v[0],
-                     (double2*)v[1], (double2*)v[2], (double2*)v[3], (double2*)v[4],
-                     (double2*)v[5], n / 2, sink);
+  StreamArgs s;
+  for (int k = 0; k < 12; ++k) s.v[k] = (double2*)v[k];
+  s.n2 = n / 2;
+  s.sink = sink;
+  switch (pattern) {
+    case 0: hipLaunchKernelGGL(k_stream<0>, dim3(grid), dim3(256), 0, st, s); break;
+    case 1: hipLaunchKernelGGL(k_stream<1>, dim3(grid), dim3(256), 0, st, s); break;
+    case 2: hipLaunchKernelGGL(k_stream<2>, dim3(grid), dim3(256), 0, st, s); break;
+    case 3: hipLaunchKernelGGL(k_stream<3>, dim3(grid), dim3(256), 0, st, s); break;
+    case 4: hipLaunchKernelGGL(k_stream<4>, dim3(grid), dim3(256), 0, st, s); break;
+    case 5: hipLaunchKernelGGL(k_stream<5>, dim3(grid), dim3(256), 0, st, s); break;
+    case 6: hipLaunchKernelGGL(k_stream<6>, dim3(grid), dim3(256), 0, st, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1830,7 +1912,7 @@ hipError_t launch_solve_rr_many(const Slot* slots, const int* idx, int n, hipStr
 }
 
 hipError_t launch_solve_rr(int variant, const PassArgs& a, int threads, hipStream_t st) {
-  const int64_t need = (int64_t)a.g.nx * ((a.g.ny + kRrRows - 1) / kRrRows);
+  const int64_t need = (int64_t)(a.g.nx + 1) * ((a.g.ny + kRrRows - 1) / kRrRows);
   if (threads < kWave || threads > kRrThreads || threads % kWave || need > threads)
     return hipErrorInvalidValue;
   if (variant == 1) hipLaunchKernelGGL((k_solve_rr<1>), dim3(1), dim3(threads), 0, st, a);

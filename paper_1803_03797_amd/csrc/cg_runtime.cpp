@@ -142,8 +142,10 @@ bool Ctx::use_wg(const cg_problem* p) const {
   return p->precision == CG_PREC_FP64 && (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
+// threads of the register-resident solver: rows of nx + 1 (one idle thread
+// per row of segments) times the segments per column
 static int64_t rr_threads_needed(int nx, int ny) {
-  return (int64_t)nx * ((ny + kRrRows - 1) / kRrRows);
+  return (int64_t)(nx + 1) * ((ny + kRrRows - 1) / kRrRows);
 }
 
 bool Ctx::use_rr(const cg_problem* p) const {
@@ -713,9 +715,9 @@ int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u
 
 int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, double* bytes) {
   Ctx& c = *this;
-  static const int nv[] = {1, 2, 3, 5, 6};
-  static const int moved[] = {1, 2, 3, 5, 12};
-  if (pattern < 0 || pattern > 4 || elems < 2 || reps < 1) return CG_E_INVALID;
+  static const int nv[] = {1, 2, 3, 5, 6, 12, 6};
+  static const int moved[] = {1, 2, 3, 5, 12, 12, 12};
+  if (pattern < 0 || pattern > 6 || elems < 2 || reps < 1) return CG_E_INVALID;
   elems &= ~(size_t)1;
   const size_t vb = round_up(elems * 8, Arena::kAlign);
   char* m = (char*)arena.alloc(nv[pattern] * vb + 256);
@@ -725,21 +727,24 @@ int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, doub
     char* m;
     ~Rel() { a.release(m); }
   } rel{arena, m};
-  double* v[6];
-  for (int k = 0; k < 6; ++k) v[k] = (double*)(m + (k < nv[pattern] ? k : 0) * vb);
+  double* v[12];
+  for (int k = 0; k < 12; ++k) v[k] = (double*)(m + (k < nv[pattern] ? k : 0) * vb);
   double* sink = (double*)(m + nv[pattern] * vb);
   HIPCHK(launch_fill(m, nv[pattern] * vb + 256, st));
-  const int grid = 8 * num_cu;
   hipEvent_t e0 = event(), e1 = event();
   double best = 1e30;
-  for (int r = 0; r < reps + 1; ++r) {
-    HIPCHK(hipEventRecord(e0, st));
-    HIPCHK(launch_stream(pattern, v, elems, sink, grid, st));
-    HIPCHK(hipEventRecord(e1, st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (r > 0) best = std::min(best, ms * 1e-3);  // the first launch warms up
+  // best over grids of 1, 2, 4 and 8 work-groups per CU
+  for (int gpc = 1; gpc <= 8; gpc *= 2) {
+    const int grid = gpc * num_cu;
+    for (int r = 0; r < reps + 1; ++r) {
+      HIPCHK(hipEventRecord(e0, st));
+      HIPCHK(launch_stream(pattern, v, elems, sink, grid, st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (r > 0) best = std::min(best, ms * 1e-3);  // the first launch warms up
+    }
   }
   ev_free.push_back(e0);
   ev_free.push_back(e1);

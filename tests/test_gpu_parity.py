@@ -43,7 +43,7 @@ def order_of(ctx, nx, ny, variant=0):
     """The reduction order a solve of this shape uses, and the plan."""
     info = ctx.cg_plan(nx, ny, variant)
     if info.path == 2:
-        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves), info
+        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols), info
     return tile_order(info), info
 
 

@@ -28,7 +28,7 @@ def torch():
 def order_of(ctx, nx, ny, variant=0, precision=0):
     info = ctx.cg_plan(nx, ny, variant, precision)
     if info.path == 2:
-        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves), info
+        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols), info
     return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2), info
 
 
@@ -106,12 +106,12 @@ def test_profiling_statistics(torch):
 
 def test_stream_probe():
     with cg.Context(device=0, arena_bytes=2 << 30) as ctx:
-        for pat, moved in ((0, 1), (1, 2), (2, 3), (3, 5), (4, 12)):
+        for pat, moved in ((0, 1), (1, 2), (2, 3), (3, 5), (4, 12), (5, 12), (6, 12)):
             t, nbytes = ctx.cg_stream_probe(pat, 1 << 22, 2)
             assert nbytes == moved * (1 << 22) * 8 and t > 0
             say("probe", pat, "%.0f GB/s" % (nbytes / t / 1e9))
         with pytest.raises(cg.CGError):
-            ctx.cg_stream_probe(5, 1 << 20, 1)
+            ctx.cg_stream_probe(7, 1 << 20, 1)
 
 
 def test_caller_arena_and_stream(torch):

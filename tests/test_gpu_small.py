@@ -18,11 +18,11 @@ pytestmark = pytest.mark.gpu
 
 VARIANTS = (cg.CG_VARIANT_CLASSIC, cg.CG_VARIANT_PIPELINED)
 
-# shapes the solver takes: nx * ceil(ny / rows) <= threads; single rows and
-# columns, one segment, ragged last segments, exactly full, a column of 512
-# segments, the 100 x 100 workload
-SHAPES = [(1, 1), (1, 20), (1, 21), (20, 1), (3, 5), (64, 20), (65, 21), (90, 70), (100, 100),
-          (512, 20), (7, 1460), (1, 10240), (33, 300)]
+# shapes the solver takes: (nx + 1) * ceil(ny / rows) <= threads; single rows
+# and columns, one segment, ragged last segments, exactly full, a column of
+# 256 segments, the 100 x 100 workload
+SHAPES = [(1, 1), (1, 20), (1, 21), (20, 1), (3, 5), (63, 20), (64, 21), (90, 70), (100, 100),
+          (511, 20), (7, 1260), (1, 5120), (33, 300), (127, 80)]
 
 
 def say(*a):
@@ -46,8 +46,9 @@ def ctx(torch):
 def seg_order(ctx, nx, ny, variant):
     info = ctx.cg_plan(nx, ny, variant)
     assert info.path == 2, (nx, ny, info.path)
-    assert info.seg_waves * info.lanes >= nx * -(-ny // info.seg_rows)
-    return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves)
+    assert info.seg_cols == nx + 1
+    assert info.seg_waves * info.lanes >= info.seg_cols * -(-ny // info.seg_rows)
+    return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols)
 
 
 def rel(a, b):
@@ -74,7 +75,7 @@ def test_lockstep_bitwise(ctx, nx, ny, variant):
         assert res.rel_res_true == ro.rel_res_true
 
 
-@pytest.mark.parametrize("nx,ny", [(100, 100), (90, 70), (7, 1460), (512, 20), (33, 300)])
+@pytest.mark.parametrize("nx,ny", [(100, 100), (90, 70), (7, 1260), (511, 20), (33, 300)])
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_natural_stop(ctx, nx, ny, variant):
     rng = np.random.default_rng(500 + nx + ny)
@@ -106,7 +107,7 @@ def test_small_workload_against_tile_path(variant, torch):
             with cg.Context(device=0, arena_bytes=256 << 20) as c:
                 info = c.cg_plan(nx, ny, variant)
                 assert info.path == (2 if rr == "1" else 1)
-                o = (oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves)
+                o = (oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols)
                      if info.path == 2 else
                      oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows,
                                   info.threads2))
@@ -158,7 +159,7 @@ def test_edge_cases(ctx, variant):
 
 
 def test_shapes_outside_the_solver_take_tiles(ctx):
-    for nx, ny in ((513, 20), (100, 103), (1, 10241)):
+    for nx, ny in ((512, 20), (100, 103), (1, 5121), (127, 81)):
         info = ctx.cg_plan(nx, ny)
         assert info.path != 2 and info.seg_rows == 0 and info.seg_waves == 0
     assert ctx.cg_plan(100, 100, precision=cg.CG_PREC_FP32_REFINED).path == 0
@@ -168,8 +169,8 @@ def test_batch_of_small_solves_bitwise_alone(ctx):
     """Small solves in a batch run one work-group each beside the step
     engine's solves; every result equals the solve alone bitwise."""
     rng = np.random.default_rng(77)
-    shapes = [(100, 100), (32, 32), (300, 200), (90, 70), (7, 1460), (200, 150), (1, 1),
-              (64, 20)]
+    shapes = [(100, 100), (32, 32), (300, 200), (90, 70), (7, 1260), (200, 150), (1, 1),
+              (63, 20)]
     probs, xs, bs = [], [], []
     for k, (nx, ny) in enumerate(shapes):
         b = rng.uniform(-1, 1, (ny, nx))
