@@ -7,17 +7,19 @@ one with the pipelined CG (Algorithm 2), each running a fixed 500 iterations
 (seeded), x0 = 0, FP64.  Inputs are resident in HBM before the timed region.
 value = unknowns x iterations per second over the whole step (GDOF-iter/s).
 
-  roofline      the dominant kernel (pcg_pass): algorithmic bytes (96 B per
-                unknown) / its average launch duration, from HIP events
-                recorded around each launch on the library's stream while the
-                same steps are repeated with profiling on; vs 8 TB/s.
+  roofline      the dominant kernel (pcg_pass, the pipelined pass of an even
+                iteration, which also brings x up to date): algorithmic bytes
+                (96 B per unknown) / its average launch duration, from HIP
+                events recorded around each launch on the library's stream
+                while the same steps are repeated with profiling on; vs
+                8 TB/s.  Odd iterations run pcg_pass_nx (80 B, x untouched).
   cpu_baseline  the CPU oracle (plain C, explicit CSR, one thread) on a
                 bounded sample of the same workload.
 
 Other workloads (one JSON line each, not the headline):
   --workload small   100 x 100, both variants, tol 1e-8: solve latency
-  --workload batch   256 uneven grids, pipelined, one persistent launch vs
-                     one-by-one solves
+  --workload batch   256 uneven grids, pipelined, all on the device at once
+                     (multi-solve step kernel) vs one-by-one solves
   --workload huge    8192 x 8192: FP32-inner / FP64-outer refinement vs FP64
                      CG, both to a true residual of 1e-10
   --workload serve   request stream with Poisson arrivals: served
@@ -37,12 +39,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-BYTES_PER_DOF = {"pcg_pass": 96, "stencil_dot": 24, "update_norm": 40}
+BYTES_PER_DOF = {"pcg_pass": 96, "pcg_pass_nx": 80, "stencil_dot": 24, "update_norm": 48,
+                 "update_norm_nx": 24}
+# algorithmic bytes per unknown and iteration, averaged over an odd/even pair
+BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
 # HBM bytes per pcg_pass launch at 4096 x 4096 from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors the library's 134 MB
 # copy kernel gives for the same counters); set to None whenever pcg_pass
 # changes, until the counters are taken again.
-PCG_TRAFFIC_BYTES = 1641154582
+PCG_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -180,8 +185,8 @@ def headline(args):
             "classic": round(dof * args.iters * args.steps / per_variant[0] / 1e9, 3),
             "pipelined": round(dof * args.iters * args.steps / per_variant[1] / 1e9, 3)},
         "algorithmic_GBps": {
-            "classic": round(64 * dof * args.iters * args.steps / per_variant[0] / 1e9, 1),
-            "pipelined": round(96 * dof * args.iters * args.steps / per_variant[1] / 1e9, 1)},
+            v: round(BYTES_PER_ITER[v] * dof * args.iters * args.steps / per_variant[i] / 1e9, 1)
+            for i, v in enumerate(("classic", "pipelined"))},
         "roofline": roof,
         "kernels": kern,
         "profiled_ms_per_step": round(prof_elapsed / args.steps * 1e3, 3),
@@ -313,7 +318,8 @@ def bench_batch(args):
           "dtype": "f64",
           "batched": {"seconds": round(tb, 4), "solves_per_s": round(len(shapes) / tb, 2),
                       "GDOF_iter_s": round(work / tb / 1e9, 3),
-                      "algorithmic_GBps": round(96 * work / tb / 1e9, 1)},
+                      "algorithmic_GBps": round(BYTES_PER_ITER["pipelined"] * work / tb / 1e9,
+                                                1)},
           "one_by_one": {"seconds": round(ts, 4), "solves_per_s": round(len(shapes) / ts, 2),
                          "GDOF_iter_s": round(work / ts / 1e9, 3)},
           "speedup": round(ts / tb, 3), "status": cg.cg_status_str(rc),

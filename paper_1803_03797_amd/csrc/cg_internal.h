@@ -86,8 +86,17 @@ enum : int32_t {
   K_REF_UPDATE,   // x += s * d
   K_APPLY,        // y = A u
   K_DOT,          // slot (u, y)
+  K_PCGX,         // K_PCG of an even iteration: also applies both x updates
+  K_CG2X,         // K_CG2 of an even iteration: also applies both x updates
   K_NKINDS
 };
+
+// Deferred x (FP64 classic and pipelined).  x is read and written only by
+// the passes that end an even iteration: such a pass applies the previous
+// (odd) iteration's update and then its own, x = fma(a_i, p_i,
+// fma(a_(i-1), p_(i-1), x)), the same operations in the same order as one
+// update per iteration.  A solve that stops after an odd iteration gets the
+// pending update from the pass that stops it.
 
 // Everything a pass may touch.  Unused pointers are null.
 struct PassArgs {
@@ -106,6 +115,7 @@ struct PassArgs {
   double* p;               // pipelined p
   const double* pc_in;     // classic: previous direction (read with halo)
   double* pc_out;          //          new direction
+  const double* pc_prev;   //          pass 2: the direction before pc_in
   float* rf;               // refinement: inner residual rho / r_in
   float* df;               //             inner solution d
   const float* pf_in;      //             inner direction ping-pong
@@ -118,8 +128,9 @@ struct PassArgs {
 struct Sc {
   double al, be;
   int32_t first;   // first iteration: previous direction vectors are zero
-  int32_t pad_;
+  int32_t xu;      // this pass ends an even iteration: apply both x updates
   double inv;      // refinement: 1 / scale
+  double alp;      // alpha of the pending x update (previous iteration)
 };
 
 // One resident solve of the multi-solve step kernel (batch and serving),

@@ -253,9 +253,14 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
   sc.al = 0.0;
   sc.be = 0.0;
   sc.first = 0;
-  sc.pad_ = 0;
+  sc.xu = 0;
   sc.inv = 0.0;
-  if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
+  sc.alp = 0.0;
+  if constexpr (KIND == K_PCGX) {
+    return transition<K_PCG>(s, sum, sc);
+  } else if constexpr (KIND == K_CG2X) {
+    return transition<K_CG2>(s, sum, sc);
+  } else if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
     return true;
   } else if constexpr (KIND == K_INIT_R) {
     return s.status == ST_RUNNING;
@@ -401,18 +406,51 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
 
 template <int KIND>
 constexpr int ndots_in() {  // partial slots the prologue consumes
-  return (KIND == K_PCG || KIND == K_INIT_W || KIND == K_CG1 || KIND == K_REF_SCALE) ? 2
-         : (KIND == K_CG2 || KIND == K_CG1F || KIND == K_CG2F)                      ? 1
-                                                                                     : 0;
+  return (KIND == K_PCG || KIND == K_PCGX || KIND == K_INIT_W || KIND == K_CG1 ||
+          KIND == K_REF_SCALE)
+             ? 2
+         : (KIND == K_CG2 || KIND == K_CG2X || KIND == K_CG1F || KIND == K_CG2F) ? 1
+                                                                                  : 0;
 }
 
 template <int KIND>
 constexpr int ndots_out() {  // partial slots the body produces
-  return (KIND == K_INIT_R || KIND == K_INIT_W || KIND == K_PCG || KIND == K_RESID) ? 2
-         : (KIND == K_CG1 || KIND == K_CG2 || KIND == K_REF_SCALE || KIND == K_CG1F ||
-            KIND == K_CG2F || KIND == K_DOT)
+  return (KIND == K_INIT_R || KIND == K_INIT_W || KIND == K_PCG || KIND == K_PCGX ||
+          KIND == K_RESID)
+             ? 2
+         : (KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X || KIND == K_REF_SCALE ||
+            KIND == K_CG1F || KIND == K_CG2F || KIND == K_DOT)
              ? 1
              : 0;
+}
+
+// The passes of FP64 CG whose x update is deferred (see cg_internal.h).
+template <int KIND>
+constexpr bool defers_x() {
+  return KIND == K_PCG || KIND == K_PCGX || KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X;
+}
+
+// transition<KIND> plus the deferred-x bookkeeping: sc.xu when this pass ends
+// an even iteration (sc.alp = the previous iteration's alpha), and `flush`
+// when this pass stops a running solve whose last iteration was odd (then
+// sc.alp = that iteration's alpha, whose update is still pending).
+template <int KIND>
+__device__ __forceinline__ bool transition_x(State& s, const double* sum, Sc& sc, bool& flush) {
+  const bool was_running = s.status == ST_RUNNING;
+  const double alpha_before = s.alpha;
+  const bool run = transition<KIND>(s, sum, sc);
+  flush = false;
+  if constexpr (defers_x<KIND>()) {
+    if (run && KIND != K_CG1 && !(s.k & 1)) {
+      sc.xu = 1;
+      sc.alp = alpha_before;
+    }
+    if (was_running && s.status != ST_RUNNING && (s.k & 1)) {
+      flush = true;
+      sc.alp = s.alpha;
+    }
+  }
+  return run;
 }
 
 // ------------------------------------------------------------- reductions --
@@ -706,12 +744,12 @@ struct PcgRow {
   Row<double, CPL> x, r, z, q, p;
 };
 
-template <int CPL>
+template <int CPL, bool XU>
 __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
   const Strip s = strip_of<CPL>(g, t);
-  const double al = sc.al, be = sc.be, nal = -sc.al;
+  const double al = sc.al, be = sc.be, nal = -sc.al, alp = sc.alp;
   const bool first = sc.first;
   double a0[CPL], a1[CPL];
 #pragma unroll
@@ -723,7 +761,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
       [=](size_t off) {
         PcgRow<CPL> v;
         const size_t oc = off + s.c;
-        v.x = ldrow<double, CPL>(X + oc);
+        if constexpr (XU) v.x = ldrow<double, CPL>(X + oc);
         v.r = ldrow<double, CPL>(Rv + oc);
         // z, q, p are ignored on the first iteration (taken as zero)
         v.z = ldrow<double, CPL>(Z + oc);
@@ -746,7 +784,9 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
             q.e[k] = fma(be, in.q.e[k], hC.e[k]);
             p.e[k] = fma(be, in.p.e[k], r.e[k]);
           }
-          x.e[k] = fma(al, p.e[k], x.e[k]);
+          // the previous iteration's update, then this one's (never on the
+          // first iteration, which is odd)
+          if constexpr (XU) x.e[k] = fma(al, p.e[k], fma(alp, in.p.e[k], x.e[k]));
           r.e[k] = fma(nal, q.e[k], r.e[k]);
           wo.e[k] = fma(nal, z.e[k], hC.e[k]);
           if (k < valid) {
@@ -758,7 +798,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
         strow<double, CPL>(Z + oc, z, valid);
         strow<double, CPL>(Q + oc, q, valid);
         strow<double, CPL>(Pp + oc, p, valid);
-        strow<double, CPL>(X + oc, x, valid);
+        if constexpr (XU) strow<double, CPL>(X + oc, x, valid);
         strow<double, CPL>(Rv + oc, r, valid);
         strow<double, CPL>(Wo + oc, wo, valid);
       });
@@ -834,22 +874,27 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
   lv[0] = fold<CPL>(a0);
 }
 
-// --- K_CG2 / K_CG2F: s = A p; x += alpha p; r -= alpha s; slot (r, r).
-template <typename T, int CPL>
+// --- K_CG2 / K_CG2X / K_CG2F: s = A p; x += alpha p; r -= alpha s; slot (r, r).
+// XM: 0 = x untouched (FP64, odd iteration), 1 = x += alpha p (the FP32 inner
+// solve's d), 2 = x += alpha_prev p_prev, then x += alpha p (FP64, even).
+template <typename T, int CPL, int XM>
 struct XrRow {
-  Row<T, CPL> x, r;
+  Row<T, CPL> x, r, pp;
 };
 
-template <typename T, int CPL>
+template <typename T, int CPL, int XM>
 __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<T, CPL>;
+  using In = XrRow<T, CPL, XM>;
   const Geo& g = a.g;
   const Strip s = strip_of<CPL>(g, t);
   const T* Pv;
+  const T* Pp = nullptr;
   T* Xv;
   T* Rv;
   if constexpr (sizeof(T) == 8) {
     Pv = a.pc_in;
+    Pp = a.pc_prev;
     Xv = a.x;
     Rv = a.r;
   } else {
@@ -857,7 +902,7 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
     Xv = a.df;
     Rv = a.rf;
   }
-  const T al = T(sc.al), nal = -al;
+  const T al = T(sc.al), nal = -al, alp = T(sc.alp);
   double a0[CPL];
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
@@ -865,25 +910,56 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
   walk_plain<T, CPL>(
       g, s, Pv,
       [=](size_t off) {
-        XrRow<T, CPL> v;
-        v.x = ldrow<T, CPL>(Xv + off + s.c);
+        In v;
+        if constexpr (XM != 0) v.x = ldrow<T, CPL>(Xv + off + s.c);
+        if constexpr (XM == 2) v.pp = ldrow<T, CPL>(Pp + off + s.c);
         v.r = ldrow<T, CPL>(Rv + off + s.c);
         return v;
       },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
-          const XrRow<T, CPL>& in) {
+          const In& in) {
         R x = in.x, r = in.r;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
           const T sv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
-          x.e[k] = fma(al, hC.e[k], x.e[k]);
+          if constexpr (XM == 1) x.e[k] = fma(al, hC.e[k], x.e[k]);
+          if constexpr (XM == 2) x.e[k] = fma(al, hC.e[k], fma(alp, in.pp.e[k], x.e[k]));
           r.e[k] = fma(nal, sv, r.e[k]);
           if (k < valid) a0[k] = fma((double)r.e[k], (double)r.e[k], a0[k]);
         }
-        strow<T, CPL>(Xv + off + s.c, x, valid);
+        if constexpr (XM != 0) strow<T, CPL>(Xv + off + s.c, x, valid);
         strow<T, CPL>(Rv + off + s.c, r, valid);
       });
   lv[0] = fold<CPL>(a0);
+}
+
+// --- pending x update of a stopped solve: x += alp * P on tile t.
+template <int CPL>
+__device__ __forceinline__ void body_flush(const PassArgs& a, int t, const double* P,
+                                           double alp) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const int valid = g.nx - s.c;
+  if (valid <= 0) return;
+  for (int j = s.j0; j < s.j1; ++j) {
+    const size_t o = (size_t)j * g.pitch + s.c;
+    const R pv = ldrow<double, CPL>(P + o);
+    R x = ldrow<double, CPL>(a.x + o);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x.e[k] = fma(alp, pv.e[k], x.e[k]);
+    strow<double, CPL>(a.x + o, x, valid);
+  }
+}
+
+// The vector whose pending x update a stopping pass of KIND applies: the
+// pipelined p, classic pass 1's incoming direction, classic pass 2's previous
+// direction.
+template <int KIND>
+__device__ __forceinline__ const double* flush_dir(const PassArgs& a) {
+  if constexpr (KIND == K_PCG || KIND == K_PCGX) return a.p;
+  else if constexpr (KIND == K_CG1) return a.pc_in;
+  else return a.pc_prev;
 }
 
 // --- K_REF_SCALE: rho = fp32((b - A x) * inv); d = 0; slot (rho, rho) in FP64.
@@ -942,13 +1018,30 @@ __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc,
   else if constexpr (KIND == K_INIT_W) body_apply<CPL, true>(a, t, lv);
   else if constexpr (KIND == K_APPLY) body_apply<CPL, false>(a, t, lv);
   else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
-  else if constexpr (KIND == K_PCG) body_pcg<CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_PCG) body_pcg<CPL, false>(a, t, sc, lv);
+  else if constexpr (KIND == K_PCGX) body_pcg<CPL, true>(a, t, sc, lv);
   else if constexpr (KIND == K_CG1) body_cg1<double, CPL>(a, t, sc, lv);
-  else if constexpr (KIND == K_CG2) body_cg2<double, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2) body_cg2<double, CPL, 0>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2X) body_cg2<double, CPL, 2>(a, t, sc, lv);
   else if constexpr (KIND == K_CG1F) body_cg1<float, CPL>(a, t, sc, lv);
-  else if constexpr (KIND == K_CG2F) body_cg2<float, CPL>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2F) body_cg2<float, CPL, 1>(a, t, sc, lv);
   else if constexpr (KIND == K_REF_SCALE) body_ref_scale<CPL>(a, t, sc, lv);
   else if constexpr (KIND == K_REF_UPDATE) body_ref_update<CPL>(a, t, sc);
+}
+
+// The body of KIND with the x variant the transition chose (for paths that
+// decide on the device: the single-work-group solver and the step kernel).
+template <int KIND, int CPL>
+__device__ __forceinline__ void run_body_any(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  if constexpr (KIND == K_PCG) {
+    if (sc.xu) run_body<K_PCGX, CPL>(a, t, sc, lv);
+    else run_body<K_PCG, CPL>(a, t, sc, lv);
+  } else if constexpr (KIND == K_CG2) {
+    if (sc.xu) run_body<K_CG2X, CPL>(a, t, sc, lv);
+    else run_body<K_CG2, CPL>(a, t, sc, lv);
+  } else {
+    run_body<KIND, CPL>(a, t, sc, lv);
+  }
 }
 
 // LDS per tile group: 4*2 doubles for the cross-tile stage, 2*4*2 for tiles.
@@ -966,9 +1059,9 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   constexpr int DI = ndots_in<KIND>(), DO = ndots_out<KIND>();
   Sc sc;
   if constexpr (KIND == K_APPLY || KIND == K_DOT) {
-    sc.al = sc.be = sc.inv = 0.0;
+    sc.al = sc.be = sc.inv = sc.alp = 0.0;
     sc.first = 0;
-    sc.pad_ = 0;
+    sc.xu = 0;
   } else {
     State s = load_state_uniform(a.st_in);
     double sum[2] = {0.0, 0.0};
@@ -981,8 +1074,20 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
       sum[0] = uniform(sum[0]);
       sum[1] = uniform(sum[1]);
     }
-    const bool run = transition<KIND>(s, sum, sc);
+    bool flush = false;
+    const bool run = transition_x<KIND>(s, sum, sc, flush);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
+    if constexpr (defers_x<KIND>()) {
+      if (flush) {
+        // this pass stopped the solve after an odd iteration: apply its update
+        const int G = gridDim.x, b = blockIdx.x;
+        const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+        const int T = a.g.tiles;
+        const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
+        for (int t = t0 + slot; t < t1; t += nb) body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
+        return;
+      }
+    }
     if (!run) return;
   }
 
@@ -1035,7 +1140,7 @@ __device__ __forceinline__ void wg_pass(const PassArgs& a, const Sc& sc, double*
   for (int i = 0, par = 0; i < iters; ++i, par ^= 1) {
     const int t = grp + kWgGroups * i;
     double lv[2] = {0.0, 0.0};
-    if (t < T) run_body<KIND, 2>(a, t, sc, lv);
+    if (t < T) run_body_any<KIND, 2>(a, t, sc, lv);
     if constexpr (DO > 0) {
       // groups past the end join the barrier but store nothing
       const int tid = threadIdx.x & (kGroup - 1), lane = tid & 63, wave = tid >> 6;
@@ -1069,7 +1174,15 @@ __device__ __forceinline__ bool wg_step(State& s, const PassArgs& a, Sc& sc, dou
     if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
     else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
   }
-  const bool run = transition<KIND>(s, sum, sc);
+  bool flush = false;
+  const bool run = transition_x<KIND>(s, sum, sc, flush);
+  if constexpr (defers_x<KIND>()) {
+    if (flush) {
+      const int grp = threadIdx.x >> 8;
+      for (int t = grp; t < a.g.tiles; t += kWgGroups) body_flush<2>(a, t, flush_dir<KIND>(a), sc.alp);
+      __syncthreads();  // x complete before the final residual reads it
+    }
+  }
   if (run) wg_pass<KIND>(a, sc, lds + 8);
   return run;
 }
@@ -1125,6 +1238,7 @@ __global__ __launch_bounds__(kWgGroups * kGroup) void k_solve_wg(PassArgs a0) {
       a.part_in = cur;
       a.part_out = nxt;
       a.pc_in = Po;
+      a.pc_prev = Pi;
       if (!wg_step<K_CG2>(s, a, sc, lds)) break;
       { double* t = cur; cur = nxt; nxt = t; }
       const double* tp = Pi; Pi = Po; Po = const_cast<double*>(tp);
@@ -1623,9 +1737,9 @@ __global__ __launch_bounds__(kRrThreads) void k_solve_rr_many(const Slot* slots,
 template <int KIND>
 __device__ __forceinline__ bool step_transition(State& s, const double* sum, Sc& sc) {
   if constexpr (KIND == K_FINAL) {
-    sc.al = sc.be = sc.inv = 0.0;
+    sc.al = sc.be = sc.inv = sc.alp = 0.0;
     sc.first = 0;
-    sc.pad_ = 0;
+    sc.xu = 0;
     s.res2 = sum[0];
     return false;
   } else {
@@ -1671,13 +1785,16 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   // ping-pong parities come from the iteration counters before the transition
   const int k0 = s.k, kin0 = s.kin;
   Sc sc;
-  const bool run = step_transition<KIND>(s, sum, sc);
+  bool flush = false;
+  bool run;
+  if constexpr (KIND == K_FINAL) run = step_transition<KIND>(s, sum, sc);
+  else run = transition_x<KIND>(s, sum, sc, flush);
   if (it.t0 == 0 && threadIdx.x == 0) {
     State o = s;
     o.kind = next_kind(KIND, run, s, S.variant, S.refined);
     *S.S[(m + 1) & 1] = o;
   }
-  if (!run) return;
+  if (!run && !flush) return;
   PassArgs a;
   a.g = S.g;
   a.st_in = nullptr;
@@ -1694,16 +1811,23 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.w_out = (KIND == K_INIT_W) ? S.W[0] : S.W[(k0 + 1) & 1];
   a.pc_in = (KIND == K_CG2) ? S.PC[(k0 + 1) & 1] : S.PC[k0 & 1];
   a.pc_out = S.PC[(k0 + 1) & 1];
+  a.pc_prev = S.PC[k0 & 1];
   a.rf = S.rf;
   a.df = S.df;
   a.pf_in = (KIND == K_CG2F) ? S.PF[(kin0 + 1) & 1] : S.PF[kin0 & 1];
   a.pf_out = S.PF[(kin0 + 1) & 1];
   a.u = nullptr;
   a.y = nullptr;
+  if constexpr (defers_x<KIND>()) {
+    if (flush) {
+      for (int t = it.t0; t < it.t1; ++t) body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
+      return;
+    }
+  }
   int par = 0;
   for (int t = it.t0; t < it.t1; ++t, par ^= 1) {
     double lv[2] = {0.0, 0.0};
-    run_body<KIND, CPL>(a, t, sc, lv);
+    run_body_any<KIND, CPL>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
 }
@@ -1870,8 +1994,10 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
     case K_INIT_R: return launch_kind<K_INIT_R>(fp32g, a, grid, st);
     case K_INIT_W: return launch_kind<K_INIT_W>(fp32g, a, grid, st);
     case K_PCG: return launch_kind<K_PCG>(fp32g, a, grid, st);
+    case K_PCGX: return launch_kind<K_PCGX>(fp32g, a, grid, st);
     case K_CG1: return launch_kind<K_CG1>(fp32g, a, grid, st);
     case K_CG2: return launch_kind<K_CG2>(fp32g, a, grid, st);
+    case K_CG2X: return launch_kind<K_CG2X>(fp32g, a, grid, st);
     case K_RESID: return launch_kind<K_RESID>(fp32g, a, grid, st);
     case K_APPLY: return launch_kind<K_APPLY>(fp32g, a, grid, st);
     case K_DOT: return launch_kind<K_DOT>(fp32g, a, grid, st);
@@ -1937,9 +2063,11 @@ static int occ() {
 
 int pass_max_blocks_per_cu(int kind, int fp32g) {
   switch (kind) {
-    case K_PCG: return fp32g ? occ<K_PCG, 4>() : occ<K_PCG, 2>();
+    case K_PCG:
+    case K_PCGX: return fp32g ? occ<K_PCGX, 4>() : occ<K_PCGX, 2>();
     case K_CG1: return fp32g ? occ<K_CG1, 4>() : occ<K_CG1, 2>();
-    case K_CG2: return fp32g ? occ<K_CG2, 4>() : occ<K_CG2, 2>();
+    case K_CG2:
+    case K_CG2X: return fp32g ? occ<K_CG2X, 4>() : occ<K_CG2X, 2>();
     case K_CG1F: return occ<K_CG1F, 4>();
     case K_CG2F: return occ<K_CG2F, 4>();
     default: return fp32g ? occ<K_RESID, 4>() : occ<K_RESID, 2>();
@@ -1953,9 +2081,11 @@ size_t pass_algorithmic_bytes(int kind, int64_t dof) {
   switch (kind) {
     case K_INIT_R: per = 8 * 3; break;          // read x, b; write r
     case K_INIT_W: per = 8 * 2; break;          // read r; write w
-    case K_PCG: per = 8 * 12; break;            // read x r w p q z; write x r w p q z
+    case K_PCG: per = 8 * 10; break;            // read r w p q z; write r w p q z
+    case K_PCGX: per = 8 * 12; break;           // ... and read, write x
     case K_CG1: per = 8 * 3; break;             // read r, p_old; write p
-    case K_CG2: per = 8 * 5; break;             // read p, x, r; write x, r
+    case K_CG2: per = 8 * 3; break;             // read p, r; write r
+    case K_CG2X: per = 8 * 6; break;            // read p, p_prev, x, r; write x, r
     case K_RESID: per = 8 * 2; break;           // read x, b
     case K_REF_SCALE: per = 8 * 2 + 4 * 2; break;  // read x, b; write rho, d
     case K_CG1F: per = 4 * 3; break;

@@ -255,9 +255,11 @@ static const char* kind_name(int kind, int fp32g) {
   switch (kind) {
     case K_INIT_R: return fp32g ? "init_r_f32geo" : "init_r";
     case K_INIT_W: return "init_w";
-    case K_PCG: return "pcg_pass";
+    case K_PCG: return "pcg_pass_nx";
+    case K_PCGX: return "pcg_pass";
     case K_CG1: return "stencil_dot";
-    case K_CG2: return "update_norm";
+    case K_CG2: return "update_norm_nx";
+    case K_CG2X: return "update_norm";
     case K_RESID: return fp32g ? "resid_f32geo" : "resid";
     case K_REF_SCALE: return "ref_scale";
     case K_CG1F: return "stencil_dot_f32";
@@ -362,7 +364,8 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
     if (e == hipSuccess)
       e = issue(c, w, K_CG2F, [&](PassArgs& a) { a.pf_in = w.pf[(i + 1) & 1]; });
   } else if (w.pl.variant == CG_VARIANT_PIPELINED) {
-    e = issue(c, w, K_PCG, [&](PassArgs& a) {
+    // iteration i + 1 of the solve: an even one also brings x up to date
+    e = issue(c, w, (i & 1) ? K_PCGX : K_PCG, [&](PassArgs& a) {
       a.w_in = w.w[i & 1];
       a.w_out = w.w[(i + 1) & 1];
     });
@@ -372,7 +375,10 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
       a.pc_out = w.pc[(i + 1) & 1];
     });
     if (e == hipSuccess)
-      e = issue(c, w, K_CG2, [&](PassArgs& a) { a.pc_in = w.pc[(i + 1) & 1]; });
+      e = issue(c, w, (i & 1) ? K_CG2X : K_CG2, [&](PassArgs& a) {
+        a.pc_in = w.pc[(i + 1) & 1];
+        a.pc_prev = w.pc[i & 1];
+      });
   }
   w.i++;
   return e;
@@ -797,8 +803,8 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
   const uint64_t k = key(nx, ny, fp32g);
   std::vector<const char*> names;
   if (fp32g) names = {"stencil_dot_f32", "update_norm_f32"};
-  else if (variant == CG_VARIANT_PIPELINED) names = {"pcg_pass"};
-  else names = {"stencil_dot", "update_norm"};
+  else if (variant == CG_VARIANT_PIPELINED) names = {"pcg_pass", "pcg_pass_nx"};
+  else names = {"stencil_dot", "update_norm", "update_norm_nx"};
   std::vector<int> cpls = {0};
   if (!fp32g && variant == CG_VARIANT_CLASSIC) cpls = {2, 4};
   const bool save_prof = prof;
@@ -831,11 +837,11 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
           auto it = stats.find(nm);
           if (it != stats.end()) {
             t += it->second.seconds;
-            launches = std::max(launches, it->second.launches);
+            launches += it->second.launches;
           }
         }
         if (launches == 0) continue;
-        t /= (double)launches;  // per iteration
+        t /= (double)p.maxit;  // per iteration (tol = 0: exactly maxit of them)
         if (t < best) {
           best = t;
           bestp = Pin{rows, gsz, cpl};

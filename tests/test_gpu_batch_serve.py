@@ -1,4 +1,4 @@
-"""GPU tests of the persistent batch kernel (cg_solve_batch) and the
+"""GPU tests of the multi-solve batch engine (cg_solve_batch) and the
 continuous-batching server (cg_submit / cg_poll): every solve gives the same
 bits in a batch or in a served mix as when solved alone (same tile geometry,
 same reduction order), and the first few also match the CPU oracle."""

@@ -94,12 +94,18 @@ def test_profiling_statistics(torch):
         say("profiling stats")
         rc, r = ctx.solve(b, x, n, n, tol=0.0, maxit=37, variant=1)
         st = ctx.cg_kernel_stats(reset=True)
-        assert st["pcg_pass"]["launches"] == 37
+        # odd iterations leave x alone (80 B per unknown), even ones update it
+        # twice (96 B); the check pass after iteration 37 applies its update
+        assert st["pcg_pass_nx"]["launches"] == 19 and st["pcg_pass"]["launches"] == 18
         assert st["final_check"]["launches"] == 1 and st["final_check"]["bytes"] == 0
-        assert st["pcg_pass"]["bytes"] == 37 * 96 * n * n
+        assert st["pcg_pass"]["bytes"] == 18 * 96 * n * n
+        assert st["pcg_pass_nx"]["bytes"] == 19 * 80 * n * n
         rc, r = ctx.solve(b, x, n, n, tol=0.0, maxit=12, variant=0)
         st = ctx.cg_kernel_stats(reset=False)
-        assert st["stencil_dot"]["launches"] == 12 and st["update_norm"]["launches"] == 12
+        assert st["stencil_dot"]["launches"] == 12
+        assert st["update_norm"]["launches"] == 6 and st["update_norm_nx"]["launches"] == 6
+        assert st["update_norm"]["bytes"] == 6 * 48 * n * n
+        assert st["update_norm_nx"]["bytes"] == 6 * 24 * n * n
         assert ctx.cg_kernel_stats(reset=True) == st
         assert ctx.cg_kernel_stats() == {}
 
