@@ -122,6 +122,8 @@ struct PassArgs {
   float* pf_out;
   const double* u;         // apply / dot inputs
   double* y;
+  int32_t rev;             // walk the tiles in reverse order (alternate passes)
+  int32_t pad_;
 };
 
 // Scalars a pass body needs, chosen by the preceding transition.

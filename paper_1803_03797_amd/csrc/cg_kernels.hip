@@ -1052,7 +1052,11 @@ constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 2;
 // grid = G work-groups of 256 threads, G a multiple of 8.  Work-group b is
 // placed by the hardware on XCD b % 8; the tiles are split into 8 contiguous
 // bands, band x served by the work-groups of XCD x, so vertically adjacent
-// tiles (whose halo rows overlap) share an L2.
+// tiles (whose halo rows overlap) share an L2.  Every other pass walks each
+// band in reverse order, so a pass starts on the tiles the previous pass
+// wrote last, while they are still in the memory-side cache.  The order in
+// which tiles are processed does not change any result: partials are stored
+// per tile and summed in tile order.
 template <int KIND, int CPL>
 __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   __shared__ double lds[kLdsPerGroup];
@@ -1096,7 +1100,8 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   const int T = a.g.tiles;
   const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
   int par = 0;
-  for (int t = t0 + slot; t < t1; t += nb, par ^= 1) {
+  for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
+    const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
     double lv[2];
     run_body<KIND, CPL>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
@@ -1768,7 +1773,7 @@ __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int
 
 template <int KIND, int CPL>
 __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, State s,
-                                          double* lds) {
+                                          double* lds, int rev) {
   constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
   constexpr int DO = (KIND == K_FINAL) ? 0 : ndots_out<KIND>();
   const int T = S.g.tiles;
@@ -1818,14 +1823,18 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.pf_out = S.PF[(kin0 + 1) & 1];
   a.u = nullptr;
   a.y = nullptr;
+  a.rev = 0;
+  a.pad_ = 0;
   if constexpr (defers_x<KIND>()) {
     if (flush) {
       for (int t = it.t0; t < it.t1; ++t) body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
       return;
     }
   }
+  // odd steps walk the item's tiles backwards (see k_step)
   int par = 0;
-  for (int t = it.t0; t < it.t1; ++t, par ^= 1) {
+  for (int tt = it.t0; tt < it.t1; ++tt, par ^= 1) {
+    const int t = rev ? it.t1 - 1 - (tt - it.t0) : tt;
     double lv[2] = {0.0, 0.0};
     run_body_any<KIND, CPL>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
@@ -1838,8 +1847,11 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
   __shared__ double lds[kLdsPerGroup];
   const int n = __builtin_amdgcn_readfirstlane(*n_items);
   const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const Item it = items[i];
+  // odd steps take the items (and their tiles) in reverse order, so a step
+  // starts on the tiles the previous one wrote last (memory-side cache)
+  const int rev = step & 1;
+  for (int ii = blockIdx.x; ii < n; ii += gridDim.x) {
+    const Item it = items[rev ? n - 1 - ii : ii];
     const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
     const int m = step - S.admit_step;
     const State s = load_state_uniform(S.S[m & 1]);
@@ -1850,25 +1862,25 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
     }
     if (S.cpl4) {
       switch (kind) {
-        case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds); break;
-        case K_CG1: step_item<K_CG1, 4>(S, it, m, s, lds); break;
-        case K_CG2: step_item<K_CG2, 4>(S, it, m, s, lds); break;
-        case K_RESID: step_item<K_RESID, 4>(S, it, m, s, lds); break;
-        case K_FINAL: step_item<K_FINAL, 4>(S, it, m, s, lds); break;
-        case K_REF_SCALE: step_item<K_REF_SCALE, 4>(S, it, m, s, lds); break;
-        case K_CG1F: step_item<K_CG1F, 4>(S, it, m, s, lds); break;
-        case K_CG2F: step_item<K_CG2F, 4>(S, it, m, s, lds); break;
-        case K_REF_UPDATE: step_item<K_REF_UPDATE, 4>(S, it, m, s, lds); break;
+        case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds, rev); break;
+        case K_CG1: step_item<K_CG1, 4>(S, it, m, s, lds, rev); break;
+        case K_CG2: step_item<K_CG2, 4>(S, it, m, s, lds, rev); break;
+        case K_RESID: step_item<K_RESID, 4>(S, it, m, s, lds, rev); break;
+        case K_FINAL: step_item<K_FINAL, 4>(S, it, m, s, lds, rev); break;
+        case K_REF_SCALE: step_item<K_REF_SCALE, 4>(S, it, m, s, lds, rev); break;
+        case K_CG1F: step_item<K_CG1F, 4>(S, it, m, s, lds, rev); break;
+        case K_CG2F: step_item<K_CG2F, 4>(S, it, m, s, lds, rev); break;
+        case K_REF_UPDATE: step_item<K_REF_UPDATE, 4>(S, it, m, s, lds, rev); break;
       }
     } else {
       switch (kind) {
-        case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds); break;
-        case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds); break;
-        case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds); break;
-        case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds); break;
-        case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds); break;
-        case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds); break;
-        case K_FINAL: step_item<K_FINAL, 2>(S, it, m, s, lds); break;
+        case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds, rev); break;
+        case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds, rev); break;
+        case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds, rev); break;
+        case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds, rev); break;
+        case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds, rev); break;
+        case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds, rev); break;
+        case K_FINAL: step_item<K_FINAL, 2>(S, it, m, s, lds, rev); break;
       }
     }
     __syncthreads();  // LDS reuse by the next item
