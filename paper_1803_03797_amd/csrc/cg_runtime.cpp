@@ -187,10 +187,18 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   } else {
     const int kind = pl.refined ? K_CG2F : (p->variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
     int cap = std::max(8, pass_max_blocks_per_cu(kind, pl.fp32g) * num_cu);
-    // the six-vector pipelined pass streams best with one work-group per CU
-    // walking several tiles (measured at 4096^2: 286 us against 297 us at
-    // four per CU); the classic passes with as many as fit
-    if (!pl.refined && p->variant == CG_VARIANT_PIPELINED) cap = std::max(8, std::min(cap, num_cu));
+    // The pipelined pass streams best with few work-groups walking several
+    // tiles each once its vectors outgrow the caches: measured per-iteration
+    // times, one / two / four work-groups per CU: 1024^2 22.8 / 20.7 / 20.0 us,
+    // 2048^2 60.4 / 62.3 / 62.3 us, 4096^2 286 / 289 / 297 us, 8192^2
+    // 1215 / 1193 / 1203 us.  The classic passes run as many as fit.
+    if (!pl.refined && p->variant == CG_VARIANT_PIPELINED) {
+      const int64_t dof = (int64_t)p->nx * p->ny;
+      if (dof > 2 * 1024 * 1024) {
+        const int per_cu = dof > 24 * 1024 * 1024 ? 2 : 1;
+        cap = std::max(8, std::min(cap, per_cu * num_cu));
+      }
+    }
     const int tpb = (T + cap - 1) / cap;          // tiles per work-group
     pl.grid = (int)round_up((size_t)((T + tpb - 1) / tpb), 8);
   }
