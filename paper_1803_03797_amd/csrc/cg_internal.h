@@ -88,12 +88,14 @@ enum : int32_t {
   K_DOT,          // slot (u, y)
   K_PCGX,         // K_PCG of an even iteration: also applies both x updates
   K_CG2X,         // K_CG2 of an even iteration: also applies both x updates
+  K_CG2FX,        // K_CG2F of an even inner iteration: both d updates
   K_NKINDS
 };
 
-// Deferred x (FP64 classic and pipelined).  x is read and written only by
-// the passes that end an even iteration: such a pass applies the previous
-// (odd) iteration's update and then its own, x = fma(a_i, p_i,
+// Deferred x (FP64 classic and pipelined; the inner solution d of the FP32
+// inner solve likewise, counted by inner iterations).  x is read and written
+// only by the passes that end an even iteration: such a pass applies the
+// previous (odd) iteration's update and then its own, x = fma(a_i, p_i,
 // fma(a_(i-1), p_(i-1), x)), the same operations in the same order as one
 // update per iteration.  A solve that stops after an odd iteration gets the
 // pending update from the pass that stops it.
@@ -120,6 +122,7 @@ struct PassArgs {
   float* df;               //             inner solution d
   const float* pf_in;      //             inner direction ping-pong
   float* pf_out;
+  const float* pf_prev;    //             pass 2: the direction before pf_in
   const double* u;         // apply / dot inputs
   double* y;
   int32_t rev;             // walk the tiles in reverse order (alternate passes)

@@ -260,6 +260,8 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     return transition<K_PCG>(s, sum, sc);
   } else if constexpr (KIND == K_CG2X) {
     return transition<K_CG2>(s, sum, sc);
+  } else if constexpr (KIND == K_CG2FX) {
+    return transition<K_CG2F>(s, sum, sc);
   } else if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
     return true;
   } else if constexpr (KIND == K_INIT_R) {
@@ -409,8 +411,10 @@ constexpr int ndots_in() {  // partial slots the prologue consumes
   return (KIND == K_PCG || KIND == K_PCGX || KIND == K_INIT_W || KIND == K_CG1 ||
           KIND == K_REF_SCALE)
              ? 2
-         : (KIND == K_CG2 || KIND == K_CG2X || KIND == K_CG1F || KIND == K_CG2F) ? 1
-                                                                                  : 0;
+         : (KIND == K_CG2 || KIND == K_CG2X || KIND == K_CG1F || KIND == K_CG2F ||
+            KIND == K_CG2FX)
+             ? 1
+             : 0;
 }
 
 template <int KIND>
@@ -419,15 +423,22 @@ constexpr int ndots_out() {  // partial slots the body produces
           KIND == K_RESID)
              ? 2
          : (KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X || KIND == K_REF_SCALE ||
-            KIND == K_CG1F || KIND == K_CG2F || KIND == K_DOT)
+            KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_DOT)
              ? 1
              : 0;
 }
 
-// The passes of FP64 CG whose x update is deferred (see cg_internal.h).
+// The passes whose solution update is deferred (see cg_internal.h): FP64 CG
+// (x, counted by k) and the FP32 inner solve (d, counted by kin).
 template <int KIND>
 constexpr bool defers_x() {
-  return KIND == K_PCG || KIND == K_PCGX || KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X;
+  return KIND == K_PCG || KIND == K_PCGX || KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X ||
+         KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX;
+}
+
+template <int KIND>
+constexpr bool inner_kind() {
+  return KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX;
 }
 
 // transition<KIND> plus the deferred-x bookkeeping: sc.xu when this pass ends
@@ -441,11 +452,12 @@ __device__ __forceinline__ bool transition_x(State& s, const double* sum, Sc& sc
   const bool run = transition<KIND>(s, sum, sc);
   flush = false;
   if constexpr (defers_x<KIND>()) {
-    if (run && KIND != K_CG1 && !(s.k & 1)) {
+    const int k = inner_kind<KIND>() ? s.kin : s.k;
+    if (run && KIND != K_CG1 && KIND != K_CG1F && !(k & 1)) {
       sc.xu = 1;
       sc.alp = alpha_before;
     }
-    if (was_running && s.status != ST_RUNNING && (s.k & 1)) {
+    if (was_running && s.status != ST_RUNNING && (k & 1)) {
       flush = true;
       sc.alp = s.alpha;
     }
@@ -875,8 +887,9 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
 }
 
 // --- K_CG2 / K_CG2X / K_CG2F: s = A p; x += alpha p; r -= alpha s; slot (r, r).
-// XM: 0 = x untouched (FP64, odd iteration), 1 = x += alpha p (the FP32 inner
-// solve's d), 2 = x += alpha_prev p_prev, then x += alpha p (FP64, even).
+// XM: 0 = x (or d) untouched (odd iteration), 1 = x += alpha p (unused),
+// 2 = x += alpha_prev p_prev, then x += alpha p (even iteration).  FP32: the
+// inner solve's d, with alpha rounded to FP32 as in the oracle.
 template <typename T, int CPL, int XM>
 struct XrRow {
   Row<T, CPL> x, r, pp;
@@ -899,6 +912,7 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
     Rv = a.r;
   } else {
     Pv = a.pf_in;
+    Pp = a.pf_prev;
     Xv = a.df;
     Rv = a.rf;
   }
@@ -952,14 +966,44 @@ __device__ __forceinline__ void body_flush(const PassArgs& a, int t, const doubl
   }
 }
 
-// The vector whose pending x update a stopping pass of KIND applies: the
-// pipelined p, classic pass 1's incoming direction, classic pass 2's previous
-// direction.
+// --- pending d update of a finished inner solve: d += alp * P (FP32).
+__device__ __forceinline__ void body_flush_f32(const PassArgs& a, int t, const float* P,
+                                               float alp) {
+  using R = Row<float, 4>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<4>(g, t);
+  const int valid = g.nx - s.c;
+  if (valid <= 0) return;
+  for (int j = s.j0; j < s.j1; ++j) {
+    const size_t o = (size_t)j * g.pitch + s.c;
+    const R pv = ldrow<float, 4>(P + o);
+    R d = ldrow<float, 4>(a.df + o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d.e[k] = fmaf(alp, pv.e[k], d.e[k]);
+    strow<float, 4>(a.df + o, d, valid);
+  }
+}
+
+// The vector whose pending update a stopping pass of KIND applies: the
+// pipelined p, pass 1's incoming direction, pass 2's previous direction.
 template <int KIND>
 __device__ __forceinline__ const double* flush_dir(const PassArgs& a) {
   if constexpr (KIND == K_PCG || KIND == K_PCGX) return a.p;
   else if constexpr (KIND == K_CG1) return a.pc_in;
   else return a.pc_prev;
+}
+
+template <int KIND>
+__device__ __forceinline__ const float* flush_dir_f32(const PassArgs& a) {
+  if constexpr (KIND == K_CG1F) return a.pf_in;
+  else return a.pf_prev;
+}
+
+// Applies a stopped solve's pending update on tile t.
+template <int KIND, int CPL>
+__device__ __forceinline__ void run_flush(const PassArgs& a, int t, const Sc& sc) {
+  if constexpr (inner_kind<KIND>()) body_flush_f32(a, t, flush_dir_f32<KIND>(a), float(sc.alp));
+  else body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
 }
 
 // --- K_REF_SCALE: rho = fp32((b - A x) * inv); d = 0; slot (rho, rho) in FP64.
@@ -1024,7 +1068,8 @@ __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc,
   else if constexpr (KIND == K_CG2) body_cg2<double, CPL, 0>(a, t, sc, lv);
   else if constexpr (KIND == K_CG2X) body_cg2<double, CPL, 2>(a, t, sc, lv);
   else if constexpr (KIND == K_CG1F) body_cg1<float, CPL>(a, t, sc, lv);
-  else if constexpr (KIND == K_CG2F) body_cg2<float, CPL, 1>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2F) body_cg2<float, CPL, 0>(a, t, sc, lv);
+  else if constexpr (KIND == K_CG2FX) body_cg2<float, CPL, 2>(a, t, sc, lv);
   else if constexpr (KIND == K_REF_SCALE) body_ref_scale<CPL>(a, t, sc, lv);
   else if constexpr (KIND == K_REF_UPDATE) body_ref_update<CPL>(a, t, sc);
 }
@@ -1039,6 +1084,9 @@ __device__ __forceinline__ void run_body_any(const PassArgs& a, int t, const Sc&
   } else if constexpr (KIND == K_CG2) {
     if (sc.xu) run_body<K_CG2X, CPL>(a, t, sc, lv);
     else run_body<K_CG2, CPL>(a, t, sc, lv);
+  } else if constexpr (KIND == K_CG2F) {
+    if (sc.xu) run_body<K_CG2FX, CPL>(a, t, sc, lv);
+    else run_body<K_CG2F, CPL>(a, t, sc, lv);
   } else {
     run_body<KIND, CPL>(a, t, sc, lv);
   }
@@ -1088,7 +1136,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
         const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
         const int T = a.g.tiles;
         const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
-        for (int t = t0 + slot; t < t1; t += nb) body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
+        for (int t = t0 + slot; t < t1; t += nb) run_flush<KIND, CPL>(a, t, sc);
         return;
       }
     }
@@ -1184,7 +1232,7 @@ __device__ __forceinline__ bool wg_step(State& s, const PassArgs& a, Sc& sc, dou
   if constexpr (defers_x<KIND>()) {
     if (flush) {
       const int grp = threadIdx.x >> 8;
-      for (int t = grp; t < a.g.tiles; t += kWgGroups) body_flush<2>(a, t, flush_dir<KIND>(a), sc.alp);
+      for (int t = grp; t < a.g.tiles; t += kWgGroups) run_flush<KIND, 2>(a, t, sc);
       __syncthreads();  // x complete before the final residual reads it
     }
   }
@@ -1821,13 +1869,14 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.df = S.df;
   a.pf_in = (KIND == K_CG2F) ? S.PF[(kin0 + 1) & 1] : S.PF[kin0 & 1];
   a.pf_out = S.PF[(kin0 + 1) & 1];
+  a.pf_prev = S.PF[kin0 & 1];
   a.u = nullptr;
   a.y = nullptr;
   a.rev = 0;
   a.pad_ = 0;
   if constexpr (defers_x<KIND>()) {
     if (flush) {
-      for (int t = it.t0; t < it.t1; ++t) body_flush<CPL>(a, t, flush_dir<KIND>(a), sc.alp);
+      for (int t = it.t0; t < it.t1; ++t) run_flush<KIND, CPL>(a, t, sc);
       return;
     }
   }
@@ -2019,6 +2068,9 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
     case K_CG1F:
       hipLaunchKernelGGL((k_pass<K_CG1F, 4>), dim3(grid), dim3(kGroup), 0, st, a);
       return hipGetLastError();
+    case K_CG2FX:
+      hipLaunchKernelGGL((k_pass<K_CG2FX, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
     case K_CG2F:
       hipLaunchKernelGGL((k_pass<K_CG2F, 4>), dim3(grid), dim3(kGroup), 0, st, a);
       return hipGetLastError();
@@ -2081,7 +2133,8 @@ int pass_max_blocks_per_cu(int kind, int fp32g) {
     case K_CG2:
     case K_CG2X: return fp32g ? occ<K_CG2X, 4>() : occ<K_CG2X, 2>();
     case K_CG1F: return occ<K_CG1F, 4>();
-    case K_CG2F: return occ<K_CG2F, 4>();
+    case K_CG2F:
+    case K_CG2FX: return occ<K_CG2FX, 4>();
     default: return fp32g ? occ<K_RESID, 4>() : occ<K_RESID, 2>();
   }
 }
@@ -2100,8 +2153,9 @@ size_t pass_algorithmic_bytes(int kind, int64_t dof) {
     case K_CG2X: per = 8 * 6; break;            // read p, p_prev, x, r; write x, r
     case K_RESID: per = 8 * 2; break;           // read x, b
     case K_REF_SCALE: per = 8 * 2 + 4 * 2; break;  // read x, b; write rho, d
-    case K_CG1F: per = 4 * 3; break;
-    case K_CG2F: per = 4 * 5; break;
+    case K_CG1F: per = 4 * 3; break;             // read r, p_old; write p (FP32)
+    case K_CG2F: per = 4 * 3; break;             // read p, r; write r
+    case K_CG2FX: per = 4 * 6; break;            // read p, p_prev, d, r; write d, r
     case K_REF_UPDATE: per = 8 * 2 + 4; break;  // read x, d; write x
     case K_APPLY: per = 8 * 2; break;
     case K_DOT: per = 8 * 2; break;

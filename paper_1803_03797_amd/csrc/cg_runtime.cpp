@@ -275,7 +275,8 @@ static const char* kind_name(int kind, int fp32g) {
     case K_RESID: return fp32g ? "resid_f32geo" : "resid";
     case K_REF_SCALE: return "ref_scale";
     case K_CG1F: return "stencil_dot_f32";
-    case K_CG2F: return "update_norm_f32";
+    case K_CG2F: return "update_norm_f32_nx";
+    case K_CG2FX: return "update_norm_f32";
     case K_REF_UPDATE: return "ref_update";
     case K_APPLY: return "apply";
     case K_DOT: return "dot";
@@ -375,7 +376,10 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
       a.pf_out = w.pf[(i + 1) & 1];
     });
     if (e == hipSuccess)
-      e = issue(c, w, K_CG2F, [&](PassArgs& a) { a.pf_in = w.pf[(i + 1) & 1]; });
+      e = issue(c, w, (i & 1) ? K_CG2FX : K_CG2F, [&](PassArgs& a) {
+        a.pf_in = w.pf[(i + 1) & 1];
+        a.pf_prev = w.pf[i & 1];
+      });
   } else if (w.pl.variant == CG_VARIANT_PIPELINED) {
     // iteration i + 1 of the solve: an even one also brings x up to date
     e = issue(c, w, (i & 1) ? K_PCGX : K_PCG, [&](PassArgs& a) {
@@ -815,7 +819,7 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
   p.x = x;
   const uint64_t k = key(nx, ny, fp32g);
   std::vector<const char*> names;
-  if (fp32g) names = {"stencil_dot_f32", "update_norm_f32"};
+  if (fp32g) names = {"stencil_dot_f32", "update_norm_f32", "update_norm_f32_nx"};
   else if (variant == CG_VARIANT_PIPELINED) names = {"pcg_pass", "pcg_pass_nx"};
   else names = {"stencil_dot", "update_norm", "update_norm_nx"};
   std::vector<int> cpls = {0};
