@@ -34,52 +34,6 @@ double now_s() {
 
 static size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
-// ------------------------------------------------------------------ arena --
-
-void* Arena::alloc(size_t n) {
-  n = round_up(n ? n : 1, kAlign);
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second >= n) {
-      size_t off = it->first, sz = it->second;
-      free_.erase(it);
-      if (sz > n) free_[off + n] = sz - n;
-      used_[off] = n;
-      in_use_ += n;
-      return base_ + off;
-    }
-  }
-  return nullptr;
-}
-
-void Arena::release(void* p) {
-  if (!p) return;
-  size_t off = (size_t)((char*)p - base_);
-  auto it = used_.find(off);
-  if (it == used_.end()) return;
-  size_t n = it->second;
-  used_.erase(it);
-  in_use_ -= n;
-  auto nx = free_.lower_bound(off);
-  if (nx != free_.end() && off + n == nx->first) {
-    n += nx->second;
-    nx = free_.erase(nx);
-  }
-  if (nx != free_.begin()) {
-    auto pv = std::prev(nx);
-    if (pv->first + pv->second == off) {
-      pv->second += n;
-      return;
-    }
-  }
-  free_[off] = n;
-}
-
-size_t Arena::largest_free() const {
-  size_t m = 0;
-  for (auto& kv : free_) m = std::max(m, kv.second);
-  return m;
-}
-
 // ------------------------------------------------------------- planning --
 
 static int32_t map_status(int32_t st) {

@@ -8,36 +8,10 @@
 #include <vector>
 
 #include "../../include/cg.h"
+#include "cg_arena.h"
 #include "cg_internal.h"
 
 namespace cgr {
-
-// First-fit allocator over one device region (the caller's arena tensor or a
-// region the library allocated).  256-byte granularity; neighbours coalesce.
-class Arena {
- public:
-  static constexpr size_t kAlign = 256;
-  void init(char* base, size_t size) {
-    base_ = base;
-    size_ = size;
-    free_.clear();
-    used_.clear();
-    in_use_ = 0;
-    free_[0] = size;
-  }
-  void* alloc(size_t n);
-  void release(void* p);
-  size_t largest_free() const;
-  size_t size() const { return size_; }
-  size_t in_use() const { return in_use_; }
-  char* base() const { return base_; }
-
- private:
-  char* base_ = nullptr;
-  size_t size_ = 0, in_use_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> bytes
-  std::map<size_t, size_t> used_;
-};
 
 struct Plan {
   int variant = 0;
