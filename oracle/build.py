@@ -2,21 +2,29 @@
 
 Plain gcc, -O2 with floating-point contraction off and no fast-math, so that
 every arithmetic operation in cg_oracle.c is one correctly rounded IEEE
-operation.
+operation; cg_oracle_fixed.c (the fixed-point variant) is integer code.
 """
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "cg_oracle.c")
+SOURCES = [os.path.join(HERE, f) for f in ("cg_oracle.c", "cg_oracle_fixed.c")]
 LIB = os.path.join(HERE, "libcg_oracle.so")
+
+
+def stale() -> bool:
+    """True when the library is missing or older than a source."""
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(f) > t for f in SOURCES)
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+           "-fPIC", "-shared", "-o", tmp] + SOURCES + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

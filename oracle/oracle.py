@@ -51,8 +51,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB) or (
-            os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+    if _build.stale():
         _build.build()
     lib = C.CDLL(_build.LIB)
     P = C.c_void_p
@@ -68,6 +67,25 @@ def _load():
     lib.oracle_cg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
                               P, P, P, C.c_double, C.c_int32, C.POINTER(_Result),
                               C.POINTER(_History)]
+    I64 = C.c_int64
+    lib.oracle_fx_quantize.restype = I64
+    lib.oracle_fx_quantize.argtypes = [C.c_double]
+    lib.oracle_fx_value.restype = C.c_double
+    lib.oracle_fx_value.argtypes = [I64]
+    lib.oracle_fx_mul.restype = I64
+    lib.oracle_fx_mul.argtypes = [I64, I64]
+    for f in (lib.oracle_fx_axpy, lib.oracle_fx_axmy):
+        f.restype = I64
+        f.argtypes = [I64, I64, I64]
+    lib.oracle_fx_div.restype = I64
+    lib.oracle_fx_div.argtypes = [I64, I64]
+    lib.oracle_fx_dot.restype = I64
+    lib.oracle_fx_dot.argtypes = [I64, P, P]
+    lib.oracle_fx_spmv.restype = C.c_int
+    lib.oracle_fx_spmv.argtypes = [C.c_int32, C.c_int32, P, P]
+    lib.oracle_cg_fixed.restype = C.c_int
+    lib.oracle_cg_fixed.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_double,
+                                    C.c_int32, C.POINTER(_Result)]
     lib.oracle_refine.restype = C.c_int
     lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
                                   C.c_int32, C.POINTER(_Result)]
@@ -165,3 +183,80 @@ def refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, maxit=200000, x0=None):
     return x, Result(status=res.status, iterations=res.iterations,
                      outer_iterations=res.outer_iterations,
                      rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
+
+
+# -- fixed point (cg_oracle_fixed.c): Q20.30 values as int64 counts of 2^-30 --
+
+FX_FRAC = 30
+FX_MAX = (1 << 49) - 1
+FX_MIN = -(1 << 49)
+FX_ONE = 1 << FX_FRAC
+
+
+def fx_quantize(v):
+    """Round-half-up, saturating quantization of one float to Q20.30 (count)."""
+    return _load().oracle_fx_quantize(float(v))
+
+
+def fx_value(k):
+    return _load().oracle_fx_value(int(k))
+
+
+def fx_mul(a, b):
+    return _load().oracle_fx_mul(int(a), int(b))
+
+
+def fx_axpy(a, x, y):
+    """Q(y + a x) of counts."""
+    return _load().oracle_fx_axpy(int(a), int(x), int(y))
+
+
+def fx_axmy(a, x, y):
+    """Q(y - a x) of counts."""
+    return _load().oracle_fx_axmy(int(a), int(x), int(y))
+
+
+def fx_div(n, d):
+    if d <= 0:
+        raise ValueError("fx_div needs d > 0")
+    return _load().oracle_fx_div(int(n), int(d))
+
+
+def _ivec(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    if n is not None and a.size != n:
+        raise ValueError("vector has %d entries, needs %d" % (a.size, n))
+    return a
+
+
+def fx_dot(a, b):
+    a = _ivec(a).ravel()
+    b = _ivec(b, a.size).ravel()
+    return _load().oracle_fx_dot(a.size, _ptr(a), _ptr(b))
+
+
+def fx_spmv(u, nx, ny):
+    u = _ivec(u, nx * ny).reshape(ny, nx)
+    y = np.zeros_like(u)
+    rc = _load().oracle_fx_spmv(nx, ny, _ptr(u), _ptr(y))
+    if rc:
+        raise RuntimeError("oracle_fx_spmv failed: %d" % rc)
+    return y
+
+
+def cg_fixed(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-6, maxit=2000, x0=None):
+    """Algorithm 1 or 2 in Q20.30 (see cg_oracle_fixed.c).  b and x0 are
+    float64 and quantized on entry.  Returns (x float64, x counts int64,
+    Result)."""
+    b = _vec(b, nx, ny)
+    x0a = _vec(x0, nx, ny) if x0 is not None else None
+    xq = np.zeros((ny, nx), np.int64)
+    x = np.zeros_like(b)
+    res = _Result()
+    rc = _load().oracle_cg_fixed(variant, nx, ny, _ptr(b), _ptr(x0a), _ptr(xq), _ptr(x), tol,
+                                 maxit, C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle_cg_fixed rejected the call: %d" % rc)
+    return x, xq, Result(status=res.status, iterations=res.iterations,
+                         outer_iterations=res.outer_iterations,
+                         rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
