@@ -37,7 +37,25 @@ extern "C" {
 typedef struct cg_ctx cg_ctx; /* opaque: device workspace, streams, scheduler */
 
 typedef enum { CG_VARIANT_CLASSIC = 0, CG_VARIANT_PIPELINED = 1 } cg_variant;
-typedef enum { CG_PREC_FP64 = 0, CG_PREC_FP32_REFINED = 1 } cg_precision;
+/* CG_PREC_FIXED: the paper's fixed-point format (Section II-B, the stencil
+ * listing's 50-bit type with 20 integer bits, round to nearest, saturate):
+ * every value is an integer multiple of 2^-30 in [-2^19, 2^19 - 2^-30].  b and
+ * x0 are rounded to it on entry (ties towards +infinity, out-of-range values
+ * saturate, NaN reads as 0); every statement of Algorithm 1 or 2 rounds its
+ * exact result once (y +- a x formed exactly; a dot product sums its rounded
+ * products exactly and saturates once; each division rounds once); the stop
+ * test compares (r, r) with tol^2 (b, b) rounded to the format; x returns as
+ * the exact FP64 value of the fixed-point result, and the result's relative
+ * residuals are sqrt of ratios of fixed-point dot products.  Integer
+ * arithmetic: the result does not depend on summation order, and every path
+ * returns the same bits.  One work-group per solve (cg_plan_info.path 3):
+ * nx * ny <= 10176 (the paper's grids reach 100 x 100); larger grids are
+ * CG_E_INVALID.  inner_tol is ignored. */
+typedef enum {
+  CG_PREC_FP64 = 0,
+  CG_PREC_FP32_REFINED = 1,
+  CG_PREC_FIXED = 2
+} cg_precision;
 typedef enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 } cg_memspace;
 
 enum {
@@ -76,7 +94,7 @@ typedef struct {
                               runs exactly maxit iterations (throughput mode)         */
   int32_t maxit;           /* >= 1; FP32-refined: cap on the total inner iterations   */
   cg_variant variant;      /* Algorithm 1 or Algorithm 2                              */
-  cg_precision precision;  /* FP64, or FP32 inner CG inside FP64 refinement           */
+  cg_precision precision;  /* FP64, FP32 inner CG inside FP64 refinement, or fixed    */
   double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
 } cg_problem;
 
@@ -86,7 +104,8 @@ typedef struct {
   int32_t outer_iterations; /* refined: refinement steps; else 0                     */
   int32_t pad_;
   double rel_res_recursive; /* sqrt((r,r)/(b,b)) of the iteration's own residual     */
-  double rel_res_true;      /* ||b - A x|| / ||b|| recomputed in FP64 on the device  */
+  double rel_res_true;      /* ||b - A x|| / ||b|| recomputed on the device (FP64;
+                               fixed point: in the fixed-point arithmetic)           */
   double device_seconds;    /* wall time the solve held the device                   */
   double latency_seconds;   /* serving: submit -> completion; else = device_seconds  */
 } cg_result;
@@ -99,11 +118,13 @@ typedef struct {
  * segment order (path 2, alone and in a batch): thread t of seg_waves*64
  * owns column t mod seg_cols and seg_rows rows of segment t div seg_cols
  * (threads of columns >= nx own nothing); fma in row order; xor butterfly;
- * waves in order.  The tile fields always describe the
+ * waves in order.  Path 3 (fixed point) is exact integer arithmetic: no order
+ * to describe.  The tile fields always describe the
  * tile geometry of the shape (cg_dot and cg_apply use it on every path). */
 typedef struct {
   int32_t path;             /* 0 = multi-work-group passes, 1 = single work-group,
-                               2 = single work-group with the vectors on chip       */
+                               2 = single work-group with the vectors on chip,
+                               3 = fixed point, single work-group                   */
   int32_t cols_per_lane, lanes, waves, rows, threads2;
   int32_t tiles;            /* tiles per pass                                        */
   int32_t grid;             /* work-groups per pass launch                           */
@@ -134,7 +155,8 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
 /* n independent solves on the device at once.  Every resident solve advances
  * by one CG pass per launch of a multi-solve step kernel (chunks of launches
  * replayed from a HIP graph); problems small enough for the on-chip solver
- * (cg_plan_info.path 2) run whole, one work-group each, beside the steps.
+ * (cg_plan_info.path 2) and fixed-point problems (path 3) run whole, one
+ * work-group each, beside the steps.
  * Solves are admitted in order while their footprint fits the arena and a
  * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
  * worst per-solve status; results[i] holds each outcome.  A breakdown of one
@@ -161,7 +183,8 @@ int cg_apply(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double*
  * order of cg_plan_info for an FP64 problem of this shape). */
 int cg_dot(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* a,
            const double* b, double* out);
-/* Fills *info for prob (host-side; no device work). */
+/* Fills *info for prob (host-side; no device work).  CG_E_INVALID for a
+ * fixed-point problem larger than the fixed-point solver takes. */
 int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info);
 /* Device bytes prob needs while resident (host-only; no context needed). */
 int cg_footprint(const cg_problem* prob, size_t* bytes);
@@ -169,7 +192,7 @@ int cg_footprint(const cg_problem* prob, size_t* bytes);
 int cg_validate(const cg_problem* prob);
 /* Autotuner: times candidate tile shapes for (nx, ny, variant, precision) on
  * the device and pins the fastest for that grid shape (cached, optionally in
- * cfg->tune_cache).  Returns CG_OK. */
+ * cfg->tune_cache).  Returns CG_OK (fixed point: nothing to tune). */
 int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision);
 /* Pins the tile shape for a grid shape: tile height (rows per wavefront
  * strip), grid size (0 = occupancy-derived) and columns per lane (0 = default:

@@ -113,11 +113,13 @@ int cg_dot(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* a
 int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   if (!ctx || !info) return CG_E_INVALID;
   if (!prob || prob->nx < 1 || prob->ny < 1) return CG_E_INVALID;
+  if (prob->precision == CG_PREC_FIXED && !cgk::fixed_fits(prob->nx, prob->ny))
+    return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   cgr::Plan pl = c->plan(prob);
   memset(info, 0, sizeof(*info));
-  info->path = pl.rr ? 2 : pl.wg ? 1 : 0;
+  info->path = pl.fixed ? 3 : pl.rr ? 2 : pl.wg ? 1 : 0;
   info->seg_rows = pl.rr ? cgk::kRrRows : 0;
   info->seg_waves = pl.rr ? pl.rr_threads / cgk::kWave : 0;
   info->seg_cols = pl.rr ? prob->nx + 1 : 0;
@@ -144,6 +146,7 @@ int cg_validate(const cg_problem* prob) { return cgr::validate(prob); }
 int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision) {
   if (!ctx || nx < 1 || ny < 1) return CG_E_INVALID;
   if (variant != CG_VARIANT_CLASSIC && variant != CG_VARIANT_PIPELINED) return CG_E_INVALID;
+  if (precision == CG_PREC_FIXED) return CG_OK;  // one work-group, no tile shape
   if (precision != CG_PREC_FP64 && precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);

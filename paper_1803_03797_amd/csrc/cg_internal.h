@@ -167,7 +167,31 @@ struct Item {
   int32_t slot, t0, t1, pad_;
 };
 
-// Host-side launchers (cg_kernels.hip).
+// Fixed-point variant (cg_fixed.hip): values are Q20.30 held as int64 counts
+// of 2^-30 in [-2^49, 2^49 - 1] (the paper's 50-bit format with 20 integer
+// bits, round to nearest with ties up, saturation).  One work-group of up to
+// kFxThreads threads runs a whole solve: thread t owns unknowns t + e*T
+// (e < kFxMaxE); two full vectors sit in LDS (kFxMaxDof int64 each, with the
+// sum slots filling the 160 KiB of a work-group exactly).
+constexpr int kFxThreads = 1024;
+constexpr int kFxMaxE = 10;
+constexpr int kFxMaxDof = 10176;
+//SA
+
+inline bool fixed_fits(int nx, int ny) {
+  return nx >= 1 && ny >= 1 && (int64_t)nx * ny <= kFxMaxDof;
+}
+
+struct FxArgs {
+  Geo g;
+  const double* b;  // staged right-hand side (pitched FP64)
+  double* x;        // staged x0 in, solution out (pitched FP64)
+  int64_t* bq;      // quantized b, compact nx*ny
+  int64_t* xq;      // pipelined: quantized x, compact nx*ny
+  State* S[2];      // tol and maxit in S[0]; the final state lands in both
+};
+
+// Host-side launchers (cg_kernels.hip, cg_fixed.hip).
 hipError_t launch_pass(int kind, int fp32_geometry, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_final(const PassArgs& a, hipStream_t s);  // res2 = sum of slot 0
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
@@ -178,6 +202,15 @@ hipError_t launch_solve_rr(int variant, const PassArgs& a, int threads, hipStrea
 // One register-resident solve per listed slot (slots[idx[i]], i < n), each
 // fitting the solver; final states land in both state buffers, kind K_DONE.
 hipError_t launch_solve_rr_many(const Slot* slots, const int* idx, int n, hipStream_t s);
+// Whole fixed-point solve in one work-group of `threads` threads:
+// fixed_fits(nx, ny), nx * ny <= threads * kFxMaxE, threads a multiple of 64
+// no larger than kFxThreads.
+hipError_t launch_solve_fixed(int variant, const FxArgs& a, int threads, hipStream_t s);
+// One fixed-point solve per listed slot (slots[idx[i]], i < n), each
+// fixed_fits; the slot's r holds the quantized b and its z (pipelined) or
+// PC[0] (classic) the quantized x.  Final states land in both state buffers,
+// kind K_DONE.
+hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the

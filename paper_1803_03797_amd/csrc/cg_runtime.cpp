@@ -55,7 +55,10 @@ int validate(const cg_problem* p) {
   if (!p->b || !p->x) return CG_E_INVALID;
   if (p->mem != CG_MEM_HOST && p->mem != CG_MEM_DEVICE) return CG_E_INVALID;
   if (p->variant != CG_VARIANT_CLASSIC && p->variant != CG_VARIANT_PIPELINED) return CG_E_INVALID;
-  if (p->precision != CG_PREC_FP64 && p->precision != CG_PREC_FP32_REFINED) return CG_E_INVALID;
+  if (p->precision != CG_PREC_FP64 && p->precision != CG_PREC_FP32_REFINED &&
+      p->precision != CG_PREC_FIXED)
+    return CG_E_INVALID;
+  if (p->precision == CG_PREC_FIXED && !fixed_fits(p->nx, p->ny)) return CG_E_INVALID;
   if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
     return CG_E_INVALID;
   return CG_OK;
@@ -114,6 +117,13 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   pl.fp32g = pl.refined ? 1 : 0;
   pl.wg = use_wg(p);
   pl.rr = allow_rr && use_rr(p);
+  pl.fixed = p->precision == CG_PREC_FIXED;
+  if (pl.fixed) {
+    // one unknown per thread up to 1024 unknowns, then 1024 threads
+    const int64_t dof = (int64_t)p->nx * p->ny;
+    pl.wg = true;
+    pl.fx_threads = (int)std::min<int64_t>(kFxThreads, round_up((size_t)dof, (size_t)kWave));
+  }
   if (pl.rr) {
     pl.wg = true;
     pl.rr_threads = (int)round_up((size_t)rr_threads_needed(p->nx, p->ny), (size_t)kWave);
@@ -569,6 +579,31 @@ static int solve_wg(Ctx& c, Work& w, const cg_problem* p, State& s) {
   return read_state(c, w, s);
 }
 
+static int solve_fixed(Ctx& c, Work& w, const cg_problem* p, State& s) {
+  FxArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = w.pl.g;
+  a.b = w.b;
+  a.x = w.x;
+  a.bq = reinterpret_cast<int64_t*>(w.r);
+  a.xq = reinterpret_cast<int64_t*>(p->variant == CG_VARIANT_PIPELINED ? w.z : w.pc[0]);
+  a.S[0] = w.S[0];
+  a.S[1] = w.S[1];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.prof) {
+    e0 = c.event();
+    e1 = c.event();
+    hipEventRecord(e0, c.st);
+  }
+  HIPCHK(launch_solve_fixed(p->variant, a, w.pl.fx_threads, c.st));
+  if (c.prof) {
+    hipEventRecord(e1, c.st);
+    c.pending.push_back({e0, e1, "solve_fixed", 0.0});
+  }
+  w.m = 1;
+  return read_state(c, w, s);
+}
+
 static int solve_rr(Ctx& c, Work& w, const cg_problem* p, State& s) {
   PassArgs a = base_args(w);
   a.st_in = w.S[0];
@@ -604,7 +639,10 @@ int Ctx::solve(const cg_problem* p, cg_result* res) {
   if (rc) return rc;
   if ((rc = stage_in(c, w, p))) return rc;
   State s;
-  rc = w.pl.rr ? solve_rr(c, w, p, s) : w.pl.wg ? solve_wg(c, w, p, s) : solve_tiled(c, w, p, s);
+  rc = w.pl.fixed ? solve_fixed(c, w, p, s)
+       : w.pl.rr  ? solve_rr(c, w, p, s)
+       : w.pl.wg  ? solve_wg(c, w, p, s)
+                  : solve_tiled(c, w, p, s);
   if (rc) return rc;
   if ((rc = stage_out(c, w, p, s))) return rc;
   fill_result(s, res, now_s() - t0, w.pl.refined);

@@ -20,6 +20,9 @@ struct Plan {
   bool wg = false;   // whole solve inside one work-group
   bool rr = false;   // ... with the vectors on chip (register-resident solver)
   int rr_threads = 0;
+  bool fixed = false;  // fixed-point solve, one work-group (cg_fixed.hip)
+  int fx_threads = 0;
+  bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};
   int grid = 8;      // work-groups per pass
   size_t v64 = 0, v32 = 0, part = 0, footprint = 0;

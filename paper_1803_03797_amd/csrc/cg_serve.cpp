@@ -165,6 +165,7 @@ class Engine {
     j->slot = slot;
     j->t_admit = now_s();
     if (w.pl.rr) rr_new_.push_back(slot);
+    else if (w.pl.fixed) fx_new_.push_back(slot);
     else ++step_jobs_;
     // a solve finishes within 5 maxit + 16 passes: 2 per inner iteration and
     // at most 3 per outer step, each outer step taking an inner iteration
@@ -179,18 +180,22 @@ class Engine {
   int run(int steps) {
     if (!active_) return CG_OK;
     if (dirty_ && upload_items()) return CG_E_DEVICE;
-    if (!rr_new_.empty()) {
-      // newly admitted small solves: whole solves on the side stream, after
-      // their staging on the main stream
-      const int n = (int)rr_new_.size();
-      memcpy(h_rr_idx_, rr_new_.data(), (size_t)n * sizeof(int));
-      if (hipMemcpyAsync(d_rr_idx_, h_rr_idx_, (size_t)n * sizeof(int), hipMemcpyHostToDevice,
-                         c_.st) ||
+    if (!rr_new_.empty() || !fx_new_.empty()) {
+      // newly admitted small and fixed-point solves: whole solves on the side
+      // stream, after their staging on the main stream (slot lists of both
+      // kinds side by side in one index buffer; each slot is listed once)
+      const int nr = (int)rr_new_.size(), nf = (int)fx_new_.size();
+      memcpy(h_rr_idx_, rr_new_.data(), (size_t)nr * sizeof(int));
+      memcpy(h_rr_idx_ + nr, fx_new_.data(), (size_t)nf * sizeof(int));
+      if (hipMemcpyAsync(d_rr_idx_, h_rr_idx_, (size_t)(nr + nf) * sizeof(int),
+                         hipMemcpyHostToDevice, c_.st) ||
           hipEventRecord(stage_ev_, c_.st) || hipStreamWaitEvent(c_.side, stage_ev_, 0) ||
-          launch_solve_rr_many(d_slots_, d_rr_idx_, n, c_.side) ||
+          (nr && launch_solve_rr_many(d_slots_, d_rr_idx_, nr, c_.side)) ||
+          (nf && launch_solve_fixed_many(d_slots_, d_rr_idx_ + nr, nf, c_.side)) ||
           hipEventRecord(rr_ev_, c_.side))
         return CG_E_DEVICE;
       rr_new_.clear();
+      fx_new_.clear();
       rr_pending_ = true;
     }
     if (!step_jobs_) return CG_OK;
@@ -271,7 +276,7 @@ class Engine {
         fill_result(s, &j->res, j->t_done - j->t_admit, j->w.pl.refined);
         j->rc = j->res.status;
       }
-      if (!j->w.pl.rr) --step_jobs_;
+      if (!j->w.pl.on_side()) --step_jobs_;
       c_.arena.release(j->w.mem);
       j->w.mem = nullptr;
       slot_job_[i] = nullptr;
@@ -288,6 +293,7 @@ class Engine {
     if (rr_pending_) hipStreamSynchronize(c_.side);
     rr_pending_ = false;
     rr_new_.clear();
+    fx_new_.clear();
     step_jobs_ = 0;
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
@@ -312,7 +318,7 @@ class Engine {
     int n = 0;
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
-      if (!j || j->w.pl.rr) continue;
+      if (!j || j->w.pl.on_side()) continue;
       const int T = j->w.pl.g.tiles;
       const int per = (T + kMaxItemsPerSolve - 1) / kMaxItemsPerSolve;
       for (int t = 0; t < T; t += per) h_items_[n++] = Item{i, t, std::min(T, t + per), 0};
@@ -354,6 +360,7 @@ class Engine {
   State* h_states_ = nullptr;
   std::vector<Job*> slot_job_;
   std::vector<int> rr_new_;  // slots of register-resident solves not yet launched
+  std::vector<int> fx_new_;  // slots of fixed-point solves not yet launched
   int* d_rr_idx_ = nullptr;
   int* h_rr_idx_ = nullptr;
   hipEvent_t rr_ev_ = nullptr, stage_ev_ = nullptr;

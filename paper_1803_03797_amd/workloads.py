@@ -107,6 +107,18 @@ def serve_rhs(m: int, nx: int, ny: int):
     return uniform_rhs(nx, ny, generator(4, m + 1))
 
 
+# -- fixed point: the paper's synthesized grids and iteration counts (Section
+# III tables: N = 16, 32, 40, 100 with 33, 60, 80, 120 iterations, 50-bit
+# values with 20 integer bits); b ~ U[-1, 1] keeps (b, b) far below the
+# format's 2^19 ceiling.  The measured batch: 256 solves of the largest grid.
+FIXED = dict(sides=(16, 32, 40, 100), iterations=(33, 60, 80, 120), batch=256)
+
+
+def fixed_rhs(n: int, item: int = 0):
+    """b ~ U[-1, 1] on the n x n grid; stream (6, n * 1000 + item)."""
+    return uniform_rhs(n, n, generator(6, n * 1000 + item))
+
+
 def poisson_arrivals(count: int, rate: float, seed_item: int = 0):
     """Arrival times (seconds) of a Poisson process of the given rate."""
     rng = generator(5, seed_item)

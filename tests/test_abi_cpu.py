@@ -45,7 +45,9 @@ def _prob(**kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
                                  dict(tol=float("nan")), dict(maxit=0), dict(b=None),
                                  dict(x=None), dict(mem=7), dict(variant=2), dict(precision=5),
-                                 dict(precision=1, inner_tol=1.5)])
+                                 dict(precision=1, inner_tol=1.5), dict(precision=3),
+                                 dict(precision=2, nx=101, ny=101),
+                                 dict(precision=2, nx=1, ny=10177)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -53,6 +55,10 @@ def test_validation_rejects(bad):
 def test_validation_accepts():
     assert cg.cg_validate(_prob()) == cg.CG_OK
     assert cg.cg_validate(_prob(tol=0.0, precision=1, inner_tol=0.0)) == cg.CG_OK
+    # fixed point: up to 10176 unknowns, any shape; inner_tol is ignored
+    for nx, ny in ((1, 1), (100, 100), (96, 106), (1, 10176), (10176, 1)):
+        assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
+    assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
 
 
 def test_footprint_per_unknown():
