@@ -25,6 +25,9 @@ Other workloads (one JSON line each, not the headline):
   --workload serve   request stream with Poisson arrivals: served
                      (continuous batching) FP32-refined and FP64 vs
                      per-request FP64
+  --workload fixed   the paper's fixed-point format (Q20.30): solve latency on
+                     its synthesized grids and iteration counts, and a batch of
+                     256 solves of its largest grid in one launch
   --probe            attainable HBM bandwidth of plain streaming kernels
 """
 import argparse
@@ -48,6 +51,14 @@ BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
 # copy kernel gives for the same counters); set to None whenever pcg_pass
 # changes, until the counters are taken again.
 PCG_TRAFFIC_BYTES = 1634008205
+# Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
+# iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
+# pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
+# four 32 x 32 -> 64-bit multiplies of two-limb operands; peak: 256 CUs x
+# 64 lanes x 2.4 GHz at the quarter rate of 32-bit integer multiplies.
+FX_PRODUCTS = {"classic": 5, "pipelined": 8}
+FX_MULS_PER_PRODUCT = 4
+FX_MUL_PEAK_G = 256 * 64 * 2.4 / 4  # Gmul/s
 
 
 def log(*a):
@@ -330,6 +341,112 @@ def bench_batch(args):
     ctx.close()
 
 
+# --------------------------------------------------------------------- fixed --
+
+def bench_fixed(args):
+    torch, cg = setup()
+    import numpy as np
+
+    from paper_1803_03797_amd import workloads
+    W = workloads.FIXED
+    FX = cg.CG_PREC_FIXED
+    names = ((0, "classic"), (1, "pipelined"))
+    ctx = cg.Context(device=0, arena_bytes=2 << 30)
+    reps = args.count or 50
+    latency = {}
+    for n, iters in zip(W["sides"], W["iterations"]):
+        b = torch.from_numpy(workloads.fixed_rhs(n)).cuda()
+        x = torch.zeros_like(b)
+        row = {}
+        for v, name in names:
+            p = cg.make_problem(b, x, n, n, tol=0.0, maxit=iters, variant=v, precision=FX)
+            for _ in range(3):
+                ctx.cg_solve(p)
+            lat = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                rc, r = ctx.cg_solve(p)
+                lat.append(time.perf_counter() - t)
+            ctx.cg_set_profiling(True)
+            ctx.cg_kernel_stats(reset=True)
+            for _ in range(5):
+                ctx.cg_solve(p)
+            ks = kern_table(ctx.cg_kernel_stats(reset=True))
+            ctx.cg_set_profiling(False)
+            k_us = ks["solve_fixed"]["avg_us"]
+            row[name] = dict(status=cg.cg_status_str(rc), iterations=r.iterations,
+                             p50_ms=round(float(np.median(lat)) * 1e3, 4),
+                             kernel_us=k_us, us_per_iteration=round(k_us / iters, 3))
+        latency["%dx%d/%d it" % (n, n, iters)] = row
+        log("fixed latency", n, json.dumps(row))
+    # throughput: W["batch"] solves of the largest grid in one launch per variant
+    n, iters = W["sides"][-1], W["iterations"][-1]
+    count = W["batch"]
+    bs = [torch.from_numpy(workloads.fixed_rhs(n, m)).cuda() for m in range(count)]
+    xs = [torch.zeros_like(b) for b in bs]
+    batch, roof = {}, {}
+    for v, name in names:
+        probs = [cg.make_problem(b, x, n, n, tol=0.0, maxit=iters, variant=v, precision=FX)
+                 for b, x in zip(bs, xs)]
+        ctx.cg_solve_batch(probs[:8])
+        torch.cuda.synchronize()
+        walls = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            rc, res = ctx.cg_solve_batch(probs)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        assert rc == cg.CG_OK and all(r.iterations == iters for r in res)
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        for _ in range(3):
+            ctx.cg_solve_batch(probs)
+        ks = kern_table(ctx.cg_kernel_stats(reset=True))
+        ctx.cg_set_profiling(False)
+        k_s = ks["solve_fixed_many"]["avg_us"] * 1e-6
+        wall = float(np.median(walls))
+        work = count * n * n * iters
+        muls = work * FX_PRODUCTS[name] * FX_MULS_PER_PRODUCT
+        batch[name] = dict(solves=count, wall_s=round(wall, 5),
+                           solves_per_s=round(count / wall, 1),
+                           GDOF_iter_s=round(work / wall / 1e9, 3),
+                           kernel_ms=round(k_s * 1e3, 4),
+                           GDOF_iter_s_kernel=round(work / k_s / 1e9, 3))
+        roof[name] = {"bound": "alu", "achieved": round(muls / k_s / 1e9, 1),
+                      "peak": FX_MUL_PEAK_G, "unit": "Gmul/s",
+                      "frac": round(muls / k_s / 1e9 / FX_MUL_PEAK_G, 4), "traffic": None}
+        log("fixed batch", name, json.dumps(batch[name]))
+    cpu = None
+    if not args.no_cpu:
+        import oracle.oracle as oo
+        cpu = {}
+        for v, name in names:
+            t = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t < 4.0 and k < 50:
+                oo.cg_fixed(bs[k].cpu().numpy(), n, n, variant=v, tol=0.0, maxit=iters)
+                k += 1
+            dt = time.perf_counter() - t
+            cpu[name] = round(k * n * n * iters / dt / 1e9, 5)
+        cpu = {"value": cpu, "unit": "GDOF-iter/s", "cores": 1, "kind": "oracle",
+               "sample": "consecutive %dx%d solves of %d iterations per variant for about "
+                         "4 s, plain C with __int128, single thread" % (n, n, iters)}
+    value = sum(batch[nm]["GDOF_iter_s"] for _, nm in names) / 2
+    emit({"metric": "fixed-point GDOF-iter/s (batch of %d %dx%d solves, %d iterations)"
+                    % (count, n, n, iters),
+          "workload": "fixed", "value": round(value, 3), "unit": "GDOF-iter/s",
+          "config": {"workload": "Q20.30 fixed point; paper grids %s with %s iterations, "
+                                 "b~U[-1,1] seeded, x0=0, tol 0" % (list(W["sides"]),
+                                                                     list(W["iterations"])),
+                     "batch": count},
+          "dtype": "q20.30 (int64)", "latency": latency, "batch": batch, "roofline": roof,
+          "cpu_baseline": cpu,
+          "paper_context": "FPGA latency at the largest FACTOR (Tables resCG/resNewCG, 100 MHz): "
+                           "N=16 CG 0.15 / NewCG 0.10 ms; N=32 0.40 / 0.26 ms; N=40 0.46 / "
+                           "0.29 ms; N=100 2.66 / 1.81 ms"})
+    ctx.close()
+
+
 # ---------------------------------------------------------------------- huge --
 
 def bench_huge(args):
@@ -540,7 +657,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
-    ap.add_argument("--workload", choices=["small", "batch", "huge", "serve"])
+    ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed"])
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="with --probe: only the 134 MB copy used for counter calibration")
@@ -564,6 +681,8 @@ def main():
         return bench_batch(args)
     if args.workload == "huge":
         return bench_huge(args)
+    if args.workload == "fixed":
+        return bench_fixed(args)
     if args.workload == "serve":
         args.count = args.count or 400
         return bench_serve(args)

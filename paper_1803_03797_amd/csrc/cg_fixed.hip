@@ -26,10 +26,14 @@
 // after the work-group sum.
 //
 // One work-group runs a whole solve (the paper's grids reach 100 x 100):
-// thread t owns unknowns k = t + e T, e < kFxMaxE.  LDS holds two full
+// thread t owns unknowns k = t + e T, e < E, the kernel being compiled for
+// E = 1, 2, 3, 4, 6, 8 or 10 (the launch takes the smallest that covers the
+// grid: small grids get small code and few registers).  LDS holds two full
 // vectors, the operand of the stencil (neighbours outside the grid read as
 // zero by predicate) and one more vector; the rest of the per-unknown state
-// lives in registers, Algorithm 2's x in global memory.  Scalars are summed
+// lives in registers, Algorithm 2's x (and q from E = 8) in global memory.
+// The scalars of a converging solve take update forms without 64-bit
+// products (fx_upd); a uniform branch falls back to the general form.  Scalars are summed
 // by a wave butterfly, one LDS slot per wave and a second butterfly over the
 // slots; each thread then computes the same quotients, so no broadcast is
 // needed.  Barriers per iteration: classic 3 (direction published, (p, s)
@@ -82,30 +86,38 @@ __device__ __forceinline__ int64_t fx_axpy(FxSplit a, int64_t x, int64_t y) {
   return fx_clamp(hh * kFxOne + rest);
 }
 
-// The same for a scalar with |ah| < 2^13 (every alpha and beta of a
-// converging solve): Q(a x) = ah x + al xh + floor((al xl + 2^29) / 2^30),
-// since ah 2^30 x / 2^30 is an integer; |ah x| < 2^62 keeps the int64 sum
-// exact, and one clamp saturates it.
-template <bool SMALL>
+// A cheaper exact form of Q(y + a x) for the scalars of a converging solve:
+// Q(a x) = ah x + al xh + floor((al xl + 2^29) / 2^30), as ah 2^30 x / 2^30
+// is an integer.  ZERO (ah = 0: 0 <= a < 1, every alpha and beta in practice)
+// and NEG (ah = -1: -1 <= a < 0, -alpha) need no 64-bit product and no
+// saturation test of the product: the int64 sum is exact, one clamp
+// saturates it.  GENERAL is fx_axpy.
+enum { FX_GENERAL = 0, FX_ZERO = 2, FX_NEG = 3 };
+
+template <int M>
 __device__ __forceinline__ int64_t fx_upd(FxSplit a, int64_t x, int64_t y) {
-  if constexpr (SMALL) {
-    const FxSplit s = fx_split(x);
-    return fx_clamp((int64_t)a.h * x + (int64_t)a.l * s.h + fx_low(a.l, s.l) + y);
-  } else {
+  if constexpr (M == FX_GENERAL) {
     return fx_axpy(a, x, y);
+  } else {
+    const FxSplit s = fx_split(x);
+    const int64_t part = (int64_t)a.l * s.h + fx_low(a.l, s.l) + y;
+    if constexpr (M == FX_ZERO) return fx_clamp(part);
+    else return fx_clamp(part - x);
   }
 }
 
-__device__ __forceinline__ bool fx_small(FxSplit a) {
-  return a.h > -(1 << 13) && a.h < (1 << 13);
+// Runs f with std::true_type when `common` (a work-group-uniform flag: the
+// update phase's scalars take the ZERO / NEG forms), std::false_type
+// otherwise (GENERAL throughout).
+template <class F>
+__device__ __forceinline__ void fx_with(bool common, F&& f) {
+  if (common) f(std::true_type{});
+  else f(std::false_type{});
 }
 
-// Runs f with the short update form when `small` (a work-group-uniform
-// flag), with the general one otherwise.
-template <class F>
-__device__ __forceinline__ void fx_with(bool small, F&& f) {
-  if (small) f(std::integral_constant<bool, true>{});
-  else f(std::integral_constant<bool, false>{});
+template <bool COMMON, int M>
+constexpr int fx_form() {
+  return COMMON ? M : FX_GENERAL;
 }
 
 // Exact running sum of Q(u v): u v rounded = h 2^30 + m.
@@ -117,6 +129,13 @@ __device__ __forceinline__ void fx_acc(FxAcc& a, int64_t u, int64_t v) {
   const FxSplit su = fx_split(u), sv = fx_split(v);
   a.h += (int64_t)su.h * sv.h;
   a.m += (int64_t)su.h * sv.l + (int64_t)su.l * sv.h + fx_low(su.l, sv.l);
+}
+
+// the same for Q(u u): the two cross products are equal
+__device__ __forceinline__ void fx_acc_sq(FxAcc& a, int64_t u) {
+  const FxSplit su = fx_split(u);
+  a.h += (int64_t)su.h * su.h;
+  a.m += ((int64_t)su.h * su.l) * 2 + fx_low(su.l, su.l);
 }
 
 // moves the multiples of 2^30 of m into h, leaving 0 <= m < 2^30
@@ -256,8 +275,12 @@ __device__ void fx_publish(const FxArgs& a, int status, int it, int64_t gamma, i
 // both nx * ny entries, then the sum slots.  Registers hold r and x
 // (Algorithm 1) or z, q and r (Algorithm 2); Algorithm 2's x stays in global
 // memory (xq), read and written once per iteration by its owner.
-template <int VARIANT>
-__device__ void fx_solve(const FxArgs& a, int64_t* lds) {
+template <int VARIANT, int E>
+__device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
+  // Algorithm 2 with 8 or more unknowns per thread keeps q in global memory
+  // too (qg): three register vectors of that many unknowns spill (measured:
+  // 100 x 100 runs 16% slower with q in registers).
+  constexpr bool QG = VARIANT == 1 && E >= 8;
   const int T = blockDim.x, t = threadIdx.x;
   const int nx = a.g.nx, ny = a.g.ny, pitch = a.g.pitch, n = nx * ny;
   int64_t* O = lds;
@@ -268,40 +291,43 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
   const int maxit = a.S[0]->maxit;
 
   // unknown k = t + e T at column i, row j: ij = i | j << 16, -1 if unowned
-  int ij[kFxMaxE];
+  int ij[E];
 #pragma unroll
-  for (int e = 0; e < kFxMaxE; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int k = t + e * T, j = k / nx;
     ij[e] = k < n ? (k - j * nx) | (j << 16) : -1;
   }
 
-  // quantized inputs; x0 is the first operand (r = b - A x)
-  int64_t bv[kFxMaxE], xv[kFxMaxE];
+  // quantized inputs; x0 is the first operand (r = b - A x).  b goes to bq
+  // and is read back by its owner (no register copy to hold meanwhile).
+  int64_t xv[E];
   FxAcc acc[2] = {{0, 0}, {0, 0}};
 #pragma unroll
-  for (int e = 0; e < kFxMaxE; ++e) {
-    bv[e] = xv[e] = 0;
+  for (int e = 0; e < E; ++e) {
+    xv[e] = 0;
     if (ij[e] >= 0) {
       const int k = t + e * T, gk = (ij[e] >> 16) * pitch + (ij[e] & 0xffff);
-      bv[e] = fx_from(a.b[gk]);
+      const int64_t bv = fx_from(a.b[gk]);
       xv[e] = fx_from(a.x[gk]);
-      a.bq[k] = bv[e];
+      a.bq[k] = bv;
       if constexpr (VARIANT == 1) {
         a.xq[k] = xv[e];
         V[k] = 0;  // p
+        if constexpr (QG) a.qg[k] = 0;
       }
       O[k] = xv[e];
-      fx_acc(acc[0], bv[e], bv[e]);
+      fx_acc_sq(acc[0], bv);
     }
   }
   __syncthreads();
-  int64_t r[kFxMaxE];
+  int64_t r[E];
 #pragma unroll
-  for (int e = 0; e < kFxMaxE; ++e) {
+  for (int e = 0; e < E; ++e) {
     r[e] = 0;
     if (ij[e] >= 0) {
-      r[e] = fx_clamp(bv[e] - fx_stencil(O, t + e * T, ij[e], nx, ny));
-      fx_acc(acc[1], r[e], r[e]);
+      const int k = t + e * T;
+      r[e] = fx_clamp(a.bq[k] - fx_stencil(O, k, ij[e], nx, ny));
+      fx_acc_sq(acc[1], r[e]);
     }
   }
   int64_t s2[2];
@@ -329,19 +355,20 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
     for (;;) {
       if ((status = stop(gamma, it)) != ST_RUNNING) break;
       const FxSplit sb = fx_split(beta);
-      fx_with(fx_small(sb), [&](auto small) {
+      fx_with(sb.h == 0, [&](auto common) {
+        constexpr int MB = fx_form<common(), FX_ZERO>();
 #pragma unroll
-        for (int e = 0; e < kFxMaxE; ++e) {
+        for (int e = 0; e < E; ++e) {
           if (ij[e] >= 0) {
             const int k = fx_opaque(t) + e * T;
-            O[k] = it == 0 ? r[e] : fx_upd<small()>(sb, O[k], r[e]);
+            O[k] = it == 0 ? r[e] : fx_upd<MB>(sb, O[k], r[e]);
           }
         }
       });
       __syncthreads();
       FxAcc api[1] = {{0, 0}};
 #pragma unroll
-      for (int e = 0; e < kFxMaxE; ++e) {
+      for (int e = 0; e < E; ++e) {
         if (ij[e] >= 0) {
           const int k = fx_opaque(t) + e * T;
           const int64_t sv = fx_stencil(O, k, ij[e], nx, ny);
@@ -358,14 +385,15 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
       const int64_t alpha = fx_div(gamma, pi[0]);
       const FxSplit sa = fx_split(alpha), sna = fx_split(-alpha);
       FxAcc ag[1] = {{0, 0}};
-      fx_with(fx_small(sa) && fx_small(sna), [&](auto small) {
+      fx_with(sa.h == 0 && sna.h == -1, [&](auto common) {
+        constexpr int MA = fx_form<common(), FX_ZERO>(), MNA = fx_form<common(), FX_NEG>();
 #pragma unroll
-        for (int e = 0; e < kFxMaxE; ++e) {
+        for (int e = 0; e < E; ++e) {
           if (ij[e] >= 0) {
             const int k = fx_opaque(t) + e * T;
-            xv[e] = fx_upd<small()>(sa, O[k], xv[e]);
-            r[e] = fx_upd<small()>(sna, V[k], r[e]);
-            fx_acc(ag[0], r[e], r[e]);
+            xv[e] = fx_upd<MA>(sa, O[k], xv[e]);
+            r[e] = fx_upd<MNA>(sna, V[k], r[e]);
+            fx_acc_sq(ag[0], r[e]);
           }
         }
       });
@@ -378,31 +406,35 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
   } else {
     // Algorithm 2: w = A r and delta = (w, r) first; then w in O, p in V
 #pragma unroll
-    for (int e = 0; e < kFxMaxE; ++e)
+    for (int e = 0; e < E; ++e)
       if (ij[e] >= 0) O[t + e * T] = r[e];
     __syncthreads();
-    int64_t z[kFxMaxE];
-    FxAcc ad[1] = {{0, 0}};
+    int64_t delta;
+    {
+      int64_t w0[E];
+      FxAcc ad[1] = {{0, 0}};
 #pragma unroll
-    for (int e = 0; e < kFxMaxE; ++e) {
-      z[e] = 0;
-      if (ij[e] >= 0) {
-        z[e] = fx_stencil(O, t + e * T, ij[e], nx, ny);  // w, parked in z
-        fx_acc(ad[0], z[e], r[e]);
+      for (int e = 0; e < E; ++e) {
+        w0[e] = 0;
+        if (ij[e] >= 0) {
+          w0[e] = fx_stencil(O, t + e * T, ij[e], nx, ny);
+          fx_acc(ad[0], w0[e], r[e]);
+        }
       }
-    }
-    int64_t d1[1];
-    fx_sum<1>(ad, red, par, d1);
-    int64_t delta = d1[0];
+      int64_t d1[1];
+      fx_sum<1>(ad, red, par, d1);
+      delta = d1[0];
 #pragma unroll
-    for (int e = 0; e < kFxMaxE; ++e) {
-      if (ij[e] >= 0) O[t + e * T] = z[e];
-      z[e] = 0;
+      for (int e = 0; e < E; ++e)
+        if (ij[e] >= 0) O[t + e * T] = w0[e];
     }
     __syncthreads();
-    int64_t q[kFxMaxE];
+    int64_t z[E];
 #pragma unroll
-    for (int e = 0; e < kFxMaxE; ++e) q[e] = 0;
+    for (int e = 0; e < E; ++e) z[e] = 0;
+    int64_t q[QG ? 1 : E];
+#pragma unroll
+    for (int e = 0; e < (QG ? 1 : E); ++e) q[e] = 0;
     int64_t alpha = 0, gamma_old = 0;
     for (;;) {
       if ((status = stop(gamma, it)) != ST_RUNNING) break;
@@ -427,33 +459,42 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
         alpha = fx_div(kFxOne, den);
       }
       const FxSplit sb = fx_split(beta), sa = fx_split(alpha), sna = fx_split(-alpha);
-      const bool small = fx_small(sb) && fx_small(sa) && fx_small(sna);
+      const bool common = sb.h == 0 && sa.h == 0 && sna.h == -1;
       // n = A w and z = n + beta z (first iteration: beta = 0, z = q = p = 0)
-      fx_with(small, [&](auto sm) {
+      fx_with(common, [&](auto cm) {
+        constexpr int MB = fx_form<cm(), FX_ZERO>();
 #pragma unroll
-        for (int e = 0; e < kFxMaxE; ++e) {
+        for (int e = 0; e < E; ++e) {
           if (ij[e] >= 0) {
             const int k = fx_opaque(t) + e * T;
-            z[e] = fx_upd<sm()>(sb, z[e], fx_stencil(O, k, ij[e], nx, ny));
+            z[e] = fx_upd<MB>(sb, z[e], fx_stencil(O, k, ij[e], nx, ny));
           }
         }
       });
       __syncthreads();  // w is overwritten below
       FxAcc gd[2] = {{0, 0}, {0, 0}};
-      fx_with(small, [&](auto sm) {
+      fx_with(common, [&](auto cm) {
+        constexpr int MB = fx_form<cm(), FX_ZERO>(), MA = fx_form<cm(), FX_ZERO>();
+        constexpr int MNA = fx_form<cm(), FX_NEG>();
 #pragma unroll
-        for (int e = 0; e < kFxMaxE; ++e) {
+        for (int e = 0; e < E; ++e) {
           if (ij[e] >= 0) {
             const int k = fx_opaque(t) + e * T;
             const int64_t w = O[k];
-            q[e] = fx_upd<sm()>(sb, q[e], w);
-            const int64_t p = fx_upd<sm()>(sb, V[k], r[e]);
+            int64_t qe;
+            if constexpr (QG) {
+              qe = fx_upd<MB>(sb, a.qg[k], w);
+              a.qg[k] = qe;
+            } else {
+              qe = q[e] = fx_upd<MB>(sb, q[e], w);
+            }
+            const int64_t p = fx_upd<MB>(sb, V[k], r[e]);
             V[k] = p;
-            a.xq[k] = fx_upd<sm()>(sa, p, a.xq[k]);
-            r[e] = fx_upd<sm()>(sna, q[e], r[e]);
-            const int64_t wn = fx_upd<sm()>(sna, z[e], w);
+            a.xq[k] = fx_upd<MA>(sa, p, a.xq[k]);
+            r[e] = fx_upd<MNA>(sna, qe, r[e]);
+            const int64_t wn = fx_upd<MNA>(sna, z[e], w);
             O[k] = wn;
-            fx_acc(gd[0], r[e], r[e]);
+            fx_acc_sq(gd[0], r[e]);
             fx_acc(gd[1], wn, r[e]);
           }
         }
@@ -466,23 +507,23 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
       ++it;
     }
 #pragma unroll
-    for (int e = 0; e < kFxMaxE; ++e)
+    for (int e = 0; e < E; ++e)
       if (ij[e] >= 0) xv[e] = a.xq[t + e * T];
   }
 
   // true residual b - A x in the same arithmetic, then x back to FP64
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < kFxMaxE; ++e)
+  for (int e = 0; e < E; ++e)
     if (ij[e] >= 0) O[t + e * T] = xv[e];
   __syncthreads();
   FxAcc at[1] = {{0, 0}};
 #pragma unroll
-  for (int e = 0; e < kFxMaxE; ++e) {
+  for (int e = 0; e < E; ++e) {
     if (ij[e] >= 0) {
       const int k = t + e * T;
       const int64_t tv = fx_clamp(a.bq[k] - fx_stencil(O, k, ij[e], nx, ny));
-      fx_acc(at[0], tv, tv);
+      fx_acc_sq(at[0], tv);
       a.x[(ij[e] >> 16) * pitch + (ij[e] & 0xffff)] = ldexp((double)xv[e], -30);
     }
   }
@@ -491,51 +532,79 @@ __device__ void fx_solve(const FxArgs& a, int64_t* lds) {
   if (t == 0) fx_publish(a, status, it, gamma, bb, tt[0]);
 }
 
-template <int VARIANT>
+template <int VARIANT, int E>
 __global__ __launch_bounds__(kFxThreads) void k_solve_fixed(FxArgs a) {
   __shared__ int64_t lds[2 * kFxMaxDof + kFxRed];
-  fx_solve<VARIANT>(a, lds);
+  fx_solve<VARIANT, E>(a, lds);
 }
 
-// Launched once per variant over the same list: a work-group whose slot runs
-// the other variant returns at once.
-template <int VARIANT>
+// One work-group per listed slot; every listed slot runs VARIANT and has at
+// most kFxThreads * E unknowns.
+template <int VARIANT, int E>
 __global__ __launch_bounds__(kFxThreads) void k_solve_fixed_many(const Slot* slots,
                                                                  const int* idx) {
   __shared__ int64_t lds[2 * kFxMaxDof + kFxRed];
   const Slot& S = slots[__builtin_amdgcn_readfirstlane(idx[blockIdx.x])];
-  if (S.variant != VARIANT) return;
   FxArgs a;
   a.g = S.g;
   a.b = S.b;
   a.x = S.x;
   a.bq = reinterpret_cast<int64_t*>(S.r);
   a.xq = reinterpret_cast<int64_t*>(VARIANT == 1 ? S.z : S.PC[0]);
+  a.qg = reinterpret_cast<int64_t*>(S.q);
   a.S[0] = S.S[0];
   a.S[1] = S.S[1];
-  fx_solve<VARIANT>(a, lds);
+  fx_solve<VARIANT, E>(a, lds);
+}
+
+template <int VARIANT>
+static hipError_t launch_one(int e, const FxArgs& a, int threads, hipStream_t st) {
+  switch (e) {
+    case 1: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 1>), 1, threads, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 2>), 1, threads, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 3>), 1, threads, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 4>), 1, threads, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 6>), 1, threads, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 8>), 1, threads, 0, st, a); break;
+    case 10: hipLaunchKernelGGL((k_solve_fixed<VARIANT, 10>), 1, threads, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int VARIANT>
+static hipError_t launch_many(int e, const Slot* slots, const int* idx, int n, hipStream_t st) {
+  const dim3 g(n), b(kFxThreads);
+  switch (e) {
+    case 1: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 1>), g, b, 0, st, slots, idx); break;
+    case 2: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 2>), g, b, 0, st, slots, idx); break;
+    case 3: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 3>), g, b, 0, st, slots, idx); break;
+    case 4: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 4>), g, b, 0, st, slots, idx); break;
+    case 6: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 6>), g, b, 0, st, slots, idx); break;
+    case 8: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 8>), g, b, 0, st, slots, idx); break;
+    case 10: hipLaunchKernelGGL((k_solve_fixed_many<VARIANT, 10>), g, b, 0, st, slots, idx);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_solve_fixed(int variant, const FxArgs& a, int threads, hipStream_t st) {
   if (!fixed_fits(a.g.nx, a.g.ny) || threads < kWave || threads > kFxThreads ||
-      threads % kWave || (int64_t)a.g.nx * a.g.ny > (int64_t)threads * kFxMaxE ||
-      a.g.pitch < a.g.nx || !a.b || !a.x || !a.bq || (variant == 1 && !a.xq) || !a.S[0] ||
-      !a.S[1])
+      threads % kWave || a.g.pitch < a.g.nx || !a.b || !a.x || !a.bq ||
+      (variant == 1 && (!a.xq || !a.qg)) || !a.S[0] || !a.S[1])
     return hipErrorInvalidValue;
-  if (variant == 1) hipLaunchKernelGGL((k_solve_fixed<1>), dim3(1), dim3(threads), 0, st, a);
-  else hipLaunchKernelGGL((k_solve_fixed<0>), dim3(1), dim3(threads), 0, st, a);
-  return hipGetLastError();
+  const int e = fixed_elems((int64_t)a.g.nx * a.g.ny, threads);
+  return variant == 1 ? launch_one<1>(e, a, threads, st) : launch_one<0>(e, a, threads, st);
 }
 
-hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, hipStream_t st) {
+hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, int variant, int e,
+                                   hipStream_t st) {
   if (n < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_solve_fixed_many<0>), dim3(n), dim3(kFxThreads), 0, st, slots, idx);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_fixed_many<1>), dim3(n), dim3(kFxThreads), 0, st, slots, idx);
-  return hipGetLastError();
+  return variant == 1 ? launch_many<1>(e, slots, idx, n, st)
+                      : launch_many<0>(e, slots, idx, n, st);
 }
 
 }  // namespace cgk

@@ -182,12 +182,20 @@ inline bool fixed_fits(int nx, int ny) {
   return nx >= 1 && ny >= 1 && (int64_t)nx * ny <= kFxMaxDof;
 }
 
+// Unknowns per thread the solver is compiled for (1, 2, 3, 4, 6, 8, 10): the
+// smallest that covers dof unknowns with `threads` threads.
+inline int fixed_elems(int64_t dof, int threads) {
+  const int64_t e = (dof + threads - 1) / threads;
+  return e <= 4 ? (int)(e < 1 ? 1 : e) : e <= 6 ? 6 : e <= 8 ? 8 : 10;
+}
+
 struct FxArgs {
   Geo g;
   const double* b;  // staged right-hand side (pitched FP64)
   double* x;        // staged x0 in, solution out (pitched FP64)
   int64_t* bq;      // quantized b, compact nx*ny
   int64_t* xq;      // pipelined: quantized x, compact nx*ny
+  int64_t* qg;      // pipelined: q, compact nx*ny (used with 8+ unknowns per thread)
   State* S[2];      // tol and maxit in S[0]; the final state lands in both
 };
 
@@ -206,11 +214,14 @@ hipError_t launch_solve_rr_many(const Slot* slots, const int* idx, int n, hipStr
 // fixed_fits(nx, ny), nx * ny <= threads * kFxMaxE, threads a multiple of 64
 // no larger than kFxThreads.
 hipError_t launch_solve_fixed(int variant, const FxArgs& a, int threads, hipStream_t s);
-// One fixed-point solve per listed slot (slots[idx[i]], i < n), each
-// fixed_fits; the slot's r holds the quantized b and its z (pipelined) or
-// PC[0] (classic) the quantized x.  Final states land in both state buffers,
-// kind K_DONE.
-hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, hipStream_t s);
+// One fixed-point solve per listed slot (slots[idx[i]], i < n), all of the
+// given variant and each with at most kFxThreads * e unknowns, e =
+// fixed_elems(dof, kFxThreads) of the largest; the slot's r holds the
+// quantized b, its z (pipelined) or PC[0] (classic) the quantized x, and its
+// q (pipelined) the vector q when it does not stay in registers.
+// Final states land in both state buffers, kind K_DONE.
+hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, int variant, int e,
+                                   hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the

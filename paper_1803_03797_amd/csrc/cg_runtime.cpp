@@ -587,6 +587,7 @@ static int solve_fixed(Ctx& c, Work& w, const cg_problem* p, State& s) {
   a.x = w.x;
   a.bq = reinterpret_cast<int64_t*>(w.r);
   a.xq = reinterpret_cast<int64_t*>(p->variant == CG_VARIANT_PIPELINED ? w.z : w.pc[0]);
+  a.qg = reinterpret_cast<int64_t*>(w.q);
   a.S[0] = w.S[0];
   a.S[1] = w.S[1];
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -185,15 +185,48 @@ class Engine {
       // stream, after their staging on the main stream (slot lists of both
       // kinds side by side in one index buffer; each slot is listed once)
       const int nr = (int)rr_new_.size(), nf = (int)fx_new_.size();
+      // fixed-point slots sorted by (unknowns per thread, variant)
+      std::vector<std::pair<int, int>> fx(nf);
+      for (int i = 0; i < nf; ++i) {
+        const cg_problem& p = slot_job_[fx_new_[i]]->p;
+        const int e = fixed_elems((int64_t)p.nx * p.ny, kFxThreads);
+        fx[i] = {e * 2 + (p.variant == CG_VARIANT_PIPELINED ? 1 : 0), fx_new_[i]};
+      }
+      std::sort(fx.begin(), fx.end());
+      fx_key_.resize(nf);
+      for (int i = 0; i < nf; ++i) {
+        fx_key_[i] = fx[i].first;
+        fx_new_[i] = fx[i].second;
+      }
       memcpy(h_rr_idx_, rr_new_.data(), (size_t)nr * sizeof(int));
       memcpy(h_rr_idx_ + nr, fx_new_.data(), (size_t)nf * sizeof(int));
       if (hipMemcpyAsync(d_rr_idx_, h_rr_idx_, (size_t)(nr + nf) * sizeof(int),
                          hipMemcpyHostToDevice, c_.st) ||
           hipEventRecord(stage_ev_, c_.st) || hipStreamWaitEvent(c_.side, stage_ev_, 0) ||
-          (nr && launch_solve_rr_many(d_slots_, d_rr_idx_, nr, c_.side)) ||
-          (nf && launch_solve_fixed_many(d_slots_, d_rr_idx_ + nr, nf, c_.side)) ||
-          hipEventRecord(rr_ev_, c_.side))
+          (nr && launch_solve_rr_many(d_slots_, d_rr_idx_, nr, c_.side)))
         return CG_E_DEVICE;
+      if (nf) {
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (c_.prof) {
+          f0 = c_.event();
+          f1 = c_.event();
+          hipEventRecord(f0, c_.side);
+        }
+        // one launch per run of equal (variant, unknowns per thread)
+        for (int g0 = 0; g0 < nf;) {
+          int g1 = g0 + 1;
+          while (g1 < nf && fx_key_[g1] == fx_key_[g0]) ++g1;
+          if (launch_solve_fixed_many(d_slots_, d_rr_idx_ + nr + g0, g1 - g0, fx_key_[g0] & 1,
+                                      fx_key_[g0] >> 1, c_.side))
+            return CG_E_DEVICE;
+          g0 = g1;
+        }
+        if (c_.prof) {
+          hipEventRecord(f1, c_.side);
+          c_.pending.push_back({f0, f1, "solve_fixed_many", 0.0});
+        }
+      }
+      if (hipEventRecord(rr_ev_, c_.side)) return CG_E_DEVICE;
       rr_new_.clear();
       fx_new_.clear();
       rr_pending_ = true;
@@ -361,6 +394,7 @@ class Engine {
   std::vector<Job*> slot_job_;
   std::vector<int> rr_new_;  // slots of register-resident solves not yet launched
   std::vector<int> fx_new_;  // slots of fixed-point solves not yet launched
+  std::vector<int> fx_key_;  // their launch keys: unknowns per thread * 2 + variant
   int* d_rr_idx_ = nullptr;
   int* h_rr_idx_ = nullptr;
   hipEvent_t rr_ev_ = nullptr, stage_ev_ = nullptr;

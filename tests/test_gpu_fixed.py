@@ -17,10 +17,12 @@ pytestmark = pytest.mark.gpu
 VARIANTS = (cg.CG_VARIANT_CLASSIC, cg.CG_VARIANT_PIPELINED)
 FX = cg.CG_PREC_FIXED
 
-# one unknown per thread (<= 1024), ragged waves, up to 10 per thread, the
-# largest grid the solver takes (96 x 106 = 10176), single rows and columns
-SHAPES = [(1, 1), (1, 7), (7, 1), (16, 16), (33, 17), (32, 32), (40, 40), (64, 65), (100, 100),
-          (96, 106), (1, 10176), (10176, 1), (127, 80)]
+# one unknown per thread (<= 1024), ragged waves, every compiled count of
+# unknowns per thread (2, 3, 4, 6, 8, 10), the largest grid the solver takes
+# (96 x 106 = 10176), single rows and columns
+SHAPES = [(1, 1), (1, 7), (7, 1), (16, 16), (33, 17), (32, 32), (40, 40), (50, 50), (60, 60),
+          (64, 65), (75, 75), (90, 90), (100, 100), (96, 106), (1, 10176), (10176, 1),
+          (127, 80)]
 
 
 def say(*a):
@@ -186,6 +188,23 @@ def test_batch_mixed_with_fp64(ctx):
             np.testing.assert_array_equal(x, xa)
 
 
+def test_batch_every_compiled_size(ctx):
+    """One launch per (variant, unknowns per thread) group inside a batch:
+    every group size, both variants, each result the oracle's."""
+    rng = np.random.default_rng(77)
+    specs = [(n, v) for n in (7, 40, 50, 60, 75, 90, 100) for v in VARIANTS]
+    rng.shuffle(specs)
+    bs = [rng.uniform(-1, 1, (n, n)) for n, _ in specs]
+    xs = [np.zeros_like(b) for b in bs]
+    probs = [cg.make_problem(b, x, n, n, tol=1e-6, maxit=3000, variant=v, precision=FX)
+             for (n, v), b, x in zip(specs, bs, xs)]
+    say("fixed batch, every size", len(specs))
+    rc, results = ctx.cg_solve_batch(probs)
+    for (n, v), b, x, r in zip(specs, bs, xs, results):
+        xo, _, ro = cg_fixed(b, n, n, variant=v, tol=1e-6, maxit=3000)
+        check_same(r.status, r, x, ro, xo)
+
+
 def test_batch_of_the_paper_grid(ctx):
     """Many copies of the largest paper grid at its synthesized iteration
     count, all in one launch: each bitwise the oracle's."""
@@ -228,3 +247,24 @@ def _poll(c, t):
             return rc, res
         assert time.time() - t0 < 60, "request not finished within a minute"
         time.sleep(0.002)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_huge_step_takes_the_general_update_form(ctx, variant):
+    """A smooth right-hand side whose curvature (p, A p) rounds to a few
+    quanta: the first alpha exceeds 2^13 (updates by the general 128-bit-free
+    form with saturation checks), and the iterates saturate.  Bitwise against
+    the oracle, a few iterations and a natural stop."""
+    from oracle.oracle import fx_div, fx_dot, fx_quantize, fx_spmv
+    nx, ny = 96, 106
+    i, j = np.arange(1, nx + 1), np.arange(1, ny + 1)
+    b = 4.98575750018027e-4 * np.outer(np.sin(np.pi * j / (ny + 1)), np.sin(np.pi * i / (nx + 1)))
+    bq = np.vectorize(fx_quantize)(b).astype(np.int64)
+    alpha = fx_div(fx_dot(bq, bq), fx_dot(bq, fx_spmv(bq, nx, ny)))
+    assert alpha >= 2 ** 43, alpha
+    for tol, maxit in ((0.0, 1), (0.0, 3), (1e-6, 200)):
+        say("fixed general form", variant, tol, maxit)
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, nx, ny, tol=tol, maxit=maxit, variant=variant, precision=FX)
+        xo, _, ro = cg_fixed(b, nx, ny, variant=variant, tol=tol, maxit=maxit)
+        check_same(rc, res, x, ro, xo)
