@@ -48,9 +48,11 @@ typedef enum { CG_VARIANT_CLASSIC = 0, CG_VARIANT_PIPELINED = 1 } cg_variant;
  * the exact FP64 value of the fixed-point result, and the result's relative
  * residuals are sqrt of ratios of fixed-point dot products.  Integer
  * arithmetic: the result does not depend on summation order, and every path
- * returns the same bits.  One work-group per solve (cg_plan_info.path 3):
- * nx * ny <= 10176 (the paper's grids reach 100 x 100); larger grids are
- * CG_E_INVALID.  inner_tol is ignored. */
+ * returns the same bits.  One work-group per solve (cg_plan_info.path 3)
+ * holding two vectors in its 160 KiB of LDS: the grid must satisfy
+ * (nx + 1)(ny + 2) + nx ny <= 20352 (100 x 100 fits; the paper's grids reach
+ * 100 x 100; a single row or column up to 5087 or 6782 unknowns); larger
+ * grids are CG_E_INVALID.  inner_tol is ignored. */
 typedef enum {
   CG_PREC_FP64 = 0,
   CG_PREC_FP32_REFINED = 1,

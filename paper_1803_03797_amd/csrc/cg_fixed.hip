@@ -55,6 +55,7 @@ constexpr int64_t kFxOne = int64_t(1) << 30;
 constexpr int kFxWaves = kFxThreads / kWave;
 constexpr int kFxRedHalf = kFxWaves * 2 * 2;  // [wave][value < 2][h, m]
 constexpr int kFxRed = 2 * kFxRedHalf;          // by call parity
+static_assert(kFxRed == kFxSumWords, "sum slots as the host budgets them");
 
 __device__ __forceinline__ int64_t fx_clamp(int64_t v) {
   return v > kFxMax ? kFxMax : (v < kFxMin ? kFxMin : v);
@@ -196,16 +197,12 @@ __device__ __forceinline__ int fx_opaque(int v) {
   return v;
 }
 
-// y = sat(A u) for unknown k = j nx + i of the operand O (nx x ny, row-major
-// in LDS); neighbours outside the grid read as zero.  ij = i | j << 16.
-__device__ __forceinline__ int64_t fx_stencil(const int64_t* O, int k, int ij, int nx, int ny) {
-  ij = fx_opaque(ij);  // predicates and addresses per use, not per loop
-  const int i = ij & 0xffff, j = ij >> 16;
-  const bool hw = i > 0, he = i + 1 < nx, hs = j > 0, hn = j + 1 < ny;
-  const int64_t c = O[k];
-  const int64_t w = O[hw ? k - 1 : k], e = O[he ? k + 1 : k];
-  const int64_t sv = O[hs ? k - nx : k], nv = O[hn ? k + nx : k];
-  return fx_clamp((((4 * c - (hw ? w : 0)) - (he ? e : 0)) - (hs ? sv : 0)) - (hn ? nv : 0));
+// y = sat(A u) at position c of the operand O stored with a zero ring: row
+// length W = nx + 1 (one zero column between consecutive rows serves as the
+// east ring of one row and the west ring of the next), a zero row above and
+// below.  No predicates: the five reads are plain LDS reads.
+__device__ __forceinline__ int64_t fx_stencil(const int64_t* O, int c, int W) {
+  return fx_clamp((((4 * O[c] - O[c - 1]) - O[c + 1]) - O[c - W]) - O[c + W]);
 }
 
 // Work-group sums of NV <= 2 accumulators; every thread gets all NV results
@@ -283,20 +280,24 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
   constexpr bool QG = VARIANT == 1 && E >= 8;
   const int T = blockDim.x, t = threadIdx.x;
   const int nx = a.g.nx, ny = a.g.ny, pitch = a.g.pitch, n = nx * ny;
+  // unknown k = t + e T (row j = k / nx, column i) sits at c = (j + 1) W + i
+  // = k + j + W of the zero-ringed operand O; V follows O; sum slots last
+  const int W = nx + 1, L = (ny + 2) * W;
   int64_t* O = lds;
-  int64_t* V = lds + kFxMaxDof;
-  int64_t* red = lds + 2 * kFxMaxDof;
+  int64_t* V = lds + L;
+  int64_t* red = lds + kFxLdsWords - kFxRed;
   int par = 0;
   const double tol = a.S[0]->tol;
   const int maxit = a.S[0]->maxit;
 
-  // unknown k = t + e T at column i, row j: ij = i | j << 16, -1 if unowned
-  int ij[E];
+  int c[E];  // -1: unowned
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int k = t + e * T, j = k / nx;
-    ij[e] = k < n ? (k - j * nx) | (j << 16) : -1;
+    const int k = t + e * T;
+    c[e] = k < n ? k + k / nx + W : -1;
   }
+  for (int q = t; q < L; q += T) O[q] = 0;
+  __syncthreads();
 
   // quantized inputs; x0 is the first operand (r = b - A x).  b goes to bq
   // and is read back by its owner (no register copy to hold meanwhile).
@@ -305,8 +306,8 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     xv[e] = 0;
-    if (ij[e] >= 0) {
-      const int k = t + e * T, gk = (ij[e] >> 16) * pitch + (ij[e] & 0xffff);
+    if (c[e] >= 0) {
+      const int k = t + e * T, j = c[e] - k - W, gk = j * pitch + (k - j * nx);
       const int64_t bv = fx_from(a.b[gk]);
       xv[e] = fx_from(a.x[gk]);
       a.bq[k] = bv;
@@ -315,7 +316,7 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
         V[k] = 0;  // p
         if constexpr (QG) a.qg[k] = 0;
       }
-      O[k] = xv[e];
+      O[c[e]] = xv[e];
       fx_acc_sq(acc[0], bv);
     }
   }
@@ -324,9 +325,9 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     r[e] = 0;
-    if (ij[e] >= 0) {
+    if (c[e] >= 0) {
       const int k = t + e * T;
-      r[e] = fx_clamp(a.bq[k] - fx_stencil(O, k, ij[e], nx, ny));
+      r[e] = fx_clamp(a.bq[k] - fx_stencil(O, c[e], W));
       fx_acc_sq(acc[1], r[e]);
     }
   }
@@ -359,9 +360,9 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
         constexpr int MB = fx_form<common(), FX_ZERO>();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (ij[e] >= 0) {
-            const int k = fx_opaque(t) + e * T;
-            O[k] = it == 0 ? r[e] : fx_upd<MB>(sb, O[k], r[e]);
+          if (c[e] >= 0) {
+            const int ce = fx_opaque(c[e]);
+            O[ce] = it == 0 ? r[e] : fx_upd<MB>(sb, O[ce], r[e]);
           }
         }
       });
@@ -369,11 +370,11 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
       FxAcc api[1] = {{0, 0}};
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if (ij[e] >= 0) {
-          const int k = fx_opaque(t) + e * T;
-          const int64_t sv = fx_stencil(O, k, ij[e], nx, ny);
+        if (c[e] >= 0) {
+          const int k = fx_opaque(t) + e * T, ce = fx_opaque(c[e]);
+          const int64_t sv = fx_stencil(O, ce, W);
           V[k] = sv;
-          fx_acc(api[0], O[k], sv);
+          fx_acc(api[0], O[ce], sv);
         }
       }
       int64_t pi[1];
@@ -389,9 +390,9 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
         constexpr int MA = fx_form<common(), FX_ZERO>(), MNA = fx_form<common(), FX_NEG>();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (ij[e] >= 0) {
-            const int k = fx_opaque(t) + e * T;
-            xv[e] = fx_upd<MA>(sa, O[k], xv[e]);
+          if (c[e] >= 0) {
+            const int k = fx_opaque(t) + e * T, ce = fx_opaque(c[e]);
+            xv[e] = fx_upd<MA>(sa, O[ce], xv[e]);
             r[e] = fx_upd<MNA>(sna, V[k], r[e]);
             fx_acc_sq(ag[0], r[e]);
           }
@@ -407,7 +408,7 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
     // Algorithm 2: w = A r and delta = (w, r) first; then w in O, p in V
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (ij[e] >= 0) O[t + e * T] = r[e];
+      if (c[e] >= 0) O[c[e]] = r[e];
     __syncthreads();
     int64_t delta;
     {
@@ -416,8 +417,8 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         w0[e] = 0;
-        if (ij[e] >= 0) {
-          w0[e] = fx_stencil(O, t + e * T, ij[e], nx, ny);
+        if (c[e] >= 0) {
+          w0[e] = fx_stencil(O, c[e], W);
           fx_acc(ad[0], w0[e], r[e]);
         }
       }
@@ -426,7 +427,7 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
       delta = d1[0];
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        if (ij[e] >= 0) O[t + e * T] = w0[e];
+        if (c[e] >= 0) O[c[e]] = w0[e];
     }
     __syncthreads();
     int64_t z[E];
@@ -465,10 +466,7 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
         constexpr int MB = fx_form<cm(), FX_ZERO>();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (ij[e] >= 0) {
-            const int k = fx_opaque(t) + e * T;
-            z[e] = fx_upd<MB>(sb, z[e], fx_stencil(O, k, ij[e], nx, ny));
-          }
+          if (c[e] >= 0) z[e] = fx_upd<MB>(sb, z[e], fx_stencil(O, fx_opaque(c[e]), W));
         }
       });
       __syncthreads();  // w is overwritten below
@@ -476,24 +474,38 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
       fx_with(common, [&](auto cm) {
         constexpr int MB = fx_form<cm(), FX_ZERO>(), MA = fx_form<cm(), FX_ZERO>();
         constexpr int MNA = fx_form<cm(), FX_NEG>();
+        // x (and q) of the next unknown are loaded before this one's stores:
+        // the global latency overlaps a whole unknown's arithmetic
+        int64_t xn = 0, qn = 0;
+        if (c[0] >= 0) {
+          const int k0 = fx_opaque(t);
+          xn = a.xq[k0];
+          if constexpr (QG) qn = a.qg[k0];
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (ij[e] >= 0) {
-            const int k = fx_opaque(t) + e * T;
-            const int64_t w = O[k];
+          const int64_t xc = xn, qc = qn;
+          if (e + 1 < E && c[e + 1 < E ? e + 1 : e] >= 0) {
+            const int kn = fx_opaque(t) + (e + 1) * T;
+            xn = a.xq[kn];
+            if constexpr (QG) qn = a.qg[kn];
+          }
+          if (c[e] >= 0) {
+            const int k = fx_opaque(t) + e * T, ce = fx_opaque(c[e]);
+            const int64_t w = O[ce];
             int64_t qe;
             if constexpr (QG) {
-              qe = fx_upd<MB>(sb, a.qg[k], w);
+              qe = fx_upd<MB>(sb, qc, w);
               a.qg[k] = qe;
             } else {
               qe = q[e] = fx_upd<MB>(sb, q[e], w);
             }
             const int64_t p = fx_upd<MB>(sb, V[k], r[e]);
             V[k] = p;
-            a.xq[k] = fx_upd<MA>(sa, p, a.xq[k]);
+            a.xq[k] = fx_upd<MA>(sa, p, xc);
             r[e] = fx_upd<MNA>(sna, qe, r[e]);
             const int64_t wn = fx_upd<MNA>(sna, z[e], w);
-            O[k] = wn;
+            O[ce] = wn;
             fx_acc_sq(gd[0], r[e]);
             fx_acc(gd[1], wn, r[e]);
           }
@@ -508,23 +520,23 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (ij[e] >= 0) xv[e] = a.xq[t + e * T];
+      if (c[e] >= 0) xv[e] = a.xq[t + e * T];
   }
 
   // true residual b - A x in the same arithmetic, then x back to FP64
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e)
-    if (ij[e] >= 0) O[t + e * T] = xv[e];
+    if (c[e] >= 0) O[c[e]] = xv[e];
   __syncthreads();
   FxAcc at[1] = {{0, 0}};
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (ij[e] >= 0) {
-      const int k = t + e * T;
-      const int64_t tv = fx_clamp(a.bq[k] - fx_stencil(O, k, ij[e], nx, ny));
+    if (c[e] >= 0) {
+      const int k = t + e * T, j = c[e] - k - W;
+      const int64_t tv = fx_clamp(a.bq[k] - fx_stencil(O, c[e], W));
       fx_acc_sq(at[0], tv);
-      a.x[(ij[e] >> 16) * pitch + (ij[e] & 0xffff)] = ldexp((double)xv[e], -30);
+      a.x[j * pitch + (k - j * nx)] = ldexp((double)xv[e], -30);
     }
   }
   int64_t tt[1];
@@ -534,7 +546,7 @@ __device__ __forceinline__ void fx_solve(const FxArgs& a, int64_t* lds) {
 
 template <int VARIANT, int E>
 __global__ __launch_bounds__(kFxThreads) void k_solve_fixed(FxArgs a) {
-  __shared__ int64_t lds[2 * kFxMaxDof + kFxRed];
+  __shared__ int64_t lds[kFxLdsWords];
   fx_solve<VARIANT, E>(a, lds);
 }
 
@@ -543,7 +555,7 @@ __global__ __launch_bounds__(kFxThreads) void k_solve_fixed(FxArgs a) {
 template <int VARIANT, int E>
 __global__ __launch_bounds__(kFxThreads) void k_solve_fixed_many(const Slot* slots,
                                                                  const int* idx) {
-  __shared__ int64_t lds[2 * kFxMaxDof + kFxRed];
+  __shared__ int64_t lds[kFxLdsWords];
   const Slot& S = slots[__builtin_amdgcn_readfirstlane(idx[blockIdx.x])];
   FxArgs a;
   a.g = S.g;

@@ -171,15 +171,18 @@ struct Item {
 // of 2^-30 in [-2^49, 2^49 - 1] (the paper's 50-bit format with 20 integer
 // bits, round to nearest with ties up, saturation).  One work-group of up to
 // kFxThreads threads runs a whole solve: thread t owns unknowns t + e*T
-// (e < kFxMaxE); two full vectors sit in LDS (kFxMaxDof int64 each, with the
-// sum slots filling the 160 KiB of a work-group exactly).
+// (e < kFxMaxE).  LDS (160 KiB, kFxLdsWords int64) holds the stencil operand
+// with a zero ring ((ny + 2) rows of nx + 1), one more full vector and the
+// kFxSumWords sum slots.
 constexpr int kFxThreads = 1024;
 constexpr int kFxMaxE = 10;
-constexpr int kFxMaxDof = 10176;
-//SA
+constexpr int kFxLdsWords = 20480;
+constexpr int kFxSumWords = 128;
 
 inline bool fixed_fits(int nx, int ny) {
-  return nx >= 1 && ny >= 1 && (int64_t)nx * ny <= kFxMaxDof;
+  return nx >= 1 && ny >= 1 &&
+         (int64_t)(ny + 2) * (nx + 1) + (int64_t)nx * ny <= kFxLdsWords - kFxSumWords &&
+         (int64_t)nx * ny <= (int64_t)kFxThreads * kFxMaxE;
 }
 
 // Unknowns per thread the solver is compiled for (1, 2, 3, 4, 6, 8, 10): the

@@ -47,7 +47,9 @@ def _prob(**kw):
                                  dict(x=None), dict(mem=7), dict(variant=2), dict(precision=5),
                                  dict(precision=1, inner_tol=1.5), dict(precision=3),
                                  dict(precision=2, nx=101, ny=101),
-                                 dict(precision=2, nx=1, ny=10177)])
+                                 dict(precision=2, nx=100, ny=101),
+                                 dict(precision=2, nx=1, ny=6783),
+                                 dict(precision=2, nx=5088, ny=1)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -55,8 +57,8 @@ def test_validation_rejects(bad):
 def test_validation_accepts():
     assert cg.cg_validate(_prob()) == cg.CG_OK
     assert cg.cg_validate(_prob(tol=0.0, precision=1, inner_tol=0.0)) == cg.CG_OK
-    # fixed point: up to 10176 unknowns, any shape; inner_tol is ignored
-    for nx, ny in ((1, 1), (100, 100), (96, 106), (1, 10176), (10176, 1)):
+    # fixed point: (nx + 1)(ny + 2) + nx ny <= 20352; inner_tol is ignored
+    for nx, ny in ((1, 1), (100, 100), (98, 102), (1, 6782), (5087, 1)):
         assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
     assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
 
