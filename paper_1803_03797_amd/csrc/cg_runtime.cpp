@@ -434,14 +434,7 @@ void Ctx::forget_graphs(const void* mem) {
   }
 }
 
-int stage_in(Ctx& c, Work& w, const cg_problem* p) {
-  const Plan& pl = w.pl;
-  HIPCHK(launch_fill(w.mem, pl.footprint, c.st));
-  const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyHostToDevice
-                                                   : hipMemcpyDeviceToDevice;
-  const size_t row = (size_t)p->nx * 8, pitch = (size_t)pl.g.pitch * 8;
-  HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, p->ny, kind, c.st));
-  if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, p->ny, kind, c.st));
+State initial_state(const cg_problem* p) {
   State s;
   memset(&s, 0, sizeof(s));
   s.status = ST_RUNNING;
@@ -449,14 +442,32 @@ int stage_in(Ctx& c, Work& w, const cg_problem* p) {
   s.tol = p->tol;
   s.inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
   s.maxit = p->maxit;
-  memcpy(c.host_state, &s, sizeof(s));
-  HIPCHK(hipMemcpyAsync(w.S[0], c.host_state, sizeof(State), hipMemcpyHostToDevice, c.st));
-  // the pinned staging buffer is reused below: wait for this copy
-  HIPCHK(hipStreamSynchronize(c.st));
+  return s;
+}
+
+int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const State* pinned) {
+  const Plan& pl = w.pl;
+  HIPCHK(launch_fill(w.mem, pl.footprint, c.st));
+  const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyHostToDevice
+                                                   : hipMemcpyDeviceToDevice;
+  const size_t row = (size_t)p->nx * 8, pitch = (size_t)pl.g.pitch * 8;
+  HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, p->ny, kind, c.st));
+  if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, p->ny, kind, c.st));
+  HIPCHK(hipMemcpyAsync(w.S[0], pinned, sizeof(State), hipMemcpyHostToDevice, c.st));
   w.m = 0;
   w.i = 0;
   w.maxit = p->maxit;
   w.check = false;
+  return CG_OK;
+}
+
+int stage_in(Ctx& c, Work& w, const cg_problem* p) {
+  const State s = initial_state(p);
+  memcpy(c.host_state, &s, sizeof(s));
+  int rc = stage_in_async(c, w, p, (const State*)c.host_state);
+  if (rc) return rc;
+  // the pinned staging buffer is reused by the next call: wait for the copy
+  HIPCHK(hipStreamSynchronize(c.st));
   return CG_OK;
 }
 

@@ -77,6 +77,10 @@ struct Ctx;
 double now_s();
 bool carve(Ctx& c, Work& w);
 int stage_in(Ctx& c, Work& w, const cg_problem* p);
+cgk::State initial_state(const cg_problem* p);
+// stage_in without waiting: the initial state is copied from `pinned` (host
+// memory the caller keeps unchanged until the stream has passed the copy).
+int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const cgk::State* pinned);
 int stage_out(Ctx& c, Work& w, const cg_problem* p, const cgk::State& s);
 void fill_result(const cgk::State& s, cg_result* res, double secs, bool refined);
 

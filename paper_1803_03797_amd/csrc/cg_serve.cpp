@@ -61,6 +61,7 @@ class Engine {
     if (h_items_) hipHostFree(h_items_);
     if (h_idx_) hipHostFree(h_idx_);
     if (h_states_) hipHostFree(h_states_);
+    if (h_admit_) hipHostFree(h_admit_);
     if (h_step_) hipHostFree(h_step_);
   }
 
@@ -89,6 +90,7 @@ class Engine {
                       hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_idx_, (size_t)n_ * sizeof(int) + 256, hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_states_, (size_t)n_ * sizeof(State), hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_admit_, (size_t)n_ * sizeof(State), hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_step_, kStepRing * sizeof(int), hipHostMallocDefault))
       return CG_E_DEVICE;
     memset(h_slots_, 0, (size_t)n_ * sizeof(Slot));
@@ -113,20 +115,18 @@ class Engine {
     j->w = Work();
     j->w.pl = c_.plan(&j->p);
     if (!carve(c_, j->w)) return CG_E_NOMEM;
-    int rc = stage_in(c_, j->w, &j->p);
+    // the first pass: r = b - A x (FP64) or the first outer residual
+    // (refined).  The slot's pinned records stay untouched until the slot is
+    // freed again, which comes after a stream synchronisation: no wait here.
+    State& s = h_admit_[slot];
+    s = initial_state(&j->p);
+    s.kind = j->w.pl.refined ? K_RESID : K_INIT_R;
+    int rc = stage_in_async(c_, j->w, &j->p, &s);
     if (rc) {
+      hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
       return rc;
     }
-    // the first pass: r = b - A x (FP64) or the first outer residual (refined)
-    State s;
-    memset(&s, 0, sizeof(s));
-    s.status = ST_RUNNING;
-    s.flags = F_BB_PENDING;
-    s.tol = j->p.tol;
-    s.inner_tol = j->p.inner_tol > 0.0 ? j->p.inner_tol : 1e-4;
-    s.maxit = j->p.maxit;
-    s.kind = j->w.pl.refined ? K_RESID : K_INIT_R;
     Slot& S = h_slots_[slot];
     memset(&S, 0, sizeof(S));
     const Work& w = j->w;
@@ -154,10 +154,8 @@ class Engine {
     S.part[1] = w.part[1];
     S.S[0] = w.S[0];
     S.S[1] = w.S[1];
-    memcpy(c_.host_state, &s, sizeof(s));
-    if (hipMemcpyAsync(w.S[0], c_.host_state, sizeof(State), hipMemcpyHostToDevice, c_.st) ||
-        hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st) ||
-        hipStreamSynchronize(c_.st)) {
+    if (hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st)) {
+      hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
       return CG_E_DEVICE;
     }
@@ -388,6 +386,7 @@ class Engine {
   int* d_nitems_ = nullptr;
   State* d_states_ = nullptr;
   Slot* h_slots_ = nullptr;
+  State* h_admit_ = nullptr;  // initial state of each slot's solve (pinned)
   Item* h_items_ = nullptr;
   int* h_idx_ = nullptr;
   State* h_states_ = nullptr;
