@@ -54,11 +54,13 @@ PCG_TRAFFIC_BYTES = 1634008205
 # Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
 # iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
 # pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
-# four 32 x 32 -> 64-bit multiplies of two-limb operands; peak: 256 CUs x
-# 64 lanes x 2.4 GHz at the quarter rate of 32-bit integer multiplies.
+# four 32 x 32 -> 64-bit multiplies of two-limb operands.  Peak: 256 CUs x
+# 4 SIMDs x 16 lanes per clock x 2.4 GHz, the 64-bit multiply-add at half
+# the 32-lane rate of 32-bit VALU operations (a probe kernel of independent
+# v_mad_u64_u32 chains reaches 30.3 T/s on the device).
 FX_PRODUCTS = {"classic": 5, "pipelined": 8}
 FX_MULS_PER_PRODUCT = 4
-FX_MUL_PEAK_G = 256 * 64 * 2.4 / 4  # Gmul/s
+FX_MUL_PEAK_G = 256 * 4 * 16 * 2.4  # Gmul/s
 
 
 def log(*a):
