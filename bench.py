@@ -28,7 +28,8 @@ Other workloads (one JSON line each, not the headline):
   --workload fixed   the paper's fixed-point format (Q20.30): solve latency on
                      its synthesized grids and iteration counts, and a batch of
                      256 solves of its largest grid in one launch
-  --probe            attainable HBM bandwidth of plain streaming kernels
+  --probe            attainable HBM bandwidth of plain streaming kernels, and
+                     the attainable rate of 32 x 32 -> 64-bit multiply-adds
 """
 import argparse
 import json
@@ -644,8 +645,10 @@ def bench_probe(args):
             for pat, nm in enumerate(names):
                 t, by = ctx.cg_stream_probe(pat, elems, 5)
                 out["%s_%dM" % (nm, elems >> 20)] = round(by / t / 1e9, 1)
+    t, ops = ctx.cg_mul_probe(4096, 5)
     emit({"metric": "attainable HBM GB/s of plain streaming kernels", "workload": "probe",
-          "results_GBps": out, "peak_GBps": HBM_PEAK_GBPS})
+          "results_GBps": out, "peak_GBps": HBM_PEAK_GBPS,
+          "mul_probe_Gmul_s": round(ops / t / 1e9, 1), "mul_peak_Gmul_s": FX_MUL_PEAK_G})
     ctx.close()
 
 

@@ -215,6 +215,12 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
  * small. */
 int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
                     double* bytes);
+/* Integer multiply probe, for measurement only (the ALU peak the fixed-point
+ * path is measured against): 8 work-groups per CU of 256 threads, each thread
+ * running 8 independent chains of `rounds` 32 x 32 -> 64-bit multiply-adds,
+ * reps + 1 times (the first warms up); returns the best time and the number
+ * of multiply-adds of one launch.  CG_E_INVALID for rounds or reps < 1. */
+int cg_mul_probe(cg_ctx* ctx, int32_t rounds, int32_t reps, double* seconds, double* ops);
 /* Profiling on/off; while on, every kernel launch is bracketed by HIP events
  * on the library's stream. */
 int cg_set_profiling(cg_ctx* ctx, int32_t on);

@@ -59,7 +59,7 @@ class cg_kstat(C.Structure):
 SYMBOLS = ["cg_create", "cg_destroy", "cg_solve", "cg_solve_batch", "cg_submit", "cg_poll",
            "cg_status_str", "cg_apply", "cg_dot", "cg_plan", "cg_footprint", "cg_validate",
            "cg_tune", "cg_pin_tile", "cg_set_profiling", "cg_kernel_stats", "cg_version",
-           "cg_stream_probe"]
+           "cg_stream_probe", "cg_mul_probe"]
 
 _lib = None
 
@@ -96,6 +96,7 @@ def load():
         "cg_tune": (C.c_int, [P, I, I, I, I]),
         "cg_pin_tile": (C.c_int, [P, I, I, I, I, I, I]),
         "cg_stream_probe": (C.c_int, [P, I, C.c_size_t, I, C.POINTER(D), C.POINTER(D)]),
+        "cg_mul_probe": (C.c_int, [P, I, I, C.POINTER(D), C.POINTER(D)]),
         "cg_set_profiling": (C.c_int, [P, I]),
         "cg_kernel_stats": (C.c_int, [P, C.POINTER(cg_kstat), I, C.POINTER(I), I]),
         "cg_version": (C.c_char_p, []),
@@ -257,6 +258,11 @@ class Context:
         _check("cg_stream_probe", self.lib.cg_stream_probe(self.h, pattern, elems, reps,
                                                            C.byref(sec), C.byref(nbytes)))
         return sec.value, nbytes.value
+
+    def cg_mul_probe(self, rounds=4096, reps=3):
+        t, n = C.c_double(), C.c_double()
+        _check("cg_mul_probe", self.lib.cg_mul_probe(self.h, rounds, reps, C.byref(t), C.byref(n)))
+        return t.value, n.value
 
     def cg_set_profiling(self, on):
         return _check("cg_set_profiling", self.lib.cg_set_profiling(self.h, 1 if on else 0))

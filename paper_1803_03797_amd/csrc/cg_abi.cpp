@@ -177,6 +177,14 @@ int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, do
   return c->stream_probe(pattern, elems, reps, seconds, bytes);
 }
 
+int cg_mul_probe(cg_ctx* ctx, int32_t rounds, int32_t reps, double* seconds, double* ops) {
+  if (!ctx || !seconds || !ops || rounds < 1 || reps < 1) return CG_E_INVALID;
+  Ctx* c = C(ctx);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
+  return c->mul_probe(rounds, reps, seconds, ops);
+}
+
 int cg_set_profiling(cg_ctx* ctx, int32_t on) {
   if (!ctx) return CG_E_INVALID;
   Ctx* c = C(ctx);

@@ -601,7 +601,32 @@ static hipError_t launch_many(int e, const Slot* slots, const int* idx, int n, h
   return hipGetLastError();
 }
 
+// Measurement only: independent chains of 32 x 32 -> 64-bit multiply-adds
+// (v_mad_u64_u32, the product the fixed-point updates are built from), 8 per
+// thread, `rounds` rounds; one value per thread is written so that the work
+// is kept.
+__global__ __launch_bounds__(256) void k_mul_probe(uint64_t* sink, int rounds, uint32_t seed) {
+  const uint32_t a = (threadIdx.x * 2654435761u + seed + blockIdx.x) | 1u;
+  uint64_t v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = a + c * 977u;
+  for (int i = 0; i < rounds; ++i) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] = (uint64_t)(uint32_t)v[c] * a + v[c];
+  }
+  uint64_t x = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x ^= v[c];
+  sink[(size_t)blockIdx.x * 256 + threadIdx.x] = x;
+}
+
 }  // namespace
+
+hipError_t launch_mul_probe(uint64_t* sink, int grid, int rounds, hipStream_t st) {
+  if (grid < 1 || rounds < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mul_probe, dim3(grid), dim3(256), 0, st, sink, rounds, 12345u);
+  return hipGetLastError();
+}
 
 hipError_t launch_solve_fixed(int variant, const FxArgs& a, int threads, hipStream_t st) {
   if (!fixed_fits(a.g.nx, a.g.ny) || threads < kWave || threads > kFxThreads ||

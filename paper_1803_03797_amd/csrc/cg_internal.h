@@ -225,6 +225,9 @@ hipError_t launch_solve_fixed(int variant, const FxArgs& a, int threads, hipStre
 // Final states land in both state buffers, kind K_DONE.
 hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, int variant, int e,
                                    hipStream_t s);
+// Measurement only: grid work-groups of 256 threads, each thread 8 chains of
+// `rounds` 32 x 32 -> 64-bit multiply-adds; writes grid * 256 words to sink.
+hipError_t launch_mul_probe(uint64_t* sink, int grid, int rounds, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the

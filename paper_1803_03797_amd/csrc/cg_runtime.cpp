@@ -780,6 +780,35 @@ int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, doub
   return CG_OK;
 }
 
+int Ctx::mul_probe(int rounds, int reps, double* seconds, double* ops) {
+  Ctx& c = *this;
+  if (rounds < 1 || reps < 1) return CG_E_INVALID;
+  const int grid = 8 * num_cu;
+  uint64_t* sink = (uint64_t*)arena.alloc((size_t)grid * 256 * sizeof(uint64_t));
+  if (!sink) return CG_E_NOMEM;
+  struct Rel {
+    Arena& a;
+    void* m;
+    ~Rel() { a.release(m); }
+  } rel{arena, sink};
+  hipEvent_t e0 = event(), e1 = event();
+  double best = 1e30;
+  for (int r = 0; r < reps + 1; ++r) {
+    HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(launch_mul_probe(sink, grid, rounds, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (r > 0) best = std::min(best, ms * 1e-3);  // the first launch warms up
+  }
+  ev_free.push_back(e0);
+  ev_free.push_back(e1);
+  *seconds = best;
+  *ops = (double)grid * 256 * 8 * rounds;
+  return CG_OK;
+}
+
 // ---------------------------------------------------------- autotuner --
 
 // Times candidate tile shapes for one grid shape on the device and pins the

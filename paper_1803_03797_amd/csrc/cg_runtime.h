@@ -145,6 +145,7 @@ struct Ctx {
   int order_after_user();
   hipError_t pass(int kind, int fp32g, const cgk::PassArgs& a, int grid, bool check = false);
   int stream_probe(int pattern, size_t elems, int reps, double* seconds, double* bytes);
+  int mul_probe(int rounds, int reps, double* seconds, double* ops);
   hipEvent_t event();
   void prof_add(const char* name, double seconds, double bytes, int64_t launches);
   void prof_collect();

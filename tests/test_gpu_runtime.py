@@ -120,6 +120,16 @@ def test_stream_probe():
             ctx.cg_stream_probe(7, 1 << 20, 1)
 
 
+def test_mul_probe():
+    with cg.Context(device=0, arena_bytes=256 << 20) as ctx:
+        t, ops = ctx.cg_mul_probe(1024, 2)
+        assert t > 0 and ops > 0 and ops % (256 * 8 * 1024) == 0
+        say("multiply probe %.1f T/s" % (ops / t / 1e12))
+        for bad in ((0, 1), (16, 0)):
+            with pytest.raises(cg.CGError):
+                ctx.cg_mul_probe(*bad)
+
+
 def test_caller_arena_and_stream(torch):
     """Workspace carved from a caller's uint8 tensor; work ordered after the
     caller's stream."""
