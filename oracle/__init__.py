@@ -6,5 +6,5 @@ this package.  The GPU library never imports, links or executes it.
 from .oracle import (  # noqa: F401
     MODE_CANONICAL, MODE_SEQUENTIAL, VARIANT_CLASSIC, VARIANT_PIPELINED,
     OR_OK, OR_NOT_CONVERGED, OR_BREAKDOWN, OR_E_INVALID,
-    Order, csr, spmv, dot, cg, refine, lib_path, cg_fixed,
+    Order, csr, spmv, dot, cg, refine, lib_path, cg_fixed, cheb_coeffs, cheb_apply, pcg,
 )

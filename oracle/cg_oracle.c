@@ -18,7 +18,9 @@
  *     Vanroose, unpreconditioned), with the sign/parenthesis readings listed
  *     in the design notes: r <- r - alpha*q, w <- w - alpha*z,
  *     alpha_i = 1 / (delta_i/gamma_i - beta_i/alpha_{i-1});
- *   - FP32-inner / FP64-outer iterative refinement around classic CG.
+ *   - FP32-inner / FP64-outer iterative refinement around classic CG;
+ *   - classic CG preconditioned by a Chebyshev polynomial in A (the M^-1 that
+ *     the pipelined-CG literature the paper builds on carries).
  *
  * Unknown (i, j), 0 <= i < nx, 0 <= j < ny, has index k = j*nx + i.
  * Build with -O2 -ffp-contract=off (no fast-math): every operation below is
@@ -537,6 +539,152 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, hist);
   csr_free(&A);
   return rc;
+}
+
+/* ------------------------------------------ Chebyshev-preconditioned CG -- */
+
+/* The preconditioner M^-1 = p_s(A): s steps of Chebyshev semi-iteration on
+ * A y = r from y = 0, over the interval [lmin, lmax] that holds the spectrum
+ * of A (closed form for this operator: 4 -+ 2cos(pi/(nx+1)) -+ 2cos(pi/(ny+1))).
+ * With theta = (lmax + lmin)/2, delta = (lmax - lmin)/2, sigma = theta/delta,
+ * rho_0 = 1/sigma:
+ *   d_0 = r * (1/theta);  y_1 = d_0;
+ *   for k = 1 .. s-1:  r_k = r_(k-1) - A d_(k-1);
+ *                      rho_k = 1 / (2 sigma - rho_(k-1));
+ *                      d_k = (rho_k rho_(k-1)) d_(k-1) + (2 rho_k / delta) r_k;
+ *                      y_(k+1) = y_k + d_k;
+ *   z = y_s.
+ * (the Chebyshev iteration of Saad, Iterative Methods for Sparse Linear
+ * Systems, Section 12.3; the residual polynomial is bounded by
+ * 1/T_s(sigma) < 1 on [lmin, lmax], so p_s is positive there and M is SPD.)
+ * c0 = 1/theta, c1[k-1] = rho_k rho_(k-1), c2[k-1] = 2 rho_k / delta. */
+int oracle_cheb_coeffs(int32_t nx, int32_t ny, int32_t s, double* c0, double* c1,
+                       double* c2) {
+  if (nx < 1 || ny < 1 || s < 1 || !c0 || (s > 1 && (!c1 || !c2))) return OR_E_INVALID;
+  const double pi = 3.14159265358979323846;
+  const double a = 2.0 * cos(pi / (double)(nx + 1)) + 2.0 * cos(pi / (double)(ny + 1));
+  const double lmax = 4.0 + a, lmin = 4.0 - a;
+  const double theta = (lmax + lmin) / 2.0, delta = (lmax - lmin) / 2.0;
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  *c0 = 1.0 / theta;
+  for (int32_t k = 1; k < s; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1[k - 1] = rn * rho;
+    c2[k - 1] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return OR_OK;
+}
+
+/* z = M^-1 r.  Canonical mode: d_0 = r * c0; d_k = fma(c1, d_(k-1), c2 * r_k);
+ * r_k = r_(k-1) - (A d_(k-1)) with the canonical stencil order; y adds d in
+ * order.  Sequential mode: d_k = c1 * d_(k-1) + c2 * r_k with both products
+ * rounded. */
+static int cheb_apply(const csr_t* A, int32_t mode, int32_t s, const double* cc0,
+                      const double* c1, const double* c2, const double* r, double* z) {
+  const int64_t n = A->n;
+  double* d = (double*)malloc((size_t)n * sizeof(double));
+  double* rk = (double*)malloc((size_t)n * sizeof(double));
+  double* t = (double*)malloc((size_t)n * sizeof(double));
+  if (!d || !rk || !t) { free(d); free(rk); free(t); return OR_E_NOMEM; }
+  const double c0 = *cc0;
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = r[i] * c0;
+    z[i] = d[i];
+    rk[i] = r[i];
+  }
+  for (int32_t k = 1; k < s; ++k) {
+    spmv(A, d, t);
+    for (int64_t i = 0; i < n; ++i) {
+      rk[i] = rk[i] - t[i];
+      d[i] = mode == MODE_CANONICAL ? fma(c1[k - 1], d[i], c2[k - 1] * rk[i])
+                                    : c1[k - 1] * d[i] + c2[k - 1] * rk[i];
+      z[i] = z[i] + d[i];
+    }
+  }
+  free(d); free(rk); free(t);
+  return OR_OK;
+}
+
+int oracle_cheb_apply(int32_t nx, int32_t ny, int32_t mode, int32_t s, const double* r,
+                      double* z) {
+  if (nx < 1 || ny < 1 || s < 1 || s > 64 || !r || !z) return OR_E_INVALID;
+  double c0, c1[64], c2[64];
+  oracle_cheb_coeffs(nx, ny, s, &c0, c1, c2);
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
+  if (rc) return rc;
+  rc = cheb_apply(&A, mode, s, &c0, c1, c2, r, z);
+  csr_free(&A);
+  return rc;
+}
+
+/* Preconditioned classic CG (Algorithm 1 with M^-1 = p_s(A)) from x0:
+ *   r = b - A x0; gamma = (r,r)
+ *   repeat: stop test on gamma (as for CG); z = M^-1 r; rho = (r,z)
+ *           (breakdown unless 0 < rho < inf); p = z (first) or
+ *           z + (rho/rho_old) p; s = A p; pi = (p,s); alpha = rho/pi;
+ *           x += alpha p; r -= alpha s; gamma = (r,r); rho_old = rho */
+int oracle_pcg(int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny, int32_t sdeg,
+               const double* b, const double* x0, double* x, double tol, int32_t maxit,
+               oracle_result* res) {
+  if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
+      sdeg < 1 || sdeg > 64)
+    return OR_E_INVALID;
+  if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
+  double c0, c1[64], c2[64];
+  oracle_cheb_coeffs(nx, ny, sdeg, &c0, c1, c2);
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
+  if (rc) return rc;
+  ctx_t c = {nx, ny, mode, ord};
+  memset(res, 0, sizeof(*res));
+  const int64_t n = A.n;
+  double* r = (double*)malloc((size_t)n * sizeof(double));
+  double* z = (double*)malloc((size_t)n * sizeof(double));
+  double* p = (double*)malloc((size_t)n * sizeof(double));
+  double* s = (double*)malloc((size_t)n * sizeof(double));
+  int st = OR_OK;
+  int32_t k = 0;
+  double gamma = 0.0, rho_old = 0.0;
+  const double bb = dot(&c, b, b);
+  if (!r || !z || !p || !s) { st = OR_E_NOMEM; goto done; }
+  if (bb == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    goto done;
+  }
+  if (x0) memcpy(x, x0, (size_t)n * sizeof(double));
+  else    memset(x, 0, (size_t)n * sizeof(double));
+  spmv(&A, x, s);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - s[i];
+  const double thr = (tol * tol) * bb;
+  gamma = dot(&c, r, r);
+  for (;;) {
+    st = stop_rule(gamma, thr, k, maxit, tol);
+    if (st != -100) break;
+    if ((rc = cheb_apply(&A, mode, sdeg, &c0, c1, c2, r, z))) { st = rc; break; }
+    const double rho = dot(&c, r, z);
+    if (!(rho > 0.0) || !isfinite(rho)) { st = OR_BREAKDOWN; break; }
+    if (k == 0) memcpy(p, z, (size_t)n * sizeof(double));
+    else        xpay(&c, n, z, rho / rho_old, p);
+    spmv(&A, p, s);
+    const double pi = dot(&c, p, s);
+    if (!(pi > 0.0) || !isfinite(pi)) { st = OR_BREAKDOWN; break; }
+    const double alpha = rho / pi;
+    axpy(&c, n, alpha, p, x);
+    axpy(&c, n, -alpha, s, r);
+    gamma = dot(&c, r, r);
+    rho_old = rho;
+    ++k;
+  }
+  finish(&A, &c, b, x, bb, gamma, res);
+done:
+  res->status = st;
+  res->iterations = k;
+  free(r); free(z); free(p); free(s);
+  csr_free(&A);
+  return st;
 }
 
 /* ---------------------------------------------------------- refinement -- */

@@ -67,6 +67,13 @@ def _load():
     lib.oracle_cg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
                               P, P, P, C.c_double, C.c_int32, C.POINTER(_Result),
                               C.POINTER(_History)]
+    lib.oracle_cheb_coeffs.restype = C.c_int
+    lib.oracle_cheb_coeffs.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
+    lib.oracle_cheb_apply.restype = C.c_int
+    lib.oracle_cheb_apply.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
+    lib.oracle_pcg.restype = C.c_int
+    lib.oracle_pcg.argtypes = [C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32, C.c_int32,
+                               P, P, P, C.c_double, C.c_int32, C.POINTER(_Result)]
     I64 = C.c_int64
     lib.oracle_fx_quantize.restype = I64
     lib.oracle_fx_quantize.argtypes = [C.c_double]
@@ -168,6 +175,43 @@ def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
         hist = {k: v[:c] for k, v in hist.items()}
         return x, out, hist
     return x, out
+
+
+def cheb_coeffs(nx, ny, s):
+    """(c0, c1[s-1], c2[s-1]) of the Chebyshev preconditioner with s steps."""
+    c0 = np.zeros(1)
+    c1 = np.zeros(max(s - 1, 1))
+    c2 = np.zeros(max(s - 1, 1))
+    rc = _load().oracle_cheb_coeffs(nx, ny, s, _ptr(c0), _ptr(c1), _ptr(c2))
+    if rc:
+        raise ValueError("oracle_cheb_coeffs rejected the call: %d" % rc)
+    return float(c0[0]), c1[:s - 1].copy(), c2[:s - 1].copy()
+
+
+def cheb_apply(r, nx, ny, s, mode=MODE_SEQUENTIAL):
+    """z = p_s(A) r, the Chebyshev preconditioner with s steps."""
+    r = _vec(r, nx, ny)
+    z = np.zeros_like(r)
+    rc = _load().oracle_cheb_apply(nx, ny, mode, s, _ptr(r), _ptr(z))
+    if rc:
+        raise ValueError("oracle_cheb_apply rejected the call: %d" % rc)
+    return z
+
+
+def pcg(b, nx, ny, s, tol=1e-8, maxit=2000, x0=None, mode=MODE_SEQUENTIAL, order=None):
+    """Classic CG preconditioned by the s-step Chebyshev polynomial in A."""
+    b = _vec(b, nx, ny)
+    x0a = _vec(x0, nx, ny) if x0 is not None else None
+    x = np.zeros_like(b)
+    res = _Result()
+    o = C.byref(order) if order is not None else None
+    rc = _load().oracle_pcg(mode, o, nx, ny, s, _ptr(b), _ptr(x0a), _ptr(x), tol, maxit,
+                            C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle_pcg rejected the call: %d" % rc)
+    return x, Result(status=res.status, iterations=res.iterations,
+                     outer_iterations=res.outer_iterations,
+                     rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
 
 
 def refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, maxit=200000, x0=None):

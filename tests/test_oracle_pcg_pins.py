@@ -1,0 +1,199 @@
+"""Pins of the Chebyshev-preconditioned CG oracle (oracle_cheb_*, oracle_pcg in
+cg_oracle.c) against closed forms, a dense textbook implementation and the
+already pinned CG oracle.
+
+The preconditioner is the s-step Chebyshev semi-iteration on A y = r from
+y = 0 over A's exact spectrum interval; its residual polynomial is the scaled
+Chebyshev polynomial T_s((theta - lambda)/delta) / T_s(theta/delta), so on an
+eigenvector of A it multiplies by p_s(lambda) = (1 - that) / lambda.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle
+from oracle import MODE_CANONICAL, MODE_SEQUENTIAL
+
+GPU_LIKE = oracle.Order(2, 64, 4, 16, 256)
+MODES = (MODE_SEQUENTIAL, MODE_CANONICAL)
+
+
+def mode_vec(nx, ny, a, b):
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    return np.sin(a * np.pi * (i + 1) / (nx + 1)) * np.sin(b * np.pi * (j + 1) / (ny + 1))
+
+
+def spectrum(nx, ny):
+    c = 2 * math.cos(math.pi / (nx + 1)) + 2 * math.cos(math.pi / (ny + 1))
+    return 4 - c, 4 + c
+
+
+def cheb_T(s, x):
+    """T_s(x) for any real x."""
+    if abs(x) <= 1:
+        return math.cos(s * math.acos(x))
+    return math.copysign(1, x) ** s * math.cosh(s * math.acosh(abs(x)))
+
+
+def p_closed(s, lam, nx, ny):
+    lo, hi = spectrum(nx, ny)
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    return (1 - cheb_T(s, (theta - lam) / delta) / cheb_T(s, theta / delta)) / lam
+
+
+def dense_A(nx, ny):
+    rp, col, val = oracle.csr(nx, ny, 0)
+    return sp.csr_matrix((val, col, rp), shape=(nx * ny, nx * ny)).toarray()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("s", [1, 2, 3, 5, 8])
+def test_eigenvectors_scale_by_the_polynomial(mode, s):
+    for nx, ny in ((37, 23), (64, 1), (100, 100)):
+        for a, b in ((1, 1), (2, 1), (nx, ny), (nx // 2 + 1, 1)):
+            if b > ny:
+                continue
+            phi = mode_vec(nx, ny, a, b)
+            lam = 4 - 2 * math.cos(a * math.pi / (nx + 1)) - 2 * math.cos(b * math.pi / (ny + 1))
+            z = oracle.cheb_apply(phi, nx, ny, s, mode)
+            want = p_closed(s, lam, nx, ny) * phi
+            # p_s(lambda) is tiny where the residual polynomial nears 1 (e.g.
+            # at lambda_max for even s): the cancellation there is measured
+            # against ||phi||
+            err = np.linalg.norm(z - want)
+            assert err <= 1e-10 * np.linalg.norm(want) + 1e-12 * np.linalg.norm(phi), \
+                (nx, ny, a, b)
+
+
+def test_coefficients():
+    for nx, ny in ((1, 1), (10, 3), (4096, 4096)):
+        c0, c1, c2 = oracle.cheb_coeffs(nx, ny, 6)
+        lo, hi = spectrum(nx, ny)
+        assert abs(c0 - 1 / ((lo + hi) / 2)) <= 1e-15
+        assert len(c1) == len(c2) == 5
+        # rho_k of the three-term recurrence: rho_k = 1/(2 sigma - rho_(k-1))
+        sigma = ((hi + lo) / 2) / ((hi - lo) / 2)
+        rho = 1 / sigma
+        for k in range(5):
+            rn = 1 / (2 * sigma - rho)
+            assert c1[k] == pytest.approx(rn * rho, rel=1e-14)
+            assert c2[k] == pytest.approx(2 * rn / ((hi - lo) / 2), rel=1e-14)
+            rho = rn
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 7])
+def test_preconditioner_is_symmetric_positive_definite(s):
+    nx, ny = 13, 9
+    n = nx * ny
+    M = np.column_stack([oracle.cheb_apply(np.eye(n)[:, k].reshape(ny, nx), nx, ny, s).ravel()
+                         for k in range(n)])
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+    ev = np.linalg.eigvalsh((M + M.T) / 2)
+    assert ev.min() > 0
+    # M = p_s(A): the eigenvalues are p_s at A's eigenvalues
+    lams = np.linalg.eigvalsh(dense_A(nx, ny))
+    want = np.sort([p_closed(s, l, nx, ny) for l in lams])
+    np.testing.assert_allclose(np.sort(ev), want, rtol=1e-10)
+
+
+def _textbook_pcg(A, M, b, iters):
+    """Dense preconditioned CG, the textbook recurrence, iters steps."""
+    x = np.zeros_like(b)
+    r = b - A @ x
+    z = M @ r
+    p = z.copy()
+    rho = r @ z
+    for _ in range(iters):
+        s = A @ p
+        alpha = rho / (p @ s)
+        x = x + alpha * p
+        r = r - alpha * s
+        z = M @ r
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return x
+
+
+@pytest.mark.parametrize("s", [2, 3, 5])
+def test_iterates_match_a_dense_textbook_pcg(s):
+    nx, ny = 12, 9
+    n = nx * ny
+    A = dense_A(nx, ny)
+    M = np.column_stack([oracle.cheb_apply(np.eye(n)[:, k].reshape(ny, nx), nx, ny, s).ravel()
+                         for k in range(n)])
+    b = np.random.default_rng(s).uniform(-1, 1, n)
+    for k in (1, 2, 5, 12):
+        xt = _textbook_pcg(A, M, b, k)
+        for mode in MODES:
+            o = GPU_LIKE if mode == MODE_CANONICAL else None
+            x, r = oracle.pcg(b.reshape(ny, nx), nx, ny, s, tol=0.0, maxit=k, mode=mode, order=o)
+            assert r.iterations == k
+            assert np.linalg.norm(x.ravel() - xt) <= 1e-11 * np.linalg.norm(xt), (s, k, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_one_step_is_plain_cg(mode):
+    """s = 1: M = I/4 exactly, and scaling by a power of two commutes with
+    rounding, so every iterate is CG's to the last bit."""
+    nx, ny = 50, 37
+    b = np.random.default_rng(3).uniform(-1, 1, (ny, nx))
+    o = GPU_LIKE if mode == MODE_CANONICAL else None
+    assert oracle.cheb_coeffs(nx, ny, 1)[0] == 0.25
+    for tol, maxit in ((0.0, 17), (1e-9, 5000)):
+        xp, rp = oracle.pcg(b, nx, ny, 1, tol=tol, maxit=maxit, mode=mode, order=o)
+        xc, rc = oracle.cg(b, nx, ny, tol=tol, maxit=maxit, mode=mode, order=o)
+        assert rp.iterations == rc.iterations and rp.status == rc.status
+        np.testing.assert_array_equal(xp, xc)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("s", [3, 8])
+def test_solution_against_cholesky(mode, s):
+    nx, ny = 40, 31
+    A = dense_A(nx, ny)
+    b = np.random.default_rng(7).uniform(-1, 1, (ny, nx))
+    xs = sla.cho_solve(sla.cho_factor(A), b.ravel()).reshape(ny, nx)
+    o = GPU_LIKE if mode == MODE_CANONICAL else None
+    x, r = oracle.pcg(b, nx, ny, s, tol=1e-12, maxit=5000, mode=mode, order=o)
+    lo, hi = spectrum(nx, ny)
+    assert r.status == 0 and r.rel_res_true <= 1.5e-12
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 2 * 1e-12 * hi / lo
+
+
+def test_fewer_iterations_than_cg():
+    """kappa(p_s(A) A) is about kappa(A) / s^2: at 128^2 eight steps cut the
+    iterations to well under half (a quarter measured)."""
+    n = 128
+    b = np.random.default_rng(5).uniform(-1, 1, (n, n))
+    _, rc = oracle.cg(b, n, n, tol=1e-8, maxit=20000)
+    its = {}
+    for s in (2, 4, 8):
+        x, r = oracle.pcg(b, n, n, s, tol=1e-8, maxit=20000)
+        assert r.status == 0 and r.rel_res_true <= 1.2e-8
+        its[s] = r.iterations
+    assert its[2] <= 0.6 * rc.iterations
+    assert its[4] <= 0.6 * rc.iterations
+    assert its[8] <= 0.4 * rc.iterations and its[8] < its[4]
+
+
+def test_edge_cases_and_rejections():
+    nx, ny = 9, 7
+    b = np.random.default_rng(1).uniform(-1, 1, (ny, nx))
+    x, r = oracle.pcg(np.zeros_like(b), nx, ny, 4, x0=np.ones_like(b))
+    assert r.status == 0 and r.iterations == 0 and not x.any()
+    x, r = oracle.pcg(b, nx, ny, 4, tol=1e-14, maxit=2)
+    assert r.status == 2 and r.iterations == 2
+    b2 = b.copy()
+    b2[3, 3] = np.nan
+    x, r = oracle.pcg(b2, nx, ny, 4)
+    assert r.status == 3 and r.iterations == 0
+    for bad in (0, 65):
+        with pytest.raises(ValueError):
+            oracle.pcg(b, nx, ny, bad)
+    with pytest.raises(ValueError):
+        oracle.cheb_apply(b, nx, ny, 0)
