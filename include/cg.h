@@ -98,6 +98,13 @@ typedef struct {
   cg_variant variant;      /* Algorithm 1 or Algorithm 2                              */
   cg_precision precision;  /* FP64, FP32 inner CG inside FP64 refinement, or fixed    */
   double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
+  int32_t precond;         /* 0: none; s = 1..8: classic FP64 CG preconditioned by
+                              M^-1 = p_s(A), s steps of Chebyshev semi-iteration over
+                              the operator's exact spectrum interval
+                              [4 -+ 2cos(pi/(nx+1)) -+ 2cos(pi/(ny+1))] (the M^-1 of
+                              the pipelined-CG literature Section I builds on);
+                              cg_solve only (batches and serving reject it)        */
+  int32_t pad_;
 } cg_problem;
 
 typedef struct {

@@ -30,7 +30,8 @@ class cg_problem(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("mem", C.c_int32),
                 ("b", C.c_void_p), ("x0", C.c_void_p), ("x", C.c_void_p),
                 ("tol", C.c_double), ("maxit", C.c_int32), ("variant", C.c_int32),
-                ("precision", C.c_int32), ("inner_tol", C.c_double)]
+                ("precision", C.c_int32), ("inner_tol", C.c_double),
+                ("precond", C.c_int32), ("pad_", C.c_int32)]
 
 
 class cg_result(C.Structure):
@@ -142,7 +143,7 @@ def _ptr_mem(a):
 
 
 def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
-                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0):
+                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0):
     pb, mb = _ptr_mem(b)
     px, mx = _ptr_mem(x)
     p0, m0 = _ptr_mem(x0)
@@ -152,7 +153,7 @@ def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
         if v is not None and (v.size if isinstance(v, np.ndarray) else v.numel()) != nx * ny:
             raise ValueError("vector size does not match the %dx%d grid" % (nx, ny))
     p = cg_problem(nx, ny, mb, pb, p0, px, float(tol), int(maxit), int(variant),
-                   int(precision), float(inner_tol))
+                   int(precision), float(inner_tol), int(precond), 0)
     return p
 
 
@@ -240,8 +241,9 @@ class Context:
         _check("cg_dot", self.lib.cg_dot(self.h, nx, ny, ma, pa, pb, C.byref(out)))
         return out.value
 
-    def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64):
-        p = cg_problem(nx, ny, CG_MEM_DEVICE, None, None, None, 1e-8, 1, variant, precision, 0.0)
+    def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64, precond=0):
+        p = cg_problem(nx, ny, CG_MEM_DEVICE, None, None, None, 1e-8, 1, variant, precision, 0.0,
+                       precond, 0)
         info = cg_plan_info()
         _check("cg_plan", self.lib.cg_plan(self.h, C.byref(p), C.byref(info)))
         return info

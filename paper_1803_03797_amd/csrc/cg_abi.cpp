@@ -56,6 +56,7 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
   for (int32_t i = 0; i < n; ++i) {
     int rc = cgr::validate(&probs[i]);
     if (rc) return rc;
+    if (probs[i].precond) return CG_E_INVALID;  // preconditioned: cg_solve only
   }
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -67,6 +68,7 @@ int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
   if (!ctx || !ticket) return CG_E_INVALID;
   int rc = cgr::validate(prob);
   if (rc) return rc;
+  if (prob->precond) return CG_E_INVALID;  // preconditioned: cg_solve only
   return cgr_server_submit(C(ctx), prob, ticket);
 }
 

@@ -23,6 +23,7 @@ constexpr int kWavesPerTile = 4;
 constexpr int kWgGroups = 2;     // tile groups of the single-work-group solver
 constexpr int kRrRows = 20;       // rows per thread of the register-resident solver
 constexpr int kRrThreads = 512;   // its largest work-group
+constexpr int kChebMaxSteps = 8;  // Chebyshev preconditioner steps (halo s - 1)
 
 // Device-side solve status (host maps it to the ABI codes).
 enum : int32_t {
@@ -36,6 +37,10 @@ enum : int32_t {
 
 enum : int32_t {
   F_BB_PENDING = 1,      // the next prologue takes (b,b) from partial slot 1
+  F_PRECOND = 2,         // classic CG preconditioned by the Chebyshev pass:
+                         // K_CG1 takes gamma = (r,r) and rho = (r,z) from the
+                         // K_CHEB partials, keeps rho in State::delta, and
+                         // K_CG2 forms alpha = rho / (p, A p)
 };
 
 // Scalar state of one solve.  Kept in device memory, double-buffered by pass
@@ -89,6 +94,7 @@ enum : int32_t {
   K_PCGX,         // K_PCG of an even iteration: also applies both x updates
   K_CG2X,         // K_CG2 of an even iteration: also applies both x updates
   K_CG2FX,        // K_CG2F of an even inner iteration: both d updates
+  K_CHEB,         // z = p_s(A) r (Chebyshev preconditioner); slots (r,r), (r,z)
   K_NKINDS
 };
 
@@ -126,7 +132,8 @@ struct PassArgs {
   const double* u;         // apply / dot inputs
   double* y;
   int32_t rev;             // walk the tiles in reverse order (alternate passes)
-  int32_t pad_;
+  int32_t cheb_s;          // K_CHEB: Chebyshev steps s (1..kChebMaxSteps)
+  const double* cheb;      // K_CHEB: c0, then c1[s-1], then c2[s-1]
 };
 
 // Scalars a pass body needs, chosen by the preceding transition.

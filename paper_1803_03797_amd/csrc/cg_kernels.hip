@@ -302,10 +302,43 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     sc.al = al;
     sc.be = be;
     return true;
+  } else if constexpr (KIND == K_CHEB) {
+    // z = M^-1 r runs while the solve does; it takes (b,b) after the first
+    // residual, the stop test stays with the next pass (on its (r,r) slot)
+    if (s.status != ST_RUNNING) return false;
+    if (s.flags & F_BB_PENDING) {
+      s.bb = sum[1];
+      s.thr = (s.tol * s.tol) * s.bb;
+      s.flags &= ~F_BB_PENDING;
+      if (s.bb == 0.0) {
+        s.status = ST_ZERO_RHS;
+        return false;
+      }
+    }
+    return true;
   } else if constexpr (KIND == K_CG1) {
     // Algorithm 1: beta = (r,r)_new / (r,r)_old, then p = r + beta p.
+    // Preconditioned: slots (r,r), (r,z) of the Chebyshev pass; beta =
+    // rho_new / rho_old with rho = (r,z) kept in delta, then p = z + beta p.
     if (s.status != ST_RUNNING) return false;
     const double gamma = sum[0];
+    if (s.flags & F_PRECOND) {
+      int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
+      const double rho = sum[1];
+      double be = 0.0;
+      if (st == ST_RUNNING) {
+        if (!(rho > 0.0) || !isfinite(rho)) st = ST_BREAKDOWN;
+        else if (s.k == 0) sc.first = 1;
+        else be = rho / s.delta;
+      }
+      s.gamma = gamma;
+      s.status = st;
+      if (st != ST_RUNNING) return false;
+      s.delta = rho;
+      s.beta = be;
+      sc.be = be;
+      return true;
+    }
     if (s.flags & F_BB_PENDING) {
       s.bb = sum[1];
       s.thr = (s.tol * s.tol) * s.bb;
@@ -333,7 +366,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
       s.status = ST_BREAKDOWN;
       return false;
     }
-    s.alpha = s.gamma / pi;
+    s.alpha = ((s.flags & F_PRECOND) ? s.delta : s.gamma) / pi;
     s.k += 1;
     sc.al = s.alpha;
     return true;
@@ -1118,7 +1151,8 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
     State s = load_state_uniform(a.st_in);
     double sum[2] = {0.0, 0.0};
     if constexpr (DI > 0) {
-      const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
+      const int din =
+          (KIND == K_CG1) ? ((s.flags & (F_BB_PENDING | F_PRECOND)) ? 2 : 1) : DI;
       if (s.status == ST_RUNNING) {
         if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
         else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
@@ -1165,6 +1199,137 @@ __global__ __launch_bounds__(kGroup) void k_final(PassArgs a) {
     State s = *a.st_in;
     s.res2 = sum[0];
     *a.st_out = s;
+  }
+}
+
+// ---------------------------------------------- Chebyshev preconditioner --
+//
+// z = p_s(A) r: s steps of Chebyshev semi-iteration on A y = r from y = 0
+// (d_0 = c0 r, y_1 = d_0; r_k = r_(k-1) - A d_(k-1), d_k = fma(c1_k, d_(k-1),
+// c2_k r_k), y_(k+1) = y_k + d_k), the coefficients from the operator's exact
+// spectrum interval (computed on the host).  Each work-group takes whole
+// tiles of the pass geometry; a tile is done strip by strip (the strip of
+// wavefront w is rows [w rows, (w+1) rows) of the tile), in blocks of at most
+// kChebRows rows: the block and a halo of s - 1 cells on every side are
+// loaded into LDS, the s - 1 stencil steps shrink the valid region by one
+// cell each, and the block's z is written.  Cells outside the grid stay zero.
+// The stencil, the fma structure and the order of the y sums are those of the
+// oracle's canonical mode.  The partials (r,r) and (r,z) of a tile follow the
+// tile order of every pass: the strip's wavefront accumulates them down its
+// rows per column (fma), the lane value is the sum of its columns, then the
+// butterfly and the wavefronts in order.
+constexpr int kChebRows = 32;
+constexpr int kChebHalo = kChebMaxSteps - 1;
+constexpr int kChebW = kWave * 2 + 2 * kChebHalo;      // region width (FP64 tiles)
+constexpr int kChebH = kChebRows + 2 * kChebHalo;      // region height
+constexpr int kChebLds = 2 * kChebW * kChebH + kWave * 2 * kChebRows;
+
+__global__ __launch_bounds__(kGroup) void k_cheb(PassArgs a) {
+  constexpr int CPL = 2, TW = kWave * CPL;
+  __shared__ double lds[kChebLds + 64];
+  double* D = lds;                       // d_k over the region
+  double* Rk = lds + kChebW * kChebH;    // r_k over the region
+  double* Y = lds + 2 * kChebW * kChebH; // y over the block
+  double* red = lds + kChebLds;          // tile_partial / cross-tile scratch
+  {
+    State s = load_state_uniform(a.st_in);
+    double sum[2] = {0.0, 0.0};
+    if (s.status == ST_RUNNING && (s.flags & F_BB_PENDING)) {
+      cross_tile_sum<2>(a.part_in, a.g.tiles, sum, red);
+      sum[0] = uniform(sum[0]);
+      sum[1] = uniform(sum[1]);
+    }
+    Sc sc;
+    const bool run = transition<K_CHEB>(s, sum, sc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
+    if (!run) return;
+  }
+  const Geo& g = a.g;
+  const int sdeg = a.cheb_s, h = sdeg - 1;
+  const double c0 = a.cheb[0];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+  const int T = g.tiles;
+  const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
+  int par = 0;
+  for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
+    const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
+    const int ct = (t % g.ntx) * TW, ty = t / g.ntx;
+    double arr[CPL], arz[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) arr[k] = arz[k] = 0.0;
+    for (int w = 0; w < kWavesPerTile; ++w) {
+      const int s0 = ty * g.th + w * g.rows, s1 = min(s0 + g.rows, g.ny);
+      for (int y0 = s0; y0 < s1; y0 += kChebRows) {
+        const int sb = min(kChebRows, s1 - y0);
+        const int RW = TW + 2 * h, RH = sb + 2 * h;
+        __syncthreads();  // the previous block's Y has been read
+        for (int q = tid; q < RW * RH; q += kGroup) {
+          const int rr = q / RW, cc = q - rr * RW;
+          const int j = y0 - h + rr, i = ct - h + cc;
+          const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+          const double rv = in ? a.r[(size_t)j * g.pitch + i] : 0.0;
+          const double dv = rv * c0;
+          D[rr * kChebW + cc] = dv;
+          Rk[rr * kChebW + cc] = rv;
+          if (rr >= h && rr < h + sb && cc >= h && cc < h + TW) Y[(rr - h) * TW + cc - h] = dv;
+        }
+        __syncthreads();
+        for (int k = 1; k < sdeg; ++k) {
+          const double c1 = a.cheb[k], c2 = a.cheb[sdeg - 1 + k];
+          const int W2 = RW - 2 * k, H2 = RH - 2 * k;
+          // r_k = r_(k-1) - A d_(k-1) on the cells whose neighbours are valid
+          for (int q = tid; q < W2 * H2; q += kGroup) {
+            const int rr = k + q / W2, cc = k + q % W2;
+            const int j = y0 - h + rr, i = ct - h + cc;
+            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+              const int o = rr * kChebW + cc;
+              const double sv =
+                  (((4.0 * D[o] - D[o - 1]) - D[o + 1]) - D[o - kChebW]) - D[o + kChebW];
+              Rk[o] = Rk[o] - sv;
+            }
+          }
+          __syncthreads();
+          // d_k = fma(c1, d_(k-1), c2 r_k); y += d_k on the block
+          for (int q = tid; q < W2 * H2; q += kGroup) {
+            const int rr = k + q / W2, cc = k + q % W2;
+            const int j = y0 - h + rr, i = ct - h + cc;
+            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+              const int o = rr * kChebW + cc;
+              const double dv = fma(c1, D[o], c2 * Rk[o]);
+              D[o] = dv;
+              if (rr >= h && rr < h + sb && cc >= h && cc < h + TW) {
+                double& yv = Y[(rr - h) * TW + cc - h];
+                yv = yv + dv;
+              }
+            }
+          }
+          __syncthreads();
+        }
+        // z of the block; the strip's wavefront accumulates the partials
+        for (int q = tid; q < TW * sb; q += kGroup) {
+          const int rr = q / TW, cc = q - rr * TW;
+          const int j = y0 + rr, i = ct + cc;
+          if (i < g.nx) a.z[(size_t)j * g.pitch + i] = Y[q];
+        }
+        if (wave == w) {
+          for (int rr = 0; rr < sb; ++rr) {
+            const size_t off = (size_t)(y0 + rr) * g.pitch + ct + lane * CPL;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+              if (ct + lane * CPL + k < g.nx) {
+                const double rv = a.r[off + k], zv = Y[rr * TW + lane * CPL + k];
+                arr[k] = fma(rv, rv, arr[k]);
+                arz[k] = fma(rv, zv, arz[k]);
+              }
+            }
+          }
+        }
+      }
+    }
+    double lv[2] = {fold<CPL>(arr), fold<CPL>(arz)};
+    tile_partial<2>(lv, a.part_out, T, t, red, par);
   }
 }
 
@@ -1873,7 +2038,8 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.u = nullptr;
   a.y = nullptr;
   a.rev = 0;
-  a.pad_ = 0;
+  a.cheb_s = 0;
+  a.cheb = nullptr;
   if constexpr (defers_x<KIND>()) {
     if (flush) {
       for (int t = it.t0; t < it.t1; ++t) run_flush<KIND, CPL>(a, t, sc);
@@ -2077,6 +2243,11 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
     case K_REF_UPDATE:
       hipLaunchKernelGGL((k_pass<K_REF_UPDATE, 4>), dim3(grid), dim3(kGroup), 0, st, a);
       return hipGetLastError();
+    case K_CHEB:
+      if (fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.z || !a.r)
+        return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_cheb, dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
 }
@@ -2159,6 +2330,7 @@ size_t pass_algorithmic_bytes(int kind, int64_t dof) {
     case K_REF_UPDATE: per = 8 * 2 + 4; break;  // read x, d; write x
     case K_APPLY: per = 8 * 2; break;
     case K_DOT: per = 8 * 2; break;
+    case K_CHEB: per = 8 * 2; break;            // read r; write z (halo not counted)
   }
   return per * (size_t)dof;
 }

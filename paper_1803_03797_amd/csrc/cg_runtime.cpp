@@ -59,6 +59,10 @@ int validate(const cg_problem* p) {
       p->precision != CG_PREC_FIXED)
     return CG_E_INVALID;
   if (p->precision == CG_PREC_FIXED && !fixed_fits(p->nx, p->ny)) return CG_E_INVALID;
+  if (p->precond < 0 || p->precond > kChebMaxSteps) return CG_E_INVALID;
+  if (p->precond > 0 &&
+      (p->precision != CG_PREC_FP64 || p->variant != CG_VARIANT_CLASSIC))
+    return CG_E_INVALID;
   if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
     return CG_E_INVALID;
   return CG_OK;
@@ -96,7 +100,8 @@ static int wg_rows(int nx, int ny) {
 }
 
 bool Ctx::use_wg(const cg_problem* p) const {
-  return p->precision == CG_PREC_FP64 && (int64_t)p->nx * p->ny <= wg_max_dof;
+  return p->precision == CG_PREC_FP64 && p->precond == 0 &&
+         (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
 // threads of the register-resident solver: rows of nx + 1 (one idle thread
@@ -106,7 +111,7 @@ static int64_t rr_threads_needed(int nx, int ny) {
 }
 
 bool Ctx::use_rr(const cg_problem* p) const {
-  return rr_enabled && p->precision == CG_PREC_FP64 &&
+  return rr_enabled && p->precision == CG_PREC_FP64 && p->precond == 0 &&
          rr_threads_needed(p->nx, p->ny) <= kRrThreads;
 }
 
@@ -118,6 +123,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   pl.wg = use_wg(p);
   pl.rr = allow_rr && use_rr(p);
   pl.fixed = p->precision == CG_PREC_FIXED;
+  pl.precond = p->precond;
   if (pl.fixed) {
     // one unknown per thread up to 1024 unknowns, then 1024 threads
     const int64_t dof = (int64_t)p->nx * p->ny;
@@ -137,7 +143,9 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
       rows = it->second.rows;
       grid = it->second.grid;
       // classic FP64 may run with 4 columns (32 B) per lane
-      if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4) pl.fp32g = 1;
+      // (not with the preconditioner, whose pass is written for 2)
+      if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4 && !pl.precond)
+        pl.fp32g = 1;
     } else {
       rows = default_rows(p->nx, p->ny, pl.fp32g);
     }
@@ -176,10 +184,11 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   } else if (p->variant == CG_VARIANT_PIPELINED) {
     n64 = 8;  // b, x, r, w, w', z, q, p
   } else {
-    n64 = 5;  // b, x, r, p, p'
+    n64 = pl.precond ? 6 : 5;  // b, x, r, p, p' (and z)
   }
   pl.part = round_up((size_t)2 * T * 8, Arena::kAlign);
-  pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256);
+  pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
+                 (pl.precond ? 256 : 0);
   return pl;
 }
 
@@ -190,10 +199,11 @@ size_t footprint_of(const cg_problem* p) {
   Geo g = make_geo(p->nx, p->ny, fp32g, 1);
   const size_t elems = (size_t)g.pitch * p->ny;
   const size_t v64 = round_up(elems * 8, Arena::kAlign), v32 = round_up(elems * 4, Arena::kAlign);
-  size_t n64 = fp32g ? 2 : (p->variant == CG_VARIANT_PIPELINED ? 8 : 5);
+  size_t n64 = fp32g ? 2 : (p->variant == CG_VARIANT_PIPELINED ? 8 : (p->precond ? 6 : 5));
   size_t n32 = fp32g ? 4 : 0;
   const size_t part = round_up((size_t)2 * g.tiles * 8, Arena::kAlign);
-  return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256);
+  return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256) +
+         (p->precond ? 256 : 0);
 }
 
 // --------------------------------------------------------- profiling --
@@ -242,6 +252,7 @@ static const char* kind_name(int kind, int fp32g) {
     case K_CG2F: return "update_norm_f32_nx";
     case K_CG2FX: return "update_norm_f32";
     case K_REF_UPDATE: return "ref_update";
+    case K_CHEB: return "cheb_precond";
     case K_APPLY: return "apply";
     case K_DOT: return "dot";
   }
@@ -291,6 +302,10 @@ bool carve(Ctx& c, Work& w) {
     w.p = (double*)take(pl.v64);
   } else {
     w.r = (double*)take(pl.v64);
+    if (pl.precond) {
+      w.z = (double*)take(pl.v64);
+      w.cheb = (double*)take(256);
+    }
     w.pc[0] = (double*)take(pl.v64);
     w.pc[1] = (double*)take(pl.v64);
   }
@@ -351,10 +366,20 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
       a.w_out = w.w[(i + 1) & 1];
     });
   } else {
-    e = issue(c, w, K_CG1, [&](PassArgs& a) {
-      a.pc_in = w.pc[i & 1];
-      a.pc_out = w.pc[(i + 1) & 1];
-    });
+    // preconditioned: z = M^-1 r first, and the direction is p = z + beta p
+    e = hipSuccess;
+    if (w.pl.precond)
+      e = issue(c, w, K_CHEB, [&](PassArgs& a) {
+        a.z = w.z;
+        a.cheb = w.cheb;
+        a.cheb_s = w.pl.precond;
+      });
+    if (e == hipSuccess)
+      e = issue(c, w, K_CG1, [&](PassArgs& a) {
+        if (w.pl.precond) a.r = w.z;
+        a.pc_in = w.pc[i & 1];
+        a.pc_out = w.pc[(i + 1) & 1];
+      });
     if (e == hipSuccess)
       e = issue(c, w, (i & 1) ? K_CG2X : K_CG2, [&](PassArgs& a) {
         a.pc_in = w.pc[(i + 1) & 1];
@@ -391,8 +416,8 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     for (int k = 0; k < iters; ++k) HIPCHK(issue_iteration(c, w));
     return CG_OK;
   }
-  GraphKey key{w.mem, w.pl.g.nx, w.pl.g.ny, w.pl.g.rows, w.pl.grid, w.pl.variant,
-               w.pl.refined, iters, w.m & 1, w.i & 1};
+  GraphKey key{w.mem,  w.pl.g.nx, w.pl.g.ny, w.pl.g.rows, w.pl.grid, w.pl.variant,
+               w.pl.refined, iters,     w.m & 1,   w.i & 1,     w.pl.precond};
   auto it = c.graphs.find(key);
   if (it == c.graphs.end()) {
     hipGraph_t g;
@@ -418,7 +443,9 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     it = c.graphs.emplace(key, ge).first;
   }
   HIPCHK(hipGraphLaunch(it->second, c.st));
-  w.m += iters * (w.pl.variant == CG_VARIANT_PIPELINED && !w.pl.refined ? 1 : 2);
+  w.m += iters * (w.pl.variant == CG_VARIANT_PIPELINED && !w.pl.refined ? 1
+                  : w.pl.precond                                          ? 3
+                                                                          : 2);
   w.i += iters;
   return CG_OK;
 }
@@ -434,11 +461,30 @@ void Ctx::forget_graphs(const void* mem) {
   }
 }
 
+// The Chebyshev preconditioner's coefficients (the same closed-form spectrum
+// interval and recurrence as the oracle; both run on the host, so both get
+// the host's cos()).
+void cheb_coeffs(int nx, int ny, int s, double* out) {
+  const double pi = 3.14159265358979323846;
+  const double a = 2.0 * std::cos(pi / (double)(nx + 1)) + 2.0 * std::cos(pi / (double)(ny + 1));
+  const double lmax = 4.0 + a, lmin = 4.0 - a;
+  const double theta = (lmax + lmin) / 2.0, delta = (lmax - lmin) / 2.0;
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  out[0] = 1.0 / theta;
+  for (int k = 1; k < s; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    out[k] = rn * rho;                   // c1
+    out[s - 1 + k] = 2.0 * rn / delta;   // c2
+    rho = rn;
+  }
+}
+
 State initial_state(const cg_problem* p) {
   State s;
   memset(&s, 0, sizeof(s));
   s.status = ST_RUNNING;
-  s.flags = F_BB_PENDING;
+  s.flags = F_BB_PENDING | (p->precond > 0 ? F_PRECOND : 0);
   s.tol = p->tol;
   s.inner_tol = p->inner_tol > 0.0 ? p->inner_tol : 1e-4;
   s.maxit = p->maxit;
@@ -466,6 +512,12 @@ int stage_in(Ctx& c, Work& w, const cg_problem* p) {
   memcpy(c.host_state, &s, sizeof(s));
   int rc = stage_in_async(c, w, p, (const State*)c.host_state);
   if (rc) return rc;
+  if (w.pl.precond) {
+    double* coef = (double*)(c.host_state + 1024);  // past the state, same pinned page
+    cheb_coeffs(p->nx, p->ny, w.pl.precond, coef);
+    HIPCHK(hipMemcpyAsync(w.cheb, coef, (size_t)(2 * w.pl.precond - 1) * sizeof(double),
+                          hipMemcpyHostToDevice, c.st));
+  }
   // the pinned staging buffer is reused by the next call: wait for the copy
   HIPCHK(hipStreamSynchronize(c.st));
   return CG_OK;

@@ -21,6 +21,7 @@ struct Plan {
   bool rr = false;   // ... with the vectors on chip (register-resident solver)
   int rr_threads = 0;
   bool fixed = false;  // fixed-point solve, one work-group (cg_fixed.hip)
+  int precond = 0;     // Chebyshev preconditioner steps (classic FP64, tile passes)
   int fx_threads = 0;
   bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};
@@ -36,12 +37,13 @@ struct Pin {
 
 struct GraphKey {
   const void* mem;
-  int nx, ny, rows, grid, variant, refined, iters, mpar, ipar;
+  int nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond;
   bool operator<(const GraphKey& o) const {
-    const int a[] = {nx, ny, rows, grid, variant, refined, iters, mpar, ipar};
-    const int b[] = {o.nx, o.ny, o.rows, o.grid, o.variant, o.refined, o.iters, o.mpar, o.ipar};
+    const int a[] = {nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond};
+    const int b[] = {o.nx, o.ny, o.rows,  o.grid, o.variant, o.refined,
+                     o.iters, o.mpar, o.ipar, o.precond};
     if (mem != o.mem) return mem < o.mem;
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 10; ++i)
       if (a[i] != b[i]) return a[i] < b[i];
     return false;
   }
@@ -65,6 +67,7 @@ struct Work {
   double *b = nullptr, *x = nullptr, *r = nullptr, *w[2] = {}, *z = nullptr, *q = nullptr,
          *p = nullptr, *pc[2] = {};
   float *rf = nullptr, *df = nullptr, *pf[2] = {};
+  double* cheb = nullptr;  // preconditioner coefficients (c0, c1[s-1], c2[s-1])
   double* part[2] = {};
   cgk::State* S[2] = {};
   int m = 0;  // passes issued (state/partial parity)
@@ -78,6 +81,8 @@ double now_s();
 bool carve(Ctx& c, Work& w);
 int stage_in(Ctx& c, Work& w, const cg_problem* p);
 cgk::State initial_state(const cg_problem* p);
+// c0, c1[s-1], c2[s-1] of the Chebyshev preconditioner with s steps
+void cheb_coeffs(int nx, int ny, int s, double* out);
 // stage_in without waiting: the initial state is copied from `pinned` (host
 // memory the caller keeps unchanged until the stream has passed the copy).
 int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const cgk::State* pinned);

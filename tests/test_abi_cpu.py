@@ -36,10 +36,11 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(nx=10, ny=7, mem=cg.CG_MEM_HOST, b=1, x0=None, x=2, tol=1e-8, maxit=10,
-             variant=0, precision=0, inner_tol=0.0)
+             variant=0, precision=0, inner_tol=0.0, precond=0)
     d.update(kw)
     return cg.cg_problem(d["nx"], d["ny"], d["mem"], d["b"], d["x0"], d["x"], d["tol"],
-                         d["maxit"], d["variant"], d["precision"], d["inner_tol"])
+                         d["maxit"], d["variant"], d["precision"], d["inner_tol"],
+                         d["precond"], 0)
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
@@ -49,7 +50,10 @@ def _prob(**kw):
                                  dict(precision=2, nx=101, ny=101),
                                  dict(precision=2, nx=100, ny=101),
                                  dict(precision=2, nx=1, ny=6783),
-                                 dict(precision=2, nx=5088, ny=1)])
+                                 dict(precision=2, nx=5088, ny=1),
+                                 dict(precond=-1), dict(precond=9),
+                                 dict(precond=4, variant=1), dict(precond=4, precision=1),
+                                 dict(precond=4, precision=2)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -61,14 +65,18 @@ def test_validation_accepts():
     for nx, ny in ((1, 1), (100, 100), (98, 102), (1, 6782), (5087, 1)):
         assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
     assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
+    # Chebyshev preconditioner: 1..8 steps, classic FP64
+    for s in range(0, 9):
+        assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
 
 
 def test_footprint_per_unknown():
     """Resident bytes per unknown: classic 5 FP64 vectors, pipelined 8, refined
-    2 FP64 + 4 FP32 (plus padding and small partial/state buffers)."""
+    2 FP64 + 4 FP32, preconditioned classic 6 (plus padding and small
+    partial/state buffers)."""
     n = 4096
-    for variant, prec, per in ((0, 0, 40), (1, 0, 64), (0, 1, 32)):
-        fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, precision=prec))
+    for variant, prec, per, pre in ((0, 0, 40, 0), (1, 0, 64, 0), (0, 1, 32, 0), (0, 0, 48, 4)):
+        fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, precision=prec, precond=pre))
         assert per * n * n <= fp <= per * n * n * 1.01 + (1 << 20)
 
 

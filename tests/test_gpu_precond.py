@@ -1,0 +1,167 @@
+"""GPU parity of Chebyshev-preconditioned classic CG (cg_problem.precond = s):
+the Chebyshev pass (z = p_s(A) r with the partials (r,r), (r,z)) plus the two
+classic passes, against the oracle's preconditioned CG in the library's tile
+order (bitwise) and in the textbook order (FP64 tolerance)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import MODE_CANONICAL, MODE_SEQUENTIAL
+from paper_1803_03797_amd import cg
+
+pytestmark = pytest.mark.gpu
+
+# one tile, ragged tiles, single rows / columns, grids that would otherwise
+# take the on-chip or single-work-group solvers, several tile rows
+SHAPES = [(1, 1), (2, 2), (64, 1), (1, 300), (100, 100), (130, 70), (300, 190), (513, 257),
+          (1024, 1024)]
+STEPS = (1, 2, 4, 8)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = cg.Context(device=0, arena_bytes=2 << 30)
+    yield c
+    c.close()
+
+
+def tile_order(ctx, nx, ny, s):
+    info = ctx.cg_plan(nx, ny, precond=s)
+    assert info.path == 0 and info.cols_per_lane == 2
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb else 1.0)
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("s", STEPS)
+def test_lockstep_bitwise(ctx, nx, ny, s):
+    b = np.random.default_rng(nx * 13 + ny + s).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, s)
+    for m in (1, 2, 7):
+        say("precond lockstep", nx, ny, "s", s, "maxit", m)
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, nx, ny, tol=0.0, maxit=m, precond=s)
+        xo, ro = oracle.pcg(b, nx, ny, s, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o)
+        assert rc == ro.status and res.iterations == ro.iterations
+        np.testing.assert_array_equal(x, xo)
+        assert res.rel_res_recursive == ro.rel_res_recursive
+        assert res.rel_res_true == ro.rel_res_true
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 100), (300, 190), (513, 257)])
+@pytest.mark.parametrize("s", [2, 4, 8])
+def test_natural_stop(ctx, nx, ny, s):
+    b = np.random.default_rng(3 * nx + ny).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, s)
+    say("precond natural stop", nx, ny, "s", s)
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-8, maxit=20000, precond=s)
+    xk, rk = oracle.pcg(b, nx, ny, s, tol=1e-8, maxit=20000, mode=MODE_CANONICAL, order=o)
+    xs, rs = oracle.pcg(b, nx, ny, s, tol=1e-8, maxit=20000, mode=MODE_SEQUENTIAL)
+    assert rc == cg.CG_OK and res.iterations == rk.iterations
+    np.testing.assert_array_equal(x, xk)
+    assert abs(res.iterations - rs.iterations) <= 2
+    assert rel(x, xs) <= 1e-10
+    assert res.rel_res_true <= 1.2e-8
+
+
+def test_one_step_is_plain_cg_on_the_gpu(ctx):
+    """s = 1 scales r by exactly 1/4: the preconditioned solve reproduces the
+    unpreconditioned one bit for bit (both on the tile passes here)."""
+    nx, ny = 513, 257
+    b = np.random.default_rng(11).uniform(-1, 1, (ny, nx))
+    assert ctx.cg_plan(nx, ny).path == 0
+    for tol, maxit in ((0.0, 9), (1e-9, 5000)):
+        xp = np.zeros_like(b)
+        xc = np.zeros_like(b)
+        rcp, rp = ctx.solve(b, xp, nx, ny, tol=tol, maxit=maxit, precond=1)
+        rcc, rc_ = ctx.solve(b, xc, nx, ny, tol=tol, maxit=maxit)
+        assert rcp == rcc and rp.iterations == rc_.iterations
+        np.testing.assert_array_equal(xp, xc)
+
+
+def test_fewer_iterations(ctx):
+    n = 512
+    b = np.random.default_rng(2).uniform(-1, 1, (n, n))
+    x = np.zeros_like(b)
+    _, r0 = ctx.solve(b, x, n, n, tol=1e-8, maxit=20000)
+    its = {}
+    for s in (4, 8):
+        x = np.zeros_like(b)
+        rc, r = ctx.solve(b, x, n, n, tol=1e-8, maxit=20000, precond=s)
+        assert rc == cg.CG_OK and r.rel_res_true <= 1.2e-8
+        its[s] = r.iterations
+    say("iterations: CG", r0.iterations, "PCG", its)
+    assert its[8] <= 0.4 * r0.iterations and its[4] <= 0.6 * r0.iterations
+
+
+def test_edge_cases(ctx):
+    nx, ny, s = 200, 150, 4
+    b = np.random.default_rng(4).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, s)
+    x = np.full_like(b, 2.0)
+    rc, res = ctx.solve(np.zeros_like(b), x, nx, ny, x0=np.ones_like(b), precond=s)
+    assert rc == cg.CG_OK and res.iterations == 0 and not x.any()
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-14, maxit=3, precond=s)
+    assert rc == cg.CG_NOT_CONVERGED and res.iterations == 3
+    b2 = b.copy()
+    b2[5, 5] = np.nan
+    rc, res = ctx.solve(b2, x, nx, ny, precond=s)
+    assert rc == cg.CG_BREAKDOWN and res.iterations == 0
+    x0 = np.random.default_rng(6).uniform(-1, 1, (ny, nx))
+    x = x0.copy()
+    rc, res = ctx.solve(b, x, nx, ny, x0=x, tol=1e-9, maxit=5000, precond=s)
+    xo, ro = oracle.pcg(b, nx, ny, s, tol=1e-9, maxit=5000, x0=x0, mode=MODE_CANONICAL,
+                        order=o)
+    assert rc == cg.CG_OK and res.iterations == ro.iterations
+    np.testing.assert_array_equal(x, xo)
+
+
+def test_batches_and_serving_reject_it(ctx):
+    b = np.ones((8, 8))
+    x = np.zeros_like(b)
+    p = cg.make_problem(b, x, 8, 8, precond=4)
+    with pytest.raises(cg.CGError):
+        ctx.cg_solve_batch([p])
+    with pytest.raises(cg.CGError):
+        ctx.cg_submit(p)
+    for bad in (9, -1):
+        with pytest.raises(cg.CGError):
+            ctx.solve(b, x, 8, 8, precond=bad)
+    with pytest.raises(cg.CGError):
+        ctx.solve(b, x, 8, 8, precond=4, variant=cg.CG_VARIANT_PIPELINED)
+
+
+def test_profiled_passes(ctx):
+    n, s, m = 512, 4, 5
+    b = np.random.default_rng(1).uniform(-1, 1, (n, n))
+    x = np.zeros_like(b)
+    ctx.cg_set_profiling(True)
+    ctx.cg_kernel_stats(reset=True)
+    ctx.solve(b, x, n, n, tol=0.0, maxit=m, precond=s)
+    st = ctx.cg_kernel_stats(reset=True)
+    ctx.cg_set_profiling(False)
+    # one Chebyshev pass per iteration; the iteration after maxit only
+    # classifies the final state (its three passes count as final_check)
+    assert st["cheb_precond"]["launches"] == m
+    assert st["cheb_precond"]["bytes"] == m * 16 * n * n
+    assert st["stencil_dot"]["launches"] == m
+    assert st["final_check"]["launches"] == 3
