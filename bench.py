@@ -28,6 +28,8 @@ Other workloads (one JSON line each, not the headline):
   --workload fixed   the paper's fixed-point format (Q20.30): solve latency on
                      its synthesized grids and iteration counts, and a batch of
                      256 solves of its largest grid in one launch
+  --workload precond 4096 x 4096 to tol 1e-8: classic CG against classic CG
+                     preconditioned by s Chebyshev steps (time to solution)
   --probe            attainable HBM bandwidth of plain streaming kernels, and
                      the attainable rate of 32 x 32 -> 64-bit multiply-adds
 """
@@ -450,6 +452,63 @@ def bench_fixed(args):
     ctx.close()
 
 
+# ------------------------------------------------------------------ precond --
+
+def bench_precond(args):
+    torch, cg = setup()
+    import numpy as np
+
+    from paper_1803_03797_amd import workloads
+    n = args.n
+    w = workloads.LARGE
+    dev = torch.device("cuda:0")
+    xs = torch.from_numpy(workloads.large_solution(n, n)).to(dev)
+    b = torch.empty_like(xs)
+    ctx = cg.Context(device=0, arena_bytes=8 << 30)
+    ctx.cg_apply(xs, b, n, n)  # b = A x* with the library's stencil
+    nxs = float(torch.linalg.norm(xs))
+    out = {}
+    for s in [0] + list(args.steps_list):
+        x = torch.zeros_like(b)
+        p = cg.make_problem(b, x, n, n, tol=w["tol"], maxit=w["maxit"], precond=s)
+        ctx.cg_solve(p)  # warm: graphs captured
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = ctx.cg_solve(p)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        err = float(torch.linalg.norm(x - xs)) / nxs
+        # per-pass kernel times over a short fixed run
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        ctx.cg_solve(cg.make_problem(b, torch.zeros_like(b), n, n, tol=0.0, maxit=20, precond=s))
+        ks = kern_table(ctx.cg_kernel_stats(reset=True))
+        ctx.cg_set_profiling(False)
+        name = "cg" if s == 0 else "pcg_s%d" % s
+        per_it = sum(v["avg_us"] * v["launches"] for k, v in ks.items()
+                     if k in ("cheb_precond", "stencil_dot", "update_norm", "update_norm_nx")) / 20
+        out[name] = dict(status=cg.cg_status_str(rc), iterations=r.iterations,
+                         seconds=round(tt, 4), rel_err_vs_xstar=float("%.3g" % err),
+                         rel_res_true=float("%.3g" % r.rel_res_true),
+                         us_per_iteration=round(per_it, 1),
+                         kernels={k: v for k, v in ks.items()
+                                  if k in ("cheb_precond", "stencil_dot", "update_norm",
+                                           "update_norm_nx")})
+        log(name, json.dumps(out[name]))
+    base = out["cg"]["seconds"]
+    best = min((v["seconds"], k) for k, v in out.items())
+    emit({"metric": "time to solution, %dx%d to tol 1e-8 (classic CG, Chebyshev-preconditioned "
+                    "classic CG)" % (n, n),
+          "workload": "precond", "value": round(best[0], 4), "unit": "s",
+          "higher_is_better": False,
+          "config": {"workload": "%dx%d Laplace, b=A(sin*sin+1e-3 noise), x0=0, tol 1e-8" % (n, n),
+                     "steps": list(args.steps_list)},
+          "dtype": "f64", "results": out, "best": best[1],
+          "speedup_vs_cg": round(base / best[0], 3)})
+    ctx.close()
+
+
 # ---------------------------------------------------------------------- huge --
 
 def bench_huge(args):
@@ -662,7 +721,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
-    ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed"])
+    ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed", "precond"])
+    ap.add_argument("--steps-list", type=int, nargs="*", default=[2, 4, 6, 8],
+                    help="--workload precond: Chebyshev steps to compare with CG")
     ap.add_argument("--probe", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="with --probe: only the 134 MB copy used for counter calibration")
@@ -688,6 +749,8 @@ def main():
         return bench_huge(args)
     if args.workload == "fixed":
         return bench_fixed(args)
+    if args.workload == "precond":
+        return bench_precond(args)
     if args.workload == "serve":
         args.count = args.count or 400
         return bench_serve(args)

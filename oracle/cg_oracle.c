@@ -544,10 +544,10 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
 /* ------------------------------------------ Chebyshev-preconditioned CG -- */
 
 /* The preconditioner M^-1 = p_s(A): s steps of Chebyshev semi-iteration on
- * A y = r from y = 0, over the interval [lmin, lmax] that holds the spectrum
- * of A (closed form for this operator: 4 -+ 2cos(pi/(nx+1)) -+ 2cos(pi/(ny+1))).
- * With theta = (lmax + lmin)/2, delta = (lmax - lmin)/2, sigma = theta/delta,
- * rho_0 = 1/sigma:
+ * A y = r from y = 0, over the interval [lo, hi] = [lmax / (2 s^2), lmax],
+ * where lmax = 4 + 2cos(pi/(nx+1)) + 2cos(pi/(ny+1)) is the largest eigenvalue
+ * of A (closed form for this operator).  With theta = (hi + lo)/2,
+ * delta = (hi - lo)/2, sigma = theta/delta, rho_0 = 1/sigma:
  *   d_0 = r * (1/theta);  y_1 = d_0;
  *   for k = 1 .. s-1:  r_k = r_(k-1) - A d_(k-1);
  *                      rho_k = 1 / (2 sigma - rho_(k-1));
@@ -555,16 +555,22 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
  *                      y_(k+1) = y_k + d_k;
  *   z = y_s.
  * (the Chebyshev iteration of Saad, Iterative Methods for Sparse Linear
- * Systems, Section 12.3; the residual polynomial is bounded by
- * 1/T_s(sigma) < 1 on [lmin, lmax], so p_s is positive there and M is SPD.)
+ * Systems, Section 12.3.)  Its residual polynomial R(l) = T_s((theta - l)/delta)
+ * / T_s(sigma) lies in [-1/T_s(sigma), 1/T_s(sigma)] on [lo, hi] and in
+ * [1/T_s(sigma), 1) on (0, lo), so p_s(l) = (1 - R(l))/l > 0 on the whole
+ * spectrum and M is SPD.  The upper end sits at lmax itself and not below it:
+ * for even s, R(lmax) would otherwise be near 1 and p_s(A) A would nearly
+ * vanish on the highest modes.  The lower end lmax/(2 s^2) leaves the lowest
+ * modes to the outer CG, which handles a few small outlying eigenvalues well,
+ * and makes the bulk of the spectrum of p_s(A) A lie within 1 -+ 1/T_s(sigma).
  * c0 = 1/theta, c1[k-1] = rho_k rho_(k-1), c2[k-1] = 2 rho_k / delta. */
 int oracle_cheb_coeffs(int32_t nx, int32_t ny, int32_t s, double* c0, double* c1,
                        double* c2) {
   if (nx < 1 || ny < 1 || s < 1 || !c0 || (s > 1 && (!c1 || !c2))) return OR_E_INVALID;
   const double pi = 3.14159265358979323846;
-  const double a = 2.0 * cos(pi / (double)(nx + 1)) + 2.0 * cos(pi / (double)(ny + 1));
-  const double lmax = 4.0 + a, lmin = 4.0 - a;
-  const double theta = (lmax + lmin) / 2.0, delta = (lmax - lmin) / 2.0;
+  const double hi = 4.0 + 2.0 * cos(pi / (double)(nx + 1)) + 2.0 * cos(pi / (double)(ny + 1));
+  const double lo = hi / (2.0 * (double)s * (double)s);
+  const double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0;
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   *c0 = 1.0 / theta;

@@ -466,9 +466,10 @@ void Ctx::forget_graphs(const void* mem) {
 // the host's cos()).
 void cheb_coeffs(int nx, int ny, int s, double* out) {
   const double pi = 3.14159265358979323846;
-  const double a = 2.0 * std::cos(pi / (double)(nx + 1)) + 2.0 * std::cos(pi / (double)(ny + 1));
-  const double lmax = 4.0 + a, lmin = 4.0 - a;
-  const double theta = (lmax + lmin) / 2.0, delta = (lmax - lmin) / 2.0;
+  const double hi = 4.0 + 2.0 * std::cos(pi / (double)(nx + 1)) +
+                    2.0 * std::cos(pi / (double)(ny + 1));
+  const double lo = hi / (2.0 * (double)s * (double)s);
+  const double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0;
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   out[0] = 1.0 / theta;

@@ -83,8 +83,10 @@ def test_natural_stop(ctx, nx, ny, s):
 
 
 def test_one_step_is_plain_cg_on_the_gpu(ctx):
-    """s = 1 scales r by exactly 1/4: the preconditioned solve reproduces the
-    unpreconditioned one bit for bit (both on the tile passes here)."""
+    """s = 1 scales r by the scalar 1/theta, under which CG is invariant: the
+    preconditioned solve tracks the unpreconditioned one up to rounding (both
+    on the tile passes here; bitwise parity with the oracle is checked
+    above)."""
     nx, ny = 513, 257
     b = np.random.default_rng(11).uniform(-1, 1, (ny, nx))
     assert ctx.cg_plan(nx, ny).path == 0
@@ -93,8 +95,8 @@ def test_one_step_is_plain_cg_on_the_gpu(ctx):
         xc = np.zeros_like(b)
         rcp, rp = ctx.solve(b, xp, nx, ny, tol=tol, maxit=maxit, precond=1)
         rcc, rc_ = ctx.solve(b, xc, nx, ny, tol=tol, maxit=maxit)
-        assert rcp == rcc and rp.iterations == rc_.iterations
-        np.testing.assert_array_equal(xp, xc)
+        assert rcp == rcc and abs(rp.iterations - rc_.iterations) <= 1
+        assert np.linalg.norm(xp - xc) <= 1e-10 * np.linalg.norm(xc)
 
 
 def test_fewer_iterations(ctx):
@@ -109,7 +111,7 @@ def test_fewer_iterations(ctx):
         assert rc == cg.CG_OK and r.rel_res_true <= 1.2e-8
         its[s] = r.iterations
     say("iterations: CG", r0.iterations, "PCG", its)
-    assert its[8] <= 0.4 * r0.iterations and its[4] <= 0.6 * r0.iterations
+    assert its[8] <= 0.2 * r0.iterations and its[4] <= 0.35 * r0.iterations
 
 
 def test_edge_cases(ctx):

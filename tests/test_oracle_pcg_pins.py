@@ -3,9 +3,9 @@ cg_oracle.c) against closed forms, a dense textbook implementation and the
 already pinned CG oracle.
 
 The preconditioner is the s-step Chebyshev semi-iteration on A y = r from
-y = 0 over A's exact spectrum interval; its residual polynomial is the scaled
-Chebyshev polynomial T_s((theta - lambda)/delta) / T_s(theta/delta), so on an
-eigenvector of A it multiplies by p_s(lambda) = (1 - that) / lambda.
+y = 0 over [lambda_max / (2 s^2), lambda_max]; its residual polynomial is the
+scaled Chebyshev polynomial T_s((theta - lambda)/delta) / T_s(theta/delta), so
+on an eigenvector of A it multiplies by p_s(lambda) = (1 - that) / lambda.
 """
 import math
 
@@ -32,6 +32,12 @@ def spectrum(nx, ny):
     return 4 - c, 4 + c
 
 
+def interval(nx, ny, s):
+    """The Chebyshev interval: the top of the spectrum and 1/(2 s^2) of it."""
+    hi = spectrum(nx, ny)[1]
+    return hi / (2 * s * s), hi
+
+
 def cheb_T(s, x):
     """T_s(x) for any real x."""
     if abs(x) <= 1:
@@ -40,7 +46,7 @@ def cheb_T(s, x):
 
 
 def p_closed(s, lam, nx, ny):
-    lo, hi = spectrum(nx, ny)
+    lo, hi = interval(nx, ny, s)
     theta, delta = (hi + lo) / 2, (hi - lo) / 2
     return (1 - cheb_T(s, (theta - lam) / delta) / cheb_T(s, theta / delta)) / lam
 
@@ -61,9 +67,8 @@ def test_eigenvectors_scale_by_the_polynomial(mode, s):
             lam = 4 - 2 * math.cos(a * math.pi / (nx + 1)) - 2 * math.cos(b * math.pi / (ny + 1))
             z = oracle.cheb_apply(phi, nx, ny, s, mode)
             want = p_closed(s, lam, nx, ny) * phi
-            # p_s(lambda) is tiny where the residual polynomial nears 1 (e.g.
-            # at lambda_max for even s): the cancellation there is measured
-            # against ||phi||
+            # p_s(lambda) is small where the residual polynomial nears 1 (the
+            # lowest modes): the cancellation there is measured against ||phi||
             err = np.linalg.norm(z - want)
             assert err <= 1e-10 * np.linalg.norm(want) + 1e-12 * np.linalg.norm(phi), \
                 (nx, ny, a, b)
@@ -72,7 +77,7 @@ def test_eigenvectors_scale_by_the_polynomial(mode, s):
 def test_coefficients():
     for nx, ny in ((1, 1), (10, 3), (4096, 4096)):
         c0, c1, c2 = oracle.cheb_coeffs(nx, ny, 6)
-        lo, hi = spectrum(nx, ny)
+        lo, hi = interval(nx, ny, 6)
         assert abs(c0 - 1 / ((lo + hi) / 2)) <= 1e-15
         assert len(c1) == len(c2) == 5
         # rho_k of the three-term recurrence: rho_k = 1/(2 sigma - rho_(k-1))
@@ -83,6 +88,32 @@ def test_coefficients():
             assert c1[k] == pytest.approx(rn * rho, rel=1e-14)
             assert c2[k] == pytest.approx(2 * rn / ((hi - lo) / 2), rel=1e-14)
             rho = rn
+
+
+def test_residual_polynomial_bounds():
+    """On [lo, hi] the residual polynomial is at most 1/T_s(sigma) in size; below
+    lo it lies in [1/T_s(sigma), 1), so p_s > 0 over the whole spectrum, at
+    the top (where an interval ending below lambda_max would fail for even s)
+    and at the bottom."""
+    nx, ny = 300, 200
+    lmin, lmax = spectrum(nx, ny)
+    for s in (1, 2, 3, 4, 6, 8):
+        lo, hi = interval(nx, ny, s)
+        theta, delta = (hi + lo) / 2, (hi - lo) / 2
+        bound = 1 / cheb_T(s, theta / delta)
+        for lam in np.linspace(lmin, lmax, 2001):
+            p = p_closed(s, lam, nx, ny)
+            R = 1 - lam * p
+            assert p > 0
+            if lam >= lo:
+                assert abs(R) <= bound * (1 + 1e-12)
+            else:
+                assert bound * (1 - 1e-12) <= R < 1
+        # the operator's largest mode keeps a gain of at least 1 - 1/T_s(sigma)
+        phi = mode_vec(nx, ny, nx, ny)
+        lam = 4 + 2 * math.cos(math.pi / (nx + 1)) + 2 * math.cos(math.pi / (ny + 1))
+        gain = (oracle.cheb_apply(phi, nx, ny, s) * phi).sum() / (phi * phi).sum() * lam
+        assert gain >= 1 - bound - 1e-12, s
 
 
 @pytest.mark.parametrize("s", [1, 2, 4, 7])
@@ -138,17 +169,19 @@ def test_iterates_match_a_dense_textbook_pcg(s):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_one_step_is_plain_cg(mode):
-    """s = 1: M = I/4 exactly, and scaling by a power of two commutes with
-    rounding, so every iterate is CG's to the last bit."""
+    """s = 1: M = c0 I with c0 = 1/theta = 4/(3 lambda_max); CG is invariant
+    under a scalar preconditioner (z = c0 r scales rho and p by c0 and alpha
+    by 1/c0), so the iterates are CG's up to rounding."""
     nx, ny = 50, 37
     b = np.random.default_rng(3).uniform(-1, 1, (ny, nx))
     o = GPU_LIKE if mode == MODE_CANONICAL else None
-    assert oracle.cheb_coeffs(nx, ny, 1)[0] == 0.25
+    hi = spectrum(nx, ny)[1]
+    assert oracle.cheb_coeffs(nx, ny, 1)[0] == pytest.approx(4 / (3 * hi), rel=1e-15)
     for tol, maxit in ((0.0, 17), (1e-9, 5000)):
         xp, rp = oracle.pcg(b, nx, ny, 1, tol=tol, maxit=maxit, mode=mode, order=o)
         xc, rc = oracle.cg(b, nx, ny, tol=tol, maxit=maxit, mode=mode, order=o)
-        assert rp.iterations == rc.iterations and rp.status == rc.status
-        np.testing.assert_array_equal(xp, xc)
+        assert abs(rp.iterations - rc.iterations) <= 1 and rp.status == rc.status
+        assert np.linalg.norm(xp - xc) <= 1e-10 * np.linalg.norm(xc)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -166,8 +199,9 @@ def test_solution_against_cholesky(mode, s):
 
 
 def test_fewer_iterations_than_cg():
-    """kappa(p_s(A) A) is about kappa(A) / s^2: at 128^2 eight steps cut the
-    iterations to well under half (a quarter measured)."""
+    """The bulk of the spectrum of p_s(A) A is squeezed to 1 -+ 1/T_s(sigma),
+    and p_s(0) grows like s^2: at 128^2 the iterations fall roughly as 1/s
+    (0.53, 0.28 and 0.16 of CG's measured for s = 2, 4, 8)."""
     n = 128
     b = np.random.default_rng(5).uniform(-1, 1, (n, n))
     _, rc = oracle.cg(b, n, n, tol=1e-8, maxit=20000)
@@ -177,8 +211,8 @@ def test_fewer_iterations_than_cg():
         assert r.status == 0 and r.rel_res_true <= 1.2e-8
         its[s] = r.iterations
     assert its[2] <= 0.6 * rc.iterations
-    assert its[4] <= 0.6 * rc.iterations
-    assert its[8] <= 0.4 * rc.iterations and its[8] < its[4]
+    assert its[4] <= 0.35 * rc.iterations
+    assert its[8] <= 0.2 * rc.iterations
 
 
 def test_edge_cases_and_rejections():
