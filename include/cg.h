@@ -99,11 +99,12 @@ typedef struct {
   cg_precision precision;  /* FP64, FP32 inner CG inside FP64 refinement, or fixed    */
   double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
   int32_t precond;         /* 0: none; s = 1..8: classic FP64 CG preconditioned by
-                              M^-1 = p_s(A), s steps of Chebyshev semi-iteration over
-                              the operator's exact spectrum interval
-                              [4 -+ 2cos(pi/(nx+1)) -+ 2cos(pi/(ny+1))] (the M^-1 of
-                              the pipelined-CG literature Section I builds on);
-                              cg_solve only (batches and serving reject it)        */
+                              M^-1 = p_s(A), s steps of Chebyshev semi-iteration on
+                              A y = r from y = 0 over [lmax / (2 s^2), lmax], lmax =
+                              4 + 2cos(pi/(nx+1)) + 2cos(pi/(ny+1)) the largest
+                              eigenvalue of A (the M^-1 of the pipelined-CG
+                              literature Section I builds on); cg_solve only
+                              (batches and serving reject it)                      */
   int32_t pad_;
 } cg_problem;
 
@@ -127,7 +128,10 @@ typedef struct {
  * segment order (path 2, alone and in a batch): thread t of seg_waves*64
  * owns column t mod seg_cols and seg_rows rows of segment t div seg_cols
  * (threads of columns >= nx own nothing); fma in row order; xor butterfly;
- * waves in order.  Path 3 (fixed point) is exact integer arithmetic: no order
+ * waves in order.  Preconditioned CG (precond > 0) sums (r, z) in the tile
+ * order of tiles 128 columns wide (2 per lane) and cheb_rows rows tall with
+ * one wavefront each, through threads2 strided threads; its other sums follow
+ * the tile fields.  Path 3 (fixed point) is exact integer arithmetic: no order
  * to describe.  The tile fields always describe the
  * tile geometry of the shape (cg_dot and cg_apply use it on every path). */
 typedef struct {
@@ -141,6 +145,10 @@ typedef struct {
   int32_t seg_rows;         /* path 2: rows per thread; else 0                       */
   int32_t seg_waves;        /* path 2: wavefronts of the work-group; else 0          */
   int32_t seg_cols;         /* path 2: threads per row of segments (nx + 1); else 0  */
+  int32_t cheb_rows;        /* precond > 0: rows of a Chebyshev tile; else 0         */
+  int32_t cheb_tiles;       /* precond > 0: Chebyshev tiles (partials of (r,z))      */
+  int32_t cheb_grid;        /* precond > 0: work-groups of the Chebyshev pass        */
+  int32_t pad_;
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 

@@ -631,20 +631,24 @@ int oracle_cheb_apply(int32_t nx, int32_t ny, int32_t mode, int32_t s, const dou
  *   repeat: stop test on gamma (as for CG); z = M^-1 r; rho = (r,z)
  *           (breakdown unless 0 < rho < inf); p = z (first) or
  *           z + (rho/rho_old) p; s = A p; pi = (p,s); alpha = rho/pi;
- *           x += alpha p; r -= alpha s; gamma = (r,r); rho_old = rho */
-int oracle_pcg(int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny, int32_t sdeg,
-               const double* b, const double* x0, double* x, double tol, int32_t maxit,
-               oracle_result* res) {
+ *           x += alpha p; r -= alpha s; gamma = (r,r); rho_old = rho
+ * Canonical mode: rho follows ord_rho (NULL: ord), every other dot ord. */
+int oracle_pcg(int32_t mode, const oracle_order* ord, const oracle_order* ord_rho, int32_t nx,
+               int32_t ny, int32_t sdeg, const double* b, const double* x0, double* x,
+               double tol, int32_t maxit, oracle_result* res) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
       sdeg < 1 || sdeg > 64)
     return OR_E_INVALID;
-  if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
+  if (!ord_rho) ord_rho = ord;
+  if (mode == MODE_CANONICAL && (!order_valid(ord, nx, ny) || !order_valid(ord_rho, nx, ny)))
+    return OR_E_INVALID;
   double c0, c1[64], c2[64];
   oracle_cheb_coeffs(nx, ny, sdeg, &c0, c1, c2);
   csr_t A;
   int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
   if (rc) return rc;
   ctx_t c = {nx, ny, mode, ord};
+  ctx_t c_rho = {nx, ny, mode, ord_rho};
   memset(res, 0, sizeof(*res));
   const int64_t n = A.n;
   double* r = (double*)malloc((size_t)n * sizeof(double));
@@ -670,7 +674,7 @@ int oracle_pcg(int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny, in
     st = stop_rule(gamma, thr, k, maxit, tol);
     if (st != -100) break;
     if ((rc = cheb_apply(&A, mode, sdeg, &c0, c1, c2, r, z))) { st = rc; break; }
-    const double rho = dot(&c, r, z);
+    const double rho = dot(&c_rho, r, z);
     if (!(rho > 0.0) || !isfinite(rho)) { st = OR_BREAKDOWN; break; }
     if (k == 0) memcpy(p, z, (size_t)n * sizeof(double));
     else        xpay(&c, n, z, rho / rho_old, p);

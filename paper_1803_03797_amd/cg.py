@@ -49,7 +49,8 @@ class cg_plan_info(C.Structure):
                 ("waves", C.c_int32), ("rows", C.c_int32), ("threads2", C.c_int32),
                 ("tiles", C.c_int32), ("grid", C.c_int32), ("pitch", C.c_int32),
                 ("seg_rows", C.c_int32), ("seg_waves", C.c_int32), ("seg_cols", C.c_int32),
-                ("footprint", C.c_size_t)]
+                ("cheb_rows", C.c_int32), ("cheb_tiles", C.c_int32), ("cheb_grid", C.c_int32),
+                ("pad_", C.c_int32), ("footprint", C.c_size_t)]
 
 
 class cg_kstat(C.Structure):

@@ -38,9 +38,10 @@ enum : int32_t {
 enum : int32_t {
   F_BB_PENDING = 1,      // the next prologue takes (b,b) from partial slot 1
   F_PRECOND = 2,         // classic CG preconditioned by the Chebyshev pass:
-                         // K_CG1 takes gamma = (r,r) and rho = (r,z) from the
-                         // K_CHEB partials, keeps rho in State::delta, and
-                         // K_CG2 forms alpha = rho / (p, A p)
+                         // K_CHEB makes the stop test on (r,r) of the pass
+                         // before it, K_CG1 takes rho = (r,z) from the K_CHEB
+                         // partials and keeps it in State::delta, and K_CG2
+                         // forms alpha = rho / (p, A p)
 };
 
 // Scalar state of one solve.  Kept in device memory, double-buffered by pass
@@ -94,7 +95,8 @@ enum : int32_t {
   K_PCGX,         // K_PCG of an even iteration: also applies both x updates
   K_CG2X,         // K_CG2 of an even iteration: also applies both x updates
   K_CG2FX,        // K_CG2F of an even inner iteration: both d updates
-  K_CHEB,         // z = p_s(A) r (Chebyshev preconditioner); slots (r,r), (r,z)
+  K_CHEB,         // z = p_s(A) r (Chebyshev preconditioner); slot (r,z) in its own
+                  // tiles: 128 columns x cheb_rows rows, one wavefront per tile
   K_NKINDS
 };
 
@@ -133,6 +135,8 @@ struct PassArgs {
   double* y;
   int32_t rev;             // walk the tiles in reverse order (alternate passes)
   int32_t cheb_s;          // K_CHEB: Chebyshev steps s (1..kChebMaxSteps)
+  int32_t cheb_rows;       // K_CHEB: rows of one Chebyshev item / partial tile
+  int32_t cheb_tiles;      // K_CG1 preconditioned: partials of the Chebyshev pass
   const double* cheb;      // K_CHEB: c0, then c1[s-1], then c2[s-1]
 };
 
@@ -236,6 +240,10 @@ hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, int
 // `rounds` 32 x 32 -> 64-bit multiply-adds; writes grid * 256 words to sink.
 hipError_t launch_mul_probe(uint64_t* sink, int grid, int rounds, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
+// Work-groups of the Chebyshev pass with s steps that fit one CU; the pass
+// runs 512-thread work-groups, grid a multiple of 8.
+int cheb_max_blocks_per_cu(int s);
+constexpr int kChebGroupCols = 896;  // columns of one Chebyshev item (7 tiles)
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the
 // device so that a captured chunk of launches can be replayed.

@@ -303,9 +303,11 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     sc.be = be;
     return true;
   } else if constexpr (KIND == K_CHEB) {
-    // z = M^-1 r runs while the solve does; it takes (b,b) after the first
-    // residual, the stop test stays with the next pass (on its (r,r) slot)
+    // Preconditioned CG: the stop test on gamma = (r,r) of the current
+    // residual (from the initial residual pass or classic pass 2, which also
+    // brings (b,b) the first time), before z = M^-1 r is formed.
     if (s.status != ST_RUNNING) return false;
+    const double gamma = sum[0];
     if (s.flags & F_BB_PENDING) {
       s.bb = sum[1];
       s.thr = (s.tol * s.tol) * s.bb;
@@ -315,25 +317,26 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
         return false;
       }
     }
-    return true;
+    const int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
+    s.gamma = gamma;
+    s.status = st;
+    return st == ST_RUNNING;
   } else if constexpr (KIND == K_CG1) {
     // Algorithm 1: beta = (r,r)_new / (r,r)_old, then p = r + beta p.
-    // Preconditioned: slots (r,r), (r,z) of the Chebyshev pass; beta =
-    // rho_new / rho_old with rho = (r,z) kept in delta, then p = z + beta p.
+    // Preconditioned: the one slot is rho = (r,z) from the Chebyshev pass
+    // (which already made the stop test); beta = rho_new / rho_old with rho
+    // kept in delta, then p = z + beta p.
     if (s.status != ST_RUNNING) return false;
     const double gamma = sum[0];
     if (s.flags & F_PRECOND) {
-      int st = stop_code(gamma, s.thr, s.k, s.maxit, s.tol);
-      const double rho = sum[1];
+      const double rho = sum[0];
       double be = 0.0;
-      if (st == ST_RUNNING) {
-        if (!(rho > 0.0) || !isfinite(rho)) st = ST_BREAKDOWN;
-        else if (s.k == 0) sc.first = 1;
-        else be = rho / s.delta;
+      if (!(rho > 0.0) || !isfinite(rho)) {
+        s.status = ST_BREAKDOWN;
+        return false;
       }
-      s.gamma = gamma;
-      s.status = st;
-      if (st != ST_RUNNING) return false;
+      if (s.k == 0) sc.first = 1;
+      else be = rho / s.delta;
       s.delta = rho;
       s.beta = be;
       sc.be = be;
@@ -466,7 +469,7 @@ constexpr int ndots_out() {  // partial slots the body produces
 template <int KIND>
 constexpr bool defers_x() {
   return KIND == K_PCG || KIND == K_PCGX || KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X ||
-         KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX;
+         KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_CHEB;
 }
 
 template <int KIND>
@@ -486,7 +489,7 @@ __device__ __forceinline__ bool transition_x(State& s, const double* sum, Sc& sc
   flush = false;
   if constexpr (defers_x<KIND>()) {
     const int k = inner_kind<KIND>() ? s.kin : s.k;
-    if (run && KIND != K_CG1 && KIND != K_CG1F && !(k & 1)) {
+    if (run && KIND != K_CG1 && KIND != K_CG1F && KIND != K_CHEB && !(k & 1)) {
       sc.xu = 1;
       sc.alp = alpha_before;
     }
@@ -1022,7 +1025,7 @@ __device__ __forceinline__ void body_flush_f32(const PassArgs& a, int t, const f
 template <int KIND>
 __device__ __forceinline__ const double* flush_dir(const PassArgs& a) {
   if constexpr (KIND == K_PCG || KIND == K_PCGX) return a.p;
-  else if constexpr (KIND == K_CG1) return a.pc_in;
+  else if constexpr (KIND == K_CG1 || KIND == K_CHEB) return a.pc_in;
   else return a.pc_prev;
 }
 
@@ -1151,11 +1154,14 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
     State s = load_state_uniform(a.st_in);
     double sum[2] = {0.0, 0.0};
     if constexpr (DI > 0) {
-      const int din =
-          (KIND == K_CG1) ? ((s.flags & (F_BB_PENDING | F_PRECOND)) ? 2 : 1) : DI;
+      // classic pass 1 takes (b,b) too after the initial residual; with the
+      // preconditioner its one slot is (r,z) in the Chebyshev pass's tiles
+      const bool pc = KIND == K_CG1 && (s.flags & F_PRECOND);
+      const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) && !pc ? 2 : 1) : DI;
+      const int tin = pc ? a.cheb_tiles : a.g.tiles;
       if (s.status == ST_RUNNING) {
-        if (din == 2) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, lds);
-        else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, lds);
+        if (din == 2) cross_tile_sum<2>(a.part_in, tin, sum, lds);
+        else cross_tile_sum<1>(a.part_in, tin, sum, lds);
       }
       sum[0] = uniform(sum[0]);
       sum[1] = uniform(sum[1]);
@@ -1206,130 +1212,232 @@ __global__ __launch_bounds__(kGroup) void k_final(PassArgs a) {
 //
 // z = p_s(A) r: s steps of Chebyshev semi-iteration on A y = r from y = 0
 // (d_0 = c0 r, y_1 = d_0; r_k = r_(k-1) - A d_(k-1), d_k = fma(c1_k, d_(k-1),
-// c2_k r_k), y_(k+1) = y_k + d_k), the coefficients from the operator's exact
-// spectrum interval (computed on the host).  Each work-group takes whole
-// tiles of the pass geometry; a tile is done strip by strip (the strip of
-// wavefront w is rows [w rows, (w+1) rows) of the tile), in blocks of at most
-// kChebRows rows: the block and a halo of s - 1 cells on every side are
-// loaded into LDS, the s - 1 stencil steps shrink the valid region by one
-// cell each, and the block's z is written.  Cells outside the grid stay zero.
-// The stencil, the fma structure and the order of the y sums are those of the
-// oracle's canonical mode.  The partials (r,r) and (r,z) of a tile follow the
-// tile order of every pass: the strip's wavefront accumulates them down its
-// rows per column (fma), the lane value is the sum of its columns, then the
-// butterfly and the wavefronts in order.
-constexpr int kChebRows = 32;
-constexpr int kChebHalo = kChebMaxSteps - 1;
-constexpr int kChebW = kWave * 2 + 2 * kChebHalo;      // region width (FP64 tiles)
-constexpr int kChebH = kChebRows + 2 * kChebHalo;      // region height
-constexpr int kChebLds = 2 * kChebW * kChebH + kWave * 2 * kChebRows;
+// c2_k r_k), y_(k+1) = y_k + d_k), the coefficients from the spectrum
+// interval of the operator (computed on the host).  The stencil, the fma
+// structure and the order of the y sums are those of the oracle's canonical
+// mode, so z is bitwise the oracle's whatever the blocking.
+//
+// Temporal blocking in registers.  A wavefront owns 128 consecutive columns
+// (lane l: columns cl = cw - 8 + 2l and cl + 1) and marches down the rows of
+// its item.  Stage k of step J computes row J - k of r_k, d_k and adds d_k
+// into y: stage 0 scales the row just loaded, stage k >= 1 applies the
+// stencil to d_(k-1) on rows J-k-1 .. J-k+1, the last of which stage k - 1
+// produced in the same step.  Each level keeps only its two newest rows of
+// d and its newest row of r, y keeps the s - 1 rows still accumulating, and
+// row J - (s - 1) of z is complete after step J.  West and east neighbours
+// come from the adjacent lanes (DPP); values near the wavefront's outer
+// columns lose one valid column per stage, so of the 128 columns the middle
+// 112 (the 8-column halo >= s - 1 on each side) are written.  Cells outside
+// the grid are held at zero through every stage (`MASK`, only for the
+// wavefronts and items that touch the grid edge).
+//
+// Items and partials.  A work-group of 8 wavefronts covers 8 x 112 = 896
+// columns, exactly 7 tiles of 128 columns, over the rows [ty H, (ty+1) H) of
+// one item (H = cheb_rows).  (r, z) is reduced in the tile order of a tile
+// 128 columns wide and H rows tall holding one wavefront: each lane
+// accumulates its two columns with fma down the rows, the wavefronts park
+// the column sums in LDS, and wavefront m folds the column pair of each lane
+// of tile m, butterflies, and stores partial[ty ntx + tx].
+constexpr int kChebHaloCols = 8;                                       // >= s - 1
+constexpr int kChebOut = 2 * kWave - 2 * kChebHaloCols;                // 112
+constexpr int kChebWaves = 8;
+constexpr int kChebThreads = kChebWaves * kWave;
+constexpr int kChebGroupTiles = kChebWaves * kChebOut / (2 * kWave);   // 7
+static_assert(kChebGroupTiles * 2 * kWave == kChebWaves * kChebOut, "whole tiles per group");
+static_assert(kChebHaloCols >= kChebMaxSteps - 1, "halo too narrow for the steps");
+static_assert(kChebGroupCols == kChebWaves * kChebOut, "item width known to the host");
 
-__global__ __launch_bounds__(kGroup) void k_cheb(PassArgs a) {
-  constexpr int CPL = 2, TW = kWave * CPL;
-  __shared__ double lds[kChebLds + 64];
-  double* D = lds;                       // d_k over the region
-  double* Rk = lds + kChebW * kChebH;    // r_k over the region
-  double* Y = lds + 2 * kChebW * kChebH; // y over the block
-  double* red = lds + kChebLds;          // tile_partial / cross-tile scratch
+struct D2 {
+  double v[2];
+};
+
+// One wavefront of an item: output columns [cw, cw + 112), rows [y0, y1).
+// acc0/acc1 receive the (r, z) column sums of the lane's two columns.
+template <int S, bool MASK>
+__device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, int y1,
+                                           double& acc0, double& acc1) {
+  constexpr int H = S - 1;             // stencil steps = halo rows
+  constexpr int L = S > 1 ? S - 1 : 1; // array extent for the per-level state
+  constexpr int PD = S <= 3 ? 4 : 2;   // rows loaded ahead
+  const Geo& g = a.g;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int cl = cw - kChebHaloCols + 2 * lane;
+  const double c0 = a.cheb[0];
+  double c1[L], c2[L];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    c1[k] = a.cheb[1 + k];
+    c2[k] = a.cheb[S + k];
+  }
+  // columns: the load address is valid for 0 <= cl < pitch (pitch is a
+  // multiple of 128 and cl is even, so the pair stays in the row)
+  bool v0 = true, v1 = true;
+  int lc = cl;
+  if constexpr (MASK) {
+    v0 = cl >= 0 && cl < g.nx;
+    v1 = cl >= 0 && cl + 1 < g.nx;
+    lc = (cl >= 0 && cl < g.pitch) ? cl : 0;
+  }
+  const double* R = a.r + lc;
+  auto load = [&](int J) {
+    const int jl = min(max(J, 0), g.ny - 1);
+    const double2 t = *reinterpret_cast<const double2*>(R + (size_t)jl * g.pitch);
+    D2 o;
+    o.v[0] = t.x;
+    o.v[1] = t.y;
+    if constexpr (MASK) {
+      const bool rv = J >= 0 && J < g.ny;
+      o.v[0] = (rv && v0) ? o.v[0] : 0.0;
+      o.v[1] = (rv && v1) ? o.v[1] : 0.0;
+    }
+    return o;
+  };
+  // state at the start of step J (levels k < H):
+  //   P1[k], P2[k] = d_k on rows J-k-2, J-k-1;  RK[k] = r_k on row J-k-1
+  //   Y[i] = y on row J-H+i (i < H);  R0[i] = r on row J-H+i (i < H)
+  D2 P1[L], P2[L], RK[L], Y[L], R0[L], LD[PD];
+#pragma unroll
+  for (int k = 0; k < L; ++k)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) P1[k].v[e] = P2[k].v[e] = RK[k].v[e] = Y[k].v[e] = R0[k].v[e] = 0.0;
+  const int Jb = y0 - H, Je = y1 + H;
+#pragma unroll
+  for (int i = 0; i < PD; ++i) LD[i] = load(Jb + i);
+  double a0 = 0.0, a1 = 0.0;
+  double* Z = a.z + cl;
+  const bool outl = lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2 &&
+                    (!MASK || cl < g.nx);
+  for (int J = Jb; J < Je; ++J) {
+    const D2 rin = LD[0];
+#pragma unroll
+    for (int i = 0; i < PD - 1; ++i) LD[i] = LD[i + 1];
+    LD[PD - 1] = load(J + PD);
+    // stage 0: d_0 = c0 r, y = d_0 on row J (zero outside the grid already)
+    D2 dn, rn, ynew;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      dn.v[e] = rin.v[e] * c0;
+      ynew.v[e] = dn.v[e];
+    }
+    rn = rin;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      // stage k on row j = J - k, from d_(k-1) on rows j-1 (P1), j (P2), j+1 (dn)
+      const D2 C = P2[k - 1], Sv = P1[k - 1], Nv = dn;
+      const double w0 = dpp<kDppWaveShr1>(C.v[1], 0.0);
+      const double e1 = dpp<kDppWaveShl1>(C.v[0], 0.0);
+      const double W[2] = {w0, C.v[0]}, E[2] = {C.v[1], e1};
+      D2 dk, rk;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double t = st5(C.v[e], W[e], E[e], Sv.v[e], Nv.v[e]);
+        rk.v[e] = RK[k - 1].v[e] - t;
+        dk.v[e] = fma(c1[k - 1], C.v[e], c2[k - 1] * rk.v[e]);
+      }
+      if constexpr (MASK) {
+        const int j = J - k;
+        const bool rv = j >= 0 && j < g.ny;
+        dk.v[0] = (rv && v0) ? dk.v[0] : 0.0;
+        dk.v[1] = (rv && v1) ? dk.v[1] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) Y[H - k].v[e] = Y[H - k].v[e] + dk.v[e];
+      // level k-1 moves down one row
+      P1[k - 1] = P2[k - 1];
+      P2[k - 1] = dn;
+      RK[k - 1] = rn;
+      dn = dk;
+      rn = rk;
+    }
+    // row J - H of z is complete: Y[0] (or the new row when s = 1)
+    const D2 zrow = H > 0 ? Y[0] : ynew;
+    const D2 rrow = H > 0 ? R0[0] : rin;
+    if (J >= y0 + H) {
+      if (outl)
+        *reinterpret_cast<double2*>(Z + (size_t)(J - H) * g.pitch) =
+            make_double2(zrow.v[0], zrow.v[1]);
+      a0 = fma(rrow.v[0], zrow.v[0], a0);
+      a1 = fma(rrow.v[1], zrow.v[1], a1);
+    }
+    if constexpr (H > 0) {
+#pragma unroll
+      for (int i = 0; i < H - 1; ++i) {
+        Y[i] = Y[i + 1];
+        R0[i] = R0[i + 1];
+      }
+      Y[H - 1] = ynew;
+      R0[H - 1] = rin;
+    }
+  }
+  acc0 = a0;
+  acc1 = a1;
+}
+
+template <int S>
+__global__ __launch_bounds__(kChebThreads) void k_cheb(PassArgs a) {
+  __shared__ double colacc[kChebWaves * kChebOut];
+  __shared__ double red[4 * 2];
   {
     State s = load_state_uniform(a.st_in);
     double sum[2] = {0.0, 0.0};
-    if (s.status == ST_RUNNING && (s.flags & F_BB_PENDING)) {
-      cross_tile_sum<2>(a.part_in, a.g.tiles, sum, red);
-      sum[0] = uniform(sum[0]);
-      sum[1] = uniform(sum[1]);
+    if (s.status == ST_RUNNING) {
+      if (s.flags & F_BB_PENDING) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, red);
+      else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, red);
     }
+    sum[0] = uniform(sum[0]);
+    sum[1] = uniform(sum[1]);
     Sc sc;
-    const bool run = transition<K_CHEB>(s, sum, sc);
+    bool flush = false;
+    const bool run = transition_x<K_CHEB>(s, sum, sc, flush);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
+    if (flush) {
+      // the stop test stopped the solve after an odd iteration: apply that
+      // iteration's x update (pass tiles, 256 threads per tile)
+      if (threadIdx.x < kGroup) {
+        const int G = gridDim.x, b = blockIdx.x;
+        const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+        const int T = a.g.tiles;
+        const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
+        for (int t = t0 + slot; t < t1; t += nb) run_flush<K_CHEB, 2>(a, t, sc);
+      }
+      return;
+    }
     if (!run) return;
   }
   const Geo& g = a.g;
-  const int sdeg = a.cheb_s, h = sdeg - 1;
-  const double c0 = a.cheb[0];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  const int ngx = (g.ntx + kChebGroupTiles - 1) / kChebGroupTiles;
+  const int Hc = a.cheb_rows, nty = (g.ny + Hc - 1) / Hc;
+  const int I = ngx * nty;
   const int G = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
-  const int T = g.tiles;
-  const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
-  int par = 0;
-  for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
-    const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
-    const int ct = (t % g.ntx) * TW, ty = t / g.ntx;
-    double arr[CPL], arz[CPL];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) arr[k] = arz[k] = 0.0;
-    for (int w = 0; w < kWavesPerTile; ++w) {
-      const int s0 = ty * g.th + w * g.rows, s1 = min(s0 + g.rows, g.ny);
-      for (int y0 = s0; y0 < s1; y0 += kChebRows) {
-        const int sb = min(kChebRows, s1 - y0);
-        const int RW = TW + 2 * h, RH = sb + 2 * h;
-        __syncthreads();  // the previous block's Y has been read
-        for (int q = tid; q < RW * RH; q += kGroup) {
-          const int rr = q / RW, cc = q - rr * RW;
-          const int j = y0 - h + rr, i = ct - h + cc;
-          const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-          const double rv = in ? a.r[(size_t)j * g.pitch + i] : 0.0;
-          const double dv = rv * c0;
-          D[rr * kChebW + cc] = dv;
-          Rk[rr * kChebW + cc] = rv;
-          if (rr >= h && rr < h + sb && cc >= h && cc < h + TW) Y[(rr - h) * TW + cc - h] = dv;
-        }
-        __syncthreads();
-        for (int k = 1; k < sdeg; ++k) {
-          const double c1 = a.cheb[k], c2 = a.cheb[sdeg - 1 + k];
-          const int W2 = RW - 2 * k, H2 = RH - 2 * k;
-          // r_k = r_(k-1) - A d_(k-1) on the cells whose neighbours are valid
-          for (int q = tid; q < W2 * H2; q += kGroup) {
-            const int rr = k + q / W2, cc = k + q % W2;
-            const int j = y0 - h + rr, i = ct - h + cc;
-            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-              const int o = rr * kChebW + cc;
-              const double sv =
-                  (((4.0 * D[o] - D[o - 1]) - D[o + 1]) - D[o - kChebW]) - D[o + kChebW];
-              Rk[o] = Rk[o] - sv;
-            }
-          }
-          __syncthreads();
-          // d_k = fma(c1, d_(k-1), c2 r_k); y += d_k on the block
-          for (int q = tid; q < W2 * H2; q += kGroup) {
-            const int rr = k + q / W2, cc = k + q % W2;
-            const int j = y0 - h + rr, i = ct - h + cc;
-            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-              const int o = rr * kChebW + cc;
-              const double dv = fma(c1, D[o], c2 * Rk[o]);
-              D[o] = dv;
-              if (rr >= h && rr < h + sb && cc >= h && cc < h + TW) {
-                double& yv = Y[(rr - h) * TW + cc - h];
-                yv = yv + dv;
-              }
-            }
-          }
-          __syncthreads();
-        }
-        // z of the block; the strip's wavefront accumulates the partials
-        for (int q = tid; q < TW * sb; q += kGroup) {
-          const int rr = q / TW, cc = q - rr * TW;
-          const int j = y0 + rr, i = ct + cc;
-          if (i < g.nx) a.z[(size_t)j * g.pitch + i] = Y[q];
-        }
-        if (wave == w) {
-          for (int rr = 0; rr < sb; ++rr) {
-            const size_t off = (size_t)(y0 + rr) * g.pitch + ct + lane * CPL;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-              if (ct + lane * CPL + k < g.nx) {
-                const double rv = a.r[off + k], zv = Y[rr * TW + lane * CPL + k];
-                arr[k] = fma(rv, rv, arr[k]);
-                arz[k] = fma(rv, zv, arz[k]);
-              }
-            }
-          }
-        }
+  const int i0 = (int)(((int64_t)I * xcd) >> 3), i1 = (int)(((int64_t)I * (xcd + 1)) >> 3);
+  for (int it = i0 + slot; it < i1; it += nb) {
+    const int gx = it % ngx, ty = it / ngx;
+    const int cw = gx * (kChebGroupTiles * 2 * kWave) + wave * kChebOut;
+    const int y0 = ty * Hc, y1 = min(y0 + Hc, g.ny);
+    double acc0 = 0.0, acc1 = 0.0;
+    if (cw < g.nx) {
+      const bool inner = cw >= kChebHaloCols && cw + kChebOut + kChebHaloCols <= g.nx &&
+                         y0 >= S - 1 && y1 + (S - 1) <= g.ny;
+      if (inner) cheb_march<S, false>(a, cw, y0, y1, acc0, acc1);
+      else cheb_march<S, true>(a, cw, y0, y1, acc0, acc1);
+    }
+    if (lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2) {
+      double* c = colacc + wave * kChebOut + 2 * (lane - kChebHaloCols / 2);
+      c[0] = acc0;
+      c[1] = acc1;
+    }
+    __syncthreads();
+    if (wave < kChebGroupTiles) {
+      const int tx = gx * kChebGroupTiles + wave;
+      if (tx < g.ntx) {
+        const double* c = colacc + wave * 2 * kWave + 2 * lane;
+        const double v = wave_sum(c[0] + c[1]);
+        if (lane == 0) a.part_out[(size_t)ty * g.ntx + tx] = v;
       }
     }
-    double lv[2] = {fold<CPL>(arr), fold<CPL>(arz)};
-    tile_partial<2>(lv, a.part_out, T, t, red, par);
+    __syncthreads();
   }
 }
 
@@ -2244,9 +2352,19 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
       hipLaunchKernelGGL((k_pass<K_REF_UPDATE, 4>), dim3(grid), dim3(kGroup), 0, st, a);
       return hipGetLastError();
     case K_CHEB:
-      if (fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.z || !a.r)
+      if (fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.z || !a.r ||
+          a.cheb_rows < 1)
         return hipErrorInvalidValue;
-      hipLaunchKernelGGL(k_cheb, dim3(grid), dim3(kGroup), 0, st, a);
+      switch (a.cheb_s) {
+        case 1: hipLaunchKernelGGL(k_cheb<1>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_cheb<2>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_cheb<3>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 4: hipLaunchKernelGGL(k_cheb<4>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 5: hipLaunchKernelGGL(k_cheb<5>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 6: hipLaunchKernelGGL(k_cheb<6>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        case 7: hipLaunchKernelGGL(k_cheb<7>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_cheb<8>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
+      }
       return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
@@ -2294,6 +2412,27 @@ static int occ() {
       hipSuccess)
     return 1;
   return n > 0 ? n : 1;
+}
+
+template <int S>
+static int occ_cheb() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cheb<S>, kChebThreads, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+int cheb_max_blocks_per_cu(int s) {
+  switch (s) {
+    case 1: return occ_cheb<1>();
+    case 2: return occ_cheb<2>();
+    case 3: return occ_cheb<3>();
+    case 4: return occ_cheb<4>();
+    case 5: return occ_cheb<5>();
+    case 6: return occ_cheb<6>();
+    case 7: return occ_cheb<7>();
+    default: return occ_cheb<8>();
+  }
 }
 
 int pass_max_blocks_per_cu(int kind, int fp32g) {

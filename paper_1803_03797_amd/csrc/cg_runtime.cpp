@@ -186,7 +186,21 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   } else {
     n64 = pl.precond ? 6 : 5;  // b, x, r, p, p' (and z)
   }
-  pl.part = round_up((size_t)2 * T * 8, Arena::kAlign);
+  if (pl.precond) {
+    // Chebyshev items: groups of 7 tiles across, cheb_rows rows tall, about
+    // one item per resident work-group (long items amortise the s - 1 halo
+    // rows each item recomputes; at least 16 rows)
+    const int ngx = (pl.g.pitch + kChebGroupCols - 1) / kChebGroupCols;
+    const int slots = std::max(1, cheb_max_blocks_per_cu(pl.precond) * num_cu);
+    const int nty = std::max(1, slots / ngx);
+    int crows = (p->ny + nty - 1) / nty;
+    crows = std::max(crows, std::min(p->ny, 16));
+    const int ntyc = (p->ny + crows - 1) / crows;
+    pl.cheb_rows = crows;
+    pl.cheb_tiles = pl.g.ntx * ntyc;
+    pl.cheb_grid = (int)round_up((size_t)std::min(ngx * ntyc, slots), 8);
+  }
+  pl.part = round_up((size_t)2 * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
   pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
                  (pl.precond ? 256 : 0);
   return pl;
@@ -343,7 +357,7 @@ static hipError_t issue(Ctx& c, Work& w, int kind, F mod) {
   a.rev = w.m & 1;
   mod(a);
   w.m++;
-  return c.pass(kind, w.pl.fp32g, a, w.pl.grid, w.check);
+  return c.pass(kind, w.pl.fp32g, a, kind == K_CHEB ? w.pl.cheb_grid : w.pl.grid, w.check);
 }
 
 static hipError_t issue_iteration(Ctx& c, Work& w) {
@@ -373,10 +387,15 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
         a.z = w.z;
         a.cheb = w.cheb;
         a.cheb_s = w.pl.precond;
+        a.cheb_rows = w.pl.cheb_rows;
+        a.pc_in = w.pc[i & 1];  // direction of a pending x update, if the test stops
       });
     if (e == hipSuccess)
       e = issue(c, w, K_CG1, [&](PassArgs& a) {
-        if (w.pl.precond) a.r = w.z;
+        if (w.pl.precond) {
+          a.r = w.z;
+          a.cheb_tiles = w.pl.cheb_tiles;
+        }
         a.pc_in = w.pc[i & 1];
         a.pc_out = w.pc[(i + 1) & 1];
       });

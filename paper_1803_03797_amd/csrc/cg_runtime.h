@@ -22,6 +22,9 @@ struct Plan {
   int rr_threads = 0;
   bool fixed = false;  // fixed-point solve, one work-group (cg_fixed.hip)
   int precond = 0;     // Chebyshev preconditioner steps (classic FP64, tile passes)
+  int cheb_rows = 0;   // ... rows of a Chebyshev item / partial tile
+  int cheb_tiles = 0;  // ... partials of the Chebyshev pass
+  int cheb_grid = 8;   // ... work-groups of the Chebyshev pass
   int fx_threads = 0;
   bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};

@@ -39,9 +39,14 @@ def ctx(torch):
 
 
 def tile_order(ctx, nx, ny, s):
+    """The pass tiles' order, and the order of rho = (r,z): tiles of the
+    Chebyshev pass, 128 columns by cheb_rows rows with one wavefront each."""
     info = ctx.cg_plan(nx, ny, precond=s)
     assert info.path == 0 and info.cols_per_lane == 2
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    assert info.cheb_rows >= 1 and info.cheb_grid >= 8 and info.cheb_grid % 8 == 0
+    assert info.cheb_tiles == (info.pitch // 128) * -(-ny // info.cheb_rows)
+    return (oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2),
+            oracle.Order(2, info.lanes, 1, info.cheb_rows, info.threads2))
 
 
 def rel(a, b):
@@ -53,12 +58,13 @@ def rel(a, b):
 @pytest.mark.parametrize("s", STEPS)
 def test_lockstep_bitwise(ctx, nx, ny, s):
     b = np.random.default_rng(nx * 13 + ny + s).uniform(-1, 1, (ny, nx))
-    o = tile_order(ctx, nx, ny, s)
+    o, orho = tile_order(ctx, nx, ny, s)
     for m in (1, 2, 7):
         say("precond lockstep", nx, ny, "s", s, "maxit", m)
         x = np.zeros_like(b)
         rc, res = ctx.solve(b, x, nx, ny, tol=0.0, maxit=m, precond=s)
-        xo, ro = oracle.pcg(b, nx, ny, s, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o)
+        xo, ro = oracle.pcg(b, nx, ny, s, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o,
+                            order_rho=orho)
         assert rc == ro.status and res.iterations == ro.iterations
         np.testing.assert_array_equal(x, xo)
         assert res.rel_res_recursive == ro.rel_res_recursive
@@ -69,17 +75,47 @@ def test_lockstep_bitwise(ctx, nx, ny, s):
 @pytest.mark.parametrize("s", [2, 4, 8])
 def test_natural_stop(ctx, nx, ny, s):
     b = np.random.default_rng(3 * nx + ny).uniform(-1, 1, (ny, nx))
-    o = tile_order(ctx, nx, ny, s)
+    o, orho = tile_order(ctx, nx, ny, s)
     say("precond natural stop", nx, ny, "s", s)
     x = np.zeros_like(b)
     rc, res = ctx.solve(b, x, nx, ny, tol=1e-8, maxit=20000, precond=s)
-    xk, rk = oracle.pcg(b, nx, ny, s, tol=1e-8, maxit=20000, mode=MODE_CANONICAL, order=o)
+    xk, rk = oracle.pcg(b, nx, ny, s, tol=1e-8, maxit=20000, mode=MODE_CANONICAL, order=o,
+                            order_rho=orho)
     xs, rs = oracle.pcg(b, nx, ny, s, tol=1e-8, maxit=20000, mode=MODE_SEQUENTIAL)
     assert rc == cg.CG_OK and res.iterations == rk.iterations
     np.testing.assert_array_equal(x, xk)
     assert abs(res.iterations - rs.iterations) <= 2
     assert rel(x, xs) <= 1e-10
     assert res.rel_res_true <= 1.2e-8
+
+
+@pytest.mark.parametrize("s", [2, 8])
+def test_full_size_eigenvector(ctx, torch, s):
+    """At 4096 x 4096, in the configuration the time-to-solution bench runs: a
+    single eigenvector b = phi_ab of A is one of p_s(A) too, so preconditioned
+    CG stops after one iteration with x = b / lambda_ab.  (The rounding of
+    phi in the other modes comes back amplified by up to kappa(p_s(A) A),
+    about 1e6 for the lowest mode at s = 2: the residual after the step is
+    about 1e-10, so the stop is tested at the bench's tolerance 1e-8.  The
+    error bound: b carries ~4e-16 relative rounding, which A^-1 amplifies by
+    up to lambda_ab / lambda_min (1.7e6 for mode (37, 2000)), spread over
+    the lowest modes; (p, A p) loses ~8 u / lambda_min / sqrt(n) ~ 1e-13 to
+    the stencil's cancellation: 1e-11 covers both.)"""
+    n = 4096
+    dev = torch.device("cuda:0")
+    i = torch.arange(1, n + 1, dtype=torch.float64, device=dev)
+    for a_, b_ in ((1, 1), (37, 2000)):
+        say("precond full size eigenvector s", s, "mode", a_, b_)
+        # 2 - 2 cos(t) = 4 sin^2(t/2): no cancellation for the lowest modes
+        lam = 4 * np.sin(a_ * np.pi / (2 * (n + 1))) ** 2 + 4 * np.sin(b_ * np.pi / (2 * (n + 1))) ** 2
+        phi = torch.outer(torch.sin(b_ * np.pi * i / (n + 1)), torch.sin(a_ * np.pi * i / (n + 1)))
+        x = torch.zeros_like(phi)
+        rc, res = ctx.cg_solve(cg.make_problem(phi, x, n, n, tol=1e-8, maxit=10, precond=s))
+        assert rc == cg.CG_OK and res.iterations == 1, (rc, res.iterations)
+        assert res.rel_res_true <= 1e-8
+        err = float(torch.linalg.norm(x - phi / lam) / torch.linalg.norm(phi / lam))
+        say("  rel err vs b/lambda %.2e" % err)
+        assert err <= 1e-11
 
 
 def test_one_step_is_plain_cg_on_the_gpu(ctx):
@@ -117,7 +153,7 @@ def test_fewer_iterations(ctx):
 def test_edge_cases(ctx):
     nx, ny, s = 200, 150, 4
     b = np.random.default_rng(4).uniform(-1, 1, (ny, nx))
-    o = tile_order(ctx, nx, ny, s)
+    o, orho = tile_order(ctx, nx, ny, s)
     x = np.full_like(b, 2.0)
     rc, res = ctx.solve(np.zeros_like(b), x, nx, ny, x0=np.ones_like(b), precond=s)
     assert rc == cg.CG_OK and res.iterations == 0 and not x.any()
@@ -132,7 +168,7 @@ def test_edge_cases(ctx):
     x = x0.copy()
     rc, res = ctx.solve(b, x, nx, ny, x0=x, tol=1e-9, maxit=5000, precond=s)
     xo, ro = oracle.pcg(b, nx, ny, s, tol=1e-9, maxit=5000, x0=x0, mode=MODE_CANONICAL,
-                        order=o)
+                        order=o, order_rho=orho)
     assert rc == cg.CG_OK and res.iterations == ro.iterations
     np.testing.assert_array_equal(x, xo)
 

@@ -18,6 +18,8 @@ import oracle
 from oracle import MODE_CANONICAL, MODE_SEQUENTIAL
 
 GPU_LIKE = oracle.Order(2, 64, 4, 16, 256)
+# (r, z) of the library's Chebyshev pass: tiles of one wavefront, 20 rows
+CHEB_LIKE = oracle.Order(2, 64, 1, 20, 256)
 MODES = (MODE_SEQUENTIAL, MODE_CANONICAL)
 
 
@@ -165,6 +167,27 @@ def test_iterates_match_a_dense_textbook_pcg(s):
             x, r = oracle.pcg(b.reshape(ny, nx), nx, ny, s, tol=0.0, maxit=k, mode=mode, order=o)
             assert r.iterations == k
             assert np.linalg.norm(x.ravel() - xt) <= 1e-11 * np.linalg.norm(xt), (s, k, mode)
+        # rho in the Chebyshev pass's own tile order
+        x, r = oracle.pcg(b.reshape(ny, nx), nx, ny, s, tol=0.0, maxit=k, mode=MODE_CANONICAL,
+                          order=GPU_LIKE, order_rho=CHEB_LIKE)
+        assert r.iterations == k
+        assert np.linalg.norm(x.ravel() - xt) <= 1e-11 * np.linalg.norm(xt), (s, k)
+
+
+def test_rho_order_is_the_one_given():
+    """order_rho changes only how rho = (r,z) is summed: with tiles of one
+    wavefront the iterates differ in the last bits from the default order
+    (so the argument is used) and agree to rounding; the default is order."""
+    nx, ny = 300, 70
+    b = np.random.default_rng(8).uniform(-1, 1, (ny, nx))
+    xa, ra = oracle.pcg(b, nx, ny, 4, tol=0.0, maxit=30, mode=MODE_CANONICAL, order=GPU_LIKE)
+    xd, rd = oracle.pcg(b, nx, ny, 4, tol=0.0, maxit=30, mode=MODE_CANONICAL, order=GPU_LIKE,
+                        order_rho=GPU_LIKE)
+    xb, rb = oracle.pcg(b, nx, ny, 4, tol=0.0, maxit=30, mode=MODE_CANONICAL, order=GPU_LIKE,
+                        order_rho=CHEB_LIKE)
+    np.testing.assert_array_equal(xa, xd)
+    assert not np.array_equal(xa, xb)
+    assert np.linalg.norm(xa - xb) <= 1e-12 * np.linalg.norm(xa)
 
 
 @pytest.mark.parametrize("mode", MODES)

@@ -111,7 +111,7 @@ def test_spmv_matches_scipy():
 
 @pytest.mark.parametrize("nx,ny", [(1, 1), (127, 1), (129, 65), (300, 77), (1000, 3)])
 @pytest.mark.parametrize("order", [GPU_LIKE, oracle.Order(4, 64, 4, 8, 256),
-                                   oracle.Order(1, 4, 3, 5, 8)])
+                                   oracle.Order(1, 4, 3, 5, 8), oracle.Order(2, 64, 1, 37, 256)])
 def test_canonical_dot_exact_on_integers(nx, ny, order):
     """Integer data: every partial sum is exact, so any correct order returns the
     exact sum; a dropped, repeated or misplaced term would not."""
