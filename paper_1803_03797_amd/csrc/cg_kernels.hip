@@ -1251,126 +1251,200 @@ struct D2 {
   double v[2];
 };
 
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
+constexpr int cmod(int a, int m) { return ((a % m) + m) % m; }
+
+// Lane shifts with zero fill (bound_ctrl): lane l receives lane l-1 (shr) or
+// lane l+1 (shl); lane 0 (shr) and lane 63 (shl) receive 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp0(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 // One wavefront of an item: output columns [cw, cw + 112), rows [y0, y1).
+// Rows are numbered from Jb = y0 - (s - 1); every ring below is indexed by
+// the row modulo its length, and the row loop is expanded over a period that
+// all the lengths divide (one step per template instance), so the rings
+// never move in registers.
+template <int S>
+struct ChebRegs {
+  static constexpr int H = S - 1;            // stencil steps = halo rows
+  static constexpr int L = H > 0 ? H : 1;    // y / r ring length
+  static constexpr int PD = S <= 3 ? 4 : 2;  // rows loaded ahead
+  static constexpr int P = clcm(clcm(2, L), PD);
+  // (r, z) needs r on row J-H at step J: kept in registers up to s = 6, read
+  // again (a cache hit: this wavefront read that row H steps before) one
+  // step ahead beyond, where the registers are needed for the stages
+  static constexpr bool RELOAD = S >= 7;
+  static constexpr int LR = RELOAD ? 1 : L;
+  D2 d[L][2];    // d_k on rows J-k-2, J-k-1 (slot (row - Jb) mod 2), levels k < H
+  D2 rk[L][2];   // r_k on row J-k-1 (same slots)
+  D2 y[L];       // y on rows J-H .. J-1 (slot (row - Jb) mod L)
+  D2 r0[LR];     // r on the same rows, for (r, z) (RELOAD: unused)
+  D2 rr[2];      // RELOAD: r on rows J-H, J-H+1 (slot (row - Jb) mod 2)
+  D2 ld[PD];     // r loaded for rows J .. J+PD-1 (slot (row - Jb) mod PD)
+  double a0, a1; // (r, z) column sums
+};
+
+struct ChebCtx {
+  const double* R;  // r + first column of the lane
+  double* Z;        // z + first column of the lane
+  int pitch, ny, y0, Je;
+  bool v0, v1, outl;
+};
+
+template <bool MASK>
+__device__ __forceinline__ D2 cheb_load(const ChebCtx& c, int J) {
+  const int jl = min(max(J, 0), c.ny - 1);
+  const double2 t = *reinterpret_cast<const double2*>(c.R + (size_t)jl * c.pitch);
+  D2 o;
+  o.v[0] = t.x;
+  o.v[1] = t.y;
+  if constexpr (MASK) {
+    const bool rv = J >= 0 && J < c.ny;
+    o.v[0] = (rv && c.v0) ? o.v[0] : 0.0;
+    o.v[1] = (rv && c.v1) ? o.v[1] : 0.0;
+  }
+  return o;
+}
+
+// Step J = J0 + Q of the march; false once the item's rows are exhausted.
+template <int S, bool MASK, int Q>
+__device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, const double* c2,
+                                          double c0, ChebRegs<S>& g, int J0) {
+  using G = ChebRegs<S>;
+  constexpr int H = G::H, L = G::L, PD = G::PD;
+  const int J = J0 + Q;
+  if (J >= c.Je) return false;
+  // keep the scheduler from interleaving steps (it would stretch the rings'
+  // live ranges past the register file)
+  __builtin_amdgcn_sched_barrier(0);
+  const D2 rin = g.ld[Q % PD];
+  g.ld[Q % PD] = cheb_load<MASK>(c, J + PD);
+  D2 rrow;
+  if constexpr (G::RELOAD) {
+    rrow = g.rr[cmod(Q - H, 2)];
+    g.rr[cmod(Q - H + 1, 2)] = cheb_load<MASK>(c, J - H + 1);
+  }
+  // stage 0: d_0 = c0 r, y = d_0 on row J (zero outside the grid already)
+  D2 dn, rn = rin, ynew;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    dn.v[e] = rin.v[e] * c0;
+    ynew.v[e] = dn.v[e];
+  }
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    // stage k on row J - k from level k-1: rows J-k-1 (slot so), J-k
+    // (slot sc) and J-k+1 (dn, this step)
+    const int so = cmod(Q - (k - 1), 2), sc = so ^ 1;
+    const D2 C = g.d[k - 1][sc], Sv = g.d[k - 1][so], Nv = dn;
+    const double w0 = dpp0<kDppWaveShr1>(C.v[1]);
+    const double e1 = dpp0<kDppWaveShl1>(C.v[0]);
+    const double W[2] = {w0, C.v[0]}, E[2] = {C.v[1], e1};
+    D2 dk, rk;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const double t = st5(C.v[e], W[e], E[e], Sv.v[e], Nv.v[e]);
+      rk.v[e] = g.rk[k - 1][sc].v[e] - t;
+      dk.v[e] = fma(c1[k - 1], C.v[e], c2[k - 1] * rk.v[e]);
+    }
+    if constexpr (MASK) {
+      const int j = J - k;
+      const bool rv = j >= 0 && j < c.ny;
+      dk.v[0] = (rv && c.v0) ? dk.v[0] : 0.0;
+      dk.v[1] = (rv && c.v1) ? dk.v[1] : 0.0;
+    }
+    D2& yk = g.y[cmod(Q - k, L)];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) yk.v[e] = yk.v[e] + dk.v[e];
+    // level k-1's row J-k+1 replaces its row J-k-1 (used just now)
+    g.d[k - 1][so] = dn;
+    g.rk[k - 1][so] = rn;
+    dn = dk;
+    rn = rk;
+  }
+  // row J - H of z is complete (slot Q mod L, which row J takes next)
+  constexpr int os = Q % L;
+  const D2 zrow = H > 0 ? g.y[os] : ynew;
+  if constexpr (!G::RELOAD) rrow = H > 0 ? g.r0[os] : rin;
+  if (J >= c.y0 + H) {
+    if (c.outl)
+      *reinterpret_cast<double2*>(c.Z + (size_t)(J - H) * c.pitch) =
+          make_double2(zrow.v[0], zrow.v[1]);
+    g.a0 = fma(rrow.v[0], zrow.v[0], g.a0);
+    g.a1 = fma(rrow.v[1], zrow.v[1], g.a1);
+  }
+  if constexpr (H > 0) {
+    g.y[os] = ynew;
+    if constexpr (!G::RELOAD) g.r0[os] = rin;
+  }
+  return true;
+}
+
+template <int S, bool MASK, int... Qs>
+__device__ __forceinline__ bool cheb_period(const ChebCtx& c, const double* c1, const double* c2,
+                                            double c0, ChebRegs<S>& g, int J0,
+                                            std::integer_sequence<int, Qs...>) {
+  return (cheb_step<S, MASK, Qs>(c, c1, c2, c0, g, J0) && ...);
+}
+
 // acc0/acc1 receive the (r, z) column sums of the lane's two columns.
 template <int S, bool MASK>
 __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, int y1,
                                            double& acc0, double& acc1) {
-  constexpr int H = S - 1;             // stencil steps = halo rows
-  constexpr int L = S > 1 ? S - 1 : 1; // array extent for the per-level state
-  constexpr int PD = S <= 3 ? 4 : 2;   // rows loaded ahead
-  const Geo& g = a.g;
+  using G = ChebRegs<S>;
+  constexpr int H = G::H, L = G::L, PD = G::PD, P = G::P;
+  const Geo& gg = a.g;
   const int lane = threadIdx.x & (kWave - 1);
   const int cl = cw - kChebHaloCols + 2 * lane;
-  const double c0 = a.cheb[0];
+  // the coefficients are uniform: scalar registers
+  const double c0 = uniform(a.cheb[0]);
   double c1[L], c2[L];
 #pragma unroll
   for (int k = 0; k < H; ++k) {
-    c1[k] = a.cheb[1 + k];
-    c2[k] = a.cheb[S + k];
+    c1[k] = uniform(a.cheb[1 + k]);
+    c2[k] = uniform(a.cheb[S + k]);
   }
+  ChebCtx c;
   // columns: the load address is valid for 0 <= cl < pitch (pitch is a
   // multiple of 128 and cl is even, so the pair stays in the row)
-  bool v0 = true, v1 = true;
+  c.v0 = c.v1 = true;
   int lc = cl;
   if constexpr (MASK) {
-    v0 = cl >= 0 && cl < g.nx;
-    v1 = cl >= 0 && cl + 1 < g.nx;
-    lc = (cl >= 0 && cl < g.pitch) ? cl : 0;
+    c.v0 = cl >= 0 && cl < gg.nx;
+    c.v1 = cl >= 0 && cl + 1 < gg.nx;
+    lc = (cl >= 0 && cl < gg.pitch) ? cl : 0;
   }
-  const double* R = a.r + lc;
-  auto load = [&](int J) {
-    const int jl = min(max(J, 0), g.ny - 1);
-    const double2 t = *reinterpret_cast<const double2*>(R + (size_t)jl * g.pitch);
-    D2 o;
-    o.v[0] = t.x;
-    o.v[1] = t.y;
-    if constexpr (MASK) {
-      const bool rv = J >= 0 && J < g.ny;
-      o.v[0] = (rv && v0) ? o.v[0] : 0.0;
-      o.v[1] = (rv && v1) ? o.v[1] : 0.0;
-    }
-    return o;
-  };
-  // state at the start of step J (levels k < H):
-  //   P1[k], P2[k] = d_k on rows J-k-2, J-k-1;  RK[k] = r_k on row J-k-1
-  //   Y[i] = y on row J-H+i (i < H);  R0[i] = r on row J-H+i (i < H)
-  D2 P1[L], P2[L], RK[L], Y[L], R0[L], LD[PD];
+  c.R = a.r + lc;
+  c.Z = a.z + cl;
+  c.pitch = gg.pitch;
+  c.ny = gg.ny;
+  c.y0 = y0;
+  c.Je = y1 + H;
+  c.outl = lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2 && (!MASK || cl < gg.nx);
+  G g;
 #pragma unroll
   for (int k = 0; k < L; ++k)
 #pragma unroll
-    for (int e = 0; e < 2; ++e) P1[k].v[e] = P2[k].v[e] = RK[k].v[e] = Y[k].v[e] = R0[k].v[e] = 0.0;
-  const int Jb = y0 - H, Je = y1 + H;
-#pragma unroll
-  for (int i = 0; i < PD; ++i) LD[i] = load(Jb + i);
-  double a0 = 0.0, a1 = 0.0;
-  double* Z = a.z + cl;
-  const bool outl = lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2 &&
-                    (!MASK || cl < g.nx);
-  for (int J = Jb; J < Je; ++J) {
-    const D2 rin = LD[0];
-#pragma unroll
-    for (int i = 0; i < PD - 1; ++i) LD[i] = LD[i + 1];
-    LD[PD - 1] = load(J + PD);
-    // stage 0: d_0 = c0 r, y = d_0 on row J (zero outside the grid already)
-    D2 dn, rn, ynew;
-#pragma unroll
     for (int e = 0; e < 2; ++e) {
-      dn.v[e] = rin.v[e] * c0;
-      ynew.v[e] = dn.v[e];
+      g.d[k][0].v[e] = g.d[k][1].v[e] = g.rk[k][0].v[e] = g.rk[k][1].v[e] = 0.0;
+      g.y[k].v[e] = 0.0;
     }
-    rn = rin;
 #pragma unroll
-    for (int k = 1; k <= H; ++k) {
-      // stage k on row j = J - k, from d_(k-1) on rows j-1 (P1), j (P2), j+1 (dn)
-      const D2 C = P2[k - 1], Sv = P1[k - 1], Nv = dn;
-      const double w0 = dpp<kDppWaveShr1>(C.v[1], 0.0);
-      const double e1 = dpp<kDppWaveShl1>(C.v[0], 0.0);
-      const double W[2] = {w0, C.v[0]}, E[2] = {C.v[1], e1};
-      D2 dk, rk;
+  for (int k = 0; k < G::LR; ++k) g.r0[k].v[0] = g.r0[k].v[1] = 0.0;
+  g.rr[0] = g.rr[1] = g.r0[0];
+  g.a0 = g.a1 = 0.0;
+  const int Jb = y0 - H;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const double t = st5(C.v[e], W[e], E[e], Sv.v[e], Nv.v[e]);
-        rk.v[e] = RK[k - 1].v[e] - t;
-        dk.v[e] = fma(c1[k - 1], C.v[e], c2[k - 1] * rk.v[e]);
-      }
-      if constexpr (MASK) {
-        const int j = J - k;
-        const bool rv = j >= 0 && j < g.ny;
-        dk.v[0] = (rv && v0) ? dk.v[0] : 0.0;
-        dk.v[1] = (rv && v1) ? dk.v[1] : 0.0;
-      }
-#pragma unroll
-      for (int e = 0; e < 2; ++e) Y[H - k].v[e] = Y[H - k].v[e] + dk.v[e];
-      // level k-1 moves down one row
-      P1[k - 1] = P2[k - 1];
-      P2[k - 1] = dn;
-      RK[k - 1] = rn;
-      dn = dk;
-      rn = rk;
-    }
-    // row J - H of z is complete: Y[0] (or the new row when s = 1)
-    const D2 zrow = H > 0 ? Y[0] : ynew;
-    const D2 rrow = H > 0 ? R0[0] : rin;
-    if (J >= y0 + H) {
-      if (outl)
-        *reinterpret_cast<double2*>(Z + (size_t)(J - H) * g.pitch) =
-            make_double2(zrow.v[0], zrow.v[1]);
-      a0 = fma(rrow.v[0], zrow.v[0], a0);
-      a1 = fma(rrow.v[1], zrow.v[1], a1);
-    }
-    if constexpr (H > 0) {
-#pragma unroll
-      for (int i = 0; i < H - 1; ++i) {
-        Y[i] = Y[i + 1];
-        R0[i] = R0[i + 1];
-      }
-      Y[H - 1] = ynew;
-      R0[H - 1] = rin;
-    }
-  }
-  acc0 = a0;
-  acc1 = a1;
+  for (int i = 0; i < PD; ++i) g.ld[i] = cheb_load<MASK>(c, Jb + i);
+  for (int J0 = Jb; J0 < c.Je; J0 += P)
+    if (!cheb_period<S, MASK>(c, c1, c2, c0, g, J0, std::make_integer_sequence<int, P>{})) break;
+  acc0 = g.a0;
+  acc1 = g.a1;
 }
 
 template <int S>
