@@ -64,6 +64,9 @@ PCG_TRAFFIC_BYTES = 1634008205
 FX_PRODUCTS = {"classic": 5, "pipelined": 8}
 FX_MULS_PER_PRODUCT = 4
 FX_MUL_PEAK_G = 256 * 4 * 16 * 2.4  # Gmul/s
+# FP64 vector operations issued per second (256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz; an fma counts once: 78.6 TFLOP/s counting it twice)
+FP64_OP_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -498,6 +501,40 @@ def bench_precond(args):
         log(name, json.dumps(out[name]))
     base = out["cg"]["seconds"]
     best = min((v["seconds"], k) for k, v in out.items())
+    # roofline of the Chebyshev pass at the fastest s: FP64 operations per
+    # unknown (stage 0 scale and the (r,z) fma, then per stencil step 5 for
+    # the stencil, 1 for r, 2 for d, 1 for y) against the FP64 vector issue
+    # rate; its HBM view (read r, write z: 16 B per unknown) beside it
+    roof = None
+    if best[1] != "cg":
+        sb = int(best[1].split("_s")[1])
+        kc = out[best[1]]["kernels"]["cheb_precond"]
+        ops = (2 + 9 * (sb - 1)) * n * n
+        ach = ops / (kc["avg_us"] * 1e-6) / 1e12
+        roof = {"kernel": "cheb_precond", "s": sb,
+                "bound": "alu" if sb >= 6 else "hbm",
+                "achieved": round(ach, 2) if sb >= 6 else kc["GBps"],
+                "peak": FP64_OP_PEAK_T if sb >= 6 else HBM_PEAK_GBPS,
+                "unit": "TOP/s (FP64 ops, fma = 1)" if sb >= 6 else "GB/s",
+                "frac": round(ach / FP64_OP_PEAK_T, 4) if sb >= 6
+                else round(kc["GBps"] / HBM_PEAK_GBPS, 4),
+                "hbm_view": {"achieved": kc["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                             "frac": round(kc["GBps"] / HBM_PEAK_GBPS, 4)},
+                "avg_launch_us": kc["avg_us"], "ops_per_launch": ops, "traffic": None}
+    cpu = None
+    if not args.no_cpu:
+        import oracle.oracle as oo
+        bh = b.cpu().numpy()
+        sb = int(best[1].split("_s")[1]) if best[1] != "cg" else 8
+        t = time.perf_counter()
+        oo.pcg(bh, n, n, sb, tol=0.0, maxit=2)
+        dt = time.perf_counter() - t
+        its = out.get("pcg_s%d" % sb, out["cg"])["iterations"]
+        cpu = {"value": round(dt / 2 * its, 1), "unit": "s (extrapolated)", "cores": 1,
+               "kind": "oracle",
+               "sample": "oracle preconditioned CG (explicit CSR, s = %d), 2 iterations at "
+                         "%dx%d in %.1f s including CSR assembly, times the GPU's %d "
+                         "iterations" % (sb, n, n, dt, its)}
     emit({"metric": "time to solution, %dx%d to tol 1e-8 (classic CG, Chebyshev-preconditioned "
                     "classic CG)" % (n, n),
           "workload": "precond", "value": round(best[0], 4), "unit": "s",
@@ -505,7 +542,7 @@ def bench_precond(args):
           "config": {"workload": "%dx%d Laplace, b=A(sin*sin+1e-3 noise), x0=0, tol 1e-8" % (n, n),
                      "steps": list(args.steps_list)},
           "dtype": "f64", "results": out, "best": best[1],
-          "speedup_vs_cg": round(base / best[0], 3)})
+          "speedup_vs_cg": round(base / best[0], 3), "roofline": roof, "cpu_baseline": cpu})
     ctx.close()
 
 

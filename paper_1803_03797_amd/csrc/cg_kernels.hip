@@ -1319,9 +1319,6 @@ __device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, co
   constexpr int H = G::H, L = G::L, PD = G::PD;
   const int J = J0 + Q;
   if (J >= c.Je) return false;
-  // keep the scheduler from interleaving steps (it would stretch the rings'
-  // live ranges past the register file)
-  __builtin_amdgcn_sched_barrier(0);
   const D2 rin = g.ld[Q % PD];
   g.ld[Q % PD] = cheb_load<MASK>(c, J + PD);
   D2 rrow;
