@@ -578,8 +578,23 @@ def bench_huge(args):
     out["fp64_classic"] = dict(status=cg.cg_status_str(rc), seconds=round(t64, 3),
                                iterations=r.iterations, rel_res_true=r.rel_res_true,
                                kernels=kern_table(ctx.cg_kernel_stats(reset=True)))
-    ctx.cg_set_profiling(False)
     log("fp64", json.dumps(out["fp64_classic"]))
+    if args.huge_precond:
+        # the same solve by classic CG preconditioned with s Chebyshev steps
+        xp = torch.zeros_like(b)
+        p = cg.make_problem(b, xp, n, n, tol=w["tol"], maxit=w["maxit"], variant=0,
+                            precond=args.huge_precond)
+        t = time.perf_counter()
+        rc, r = ctx.cg_solve(p)
+        tp = time.perf_counter() - t
+        out["fp64_pcg_s%d" % args.huge_precond] = dict(
+            status=cg.cg_status_str(rc), seconds=round(tp, 3), iterations=r.iterations,
+            rel_res_true=r.rel_res_true,
+            rel_err_vs_fp64_classic=((xp - x64).norm() / x64.norm()).item(),
+            kernels=kern_table(ctx.cg_kernel_stats(reset=True)))
+        log("fp64 pcg", json.dumps(out["fp64_pcg_s%d" % args.huge_precond]))
+        del xp
+    ctx.cg_set_profiling(False)
     err = ((xr - x64).norm() / x64.norm()).item()
     kappa = (4 - 4 * math.cos(n * math.pi / (n + 1))) / (4 - 4 * math.cos(math.pi / (n + 1)))
     cpu = None
@@ -759,6 +774,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
     ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed", "precond"])
+    ap.add_argument("--huge-precond", type=int, default=8,
+                    help="--workload huge: also solve with s Chebyshev steps (0: skip)")
     ap.add_argument("--steps-list", type=int, nargs="*", default=[2, 4, 6, 8],
                     help="--workload precond: Chebyshev steps to compare with CG")
     ap.add_argument("--probe", action="store_true")
