@@ -771,7 +771,7 @@ def main():
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=48)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
     ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed", "precond"])
     ap.add_argument("--huge-precond", type=int, default=8,

@@ -50,7 +50,8 @@ enum : int32_t {
 struct alignas(16) State {
   double gamma;      // (r, r) of the current iterate
   double gamma0;     // refinement: (rho, rho) at the start of the inner solve
-  double delta;      // pipelined: (w, r)
+  double delta;      // pipelined: (w, r); classic: alpha's numerator ((r, r), or
+                     // rho = (r, z) when preconditioned)
   double alpha, beta;
   double bb;         // (b, b)
   double thr;        // stop when gamma <= thr = tol^2 (b, b)

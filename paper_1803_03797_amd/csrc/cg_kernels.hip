@@ -356,6 +356,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     if (s.k == 0) sc.first = 1;
     else be = gamma / s.gamma;
     s.gamma = gamma;
+    s.delta = gamma;  // alpha's numerator for pass 2
     s.status = st;
     if (st != ST_RUNNING) return false;
     s.beta = be;
@@ -369,7 +370,10 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
       s.status = ST_BREAKDOWN;
       return false;
     }
-    s.alpha = ((s.flags & F_PRECOND) ? s.delta : s.gamma) / pi;
+    // delta holds alpha's numerator: rho = (r,z) preconditioned, else (r,r)
+    // (one field read unconditionally: a select between two fields of the
+    // state would make the compiler address it through scratch memory)
+    s.alpha = s.delta / pi;
     s.k += 1;
     sc.al = s.alpha;
     return true;
