@@ -626,18 +626,112 @@ int oracle_cheb_apply(int32_t nx, int32_t ny, int32_t mode, int32_t s, const dou
   return rc;
 }
 
+/* Preconditioned pipelined CG (Ghysels and Vanroose's preconditioned form of
+ * Algorithm 2, M^-1 = p_s(A)) from x0, with Algorithm 2's first block
+ * unrolled and the stop test on the unpreconditioned (r,r):
+ *   r = b - A x0; u = M^-1 r; w = A u
+ *   gamma = (r,u); delta = (w,u); stop test on (r,r)
+ *   breakdown unless delta > 0; m = M^-1 w; n = A m; alpha = gamma/delta
+ *   z = n; q = m; s = w; p = u
+ *   x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z      (k = 1)
+ *   repeat: gamma_old = gamma; gamma = (r,u); delta = (w,u); stop test on (r,r)
+ *           m = M^-1 w; n = A m; beta = gamma/gamma_old;
+ *           alpha = 1/(delta/gamma - beta/alpha) (breakdown unless the
+ *           denominator is > 0); z = n + beta z; q = m + beta q;
+ *           s = w + beta s; p = u + beta p;
+ *           x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z
+ * In exact arithmetic its iterates are preconditioned classic CG's.  Every dot
+ * follows ord in canonical mode. */
+static int ppcg_run(const csr_t* A, const ctx_t* c, int32_t sdeg, const double* cc0,
+                    const double* c1, const double* c2, const double* b, const double* x0,
+                    double* x, double tol, int32_t maxit, oracle_result* res) {
+  const int64_t n = A->n;
+  double* v[9];
+  for (int i = 0; i < 9; ++i) v[i] = (double*)malloc((size_t)n * sizeof(double));
+  double *r = v[0], *u = v[1], *w = v[2], *m = v[3], *nv = v[4], *z = v[5], *q = v[6],
+         *sv = v[7], *p = v[8];
+  int st = OR_OK, rc;
+  int32_t k = 0;
+  double rr = 0.0;
+  const double bb = dot(c, b, b);
+  for (int i = 0; i < 9; ++i)
+    if (!v[i]) { st = OR_E_NOMEM; goto done; }
+  if (bb == 0.0) {
+    memset(x, 0, (size_t)n * sizeof(double));
+    res->rel_res_recursive = res->rel_res_true = 0.0;
+    goto done;
+  }
+  if (x0) memcpy(x, x0, (size_t)n * sizeof(double));
+  else    memset(x, 0, (size_t)n * sizeof(double));
+  spmv(A, x, nv);
+  for (int64_t i = 0; i < n; ++i) r[i] = b[i] - nv[i];
+  if ((rc = cheb_apply(A, c->mode, sdeg, cc0, c1, c2, r, u))) { st = rc; goto done; }
+  spmv(A, u, w);
+  const double thr = (tol * tol) * bb;
+  double gamma = dot(c, r, u), delta = dot(c, w, u);
+  rr = dot(c, r, r);
+  st = stop_rule(rr, thr, k, maxit, tol);
+  if (st != -100) goto fin;
+  if (!(delta > 0.0) || !isfinite(delta)) { st = OR_BREAKDOWN; goto fin; }
+  if ((rc = cheb_apply(A, c->mode, sdeg, cc0, c1, c2, w, m))) { st = rc; goto done; }
+  spmv(A, m, nv);
+  double alpha = gamma / delta;
+  memcpy(z, nv, (size_t)n * sizeof(double));
+  memcpy(q, m, (size_t)n * sizeof(double));
+  memcpy(sv, w, (size_t)n * sizeof(double));
+  memcpy(p, u, (size_t)n * sizeof(double));
+  axpy(c, n, alpha, p, x);
+  axpy(c, n, -alpha, sv, r);
+  axpy(c, n, -alpha, q, u);
+  axpy(c, n, -alpha, z, w);
+  k = 1;
+  for (;;) {
+    const double gamma_old = gamma;
+    gamma = dot(c, r, u);
+    delta = dot(c, w, u);
+    rr = dot(c, r, r);
+    st = stop_rule(rr, thr, k, maxit, tol);
+    if (st != -100) break;
+    if ((rc = cheb_apply(A, c->mode, sdeg, cc0, c1, c2, w, m))) { st = rc; goto done; }
+    spmv(A, m, nv);
+    const double beta = gamma / gamma_old;
+    const double den = delta / gamma - beta / alpha;
+    if (!(den > 0.0) || !isfinite(den)) { st = OR_BREAKDOWN; break; }
+    alpha = 1.0 / den;
+    xpay(c, n, nv, beta, z);
+    xpay(c, n, m, beta, q);
+    xpay(c, n, w, beta, sv);
+    xpay(c, n, u, beta, p);
+    axpy(c, n, alpha, p, x);
+    axpy(c, n, -alpha, sv, r);
+    axpy(c, n, -alpha, q, u);
+    axpy(c, n, -alpha, z, w);
+    ++k;
+  }
+fin:
+  finish(A, c, b, x, bb, rr, res);
+done:
+  res->status = st;
+  res->iterations = k;
+  res->outer_iterations = 0;
+  for (int i = 0; i < 9; ++i) free(v[i]);
+  return st;
+}
+
 /* Preconditioned classic CG (Algorithm 1 with M^-1 = p_s(A)) from x0:
  *   r = b - A x0; gamma = (r,r)
  *   repeat: stop test on gamma (as for CG); z = M^-1 r; rho = (r,z)
  *           (breakdown unless 0 < rho < inf); p = z (first) or
  *           z + (rho/rho_old) p; s = A p; pi = (p,s); alpha = rho/pi;
  *           x += alpha p; r -= alpha s; gamma = (r,r); rho_old = rho
- * Canonical mode: rho follows ord_rho (NULL: ord), every other dot ord. */
-int oracle_pcg(int32_t mode, const oracle_order* ord, const oracle_order* ord_rho, int32_t nx,
-               int32_t ny, int32_t sdeg, const double* b, const double* x0, double* x,
-               double tol, int32_t maxit, oracle_result* res) {
+ * Canonical mode: rho follows ord_rho (NULL: ord), every other dot ord.
+ * variant 1 runs the preconditioned pipelined CG above (ord_rho unused). */
+int oracle_pcg(int32_t variant, int32_t mode, const oracle_order* ord,
+               const oracle_order* ord_rho, int32_t nx, int32_t ny, int32_t sdeg,
+               const double* b, const double* x0, double* x, double tol, int32_t maxit,
+               oracle_result* res) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
-      sdeg < 1 || sdeg > 64)
+      sdeg < 1 || sdeg > 64 || (variant != VARIANT_CLASSIC && variant != VARIANT_PIPELINED))
     return OR_E_INVALID;
   if (!ord_rho) ord_rho = ord;
   if (mode == MODE_CANONICAL && (!order_valid(ord, nx, ny) || !order_valid(ord_rho, nx, ny)))
@@ -650,6 +744,11 @@ int oracle_pcg(int32_t mode, const oracle_order* ord, const oracle_order* ord_rh
   ctx_t c = {nx, ny, mode, ord};
   ctx_t c_rho = {nx, ny, mode, ord_rho};
   memset(res, 0, sizeof(*res));
+  if (variant == VARIANT_PIPELINED) {
+    rc = ppcg_run(&A, &c, sdeg, &c0, c1, c2, b, x0, x, tol, maxit, res);
+    csr_free(&A);
+    return rc;
+  }
   const int64_t n = A.n;
   double* r = (double*)malloc((size_t)n * sizeof(double));
   double* z = (double*)malloc((size_t)n * sizeof(double));

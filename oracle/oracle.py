@@ -72,8 +72,8 @@ def _load():
     lib.oracle_cheb_apply.restype = C.c_int
     lib.oracle_cheb_apply.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
     lib.oracle_pcg.restype = C.c_int
-    lib.oracle_pcg.argtypes = [C.c_int32, C.POINTER(Order), C.POINTER(Order), C.c_int32,
-                               C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_int32,
+    lib.oracle_pcg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.POINTER(Order),
+                               C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_int32,
                                C.POINTER(_Result)]
     I64 = C.c_int64
     lib.oracle_fx_quantize.restype = I64
@@ -200,17 +200,19 @@ def cheb_apply(r, nx, ny, s, mode=MODE_SEQUENTIAL):
 
 
 def pcg(b, nx, ny, s, tol=1e-8, maxit=2000, x0=None, mode=MODE_SEQUENTIAL, order=None,
-        order_rho=None):
-    """Classic CG preconditioned by the s-step Chebyshev polynomial in A.
-    Canonical mode: rho = (r, z) is summed in order_rho (default: order)."""
+        order_rho=None, variant=VARIANT_CLASSIC):
+    """CG preconditioned by the s-step Chebyshev polynomial in A: classic
+    (variant 0) or pipelined (variant 1, Ghysels and Vanroose's form of
+    Algorithm 2).  Canonical mode: classic sums rho = (r, z) in order_rho
+    (default: order); every other dot follows order."""
     b = _vec(b, nx, ny)
     x0a = _vec(x0, nx, ny) if x0 is not None else None
     x = np.zeros_like(b)
     res = _Result()
     o = C.byref(order) if order is not None else None
     orho = C.byref(order_rho) if order_rho is not None else None
-    rc = _load().oracle_pcg(mode, o, orho, nx, ny, s, _ptr(b), _ptr(x0a), _ptr(x), tol, maxit,
-                            C.byref(res))
+    rc = _load().oracle_pcg(variant, mode, o, orho, nx, ny, s, _ptr(b), _ptr(x0a), _ptr(x), tol,
+                            maxit, C.byref(res))
     if rc < 0:
         raise ValueError("oracle_pcg rejected the call: %d" % rc)
     return x, Result(status=res.status, iterations=res.iterations,

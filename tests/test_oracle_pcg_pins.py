@@ -254,3 +254,80 @@ def test_edge_cases_and_rejections():
             oracle.pcg(b, nx, ny, bad)
     with pytest.raises(ValueError):
         oracle.cheb_apply(b, nx, ny, 0)
+
+
+# --------------------------------------------- preconditioned pipelined CG --
+PIPE = oracle.VARIANT_PIPELINED
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("nx,ny,s", [(6, 5, 2), (16, 16, 5), (13, 9, 8), (1, 7, 3)])
+def test_pipelined_iterates_match_classic(mode, nx, ny, s):
+    """In exact arithmetic the preconditioned pipelined recurrences (r, u, w,
+    s, q, z) give the iterates of preconditioned classic CG; in FP64 they
+    agree to rounding over the first 20 iterations (a sign or beta slip in
+    any of the eight updates breaks this)."""
+    b = np.random.default_rng(nx * ny + s).uniform(-1, 1, (ny, nx))
+    o = GPU_LIKE if mode == MODE_CANONICAL else None
+    for k in range(1, min(21, nx * ny + 1)):
+        xc, rc = oracle.pcg(b, nx, ny, s, tol=0.0, maxit=k, mode=mode, order=o)
+        xp, rp = oracle.pcg(b, nx, ny, s, tol=0.0, maxit=k, mode=mode, order=o, variant=PIPE)
+        assert rp.iterations == rc.iterations == k
+        assert np.linalg.norm(xp - xc) <= 1e-12 * np.linalg.norm(xc), (k, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_pipelined_iterates_match_a_dense_textbook_pcg(mode):
+    nx, ny, s = 12, 9, 3
+    n = nx * ny
+    A = dense_A(nx, ny)
+    M = np.column_stack([oracle.cheb_apply(np.eye(n)[:, k].reshape(ny, nx), nx, ny, s).ravel()
+                         for k in range(n)])
+    b = np.random.default_rng(17).uniform(-1, 1, n)
+    o = GPU_LIKE if mode == MODE_CANONICAL else None
+    for k in (1, 2, 5, 12):
+        xt = _textbook_pcg(A, M, b, k)
+        x, r = oracle.pcg(b.reshape(ny, nx), nx, ny, s, tol=0.0, maxit=k, mode=mode, order=o,
+                          variant=PIPE)
+        assert np.linalg.norm(x.ravel() - xt) <= 1e-11 * np.linalg.norm(xt), k
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("s", [2, 8])
+def test_pipelined_solution_against_cholesky(mode, s):
+    nx, ny = 40, 31
+    A = dense_A(nx, ny)
+    b = np.random.default_rng(9).uniform(-1, 1, (ny, nx))
+    xs = sla.cho_solve(sla.cho_factor(A), b.ravel()).reshape(ny, nx)
+    o = GPU_LIKE if mode == MODE_CANONICAL else None
+    x, r = oracle.pcg(b, nx, ny, s, tol=1e-12, maxit=5000, mode=mode, order=o, variant=PIPE)
+    lo, hi = spectrum(nx, ny)
+    # the pipelined recurrences let the true residual drift a little above
+    # the recursive one (reading 11 of the unpreconditioned variant)
+    assert r.status == 0 and r.rel_res_recursive <= 1e-12 and r.rel_res_true <= 1e-11
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 20 * 1e-12 * hi / lo
+
+
+def test_pipelined_single_mode_and_edge_cases():
+    nx, ny = 20, 11
+    phi = mode_vec(nx, ny, 3, 2)
+    lam = 4 - 2 * math.cos(3 * math.pi / (nx + 1)) - 2 * math.cos(2 * math.pi / (ny + 1))
+    x, r = oracle.pcg(phi, nx, ny, 4, tol=1e-10, maxit=50, variant=PIPE)
+    assert r.status == 0 and r.iterations == 1
+    assert np.linalg.norm(x - phi / lam) <= 1e-12 * np.linalg.norm(phi / lam)
+    b = np.random.default_rng(2).uniform(-1, 1, (ny, nx))
+    x, r = oracle.pcg(np.zeros_like(b), nx, ny, 4, x0=np.ones_like(b), variant=PIPE)
+    assert r.status == 0 and r.iterations == 0 and not x.any()
+    x, r = oracle.pcg(b, nx, ny, 4, tol=1e-14, maxit=3, variant=PIPE)
+    assert r.status == 2 and r.iterations == 3
+    b2 = b.copy()
+    b2[4, 4] = np.inf
+    x, r = oracle.pcg(b2, nx, ny, 4, variant=PIPE)
+    assert r.status == 3 and r.iterations == 0
+    x0 = np.random.default_rng(3).uniform(-1, 1, (ny, nx))
+    xp, rp = oracle.pcg(b, nx, ny, 4, tol=1e-10, maxit=500, x0=x0, variant=PIPE)
+    xc, rc = oracle.pcg(b, nx, ny, 4, tol=1e-10, maxit=500, x0=x0)
+    assert rp.status == 0 and abs(rp.iterations - rc.iterations) <= 1
+    assert np.linalg.norm(xp - xc) <= 1e-9 * np.linalg.norm(xc)
+    with pytest.raises(ValueError):
+        oracle.pcg(b, nx, ny, 4, variant=2)
