@@ -471,9 +471,12 @@ def bench_precond(args):
     ctx.cg_apply(xs, b, n, n)  # b = A x* with the library's stencil
     nxs = float(torch.linalg.norm(xs))
     out = {}
-    for s in [0] + list(args.steps_list):
+    legs = [(0, 0)] + [(0, s) for s in args.steps_list] + \
+        [(1, s) for s in args.steps_list if s in (4, 8)]
+    for variant, s in legs:
         x = torch.zeros_like(b)
-        p = cg.make_problem(b, x, n, n, tol=w["tol"], maxit=w["maxit"], precond=s)
+        p = cg.make_problem(b, x, n, n, tol=w["tol"], maxit=w["maxit"], precond=s,
+                            variant=variant)
         ctx.cg_solve(p)  # warm: graphs captured
         x.zero_()
         torch.cuda.synchronize()
@@ -485,19 +488,19 @@ def bench_precond(args):
         # per-pass kernel times over a short fixed run
         ctx.cg_set_profiling(True)
         ctx.cg_kernel_stats(reset=True)
-        ctx.cg_solve(cg.make_problem(b, torch.zeros_like(b), n, n, tol=0.0, maxit=20, precond=s))
+        ctx.cg_solve(cg.make_problem(b, torch.zeros_like(b), n, n, tol=0.0, maxit=20, precond=s,
+                                     variant=variant))
         ks = kern_table(ctx.cg_kernel_stats(reset=True))
         ctx.cg_set_profiling(False)
-        name = "cg" if s == 0 else "pcg_s%d" % s
-        per_it = sum(v["avg_us"] * v["launches"] for k, v in ks.items()
-                     if k in ("cheb_precond", "stencil_dot", "update_norm", "update_norm_nx")) / 20
+        name = "cg" if s == 0 else ("pcg_s%d" if variant == 0 else "ppcg_s%d") % s
+        iter_kernels = ("cheb_precond", "stencil_dot", "update_norm", "update_norm_nx",
+                        "cheb_precond_w", "ppcg_pass")
+        per_it = sum(v["avg_us"] * v["launches"] for k, v in ks.items() if k in iter_kernels) / 20
         out[name] = dict(status=cg.cg_status_str(rc), iterations=r.iterations,
                          seconds=round(tt, 4), rel_err_vs_xstar=float("%.3g" % err),
                          rel_res_true=float("%.3g" % r.rel_res_true),
                          us_per_iteration=round(per_it, 1),
-                         kernels={k: v for k, v in ks.items()
-                                  if k in ("cheb_precond", "stencil_dot", "update_norm",
-                                           "update_norm_nx")})
+                         kernels={k: v for k, v in ks.items() if k in iter_kernels})
         log(name, json.dumps(out[name]))
     base = out["cg"]["seconds"]
     best = min((v["seconds"], k) for k, v in out.items())
@@ -508,7 +511,8 @@ def bench_precond(args):
     roof = None
     if best[1] != "cg":
         sb = int(best[1].split("_s")[1])
-        kc = out[best[1]]["kernels"]["cheb_precond"]
+        kb = out[best[1]]["kernels"]
+        kc = kb["cheb_precond"] if "cheb_precond" in kb else kb["cheb_precond_w"]
         ops = (2 + 9 * (sb - 1)) * n * n
         ach = ops / (kc["avg_us"] * 1e-6) / 1e12
         roof = {"kernel": "cheb_precond", "s": sb,
@@ -536,7 +540,7 @@ def bench_precond(args):
                          "%dx%d in %.1f s including CSR assembly, times the GPU's %d "
                          "iterations" % (sb, n, n, dt, its)}
     emit({"metric": "time to solution, %dx%d to tol 1e-8 (classic CG, Chebyshev-preconditioned "
-                    "classic CG)" % (n, n),
+                    "classic and pipelined CG)" % (n, n),
           "workload": "precond", "value": round(best[0], 4), "unit": "s",
           "higher_is_better": False,
           "config": {"workload": "%dx%d Laplace, b=A(sin*sin+1e-3 noise), x0=0, tol 1e-8" % (n, n),

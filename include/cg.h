@@ -98,13 +98,16 @@ typedef struct {
   cg_variant variant;      /* Algorithm 1 or Algorithm 2                              */
   cg_precision precision;  /* FP64, FP32 inner CG inside FP64 refinement, or fixed    */
   double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
-  int32_t precond;         /* 0: none; s = 1..8: classic FP64 CG preconditioned by
+  int32_t precond;         /* 0: none; s = 1..8: FP64 CG preconditioned by
                               M^-1 = p_s(A), s steps of Chebyshev semi-iteration on
                               A y = r from y = 0 over [lmax / (2 s^2), lmax], lmax =
                               4 + 2cos(pi/(nx+1)) + 2cos(pi/(ny+1)) the largest
                               eigenvalue of A (the M^-1 of the pipelined-CG
-                              literature Section I builds on); cg_solve only
-                              (batches and serving reject it)                      */
+                              literature Section I builds on): classic CG with
+                              z = M^-1 r, or the preconditioned pipelined CG of
+                              Ghysels and Vanroose (variant PIPELINED); the stop
+                              test stays on ||r||; cg_solve only (batches and
+                              serving reject it)                                   */
   int32_t pad_;
 } cg_problem;
 

@@ -49,7 +49,8 @@ enum : int32_t {
 // state[(m + 1) & 1], so no work-group overwrites what another still reads.
 struct alignas(16) State {
   double gamma;      // (r, r) of the current iterate
-  double gamma0;     // refinement: (rho, rho) at the start of the inner solve
+  double gamma0;     // refinement: (rho, rho) at the start of the inner solve;
+                     // preconditioned pipelined: (r, u)
   double delta;      // pipelined: (w, r); classic: alpha's numerator ((r, r), or
                      // rho = (r, z) when preconditioned)
   double alpha, beta;
@@ -98,6 +99,11 @@ enum : int32_t {
   K_CG2FX,        // K_CG2F of an even inner iteration: both d updates
   K_CHEB,         // z = p_s(A) r (Chebyshev preconditioner); slot (r,z) in its own
                   // tiles: 128 columns x cheb_rows rows, one wavefront per tile
+  K_INIT_WU,      // preconditioned pipelined: w = A u; slots (r,u), (w,u), (r,r)
+  K_CHEBW,        // preconditioned pipelined: m = p_s(A) w after the scalar step
+                  // (stop test, alpha, beta from the three slots); no slots
+  K_PPCG,         // preconditioned pipelined fused iteration (n = A m and the eight
+                  // updates); slots (r,u), (w,u), (r,r)
   K_NKINDS
 };
 
@@ -139,6 +145,10 @@ struct PassArgs {
   int32_t cheb_rows;       // K_CHEB: rows of one Chebyshev item / partial tile
   int32_t cheb_tiles;      // K_CG1 preconditioned: partials of the Chebyshev pass
   const double* cheb;      // K_CHEB: c0, then c1[s-1], then c2[s-1]
+  double* uu;              // preconditioned pipelined: u = M^-1 r
+  double* sv;              //                           s (the direction of r)
+  const double* mv;        //                           m = M^-1 w (read with halo)
+  double* wv;              //                           w (updated in place)
 };
 
 // Scalars a pass body needs, chosen by the preceding transition.

@@ -273,6 +273,44 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     s.flags &= ~F_BB_PENDING;
     if (s.bb == 0.0) s.status = ST_ZERO_RHS;
     return s.status == ST_RUNNING;
+  } else if constexpr (KIND == K_INIT_WU) {
+    return s.status == ST_RUNNING;
+  } else if constexpr (KIND == K_CHEBW) {
+    // Preconditioned pipelined CG: gamma = (r,u), delta = (w,u) and the stop
+    // test on (r,r); first pass alpha = gamma/delta, later beta =
+    // gamma/gamma_old, alpha = 1/(delta/gamma - beta/alpha_old).  gamma is
+    // kept in gamma0 (State::gamma holds (r,r), the residual reported).
+    if (s.status != ST_RUNNING) return false;
+    const double gu = sum[0], du = sum[1], rr = sum[2];
+    int st = stop_code(rr, s.thr, s.k, s.maxit, s.tol);
+    double al = 0.0, be = 0.0;
+    if (st == ST_RUNNING) {
+      if (s.k == 0) {
+        if (!(du > 0.0) || !isfinite(du)) st = ST_BREAKDOWN;
+        else al = gu / du;
+      } else {
+        be = gu / s.gamma0;
+        const double den = du / gu - be / s.alpha;
+        if (!(den > 0.0) || !isfinite(den)) st = ST_BREAKDOWN;
+        else al = 1.0 / den;
+      }
+    }
+    s.gamma = rr;
+    s.gamma0 = gu;
+    s.delta = du;
+    s.status = st;
+    if (st != ST_RUNNING) return false;
+    s.alpha = al;
+    s.beta = be;
+    s.k += 1;
+    return true;
+  } else if constexpr (KIND == K_PPCG) {
+    // the scalars of this iteration were set by the Chebyshev pass before it
+    if (s.status != ST_RUNNING) return false;
+    sc.al = s.alpha;
+    sc.be = s.beta;
+    sc.first = s.k == 1;
+    return true;
   } else if constexpr (KIND == K_PCG) {
     // Algorithm 2: gamma = (r,r), delta = (w,r); first pass alpha = gamma/delta,
     // later beta = gamma/gamma_old, alpha = 1/(delta/gamma - beta/alpha_old).
@@ -459,8 +497,9 @@ constexpr int ndots_in() {  // partial slots the prologue consumes
 
 template <int KIND>
 constexpr int ndots_out() {  // partial slots the body produces
-  return (KIND == K_INIT_R || KIND == K_INIT_W || KIND == K_PCG || KIND == K_PCGX ||
-          KIND == K_RESID)
+  return (KIND == K_INIT_WU || KIND == K_PPCG) ? 3
+         : (KIND == K_INIT_R || KIND == K_INIT_W || KIND == K_PCG || KIND == K_PCGX ||
+            KIND == K_RESID)
              ? 2
          : (KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X || KIND == K_REF_SCALE ||
             KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_DOT)
@@ -858,6 +897,119 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   lv[1] = fold<CPL>(a1);
 }
 
+// --- K_INIT_WU: w = A u; slots (r,u), (w,u), (r,r)   [preconditioned pipelined]
+template <int CPL>
+__device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  double a0[CPL], a1[CPL], a2[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = a2[k] = 0.0;
+  const int valid = g.nx - s.c;
+  const double* Rv = a.r;
+  double* Wv = a.wv;
+  walk_plain<double, CPL>(
+      g, s, a.uu, [=](size_t off) { return ldrow<double, CPL>(Rv + off + s.c); },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& r) {
+        R out;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          out.e[k] = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (k < valid) {
+            a0[k] = fma(r.e[k], hC.e[k], a0[k]);
+            a1[k] = fma(out.e[k], hC.e[k], a1[k]);
+            a2[k] = fma(r.e[k], r.e[k], a2[k]);
+          }
+        }
+        strow<double, CPL>(Wv + off + s.c, out, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+  lv[1] = fold<CPL>(a1);
+  lv[2] = fold<CPL>(a2);
+}
+
+// --- K_PPCG: one fused iteration of preconditioned pipelined CG (Ghysels and
+//     Vanroose): n = A m; z = n + beta z; q = m + beta q; s = w + beta s;
+//     p = u + beta p; x += alpha p; r -= alpha s; u -= alpha q;
+//     w -= alpha z; slots (r,u), (w,u), (r,r) of the new vectors.  On the
+//     first iteration z, q, s, p are taken as zero.
+template <int CPL>
+struct PpcgRow {
+  Row<double, CPL> x, r, u, w, z, q, s, p;
+};
+
+template <int CPL>
+__device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  using R = Row<double, CPL>;
+  const Geo& g = a.g;
+  const Strip s = strip_of<CPL>(g, t);
+  const double al = sc.al, be = sc.be, nal = -sc.al;
+  const bool first = sc.first;
+  double a0[CPL], a1[CPL], a2[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = a2[k] = 0.0;
+  const int valid = g.nx - s.c;
+  double *X = a.x, *Rv = a.r, *U = a.uu, *Wv = a.wv, *Z = a.z, *Q = a.q, *Sv = a.sv, *Pp = a.p;
+  walk_plain<double, CPL>(
+      g, s, a.mv,
+      [=](size_t off) {
+        PpcgRow<CPL> v;
+        const size_t oc = off + s.c;
+        v.x = ldrow<double, CPL>(X + oc);
+        v.r = ldrow<double, CPL>(Rv + oc);
+        v.u = ldrow<double, CPL>(U + oc);
+        v.w = ldrow<double, CPL>(Wv + oc);
+        // z, q, s, p are ignored on the first iteration (taken as zero)
+        v.z = ldrow<double, CPL>(Z + oc);
+        v.q = ldrow<double, CPL>(Q + oc);
+        v.s = ldrow<double, CPL>(Sv + oc);
+        v.p = ldrow<double, CPL>(Pp + oc);
+        return v;
+      },
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const PpcgRow<CPL>& in) {
+        R x = in.x, r = in.r, u = in.u, w = in.w, z, q, sv, p;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+          const double nv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          if (first) {
+            z.e[k] = nv;
+            q.e[k] = hC.e[k];
+            sv.e[k] = w.e[k];
+            p.e[k] = u.e[k];
+          } else {
+            z.e[k] = fma(be, in.z.e[k], nv);
+            q.e[k] = fma(be, in.q.e[k], hC.e[k]);
+            sv.e[k] = fma(be, in.s.e[k], w.e[k]);
+            p.e[k] = fma(be, in.p.e[k], u.e[k]);
+          }
+          x.e[k] = fma(al, p.e[k], x.e[k]);
+          r.e[k] = fma(nal, sv.e[k], r.e[k]);
+          u.e[k] = fma(nal, q.e[k], u.e[k]);
+          w.e[k] = fma(nal, z.e[k], w.e[k]);
+          if (k < valid) {
+            a0[k] = fma(r.e[k], u.e[k], a0[k]);
+            a1[k] = fma(w.e[k], u.e[k], a1[k]);
+            a2[k] = fma(r.e[k], r.e[k], a2[k]);
+          }
+        }
+        const size_t oc = off + s.c;
+        strow<double, CPL>(Z + oc, z, valid);
+        strow<double, CPL>(Q + oc, q, valid);
+        strow<double, CPL>(Sv + oc, sv, valid);
+        strow<double, CPL>(Pp + oc, p, valid);
+        strow<double, CPL>(X + oc, x, valid);
+        strow<double, CPL>(Rv + oc, r, valid);
+        strow<double, CPL>(U + oc, u, valid);
+        strow<double, CPL>(Wv + oc, w, valid);
+      });
+  lv[0] = fold<CPL>(a0);
+  lv[1] = fold<CPL>(a1);
+  lv[2] = fold<CPL>(a2);
+}
+
 // --- K_CG1 / K_CG1F: p = r + beta p_old (on tile + halo); s = A p; store p;
 //     slot (p, s).  First iteration: p = r.
 template <typename T, int CPL>
@@ -1100,6 +1252,8 @@ __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc,
   if constexpr (KIND == K_INIT_R) body_residual<CPL, true>(a, t, lv);
   else if constexpr (KIND == K_RESID) body_residual<CPL, false>(a, t, lv);
   else if constexpr (KIND == K_INIT_W) body_apply<CPL, true>(a, t, lv);
+  else if constexpr (KIND == K_INIT_WU) body_init_wu<CPL>(a, t, lv);
+  else if constexpr (KIND == K_PPCG) body_ppcg<CPL>(a, t, sc, lv);
   else if constexpr (KIND == K_APPLY) body_apply<CPL, false>(a, t, lv);
   else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
   else if constexpr (KIND == K_PCG) body_pcg<CPL, false>(a, t, sc, lv);
@@ -1132,8 +1286,9 @@ __device__ __forceinline__ void run_body_any(const PassArgs& a, int t, const Sc&
   }
 }
 
-// LDS per tile group: 4*2 doubles for the cross-tile stage, 2*4*2 for tiles.
-constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 2;
+// LDS per tile group: 4*2 doubles for the cross-tile stage, then 2*4*D for
+// the tiles of a pass with D <= 3 slots (at offset 8).
+constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 3;
 
 // ------------------------------------------------------ multi-group pass --
 //
@@ -1194,7 +1349,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   int par = 0;
   for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
     const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
-    double lv[2];
+    double lv[DO > 2 ? DO : 2];
     run_body<KIND, CPL>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
@@ -1448,22 +1603,28 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
   acc1 = g.a1;
 }
 
-template <int S>
+// PIPE = false: K_CHEB (z = M^-1 r of classic CG, and of the pipelined
+// variant's first residual); PIPE = true: K_CHEBW (m = M^-1 w of the
+// pipelined variant, after its scalar step; no partials).  The input vector
+// is a.r, the output a.z.
+template <int S, bool PIPE>
 __global__ __launch_bounds__(kChebThreads) void k_cheb(PassArgs a) {
   __shared__ double colacc[kChebWaves * kChebOut];
-  __shared__ double red[4 * 2];
+  __shared__ double red[4 * 3];
   {
     State s = load_state_uniform(a.st_in);
-    double sum[2] = {0.0, 0.0};
+    double sum[3] = {0.0, 0.0, 0.0};
     if (s.status == ST_RUNNING) {
-      if (s.flags & F_BB_PENDING) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, red);
+      if (PIPE) cross_tile_sum<3>(a.part_in, a.g.tiles, sum, red);
+      else if (s.flags & F_BB_PENDING) cross_tile_sum<2>(a.part_in, a.g.tiles, sum, red);
       else cross_tile_sum<1>(a.part_in, a.g.tiles, sum, red);
     }
-    sum[0] = uniform(sum[0]);
-    sum[1] = uniform(sum[1]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sum[d] = uniform(sum[d]);
     Sc sc;
     bool flush = false;
-    const bool run = transition_x<K_CHEB>(s, sum, sc, flush);
+    const bool run = PIPE ? transition<K_CHEBW>(s, sum, sc)
+                          : transition_x<K_CHEB>(s, sum, sc, flush);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
     if (flush) {
       // the stop test stopped the solve after an odd iteration: apply that
@@ -1498,13 +1659,17 @@ __global__ __launch_bounds__(kChebThreads) void k_cheb(PassArgs a) {
       if (inner) cheb_march<S, false>(a, cw, y0, y1, acc0, acc1);
       else cheb_march<S, true>(a, cw, y0, y1, acc0, acc1);
     }
-    if (lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2) {
+    // PIPE: no partials, the fused pass sums its dots.  The column sums are
+    // still formed: without them the compiler schedules the march of s = 8
+    // into more than 256 registers and spills.
+    if constexpr (PIPE) __asm__ volatile("" ::"v"(acc0), "v"(acc1));
+    if (!PIPE && lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2) {
       double* c = colacc + wave * kChebOut + 2 * (lane - kChebHaloCols / 2);
       c[0] = acc0;
       c[1] = acc1;
     }
     __syncthreads();
-    if (wave < kChebGroupTiles) {
+    if (!PIPE && wave < kChebGroupTiles) {
       const int tx = gx * kChebGroupTiles + wave;
       if (tx < g.ntx) {
         const double* c = colacc + wave * 2 * kWave + 2 * lane;
@@ -1534,6 +1699,7 @@ __global__ void k_fill(uint32_t* p, size_t n) {
 template <int KIND>
 __device__ __forceinline__ void wg_pass(const PassArgs& a, const Sc& sc, double* lds) {
   constexpr int DO = ndots_out<KIND>();
+  static_assert(DO <= 2, "passes with three slots run only as multi-work-group passes");
   const int grp = threadIdx.x >> 8;
   const int T = a.g.tiles;
   // every group runs the same number of tile iterations (barrier balance)
@@ -2172,6 +2338,7 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
                                           double* lds, int rev) {
   constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
   constexpr int DO = (KIND == K_FINAL) ? 0 : ndots_out<KIND>();
+  static_assert(DO <= 2, "passes with three slots run only as multi-work-group passes");
   const int T = S.g.tiles;
   double sum[2] = {0.0, 0.0};
   if constexpr (DI > 0) {
@@ -2391,6 +2558,22 @@ hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, 
 
 // ---------------------------------------------------------------- launchers --
 
+template <bool PIPE>
+static hipError_t launch_cheb(const PassArgs& a, int grid, hipStream_t st) {
+  const dim3 G(grid), B(kChebThreads);
+  switch (a.cheb_s) {
+    case 1: hipLaunchKernelGGL((k_cheb<1, PIPE>), G, B, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_cheb<2, PIPE>), G, B, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_cheb<3, PIPE>), G, B, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_cheb<4, PIPE>), G, B, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_cheb<5, PIPE>), G, B, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_cheb<6, PIPE>), G, B, 0, st, a); break;
+    case 7: hipLaunchKernelGGL((k_cheb<7, PIPE>), G, B, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_cheb<8, PIPE>), G, B, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
 template <int KIND>
 static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_t st) {
   if (fp32g) hipLaunchKernelGGL((k_pass<KIND, 4>), dim3(grid), dim3(kGroup), 0, st, a);
@@ -2430,16 +2613,20 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
       if (fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.z || !a.r ||
           a.cheb_rows < 1)
         return hipErrorInvalidValue;
-      switch (a.cheb_s) {
-        case 1: hipLaunchKernelGGL(k_cheb<1>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 2: hipLaunchKernelGGL(k_cheb<2>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 3: hipLaunchKernelGGL(k_cheb<3>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 4: hipLaunchKernelGGL(k_cheb<4>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 5: hipLaunchKernelGGL(k_cheb<5>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 6: hipLaunchKernelGGL(k_cheb<6>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        case 7: hipLaunchKernelGGL(k_cheb<7>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_cheb<8>, dim3(grid), dim3(kChebThreads), 0, st, a); break;
-      }
+      return launch_cheb<false>(a, grid, st);
+    case K_CHEBW:
+      if (fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.z || !a.r ||
+          a.cheb_rows < 1)
+        return hipErrorInvalidValue;
+      return launch_cheb<true>(a, grid, st);
+    case K_INIT_WU:
+      if (fp32g || !a.uu || !a.wv || !a.r) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_pass<K_INIT_WU, 2>), dim3(grid), dim3(kGroup), 0, st, a);
+      return hipGetLastError();
+    case K_PPCG:
+      if (fp32g || !a.uu || !a.wv || !a.mv || !a.sv || !a.r || !a.x || !a.z || !a.q || !a.p)
+        return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_pass<K_PPCG, 2>), dim3(grid), dim3(kGroup), 0, st, a);
       return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
@@ -2492,7 +2679,8 @@ static int occ() {
 template <int S>
 static int occ_cheb() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cheb<S>, kChebThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cheb<S, false>, kChebThreads, 0) !=
+      hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
@@ -2514,6 +2702,7 @@ int pass_max_blocks_per_cu(int kind, int fp32g) {
   switch (kind) {
     case K_PCG:
     case K_PCGX: return fp32g ? occ<K_PCGX, 4>() : occ<K_PCGX, 2>();
+    case K_PPCG: return occ<K_PPCG, 2>();
     case K_CG1: return fp32g ? occ<K_CG1, 4>() : occ<K_CG1, 2>();
     case K_CG2:
     case K_CG2X: return fp32g ? occ<K_CG2X, 4>() : occ<K_CG2X, 2>();
@@ -2545,6 +2734,9 @@ size_t pass_algorithmic_bytes(int kind, int64_t dof) {
     case K_APPLY: per = 8 * 2; break;
     case K_DOT: per = 8 * 2; break;
     case K_CHEB: per = 8 * 2; break;            // read r; write z (halo not counted)
+    case K_CHEBW: per = 8 * 2; break;           // read w; write m
+    case K_INIT_WU: per = 8 * 3; break;         // read u, r; write w
+    case K_PPCG: per = 8 * 17; break;           // read m x r u w z q s p; write all but m
   }
   return per * (size_t)dof;
 }

@@ -60,12 +60,15 @@ int validate(const cg_problem* p) {
     return CG_E_INVALID;
   if (p->precision == CG_PREC_FIXED && !fixed_fits(p->nx, p->ny)) return CG_E_INVALID;
   if (p->precond < 0 || p->precond > kChebMaxSteps) return CG_E_INVALID;
-  if (p->precond > 0 &&
-      (p->precision != CG_PREC_FP64 || p->variant != CG_VARIANT_CLASSIC))
-    return CG_E_INVALID;
+  if (p->precond > 0 && p->precision != CG_PREC_FP64) return CG_E_INVALID;
   if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
     return CG_E_INVALID;
   return CG_OK;
+}
+
+// Partial slots per tile the passes of a solve write at most.
+static int ndots_max(const cg_problem* p) {
+  return p->precond > 0 && p->variant == CG_VARIANT_PIPELINED ? 3 : 2;
 }
 
 Geo make_geo(int nx, int ny, int fp32g, int rows) {
@@ -157,7 +160,9 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   } else if (grid > 0) {
     pl.grid = std::max(8, (int)round_up((size_t)grid, 8));
   } else {
-    const int kind = pl.refined ? K_CG2F : (p->variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
+    const int kind = pl.refined ? K_CG2F
+                     : p->variant == CG_VARIANT_PIPELINED ? (pl.precond ? K_PPCG : K_PCG)
+                                                          : K_CG2;
     int cap = std::max(8, pass_max_blocks_per_cu(kind, pl.fp32g) * num_cu);
     // The pipelined pass streams best with few work-groups walking several
     // tiles each once its vectors outgrow the caches: measured per-iteration
@@ -182,7 +187,8 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     n64 = 2;  // b, x
     n32 = 4;  // rho, d, p, p'
   } else if (p->variant == CG_VARIANT_PIPELINED) {
-    n64 = 8;  // b, x, r, w, w', z, q, p
+    // b, x, r, w, w', z, q, p; preconditioned: b, x, r, u, w, m, z, q, s, p
+    n64 = pl.precond ? 10 : 8;
   } else {
     n64 = pl.precond ? 6 : 5;  // b, x, r, p, p' (and z)
   }
@@ -200,7 +206,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     pl.cheb_tiles = pl.g.ntx * ntyc;
     pl.cheb_grid = (int)round_up((size_t)std::min(ngx * ntyc, slots), 8);
   }
-  pl.part = round_up((size_t)2 * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
+  pl.part = round_up((size_t)ndots_max(p) * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
   pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
                  (pl.precond ? 256 : 0);
   return pl;
@@ -213,9 +219,11 @@ size_t footprint_of(const cg_problem* p) {
   Geo g = make_geo(p->nx, p->ny, fp32g, 1);
   const size_t elems = (size_t)g.pitch * p->ny;
   const size_t v64 = round_up(elems * 8, Arena::kAlign), v32 = round_up(elems * 4, Arena::kAlign);
-  size_t n64 = fp32g ? 2 : (p->variant == CG_VARIANT_PIPELINED ? 8 : (p->precond ? 6 : 5));
+  size_t n64 = fp32g ? 2
+               : p->variant == CG_VARIANT_PIPELINED ? (p->precond ? 10 : 8)
+                                                    : (p->precond ? 6 : 5);
   size_t n32 = fp32g ? 4 : 0;
-  const size_t part = round_up((size_t)2 * g.tiles * 8, Arena::kAlign);
+  const size_t part = round_up((size_t)ndots_max(p) * g.tiles * 8, Arena::kAlign);
   return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256) +
          (p->precond ? 256 : 0);
 }
@@ -267,6 +275,9 @@ static const char* kind_name(int kind, int fp32g) {
     case K_CG2FX: return "update_norm_f32";
     case K_REF_UPDATE: return "ref_update";
     case K_CHEB: return "cheb_precond";
+    case K_CHEBW: return "cheb_precond_w";
+    case K_INIT_WU: return "init_wu";
+    case K_PPCG: return "ppcg_pass";
     case K_APPLY: return "apply";
     case K_DOT: return "dot";
   }
@@ -310,7 +321,14 @@ bool carve(Ctx& c, Work& w) {
   } else if (pl.variant == CG_VARIANT_PIPELINED) {
     w.r = (double*)take(pl.v64);
     w.w[0] = (double*)take(pl.v64);
-    w.w[1] = (double*)take(pl.v64);
+    if (pl.precond) {
+      w.u = (double*)take(pl.v64);
+      w.mv = (double*)take(pl.v64);
+      w.sv = (double*)take(pl.v64);
+      w.cheb = (double*)take(256);
+    } else {
+      w.w[1] = (double*)take(pl.v64);
+    }
     w.z = (double*)take(pl.v64);
     w.q = (double*)take(pl.v64);
     w.p = (double*)take(pl.v64);
@@ -342,6 +360,10 @@ static PassArgs base_args(const Work& w) {
   a.p = w.p;
   a.rf = w.rf;
   a.df = w.df;
+  a.uu = w.u;
+  a.sv = w.sv;
+  a.mv = w.mv;
+  a.wv = w.w[0];
   return a;
 }
 
@@ -357,7 +379,8 @@ static hipError_t issue(Ctx& c, Work& w, int kind, F mod) {
   a.rev = w.m & 1;
   mod(a);
   w.m++;
-  return c.pass(kind, w.pl.fp32g, a, kind == K_CHEB ? w.pl.cheb_grid : w.pl.grid, w.check);
+  const int grid = (kind == K_CHEB || kind == K_CHEBW) ? w.pl.cheb_grid : w.pl.grid;
+  return c.pass(kind, w.pl.fp32g, a, grid, w.check);
 }
 
 static hipError_t issue_iteration(Ctx& c, Work& w) {
@@ -373,6 +396,16 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
         a.pf_in = w.pf[(i + 1) & 1];
         a.pf_prev = w.pf[i & 1];
       });
+  } else if (w.pl.variant == CG_VARIANT_PIPELINED && w.pl.precond) {
+    // preconditioned: the scalar step and m = M^-1 w, then the fused pass
+    e = issue(c, w, K_CHEBW, [&](PassArgs& a) {
+      a.r = w.w[0];  // input of the Chebyshev pass
+      a.z = w.mv;    // its output
+      a.cheb = w.cheb;
+      a.cheb_s = w.pl.precond;
+      a.cheb_rows = w.pl.cheb_rows;
+    });
+    if (e == hipSuccess) e = issue(c, w, K_PPCG, [](PassArgs&) {});
   } else if (w.pl.variant == CG_VARIANT_PIPELINED) {
     // iteration i + 1 of the solve: an even one also brings x up to date
     e = issue(c, w, (i & 1) ? K_PCGX : K_PCG, [&](PassArgs& a) {
@@ -462,9 +495,10 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     it = c.graphs.emplace(key, ge).first;
   }
   HIPCHK(hipGraphLaunch(it->second, c.st));
-  w.m += iters * (w.pl.variant == CG_VARIANT_PIPELINED && !w.pl.refined ? 1
-                  : w.pl.precond                                          ? 3
-                                                                          : 2);
+  w.m += iters * (w.pl.variant == CG_VARIANT_PIPELINED && !w.pl.refined
+                      ? (w.pl.precond ? 2 : 1)
+                  : w.pl.precond ? 3
+                                 : 2);
   w.i += iters;
   return CG_OK;
 }
@@ -608,8 +642,18 @@ static int solve_tiled(Ctx& c, Work& w, const cg_problem* p, State& s) {
     return CG_OK;
   }
   HIPCHK(issue(c, w, K_INIT_R, [](PassArgs&) {}));
-  if (w.pl.variant == CG_VARIANT_PIPELINED)
+  if (w.pl.variant == CG_VARIANT_PIPELINED && w.pl.precond) {
+    // u = M^-1 r (with the first stop test), then w = A u and the three sums
+    HIPCHK(issue(c, w, K_CHEB, [&](PassArgs& a) {
+      a.z = w.u;
+      a.cheb = w.cheb;
+      a.cheb_s = w.pl.precond;
+      a.cheb_rows = w.pl.cheb_rows;
+    }));
+    HIPCHK(issue(c, w, K_INIT_WU, [](PassArgs&) {}));
+  } else if (w.pl.variant == CG_VARIANT_PIPELINED) {
     HIPCHK(issue(c, w, K_INIT_W, [&](PassArgs& a) { a.w_out = w.w[0]; }));
+  }
   const int K = chunk_iters(c, w);
   for (;;) {
     // never issue iterations past maxit: after maxit iterations one more

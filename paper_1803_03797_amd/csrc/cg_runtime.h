@@ -71,6 +71,7 @@ struct Work {
          *p = nullptr, *pc[2] = {};
   float *rf = nullptr, *df = nullptr, *pf[2] = {};
   double* cheb = nullptr;  // preconditioner coefficients (c0, c1[s-1], c2[s-1])
+  double *u = nullptr, *sv = nullptr, *mv = nullptr;  // preconditioned pipelined
   double* part[2] = {};
   cgk::State* S[2] = {};
   int m = 0;  // passes issued (state/partial parity)

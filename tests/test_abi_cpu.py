@@ -52,7 +52,7 @@ def _prob(**kw):
                                  dict(precision=2, nx=1, ny=6783),
                                  dict(precision=2, nx=5088, ny=1),
                                  dict(precond=-1), dict(precond=9),
-                                 dict(precond=4, variant=1), dict(precond=4, precision=1),
+                                 dict(precond=4, precision=1),
                                  dict(precond=4, precision=2)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
@@ -65,9 +65,10 @@ def test_validation_accepts():
     for nx, ny in ((1, 1), (100, 100), (98, 102), (1, 6782), (5087, 1)):
         assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
     assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
-    # Chebyshev preconditioner: 1..8 steps, classic FP64
+    # Chebyshev preconditioner: 1..8 steps, FP64, either variant
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
+        assert cg.cg_validate(_prob(precond=s, variant=1)) == cg.CG_OK
 
 
 def test_footprint_per_unknown():
