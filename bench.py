@@ -659,6 +659,8 @@ def bench_serve(args):
         rc, r = ctx.cg_solve(prob(m, x64[m], 0))
         svc[m] = time.perf_counter() - t
         ok64 += met(rc, r, m)
+        if (m + 1) % 2000 == 0:
+            log("per-request FP64: %d done" % (m + 1))
     cap64 = len(reqs) / (time.perf_counter() - t0)
     log("per-request FP64: %.1f solves/s" % cap64)
 
@@ -687,14 +689,25 @@ def bench_serve(args):
 
         th = threading.Thread(target=submitter)
         th.start()
+        pending, nxt, shown = [], 0, 0
         while len(results) < len(reqs):
-            for m in range(len(reqs)):
-                if m in results or tickets[m] is None:
-                    continue
+            # poll only the submitted, unfinished tickets (latency is stamped
+            # by the server at completion, so the sweep period does not enter it)
+            while nxt < len(reqs) and tickets[nxt] is not None:
+                pending.append(nxt)
+                nxt += 1
+            still = []
+            for m in pending:
                 rc, r = ctx.cg_poll(tickets[m])
                 if rc != cg.CG_PENDING:
                     results[m] = (rc, cg.cg_result.from_buffer_copy(r), time.perf_counter() - start)
-            time.sleep(0.0005)
+                else:
+                    still.append(m)
+            pending = still
+            if len(results) >= shown + 2000:
+                shown = len(results) // 2000 * 2000
+                log("served: %d done" % len(results))
+            time.sleep(0.002 if len(reqs) > 1000 else 0.0005)
         th.join()
         makespan = max(v[2] for v in results.values())
         lat = np.array([results[m][1].latency_seconds for m in range(len(reqs))])
