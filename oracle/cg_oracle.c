@@ -20,7 +20,9 @@
  *     alpha_i = 1 / (delta_i/gamma_i - beta_i/alpha_{i-1});
  *   - FP32-inner / FP64-outer iterative refinement around classic CG;
  *   - classic CG preconditioned by a Chebyshev polynomial in A (the M^-1 that
- *     the pipelined-CG literature the paper builds on carries).
+ *     the pipelined-CG literature the paper builds on carries);
+ *   - both CG variants on the 3D 7-point Laplacian (oracle_cg3), the next
+ *     structured-grid finite-difference system after the paper's 2D one.
  *
  * Unknown (i, j), 0 <= i < nx, 0 <= j < ny, has index k = j*nx + i.
  * Build with -O2 -ffp-contract=off (no fast-math): every operation below is
@@ -537,6 +539,102 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
   memset(res, 0, sizeof(*res));
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, hist)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, hist);
+  csr_free(&A);
+  return rc;
+}
+
+/* ------------------------------------------------ 3D 7-point Laplacian -- */
+
+/* The unscaled 7-point Laplacian on an nx-by-ny-by-nz interior grid with zero
+ * Dirichlet boundary: centre 6, the six face neighbours -1.  Unknown (i, j, l),
+ * 0 <= i < nx, 0 <= j < ny, 0 <= l < nz, has index k = (l*ny + j)*nx + i: nz
+ * planes of ny rows, i.e. ny*nz rows of nx, on which every dot product of the
+ * 2D case (and its canonical orders) applies unchanged. */
+int64_t oracle_csr3_nnz(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  const int64_t n = (int64_t)nx * ny * nz;
+  return n + 2 * (int64_t)(nx - 1) * ny * nz + 2 * (int64_t)nx * (ny - 1) * nz +
+         2 * (int64_t)nx * ny * (nz - 1);
+}
+
+/* order 0: entries of a row sorted by column.  order 1: centre, west (i-1),
+ * east (i+1), south (j-1), north (j+1), below (l-1), above (l+1), so that the
+ * CSR loop evaluates (((((6uC - uW) - uE) - uS) - uN) - uB) - uT. */
+int64_t oracle_csr3_assemble(int32_t nx, int32_t ny, int32_t nz, int32_t order,
+                             int64_t* row_ptr, int32_t* col, double* val) {
+  if (nx < 1 || ny < 1 || nz < 1) return OR_E_INVALID;
+  const int64_t plane = (int64_t)nx * ny;
+  int64_t e = 0;
+  for (int32_t l = 0; l < nz; ++l) {
+    for (int32_t j = 0; j < ny; ++j) {
+      for (int32_t i = 0; i < nx; ++i) {
+        const int64_t k = l * plane + (int64_t)j * nx + i;
+        row_ptr[k] = e;
+        if (order == 0) {
+          if (l > 0)      { col[e] = (int32_t)(k - plane); val[e++] = -1.0; }
+          if (j > 0)      { col[e] = (int32_t)(k - nx);    val[e++] = -1.0; }
+          if (i > 0)      { col[e] = (int32_t)(k - 1);     val[e++] = -1.0; }
+          col[e] = (int32_t)k; val[e++] = 6.0;
+          if (i < nx - 1) { col[e] = (int32_t)(k + 1);     val[e++] = -1.0; }
+          if (j < ny - 1) { col[e] = (int32_t)(k + nx);    val[e++] = -1.0; }
+          if (l < nz - 1) { col[e] = (int32_t)(k + plane); val[e++] = -1.0; }
+        } else {
+          col[e] = (int32_t)k; val[e++] = 6.0;
+          if (i > 0)      { col[e] = (int32_t)(k - 1);     val[e++] = -1.0; }
+          if (i < nx - 1) { col[e] = (int32_t)(k + 1);     val[e++] = -1.0; }
+          if (j > 0)      { col[e] = (int32_t)(k - nx);    val[e++] = -1.0; }
+          if (j < ny - 1) { col[e] = (int32_t)(k + nx);    val[e++] = -1.0; }
+          if (l > 0)      { col[e] = (int32_t)(k - plane); val[e++] = -1.0; }
+          if (l < nz - 1) { col[e] = (int32_t)(k + plane); val[e++] = -1.0; }
+        }
+      }
+    }
+  }
+  row_ptr[plane * nz] = e;
+  return e;
+}
+
+static int csr3_build(csr_t* A, int32_t nx, int32_t ny, int32_t nz, int32_t order) {
+  memset(A, 0, sizeof(*A));
+  const int64_t nnz = oracle_csr3_nnz(nx, ny, nz);
+  if (nnz < 0 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31)) return OR_E_INVALID;
+  A->nx = nx; A->ny = ny * nz; A->n = (int64_t)nx * ny * nz;
+  A->row_ptr = (int64_t*)malloc((size_t)(A->n + 1) * sizeof(int64_t));
+  A->col = (int32_t*)malloc((size_t)nnz * sizeof(int32_t));
+  A->val = (double*)malloc((size_t)nnz * sizeof(double));
+  if (!A->row_ptr || !A->col || !A->val) { csr_free(A); return OR_E_NOMEM; }
+  oracle_csr3_assemble(nx, ny, nz, order, A->row_ptr, A->col, A->val);
+  return OR_OK;
+}
+
+int oracle_spmv3(int32_t nx, int32_t ny, int32_t nz, int32_t order, const double* u,
+                 double* y) {
+  csr_t A;
+  int rc = csr3_build(&A, nx, ny, nz, order);
+  if (rc) return rc;
+  spmv(&A, u, y);
+  csr_free(&A);
+  return OR_OK;
+}
+
+/* Algorithms 1 and 2 on the 7-point operator (the same loops as oracle_cg;
+ * canonical dots over the ny*nz rows of nx). */
+int oracle_cg3(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny,
+               int32_t nz, const double* b, const double* x0, double* x, double tol,
+               int32_t maxit, oracle_result* res) {
+  if (nx < 1 || ny < 1 || nz < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) ||
+      tol >= 1.0 || (variant != VARIANT_CLASSIC && variant != VARIANT_PIPELINED))
+    return OR_E_INVALID;
+  if ((int64_t)ny * nz >= ((int64_t)1 << 31)) return OR_E_INVALID;
+  const int32_t rows = ny * nz;
+  if (mode == MODE_CANONICAL && !order_valid(ord, nx, rows)) return OR_E_INVALID;
+  csr_t A;
+  int rc = csr3_build(&A, nx, ny, nz, mode == MODE_CANONICAL ? 1 : 0);
+  if (rc) return rc;
+  ctx_t c = {nx, rows, mode, ord};
+  memset(res, 0, sizeof(*res));
+  rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
+                                      : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
   csr_free(&A);
   return rc;
 }

@@ -97,6 +97,15 @@ def _load():
     lib.oracle_refine.restype = C.c_int
     lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
                                   C.c_int32, C.POINTER(_Result)]
+    lib.oracle_csr3_nnz.restype = C.c_int64
+    lib.oracle_csr3_nnz.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    lib.oracle_csr3_assemble.restype = C.c_int64
+    lib.oracle_csr3_assemble.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
+    lib.oracle_spmv3.restype = C.c_int
+    lib.oracle_spmv3.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
+    lib.oracle_cg3.restype = C.c_int
+    lib.oracle_cg3.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
+                               C.c_int32, P, P, P, C.c_double, C.c_int32, C.POINTER(_Result)]
     _lib = lib
     return lib
 
@@ -124,6 +133,48 @@ def csr(nx, ny, order=0):
     got = lib.oracle_csr_assemble(nx, ny, order, _ptr(rp), _ptr(col), _ptr(val))
     assert got == nnz
     return rp, col, val
+
+
+def csr3(nx, ny, nz, order=0):
+    """The 7-point matrix of an nx x ny x nz grid as (row_ptr, col, val)."""
+    lib = _load()
+    nnz = lib.oracle_csr3_nnz(nx, ny, nz)
+    if nnz < 0:
+        raise ValueError("bad grid")
+    rp = np.zeros(nx * ny * nz + 1, np.int64)
+    col = np.zeros(nnz, np.int32)
+    val = np.zeros(nnz, np.float64)
+    got = lib.oracle_csr3_assemble(nx, ny, nz, order, _ptr(rp), _ptr(col), _ptr(val))
+    assert got == nnz
+    return rp, col, val
+
+
+def spmv3(u, nx, ny, nz, order=0):
+    """A u for the 7-point operator; u has nz*ny rows of nx (any shape of that size)."""
+    u = _vec(u, nx, ny * nz)
+    y = np.zeros_like(u)
+    rc = _load().oracle_spmv3(nx, ny, nz, order, _ptr(u), _ptr(y))
+    if rc:
+        raise RuntimeError("oracle_spmv3 failed: %d" % rc)
+    return y
+
+
+def cg3(b, nx, ny, nz, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
+        mode=MODE_SEQUENTIAL, order=None):
+    """Solve the 7-point system on an nx x ny x nz grid (vectors as ny*nz rows of
+    nx; canonical orders see those rows)."""
+    b = _vec(b, nx, ny * nz)
+    x0a = _vec(x0, nx, ny * nz) if x0 is not None else None
+    x = np.zeros_like(b)
+    res = _Result()
+    o = C.byref(order) if order is not None else None
+    rc = _load().oracle_cg3(variant, mode, o, nx, ny, nz, _ptr(b), _ptr(x0a), _ptr(x), tol,
+                            maxit, C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle_cg3 rejected the call: %d" % rc)
+    return x, Result(status=res.status, iterations=res.iterations,
+                     outer_iterations=res.outer_iterations,
+                     rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
 
 
 def spmv(u, nx, ny, order=0):
