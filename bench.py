@@ -30,6 +30,8 @@ Other workloads (one JSON line each, not the headline):
                      256 solves of its largest grid in one launch
   --workload precond 4096 x 4096 to tol 1e-8: classic CG against classic CG
                      preconditioned by s Chebyshev steps (time to solution)
+  --workload cube    the 3D 7-point operator on 256^3: both variants, fixed
+                     iterations and to tol 1e-8
   --probe            attainable HBM bandwidth of plain streaming kernels, and
                      the attainable rate of 32 x 32 -> 64-bit multiply-adds
 """
@@ -550,6 +552,78 @@ def bench_precond(args):
     ctx.close()
 
 
+# ------------------------------------------------------------------------ 3d --
+
+def bench_cube(args):
+    """The 7-point operator on n^3: both variants, a fixed number of iterations
+    (throughput, per-kernel times, the pipelined pass's roofline), then each to
+    tol 1e-8."""
+    torch, cg = setup()
+    from paper_1803_03797_amd import workloads
+    w = workloads.CUBE
+    n = args.n_cube
+    dof = n ** 3
+    its = w["iterations"]
+    b = torch.from_numpy(workloads.cube_rhs(n)).cuda()
+    ctx = cg.Context(device=0, arena_bytes=64 * dof + (1 << 30))
+    x = torch.zeros_like(b)
+    out = {}
+    for v, name in ((0, "classic"), (1, "pipelined")):
+        p = cg.make_problem(b, x, n, n, tol=0.0, maxit=its, variant=v, nz=n)
+        ctx.cg_solve(p)  # warm: graphs captured
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = ctx.cg_solve(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        ctx.cg_solve(cg.make_problem(b, torch.zeros_like(b), n, n, tol=0.0, maxit=40, variant=v,
+                                     nz=n))
+        ks = kern_table(ctx.cg_kernel_stats(reset=True))
+        ctx.cg_set_profiling(False)
+        x2 = torch.zeros_like(b)
+        p2 = cg.make_problem(b, x2, n, n, tol=w["tol"], maxit=w["maxit"], variant=v, nz=n)
+        t1 = time.perf_counter()
+        rc2, r2 = ctx.cg_solve(p2)
+        dt2 = time.perf_counter() - t1
+        out[name] = dict(GDOF_iter_s=round(dof * its / dt / 1e9, 3),
+                         seconds_fixed=round(dt, 4),
+                         algorithmic_GBps=round(dof * its * BYTES_PER_ITER[name] / dt / 1e9, 1),
+                         kernels={k: vv for k, vv in ks.items() if k != "final_check"},
+                         tol_1e8=dict(status=cg.cg_status_str(rc2), iterations=r2.iterations,
+                                      seconds=round(dt2, 4), rel_res_true=r2.rel_res_true))
+        log("3d", name, json.dumps(out[name]))
+    pk = out["pipelined"]["kernels"].get("pcg_pass")
+    roof = None
+    if pk:
+        ach = BYTES_PER_DOF["pcg_pass"] * dof / (pk["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": "pcg_pass (7-point)", "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                "avg_launch_us": pk["avg_us"], "bytes_per_launch": BYTES_PER_DOF["pcg_pass"] * dof,
+                "traffic": None}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        bh = b.cpu().numpy()
+        k = 4
+        t = time.perf_counter()
+        oracle.cg3(bh, n, n, n, variant=0, tol=0.0, maxit=k)
+        ct = time.perf_counter() - t
+        cpu = {"value": round(dof * k / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "%d classic iterations of the 3D oracle at %d^3 (explicit 7-point CSR, "
+                         "single thread, %.1f s incl. assembly)" % (k, n, ct)}
+    value = (out["classic"]["GDOF_iter_s"] + out["pipelined"]["GDOF_iter_s"]) / 2
+    emit({"metric": "CG GDOF-iter/s, 3D 7-point Laplacian %d^3 FP64 (classic + pipelined, %d "
+                    "iterations each)" % (n, its),
+          "workload": "cube", "value": round(value, 3), "unit": "GDOF-iter/s",
+          "config": {"workload": "%d^3 7-point Laplacian, b~U[-1,1] seeded, x0=0; fixed %d "
+                                 "iterations, then tol 1e-8" % (n, its)},
+          "dtype": "f64", "results": out, "roofline": roof, "cpu_baseline": cpu})
+    ctx.close()
+
+
 # ---------------------------------------------------------------------- huge --
 
 def bench_huge(args):
@@ -790,7 +864,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=48)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
-    ap.add_argument("--workload", choices=["small", "batch", "huge", "serve", "fixed", "precond"])
+    ap.add_argument("--workload",
+                    choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube"])
+    ap.add_argument("--n-cube", type=int, default=256, help="--workload cube: grid side")
     ap.add_argument("--huge-precond", type=int, default=8,
                     help="--workload huge: also solve with s Chebyshev steps (0: skip)")
     ap.add_argument("--steps-list", type=int, nargs="*", default=[2, 4, 6, 8],
@@ -822,6 +898,8 @@ def main():
         return bench_fixed(args)
     if args.workload == "precond":
         return bench_precond(args)
+    if args.workload == "cube":
+        return bench_cube(args)
     if args.workload == "serve":
         args.count = args.count or 400
         return bench_serve(args)

@@ -108,7 +108,14 @@ typedef struct {
                               Ghysels and Vanroose (variant PIPELINED); the stop
                               test stays on ||r||; cg_solve only (batches and
                               serving reject it)                                   */
-  int32_t pad_;
+  int32_t nz;              /* 0 or 1: the 2D problem above.  nz > 1: the 3D 7-point
+                              Laplacian (centre 6, the six face neighbours -1) on an
+                              nx x ny x nz interior grid with zero Dirichlet
+                              boundary, the next structured-grid case the paper's
+                              Section I names; unknown (i, j, l) at (l ny + j) nx + i,
+                              so b, x0 and x hold nx * ny * nz values; FP64, either
+                              variant, precond 0, cg_solve only (batches and serving
+                              reject it)                                            */
 } cg_problem;
 
 typedef struct {

@@ -31,7 +31,7 @@ class cg_problem(C.Structure):
                 ("b", C.c_void_p), ("x0", C.c_void_p), ("x", C.c_void_p),
                 ("tol", C.c_double), ("maxit", C.c_int32), ("variant", C.c_int32),
                 ("precision", C.c_int32), ("inner_tol", C.c_double),
-                ("precond", C.c_int32), ("pad_", C.c_int32)]
+                ("precond", C.c_int32), ("nz", C.c_int32)]
 
 
 class cg_result(C.Structure):
@@ -144,17 +144,19 @@ def _ptr_mem(a):
 
 
 def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
-                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0):
+                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0, nz=0):
+    """nz > 1: the 3D 7-point problem on nx x ny x nz (vectors of nx*ny*nz)."""
     pb, mb = _ptr_mem(b)
     px, mx = _ptr_mem(x)
     p0, m0 = _ptr_mem(x0)
     if mb != mx or (m0 is not None and m0 != mb):
         raise ValueError("b, x and x0 must live in the same memory space")
+    n = nx * ny * max(nz, 1)
     for v in (b, x, x0):
-        if v is not None and (v.size if isinstance(v, np.ndarray) else v.numel()) != nx * ny:
-            raise ValueError("vector size does not match the %dx%d grid" % (nx, ny))
+        if v is not None and (v.size if isinstance(v, np.ndarray) else v.numel()) != n:
+            raise ValueError("vector size does not match the %dx%dx%d grid" % (nx, ny, max(nz, 1)))
     p = cg_problem(nx, ny, mb, pb, p0, px, float(tol), int(maxit), int(variant),
-                   int(precision), float(inner_tol), int(precond), 0)
+                   int(precision), float(inner_tol), int(precond), int(nz))
     return p
 
 
@@ -242,9 +244,10 @@ class Context:
         _check("cg_dot", self.lib.cg_dot(self.h, nx, ny, ma, pa, pb, C.byref(out)))
         return out.value
 
-    def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64, precond=0):
+    def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64, precond=0,
+                nz=0):
         p = cg_problem(nx, ny, CG_MEM_DEVICE, None, None, None, 1e-8, 1, variant, precision, 0.0,
-                       precond, 0)
+                       precond, nz)
         info = cg_plan_info()
         _check("cg_plan", self.lib.cg_plan(self.h, C.byref(p), C.byref(info)))
         return info

@@ -56,7 +56,8 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
   for (int32_t i = 0; i < n; ++i) {
     int rc = cgr::validate(&probs[i]);
     if (rc) return rc;
-    if (probs[i].precond) return CG_E_INVALID;  // preconditioned: cg_solve only
+    // preconditioned and 3D problems: cg_solve only
+    if (probs[i].precond || probs[i].nz > 1) return CG_E_INVALID;
   }
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -68,7 +69,7 @@ int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
   if (!ctx || !ticket) return CG_E_INVALID;
   int rc = cgr::validate(prob);
   if (rc) return rc;
-  if (prob->precond) return CG_E_INVALID;  // preconditioned: cg_solve only
+  if (prob->precond || prob->nz > 1) return CG_E_INVALID;  // cg_solve only
   return cgr_server_submit(C(ctx), prob, ticket);
 }
 
@@ -114,7 +115,7 @@ int cg_dot(cg_ctx* ctx, int32_t nx, int32_t ny, cg_memspace mem, const double* a
 
 int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   if (!ctx || !info) return CG_E_INVALID;
-  if (!prob || prob->nx < 1 || prob->ny < 1) return CG_E_INVALID;
+  if (!prob || prob->nx < 1 || prob->ny < 1 || prob->nz < 0) return CG_E_INVALID;
   if (prob->precision == CG_PREC_FIXED && !cgk::fixed_fits(prob->nx, prob->ny))
     return CG_E_INVALID;
   Ctx* c = C(ctx);

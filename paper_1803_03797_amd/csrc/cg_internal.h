@@ -78,6 +78,8 @@ struct Geo {
   int32_t ntx, nty, tiles;
   int32_t rows;      // rows per wavefront strip
   int32_t th;        // rows per tile = 4 * rows
+  int32_t plane;     // 3D (7-point operator): rows per plane, ny = plane * nz; 2D: 0
+  int32_t pad_;
 };
 
 // Pass kinds.

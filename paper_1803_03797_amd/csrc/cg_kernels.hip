@@ -129,6 +129,14 @@ __device__ __forceinline__ T st5(T c, T w, T e, T s, T n) {
   return (((T(4) * c - w) - e) - s) - n;
 }
 
+// The 7-point operator in 3D: (((((6 uC - uW) - uE) - uS) - uN) - uB) - uT,
+// B = plane l-1, T = plane l+1; stn picks it or the 5-point one.
+template <bool D3, typename T>
+__device__ __forceinline__ T stn(T c, T w, T e, T s, T n, T b, T t) {
+  if constexpr (D3) return (((((T(6) * c - w) - e) - s) - n) - b) - t;
+  else return st5(c, w, e, s, n);
+}
+
 // Reads a State every lane needs with the same value into scalar registers
 // (readfirstlane), so the solve's scalars do not hold vector registers (which
 // the compiler would otherwise spill across the prologue's barriers).
@@ -656,8 +664,15 @@ __device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
 //   emake(raw) -> H just outside the tile for lanes 0 / 63 (zero elsewhere)
 //   point(off) -> Bundle: the point-wise operands of that row
 //   comp(off, S, C, N, W, E, bundle): row j's arithmetic and stores
-template <typename T, int CPL, int PD, class HLoad, class HMake, class ELoad, class EMake,
-          class Point, class Comp>
+//
+// D3 (the 7-point operator of an nx x (ny / plane) x ... grid stored as
+// g.ny rows of nx, g.plane rows per plane): the walker also loads the halo
+// vector one plane below and above each row (raw, PD rows ahead with the point
+// data) and hands comp hS / hN zeroed at the plane's first / last row, and the
+// rows below / above (zero outside the grid).  In 2D those are zero rows.
+//   comp(off, S, C, N, W, E, below, above, bundle)
+template <typename T, int CPL, int PD, bool D3, class HLoad, class HMake, class ELoad,
+          class EMake, class Point, class Comp>
 __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
                                      ELoad eload, EMake emake, Point point, Comp comp) {
   using R = Row<T, CPL>;
@@ -668,6 +683,12 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
   const size_t P = g.pitch;
   const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
   const size_t o0 = (size_t)s.j0 * P;
+  // 3D: rows j - plane and j + plane (clamped into the grid for the load)
+  const int pl = D3 ? g.plane : 0;
+  auto boff = [&](int r) { return (size_t)max(r - pl, 0) * P; };
+  auto toff = [&](int r) { return (size_t)min(r + pl, g.ny - 1) * P; };
+  RawH qb[D3 ? PD : 1], qt[D3 ? PD : 1];
+  int jp = D3 ? s.j0 % pl : 0;  // row within its plane
   R hS = zrow<T, CPL>();
   {
     const R v = hmake(hload((size_t)max(s.j0 - 1, 0) * P));
@@ -686,7 +707,12 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
     const size_t ro = (size_t)min(r, hmax) * P;
     q[k] = hload(ro);
     qe[k] = eload(ro);
-    pt[k] = point((size_t)min(s.j0 + k, s.j1 - 1) * P);
+    const int rp = min(s.j0 + k, s.j1 - 1);
+    pt[k] = point((size_t)rp * P);
+    if constexpr (D3) {
+      qb[k] = hload(boff(rp));
+      qt[k] = hload(toff(rp));
+    }
   }
   size_t o = o0;
   for (int j = s.j0; j < s.j1; ++j, o += P) {
@@ -696,7 +722,13 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
     const size_t ho = (size_t)min(rh, hmax) * P;
     const RawH hn = hload(ho);
     const RawE en = eload(ho);
-    const B pn = point((size_t)min(j + PD, s.j1 - 1) * P);
+    const int rp = min(j + PD, s.j1 - 1);
+    const B pn = point((size_t)rp * P);
+    RawH bn, tn;
+    if constexpr (D3) {
+      bn = hload(boff(rp));
+      tn = hload(toff(rp));
+    }
     // row j+1 enters the window
     R hN = hmake(q[0]);
     T eN = emake(qe[0]);
@@ -706,7 +738,18 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
     }
     R W, E;
     west_east<T, CPL>(hC, eC, eC, W, E);
-    comp(o, hS, hC, hN, W, E, pt[0]);
+    if constexpr (D3) {
+      // in-plane neighbours stop at the plane's edges; the planes below and
+      // above exist for j >= plane and j + plane < ny
+      const R zr = zrow<T, CPL>();
+      const R Bl = j >= pl ? hmake(qb[0]) : zr;
+      const R Ab = j + pl < g.ny ? hmake(qt[0]) : zr;
+      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, pt[0]);
+      if (++jp == pl) jp = 0;
+    } else {
+      const R zr = zrow<T, CPL>();
+      comp(o, hS, hC, hN, W, E, zr, zr, pt[0]);
+    }
     hS = hC;
     hC = hN;
     eC = eN;
@@ -716,11 +759,19 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qe[k] = qe[k + 1];
       qv[k] = qv[k + 1];
       pt[k] = pt[k + 1];
+      if constexpr (D3) {
+        qb[k] = qb[k + 1];
+        qt[k] = qt[k + 1];
+      }
     }
     q[PD - 1] = hn;
     qe[PD - 1] = en;
     qv[PD - 1] = nv;
     pt[PD - 1] = pn;
+    if constexpr (D3) {
+      qb[PD - 1] = bn;
+      qt[PD - 1] = tn;
+    }
   }
 }
 
@@ -729,12 +780,12 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #endif
 
 // Loaders for a halo vector that is stored as is.
-template <typename T, int CPL, class Point, class Comp>
+template <typename T, int CPL, bool D3, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
   const int c = s.c;
-  walk<T, CPL, 1>(
+  walk<T, CPL, 1, D3>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
       [=](T v) { return ea.emask ? v : T(0); }, point, comp);
@@ -744,7 +795,7 @@ struct Empty {};
 
 // --- K_INIT_R: r = b - A x; slots (r,r), (b,b)
 // --- K_RESID:  t = b - A x; slots (t,t), (b,b)   (no store)
-template <int CPL, bool STORE>
+template <int CPL, bool STORE, bool D3 = false>
 __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -755,14 +806,14 @@ __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* 
   const int valid = g.nx - s.c;
   const double* B = a.b;
   double* Rr = a.r;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const R& bb) {
         R res;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          res.e[k] = bb.e[k] - st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          res.e[k] = bb.e[k] - stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (k < valid) {
             a0[k] = fma(res.e[k], res.e[k], a0[k]);
             a1[k] = fma(bb.e[k], bb.e[k], a1[k]);
@@ -776,7 +827,7 @@ __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* 
 
 // --- K_INIT_W: w = A r; slots (r,r), (w,r)
 // --- K_APPLY:  y = A u; no slots
-template <int CPL, bool INITW>
+template <int CPL, bool INITW, bool D3 = false>
 __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -787,14 +838,14 @@ __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv)
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, U, [](size_t) { return Empty{}; },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const Empty&) {
         R out;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          out.e[k] = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          out.e[k] = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (INITW && k < valid) {
             a0[k] = fma(hC.e[k], hC.e[k], a0[k]);
             a1[k] = fma(out.e[k], hC.e[k], a1[k]);
@@ -835,7 +886,7 @@ struct PcgRow {
   Row<double, CPL> x, r, z, q, p;
 };
 
-template <int CPL, bool XU>
+template <int CPL, bool XU, bool D3 = false>
 __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -847,7 +898,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
@@ -860,12 +911,12 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
         v.p = ldrow<double, CPL>(Pp + oc);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const PcgRow<CPL>& in) {
         R x = in.x, r = in.r, z, q, p, wo;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double nv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          const double nv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (first) {
             z.e[k] = nv;
             q.e[k] = hC.e[k];
@@ -898,7 +949,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
 }
 
 // --- K_INIT_WU: w = A u; slots (r,u), (w,u), (r,r)   [preconditioned pipelined]
-template <int CPL>
+template <int CPL, bool D3 = false>
 __device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -909,14 +960,14 @@ __device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* l
   const int valid = g.nx - s.c;
   const double* Rv = a.r;
   double* Wv = a.wv;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, a.uu, [=](size_t off) { return ldrow<double, CPL>(Rv + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const R& r) {
         R out;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          out.e[k] = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          out.e[k] = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (k < valid) {
             a0[k] = fma(r.e[k], hC.e[k], a0[k]);
             a1[k] = fma(out.e[k], hC.e[k], a1[k]);
@@ -940,7 +991,7 @@ struct PpcgRow {
   Row<double, CPL> x, r, u, w, z, q, s, p;
 };
 
-template <int CPL>
+template <int CPL, bool D3 = false>
 __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -952,7 +1003,7 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = a2[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *U = a.uu, *Wv = a.wv, *Z = a.z, *Q = a.q, *Sv = a.sv, *Pp = a.p;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, a.mv,
       [=](size_t off) {
         PpcgRow<CPL> v;
@@ -968,12 +1019,12 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
         v.p = ldrow<double, CPL>(Pp + oc);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const PpcgRow<CPL>& in) {
         R x = in.x, r = in.r, u = in.u, w = in.w, z, q, sv, p;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double nv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          const double nv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (first) {
             z.e[k] = nv;
             q.e[k] = hC.e[k];
@@ -1012,7 +1063,7 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
 
 // --- K_CG1 / K_CG1F: p = r + beta p_old (on tile + halo); s = A p; store p;
 //     slot (p, s).  First iteration: p = r.
-template <typename T, int CPL>
+template <typename T, int CPL, bool D3 = false>
 __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<T, CPL>;
   const Geo& g = a.g;
@@ -1044,7 +1095,7 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
     T r, po;
   };
   const EdgeAddr ea = edge_addr<CPL>(s, g);
-  walk<T, CPL, CG1_PREFETCH>(
+  walk<T, CPL, CG1_PREFETCH, D3>(
       g, s,
       [=](size_t off) {
         Raw v;
@@ -1066,11 +1117,11 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
       },
       [=](const RawE& v) { return ea.emask ? (first ? v.r : fma(be, v.po, v.r)) : T(0); },
       [](size_t) { return Empty{}; },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const Empty&) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const T sv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          const T sv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if (k < valid) a0[k] = fma((double)hC.e[k], (double)sv, a0[k]);
         }
         strow<T, CPL>(Pn + off + s.c, hC, valid);
@@ -1087,7 +1138,7 @@ struct XrRow {
   Row<T, CPL> x, r, pp;
 };
 
-template <typename T, int CPL, int XM>
+template <typename T, int CPL, int XM, bool D3 = false>
 __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<T, CPL>;
   using In = XrRow<T, CPL, XM>;
@@ -1113,7 +1164,7 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk_plain<T, CPL>(
+  walk_plain<T, CPL, D3>(
       g, s, Pv,
       [=](size_t off) {
         In v;
@@ -1122,12 +1173,12 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
         v.r = ldrow<T, CPL>(Rv + off + s.c);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const In& in) {
         R x = in.x, r = in.r;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const T sv = st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          const T sv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           if constexpr (XM == 1) x.e[k] = fma(al, hC.e[k], x.e[k]);
           if constexpr (XM == 2) x.e[k] = fma(al, hC.e[k], fma(alp, in.pp.e[k], x.e[k]));
           r.e[k] = fma(nal, sv, r.e[k]);
@@ -1199,7 +1250,7 @@ __device__ __forceinline__ void run_flush(const PassArgs& a, int t, const Sc& sc
 }
 
 // --- K_REF_SCALE: rho = fp32((b - A x) * inv); d = 0; slot (rho, rho) in FP64.
-template <int CPL>
+template <int CPL, bool D3 = false>
 __device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const Sc& sc,
                                                double* lv) {
   using R = Row<double, CPL>;
@@ -1213,14 +1264,14 @@ __device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const S
   const int valid = g.nx - s.c;
   const double* B = a.b;
   float *Rf = a.rf, *Df = a.df;
-  walk_plain<double, CPL>(
+  walk_plain<double, CPL, D3>(
       g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
           const R& bb) {
         RF rho;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double res = bb.e[k] - st5(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k]);
+          const double res = bb.e[k] - stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
           rho.e[k] = (float)(res * inv);
           if (k < valid) a0[k] = fma((double)rho.e[k], (double)rho.e[k], a0[k]);
         }
@@ -1247,8 +1298,26 @@ __device__ __forceinline__ void body_ref_update(const PassArgs& a, int t, const 
   }
 }
 
-template <int KIND, int CPL>
+// D3: the 7-point operator (multi-work-group passes of the FP64 kinds only).
+template <int KIND, int CPL, bool D3 = false>
 __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc, double* lv) {
+  static_assert(!D3 || KIND == K_INIT_R || KIND == K_RESID || KIND == K_INIT_W ||
+                    KIND == K_APPLY || KIND == K_DOT || KIND == K_PCG || KIND == K_PCGX ||
+                    KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X,
+                "no 3D form of this pass");
+  if constexpr (D3) {
+    if constexpr (KIND == K_INIT_R) body_residual<CPL, true, true>(a, t, lv);
+    else if constexpr (KIND == K_RESID) body_residual<CPL, false, true>(a, t, lv);
+    else if constexpr (KIND == K_INIT_W) body_apply<CPL, true, true>(a, t, lv);
+    else if constexpr (KIND == K_APPLY) body_apply<CPL, false, true>(a, t, lv);
+    else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
+    else if constexpr (KIND == K_PCG) body_pcg<CPL, false, true>(a, t, sc, lv);
+    else if constexpr (KIND == K_PCGX) body_pcg<CPL, true, true>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG1) body_cg1<double, CPL, true>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG2) body_cg2<double, CPL, 0, true>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG2X) body_cg2<double, CPL, 2, true>(a, t, sc, lv);
+    return;
+  }
   if constexpr (KIND == K_INIT_R) body_residual<CPL, true>(a, t, lv);
   else if constexpr (KIND == K_RESID) body_residual<CPL, false>(a, t, lv);
   else if constexpr (KIND == K_INIT_W) body_apply<CPL, true>(a, t, lv);
@@ -1300,7 +1369,7 @@ constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 3;
 // wrote last, while they are still in the memory-side cache.  The order in
 // which tiles are processed does not change any result: partials are stored
 // per tile and summed in tile order.
-template <int KIND, int CPL>
+template <int KIND, int CPL, bool D3 = false>
 __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   __shared__ double lds[kLdsPerGroup];
   constexpr int DI = ndots_in<KIND>(), DO = ndots_out<KIND>();
@@ -1350,7 +1419,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
     const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
     double lv[DO > 2 ? DO : 2];
-    run_body<KIND, CPL>(a, t, sc, lv);
+    run_body<KIND, CPL, D3>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
 }
@@ -2576,13 +2645,26 @@ static hipError_t launch_cheb(const PassArgs& a, int grid, hipStream_t st) {
 
 template <int KIND>
 static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_t st) {
-  if (fp32g) hipLaunchKernelGGL((k_pass<KIND, 4>), dim3(grid), dim3(kGroup), 0, st, a);
-  else hipLaunchKernelGGL((k_pass<KIND, 2>), dim3(grid), dim3(kGroup), 0, st, a);
+  if (a.g.plane > 0) {
+    // the 7-point operator: FP64 geometry only
+    if (fp32g) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_pass<KIND, 2, true>), dim3(grid), dim3(kGroup), 0, st, a);
+  } else if (fp32g) {
+    hipLaunchKernelGGL((k_pass<KIND, 4>), dim3(grid), dim3(kGroup), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_pass<KIND, 2>), dim3(grid), dim3(kGroup), 0, st, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStream_t st) {
   if (grid < 8 || (grid & 7)) return hipErrorInvalidValue;
+  // 3D grids run the passes that launch_kind dispatches, nothing else
+  if (a.g.plane > 0 && !(kind == K_INIT_R || kind == K_INIT_W || kind == K_PCG ||
+                         kind == K_PCGX || kind == K_CG1 || kind == K_CG2 || kind == K_CG2X ||
+                         kind == K_RESID || kind == K_APPLY || kind == K_DOT))
+    return hipErrorInvalidValue;
+  if (a.g.plane > 0 && (a.g.plane > a.g.ny || a.g.ny % a.g.plane)) return hipErrorInvalidValue;
   switch (kind) {
     case K_INIT_R: return launch_kind<K_INIT_R>(fp32g, a, grid, st);
     case K_INIT_W: return launch_kind<K_INIT_W>(fp32g, a, grid, st);

@@ -48,8 +48,11 @@ static int32_t map_status(int32_t st) {
 
 int validate(const cg_problem* p) {
   if (!p) return CG_E_INVALID;
-  if (p->nx < 1 || p->ny < 1) return CG_E_INVALID;
-  if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return CG_E_INVALID;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 0) return CG_E_INVALID;
+  if ((int64_t)p->ny * std::max(p->nz, 1) >= (int64_t)1 << 31) return CG_E_INVALID;
+  if ((int64_t)p->nx * p->ny * std::max(p->nz, 1) > (int64_t)1 << 31) return CG_E_INVALID;
+  // 3D (7-point operator): FP64 CG of either variant, no preconditioner
+  if (p->nz > 1 && (p->precision != CG_PREC_FP64 || p->precond != 0)) return CG_E_INVALID;
   if (!(p->tol >= 0.0) || !(p->tol < 1.0)) return CG_E_INVALID;
   if (p->maxit < 1) return CG_E_INVALID;
   if (!p->b || !p->x) return CG_E_INVALID;
@@ -66,13 +69,16 @@ int validate(const cg_problem* p) {
   return CG_OK;
 }
 
+// Rows of the stored grid: ny, or ny * nz planes of the 3D operator.
+int rows_of(const cg_problem* p) { return p->nz > 1 ? p->ny * p->nz : p->ny; }
+
 // Partial slots per tile the passes of a solve write at most.
 static int ndots_max(const cg_problem* p) {
   return p->precond > 0 && p->variant == CG_VARIANT_PIPELINED ? 3 : 2;
 }
 
 Geo make_geo(int nx, int ny, int fp32g, int rows) {
-  Geo g;
+  Geo g{};
   const int cpl = fp32g ? 4 : 2, tw = kWave * cpl;
   g.nx = nx;
   g.ny = ny;
@@ -103,7 +109,7 @@ static int wg_rows(int nx, int ny) {
 }
 
 bool Ctx::use_wg(const cg_problem* p) const {
-  return p->precision == CG_PREC_FP64 && p->precond == 0 &&
+  return p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 &&
          (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
@@ -114,12 +120,13 @@ static int64_t rr_threads_needed(int nx, int ny) {
 }
 
 bool Ctx::use_rr(const cg_problem* p) const {
-  return rr_enabled && p->precision == CG_PREC_FP64 && p->precond == 0 &&
+  return rr_enabled && p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 &&
          rr_threads_needed(p->nx, p->ny) <= kRrThreads;
 }
 
 Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   Plan pl;
+  const int ny = rows_of(p);
   pl.variant = p->variant;
   pl.refined = p->precision == CG_PREC_FP32_REFINED;
   pl.fp32g = pl.refined ? 1 : 0;
@@ -141,7 +148,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   if (pl.wg) {
     rows = wg_rows(p->nx, p->ny);
   } else {
-    auto it = pins.find(key(p->nx, p->ny, pl.fp32g));
+    auto it = pins.find(key(p->nx, ny, pl.fp32g));
     if (it != pins.end()) {
       rows = it->second.rows;
       grid = it->second.grid;
@@ -150,10 +157,11 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
       if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4 && !pl.precond)
         pl.fp32g = 1;
     } else {
-      rows = default_rows(p->nx, p->ny, pl.fp32g);
+      rows = default_rows(p->nx, ny, pl.fp32g);
     }
   }
-  pl.g = make_geo(p->nx, p->ny, pl.fp32g, rows);
+  pl.g = make_geo(p->nx, ny, pl.fp32g, rows);
+  pl.g.plane = p->nz > 1 ? p->ny : 0;
   const int T = pl.g.tiles;
   if (pl.wg) {
     pl.grid = 1;
@@ -170,7 +178,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     // 2048^2 60.4 / 62.3 / 62.3 us, 4096^2 286 / 289 / 297 us, 8192^2
     // 1215 / 1193 / 1203 us.  The classic passes run as many as fit.
     if (!pl.refined && p->variant == CG_VARIANT_PIPELINED) {
-      const int64_t dof = (int64_t)p->nx * p->ny;
+      const int64_t dof = (int64_t)p->nx * ny;
       if (dof > 2 * 1024 * 1024) {
         const int per_cu = dof > 24 * 1024 * 1024 ? 2 : 1;
         cap = std::max(8, std::min(cap, per_cu * num_cu));
@@ -179,7 +187,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     const int tpb = (T + cap - 1) / cap;          // tiles per work-group
     pl.grid = (int)round_up((size_t)((T + tpb - 1) / tpb), 8);
   }
-  const size_t elems = (size_t)pl.g.pitch * p->ny;
+  const size_t elems = (size_t)pl.g.pitch * ny;
   pl.v64 = round_up(elems * 8, Arena::kAlign);
   pl.v32 = round_up(elems * 4, Arena::kAlign);
   int n64, n32 = 0;
@@ -216,8 +224,8 @@ size_t footprint_of(const cg_problem* p) {
   // same arithmetic as Ctx::plan, without a device (tiling affects only the
   // partial buffers, bounded here by one tile per 2 rows)
   const int fp32g = p->precision == CG_PREC_FP32_REFINED;
-  Geo g = make_geo(p->nx, p->ny, fp32g, 1);
-  const size_t elems = (size_t)g.pitch * p->ny;
+  Geo g = make_geo(p->nx, rows_of(p), fp32g, 1);
+  const size_t elems = (size_t)g.pitch * rows_of(p);
   const size_t v64 = round_up(elems * 8, Arena::kAlign), v32 = round_up(elems * 4, Arena::kAlign);
   size_t n64 = fp32g ? 2
                : p->variant == CG_VARIANT_PIPELINED ? (p->precond ? 10 : 8)
@@ -551,8 +559,8 @@ int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const State* pinned) {
   const hipMemcpyKind kind = p->mem == CG_MEM_HOST ? hipMemcpyHostToDevice
                                                    : hipMemcpyDeviceToDevice;
   const size_t row = (size_t)p->nx * 8, pitch = (size_t)pl.g.pitch * 8;
-  HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, p->ny, kind, c.st));
-  if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, p->ny, kind, c.st));
+  HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, rows_of(p), kind, c.st));
+  if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, rows_of(p), kind, c.st));
   HIPCHK(hipMemcpyAsync(w.S[0], pinned, sizeof(State), hipMemcpyHostToDevice, c.st));
   w.m = 0;
   w.i = 0;
@@ -582,10 +590,10 @@ int stage_out(Ctx& c, Work& w, const cg_problem* p, const State& s) {
                                                    : hipMemcpyDeviceToDevice;
   const size_t row = (size_t)p->nx * 8, pitch = (size_t)w.pl.g.pitch * 8;
   if (s.status == ST_ZERO_RHS) {
-    if (p->mem == CG_MEM_HOST) memset(p->x, 0, row * p->ny);
-    else HIPCHK(hipMemsetAsync(p->x, 0, row * p->ny, c.st));
+    if (p->mem == CG_MEM_HOST) memset(p->x, 0, row * rows_of(p));
+    else HIPCHK(hipMemsetAsync(p->x, 0, row * rows_of(p), c.st));
   } else {
-    HIPCHK(hipMemcpy2DAsync(p->x, row, w.x, pitch, row, p->ny, kind, c.st));
+    HIPCHK(hipMemcpy2DAsync(p->x, row, w.x, pitch, row, rows_of(p), kind, c.st));
   }
   HIPCHK(hipStreamSynchronize(c.st));
   return CG_OK;

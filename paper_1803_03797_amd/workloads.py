@@ -123,3 +123,13 @@ def poisson_arrivals(count: int, rate: float, seed_item: int = 0):
     """Arrival times (seconds) of a Poisson process of the given rate."""
     rng = generator(5, seed_item)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+# -- the 3D 7-point operator: n x n x n, b ~ U[-1,1], tol 1e-8 and a fixed 500
+#    iterations (256^3 has the 16.8M unknowns of the 4096^2 workload) --
+CUBE = dict(n=256, tol=1e-8, maxit=20000, iterations=500)
+
+
+def cube_rhs(n: int) -> np.ndarray:
+    """b i.i.d. uniform[-1, 1] on an n^3 grid, as n*n rows of n (plane-major)."""
+    return uniform_rhs(n, n * n, generator(5))

@@ -36,11 +36,11 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(nx=10, ny=7, mem=cg.CG_MEM_HOST, b=1, x0=None, x=2, tol=1e-8, maxit=10,
-             variant=0, precision=0, inner_tol=0.0, precond=0)
+             variant=0, precision=0, inner_tol=0.0, precond=0, nz=0)
     d.update(kw)
     return cg.cg_problem(d["nx"], d["ny"], d["mem"], d["b"], d["x0"], d["x"], d["tol"],
                          d["maxit"], d["variant"], d["precision"], d["inner_tol"],
-                         d["precond"], 0)
+                         d["precond"], d["nz"])
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
@@ -53,7 +53,9 @@ def _prob(**kw):
                                  dict(precision=2, nx=5088, ny=1),
                                  dict(precond=-1), dict(precond=9),
                                  dict(precond=4, precision=1),
-                                 dict(precond=4, precision=2)])
+                                 dict(precond=4, precision=2),
+                                 dict(nz=-1), dict(nz=3, precond=2), dict(nz=3, precision=1),
+                                 dict(nz=3, precision=2), dict(nx=2048, ny=2048, nz=1024)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -65,6 +67,10 @@ def test_validation_accepts():
     for nx, ny in ((1, 1), (100, 100), (98, 102), (1, 6782), (5087, 1)):
         assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
     assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
+    # the 3D operator: nz > 1 (nz = 0 or 1 is the 2D problem)
+    for nz in (0, 1, 2, 64):
+        for v in (0, 1):
+            assert cg.cg_validate(_prob(nz=nz, variant=v)) == cg.CG_OK
     # Chebyshev preconditioner: 1..8 steps, FP64, either variant
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
