@@ -63,6 +63,9 @@ PCG_TRAFFIC_BYTES = 1634008205
 # 4 SIMDs x 16 lanes per clock x 2.4 GHz, the 64-bit multiply-add at half
 # the 32-lane rate of 32-bit VALU operations (a probe kernel of independent
 # v_mad_u64_u32 chains reaches 30.3 T/s on the device).
+# HBM bytes per Chebyshev-pass launch (classic form) at 4096 x 4096 from the two
+# rocprofv3 --pmc runs, by the same calibration: s -> bytes
+CHEB_TRAFFIC_BYTES = {8: (120324 * 2 + 131086) * 1024}
 FX_PRODUCTS = {"classic": 5, "pipelined": 8}
 FX_MULS_PER_PRODUCT = 4
 FX_MUL_PEAK_G = 256 * 4 * 16 * 2.4  # Gmul/s
@@ -526,7 +529,8 @@ def bench_precond(args):
                 else round(kc["GBps"] / HBM_PEAK_GBPS, 4),
                 "hbm_view": {"achieved": kc["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                              "frac": round(kc["GBps"] / HBM_PEAK_GBPS, 4)},
-                "avg_launch_us": kc["avg_us"], "ops_per_launch": ops, "traffic": None}
+                "avg_launch_us": kc["avg_us"], "ops_per_launch": ops,
+                "traffic": CHEB_TRAFFIC_BYTES.get(sb) if n == 4096 else None}
     cpu = None
     if not args.no_cpu:
         import oracle.oracle as oo
