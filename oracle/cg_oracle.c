@@ -22,7 +22,10 @@
  *   - classic CG preconditioned by a Chebyshev polynomial in A (the M^-1 that
  *     the pipelined-CG literature the paper builds on carries);
  *   - both CG variants on the 3D 7-point Laplacian (oracle_cg3), the next
- *     structured-grid finite-difference system after the paper's 2D one.
+ *     structured-grid finite-difference system after the paper's 2D one;
+ *   - both CG variants on the variable-coefficient 5-point operator
+ *     (oracle_cg_vc): the finite-volume form of -div(k grad u) with face
+ *     conductivities, equal to the paper's operator when k = 1.
  *
  * Unknown (i, j), 0 <= i < nx, 0 <= j < ny, has index k = j*nx + i.
  * Build with -O2 -ffp-contract=off (no fast-math): every operation below is
@@ -632,6 +635,93 @@ int oracle_cg3(int32_t variant, int32_t mode, const oracle_order* ord, int32_t n
   int rc = csr3_build(&A, nx, ny, nz, mode == MODE_CANONICAL ? 1 : 0);
   if (rc) return rc;
   ctx_t c = {nx, rows, mode, ord};
+  memset(res, 0, sizeof(*res));
+  rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
+                                      : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
+  csr_free(&A);
+  return rc;
+}
+
+/* ------------------------------------- variable-coefficient 5-point -- */
+
+/* The finite-volume operator of -div(k grad u) on the nx-by-ny grid with zero
+ * Dirichlet boundary and face conductivities: kx holds ny rows of nx + 1 faces
+ * (kx[j][i] between cells i-1 and i of row j; i = 0 and i = nx are boundary
+ * faces), ky holds ny + 1 rows of nx faces (ky[j][i] between rows j-1 and j).
+ * With kW = kx[j][i], kE = kx[j][i+1], kS = ky[j][i], kN = ky[j+1][i]:
+ *   A[k][k] = ((kW + kE) + kS) + kN,  A[k][k-1] = -kW,  A[k][k+1] = -kE,
+ *   A[k][k-nx] = -kS,  A[k][k+nx] = -kN   (neighbours inside the grid only).
+ * Every k = 1 gives the 5-point operator of Section II-B.  Entry orders as for
+ * oracle_csr_assemble (order 1: centre, west, east, south, north, so that the
+ * CSR loop evaluates (((d uC - kW uW) - kE uE) - kS uS) - kN uN, each product
+ * rounded before its subtraction). */
+int64_t oracle_csr_vc_assemble(int32_t nx, int32_t ny, const double* kx, const double* ky,
+                               int32_t order, int64_t* row_ptr, int32_t* col, double* val) {
+  if (nx < 1 || ny < 1 || !kx || !ky) return OR_E_INVALID;
+  int64_t e = 0;
+  for (int32_t j = 0; j < ny; ++j) {
+    for (int32_t i = 0; i < nx; ++i) {
+      const int64_t k = (int64_t)j * nx + i;
+      const double kw = kx[(int64_t)j * (nx + 1) + i], ke = kx[(int64_t)j * (nx + 1) + i + 1];
+      const double ks = ky[(int64_t)j * nx + i], kn = ky[(int64_t)(j + 1) * nx + i];
+      const double d = ((kw + ke) + ks) + kn;
+      row_ptr[k] = e;
+      if (order == 0) {
+        if (j > 0)      { col[e] = (int32_t)(k - nx); val[e++] = -ks; }
+        if (i > 0)      { col[e] = (int32_t)(k - 1);  val[e++] = -kw; }
+        col[e] = (int32_t)k; val[e++] = d;
+        if (i < nx - 1) { col[e] = (int32_t)(k + 1);  val[e++] = -ke; }
+        if (j < ny - 1) { col[e] = (int32_t)(k + nx); val[e++] = -kn; }
+      } else {
+        col[e] = (int32_t)k; val[e++] = d;
+        if (i > 0)      { col[e] = (int32_t)(k - 1);  val[e++] = -kw; }
+        if (i < nx - 1) { col[e] = (int32_t)(k + 1);  val[e++] = -ke; }
+        if (j > 0)      { col[e] = (int32_t)(k - nx); val[e++] = -ks; }
+        if (j < ny - 1) { col[e] = (int32_t)(k + nx); val[e++] = -kn; }
+      }
+    }
+  }
+  row_ptr[(int64_t)nx * ny] = e;
+  return e;
+}
+
+static int csr_vc_build(csr_t* A, int32_t nx, int32_t ny, const double* kx, const double* ky,
+                        int32_t order) {
+  memset(A, 0, sizeof(*A));
+  const int64_t nnz = oracle_csr_nnz(nx, ny);
+  if (nnz < 0 || !kx || !ky) return OR_E_INVALID;
+  A->nx = nx; A->ny = ny; A->n = (int64_t)nx * ny;
+  A->row_ptr = (int64_t*)malloc((size_t)(A->n + 1) * sizeof(int64_t));
+  A->col = (int32_t*)malloc((size_t)nnz * sizeof(int32_t));
+  A->val = (double*)malloc((size_t)nnz * sizeof(double));
+  if (!A->row_ptr || !A->col || !A->val) { csr_free(A); return OR_E_NOMEM; }
+  oracle_csr_vc_assemble(nx, ny, kx, ky, order, A->row_ptr, A->col, A->val);
+  return OR_OK;
+}
+
+int oracle_spmv_vc(int32_t nx, int32_t ny, const double* kx, const double* ky, int32_t order,
+                   const double* u, double* y) {
+  csr_t A;
+  int rc = csr_vc_build(&A, nx, ny, kx, ky, order);
+  if (rc) return rc;
+  spmv(&A, u, y);
+  csr_free(&A);
+  return OR_OK;
+}
+
+/* Algorithms 1 and 2 on the variable-coefficient operator (the same loops as
+ * oracle_cg). */
+int oracle_cg_vc(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny,
+                 const double* kx, const double* ky, const double* b, const double* x0,
+                 double* x, double tol, int32_t maxit, oracle_result* res) {
+  if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
+      (variant != VARIANT_CLASSIC && variant != VARIANT_PIPELINED))
+    return OR_E_INVALID;
+  if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
+  csr_t A;
+  int rc = csr_vc_build(&A, nx, ny, kx, ky, mode == MODE_CANONICAL ? 1 : 0);
+  if (rc) return rc;
+  ctx_t c = {nx, ny, mode, ord};
   memset(res, 0, sizeof(*res));
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);

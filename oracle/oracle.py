@@ -106,6 +106,13 @@ def _load():
     lib.oracle_cg3.restype = C.c_int
     lib.oracle_cg3.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
                                C.c_int32, P, P, P, C.c_double, C.c_int32, C.POINTER(_Result)]
+    lib.oracle_csr_vc_assemble.restype = C.c_int64
+    lib.oracle_csr_vc_assemble.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, P, P, P]
+    lib.oracle_spmv_vc.restype = C.c_int
+    lib.oracle_spmv_vc.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, P, P]
+    lib.oracle_cg_vc.restype = C.c_int
+    lib.oracle_cg_vc.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
+                                 P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(_Result)]
     _lib = lib
     return lib
 
@@ -172,6 +179,56 @@ def cg3(b, nx, ny, nz, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
                             maxit, C.byref(res))
     if rc < 0:
         raise ValueError("oracle_cg3 rejected the call: %d" % rc)
+    return x, Result(status=res.status, iterations=res.iterations,
+                     outer_iterations=res.outer_iterations,
+                     rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
+
+
+def _faces(kx, ky, nx, ny):
+    kx = np.ascontiguousarray(kx, dtype=np.float64)
+    ky = np.ascontiguousarray(ky, dtype=np.float64)
+    if kx.size != ny * (nx + 1) or ky.size != (ny + 1) * nx:
+        raise ValueError("kx needs %d x %d faces, ky %d x %d" % (ny, nx + 1, ny + 1, nx))
+    return kx, ky
+
+
+def csr_vc(nx, ny, kx, ky, order=0):
+    """The variable-coefficient matrix as (row_ptr, col, val)."""
+    kx, ky = _faces(kx, ky, nx, ny)
+    nnz = _load().oracle_csr_nnz(nx, ny)
+    rp = np.zeros(nx * ny + 1, np.int64)
+    col = np.zeros(nnz, np.int32)
+    val = np.zeros(nnz, np.float64)
+    got = _load().oracle_csr_vc_assemble(nx, ny, _ptr(kx), _ptr(ky), order, _ptr(rp), _ptr(col),
+                                         _ptr(val))
+    assert got == nnz
+    return rp, col, val
+
+
+def spmv_vc(u, nx, ny, kx, ky, order=0):
+    kx, ky = _faces(kx, ky, nx, ny)
+    u = _vec(u, nx, ny)
+    y = np.zeros_like(u)
+    rc = _load().oracle_spmv_vc(nx, ny, _ptr(kx), _ptr(ky), order, _ptr(u), _ptr(y))
+    if rc:
+        raise RuntimeError("oracle_spmv_vc failed: %d" % rc)
+    return y
+
+
+def cg_vc(b, nx, ny, kx, ky, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
+          mode=MODE_SEQUENTIAL, order=None):
+    """Solve the variable-coefficient 5-point system (face conductivities kx of
+    shape (ny, nx + 1) and ky of shape (ny + 1, nx))."""
+    kx, ky = _faces(kx, ky, nx, ny)
+    b = _vec(b, nx, ny)
+    x0a = _vec(x0, nx, ny) if x0 is not None else None
+    x = np.zeros_like(b)
+    res = _Result()
+    o = C.byref(order) if order is not None else None
+    rc = _load().oracle_cg_vc(variant, mode, o, nx, ny, _ptr(kx), _ptr(ky), _ptr(b), _ptr(x0a),
+                              _ptr(x), tol, maxit, C.byref(res))
+    if rc < 0:
+        raise ValueError("oracle_cg_vc rejected the call: %d" % rc)
     return x, Result(status=res.status, iterations=res.iterations,
                      outer_iterations=res.outer_iterations,
                      rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
