@@ -32,6 +32,9 @@ Other workloads (one JSON line each, not the headline):
                      preconditioned by s Chebyshev steps (time to solution)
   --workload cube    the 3D 7-point operator on 256^3: both variants, fixed
                      iterations and to tol 1e-8
+  --workload vc      the variable-coefficient 5-point operator on 4096^2 (face
+                     conductivities log-uniform on [0.1, 10]): both variants,
+                     fixed iterations and to tol 1e-8
   --probe            attainable HBM bandwidth of plain streaming kernels, and
                      the attainable rate of 32 x 32 -> 64-bit multiply-adds
 """
@@ -586,17 +589,20 @@ def bench_cube(args):
                                      nz=n))
         ks = kern_table(ctx.cg_kernel_stats(reset=True))
         ctx.cg_set_profiling(False)
-        x2 = torch.zeros_like(b)
-        p2 = cg.make_problem(b, x2, n, n, tol=w["tol"], maxit=w["maxit"], variant=v, nz=n)
-        t1 = time.perf_counter()
-        rc2, r2 = ctx.cg_solve(p2)
-        dt2 = time.perf_counter() - t1
+        tol_run = None
+        if not args.fixed_only:
+            x2 = torch.zeros_like(b)
+            p2 = cg.make_problem(b, x2, n, n, tol=w["tol"], maxit=w["maxit"], variant=v, nz=n)
+            t1 = time.perf_counter()
+            rc2, r2 = ctx.cg_solve(p2)
+            dt2 = time.perf_counter() - t1
+            tol_run = dict(status=cg.cg_status_str(rc2), iterations=r2.iterations,
+                           seconds=round(dt2, 4), rel_res_true=r2.rel_res_true)
         out[name] = dict(GDOF_iter_s=round(dof * its / dt / 1e9, 3),
                          seconds_fixed=round(dt, 4),
                          algorithmic_GBps=round(dof * its * BYTES_PER_ITER[name] / dt / 1e9, 1),
                          kernels={k: vv for k, vv in ks.items() if k != "final_check"},
-                         tol_1e8=dict(status=cg.cg_status_str(rc2), iterations=r2.iterations,
-                                      seconds=round(dt2, 4), rel_res_true=r2.rel_res_true))
+                         tol_1e8=tol_run)
         log("3d", name, json.dumps(out[name]))
     pk = out["pipelined"]["kernels"].get("pcg_pass")
     roof = None
@@ -624,6 +630,89 @@ def bench_cube(args):
           "workload": "cube", "value": round(value, 3), "unit": "GDOF-iter/s",
           "config": {"workload": "%d^3 7-point Laplacian, b~U[-1,1] seeded, x0=0; fixed %d "
                                  "iterations, then tol 1e-8" % (n, its)},
+          "dtype": "f64", "results": out, "roofline": roof, "cpu_baseline": cpu})
+    ctx.close()
+
+
+# ------------------------------------------------------------------------ vc --
+
+def bench_vc(args):
+    """The variable-coefficient 5-point operator on n^2 (face conductivities
+    log-uniform over [0.1, 10]): both variants, a fixed number of iterations
+    (throughput, per-kernel times, the pipelined pass's roofline), then each to
+    tol 1e-8."""
+    torch, cg = setup()
+    from paper_1803_03797_amd import workloads
+    w = workloads.VC
+    n = args.n_vc
+    dof = n * n
+    its = w["iterations"]
+    kxh, kyh = workloads.vc_faces(n, n, w["k_lo"], w["k_hi"])
+    bh = workloads.vc_rhs(n, n)
+    b, kx, ky = (torch.from_numpy(a).cuda() for a in (bh, kxh, kyh))
+    ctx = cg.Context(device=0, arena_bytes=100 * dof + (1 << 30))
+    x = torch.zeros_like(b)
+    out = {}
+    for v, name in ((0, "classic"), (1, "pipelined")):
+        p = cg.make_problem(b, x, n, n, tol=0.0, maxit=its, variant=v, kx=kx, ky=ky)
+        ctx.cg_solve(p)  # warm: graphs captured
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = ctx.cg_solve(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        ctx.cg_solve(cg.make_problem(b, torch.zeros_like(b), n, n, tol=0.0, maxit=40, variant=v,
+                                     kx=kx, ky=ky))
+        ks = kern_table(ctx.cg_kernel_stats(reset=True))
+        ctx.cg_set_profiling(False)
+        tol_run = None
+        if not args.fixed_only:
+            x2 = torch.zeros_like(b)
+            p2 = cg.make_problem(b, x2, n, n, tol=w["tol"], maxit=w["maxit"], variant=v, kx=kx,
+                                 ky=ky)
+            t1 = time.perf_counter()
+            rc2, r2 = ctx.cg_solve(p2)
+            dt2 = time.perf_counter() - t1
+            tol_run = dict(status=cg.cg_status_str(rc2), iterations=r2.iterations,
+                           seconds=round(dt2, 4), rel_res_true=r2.rel_res_true)
+        # each stencil pass also reads the four coefficients (32 B per unknown):
+        # classic applies the stencil in both of its passes, pipelined in one
+        per_iter = BYTES_PER_ITER[name] + (32 if name == "pipelined" else 64)
+        out[name] = dict(GDOF_iter_s=round(dof * its / dt / 1e9, 3),
+                         seconds_fixed=round(dt, 4),
+                         algorithmic_GBps=round(dof * its * per_iter / dt / 1e9, 1),
+                         kernels={k: vv for k, vv in ks.items() if k != "final_check"},
+                         tol_1e8=tol_run)
+        log("vc", name, json.dumps(out[name]))
+    pk = out["pipelined"]["kernels"].get("pcg_pass")
+    roof = None
+    if pk:
+        per_launch = (BYTES_PER_DOF["pcg_pass"] + 32) * dof
+        ach = per_launch / (pk["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": "pcg_pass (variable coefficients)",
+                "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "avg_launch_us": pk["avg_us"],
+                "bytes_per_launch": per_launch, "traffic": None}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k = 4
+        t = time.perf_counter()
+        oracle.cg_vc(bh, n, n, kxh, kyh, variant=0, tol=0.0, maxit=k)
+        ct = time.perf_counter() - t
+        cpu = {"value": round(dof * k / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "%d classic iterations of the variable-coefficient oracle at %d^2 "
+                         "(explicit CSR, single thread, %.1f s incl. assembly)" % (k, n, ct)}
+    value = (out["classic"]["GDOF_iter_s"] + out["pipelined"]["GDOF_iter_s"]) / 2
+    emit({"metric": "CG GDOF-iter/s, variable-coefficient 5-point operator %d^2 FP64 (classic "
+                    "+ pipelined, %d iterations each)" % (n, its),
+          "workload": "vc", "value": round(value, 3), "unit": "GDOF-iter/s",
+          "config": {"workload": "%d^2 finite-volume -div(k grad u), face k log-uniform on "
+                                 "[%g, %g] seeded, b~U[-1,1] seeded, x0=0; fixed %d "
+                                 "iterations, then tol 1e-8" % (n, w["k_lo"], w["k_hi"], its)},
           "dtype": "f64", "results": out, "roofline": roof, "cpu_baseline": cpu})
     ctx.close()
 
@@ -869,8 +958,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=48)
     ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
     ap.add_argument("--workload",
-                    choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube"])
+                    choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube", "vc"])
     ap.add_argument("--n-cube", type=int, default=256, help="--workload cube: grid side")
+    ap.add_argument("--n-vc", type=int, default=4096, help="--workload vc: grid side")
+    ap.add_argument("--fixed-only", action="store_true",
+                    help="--workload cube / vc: only the fixed-iteration runs (no tol solves)")
     ap.add_argument("--huge-precond", type=int, default=8,
                     help="--workload huge: also solve with s Chebyshev steps (0: skip)")
     ap.add_argument("--steps-list", type=int, nargs="*", default=[2, 4, 6, 8],
@@ -904,6 +996,8 @@ def main():
         return bench_precond(args)
     if args.workload == "cube":
         return bench_cube(args)
+    if args.workload == "vc":
+        return bench_vc(args)
     if args.workload == "serve":
         args.count = args.count or 400
         return bench_serve(args)

@@ -116,6 +116,26 @@ typedef struct {
                               so b, x0 and x hold nx * ny * nz values; FP64, either
                               variant, precond 0, cg_solve only (batches and serving
                               reject it)                                            */
+  int32_t pad_;
+  const double* kx;        /* NULL (with ky NULL): the constant-coefficient operators
+                              above.  Else the variable-coefficient 5-point operator,
+                              the other structured-grid case Section I names beside
+                              3D: the finite-volume form of -div(k grad u) with zero
+                              Dirichlet boundary, (A u)_ij = d u_ij - kW u_W - kE u_E
+                              - kS u_S - kN u_N (out-of-grid neighbours 0), d = ((kW
+                              + kE) + kS) + kN; kx holds the conductivities of the
+                              faces between columns, ny x (nx + 1) row-major (kW =
+                              kx[j][i], kE = kx[j][i+1]; columns 0 and nx are the
+                              boundary faces), in the memory space of b; read until
+                              the final status is returned.  All ones give the
+                              Section II-B operator.  Values must be positive and
+                              finite (A is then symmetric positive definite); other
+                              values are not checked and make the result undefined
+                              (typically CG_BREAKDOWN).  FP64, 2D (nz <= 1), either
+                              variant, precond 0, cg_solve only                    */
+  const double* ky;        /* with kx: the conductivities of the faces between rows,
+                              (ny + 1) x nx row-major (kS = ky[j][i], kN = ky[j+1][i];
+                              rows 0 and ny are the boundary faces)                */
 } cg_problem;
 
 typedef struct {

@@ -31,7 +31,8 @@ class cg_problem(C.Structure):
                 ("b", C.c_void_p), ("x0", C.c_void_p), ("x", C.c_void_p),
                 ("tol", C.c_double), ("maxit", C.c_int32), ("variant", C.c_int32),
                 ("precision", C.c_int32), ("inner_tol", C.c_double),
-                ("precond", C.c_int32), ("nz", C.c_int32)]
+                ("precond", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
+                ("kx", C.c_void_p), ("ky", C.c_void_p)]
 
 
 class cg_result(C.Structure):
@@ -143,21 +144,41 @@ def _ptr_mem(a):
     raise TypeError("unsupported vector type %r" % type(a))
 
 
+def _numel(v):
+    return v.size if isinstance(v, np.ndarray) else v.numel()
+
+
 def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
-                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0, nz=0):
-    """nz > 1: the 3D 7-point problem on nx x ny x nz (vectors of nx*ny*nz)."""
+                 precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0, nz=0, kx=None,
+                 ky=None):
+    """nz > 1: the 3D 7-point problem on nx x ny x nz (vectors of nx*ny*nz).
+    kx, ky: face conductivities of the variable-coefficient operator, ny x
+    (nx+1) and (ny+1) x nx, in the memory space of b (the caller keeps them
+    alive until the solve returns)."""
     pb, mb = _ptr_mem(b)
     px, mx = _ptr_mem(x)
     p0, m0 = _ptr_mem(x0)
+    pkx, mkx = _ptr_mem(kx)
+    pky, mky = _ptr_mem(ky)
     if mb != mx or (m0 is not None and m0 != mb):
         raise ValueError("b, x and x0 must live in the same memory space")
+    if (kx is None) != (ky is None):
+        raise ValueError("kx and ky come together")
+    if kx is not None:
+        if mkx != mb or mky != mb:
+            raise ValueError("kx and ky must live in the memory space of b")
+        if _numel(kx) != ny * (nx + 1) or _numel(ky) != (ny + 1) * nx:
+            raise ValueError("kx must hold ny*(nx+1) values and ky (ny+1)*nx")
     n = nx * ny * max(nz, 1)
     for v in (b, x, x0):
-        if v is not None and (v.size if isinstance(v, np.ndarray) else v.numel()) != n:
+        if v is not None and _numel(v) != n:
             raise ValueError("vector size does not match the %dx%dx%d grid" % (nx, ny, max(nz, 1)))
     p = cg_problem(nx, ny, mb, pb, p0, px, float(tol), int(maxit), int(variant),
-                   int(precision), float(inner_tol), int(precond), int(nz))
+                   int(precision), float(inner_tol), int(precond), int(nz), 0, pkx, pky)
     return p
+
+
+_VC_PLACEHOLDER = C.c_double(1.0)
 
 
 class Context:
@@ -245,9 +266,12 @@ class Context:
         return out.value
 
     def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64, precond=0,
-                nz=0):
+                nz=0, vc=False):
+        """vc: plan the variable-coefficient operator (the coefficients are not
+        read: a placeholder stands for them)."""
+        k = C.addressof(_VC_PLACEHOLDER) if vc else None
         p = cg_problem(nx, ny, CG_MEM_DEVICE, None, None, None, 1e-8, 1, variant, precision, 0.0,
-                       precond, nz)
+                       precond, nz, 0, k, k)
         info = cg_plan_info()
         _check("cg_plan", self.lib.cg_plan(self.h, C.byref(p), C.byref(info)))
         return info

@@ -80,6 +80,10 @@ struct Geo {
   int32_t th;        // rows per tile = 4 * rows
   int32_t plane;     // 3D (7-point operator): rows per plane, ny = plane * nz; 2D: 0
   int32_t pad_;
+  // variable-coefficient 5-point operator: the west, east, south and north
+  // face conductivities of every cell, four arrays of ny * pitch one after the
+  // other, each laid out like a vector (zero in the padding); null otherwise
+  const double* kc;
 };
 
 // Pass kinds.

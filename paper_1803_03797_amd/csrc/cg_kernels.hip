@@ -129,12 +129,45 @@ __device__ __forceinline__ T st5(T c, T w, T e, T s, T n) {
   return (((T(4) * c - w) - e) - s) - n;
 }
 
-// The 7-point operator in 3D: (((((6 uC - uW) - uE) - uS) - uN) - uB) - uT,
-// B = plane l-1, T = plane l+1; stn picks it or the 5-point one.
-template <bool D3, typename T>
-__device__ __forceinline__ T stn(T c, T w, T e, T s, T n, T b, T t) {
-  if constexpr (D3) return (((((T(6) * c - w) - e) - s) - n) - b) - t;
-  else return st5(c, w, e, s, n);
+// The operator at one point, selected by OP:
+//   0: the 5-point stencil;
+//   1: the 7-point one in 3D, (((((6 uC - uW) - uE) - uS) - uN) - uB) - uT,
+//      B = plane l-1, T = plane l+1;
+//   2: the variable-coefficient 5-point one with face conductivities kw, ke,
+//      ks, kn: d = ((kw + ke) + ks) + kn, then (((d uC - kw uW) - ke uE) -
+//      ks uS) - kn uN, each product rounded before its subtraction.
+template <int OP, typename T>
+__device__ __forceinline__ T stn(T c, T w, T e, T s, T n, T b, T t, T kw, T ke, T ks, T kn) {
+  if constexpr (OP == 1) {
+    return (((((T(6) * c - w) - e) - s) - n) - b) - t;
+  } else if constexpr (OP == 2) {
+    const T d = ((kw + ke) + ks) + kn;
+    const T pc = d * c, pw = kw * w, pe = ke * e, ps = ks * s, pn = kn * n;
+    return (((pc - pw) - pe) - ps) - pn;
+  } else {
+    return st5(c, w, e, s, n);
+  }
+}
+
+// The four face conductivities of a lane's cells on one row.
+template <typename T, int CPL>
+struct Kc {
+  Row<T, CPL> w, e, s, n;
+};
+
+// The operator at column k of a lane's row from the walker's rows.
+template <int OP, typename T, int CPL, class KC>
+__device__ __forceinline__ T op_at(const Row<T, CPL>& S, const Row<T, CPL>& C,
+                                   const Row<T, CPL>& N, const Row<T, CPL>& W,
+                                   const Row<T, CPL>& E, const Row<T, CPL>& B,
+                                   const Row<T, CPL>& U, const KC& kc, int k) {
+  if constexpr (OP == 2) {
+    return stn<2>(C.e[k], W.e[k], E.e[k], S.e[k], N.e[k], T(0), T(0), kc.w.e[k], kc.e.e[k],
+                  kc.s.e[k], kc.n.e[k]);
+  } else {
+    return stn<OP>(C.e[k], W.e[k], E.e[k], S.e[k], N.e[k], B.e[k], U.e[k], T(0), T(0), T(0),
+                   T(0));
+  }
 }
 
 // Reads a State every lane needs with the same value into scalar registers
@@ -670,8 +703,14 @@ __device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
 // vector one plane below and above each row (raw, PD rows ahead with the point
 // data) and hands comp hS / hN zeroed at the plane's first / last row, and the
 // rows below / above (zero outside the grid).  In 2D those are zero rows.
-//   comp(off, S, C, N, W, E, below, above, bundle)
-template <typename T, int CPL, int PD, bool D3, class HLoad, class HMake, class ELoad,
+//   comp(off, S, C, N, W, E, below, above, kc, bundle)
+//
+// OP selects the operator: 0 the 5-point stencil, 1 the 7-point one (D3
+// above), 2 the variable-coefficient 5-point one, for which the walker also
+// loads the row's four face conductivities (kc: Kc rows of the west, east,
+// south and north arrays that g.kc holds one after the other, each laid out
+// like a vector) PD rows ahead with the point data.
+template <typename T, int CPL, int PD, int OP, class HLoad, class HMake, class ELoad,
           class EMake, class Point, class Comp>
 __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
                                      ELoad eload, EMake emake, Point point, Comp comp) {
@@ -683,12 +722,28 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
   const size_t P = g.pitch;
   const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
   const size_t o0 = (size_t)s.j0 * P;
+  constexpr bool D3 = OP == 1, VC = OP == 2;
   // 3D: rows j - plane and j + plane (clamped into the grid for the load)
   const int pl = D3 ? g.plane : 0;
   auto boff = [&](int r) { return (size_t)max(r - pl, 0) * P; };
   auto toff = [&](int r) { return (size_t)min(r + pl, g.ny - 1) * P; };
   RawH qb[D3 ? PD : 1], qt[D3 ? PD : 1];
   int jp = D3 ? s.j0 % pl : 0;  // row within its plane
+  // variable coefficients: the row's four face conductivities, PD rows ahead
+  using K = Kc<T, CPL>;
+  const size_t kst = (size_t)g.ny * P;  // one coefficient array
+  auto kload = [&](size_t off) {
+    K k;
+    if constexpr (VC) {
+      const double* c0 = g.kc + off + s.c;
+      k.w = ldrow<T, CPL>(c0);
+      k.e = ldrow<T, CPL>(c0 + kst);
+      k.s = ldrow<T, CPL>(c0 + 2 * kst);
+      k.n = ldrow<T, CPL>(c0 + 3 * kst);
+    }
+    return k;
+  };
+  K qk[VC ? PD : 1];
   R hS = zrow<T, CPL>();
   {
     const R v = hmake(hload((size_t)max(s.j0 - 1, 0) * P));
@@ -713,6 +768,7 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qb[k] = hload(boff(rp));
       qt[k] = hload(toff(rp));
     }
+    if constexpr (VC) qk[k] = kload((size_t)rp * P);
   }
   size_t o = o0;
   for (int j = s.j0; j < s.j1; ++j, o += P) {
@@ -729,6 +785,8 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       bn = hload(boff(rp));
       tn = hload(toff(rp));
     }
+    K kn;
+    if constexpr (VC) kn = kload((size_t)rp * P);
     // row j+1 enters the window
     R hN = hmake(q[0]);
     T eN = emake(qe[0]);
@@ -744,11 +802,11 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       const R zr = zrow<T, CPL>();
       const R Bl = j >= pl ? hmake(qb[0]) : zr;
       const R Ab = j + pl < g.ny ? hmake(qt[0]) : zr;
-      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, pt[0]);
+      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, qk[0], pt[0]);
       if (++jp == pl) jp = 0;
     } else {
       const R zr = zrow<T, CPL>();
-      comp(o, hS, hC, hN, W, E, zr, zr, pt[0]);
+      comp(o, hS, hC, hN, W, E, zr, zr, qk[0], pt[0]);
     }
     hS = hC;
     hC = hN;
@@ -763,6 +821,7 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
         qb[k] = qb[k + 1];
         qt[k] = qt[k + 1];
       }
+      if constexpr (VC) qk[k] = qk[k + 1];
     }
     q[PD - 1] = hn;
     qe[PD - 1] = en;
@@ -772,6 +831,7 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qb[PD - 1] = bn;
       qt[PD - 1] = tn;
     }
+    if constexpr (VC) qk[PD - 1] = kn;
   }
 }
 
@@ -780,12 +840,12 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #endif
 
 // Loaders for a halo vector that is stored as is.
-template <typename T, int CPL, bool D3, class Point, class Comp>
+template <typename T, int CPL, int OP, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
   const int c = s.c;
-  walk<T, CPL, 1, D3>(
+  walk<T, CPL, 1, OP>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
       [=](T v) { return ea.emask ? v : T(0); }, point, comp);
@@ -795,7 +855,7 @@ struct Empty {};
 
 // --- K_INIT_R: r = b - A x; slots (r,r), (b,b)
 // --- K_RESID:  t = b - A x; slots (t,t), (b,b)   (no store)
-template <int CPL, bool STORE, bool D3 = false>
+template <int CPL, bool STORE, int OP = 0>
 __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -806,14 +866,15 @@ __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* 
   const int valid = g.nx - s.c;
   const double* B = a.b;
   double* Rr = a.r;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const R& bb) {
         R res;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          res.e[k] = bb.e[k] - stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          res.e[k] = bb.e[k] - op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (k < valid) {
             a0[k] = fma(res.e[k], res.e[k], a0[k]);
             a1[k] = fma(bb.e[k], bb.e[k], a1[k]);
@@ -827,7 +888,7 @@ __device__ __forceinline__ void body_residual(const PassArgs& a, int t, double* 
 
 // --- K_INIT_W: w = A r; slots (r,r), (w,r)
 // --- K_APPLY:  y = A u; no slots
-template <int CPL, bool INITW, bool D3 = false>
+template <int CPL, bool INITW, int OP = 0>
 __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -838,14 +899,15 @@ __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv)
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, U, [](size_t) { return Empty{}; },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const Empty&) {
         R out;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          out.e[k] = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          out.e[k] = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (INITW && k < valid) {
             a0[k] = fma(hC.e[k], hC.e[k], a0[k]);
             a1[k] = fma(out.e[k], hC.e[k], a1[k]);
@@ -886,7 +948,7 @@ struct PcgRow {
   Row<double, CPL> x, r, z, q, p;
 };
 
-template <int CPL, bool XU, bool D3 = false>
+template <int CPL, bool XU, int OP = 0>
 __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -898,7 +960,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
@@ -911,12 +973,13 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
         v.p = ldrow<double, CPL>(Pp + oc);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const PcgRow<CPL>& in) {
         R x = in.x, r = in.r, z, q, p, wo;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double nv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          const double nv = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (first) {
             z.e[k] = nv;
             q.e[k] = hC.e[k];
@@ -949,7 +1012,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
 }
 
 // --- K_INIT_WU: w = A u; slots (r,u), (w,u), (r,r)   [preconditioned pipelined]
-template <int CPL, bool D3 = false>
+template <int CPL, int OP = 0>
 __device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -960,14 +1023,15 @@ __device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* l
   const int valid = g.nx - s.c;
   const double* Rv = a.r;
   double* Wv = a.wv;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, a.uu, [=](size_t off) { return ldrow<double, CPL>(Rv + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const R& r) {
         R out;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          out.e[k] = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          out.e[k] = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (k < valid) {
             a0[k] = fma(r.e[k], hC.e[k], a0[k]);
             a1[k] = fma(out.e[k], hC.e[k], a1[k]);
@@ -991,7 +1055,7 @@ struct PpcgRow {
   Row<double, CPL> x, r, u, w, z, q, s, p;
 };
 
-template <int CPL, bool D3 = false>
+template <int CPL, int OP = 0>
 __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<double, CPL>;
   const Geo& g = a.g;
@@ -1003,7 +1067,7 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = a2[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *U = a.uu, *Wv = a.wv, *Z = a.z, *Q = a.q, *Sv = a.sv, *Pp = a.p;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, a.mv,
       [=](size_t off) {
         PpcgRow<CPL> v;
@@ -1019,12 +1083,13 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
         v.p = ldrow<double, CPL>(Pp + oc);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const PpcgRow<CPL>& in) {
         R x = in.x, r = in.r, u = in.u, w = in.w, z, q, sv, p;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double nv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          const double nv = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (first) {
             z.e[k] = nv;
             q.e[k] = hC.e[k];
@@ -1063,7 +1128,7 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
 
 // --- K_CG1 / K_CG1F: p = r + beta p_old (on tile + halo); s = A p; store p;
 //     slot (p, s).  First iteration: p = r.
-template <typename T, int CPL, bool D3 = false>
+template <typename T, int CPL, int OP = 0>
 __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<T, CPL>;
   const Geo& g = a.g;
@@ -1095,7 +1160,7 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
     T r, po;
   };
   const EdgeAddr ea = edge_addr<CPL>(s, g);
-  walk<T, CPL, CG1_PREFETCH, D3>(
+  walk<T, CPL, CG1_PREFETCH, OP>(
       g, s,
       [=](size_t off) {
         Raw v;
@@ -1117,11 +1182,12 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
       },
       [=](const RawE& v) { return ea.emask ? (first ? v.r : fma(be, v.po, v.r)) : T(0); },
       [](size_t) { return Empty{}; },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const Empty&) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const T sv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          const T sv = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if (k < valid) a0[k] = fma((double)hC.e[k], (double)sv, a0[k]);
         }
         strow<T, CPL>(Pn + off + s.c, hC, valid);
@@ -1138,7 +1204,7 @@ struct XrRow {
   Row<T, CPL> x, r, pp;
 };
 
-template <typename T, int CPL, int XM, bool D3 = false>
+template <typename T, int CPL, int XM, int OP = 0>
 __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc, double* lv) {
   using R = Row<T, CPL>;
   using In = XrRow<T, CPL, XM>;
@@ -1164,7 +1230,7 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk_plain<T, CPL, D3>(
+  walk_plain<T, CPL, OP>(
       g, s, Pv,
       [=](size_t off) {
         In v;
@@ -1173,12 +1239,13 @@ __device__ __forceinline__ void body_cg2(const PassArgs& a, int t, const Sc& sc,
         v.r = ldrow<T, CPL>(Rv + off + s.c);
         return v;
       },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const In& in) {
         R x = in.x, r = in.r;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const T sv = stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          const T sv = op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           if constexpr (XM == 1) x.e[k] = fma(al, hC.e[k], x.e[k]);
           if constexpr (XM == 2) x.e[k] = fma(al, hC.e[k], fma(alp, in.pp.e[k], x.e[k]));
           r.e[k] = fma(nal, sv, r.e[k]);
@@ -1250,7 +1317,7 @@ __device__ __forceinline__ void run_flush(const PassArgs& a, int t, const Sc& sc
 }
 
 // --- K_REF_SCALE: rho = fp32((b - A x) * inv); d = 0; slot (rho, rho) in FP64.
-template <int CPL, bool D3 = false>
+template <int CPL, int OP = 0>
 __device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const Sc& sc,
                                                double* lv) {
   using R = Row<double, CPL>;
@@ -1264,14 +1331,15 @@ __device__ __forceinline__ void body_ref_scale(const PassArgs& a, int t, const S
   const int valid = g.nx - s.c;
   const double* B = a.b;
   float *Rf = a.rf, *Df = a.df;
-  walk_plain<double, CPL, D3>(
+  walk_plain<double, CPL, OP>(
       g, s, a.x, [=](size_t off) { return ldrow<double, CPL>(B + off + s.c); },
-      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E, const R& B3, const R& T3,
+      [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
+          const R& B3, const R& T3, const auto& kc,
           const R& bb) {
         RF rho;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-          const double res = bb.e[k] - stn<D3>(hC.e[k], W.e[k], E.e[k], hS.e[k], hN.e[k], B3.e[k], T3.e[k]);
+          const double res = bb.e[k] - op_at<OP>(hS, hC, hN, W, E, B3, T3, kc, k);
           rho.e[k] = (float)(res * inv);
           if (k < valid) a0[k] = fma((double)rho.e[k], (double)rho.e[k], a0[k]);
         }
@@ -1298,24 +1366,25 @@ __device__ __forceinline__ void body_ref_update(const PassArgs& a, int t, const 
   }
 }
 
-// D3: the 7-point operator (multi-work-group passes of the FP64 kinds only).
-template <int KIND, int CPL, bool D3 = false>
+// OP != 0: the 7-point or the variable-coefficient operator (multi-work-group
+// passes of the FP64 kinds only).
+template <int KIND, int CPL, int OP = 0>
 __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc, double* lv) {
-  static_assert(!D3 || KIND == K_INIT_R || KIND == K_RESID || KIND == K_INIT_W ||
+  static_assert(OP == 0 || KIND == K_INIT_R || KIND == K_RESID || KIND == K_INIT_W ||
                     KIND == K_APPLY || KIND == K_DOT || KIND == K_PCG || KIND == K_PCGX ||
                     KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X,
-                "no 3D form of this pass");
-  if constexpr (D3) {
-    if constexpr (KIND == K_INIT_R) body_residual<CPL, true, true>(a, t, lv);
-    else if constexpr (KIND == K_RESID) body_residual<CPL, false, true>(a, t, lv);
-    else if constexpr (KIND == K_INIT_W) body_apply<CPL, true, true>(a, t, lv);
-    else if constexpr (KIND == K_APPLY) body_apply<CPL, false, true>(a, t, lv);
+                "no form of this pass for the operator");
+  if constexpr (OP != 0) {
+    if constexpr (KIND == K_INIT_R) body_residual<CPL, true, OP>(a, t, lv);
+    else if constexpr (KIND == K_RESID) body_residual<CPL, false, OP>(a, t, lv);
+    else if constexpr (KIND == K_INIT_W) body_apply<CPL, true, OP>(a, t, lv);
+    else if constexpr (KIND == K_APPLY) body_apply<CPL, false, OP>(a, t, lv);
     else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
-    else if constexpr (KIND == K_PCG) body_pcg<CPL, false, true>(a, t, sc, lv);
-    else if constexpr (KIND == K_PCGX) body_pcg<CPL, true, true>(a, t, sc, lv);
-    else if constexpr (KIND == K_CG1) body_cg1<double, CPL, true>(a, t, sc, lv);
-    else if constexpr (KIND == K_CG2) body_cg2<double, CPL, 0, true>(a, t, sc, lv);
-    else if constexpr (KIND == K_CG2X) body_cg2<double, CPL, 2, true>(a, t, sc, lv);
+    else if constexpr (KIND == K_PCG) body_pcg<CPL, false, OP>(a, t, sc, lv);
+    else if constexpr (KIND == K_PCGX) body_pcg<CPL, true, OP>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG1) body_cg1<double, CPL, OP>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG2) body_cg2<double, CPL, 0, OP>(a, t, sc, lv);
+    else if constexpr (KIND == K_CG2X) body_cg2<double, CPL, 2, OP>(a, t, sc, lv);
     return;
   }
   if constexpr (KIND == K_INIT_R) body_residual<CPL, true>(a, t, lv);
@@ -1369,7 +1438,7 @@ constexpr int kLdsPerGroup = 4 * 2 + 2 * 4 * 3;
 // wrote last, while they are still in the memory-side cache.  The order in
 // which tiles are processed does not change any result: partials are stored
 // per tile and summed in tile order.
-template <int KIND, int CPL, bool D3 = false>
+template <int KIND, int CPL, int OP = 0>
 __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   __shared__ double lds[kLdsPerGroup];
   constexpr int DI = ndots_in<KIND>(), DO = ndots_out<KIND>();
@@ -1419,7 +1488,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
   for (int tt = t0 + slot; tt < t1; tt += nb, par ^= 1) {
     const int t = a.rev ? t1 - 1 - (tt - t0) : tt;
     double lv[DO > 2 ? DO : 2];
-    run_body<KIND, CPL, D3>(a, t, sc, lv);
+    run_body<KIND, CPL, OP>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
 }
@@ -2645,10 +2714,11 @@ static hipError_t launch_cheb(const PassArgs& a, int grid, hipStream_t st) {
 
 template <int KIND>
 static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_t st) {
-  if (a.g.plane > 0) {
-    // the 7-point operator: FP64 geometry only
-    if (fp32g) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_pass<KIND, 2, true>), dim3(grid), dim3(kGroup), 0, st, a);
+  if (a.g.plane > 0 || a.g.kc) {
+    // the 7-point or the variable-coefficient operator: FP64 geometry only
+    if (fp32g || (a.g.plane > 0 && a.g.kc)) return hipErrorInvalidValue;
+    if (a.g.plane > 0) hipLaunchKernelGGL((k_pass<KIND, 2, 1>), dim3(grid), dim3(kGroup), 0, st, a);
+    else hipLaunchKernelGGL((k_pass<KIND, 2, 2>), dim3(grid), dim3(kGroup), 0, st, a);
   } else if (fp32g) {
     hipLaunchKernelGGL((k_pass<KIND, 4>), dim3(grid), dim3(kGroup), 0, st, a);
   } else {
@@ -2659,8 +2729,9 @@ static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_
 
 hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStream_t st) {
   if (grid < 8 || (grid & 7)) return hipErrorInvalidValue;
-  // 3D grids run the passes that launch_kind dispatches, nothing else
-  if (a.g.plane > 0 && !(kind == K_INIT_R || kind == K_INIT_W || kind == K_PCG ||
+  // 3D and variable-coefficient grids run the passes that launch_kind
+  // dispatches, nothing else
+  if ((a.g.plane > 0 || a.g.kc) && !(kind == K_INIT_R || kind == K_INIT_W || kind == K_PCG ||
                          kind == K_PCGX || kind == K_CG1 || kind == K_CG2 || kind == K_CG2X ||
                          kind == K_RESID || kind == K_APPLY || kind == K_DOT))
     return hipErrorInvalidValue;

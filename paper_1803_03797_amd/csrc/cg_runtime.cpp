@@ -53,6 +53,11 @@ int validate(const cg_problem* p) {
   if ((int64_t)p->nx * p->ny * std::max(p->nz, 1) > (int64_t)1 << 31) return CG_E_INVALID;
   // 3D (7-point operator): FP64 CG of either variant, no preconditioner
   if (p->nz > 1 && (p->precision != CG_PREC_FP64 || p->precond != 0)) return CG_E_INVALID;
+  // variable coefficients: both arrays, 2D FP64 CG of either variant, no
+  // preconditioner
+  if ((p->kx == nullptr) != (p->ky == nullptr)) return CG_E_INVALID;
+  if (p->kx && (p->nz > 1 || p->precision != CG_PREC_FP64 || p->precond != 0))
+    return CG_E_INVALID;
   if (!(p->tol >= 0.0) || !(p->tol < 1.0)) return CG_E_INVALID;
   if (p->maxit < 1) return CG_E_INVALID;
   if (!p->b || !p->x) return CG_E_INVALID;
@@ -109,7 +114,7 @@ static int wg_rows(int nx, int ny) {
 }
 
 bool Ctx::use_wg(const cg_problem* p) const {
-  return p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 &&
+  return p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 && !p->kx &&
          (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
@@ -121,7 +126,7 @@ static int64_t rr_threads_needed(int nx, int ny) {
 
 bool Ctx::use_rr(const cg_problem* p) const {
   return rr_enabled && p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 &&
-         rr_threads_needed(p->nx, p->ny) <= kRrThreads;
+         !p->kx && rr_threads_needed(p->nx, p->ny) <= kRrThreads;
 }
 
 Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
@@ -134,6 +139,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   pl.rr = allow_rr && use_rr(p);
   pl.fixed = p->precision == CG_PREC_FIXED;
   pl.precond = p->precond;
+  pl.vc = p->kx != nullptr;
   if (pl.fixed) {
     // one unknown per thread up to 1024 unknowns, then 1024 threads
     const int64_t dof = (int64_t)p->nx * p->ny;
@@ -152,9 +158,11 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     if (it != pins.end()) {
       rows = it->second.rows;
       grid = it->second.grid;
-      // classic FP64 may run with 4 columns (32 B) per lane
-      // (not with the preconditioner, whose pass is written for 2)
-      if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4 && !pl.precond)
+      // classic FP64 may run with 4 columns (32 B) per lane (the 5-point
+      // operator without the preconditioner: the other passes are written
+      // for 2)
+      if (!pl.refined && p->variant == CG_VARIANT_CLASSIC && it->second.cpl == 4 && !pl.precond &&
+          !pl.vc && p->nz <= 1)
         pl.fp32g = 1;
     } else {
       rows = default_rows(p->nx, ny, pl.fp32g);
@@ -216,7 +224,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
   }
   pl.part = round_up((size_t)ndots_max(p) * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
   pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
-                 (pl.precond ? 256 : 0);
+                 (pl.precond ? 256 : 0) + (pl.vc ? round_up(4 * elems * 8, Arena::kAlign) : 0);
   return pl;
 }
 
@@ -233,7 +241,7 @@ size_t footprint_of(const cg_problem* p) {
   size_t n32 = fp32g ? 4 : 0;
   const size_t part = round_up((size_t)ndots_max(p) * g.tiles * 8, Arena::kAlign);
   return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256) +
-         (p->precond ? 256 : 0);
+         (p->precond ? 256 : 0) + (p->kx ? round_up(4 * elems * 8, Arena::kAlign) : 0);
 }
 
 // --------------------------------------------------------- profiling --
@@ -301,9 +309,12 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool chec
   hipEventRecord(e0, st);
   hipError_t rc = launch_pass(kind, fp32g, a, grid, st);
   hipEventRecord(e1, st);
+  // the variable-coefficient operator also reads its four coefficients per
+  // unknown in every pass that applies it
+  const int64_t dof = (int64_t)a.g.nx * a.g.ny;
+  const double kc_bytes = a.g.kc && kind != K_DOT ? 32.0 * (double)dof : 0.0;
   pending.push_back({e0, e1, check ? "final_check" : kind_name(kind, fp32g),
-                     check ? 0.0
-                           : (double)pass_algorithmic_bytes(kind, (int64_t)a.g.nx * a.g.ny)});
+                     check ? 0.0 : (double)pass_algorithmic_bytes(kind, dof) + kc_bytes});
   return rc;
 }
 
@@ -353,6 +364,7 @@ bool carve(Ctx& c, Work& w) {
   w.part[1] = (double*)take(pl.part);
   w.S[0] = (State*)take(round_up(sizeof(State), 256));
   w.S[1] = (State*)take(round_up(sizeof(State), 256));
+  if (pl.vc) w.kc = (double*)take(round_up(4 * (size_t)pl.g.pitch * pl.g.ny * 8, Arena::kAlign));
   return true;
 }
 
@@ -360,6 +372,7 @@ static PassArgs base_args(const Work& w) {
   PassArgs a;
   memset(&a, 0, sizeof(a));
   a.g = w.pl.g;
+  a.g.kc = w.kc;
   a.b = w.b;
   a.x = w.x;
   a.r = w.r;
@@ -476,8 +489,10 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     for (int k = 0; k < iters; ++k) HIPCHK(issue_iteration(c, w));
     return CG_OK;
   }
-  GraphKey key{w.mem,  w.pl.g.nx, w.pl.g.ny, w.pl.g.rows, w.pl.grid, w.pl.variant,
-               w.pl.refined, iters,     w.m & 1,   w.i & 1,     w.pl.precond};
+  const Plan& pl = w.pl;
+  GraphKey key{w.mem,
+               {pl.g.nx, pl.g.ny, pl.g.rows, pl.grid, pl.variant, pl.refined, iters, w.m & 1,
+                w.i & 1, pl.precond, pl.fp32g, pl.g.plane, pl.vc, pl.cheb_rows}};
   auto it = c.graphs.find(key);
   if (it == c.graphs.end()) {
     hipGraph_t g;
@@ -561,6 +576,15 @@ int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const State* pinned) {
   const size_t row = (size_t)p->nx * 8, pitch = (size_t)pl.g.pitch * 8;
   HIPCHK(hipMemcpy2DAsync(w.b, pitch, p->b, row, row, rows_of(p), kind, c.st));
   if (p->x0) HIPCHK(hipMemcpy2DAsync(w.x, pitch, p->x0, row, row, rows_of(p), kind, c.st));
+  if (pl.vc) {
+    // cell arrays of the face conductivities: west kx[j][i], east kx[j][i+1],
+    // south ky[j][i], north ky[j+1][i] (padding stays zero from the fill)
+    const size_t one = (size_t)pl.g.pitch * pl.g.ny, rx = (size_t)(p->nx + 1) * 8;
+    HIPCHK(hipMemcpy2DAsync(w.kc, pitch, p->kx, rx, row, p->ny, kind, c.st));
+    HIPCHK(hipMemcpy2DAsync(w.kc + one, pitch, p->kx + 1, rx, row, p->ny, kind, c.st));
+    HIPCHK(hipMemcpy2DAsync(w.kc + 2 * one, pitch, p->ky, row, row, p->ny, kind, c.st));
+    HIPCHK(hipMemcpy2DAsync(w.kc + 3 * one, pitch, p->ky + p->nx, row, row, p->ny, kind, c.st));
+  }
   HIPCHK(hipMemcpyAsync(w.S[0], pinned, sizeof(State), hipMemcpyHostToDevice, c.st));
   w.m = 0;
   w.i = 0;
@@ -785,8 +809,10 @@ int Ctx::solve(const cg_problem* p, cg_result* res) {
   return res->status;
 }
 
+// The caller's stream (the null stream when none was given) must reach this
+// point before the library reads any input: the library's own streams are
+// non-blocking, so nothing orders them after the null stream implicitly.
 int Ctx::order_after_user() {
-  if (!user_stream) return CG_OK;
   Ctx& c = *this;
   HIPCHK(hipEventRecord(user_ev, user_stream));
   HIPCHK(hipStreamWaitEvent(st, user_ev, 0));

@@ -26,6 +26,7 @@ struct Plan {
   int cheb_tiles = 0;  // ... partials of the Chebyshev pass
   int cheb_grid = 8;   // ... work-groups of the Chebyshev pass
   int fx_threads = 0;
+  bool vc = false;     // variable-coefficient operator (four coefficient arrays)
   bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};
   int grid = 8;      // work-groups per pass
@@ -38,16 +39,17 @@ struct Pin {
   int cpl = 0;  // columns per lane; 0 = default (2 for FP64, 4 for refined)
 };
 
+// A captured chunk of iterations holds every pass argument, so its key names
+// everything that shapes them: the workspace, the geometry and operator, the
+// iteration and the buffer parities.
 struct GraphKey {
   const void* mem;
-  int nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond;
+  int v[14];  // nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond,
+              // fp32g, plane, vc, cheb_rows
   bool operator<(const GraphKey& o) const {
-    const int a[] = {nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond};
-    const int b[] = {o.nx, o.ny, o.rows,  o.grid, o.variant, o.refined,
-                     o.iters, o.mpar, o.ipar, o.precond};
     if (mem != o.mem) return mem < o.mem;
-    for (int i = 0; i < 10; ++i)
-      if (a[i] != b[i]) return a[i] < b[i];
+    for (int i = 0; i < 14; ++i)
+      if (v[i] != o.v[i]) return v[i] < o.v[i];
     return false;
   }
 };
@@ -72,6 +74,7 @@ struct Work {
   float *rf = nullptr, *df = nullptr, *pf[2] = {};
   double* cheb = nullptr;  // preconditioner coefficients (c0, c1[s-1], c2[s-1])
   double *u = nullptr, *sv = nullptr, *mv = nullptr;  // preconditioned pipelined
+  double* kc = nullptr;  // variable coefficients: west, east, south, north arrays
   double* part[2] = {};
   cgk::State* S[2] = {};
   int m = 0;  // passes issued (state/partial parity)

@@ -32,7 +32,14 @@ namespace cgr {
 using namespace cgk;
 
 struct Job {
+  Job() = default;
+  Job(const Job&) = delete;
+  Job& operator=(const Job&) = delete;
+  ~Job() {
+    if (ready) hipEventDestroy(ready);
+  }
   cg_problem p;
+  hipEvent_t ready = nullptr;  // served request: the caller's stream at submission
   uint64_t ticket = 0;
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   Work w;
@@ -121,7 +128,11 @@ class Engine {
     State& s = h_admit_[slot];
     s = initial_state(&j->p);
     s.kind = j->w.pl.refined ? K_RESID : K_INIT_R;
-    int rc = stage_in_async(c_, j->w, &j->p, &s);
+    // a served request's inputs are complete once the caller's stream has
+    // passed the point of submission
+    int rc = j->ready && hipStreamWaitEvent(c_.st, j->ready, 0) != hipSuccess
+                 ? CG_E_DEVICE
+                 : stage_in_async(c_, j->w, &j->p, &s);
     if (rc) {
       hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
@@ -466,6 +477,14 @@ class Server {
     Job* j = new Job;
     j->p = *p;
     j->t_submit = now_s();
+    // the inputs may still be in flight on the caller's stream (the null
+    // stream when the context names none): remember where it stands now
+    if (hipSetDevice(c_.device) != hipSuccess ||
+        hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(j->ready, c_.user_stream) != hipSuccess) {
+      delete j;
+      return CG_E_DEVICE;
+    }
     {
       std::lock_guard<std::mutex> lk(m_);
       if (stopping_) {

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the five workload shapes (inputs only).
+"""Seeded synthetic inputs for the workload shapes (inputs only).
 
 This module holds no arithmetic of the method: it draws right-hand sides,
 manufactured solutions, grid sizes, tolerances and arrival times.  Both the
@@ -133,3 +133,23 @@ CUBE = dict(n=256, tol=1e-8, maxit=20000, iterations=500)
 def cube_rhs(n: int) -> np.ndarray:
     """b i.i.d. uniform[-1, 1] on an n^3 grid, as n*n rows of n (plane-major)."""
     return uniform_rhs(n, n * n, generator(5))
+
+
+# -- the variable-coefficient 5-point operator: 4096 x 4096, face
+#    conductivities i.i.d. log-uniform over two decades [0.1, 10], b ~ U[-1,1],
+#    a fixed 500 iterations, then tol 1e-8 --
+VC = dict(n=4096, tol=1e-8, maxit=60000, iterations=500, k_lo=0.1, k_hi=10.0)
+
+
+def vc_faces(nx: int, ny: int, lo: float = 0.1, hi: float = 10.0):
+    """(kx, ky): conductivities of the faces between columns, (ny, nx + 1), and
+    between rows, (ny + 1, nx), each i.i.d. exp(U[log lo, log hi])."""
+    rng = generator(6)
+    kx = np.exp(rng.uniform(math.log(lo), math.log(hi), (ny, nx + 1)))
+    ky = np.exp(rng.uniform(math.log(lo), math.log(hi), (ny + 1, nx)))
+    return kx, ky
+
+
+def vc_rhs(nx: int, ny: int) -> np.ndarray:
+    """b i.i.d. uniform[-1, 1] for the variable-coefficient workload."""
+    return uniform_rhs(nx, ny, generator(6, 1))

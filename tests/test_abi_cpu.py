@@ -36,11 +36,11 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(nx=10, ny=7, mem=cg.CG_MEM_HOST, b=1, x0=None, x=2, tol=1e-8, maxit=10,
-             variant=0, precision=0, inner_tol=0.0, precond=0, nz=0)
+             variant=0, precision=0, inner_tol=0.0, precond=0, nz=0, kx=None, ky=None)
     d.update(kw)
     return cg.cg_problem(d["nx"], d["ny"], d["mem"], d["b"], d["x0"], d["x"], d["tol"],
                          d["maxit"], d["variant"], d["precision"], d["inner_tol"],
-                         d["precond"], d["nz"])
+                         d["precond"], d["nz"], 0, d["kx"], d["ky"])
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
@@ -55,7 +55,10 @@ def _prob(**kw):
                                  dict(precond=4, precision=1),
                                  dict(precond=4, precision=2),
                                  dict(nz=-1), dict(nz=3, precond=2), dict(nz=3, precision=1),
-                                 dict(nz=3, precision=2), dict(nx=2048, ny=2048, nz=1024)])
+                                 dict(nz=3, precision=2), dict(nx=2048, ny=2048, nz=1024),
+                                 dict(kx=3), dict(ky=4), dict(kx=3, ky=4, nz=2),
+                                 dict(kx=3, ky=4, precond=2), dict(kx=3, ky=4, precision=1),
+                                 dict(kx=3, ky=4, precision=2)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -71,6 +74,10 @@ def test_validation_accepts():
     for nz in (0, 1, 2, 64):
         for v in (0, 1):
             assert cg.cg_validate(_prob(nz=nz, variant=v)) == cg.CG_OK
+    # variable coefficients: 2D FP64, either variant (nz = 1 is 2D)
+    for v in (0, 1):
+        for nz in (0, 1):
+            assert cg.cg_validate(_prob(kx=3, ky=4, variant=v, nz=nz)) == cg.CG_OK
     # Chebyshev preconditioner: 1..8 steps, FP64, either variant
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
@@ -79,11 +86,15 @@ def test_validation_accepts():
 
 def test_footprint_per_unknown():
     """Resident bytes per unknown: classic 5 FP64 vectors, pipelined 8, refined
-    2 FP64 + 4 FP32, preconditioned classic 6 (plus padding and small
-    partial/state buffers)."""
+    2 FP64 + 4 FP32, preconditioned classic 6, variable coefficients 4 more
+    (plus padding and small partial/state buffers)."""
     n = 4096
     for variant, prec, per, pre in ((0, 0, 40, 0), (1, 0, 64, 0), (0, 1, 32, 0), (0, 0, 48, 4)):
         fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, precision=prec, precond=pre))
+        assert per * n * n <= fp <= per * n * n * 1.01 + (1 << 20)
+    # variable coefficients: four more FP64 arrays (west, east, south, north)
+    for variant, per in ((0, 72), (1, 96)):
+        fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, kx=3, ky=4))
         assert per * n * n <= fp <= per * n * n * 1.01 + (1 << 20)
 
 

@@ -1,8 +1,10 @@
 """GPU tests of the runtime around the kernels: autotuner and its cache, pinned
 tile shapes (the reduction order follows the shape), profiling statistics,
-the HBM probe, and a caller-provided arena tensor and stream."""
+the HBM probe, a caller-provided arena tensor and stream, and the ordering
+after the null stream when the caller names none."""
 import json
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -154,3 +156,50 @@ def test_caller_arena_and_stream(torch):
     h = C.c_void_p()
     cfg = cg.cg_config(0, None, arena.data_ptr(), 0, 0, None)
     assert cg.load().cg_create(C.byref(cfg), C.byref(h)) == cg.CG_E_INVALID
+
+
+def test_null_stream_ordering(torch):
+    """A context without a stream orders every call after the null stream:
+    inputs that the caller's kernels are still writing (a backlog of products
+    queued ahead of the final copy into b) are read only once written, by
+    cg_solve, cg_solve_batch and cg_submit alike."""
+    nx, ny = 600, 500
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(np.random.default_rng(8).uniform(-1, 1, (ny, nx))).to(dev)
+    big = torch.randn(4096, 4096, dtype=torch.float64, device=dev)
+    with cg.Context(device=0, arena_bytes=1 << 30) as ctx:
+        torch.cuda.synchronize()
+        want = torch.zeros_like(src)
+        ctx.solve(src, want, nx, ny, tol=1e-9, maxit=5000)
+        want = want.cpu().numpy()
+
+        def pending_rhs():
+            b = torch.zeros_like(src)
+            t = big
+            for _ in range(24):
+                t = t @ big  # about 0.1 s of queued work on the null stream
+            b.copy_(src + 0.0 * t[:ny, :nx])
+            return b
+
+        b = pending_rhs()
+        x = torch.zeros_like(b)
+        rc, r = ctx.solve(b, x, nx, ny, tol=1e-9, maxit=5000)
+        assert rc == cg.CG_OK
+        np.testing.assert_array_equal(x.cpu().numpy(), want)
+        b = pending_rhs()
+        x = torch.zeros_like(b)
+        rc, rs = ctx.cg_solve_batch([cg.make_problem(b, x, nx, ny, tol=1e-9, maxit=5000)])
+        assert rc == cg.CG_OK and rs[0].iterations == r.iterations
+        np.testing.assert_array_equal(x.cpu().numpy(), want)
+        b = pending_rhs()
+        x = torch.zeros_like(b)
+        t = ctx.cg_submit(cg.make_problem(b, x, nx, ny, tol=1e-9, maxit=5000))
+        deadline = time.time() + 60
+        while True:
+            rc, rp = ctx.cg_poll(t)
+            if rc != cg.CG_PENDING or time.time() > deadline:
+                break
+            time.sleep(0.001)
+        assert rc == cg.CG_OK and rp.iterations == r.iterations
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(x.cpu().numpy(), want)

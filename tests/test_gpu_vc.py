@@ -1,0 +1,243 @@
+"""GPU parity of both CG variants on the variable-coefficient 5-point operator
+(cg_problem.kx / ky): the tile passes with the four face conductivities of
+each cell, against the variable-coefficient oracle in the library's tile
+order (bitwise) and in the textbook order (FP64 tolerance); at 4096^2 a
+bitwise lockstep and, with separable conductivities, single-mode and
+finite-termination properties."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from oracle import MODE_CANONICAL, MODE_SEQUENTIAL
+from paper_1803_03797_amd import cg
+
+pytestmark = pytest.mark.gpu
+
+# single cells, single rows and columns, ragged tiles, several tile columns
+SHAPES = [(1, 1), (2, 3), (64, 1), (1, 70), (130, 7), (37, 40), (257, 300), (500, 129)]
+VARIANTS = (cg.CG_VARIANT_CLASSIC, cg.CG_VARIANT_PIPELINED)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = cg.Context(device=0, arena_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def faces(nx, ny, seed, lo=0.25, hi=4.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, (ny, nx + 1)), rng.uniform(lo, hi, (ny + 1, nx))
+
+
+def tile_order(ctx, nx, ny, variant):
+    info = ctx.cg_plan(nx, ny, variant=variant, vc=True)
+    assert info.path == 0 and info.cols_per_lane == 2
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb else 1.0)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_lockstep_bitwise(ctx, nx, ny, variant):
+    kx, ky = faces(nx, ny, nx + 7 * ny)
+    b = np.random.default_rng(nx + 3 * ny).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, variant)
+    for m in (1, 2, 7):
+        say("vc lockstep", nx, ny, "variant", variant, "maxit", m)
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, nx, ny, tol=0.0, maxit=m, variant=variant, kx=kx, ky=ky)
+        xo, ro = oracle.cg_vc(b, nx, ny, kx, ky, variant=variant, tol=0.0, maxit=m,
+                              mode=MODE_CANONICAL, order=o)
+        assert rc == ro.status and res.iterations == ro.iterations
+        np.testing.assert_array_equal(x, xo)
+        assert res.rel_res_recursive == ro.rel_res_recursive
+        assert res.rel_res_true == ro.rel_res_true
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("nx,ny", [(37, 40), (200, 150)])
+def test_natural_stop(ctx, nx, ny, variant):
+    kx, ky = faces(nx, ny, 5 * nx + ny)
+    b = np.random.default_rng(3 * nx + ny).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, variant)
+    say("vc natural stop", nx, ny, "variant", variant)
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-8, maxit=20000, variant=variant, kx=kx, ky=ky)
+    xk, rk = oracle.cg_vc(b, nx, ny, kx, ky, variant=variant, tol=1e-8, maxit=20000,
+                          mode=MODE_CANONICAL, order=o)
+    xs, rs = oracle.cg_vc(b, nx, ny, kx, ky, variant=variant, tol=1e-8, maxit=20000,
+                          mode=MODE_SEQUENTIAL)
+    assert rc == cg.CG_OK and res.iterations == rk.iterations
+    np.testing.assert_array_equal(x, xk)
+    assert abs(res.iterations - rs.iterations) <= 3
+    say("  iterations %d, textbook-order spread %.2e, true residual %.3g" %
+        (res.iterations, rel(x, xs), res.rel_res_true))
+    assert rel(x, xs) <= (1e-9 if variant == cg.CG_VARIANT_CLASSIC else 1e-8)
+    assert res.rel_res_true <= (1.2e-8 if variant == cg.CG_VARIANT_CLASSIC else 1e-7)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_unit_coefficients_are_the_5_point_operator(ctx, variant):
+    """k = 1 everywhere: d = 4 and every product exact, so the solve is the
+    5-point one bitwise (same tile passes, same order)."""
+    for nx, ny in ((300, 200), (1000, 77)):
+        kx, ky = np.ones((ny, nx + 1)), np.ones((ny + 1, nx))
+        b = np.random.default_rng(nx).uniform(-1, 1, (ny, nx))
+        say("vc unit coefficients", nx, ny, "variant", variant)
+        assert ctx.cg_plan(nx, ny, variant=variant).path == 0
+        for m, tol in ((5, 0.0), (20000, 1e-9)):
+            x1, x2 = np.zeros_like(b), np.zeros_like(b)
+            rc1, r1 = ctx.solve(b, x1, nx, ny, tol=tol, maxit=m, variant=variant, kx=kx, ky=ky)
+            rc2, r2 = ctx.solve(b, x2, nx, ny, tol=tol, maxit=m, variant=variant)
+            assert rc1 == rc2 and r1.iterations == r2.iterations
+            np.testing.assert_array_equal(x1, x2)
+            assert r1.rel_res_true == r2.rel_res_true
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_lockstep(ctx, torch, variant):
+    """4096^2 with random conductivities in [0.25, 4], vectors and
+    coefficients resident on the device: two iterations bitwise against the
+    oracle in the library's tile order."""
+    n = 4096
+    kx, ky = faces(n, n, 11)
+    b = np.random.default_rng(12).uniform(-1, 1, (n, n))
+    o = tile_order(ctx, n, n, variant)
+    say("vc full-size lockstep", variant)
+    dev = torch.device("cuda:0")
+    bt, kxt, kyt = (torch.from_numpy(a).to(dev) for a in (b, kx, ky))
+    xt = torch.zeros_like(bt)
+    rc, res = ctx.cg_solve(cg.make_problem(bt, xt, n, n, tol=0.0, maxit=2, variant=variant,
+                                           kx=kxt, ky=kyt))
+    xo, ro = oracle.cg_vc(b, n, n, kx, ky, variant=variant, tol=0.0, maxit=2,
+                          mode=MODE_CANONICAL, order=o)
+    assert rc == ro.status and res.iterations == 2
+    np.testing.assert_array_equal(xt.cpu().numpy(), xo)
+    assert res.rel_res_true == ro.rel_res_true
+
+
+def tridiag_modes(g, idx):
+    """Eigenpairs number idx (ascending) of the 1D operator with face
+    conductivities g (len m + 1): diagonal g[i] + g[i+1], off-diagonal -g[i]."""
+    d = g[:-1] + g[1:]
+    e = -g[1:-1]
+    out = []
+    for i in idx:
+        w, v = sla.eigh_tridiagonal(d, e, select="i", select_range=(i, i))
+        out.append((w[0], v[:, 0]))
+    return out
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_separable_modes(ctx, torch, variant):
+    """4096^2 with kx depending on the column only and ky on the row only:
+    A = I (x) T_x + T_y (x) I, whose eigenvectors are products of the 1D
+    ones.  One such mode takes one iteration to x = b / lambda; four with
+    distinct eigenvalues take four (or five) to the closed-form solution."""
+    n = 4096
+    rng = np.random.default_rng(21)
+    gx, gy = rng.uniform(0.5, 3.0, n + 1), rng.uniform(0.5, 3.0, n + 1)
+    kx, ky = np.tile(gx, (n, 1)), np.tile(gy[:, None], (1, n))
+    mx = tridiag_modes(gx, (700, 1500, 2300, 3100))
+    my = tridiag_modes(gy, (900, 1700, 2500, 3300))
+    dev = torch.device("cuda:0")
+    kxt, kyt = torch.from_numpy(kx).to(dev), torch.from_numpy(ky).to(dev)
+
+    def mode(a, b):
+        return torch.from_numpy(np.outer(my[b][1], mx[a][1])).to(dev), mx[a][0] + my[b][0]
+
+    phi, lam = mode(1, 2)
+    x = torch.zeros_like(phi)
+    rc, res = ctx.cg_solve(cg.make_problem(phi, x, n, n, tol=1e-8, maxit=10, variant=variant,
+                                           kx=kxt, ky=kyt))
+    err = float(torch.linalg.norm(x - phi / lam) / torch.linalg.norm(phi / lam))
+    say("vc single mode", variant, res.iterations, "err %.2e" % err)
+    assert rc == cg.CG_OK and res.iterations == 1 and err <= 1e-11
+    pairs = [(0, 0), (1, 3), (2, 1), (3, 2)]
+    coef = [1.0, -0.5, 0.25, 0.125]
+    ms = [mode(a, b) for a, b in pairs]
+    assert len({round(l, 6) for _, l in ms}) == 4
+    b = sum(c * m for c, (m, _) in zip(coef, ms))
+    xw = sum((c / l) * m for c, (m, l) in zip(coef, ms))
+    x = torch.zeros_like(b)
+    rc, res = ctx.cg_solve(cg.make_problem(b, x, n, n, tol=1e-10, maxit=50, variant=variant,
+                                           kx=kxt, ky=kyt))
+    err = float(torch.linalg.norm(x - xw) / torch.linalg.norm(xw))
+    say("vc finite termination", variant, res.iterations, "err %.2e" % err)
+    assert rc == cg.CG_OK and res.iterations in (4, 5) and err <= 1e-10
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_edge_cases(ctx, variant):
+    nx, ny = 150, 90
+    kx, ky = faces(nx, ny, 4)
+    b = np.random.default_rng(4).uniform(-1, 1, (ny, nx))
+    o = tile_order(ctx, nx, ny, variant)
+    kw = dict(variant=variant, kx=kx, ky=ky)
+    x = np.full_like(b, 2.0)
+    rc, res = ctx.solve(np.zeros_like(b), x, nx, ny, x0=np.ones_like(b), **kw)
+    assert rc == cg.CG_OK and res.iterations == 0 and not x.any()
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-14, maxit=3, **kw)
+    assert rc == cg.CG_NOT_CONVERGED and res.iterations == 3
+    b2 = b.copy()
+    b2[5, 5] = np.nan
+    rc, res = ctx.solve(b2, x, nx, ny, **kw)
+    assert rc == cg.CG_BREAKDOWN and res.iterations == 0
+    x0 = np.random.default_rng(6).uniform(-1, 1, (ny, nx))
+    x = x0.copy()
+    rc, res = ctx.solve(b, x, nx, ny, x0=x, tol=1e-9, maxit=5000, **kw)
+    xo, ro = oracle.cg_vc(b, nx, ny, kx, ky, variant=variant, tol=1e-9, maxit=5000, x0=x0,
+                          mode=MODE_CANONICAL, order=o)
+    assert rc == cg.CG_OK and res.iterations == ro.iterations
+    np.testing.assert_array_equal(x, xo)
+    # strongly varying conductivities (six decades): still bitwise in lockstep
+    rng = np.random.default_rng(9)
+    kx2, ky2 = 10.0 ** rng.uniform(-3, 3, kx.shape), 10.0 ** rng.uniform(-3, 3, ky.shape)
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=0.0, maxit=25, variant=variant, kx=kx2, ky=ky2)
+    xo, ro = oracle.cg_vc(b, nx, ny, kx2, ky2, variant=variant, tol=0.0, maxit=25,
+                          mode=MODE_CANONICAL, order=o)
+    np.testing.assert_array_equal(x, xo)
+
+
+def test_rejections(ctx):
+    nx, ny = 16, 12
+    kx, ky = faces(nx, ny, 1)
+    b = np.ones((ny, nx))
+    x = np.zeros_like(b)
+    p = cg.make_problem(b, x, nx, ny, kx=kx, ky=ky)
+    with pytest.raises(cg.CGError):
+        ctx.cg_solve_batch([p])
+    with pytest.raises(cg.CGError):
+        ctx.cg_submit(p)
+    for kw in (dict(precond=4), dict(precision=cg.CG_PREC_FP32_REFINED),
+               dict(precision=cg.CG_PREC_FIXED)):
+        with pytest.raises(cg.CGError):
+            ctx.solve(b, x, nx, ny, kx=kx, ky=ky, **kw)
+    with pytest.raises(cg.CGError):
+        ctx.solve(np.ones((ny * 3, nx)), np.zeros((ny * 3, nx)), nx, ny, nz=3,
+                  kx=kx, ky=np.ones((ny + 1, nx)))
+    with pytest.raises(ValueError):
+        cg.make_problem(b, x, nx, ny, kx=kx)
+    with pytest.raises(ValueError):
+        cg.make_problem(b, x, nx, ny, kx=kx[:, :-1].copy(), ky=ky)
