@@ -59,6 +59,9 @@ BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
 # copy kernel gives for the same counters); set to None whenever pcg_pass
 # changes, until the counters are taken again.
 PCG_TRAFFIC_BYTES = 1634008205
+# The same for pcg_pass of the variable-coefficient operator at 4096 x 4096
+# (128 algorithmic bytes per unknown: 96 of vectors, 32 of coefficients).
+VC_TRAFFIC_BYTES = 2183685888
 # Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
 # iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
 # pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
@@ -694,7 +697,8 @@ def bench_vc(args):
         roof = {"bound": "hbm", "kernel": "pcg_pass (variable coefficients)",
                 "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "avg_launch_us": pk["avg_us"],
-                "bytes_per_launch": per_launch, "traffic": None}
+                "bytes_per_launch": per_launch,
+                "traffic": VC_TRAFFIC_BYTES if n == 4096 else None}
     cpu = None
     if not args.no_cpu:
         import oracle
