@@ -171,14 +171,17 @@ typedef struct {
   int32_t cols_per_lane, lanes, waves, rows, threads2;
   int32_t tiles;            /* tiles per pass                                        */
   int32_t grid;             /* work-groups per pass launch                           */
-  int32_t pitch;            /* padded row length in elements                         */
+  int32_t pitch;            /* padded row length of one vector, in elements          */
   int32_t seg_rows;         /* path 2: rows per thread; else 0                       */
   int32_t seg_waves;        /* path 2: wavefronts of the work-group; else 0          */
   int32_t seg_cols;         /* path 2: threads per row of segments (nx + 1); else 0  */
   int32_t cheb_rows;        /* precond > 0: rows of a Chebyshev tile; else 0         */
   int32_t cheb_tiles;       /* precond > 0: Chebyshev tiles (partials of (r,z))      */
   int32_t cheb_grid;        /* precond > 0: work-groups of the Chebyshev pass        */
-  int32_t pad_;
+  int32_t row_stride;       /* elements from a row of a device vector to its next:
+                               pitch, or pitch times the number of FP64 vectors
+                               whose rows the workspace interleaves (pipelined
+                               FP64 on path 0 without the preconditioner)          */
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 

@@ -133,7 +133,8 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   info->threads2 = cgk::kGroup;
   info->tiles = pl.g.tiles;
   info->grid = pl.grid;
-  info->pitch = pl.g.pitch;
+  info->pitch = pl.width;
+  info->row_stride = pl.g.pitch;
   info->cheb_rows = pl.cheb_rows;
   info->cheb_tiles = pl.cheb_tiles;
   info->cheb_grid = pl.precond ? pl.cheb_grid : 0;

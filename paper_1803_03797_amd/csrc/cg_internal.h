@@ -74,16 +74,21 @@ constexpr int32_t K_FINAL = 100;  // step engine: sum the true residual, then do
 constexpr int32_t K_DONE = -1;    // step engine: nothing left to run
 
 struct Geo {
-  int32_t nx, ny, pitch;
+  int32_t nx, ny;
+  int32_t pitch;     // row stride of every vector of the solve, in elements: the
+                     // padded row length ntx * 64 * cols_per_lane, times the
+                     // number of FP64 vectors whose rows are interleaved (one
+                     // row of each vector after the other) on the tile passes
   int32_t ntx, nty, tiles;
   int32_t rows;      // rows per wavefront strip
   int32_t th;        // rows per tile = 4 * rows
   int32_t plane;     // 3D (7-point operator): rows per plane, ny = plane * nz; 2D: 0
   int32_t pad_;
   // variable-coefficient 5-point operator: the west, east, south and north
-  // face conductivities of every cell, four arrays of ny * pitch one after the
-  // other, each laid out like a vector (zero in the padding); null otherwise
+  // face conductivities of every cell, four arrays laid out like a vector
+  // (zero in the padding), kcs elements apart; null otherwise
   const double* kc;
+  int64_t kcs;
 };
 
 // Pass kinds.

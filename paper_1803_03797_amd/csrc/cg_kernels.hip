@@ -731,7 +731,7 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
   int jp = D3 ? s.j0 % pl : 0;  // row within its plane
   // variable coefficients: the row's four face conductivities, PD rows ahead
   using K = Kc<T, CPL>;
-  const size_t kst = (size_t)g.ny * P;  // one coefficient array
+  const size_t kst = (size_t)g.kcs;  // from one coefficient array to the next
   auto kload = [&](size_t off) {
     K k;
     if constexpr (VC) {
@@ -1704,14 +1704,14 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
     c2[k] = uniform(a.cheb[S + k]);
   }
   ChebCtx c;
-  // columns: the load address is valid for 0 <= cl < pitch (pitch is a
-  // multiple of 128 and cl is even, so the pair stays in the row)
+  // columns: the load address is valid for 0 <= cl < the padded row length
+  // (a multiple of 128; cl is even, so the pair stays in the row)
   c.v0 = c.v1 = true;
   int lc = cl;
   if constexpr (MASK) {
     c.v0 = cl >= 0 && cl < gg.nx;
     c.v1 = cl >= 0 && cl + 1 < gg.nx;
-    lc = (cl >= 0 && cl < gg.pitch) ? cl : 0;
+    lc = (cl >= 0 && cl < gg.ntx * 2 * kWave) ? cl : 0;
   }
   c.R = a.r + lc;
   c.Z = a.z + cl;

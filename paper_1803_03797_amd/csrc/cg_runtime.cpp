@@ -129,7 +129,7 @@ bool Ctx::use_rr(const cg_problem* p) const {
          !p->kx && rr_threads_needed(p->nx, p->ny) <= kRrThreads;
 }
 
-Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
+Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   Plan pl;
   const int ny = rows_of(p);
   pl.variant = p->variant;
@@ -195,7 +195,8 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     const int tpb = (T + cap - 1) / cap;          // tiles per work-group
     pl.grid = (int)round_up((size_t)((T + tpb - 1) / tpb), 8);
   }
-  const size_t elems = (size_t)pl.g.pitch * ny;
+  pl.width = pl.g.pitch;
+  const size_t elems = (size_t)pl.width * ny;
   pl.v64 = round_up(elems * 8, Arena::kAlign);
   pl.v32 = round_up(elems * 4, Arena::kAlign);
   int n64, n32 = 0;
@@ -223,8 +224,24 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr) {
     pl.cheb_grid = (int)round_up((size_t)std::min(ngx * ntyc, slots), 8);
   }
   pl.part = round_up((size_t)ndots_max(p) * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
-  pl.footprint = n64 * pl.v64 + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
-                 (pl.precond ? 256 : 0) + (pl.vc ? round_up(4 * elems * 8, Arena::kAlign) : 0);
+  // Pipelined FP64 tile passes: the rows of all vectors interleaved, row j
+  // of every vector after the other, so that a pass streams one region
+  // instead of seven (a six-vector read-modify-write probe: 5.7-5.9 TB/s with
+  // interleaved rows against 4.6-5.1 TB/s with separate vectors; pcg_pass at
+  // 4096^2 312 -> 295 us).  The classic passes touch three or four of their
+  // five vectors and measured slower interleaved (update_norm 143 -> 155 us),
+  // so they keep separate vectors.
+  size_t vec_bytes = n64 * pl.v64 + (pl.vc ? round_up(4 * elems * 8, Arena::kAlign) : 0);
+  pl.g.kcs = (int64_t)elems;
+  if (interleave && !pl.wg && !pl.refined && !pl.precond && !pl.fixed &&
+      p->variant == CG_VARIANT_PIPELINED) {
+    pl.il = n64 + (pl.vc ? 4 : 0);
+    pl.g.pitch = pl.width * pl.il;
+    pl.g.kcs = pl.width;
+    vec_bytes = round_up((size_t)pl.il * elems * 8, Arena::kAlign);
+  }
+  pl.footprint = vec_bytes + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
+                 (pl.precond ? 256 : 0);
   return pl;
 }
 
@@ -321,6 +338,9 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool chec
 // ---------------------------------------------------------------- solve --
 
 bool carve(Ctx& c, Work& w) {
+  // an interleaved block holds exactly the vectors carved from it below
+  if (w.pl.il > 1 && (w.pl.variant != CG_VARIANT_PIPELINED || w.pl.il != 8 + (w.pl.vc ? 4 : 0)))
+    return false;
   w.mem = (char*)c.arena.alloc(w.pl.footprint);
   if (!w.mem) return false;
   char* q = w.mem;
@@ -330,6 +350,30 @@ bool carve(Ctx& c, Work& w) {
     return r;
   };
   const Plan& pl = w.pl;
+  if (pl.il > 1) {
+    // one block, the vectors' rows interleaved: vector k starts k rows of
+    // one vector in
+    double* blk = (double*)take(round_up((size_t)pl.il * pl.width * pl.g.ny * 8, Arena::kAlign));
+    int k = 0;
+    auto vec = [&]() { return blk + (size_t)(k++) * pl.width; };
+    w.b = vec();
+    w.x = vec();
+    w.r = vec();
+    w.w[0] = vec();
+    w.w[1] = vec();
+    w.z = vec();
+    w.q = vec();
+    w.p = vec();
+    if (pl.vc) {
+      w.kc = vec();  // west; east, south and north follow, width apart
+      k += 3;
+    }
+    w.part[0] = (double*)take(pl.part);
+    w.part[1] = (double*)take(pl.part);
+    w.S[0] = (State*)take(round_up(sizeof(State), 256));
+    w.S[1] = (State*)take(round_up(sizeof(State), 256));
+    return true;
+  }
   w.b = (double*)take(pl.v64);
   w.x = (double*)take(pl.v64);
   if (pl.refined) {
@@ -579,7 +623,7 @@ int stage_in_async(Ctx& c, Work& w, const cg_problem* p, const State* pinned) {
   if (pl.vc) {
     // cell arrays of the face conductivities: west kx[j][i], east kx[j][i+1],
     // south ky[j][i], north ky[j+1][i] (padding stays zero from the fill)
-    const size_t one = (size_t)pl.g.pitch * pl.g.ny, rx = (size_t)(p->nx + 1) * 8;
+    const size_t one = (size_t)pl.g.kcs, rx = (size_t)(p->nx + 1) * 8;
     HIPCHK(hipMemcpy2DAsync(w.kc, pitch, p->kx, rx, row, p->ny, kind, c.st));
     HIPCHK(hipMemcpy2DAsync(w.kc + one, pitch, p->kx + 1, rx, row, p->ny, kind, c.st));
     HIPCHK(hipMemcpy2DAsync(w.kc + 2 * one, pitch, p->ky, row, row, p->ny, kind, c.st));
@@ -833,7 +877,7 @@ int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u
   p.precision = CG_PREC_FP64;
   // the tile geometry (hence reduction order) of this shape; always run by
   // the multi-work-group pass kernels
-  Plan pl = plan(&p, false);
+  Plan pl = plan(&p, false, false);
   if (pl.wg) {
     const int cap = std::max(8, pass_max_blocks_per_cu(kind, 0) * num_cu);
     pl.grid = (int)round_up((size_t)std::min(pl.g.tiles, cap), 8);

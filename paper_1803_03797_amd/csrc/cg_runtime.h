@@ -27,6 +27,8 @@ struct Plan {
   int cheb_grid = 8;   // ... work-groups of the Chebyshev pass
   int fx_threads = 0;
   bool vc = false;     // variable-coefficient operator (four coefficient arrays)
+  int width = 0;       // padded row length of one vector, in elements
+  int il = 1;          // FP64 vectors with interleaved rows (g.pitch = il * width)
   bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};
   int grid = 8;      // work-groups per pass
@@ -146,7 +148,9 @@ struct Ctx {
   bool use_rr(const cg_problem* p) const;
   // allow_rr = false: the tile geometry even where the register-resident
   // solver would run the problem (building blocks use tiles)
-  Plan plan(const cg_problem* p, bool allow_rr = true);
+  // interleave: lay the FP64 vectors of a tile-pass solve out with their rows
+  // interleaved (off for the building blocks' scratch vectors)
+  Plan plan(const cg_problem* p, bool allow_rr = true, bool interleave = true);
   int solve(const cg_problem* p, cg_result* res);
   int solve_batch(const cg_problem* p, int n, cg_result* res);
   int apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u, const double* y_in,

@@ -203,3 +203,23 @@ def test_null_stream_ordering(torch):
         assert rc == cg.CG_OK and rp.iterations == r.iterations
         torch.cuda.synchronize()
         np.testing.assert_array_equal(x.cpu().numpy(), want)
+
+
+def test_interleaved_rows_layout():
+    """Pipelined FP64 tile-pass solves lay their vectors out with interleaved
+    rows (row stride = padded width x vectors); the other paths keep one
+    vector per region.  The results do not depend on it (every pipelined
+    parity test on path 0 runs on it)."""
+    with cg.Context(device=0, arena_bytes=1 << 30) as ctx:
+        n = 1024
+        for kw, vecs in ((dict(variant=0), 1), (dict(variant=1), 8),
+                         (dict(variant=0, vc=True), 1), (dict(variant=1, vc=True), 12),
+                         (dict(variant=1, nz=4), 8), (dict(variant=0, precond=4), 1),
+                         (dict(variant=1, precond=4), 1),
+                         (dict(variant=0, precision=cg.CG_PREC_FP32_REFINED), 1)):
+            info = ctx.cg_plan(n, n, **kw)
+            assert info.path == 0
+            assert info.row_stride == vecs * info.pitch, (kw, info.row_stride, info.pitch)
+        for kw in (dict(variant=0), dict(variant=1), dict(precision=cg.CG_PREC_FIXED)):
+            info = ctx.cg_plan(100, 100, **kw)
+            assert info.path != 0 and info.row_stride == info.pitch
