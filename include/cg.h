@@ -181,7 +181,7 @@ typedef struct {
   int32_t row_stride;       /* elements from a row of a device vector to its next:
                                pitch, or pitch times the number of FP64 vectors
                                whose rows the workspace interleaves (pipelined
-                               FP64 on path 0 without the preconditioner)          */
+                               FP64 on path 0)                                     */
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 

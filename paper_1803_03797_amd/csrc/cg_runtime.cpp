@@ -233,8 +233,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   // so they keep separate vectors.
   size_t vec_bytes = n64 * pl.v64 + (pl.vc ? round_up(4 * elems * 8, Arena::kAlign) : 0);
   pl.g.kcs = (int64_t)elems;
-  if (interleave && !pl.wg && !pl.refined && !pl.precond && !pl.fixed &&
-      p->variant == CG_VARIANT_PIPELINED) {
+  if (interleave && !pl.wg && !pl.refined && !pl.fixed && p->variant == CG_VARIANT_PIPELINED) {
     pl.il = n64 + (pl.vc ? 4 : 0);
     pl.g.pitch = pl.width * pl.il;
     pl.g.kcs = pl.width;
@@ -339,7 +338,8 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool chec
 
 bool carve(Ctx& c, Work& w) {
   // an interleaved block holds exactly the vectors carved from it below
-  if (w.pl.il > 1 && (w.pl.variant != CG_VARIANT_PIPELINED || w.pl.il != 8 + (w.pl.vc ? 4 : 0)))
+  if (w.pl.il > 1 && (w.pl.variant != CG_VARIANT_PIPELINED ||
+                      w.pl.il != (w.pl.precond ? 10 : 8) + (w.pl.vc ? 4 : 0)))
     return false;
   w.mem = (char*)c.arena.alloc(w.pl.footprint);
   if (!w.mem) return false;
@@ -360,7 +360,13 @@ bool carve(Ctx& c, Work& w) {
     w.x = vec();
     w.r = vec();
     w.w[0] = vec();
-    w.w[1] = vec();
+    if (pl.precond) {
+      w.u = vec();
+      w.mv = vec();
+      w.sv = vec();
+    } else {
+      w.w[1] = vec();
+    }
     w.z = vec();
     w.q = vec();
     w.p = vec();
@@ -368,6 +374,7 @@ bool carve(Ctx& c, Work& w) {
       w.kc = vec();  // west; east, south and north follow, width apart
       k += 3;
     }
+    if (pl.precond) w.cheb = (double*)take(256);
     w.part[0] = (double*)take(pl.part);
     w.part[1] = (double*)take(pl.part);
     w.S[0] = (State*)take(round_up(sizeof(State), 256));

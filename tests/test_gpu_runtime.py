@@ -215,7 +215,7 @@ def test_interleaved_rows_layout():
         for kw, vecs in ((dict(variant=0), 1), (dict(variant=1), 8),
                          (dict(variant=0, vc=True), 1), (dict(variant=1, vc=True), 12),
                          (dict(variant=1, nz=4), 8), (dict(variant=0, precond=4), 1),
-                         (dict(variant=1, precond=4), 1),
+                         (dict(variant=1, precond=4), 10),
                          (dict(variant=0, precision=cg.CG_PREC_FP32_REFINED), 1)):
             info = ctx.cg_plan(n, n, **kw)
             assert info.path == 0
