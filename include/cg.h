@@ -217,7 +217,7 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
  * queued requests in order when the device footprint fits the free arena and
  * a slot is free; admitted requests join the resident set at the next chunk
  * of steps (or run whole on the on-chip solver) and are retired when final.
- * The request's b, x0 and coefficients are read only once the caller's stream
+ * The request's b and x0 are read only once the caller's stream
  * (cg_config.stream) has passed the point of this call; x is written before
  * cg_poll returns the final status.  CG_E_NOMEM if its footprint exceeds
  * arena_bytes; CG_E_DEVICE if the ordering event cannot be recorded. */
