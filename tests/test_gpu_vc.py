@@ -241,3 +241,27 @@ def test_rejections(ctx):
         cg.make_problem(b, x, nx, ny, kx=kx)
     with pytest.raises(ValueError):
         cg.make_problem(b, x, nx, ny, kx=kx[:, :-1].copy(), ky=ky)
+
+
+def test_profiled_passes(ctx):
+    """Each stencil pass counts the four coefficient arrays (32 B per unknown)
+    in its algorithmic bytes; profiling (no graphs) leaves the result bitwise."""
+    n, m = 512, 6
+    kx, ky = faces(n, n, 3)
+    b = np.random.default_rng(1).uniform(-1, 1, (n, n))
+    for variant, passes in ((cg.CG_VARIANT_CLASSIC, (("stencil_dot", 56, 6), ("update_norm", 80, 3),
+                                                     ("update_norm_nx", 56, 3))),
+                            (cg.CG_VARIANT_PIPELINED, (("pcg_pass", 128, 3),
+                                                       ("pcg_pass_nx", 112, 3)))):
+        x_ref = np.zeros_like(b)
+        ctx.solve(b, x_ref, n, n, tol=0.0, maxit=m, variant=variant, kx=kx, ky=ky)
+        x = np.zeros_like(b)
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        ctx.solve(b, x, n, n, tol=0.0, maxit=m, variant=variant, kx=kx, ky=ky)
+        st = ctx.cg_kernel_stats(reset=True)
+        ctx.cg_set_profiling(False)
+        np.testing.assert_array_equal(x, x_ref)
+        for name, per, launches in passes:
+            assert st[name]["launches"] == launches, (name, st[name])
+            assert st[name]["bytes"] == launches * per * n * n, (name, st[name])
