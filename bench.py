@@ -931,8 +931,9 @@ def bench_probe(args):
     torch, cg = setup()
     ctx = cg.Context(device=0, arena_bytes=8 << 30)
     # 6R6W: in place (the traffic of pcg_pass); 6R6W_out: six other vectors
-    # written; 6R6W_nt: in place with non-temporal stores
-    names = ["read", "copy", "2R1W", "3R2W", "6R6W", "6R6W_out", "6R6W_nt"]
+    # written; 6R6W_nt: in place with non-temporal stores; 6R6W_il: in place
+    # with the six vectors' rows interleaved (the pipelined solve's layout)
+    names = ["read", "copy", "2R1W", "3R2W", "6R6W", "6R6W_out", "6R6W_nt", "6R6W_il"]
     out = {}
     if args.copy_only:
         # the known-size copy that calibrates the traffic counters: one

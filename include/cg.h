@@ -262,8 +262,10 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
  * copy that calibrates hardware traffic counters); 2: two reads, one write;
  * 3: three reads, two writes; 4: six vectors read and written in place (the
  * traffic mix of a pipelined CG pass); 5: six vectors read, six others
- * written; 6: as 4 with non-temporal stores.  CG_E_NOMEM if the arena is too
- * small. */
+ * written; 6: as 4 with non-temporal stores; 7: as 4 with the six vectors'
+ * rows (4096 doubles each) interleaved in one block, the layout of the
+ * pipelined solve (elems rounded down to a multiple of 4096; CG_E_INVALID if
+ * that leaves none).  CG_E_NOMEM if the arena is too small. */
 int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
                     double* bytes);
 /* Integer multiply probe, for measurement only (the ALU peak the fixed-point

@@ -176,7 +176,7 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
 
 int cg_stream_probe(cg_ctx* ctx, int32_t pattern, size_t elems, int32_t reps, double* seconds,
                     double* bytes) {
-  if (!ctx || !seconds || !bytes || pattern < 0 || pattern > 6 || elems < 2 || reps < 1)
+  if (!ctx || !seconds || !bytes || pattern < 0 || pattern > 7 || elems < 2 || reps < 1)
     return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);

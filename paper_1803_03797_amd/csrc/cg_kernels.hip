@@ -2624,7 +2624,9 @@ int step_max_blocks_per_cu() {
 // Plain streaming kernels over `nv` device vectors of n doubles (16 B per
 // lane access, grid-stride): the attainable bandwidth of a read/write mix,
 // and the copy kernel of known size that calibrates the traffic counters.
-// pattern 0: read 1; 1: copy (1R 1W); 2: 2R 1W; 3: 3R 2W; 4: 6R 6W in place.
+// pattern 0: read 1; 1: copy (1R 1W); 2: 2R 1W; 3: 3R 2W; 4: 6R 6W in place;
+// 7: 6R 6W in place with the six vectors' rows interleaved (rows of 4096
+// doubles, vector k's row j at (6 j + k) * 4096 of one block).
 struct StreamArgs {
   double2* v[12];
   size_t n2;
@@ -2654,6 +2656,18 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs s) {
       const double2 a = v[0][i], b = v[1][i], c = v[2][i];
       v[3][i] = make_double2(a.x + b.x, a.y + b.y);
       v[4][i] = make_double2(b.x - c.x, b.y - c.y);
+    } else if constexpr (PATTERN == 7) {
+      constexpr size_t W2 = 2048;  // one row of 4096 doubles
+      const size_t j = i / W2, c = i - j * W2;
+      double2* r = v[0] + j * 6 * W2 + c;
+      const double2 a = r[0], b = r[W2], cc = r[2 * W2], d = r[3 * W2], e = r[4 * W2],
+                    f = r[5 * W2];
+      r[0] = make_double2(a.x + 0.5 * b.x, a.y + 0.5 * b.y);
+      r[W2] = make_double2(b.x - 0.25 * cc.x, b.y - 0.25 * cc.y);
+      r[2 * W2] = make_double2(cc.x + d.x, cc.y + d.y);
+      r[3 * W2] = make_double2(d.x * 0.75, d.y * 0.75);
+      r[4 * W2] = make_double2(e.x + f.x, e.y + f.y);
+      r[5 * W2] = make_double2(f.x - a.x, f.y - a.y);
     } else {
       // six vectors in; six out: in place (4), to six other vectors (5), or
       // in place with non-temporal stores (6)
@@ -2689,6 +2703,10 @@ hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, 
     case 4: hipLaunchKernelGGL(k_stream<4>, dim3(grid), dim3(256), 0, st, s); break;
     case 5: hipLaunchKernelGGL(k_stream<5>, dim3(grid), dim3(256), 0, st, s); break;
     case 6: hipLaunchKernelGGL(k_stream<6>, dim3(grid), dim3(256), 0, st, s); break;
+    case 7:
+      if (n % 4096) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_stream<7>, dim3(grid), dim3(256), 0, st, s);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -226,9 +226,9 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   pl.part = round_up((size_t)ndots_max(p) * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
   // Pipelined FP64 tile passes: the rows of all vectors interleaved, row j
   // of every vector after the other, so that a pass streams one region
-  // instead of seven (a six-vector read-modify-write probe: 5.7-5.9 TB/s with
-  // interleaved rows against 4.6-5.1 TB/s with separate vectors; pcg_pass at
-  // 4096^2 312 -> 295 us).  The classic passes touch three or four of their
+  // instead of seven (the six-vector read-modify-write of cg_stream_probe:
+  // 6.08 TB/s with interleaved rows, pattern 7, against 5.29 TB/s with
+  // separate vectors, pattern 4; pcg_pass at 4096^2 312 -> 295 us).  The classic passes touch three or four of their
   // five vectors and measured slower interleaved (update_norm 143 -> 155 us),
   // so they keep separate vectors.
   size_t vec_bytes = n64 * pl.v64 + (pl.vc ? round_up(4 * elems * 8, Arena::kAlign) : 0);
@@ -943,10 +943,15 @@ int Ctx::apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u
 
 int Ctx::stream_probe(int pattern, size_t elems, int reps, double* seconds, double* bytes) {
   Ctx& c = *this;
-  static const int nv[] = {1, 2, 3, 5, 6, 12, 6};
-  static const int moved[] = {1, 2, 3, 5, 12, 12, 12};
-  if (pattern < 0 || pattern > 6 || elems < 2 || reps < 1) return CG_E_INVALID;
+  static const int nv[] = {1, 2, 3, 5, 6, 12, 6, 6};
+  static const int moved[] = {1, 2, 3, 5, 12, 12, 12, 12};
+  if (pattern < 0 || pattern > 7 || elems < 2 || reps < 1) return CG_E_INVALID;
   elems &= ~(size_t)1;
+  if (pattern == 7) {
+    // whole rows of 4096 doubles; the six vectors form one contiguous block
+    elems &= ~(size_t)4095;
+    if (elems == 0) return CG_E_INVALID;
+  }
   const size_t vb = round_up(elems * 8, Arena::kAlign);
   char* m = (char*)arena.alloc(nv[pattern] * vb + 256);
   if (!m) return CG_E_NOMEM;

@@ -114,12 +114,14 @@ def test_profiling_statistics(torch):
 
 def test_stream_probe():
     with cg.Context(device=0, arena_bytes=2 << 30) as ctx:
-        for pat, moved in ((0, 1), (1, 2), (2, 3), (3, 5), (4, 12), (5, 12), (6, 12)):
+        for pat, moved in ((0, 1), (1, 2), (2, 3), (3, 5), (4, 12), (5, 12), (6, 12), (7, 12)):
             t, nbytes = ctx.cg_stream_probe(pat, 1 << 22, 2)
             assert nbytes == moved * (1 << 22) * 8 and t > 0
             say("probe", pat, "%.0f GB/s" % (nbytes / t / 1e9))
         with pytest.raises(cg.CGError):
-            ctx.cg_stream_probe(7, 1 << 20, 1)
+            ctx.cg_stream_probe(8, 1 << 20, 1)
+        with pytest.raises(cg.CGError):
+            ctx.cg_stream_probe(7, 4094, 1)  # no whole row of 4096
 
 
 def test_mul_probe():
