@@ -166,6 +166,16 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
         pl.fp32g = 1;
     } else {
       rows = default_rows(p->nx, ny, pl.fp32g);
+      // pipelined FP64 5-point solves of 16M unknowns and more: about 4096
+      // tiles, so that each of the one-per-CU work-groups walks some 16
+      // short ones (pcg_pass at 4096^2 with interleaved rows: 288 us with 8
+      // rows per strip against 296 us with 32; 8192^2 gets 32 either way)
+      if (!pl.refined && !pl.precond && !pl.vc && p->nz <= 1 &&
+          p->variant == CG_VARIANT_PIPELINED && (int64_t)p->nx * ny >= 16 * 1024 * 1024) {
+        const int ntx = (p->nx + 2 * kWave - 1) / (2 * kWave);
+        const int want_nty = std::max(1, (4096 + ntx - 1) / ntx);
+        rows = std::min(32, std::max(2, ny / (kWavesPerTile * want_nty)));
+      }
     }
   }
   pl.g = make_geo(p->nx, ny, pl.fp32g, rows);
