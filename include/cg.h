@@ -244,14 +244,18 @@ int cg_footprint(const cg_problem* prob, size_t* bytes);
 /* CG_OK or CG_E_INVALID (host-only; no context needed). */
 int cg_validate(const cg_problem* prob);
 /* Autotuner: times candidate tile shapes for (nx, ny, variant, precision) on
- * the device and pins the fastest for that grid shape (cached, optionally in
- * cfg->tune_cache).  Returns CG_OK (fixed point: nothing to tune). */
+ * the device, the shape an unpinned solve would take first, and pins the
+ * fastest for that grid shape, precision and variant (refined solves: one pin
+ * for both variants).  With cfg->tune_cache the pins are saved as JSON lines
+ * that name the device architecture and the HIP runtime version; a new
+ * context loads only the lines of its own architecture and runtime.  Returns
+ * CG_OK (fixed point: nothing to tune). */
 int cg_tune(cg_ctx* ctx, int32_t nx, int32_t ny, cg_variant variant, cg_precision precision);
-/* Pins the tile shape for a grid shape: tile height (rows per wavefront
- * strip), grid size (0 = occupancy-derived) and columns per lane (0 = default:
- * 2 for FP64, 4 for FP32-refined; classic FP64 may also use 4).  The reduction
- * order follows the pinned shape (cg_plan reports it).  For the autotuner,
- * experiments and tests. */
+/* Pins the tile shape for a grid shape and precision, for both variants: tile
+ * height (rows per wavefront strip), grid size (0 = occupancy-derived) and
+ * columns per lane (0 = default: 2 for FP64, 4 for FP32-refined; classic FP64
+ * may also use 4).  The reduction order follows the pinned shape (cg_plan
+ * reports it).  For the autotuner, experiments and tests. */
 int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int32_t rows,
                 int32_t grid, int32_t cols_per_lane);
 /* HBM probe, for measurement only: runs a plain streaming kernel over

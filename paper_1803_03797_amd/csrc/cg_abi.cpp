@@ -169,8 +169,10 @@ int cg_pin_tile(cg_ctx* ctx, int32_t nx, int32_t ny, cg_precision precision, int
   if (precision == CG_PREC_FP32_REFINED && cols_per_lane == 2) return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
-  c->pins[Ctx::key(nx, ny, precision == CG_PREC_FP32_REFINED)] =
-      cgr::Pin{rows, grid, cols_per_lane};
+  // the shape is pinned for both variants (refined solves have one key)
+  const int fp = precision == CG_PREC_FP32_REFINED;
+  for (int v = 0; v < 2; ++v)
+    c->pins[Ctx::key(nx, ny, fp, v)] = cgr::Pin{rows, grid, cols_per_lane};
   return CG_OK;
 }
 

@@ -51,6 +51,9 @@ int validate(const cg_problem* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 0) return CG_E_INVALID;
   if ((int64_t)p->ny * std::max(p->nz, 1) >= (int64_t)1 << 31) return CG_E_INVALID;
   if ((int64_t)p->nx * p->ny * std::max(p->nz, 1) > (int64_t)1 << 31) return CG_E_INVALID;
+  // the row stride (Geo::pitch, int32) is the padded width (at most nx
+  // rounded up to 256 columns) times up to 14 interleaved vectors
+  if (((int64_t)p->nx + 255) / 256 * 256 * 14 > (int64_t)INT32_MAX) return CG_E_INVALID;
   // 3D (7-point operator): FP64 CG of either variant, no preconditioner
   if (p->nz > 1 && (p->precision != CG_PREC_FP64 || p->precond != 0)) return CG_E_INVALID;
   // variable coefficients: both arrays, 2D FP64 CG of either variant, no
@@ -113,6 +116,21 @@ static int wg_rows(int nx, int ny) {
   return std::max(1, (ny + kWavesPerTile * nty - 1) / (kWavesPerTile * nty));
 }
 
+int Ctx::unpinned_rows(const cg_problem* p, int fp32g) const {
+  const int ny = rows_of(p);
+  // pipelined FP64 5-point solves of 16M unknowns and more: about 4096
+  // tiles, so that each of the one-per-CU work-groups walks some 16 short
+  // ones (pcg_pass at 4096^2 with interleaved rows: 288 us with 8 rows per
+  // strip against 296 us with 32; 8192^2 gets 32 either way)
+  if (!fp32g && !p->precond && !p->kx && p->nz <= 1 && p->variant == CG_VARIANT_PIPELINED &&
+      (int64_t)p->nx * ny >= 16 * 1024 * 1024) {
+    const int ntx = (p->nx + 2 * kWave - 1) / (2 * kWave);
+    const int want_nty = std::max(1, (4096 + ntx - 1) / ntx);
+    return std::min(32, std::max(2, ny / (kWavesPerTile * want_nty)));
+  }
+  return default_rows(p->nx, ny, fp32g);
+}
+
 bool Ctx::use_wg(const cg_problem* p) const {
   return p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 && !p->kx &&
          (int64_t)p->nx * p->ny <= wg_max_dof;
@@ -154,7 +172,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   if (pl.wg) {
     rows = wg_rows(p->nx, p->ny);
   } else {
-    auto it = pins.find(key(p->nx, ny, pl.fp32g));
+    auto it = pins.find(key(p->nx, ny, pl.fp32g, p->variant));
     if (it != pins.end()) {
       rows = it->second.rows;
       grid = it->second.grid;
@@ -165,17 +183,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
           !pl.vc && p->nz <= 1)
         pl.fp32g = 1;
     } else {
-      rows = default_rows(p->nx, ny, pl.fp32g);
-      // pipelined FP64 5-point solves of 16M unknowns and more: about 4096
-      // tiles, so that each of the one-per-CU work-groups walks some 16
-      // short ones (pcg_pass at 4096^2 with interleaved rows: 288 us with 8
-      // rows per strip against 296 us with 32; 8192^2 gets 32 either way)
-      if (!pl.refined && !pl.precond && !pl.vc && p->nz <= 1 &&
-          p->variant == CG_VARIANT_PIPELINED && (int64_t)p->nx * ny >= 16 * 1024 * 1024) {
-        const int ntx = (p->nx + 2 * kWave - 1) / (2 * kWave);
-        const int want_nty = std::max(1, (4096 + ntx - 1) / ntx);
-        rows = std::min(32, std::max(2, ny / (kWavesPerTile * want_nty)));
-      }
+      rows = unpinned_rows(p, pl.fp32g);
     }
   }
   pl.g = make_geo(p->nx, ny, pl.fp32g, rows);
@@ -1066,7 +1074,7 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
   HIPCHK(hipStreamSynchronize(st));
   p.b = b;
   p.x = x;
-  const uint64_t k = key(nx, ny, fp32g);
+  const uint64_t k = key(nx, ny, fp32g, variant);
   std::vector<const char*> names;
   if (fp32g) names = {"stencil_dot_f32", "update_norm_f32", "update_norm_f32_nx"};
   else if (variant == CG_VARIANT_PIPELINED) names = {"pcg_pass", "pcg_pass_nx"};
@@ -1077,7 +1085,32 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
   const auto save_stats = stats;
   prof = true;
   double best = 1e30;
-  Pin bestp{default_rows(nx, ny, fp32g), 0, 0};
+  // the shape the solve takes unpinned is the fallback and the first
+  // candidate, so the pick is never slower than it by the tuner's measure
+  pins.erase(k);
+  Pin bestp{unpinned_rows(&p, fp32g), plan(&p).grid, 0};
+  auto score = [&](const Pin& pin, double& t) {
+    pins[k] = pin;
+    cg_result r;
+    if (solve(&p, &r) < 0) return false;  // warms graphs and caches
+    stats.clear();
+    if (solve(&p, &r) < 0) return false;
+    t = 0.0;
+    int64_t launches = 0;
+    for (const char* nm : names) {
+      auto it = stats.find(nm);
+      if (it != stats.end()) {
+        t += it->second.seconds;
+        launches += it->second.launches;
+      }
+    }
+    t /= (double)p.maxit;  // per iteration (tol = 0: exactly maxit of them)
+    return launches > 0;
+  };
+  {
+    double t;
+    if (score(bestp, t)) best = t;
+  }
   for (int cpl : cpls) {
     const int geo4 = fp32g || cpl == 4;
     const int kind = fp32g ? K_CG2F : (variant == CG_VARIANT_PIPELINED ? K_PCG : K_CG2);
@@ -1092,22 +1125,8 @@ int Ctx::tune(int nx, int ny, int variant, int precision) {
         if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
       }
       for (int gsz : grids) {
-        pins[k] = Pin{rows, gsz, cpl};
-        cg_result r;
-        if (solve(&p, &r) < 0) continue;  // warms graphs and caches
-        stats.clear();
-        if (solve(&p, &r) < 0) continue;
-        double t = 0.0;
-        int64_t launches = 0;
-        for (const char* nm : names) {
-          auto it = stats.find(nm);
-          if (it != stats.end()) {
-            t += it->second.seconds;
-            launches += it->second.launches;
-          }
-        }
-        if (launches == 0) continue;
-        t /= (double)p.maxit;  // per iteration (tol = 0: exactly maxit of them)
+        double t;
+        if (!score(Pin{rows, gsz, cpl}, t)) continue;
         if (t < best) {
           best = t;
           bestp = Pin{rows, gsz, cpl};
@@ -1130,12 +1149,16 @@ void Ctx::load_tune_cache() {
   if (!f) return;
   char line[512];
   while (fgets(line, sizeof(line), f)) {
-    int nx, ny, fp, rows, grid, cpl;
+    // a pin measured on another architecture or HIP runtime is ignored
+    int nx, ny, fp, var, rows, grid, cpl, hv;
+    char ar[64];
     if (sscanf(line,
-               " {\"nx\": %d, \"ny\": %d, \"fp32\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}",
-               &nx, &ny, &fp, &rows, &grid, &cpl) == 6 &&
-        nx > 0 && ny > 0 && rows > 0 && grid >= 0 && (cpl == 0 || cpl == 2 || cpl == 4))
-      pins[key(nx, ny, fp)] = Pin{rows, grid, cpl};
+               " {\"arch\": \"%63[^\"]\", \"hip\": %d, \"nx\": %d, \"ny\": %d, \"fp32\": %d, "
+               "\"variant\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}",
+               ar, &hv, &nx, &ny, &fp, &var, &rows, &grid, &cpl) == 9 &&
+        arch == ar && hv == hip_version && nx > 0 && ny > 0 && rows > 0 && rows <= 4096 &&
+        grid >= 0 && (var == 0 || var == 1) && (cpl == 0 || cpl == 2 || cpl == 4))
+      pins[key(nx, ny, fp, var)] = Pin{rows, grid, cpl};
   }
   fclose(f);
 }
@@ -1145,8 +1168,11 @@ void Ctx::save_tune_cache() {
   FILE* f = fopen(tune_path.c_str(), "w");
   if (!f) return;
   for (auto& kv : pins)
-    fprintf(f, "{\"nx\": %d, \"ny\": %d, \"fp32\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}\n",
-            (int)(kv.first >> 33), (int)((kv.first >> 1) & 0xffffffff), (int)(kv.first & 1),
+    fprintf(f,
+            "{\"arch\": \"%s\", \"hip\": %d, \"nx\": %d, \"ny\": %d, \"fp32\": %d, "
+            "\"variant\": %d, \"rows\": %d, \"grid\": %d, \"cpl\": %d}\n",
+            arch.c_str(), hip_version, (int)(kv.first >> 34),
+            (int)((kv.first >> 2) & 0xffffffff), (int)(kv.first & 1), (int)((kv.first >> 1) & 1),
             kv.second.rows, kv.second.grid, kv.second.cpl);
   fclose(f);
 }
@@ -1163,6 +1189,12 @@ int Ctx::init(const cg_config* cfg) {
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, device));
   num_cu = prop.multiProcessorCount;
+  {
+    // "gfx950:sramecc+:xnack-": the architecture name before the features
+    std::string a = prop.gcnArchName;
+    arch = a.substr(0, a.find(':'));
+    if (hipRuntimeGetVersion(&hip_version) != hipSuccess) hip_version = 0;
+  }
   HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&user_ev, hipEventDisableTiming));

@@ -139,9 +139,15 @@ struct Ctx {
   Server* server = nullptr;
   std::mutex server_mu;  // guards `server` only (submit/poll never wait for an epoch)
 
-  static uint64_t key(int nx, int ny, int fp32g) {
-    return ((uint64_t)(uint32_t)nx << 33) | ((uint64_t)(uint32_t)ny << 1) | (uint64_t)(fp32g & 1);
+  // pins are kept per grid shape, precision and variant (the refined inner
+  // solve is classic whatever the variant, so refined pins use variant 0)
+  static uint64_t key(int nx, int ny, int fp32g, int variant) {
+    const uint64_t v = fp32g ? 0 : (uint64_t)(variant & 1);
+    return ((uint64_t)(uint32_t)nx << 34) | ((uint64_t)(uint32_t)ny << 2) | (v << 1) |
+           (uint64_t)(fp32g & 1);
   }
+  std::string arch;      // gcnArchName of the device (tune cache key)
+  int hip_version = 0;   // hipRuntimeGetVersion (tune cache key)
   int init(const cg_config* cfg);
   ~Ctx();
   bool use_wg(const cg_problem* p) const;
@@ -151,6 +157,8 @@ struct Ctx {
   // interleave: lay the FP64 vectors of a tile-pass solve out with their rows
   // interleaved (off for the building blocks' scratch vectors)
   Plan plan(const cg_problem* p, bool allow_rr = true, bool interleave = true);
+  // strip height of a tile-pass solve when no tile shape is pinned
+  int unpinned_rows(const cg_problem* p, int fp32g) const;
   int solve(const cg_problem* p, cg_result* res);
   int solve_batch(const cg_problem* p, int n, cg_result* res);
   int apply_or_dot(int kind, int nx, int ny, cg_memspace mem, const double* u, const double* y_in,

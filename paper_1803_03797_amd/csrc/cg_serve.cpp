@@ -44,7 +44,7 @@ struct Job {
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   Work w;
   int slot = -1;
-  int steps_cap = 0;
+  int64_t steps_cap = 0;
   bool finished = false;
   int rc = CG_PENDING;  // final status (or a negative error)
   cg_result res{};
@@ -176,9 +176,9 @@ class Engine {
     if (w.pl.rr) rr_new_.push_back(slot);
     else if (w.pl.fixed) fx_new_.push_back(slot);
     else ++step_jobs_;
-    // a solve finishes within 5 maxit + 16 passes: 2 per inner iteration and
-    // at most 3 per outer step, each outer step taking an inner iteration
-    j->steps_cap = step_ + 5 * j->p.maxit + 16;
+    // a bound on the passes of the solve (a guard against a solve that never
+    // reaches K_DONE; it cannot trigger for a correct pass sequence)
+    j->steps_cap = (int64_t)step_ + step_bound(j->p, w.pl.refined);
     ++active_;
     dirty_ = true;
     return CG_OK;
@@ -306,11 +306,14 @@ class Engine {
       const int i = h_idx_[k];
       Job* j = slot_job_[i];
       const State& s = h_states_[k];
+      int rc;
       if (s.kind != K_DONE) {
-        if (step_ > j->steps_cap) return CG_E_DEVICE;  // cannot happen: passes are bounded
-        continue;
+        if (step_ <= j->steps_cap) continue;
+        // past its pass bound: this solve alone fails; the others go on
+        rc = CG_E_DEVICE;
+      } else {
+        rc = stage_out(c_, j->w, &j->p, s);
       }
-      int rc = stage_out(c_, j->w, &j->p, s);
       j->t_done = now_s();
       if (rc) {
         j->rc = rc;
@@ -353,6 +356,20 @@ class Engine {
 
  private:
   static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+  // Upper bound on the step-engine passes of one solve from admission to
+  // K_DONE.  FP64: the initial passes, at most two per iteration (classic:
+  // pass 1 and pass 2; pipelined: one), the pass that detects the stop, the
+  // true residual and its sum.  Refined: each outer step runs RESID,
+  // REF_SCALE, two passes per inner iteration, the pass 1 that ends the
+  // inner solve and REF_UPDATE, i.e. 2 K + 4 passes for K inner iterations,
+  // and every outer step but the last takes at least one of the maxit inner
+  // iterations, so at most 2 maxit + 4 (maxit + 1) passes, plus the final
+  // RESID and REF_SCALE.
+  static int64_t step_bound(const cg_problem& p, bool refined) {
+    const int64_t m = p.maxit;
+    return refined ? 6 * m + 32 : 2 * m + 32;
+  }
 
   // Rebuilds the item table: each resident solve contributes up to
   // kMaxItemsPerSolve items of consecutive tiles.

@@ -58,7 +58,10 @@ def _prob(**kw):
                                  dict(nz=3, precision=2), dict(nx=2048, ny=2048, nz=1024),
                                  dict(kx=3), dict(ky=4), dict(kx=3, ky=4, nz=2),
                                  dict(kx=3, ky=4, precond=2), dict(kx=3, ky=4, precision=1),
-                                 dict(kx=3, ky=4, precision=2)])
+                                 dict(kx=3, ky=4, precision=2),
+                                 # padded row stride times 14 interleaved vectors > int32
+                                 dict(nx=300_000_000, ny=7, variant=1),
+                                 dict(nx=153_391_617, ny=1)])
 def test_validation_rejects(bad):
     assert cg.cg_validate(_prob(**bad)) == cg.CG_E_INVALID
 
@@ -70,6 +73,8 @@ def test_validation_accepts():
     for nx, ny in ((1, 1), (100, 100), (98, 102), (1, 6782), (5087, 1)):
         assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=2)) == cg.CG_OK
     assert cg.cg_validate(_prob(precision=2, inner_tol=7.0)) == cg.CG_OK
+    # widest row whose padded stride times 14 vectors still fits int32
+    assert cg.cg_validate(_prob(nx=153_391_360, ny=1, variant=1)) == cg.CG_OK
     # the 3D operator: nz > 1 (nz = 0 or 1 is the 2D problem)
     for nz in (0, 1, 2, 64):
         for v in (0, 1):

@@ -39,6 +39,14 @@ def mixed_problems(count, seed, refined_every=0, big=False):
     return out
 
 
+def order_of(ctx, nx, ny, variant):
+    """The reduction order of the plan a solve of this shape takes."""
+    info = ctx.cg_plan(nx, ny, variant)
+    if info.path == 2:
+        return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+
+
 def make(d, x, maxit=20000):
     return cg.make_problem(d["b"], x, d["nx"], d["ny"], tol=d["tol"], maxit=maxit,
                            variant=d["variant"], precision=d["precision"], inner_tol=1e-4)
@@ -103,6 +111,48 @@ def test_batch_failure_isolated_and_edge_cases():
             rca, ra, xa = alone(ctx, dict(nx=90, ny=70, b=bs[k], variant=k % 2, precision=0,
                                           tol=1e-8))
             np.testing.assert_array_equal(xs[k], xa)
+
+
+def test_batch_refined_slow_inner_solves_stay_isolated():
+    """A refined request whose inner solves stop after about one iteration
+    (inner tol 0.99) reaches maxit as CG_NOT_CONVERGED, with about six passes
+    per inner iteration, in a batch and served, and leaves the others intact."""
+    rng = np.random.default_rng(21)
+    shapes = [(300, 200), (257, 129), (300, 200)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny in shapes]
+    with cg.Context(device=0, arena_bytes=1 << 30) as ctx:
+        for maxit in (15, 40):
+            xs = [np.zeros_like(b) for b in bs]
+            probs = [cg.make_problem(bs[0], xs[0], 300, 200, tol=1e-8, maxit=20000, variant=1),
+                     cg.make_problem(bs[1], xs[1], 257, 129, tol=1e-10, maxit=maxit,
+                                     precision=cg.CG_PREC_FP32_REFINED, inner_tol=0.99),
+                     cg.make_problem(bs[2], xs[2], 300, 200, tol=1e-8, maxit=20000, variant=0)]
+            say("refined inner tol 0.99, maxit", maxit)
+            rc, res = ctx.cg_solve_batch(probs)
+            assert [r.status for r in res] == [cg.CG_OK, cg.CG_NOT_CONVERGED, cg.CG_OK]
+            assert res[1].iterations == maxit
+            for k in (0, 2):
+                rca, ra, xa = alone(ctx, dict(nx=300, ny=200, b=bs[k], variant=1 - k // 2,
+                                              precision=0, tol=1e-8))
+                np.testing.assert_array_equal(xs[k], xa)
+            xa = np.zeros_like(bs[1])
+            rca, ra = ctx.cg_solve(cg.make_problem(bs[1], xa, 257, 129, tol=1e-10, maxit=maxit,
+                                                   precision=cg.CG_PREC_FP32_REFINED,
+                                                   inner_tol=0.99))
+            assert rca == cg.CG_NOT_CONVERGED and ra.iterations == maxit
+            np.testing.assert_array_equal(xs[1], xa)
+            # served
+            xsv = np.zeros_like(bs[1])
+            t = ctx.cg_submit(cg.make_problem(bs[1], xsv, 257, 129, tol=1e-10, maxit=maxit,
+                                              precision=cg.CG_PREC_FP32_REFINED, inner_tol=0.99))
+            deadline = time.time() + 60
+            while time.time() < deadline:
+                rc, r = ctx.cg_poll(t)
+                if rc != cg.CG_PENDING:
+                    break
+                time.sleep(0.001)
+            assert rc == cg.CG_NOT_CONVERGED and r.iterations == maxit
+            np.testing.assert_array_equal(xsv, xa)
 
 
 def test_batch_more_solves_than_slots_and_small_arena():
@@ -184,6 +234,27 @@ def test_serve_alone_vs_mix():
             assert rc == rca and r.iterations == ra.iterations
             np.testing.assert_array_equal(x, xa)
             assert r.latency_seconds >= r.device_seconds > 0
+        # served results against the oracle: FP64 ones bitwise against its
+        # canonical order (the order of the request's plan), refined ones
+        # within 1e-9 of the FP64 oracle solution at the same tolerance
+        n64 = nref = 0
+        for d, x, t in zip(probs, xs, tickets):
+            rc, r = results[t]
+            nx, ny = d["nx"], d["ny"]
+            if d["precision"] == 0 and n64 < 8:
+                o = order_of(ctx, nx, ny, d["variant"])
+                xo, ro = oracle.cg(d["b"], nx, ny, variant=d["variant"], tol=d["tol"],
+                                   maxit=20000, mode=oracle.MODE_CANONICAL, order=o)
+                assert rc == ro.status and r.iterations == ro.iterations
+                np.testing.assert_array_equal(x, xo)
+                n64 += 1
+            elif d["precision"] == cg.CG_PREC_FP32_REFINED and nref < 4:
+                xo, ro = oracle.cg(d["b"], nx, ny, tol=d["tol"], maxit=20000)
+                err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+                say("  served refined %dx%d: err vs FP64 oracle %.2e" % (nx, ny, err))
+                assert rc == cg.CG_OK and r.rel_res_true <= d["tol"] and err <= 1e-9
+                nref += 1
+        assert n64 >= 6 and nref >= 3
         with pytest.raises(cg.CGError) as e:
             ctx.cg_poll(tickets[0])
         assert e.value.code == cg.CG_E_TICKET

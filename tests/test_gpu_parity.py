@@ -272,6 +272,55 @@ def test_full_size_lockstep_sampled(ctx, torch, variant):
     np.testing.assert_array_equal(x, xo)
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_size_lockstep_across_graph_chunks(ctx, torch, variant):
+    """The 4096 x 4096 workload for 70 iterations: more than two captured
+    chunks of iterations (the benchmark replays chunks of 32), a ragged last
+    chunk and an even stop (deferred x applied by the stopping pass), bitwise
+    against the canonical oracle."""
+    nx = ny = 4096
+    m = 70
+    say("4096^2 lockstep %d iterations" % m, variant)
+    xs = workloads.large_solution(nx, ny)
+    b = oracle.spmv(xs, nx, ny, order=0)
+    o, info = order_of(ctx, nx, ny, variant)
+    assert info.path == 0
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    rc, res = ctx.solve(bd, xd, nx, ny, tol=0.0, maxit=m, variant=variant)
+    xo, ro = oracle.cg(b, nx, ny, variant=variant, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o)
+    assert rc == cg.CG_OK and res.iterations == ro.iterations == m
+    np.testing.assert_array_equal(xd.cpu().numpy(), xo)
+    assert res.rel_res_recursive == ro.rel_res_recursive
+    assert res.rel_res_true == ro.rel_res_true
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_huge_grid_lockstep_bitwise(torch, variant):
+    """8192 x 8192 (the refinement workload's grid and right-hand side), 4
+    iterations in the plan solves of that size take (pipelined: two work-groups
+    per CU, interleaved rows), in both tile-walk directions and with the
+    deferred x of an even stop: bitwise against the canonical oracle."""
+    n = workloads.HUGE["nx"]
+    m = 4
+    b = workloads.huge_rhs(n, n)
+    with cg.Context(device=0, arena_bytes=(72 * n * n) + (1 << 30)) as c:
+        o, info = order_of(c, n, n, variant)
+        say("8192^2 lockstep %d iterations variant %d: rows %d grid %d tiles %d" %
+            (m, variant, info.rows, info.grid, info.tiles))
+        assert info.path == 0
+        bd = torch.from_numpy(b).cuda()
+        xd = torch.zeros_like(bd)
+        rc, res = c.solve(bd, xd, n, n, tol=0.0, maxit=m, variant=variant)
+        x = xd.cpu().numpy()
+        del bd, xd
+    xo, ro = oracle.cg(b, n, n, variant=variant, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o)
+    assert rc == cg.CG_OK and res.iterations == ro.iterations == m
+    np.testing.assert_array_equal(x, xo)
+    assert res.rel_res_recursive == ro.rel_res_recursive
+    assert res.rel_res_true == ro.rel_res_true
+
+
 # ----------------------------------------------------------- refinement --
 
 @pytest.mark.parametrize("nx,ny", [(256, 256), (300, 190)])
@@ -290,3 +339,22 @@ def test_refinement_parity(ctx, nx, ny):
     assert res.rel_res_true <= 1e-10
     assert rel(x, xo) <= 1e-9
     assert abs(res.outer_iterations - rr.outer_iterations) <= 1
+
+
+def test_refinement_parity_1024(ctx):
+    """FP32-refined to a true relative residual of 1e-10 on 1024 x 1024 (b ~
+    N(0,1), inner tol 1e-4): within 1e-9 of the FP64 oracle's solution at the
+    same tolerance."""
+    n = 1024
+    say("refinement 1024^2")
+    b = np.random.default_rng(1024).standard_normal((n, n))
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, n, n, tol=1e-10, maxit=200000, precision=cg.CG_PREC_FP32_REFINED,
+                        inner_tol=1e-4)
+    xo, ro = oracle.cg(b, n, n, tol=1e-10, maxit=200000)
+    err = rel(x, xo)
+    say("  refined outer %d inner %d, fp64 oracle %d iterations; err vs fp64 oracle %.2e"
+        % (res.outer_iterations, res.iterations, ro.iterations, err))
+    assert rc == cg.CG_OK and ro.status == 0
+    assert res.rel_res_true <= 1e-10
+    assert err <= 1e-9

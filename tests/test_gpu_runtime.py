@@ -43,7 +43,9 @@ def test_tune_cache_and_parity(tmp_path, variant):
         ctx.cg_tune(nx, ny, variant)
         o, info = order_of(ctx, nx, ny, variant)
         lines = [json.loads(l) for l in open(cache)]
-        assert any(d["nx"] == nx and d["ny"] == ny and d["rows"] == info.rows for d in lines)
+        assert any(d["nx"] == nx and d["ny"] == ny and d["rows"] == info.rows and
+                   d["variant"] == variant and d["arch"].startswith("gfx9") and d["hip"] > 0
+                   for d in lines)
         b = np.random.default_rng(1).uniform(-1, 1, (ny, nx))
         x = np.zeros_like(b)
         rc, r = ctx.solve(b, x, nx, ny, tol=0.0, maxit=30, variant=variant)
@@ -54,6 +56,29 @@ def test_tune_cache_and_parity(tmp_path, variant):
         info2 = ctx2.cg_plan(nx, ny, variant)
         assert (info2.rows, info2.cols_per_lane, info2.grid) == (info.rows, info.cols_per_lane,
                                                                 info.grid)
+
+
+def test_tune_keeps_variants_apart(tmp_path):
+    """Tuning one variant leaves the other variant's pinned shape alone, and
+    a cache line of another architecture or HIP runtime is ignored."""
+    nx, ny = 600, 260
+    cache = str(tmp_path / "tune.json")
+    with cg.Context(device=0, arena_bytes=1 << 30, tune_cache=cache) as ctx:
+        say("tune both variants", nx, ny)
+        ctx.cg_tune(nx, ny, 1)
+        p1 = ctx.cg_plan(nx, ny, 1)
+        ctx.cg_tune(nx, ny, 0)
+        p1b = ctx.cg_plan(nx, ny, 1)
+        assert (p1.rows, p1.grid, p1.cols_per_lane) == (p1b.rows, p1b.grid, p1b.cols_per_lane)
+        lines = [json.loads(l) for l in open(cache)]
+        assert sorted(d["variant"] for d in lines if d["nx"] == nx) == [0, 1]
+    # the same lines claimed for another architecture: not loaded
+    with open(cache, "w") as f:
+        for d in lines:
+            d = dict(d, arch="gfx000", rows=1)
+            f.write(json.dumps(d) + "\n")
+    with cg.Context(device=0, arena_bytes=1 << 30, tune_cache=cache) as ctx2:
+        assert ctx2.cg_plan(nx, ny, 1).rows != 1
 
 
 @pytest.mark.parametrize("rows", [1, 3, 32])
