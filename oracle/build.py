@@ -11,26 +11,36 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, f) for f in ("cg_oracle.c", "cg_oracle_fixed.c")]
 LIB = os.path.join(HERE, "libcg_oracle.so")
+# the all-core timing build of the same sources (CPU baseline only)
+LIB_OMP = os.path.join(HERE, "libcg_oracle_omp.so")
 
 
-def stale() -> bool:
+def stale(omp: bool = False) -> bool:
     """True when the library is missing or older than a source."""
-    if not os.path.exists(LIB):
+    lib = LIB_OMP if omp else LIB
+    if not os.path.exists(lib):
         return True
-    t = os.path.getmtime(LIB)
+    t = os.path.getmtime(lib)
     return any(os.path.getmtime(f) > t for f in SOURCES)
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, omp: bool = False) -> str:
+    lib = LIB_OMP if omp else LIB
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-fPIC", "-shared", "-o", tmp] + SOURCES + ["-lm"]
+           "-Wno-unknown-pragmas", "-fPIC", "-shared"] + (["-fopenmp"] if omp else []) + \
+          ["-o", tmp] + SOURCES + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build_all(verbose: bool = False):
+    build(verbose)
+    build(verbose, omp=True)
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build_all(verbose="-v" in sys.argv)

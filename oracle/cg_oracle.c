@@ -45,10 +45,40 @@
  *                    at dot_canonical() below, or, for the column-segment
  *                    layout of the small-grid solver, dot_segments().
  */
+#define _POSIX_C_SOURCE 200809L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* All-core timing build.  Built with -fopenmp (the benchmark's CPU baseline
+ * only; the tests use the plain build, in which the pragmas below are inert),
+ * the matrix-vector product and the vector updates split their rows over the
+ * threads (each row's arithmetic unchanged), and the sequential-mode dot
+ * product sums one contiguous block per thread in order and then adds the
+ * per-thread partials in thread order: deterministic for a given number of
+ * threads, and not the sequential order. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Seconds the last solve of the calling thread spent after assembling its
+ * matrix (the iterations, without the CSR assembly). */
+static _Thread_local double g_solve_seconds = 0.0;
+double oracle_last_solve_seconds(void) { return g_solve_seconds; }
+static double wall_now(void) {
+  struct timespec t;
+  clock_gettime(CLOCK_MONOTONIC, &t);
+  return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
 
 enum { OR_OK = 0, OR_NOT_CONVERGED = 2, OR_BREAKDOWN = 3,
        OR_E_INVALID = -1, OR_E_NOMEM = -2 };
@@ -161,6 +191,7 @@ static int csr_build(csr_t* A, int32_t nx, int32_t ny, int32_t order, int want_f
 
 /* y = A u, each row summed in the stored entry order, starting from +0. */
 static void spmv(const csr_t* A, const double* u, double* y) {
+#pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < A->n; ++k) {
     double acc = 0.0;
     for (int64_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e)
@@ -191,6 +222,26 @@ int oracle_spmv(int32_t nx, int32_t ny, int32_t order, const double* u, double* 
 /* ----------------------------------------------------------------- dots -- */
 
 static double dot_sequential(int64_t n, const double* a, const double* b) {
+#ifdef _OPENMP
+  const int nt = omp_get_max_threads();
+  if (nt > 1 && n >= 65536) {
+    double part[1024];
+    const int T = nt < 1024 ? nt : 1024;
+#pragma omp parallel num_threads(T)
+    {
+      const int t = omp_get_thread_num(), tt = omp_get_num_threads();
+      const int64_t k0 = n * t / tt, k1 = n * (t + 1) / tt;
+      double s = 0.0;
+      for (int64_t k = k0; k < k1; ++k) s = s + a[k] * b[k];
+      part[t] = s;
+      if (t == 0)
+        for (int u = tt; u < T; ++u) part[u] = 0.0;
+    }
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) s = s + part[t];
+    return s;
+  }
+#endif
   double s = 0.0;
   for (int64_t k = 0; k < n; ++k) s = s + a[k] * b[k];
   return s;
@@ -330,14 +381,16 @@ static double dot(const ctx_t* c, const double* a, const double* b) {
 
 /* y <- y + a*x */
 static void axpy(const ctx_t* c, int64_t n, double a, const double* x, double* y) {
-  if (c->mode == MODE_CANONICAL) for (int64_t k = 0; k < n; ++k) y[k] = fma(a, x[k], y[k]);
-  else                           for (int64_t k = 0; k < n; ++k) y[k] = y[k] + a * x[k];
+  const int fused = c->mode == MODE_CANONICAL;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) y[k] = fused ? fma(a, x[k], y[k]) : y[k] + a * x[k];
 }
 
 /* y <- x + a*y */
 static void xpay(const ctx_t* c, int64_t n, const double* x, double a, double* y) {
-  if (c->mode == MODE_CANONICAL) for (int64_t k = 0; k < n; ++k) y[k] = fma(a, y[k], x[k]);
-  else                           for (int64_t k = 0; k < n; ++k) y[k] = x[k] + a * y[k];
+  const int fused = c->mode == MODE_CANONICAL;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) y[k] = fused ? fma(a, y[k], x[k]) : x[k] + a * y[k];
 }
 
 static void record(oracle_history* h, int64_t n, double gamma, const double* r,
@@ -540,8 +593,10 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
   if (rc) return rc;
   ctx_t c = {nx, ny, mode, ord};
   memset(res, 0, sizeof(*res));
+  const double t0 = wall_now();
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, hist)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, hist);
+  g_solve_seconds = wall_now() - t0;
   csr_free(&A);
   return rc;
 }
@@ -986,11 +1041,39 @@ done:
 
 /* ---------------------------------------------------------- refinement -- */
 
-static double dot_f32_in_f64(int64_t n, const float* a, const float* b) {
+/* Planted mistakes, for the tests that show the refinement pins catch them
+ * (a test builds a copy of this file with one of them; every real build has
+ * ORACLE_MUTANT 0):
+ *   1: the inner vectors kept in binary64;
+ *   2: the inner dot products summed in binary32;
+ *   3: alpha and beta of the inner solve left in binary64. */
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+#if ORACLE_MUTANT == 1
+typedef double inner_t;
+#define spmv_inner spmv
+#else
+typedef float inner_t;
+#define spmv_inner spmv_f32
+#endif
+#if ORACLE_MUTANT == 3
+typedef double inner_scalar_t;
+#else
+typedef inner_t inner_scalar_t;
+#endif
+
+static double dot_f32_in_f64(int64_t n, const inner_t* a, const inner_t* b) {
   /* each product of two binary32 values is exact in binary64 */
+#if ORACLE_MUTANT == 2
+  float s = 0.0f;
+  for (int64_t k = 0; k < n; ++k) s = s + (float)((double)a[k] * (double)b[k]);
+  return s;
+#else
   double s = 0.0;
   for (int64_t k = 0; k < n; ++k) s = s + (double)a[k] * (double)b[k];
   return s;
+#endif
 }
 
 /* FP32-inner / FP64-outer iterative refinement around classic CG:
@@ -1013,10 +1096,10 @@ int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, dou
   if (rc) return rc;
   const int64_t n = A.n;
   double* r = (double*)malloc((size_t)n * sizeof(double));
-  float* ri = (float*)malloc((size_t)n * sizeof(float));
-  float* d = (float*)malloc((size_t)n * sizeof(float));
-  float* p = (float*)malloc((size_t)n * sizeof(float));
-  float* s = (float*)malloc((size_t)n * sizeof(float));
+  inner_t* ri = (inner_t*)malloc((size_t)n * sizeof(inner_t));
+  inner_t* d = (inner_t*)malloc((size_t)n * sizeof(inner_t));
+  inner_t* p = (inner_t*)malloc((size_t)n * sizeof(inner_t));
+  inner_t* s = (inner_t*)malloc((size_t)n * sizeof(inner_t));
   memset(res, 0, sizeof(*res));
   int st = OR_OK;
   int32_t total = 0, outer = 0;
@@ -1039,23 +1122,26 @@ int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, dou
     if (total >= maxit) { st = OR_NOT_CONVERGED; break; }
     const double sc = sqrt(g), inv = 1.0 / sc;
     for (int64_t k = 0; k < n; ++k) {
-      ri[k] = (float)(r[k] * inv);
-      d[k] = 0.0f;
+      ri[k] = (inner_t)(r[k] * inv);
+      d[k] = 0;
       p[k] = ri[k];
     }
     double gamma = dot_f32_in_f64(n, ri, ri);
     const double thr_in = (inner_tol * inner_tol) * gamma;
     int32_t kin = 0;
     while (!(gamma <= thr_in) && total < maxit) {
-      spmv_f32(&A, p, s);
+      spmv_inner(&A, p, s);
       double pi = dot_f32_in_f64(n, p, s);
       if (!(pi > 0.0) || !isfinite(pi)) break;
       double alpha = gamma / pi;
-      float af = (float)alpha;
-      for (int64_t k = 0; k < n; ++k) { d[k] = d[k] + af * p[k]; ri[k] = ri[k] - af * s[k]; }
+      inner_scalar_t af = (inner_scalar_t)alpha;
+      for (int64_t k = 0; k < n; ++k) {
+        d[k] = (inner_t)(d[k] + af * p[k]);
+        ri[k] = (inner_t)(ri[k] - af * s[k]);
+      }
       double gnew = dot_f32_in_f64(n, ri, ri);
-      float bf = (float)(gnew / gamma);
-      for (int64_t k = 0; k < n; ++k) p[k] = ri[k] + bf * p[k];
+      inner_scalar_t bf = (inner_scalar_t)(gnew / gamma);
+      for (int64_t k = 0; k < n; ++k) p[k] = (inner_t)(ri[k] + bf * p[k]);
       gamma = gnew;
       ++kin; ++total;
     }

@@ -94,6 +94,8 @@ def _load():
     lib.oracle_cg_fixed.restype = C.c_int
     lib.oracle_cg_fixed.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_double,
                                     C.c_int32, C.POINTER(_Result)]
+    lib.oracle_last_solve_seconds.restype = C.c_double
+    lib.oracle_threads.restype = C.c_int
     lib.oracle_refine.restype = C.c_int
     lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
                                   C.c_int32, C.POINTER(_Result)]
@@ -284,6 +286,45 @@ def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
         hist = {k: v[:c] for k, v in hist.items()}
         return x, out, hist
     return x, out
+
+
+_lib_omp = None
+
+
+def _load_omp():
+    """The all-core OpenMP timing build of the same sources (CPU baseline)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if _build.stale(omp=True):
+            _build.build(omp=True)
+        lib = C.CDLL(_build.LIB_OMP)
+        P = C.c_void_p
+        lib.oracle_cg.restype = C.c_int
+        lib.oracle_cg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
+                                  P, P, P, C.c_double, C.c_int32, C.POINTER(_Result),
+                                  C.POINTER(_History)]
+        lib.oracle_last_solve_seconds.restype = C.c_double
+        lib.oracle_threads.restype = C.c_int
+        _lib_omp = lib
+    return _lib_omp
+
+
+def cg_timed(b, nx, ny, variant=VARIANT_CLASSIC, tol=0.0, maxit=10, all_cores=False):
+    """The sequential-mode solve, timed: returns (Result, seconds of the
+    iterations without the CSR assembly, threads used).  all_cores: the
+    OpenMP build (rows split over the threads, per-thread partial sums added
+    in thread order)."""
+    lib = _load_omp() if all_cores else _load()
+    b = _vec(b, nx, ny)
+    x = np.zeros_like(b)
+    res = _Result()
+    rc = lib.oracle_cg(variant, MODE_SEQUENTIAL, None, nx, ny, _ptr(b), None, _ptr(x), tol, maxit,
+                       C.byref(res), None)
+    if rc < 0:
+        raise ValueError("oracle_cg rejected the call: %d" % rc)
+    out = Result(status=res.status, iterations=res.iterations,
+                 rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
+    return out, lib.oracle_last_solve_seconds(), lib.oracle_threads()
 
 
 def cheb_coeffs(nx, ny, s):

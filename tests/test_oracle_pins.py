@@ -379,3 +379,125 @@ def test_refinement_inner_cap_and_zero():
     assert r.status == oracle.OR_NOT_CONVERGED and r.iterations == 10
     x, r = oracle.refine(np.zeros((3, 3)), 3, 3)
     assert r.status == oracle.OR_OK and r.iterations == 0 and not x.any()
+
+
+# ------------------------------------------- refinement: the FP32 inner solve --
+#
+# The refinement oracle's inner solve keeps its vectors, its stencil and its
+# axpys in binary32 and forms its dot products and scalar ratios in binary64,
+# rounding alpha and beta to binary32 once.  On a right-hand side built so that
+# every quantity of the first inner iteration is exact (integers of at most 21
+# bits scaled by a power of two, ||b|| a power of two), that iteration has one
+# correct outcome, fixed by the definitions alone: alpha = (rho, rho) /
+# (rho, A rho) evaluated exactly, rounded to binary64 and then to binary32,
+# and d = fl32(alpha * rho).
+
+def _rhs_with_power_of_two_norm(nx, ny, seed):
+    """Integers in [-4095, 4095] whose squares sum to 4^m: the last few
+    entries (greedy squares) complete the sum.  Returns (b, m)."""
+    n = nx * ny
+    rng = np.random.default_rng(seed)
+    while True:
+        v = rng.integers(-4095, 4096, n).astype(np.int64)
+        head = n - 16
+        S = int(np.sum(v[:head] * v[:head]))
+        m = (S.bit_length() + 1) // 2 + 1          # 4^m > S
+        R = 4 ** m - S
+        tail = []
+        while R > 0 and len(tail) < 16:
+            a = math.isqrt(R)
+            tail.append(a)
+            R -= a * a
+        if R == 0:
+            v[head:] = 0
+            v[head:head + len(tail)] = np.asarray(tail) * rng.choice([-1, 1], len(tail))
+            assert int(np.sum(v * v)) == 4 ** m
+            return v.reshape(ny, nx), m
+
+
+def _stencil_int(v):
+    """A v in exact integer arithmetic (the 5-point Laplacian, zero ring)."""
+    out = 4 * v
+    out[:, 1:] -= v[:, :-1]
+    out[:, :-1] -= v[:, 1:]
+    out[1:, :] -= v[:-1, :]
+    out[:-1, :] -= v[1:, :]
+    return out
+
+
+def _first_inner_step_pin(refine, nx=64, ny=64, seed=77):
+    """True when one outer step with one inner iteration of `refine` gives
+    x = ||b|| * fl32(alpha32 * rho) exactly."""
+    from fractions import Fraction
+    bi, m = _rhs_with_power_of_two_norm(nx, ny, seed)
+    b = bi.astype(np.float64)
+    x, r = refine(b, nx, ny, tol=1e-12, inner_tol=1e-4, maxit=1)
+    assert r.status == oracle.OR_NOT_CONVERGED and r.iterations == 1
+    assert r.outer_iterations == 1
+    scale = 2.0 ** m                                  # ||b||, exactly
+    rho = (b / scale).astype(np.float32)              # exact: 21-bit integers / 2^m
+    assert np.array_equal(rho.astype(np.float64) * scale, b)
+    Ab = _stencil_int(bi)
+    gamma = Fraction(int(np.sum(bi * bi)), 4 ** m)    # = 1
+    pi = Fraction(int(np.sum(bi * Ab)), 4 ** m)
+    alpha32 = np.float32(float(gamma / pi))           # binary64, then binary32
+    d_want = np.float32(alpha32) * rho                # one binary32 rounding each
+    return bool(np.array_equal(x / scale, d_want.astype(np.float64)))
+
+
+def test_refinement_first_inner_step_is_binary32_with_binary64_dots():
+    assert _first_inner_step_pin(oracle.refine)
+
+
+def test_refinement_inner_accuracy_is_binary32_limited():
+    """Whatever the inner tolerance, one outer step cannot take the true
+    residual below what binary32 vectors hold (about kappa * 2^-24 of ||b||):
+    even with inner tol 1e-12 a tolerance of 1e-11 needs a second outer step;
+    after each outer step x / ||r|| increment is binary32 (d is stored so)."""
+    nx, ny = 40, 30
+    b = np.random.default_rng(12).standard_normal((ny, nx))
+    x, r = oracle.refine(b, nx, ny, tol=1e-11, inner_tol=1e-12)
+    assert r.status == oracle.OR_OK and r.outer_iterations >= 2
+    rt = np.linalg.norm(b.ravel() - sparse_A(nx, ny) @ x.ravel()) / np.linalg.norm(b)
+    assert rt <= 1e-11
+    # one outer step only (maxit = the first inner solve's length is not
+    # known, so cap the inner iterations well inside it): x = ||b|| * d
+    x1, r1 = oracle.refine(b, nx, ny, tol=1e-11, inner_tol=1e-12, maxit=20)
+    assert r1.outer_iterations == 1 and r1.iterations == 20
+    d = x1 / math.sqrt(math.fsum((b * b).ravel()))
+    nz = d != 0
+    assert nz.sum() > 0.9 * d.size
+    rel32 = np.abs(d[nz] - d[nz].astype(np.float32)) / np.abs(d[nz])
+    assert rel32.max() <= 1e-15
+
+
+@pytest.mark.parametrize("mutant", [1, 2, 3])
+def test_refinement_pins_catch_planted_mistakes(tmp_path, mutant):
+    """Copies of the oracle built with a planted mistake (1: binary64 inner
+    vectors, 2: binary32 inner dots, 3: alpha and beta left in binary64) fail
+    the first-inner-step pin that the real oracle passes."""
+    import ctypes as C
+    import subprocess
+    from oracle import oracle as _oracle_mod
+    src = os.path.join(os.path.dirname(oracle.lib_path()), "cg_oracle.c")
+    lib_path = str(tmp_path / ("mutant%d.so" % mutant))
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                    "-shared", "-DORACLE_MUTANT=%d" % mutant, "-o", lib_path, src, "-lm"],
+                   check=True)
+    lib = C.CDLL(lib_path)
+    P = C.c_void_p
+    lib.oracle_refine.restype = C.c_int
+    lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
+                                  C.c_int32, C.POINTER(_oracle_mod._Result)]
+
+    def refine(b, nx, ny, tol, inner_tol, maxit):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b)
+        res = _oracle_mod._Result()
+        rc = lib.oracle_refine(nx, ny, b.ctypes.data, None, x.ctypes.data, tol, inner_tol, maxit,
+                               C.byref(res))
+        assert rc >= 0
+        return x, _oracle_mod.Result(status=res.status, iterations=res.iterations,
+                                outer_iterations=res.outer_iterations)
+
+    assert not _first_inner_step_pin(refine)
