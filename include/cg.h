@@ -106,8 +106,8 @@ typedef struct {
                               literature Section I builds on): classic CG with
                               z = M^-1 r, or the preconditioned pipelined CG of
                               Ghysels and Vanroose (variant PIPELINED); the stop
-                              test stays on ||r||; cg_solve only (batches and
-                              serving reject it)                                   */
+                              test stays on ||r||; FP64; alone, in batches and
+                              served                                               */
   int32_t nz;              /* 0 or 1: the 2D problem above.  nz > 1: the 3D 7-point
                               Laplacian (centre 6, the six face neighbours -1) on an
                               nx x ny x nz interior grid with zero Dirichlet

@@ -180,6 +180,14 @@ struct alignas(64) Slot {
   int32_t variant, refined;
   int32_t cpl4;      // 4 columns per lane (refined, or pinned classic FP64)
   int32_t admit_step;
+  int32_t precond;     // Chebyshev steps s of the preconditioner; 0 = none
+  int32_t cheb_rows;   // rows of a Chebyshev item / partial tile
+  int32_t cheb_tiles;  // partials of the Chebyshev pass
+  int32_t cheb_items;  // Chebyshev items of one pass (the step's items number them)
+  const double* cheb;  // c0, c1[s-1], c2[s-1]
+  double* u;           // preconditioned pipelined: u = M^-1 r
+  double* sv;          //                           s
+  double* mv;          //                           m = M^-1 w
   double* b;
   double* x;
   double* r;
@@ -195,7 +203,8 @@ struct alignas(64) Slot {
   State* S[2];       // state, by pass parity
 };
 
-// A unit of work of one step: tiles [t0, t1) of one resident solve.
+// A unit of work of one step: tiles [t0, t1) of one resident solve (for the
+// Chebyshev step kernel: its Chebyshev items [t0, t1)).
 struct Item {
   int32_t slot, t0, t1, pad_;
 };
@@ -275,6 +284,13 @@ hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
 hipError_t launch_gather(const Slot* slots, const int* idx, int n, int step, State* out,
                          hipStream_t s);
 int step_max_blocks_per_cu();
+// The Chebyshev passes (K_CHEB, K_CHEBW) of step *step_base + k of the
+// resident preconditioned solves with s Chebyshev steps (1 <= s <= 8):
+// work-groups of 512 threads stride over cinfo[2 s] items (Chebyshev item
+// ranges) that start at items + cinfo[2 s + 1] (both read on the device);
+// every other solve and pass kind is left to launch_step.
+hipError_t launch_step_cheb(int s, const Slot* slots, const Item* items, const int* cinfo,
+                            const int* step_base, int k, int grid, hipStream_t st);
 hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
                          hipStream_t s);
 size_t pass_algorithmic_bytes(int kind, int64_t dof);

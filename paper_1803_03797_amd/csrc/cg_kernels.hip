@@ -1741,6 +1741,46 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
   acc1 = g.a1;
 }
 
+// Chebyshev item `it` (ngx items across): each wavefront marches its 112
+// output columns over the item's rows; without PIPE the (r, z) column sums
+// become one partial per 128-column tile (wavefront m folds tile m).
+// `colacc` holds kChebWaves * kChebOut doubles.
+template <int S, bool PIPE>
+__device__ __forceinline__ void cheb_item(const PassArgs& a, int it, int ngx, double* colacc) {
+  const Geo& g = a.g;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+  const int Hc = a.cheb_rows;
+  const int gx = it % ngx, ty = it / ngx;
+  const int cw = gx * (kChebGroupTiles * 2 * kWave) + wave * kChebOut;
+  const int y0 = ty * Hc, y1 = min(y0 + Hc, g.ny);
+  double acc0 = 0.0, acc1 = 0.0;
+  if (cw < g.nx) {
+    const bool inner = cw >= kChebHaloCols && cw + kChebOut + kChebHaloCols <= g.nx &&
+                       y0 >= S - 1 && y1 + (S - 1) <= g.ny;
+    if (inner) cheb_march<S, false>(a, cw, y0, y1, acc0, acc1);
+    else cheb_march<S, true>(a, cw, y0, y1, acc0, acc1);
+  }
+  // PIPE: no partials, the fused pass sums its dots.  The column sums are
+  // still formed: without them the compiler schedules the march of s = 8
+  // into more than 256 registers and spills.
+  if constexpr (PIPE) __asm__ volatile("" ::"v"(acc0), "v"(acc1));
+  if (!PIPE && lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2) {
+    double* c = colacc + wave * kChebOut + 2 * (lane - kChebHaloCols / 2);
+    c[0] = acc0;
+    c[1] = acc1;
+  }
+  __syncthreads();
+  if (!PIPE && wave < kChebGroupTiles) {
+    const int tx = gx * kChebGroupTiles + wave;
+    if (tx < g.ntx) {
+      const double* c = colacc + wave * 2 * kWave + 2 * lane;
+      const double v = wave_sum(c[0] + c[1]);
+      if (lane == 0) a.part_out[(size_t)ty * g.ntx + tx] = v;
+    }
+  }
+  __syncthreads();
+}
+
 // PIPE = false: K_CHEB (z = M^-1 r of classic CG, and of the pipelined
 // variant's first residual); PIPE = true: K_CHEBW (m = M^-1 w of the
 // pipelined variant, after its scalar step; no partials).  The input vector
@@ -1779,44 +1819,13 @@ __global__ __launch_bounds__(kChebThreads) void k_cheb(PassArgs a) {
     if (!run) return;
   }
   const Geo& g = a.g;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int ngx = (g.ntx + kChebGroupTiles - 1) / kChebGroupTiles;
   const int Hc = a.cheb_rows, nty = (g.ny + Hc - 1) / Hc;
   const int I = ngx * nty;
   const int G = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
   const int i0 = (int)(((int64_t)I * xcd) >> 3), i1 = (int)(((int64_t)I * (xcd + 1)) >> 3);
-  for (int it = i0 + slot; it < i1; it += nb) {
-    const int gx = it % ngx, ty = it / ngx;
-    const int cw = gx * (kChebGroupTiles * 2 * kWave) + wave * kChebOut;
-    const int y0 = ty * Hc, y1 = min(y0 + Hc, g.ny);
-    double acc0 = 0.0, acc1 = 0.0;
-    if (cw < g.nx) {
-      const bool inner = cw >= kChebHaloCols && cw + kChebOut + kChebHaloCols <= g.nx &&
-                         y0 >= S - 1 && y1 + (S - 1) <= g.ny;
-      if (inner) cheb_march<S, false>(a, cw, y0, y1, acc0, acc1);
-      else cheb_march<S, true>(a, cw, y0, y1, acc0, acc1);
-    }
-    // PIPE: no partials, the fused pass sums its dots.  The column sums are
-    // still formed: without them the compiler schedules the march of s = 8
-    // into more than 256 registers and spills.
-    if constexpr (PIPE) __asm__ volatile("" ::"v"(acc0), "v"(acc1));
-    if (!PIPE && lane >= kChebHaloCols / 2 && lane < kWave - kChebHaloCols / 2) {
-      double* c = colacc + wave * kChebOut + 2 * (lane - kChebHaloCols / 2);
-      c[0] = acc0;
-      c[1] = acc1;
-    }
-    __syncthreads();
-    if (!PIPE && wave < kChebGroupTiles) {
-      const int tx = gx * kChebGroupTiles + wave;
-      if (tx < g.ntx) {
-        const double* c = colacc + wave * 2 * kWave + 2 * lane;
-        const double v = wave_sum(c[0] + c[1]);
-        if (lane == 0) a.part_out[(size_t)ty * g.ntx + tx] = v;
-      }
-    }
-    __syncthreads();
-  }
+  for (int it = i0 + slot; it < i1; it += nb) cheb_item<S, PIPE>(a, it, ngx, colacc);
 }
 
 __global__ void k_fill(uint32_t* p, size_t n) {
@@ -2452,15 +2461,23 @@ __device__ __forceinline__ bool step_transition(State& s, const double* sum, Sc&
   }
 }
 
-// Kind of the pass after `kind`, given whether its body ran.
+// Kind of the pass after `kind`, given whether its body ran.  Preconditioned
+// (precond != 0): classic CG runs K_CHEB, K_CG1, K_CG2 per iteration; the
+// pipelined variant K_CHEB and K_INIT_WU once, then K_CHEBW, K_PPCG.
 __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int variant,
-                                         int refined) {
+                                         int refined, int precond) {
+  const int stop = s.status == ST_ZERO_RHS ? K_DONE : K_RESID;
   switch (kind) {
-    case K_INIT_R: return variant == 1 ? K_INIT_W : K_CG1;
+    case K_INIT_R:
+      return precond ? K_CHEB : variant == 1 ? K_INIT_W : K_CG1;
     case K_INIT_W: return ran ? K_PCG : K_DONE;
-    case K_PCG: return ran ? K_PCG : (s.status == ST_ZERO_RHS ? K_DONE : K_RESID);
-    case K_CG1: return ran ? K_CG2 : (s.status == ST_ZERO_RHS ? K_DONE : K_RESID);
-    case K_CG2: return ran ? K_CG1 : K_RESID;
+    case K_PCG: return ran ? K_PCG : stop;
+    case K_CHEB: return ran ? (variant == 1 ? K_INIT_WU : K_CG1) : stop;
+    case K_INIT_WU: return ran ? K_CHEBW : stop;
+    case K_CHEBW: return ran ? K_PPCG : stop;
+    case K_PPCG: return ran ? K_CHEBW : stop;
+    case K_CG1: return ran ? K_CG2 : stop;
+    case K_CG2: return ran ? (precond ? K_CHEB : K_CG1) : K_RESID;
     case K_RESID: return refined ? K_REF_SCALE : K_FINAL;
     case K_FINAL: return K_DONE;
     case K_REF_SCALE: return ran ? K_CG1F : K_DONE;
@@ -2471,36 +2488,10 @@ __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int
   return K_DONE;
 }
 
-template <int KIND, int CPL>
-__device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, State s,
-                                          double* lds, int rev) {
-  constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
-  constexpr int DO = (KIND == K_FINAL) ? 0 : ndots_out<KIND>();
-  static_assert(DO <= 2, "passes with three slots run only as multi-work-group passes");
-  const int T = S.g.tiles;
-  double sum[2] = {0.0, 0.0};
-  if constexpr (DI > 0) {
-    const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) ? 2 : 1) : DI;
-    if (s.status == ST_RUNNING || KIND == K_FINAL) {
-      if (din == 2) cross_tile_sum<2>(S.part[m & 1], T, sum, lds);
-      else cross_tile_sum<1>(S.part[m & 1], T, sum, lds);
-    }
-    sum[0] = uniform(sum[0]);
-    sum[1] = uniform(sum[1]);
-  }
-  // ping-pong parities come from the iteration counters before the transition
-  const int k0 = s.k, kin0 = s.kin;
-  Sc sc;
-  bool flush = false;
-  bool run;
-  if constexpr (KIND == K_FINAL) run = step_transition<KIND>(s, sum, sc);
-  else run = transition_x<KIND>(s, sum, sc, flush);
-  if (it.t0 == 0 && threadIdx.x == 0) {
-    State o = s;
-    o.kind = next_kind(KIND, run, s, S.variant, S.refined);
-    *S.S[(m + 1) & 1] = o;
-  }
-  if (!run && !flush) return;
+// The pass arguments of a resident solve at pass m (vector ping-pong
+// parities from the iteration counters k0, kin0 before the transition).
+template <int KIND>
+__device__ __forceinline__ PassArgs slot_args(const Slot& S, int m, int k0, int kin0) {
   PassArgs a;
   a.g = S.g;
   a.st_in = nullptr;
@@ -2509,7 +2500,8 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.part_out = S.part[(m + 1) & 1];
   a.b = S.b;
   a.x = S.x;
-  a.r = S.r;
+  // preconditioned classic pass 1 forms p = z + beta p
+  a.r = (KIND == K_CG1 && S.precond) ? S.z : S.r;
   a.z = S.z;
   a.q = S.q;
   a.p = S.p;
@@ -2526,8 +2518,52 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   a.u = nullptr;
   a.y = nullptr;
   a.rev = 0;
-  a.cheb_s = 0;
-  a.cheb = nullptr;
+  a.cheb_s = S.precond;
+  a.cheb_rows = S.cheb_rows;
+  a.cheb_tiles = S.cheb_tiles;
+  a.cheb = S.cheb;
+  a.uu = S.u;
+  a.sv = S.sv;
+  a.mv = S.mv;
+  a.wv = S.W[0];
+  return a;
+}
+
+template <int KIND, int CPL>
+__device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, State s,
+                                          double* lds, int rev) {
+  constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
+  constexpr int DO = (KIND == K_FINAL) ? 0 : ndots_out<KIND>();
+  static_assert(DO <= 3, "at most three partial slots per pass");
+  const int T = S.g.tiles;
+  double sum[2] = {0.0, 0.0};
+  if constexpr (DI > 0) {
+    // classic pass 1 also takes (b,b) after the initial residual; with the
+    // preconditioner its one slot is (r,z) in the Chebyshev pass's tiles
+    const bool pc = KIND == K_CG1 && (s.flags & F_PRECOND);
+    const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) && !pc ? 2 : 1) : DI;
+    const int tin = pc ? S.cheb_tiles : T;
+    if (s.status == ST_RUNNING || KIND == K_FINAL) {
+      if (din == 2) cross_tile_sum<2>(S.part[m & 1], tin, sum, lds);
+      else cross_tile_sum<1>(S.part[m & 1], tin, sum, lds);
+    }
+    sum[0] = uniform(sum[0]);
+    sum[1] = uniform(sum[1]);
+  }
+  // ping-pong parities come from the iteration counters before the transition
+  const int k0 = s.k, kin0 = s.kin;
+  Sc sc;
+  bool flush = false;
+  bool run;
+  if constexpr (KIND == K_FINAL) run = step_transition<KIND>(s, sum, sc);
+  else run = transition_x<KIND>(s, sum, sc, flush);
+  if (it.t0 == 0 && threadIdx.x == 0) {
+    State o = s;
+    o.kind = next_kind(KIND, run, s, S.variant, S.refined, S.precond);
+    *S.S[(m + 1) & 1] = o;
+  }
+  if (!run && !flush) return;
+  const PassArgs a = slot_args<KIND>(S, m, k0, kin0);
   if constexpr (defers_x<KIND>()) {
     if (flush) {
       for (int t = it.t0; t < it.t1; ++t) run_flush<KIND, CPL>(a, t, sc);
@@ -2538,7 +2574,7 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   int par = 0;
   for (int tt = it.t0; tt < it.t1; ++tt, par ^= 1) {
     const int t = rev ? it.t1 - 1 - (tt - it.t0) : tt;
-    double lv[2] = {0.0, 0.0};
+    double lv[3] = {0.0, 0.0, 0.0};
     run_body_any<KIND, CPL>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
@@ -2563,6 +2599,8 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
       if (it.t0 == 0 && threadIdx.x == 0) *S.S[(m + 1) & 1] = s;
       continue;
     }
+    // the Chebyshev passes belong to the Chebyshev step kernel
+    if (kind == K_CHEB || kind == K_CHEBW) continue;
     if (S.cpl4) {
       switch (kind) {
         case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds, rev); break;
@@ -2580,6 +2618,8 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
         case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds, rev); break;
         case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds, rev); break;
         case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds, rev); break;
+        case K_INIT_WU: step_item<K_INIT_WU, 2>(S, it, m, s, lds, rev); break;
+        case K_PPCG: step_item<K_PPCG, 2>(S, it, m, s, lds, rev); break;
         case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds, rev); break;
         case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds, rev); break;
         case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds, rev); break;
@@ -2587,6 +2627,77 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
       }
     }
     __syncthreads();  // LDS reuse by the next item
+  }
+}
+
+// The Chebyshev passes of the step engine: for a solve whose state names
+// K_CHEB or K_CHEBW at this step, the item's work-group sums the previous
+// pass's partials, applies the transition of k_cheb and marches Chebyshev
+// items [t0, t1) of the solve exactly as k_cheb does (same items, same
+// partial tiles, hence the same bits); a stop after an odd iteration applies
+// the pending x update on the tiles matching the item's share instead.
+// Solves at any other pass are skipped (k_step runs them).
+template <int S>
+__global__ __launch_bounds__(kChebThreads) void k_step_cheb(const Slot* slots, const Item* items,
+                                                           const int* cinfo,
+                                                           const int* step_base, int k) {
+  __shared__ double colacc[kChebWaves * kChebOut];
+  __shared__ double red[4 * 3];
+  // this s's items: cinfo[2 s] items from items + cinfo[2 s + 1]
+  const int n = __builtin_amdgcn_readfirstlane(cinfo[2 * S]);
+  items += __builtin_amdgcn_readfirstlane(cinfo[2 * S + 1]);
+  const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
+  for (int ii = blockIdx.x; ii < n; ii += gridDim.x) {
+    const Item it = items[ii];
+    const Slot& Sl = slots[__builtin_amdgcn_readfirstlane(it.slot)];
+    const int m = step - Sl.admit_step;
+    State s = load_state_uniform(Sl.S[m & 1]);
+    const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+    if (kind != K_CHEB && kind != K_CHEBW) continue;
+    const bool pipe = kind == K_CHEBW;
+    const int T = Sl.g.tiles;
+    double sum[3] = {0.0, 0.0, 0.0};
+    if (s.status == ST_RUNNING) {
+      if (pipe) cross_tile_sum<3>(Sl.part[m & 1], T, sum, red);
+      else if (s.flags & F_BB_PENDING) cross_tile_sum<2>(Sl.part[m & 1], T, sum, red);
+      else cross_tile_sum<1>(Sl.part[m & 1], T, sum, red);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sum[d] = uniform(sum[d]);
+    const int k0 = s.k;
+    Sc sc;
+    bool flush = false;
+    const bool run = pipe ? transition<K_CHEBW>(s, sum, sc)
+                          : transition_x<K_CHEB>(s, sum, sc, flush);
+    if (it.t0 == 0 && threadIdx.x == 0) {
+      State o = s;
+      o.kind = next_kind(kind, run, s, Sl.variant, Sl.refined, Sl.precond);
+      *Sl.S[(m + 1) & 1] = o;
+    }
+    PassArgs a = slot_args<K_CHEB>(Sl, m, k0, 0);
+    if (flush) {
+      // the test stopped the solve after an odd iteration: x update on the
+      // tiles in proportion to this item's share of the Chebyshev items
+      const int I = Sl.cheb_items;
+      const int t0 = (int)((int64_t)T * it.t0 / I), t1 = (int)((int64_t)T * it.t1 / I);
+      if (threadIdx.x < kGroup)
+        for (int t = t0; t < t1; ++t) run_flush<K_CHEB, 2>(a, t, sc);
+      continue;
+    }
+    if (!run) continue;
+    // input and output: classic z = M^-1 r; pipelined u = M^-1 r first, then
+    // m = M^-1 w
+    if (pipe) {
+      a.r = Sl.W[0];
+      a.z = Sl.mv;
+    } else if (Sl.variant == 1) {
+      a.z = Sl.u;
+    }
+    const int ngx = (Sl.g.ntx + kChebGroupTiles - 1) / kChebGroupTiles;
+    for (int ci = it.t0; ci < it.t1; ++ci) {
+      if (pipe) cheb_item<S, true>(a, ci, ngx, colacc);
+      else cheb_item<S, false>(a, ci, ngx, colacc);
+    }
   }
 }
 
@@ -2603,6 +2714,30 @@ hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
   if (grid < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_step, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items, step_base,
                      k);
+  return hipGetLastError();
+}
+
+template <int S>
+static void launch_step_cheb_s(const Slot* slots, const Item* items, const int* cinfo,
+                               const int* step_base, int k, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_cheb<S>, dim3(grid), dim3(kChebThreads), 0, st, slots, items, cinfo,
+                     step_base, k);
+}
+
+hipError_t launch_step_cheb(int s, const Slot* slots, const Item* items, const int* cinfo,
+                            const int* step_base, int k, int grid, hipStream_t st) {
+  if (grid < 1) return hipErrorInvalidValue;
+  switch (s) {
+    case 1: launch_step_cheb_s<1>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 2: launch_step_cheb_s<2>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 3: launch_step_cheb_s<3>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 4: launch_step_cheb_s<4>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 5: launch_step_cheb_s<5>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 6: launch_step_cheb_s<6>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 7: launch_step_cheb_s<7>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 8: launch_step_cheb_s<8>(slots, items, cinfo, step_base, k, grid, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

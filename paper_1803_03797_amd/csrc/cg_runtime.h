@@ -125,8 +125,8 @@ struct Ctx {
   int serve_chunk = 8;         // serving: steps between admissions
   int step_chunk_for(bool serving) const { return serving ? serve_chunk : step_chunk; }
   size_t engine_bytes() const {  // control block of the multi-solve engine
-    return (size_t)max_slots * (sizeof(cgk::Slot) + 256 * sizeof(cgk::Item) + 2 * sizeof(int) +
-                                sizeof(cgk::State)) + 4096;
+    return (size_t)max_slots * (sizeof(cgk::Slot) + 2 * 256 * sizeof(cgk::Item) +
+                                2 * sizeof(int) + sizeof(cgk::State)) + 8192;
   }
   bool capturing = false;
   bool prof = false;

@@ -69,6 +69,8 @@ class Engine {
     if (h_idx_) hipHostFree(h_idx_);
     if (h_states_) hipHostFree(h_states_);
     if (h_admit_) hipHostFree(h_admit_);
+    if (h_coef_) hipHostFree(h_coef_);
+    if (h_citems_) hipHostFree(h_citems_);
     if (h_step_) hipHostFree(h_step_);
   }
 
@@ -79,8 +81,15 @@ class Engine {
     const size_t b_idx = round256((size_t)n_ * sizeof(int) + sizeof(int));
     const size_t b_states = round256((size_t)n_ * sizeof(State));
     const size_t b_rr = round256((size_t)n_ * sizeof(int));
-    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states + b_rr + 256);
+    // Chebyshev items (the same budget as the tile items) and, per s, their
+    // count and offset
+    const size_t b_citems = round256((size_t)max_items_ * sizeof(Item));
+    const size_t b_cinfo = round256(2 * (kChebMaxSteps + 1) * sizeof(int));
+    ctrl_ = (char*)c_.arena.alloc(b_slots + b_items + b_idx + b_states + b_rr + 256 + b_citems +
+                                  b_cinfo);
     if (!ctrl_) return CG_E_NOMEM;
+    d_citems_ = (Item*)(ctrl_ + b_slots + b_items + b_idx + b_states + b_rr + 256);
+    d_cinfo_ = (int*)((char*)d_citems_ + b_citems);
     d_slots_ = (Slot*)ctrl_;
     d_items_ = (Item*)(ctrl_ + b_slots);
     d_idx_ = (int*)(ctrl_ + b_slots + b_items);
@@ -98,6 +107,11 @@ class Engine {
         hipHostMalloc((void**)&h_idx_, (size_t)n_ * sizeof(int) + 256, hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_states_, (size_t)n_ * sizeof(State), hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_admit_, (size_t)n_ * sizeof(State), hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_coef_, (size_t)n_ * kCoefPerSlot * sizeof(double),
+                      hipHostMallocDefault) ||
+        hipHostMalloc((void**)&h_citems_,
+                      (size_t)max_items_ * sizeof(Item) + 2 * (kChebMaxSteps + 1) * sizeof(int),
+                      hipHostMallocDefault) ||
         hipHostMalloc((void**)&h_step_, kStepRing * sizeof(int), hipHostMallocDefault))
       return CG_E_DEVICE;
     memset(h_slots_, 0, (size_t)n_ * sizeof(Slot));
@@ -133,6 +147,14 @@ class Engine {
     int rc = j->ready && hipStreamWaitEvent(c_.st, j->ready, 0) != hipSuccess
                  ? CG_E_DEVICE
                  : stage_in_async(c_, j->w, &j->p, &s);
+    if (!rc && j->w.pl.precond) {
+      // the preconditioner's coefficients, from the slot's pinned records
+      double* coef = h_coef_ + (size_t)slot * kCoefPerSlot;
+      cheb_coeffs(j->p.nx, j->p.ny, j->w.pl.precond, coef);
+      if (hipMemcpyAsync(j->w.cheb, coef, (size_t)(2 * j->w.pl.precond - 1) * sizeof(double),
+                         hipMemcpyHostToDevice, c_.st))
+        rc = CG_E_DEVICE;
+    }
     if (rc) {
       hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
@@ -165,6 +187,16 @@ class Engine {
     S.part[1] = w.part[1];
     S.S[0] = w.S[0];
     S.S[1] = w.S[1];
+    S.precond = w.pl.precond;
+    if (w.pl.precond) {
+      S.cheb_rows = w.pl.cheb_rows;
+      S.cheb_tiles = w.pl.cheb_tiles;
+      S.cheb_items = cheb_items_of(w.pl);
+      S.cheb = w.cheb;
+      S.u = w.u;
+      S.sv = w.sv;
+      S.mv = w.mv;
+    }
     if (hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st)) {
       hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
@@ -178,7 +210,7 @@ class Engine {
     else ++step_jobs_;
     // a bound on the passes of the solve (a guard against a solve that never
     // reaches K_DONE; it cannot trigger for a correct pass sequence)
-    j->steps_cap = (int64_t)step_ + step_bound(j->p, w.pl.refined);
+    j->steps_cap = (int64_t)step_ + step_bound(j->p, w.pl.refined, w.pl.precond);
     ++active_;
     dirty_ = true;
     return CG_OK;
@@ -252,14 +284,13 @@ class Engine {
     *hs = step_;
     if (hipMemcpyAsync(d_step_, hs, sizeof(int), hipMemcpyHostToDevice, c_.st)) return CG_E_DEVICE;
     const bool use_graph = c_.graph_chunk > 0 && steps == c_.step_chunk_for(this_is_serving_);
-    if (use_graph && (!graph_ || graph_steps_ != steps)) {
+    if (use_graph && (!graph_ || graph_steps_ != steps || graph_mask_ != cheb_mask_)) {
       if (graph_) hipGraphExecDestroy(graph_);
       graph_ = nullptr;
       hipGraph_t g;
       if (hipStreamBeginCapture(c_.st, hipStreamCaptureModeThreadLocal)) return CG_E_DEVICE;
       hipError_t e = hipSuccess;
-      for (int k = 0; k < steps && e == hipSuccess; ++k)
-        e = launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st);
+      for (int k = 0; k < steps && e == hipSuccess; ++k) e = launch_one_step(k);
       hipError_t e2 = hipStreamEndCapture(c_.st, &g);
       if (e || e2) return CG_E_DEVICE;
       e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
@@ -269,13 +300,13 @@ class Engine {
         return CG_E_DEVICE;
       }
       graph_steps_ = steps;
+      graph_mask_ = cheb_mask_;
     }
     if (use_graph) {
       if (hipGraphLaunch(graph_, c_.st)) return CG_E_DEVICE;
     } else {
       for (int k = 0; k < steps; ++k)
-        if (launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st) != hipSuccess)
-          return CG_E_DEVICE;
+        if (launch_one_step(k) != hipSuccess) return CG_E_DEVICE;
     }
     if (c_.prof) {
       hipEventRecord(e1, c_.st);
@@ -366,9 +397,19 @@ class Engine {
   // and every outer step but the last takes at least one of the maxit inner
   // iterations, so at most 2 maxit + 4 (maxit + 1) passes, plus the final
   // RESID and REF_SCALE.
-  static int64_t step_bound(const cg_problem& p, bool refined) {
+  // Preconditioned: classic runs three passes per iteration (K_CHEB, K_CG1,
+  // K_CG2), the pipelined variant two (K_CHEBW, K_PPCG).
+  static int64_t step_bound(const cg_problem& p, bool refined, int precond) {
     const int64_t m = p.maxit;
-    return refined ? 6 * m + 32 : 2 * m + 32;
+    return refined ? 6 * m + 32 : precond ? 3 * m + 32 : 2 * m + 32;
+  }
+
+  // Chebyshev items of one pass of a preconditioned solve (as k_cheb numbers
+  // them: groups of kChebGroupCols columns by cheb_rows rows)
+  static int cheb_items_of(const Plan& pl) {
+    const int ngx = (pl.g.ntx * 2 * kWave + kChebGroupCols - 1) / kChebGroupCols;
+    const int nty = (pl.g.ny + pl.cheb_rows - 1) / pl.cheb_rows;
+    return ngx * nty;
   }
 
   // Rebuilds the item table: each resident solve contributes up to
@@ -384,13 +425,47 @@ class Engine {
     }
     int* nn = (int*)(h_items_ + max_items_);
     *nn = n;
+    // Chebyshev items, grouped by s (each group's count and offset in cinfo)
+    int nc = 0;
+    int* cinfo = (int*)(h_citems_ + max_items_);
+    for (int sd = 0; sd <= kChebMaxSteps; ++sd) {
+      cinfo[2 * sd] = 0;
+      cinfo[2 * sd + 1] = nc;
+      if (sd == 0) continue;
+      for (int i = 0; i < n_; ++i) {
+        Job* j = slot_job_[i];
+        if (!j || j->w.pl.on_side() || j->w.pl.precond != sd) continue;
+        const int I = cheb_items_of(j->w.pl);
+        const int per = (I + kMaxItemsPerSolve - 1) / kMaxItemsPerSolve;
+        for (int t = 0; t < I; t += per) h_citems_[nc++] = Item{i, t, std::min(I, t + per), 0};
+      }
+      cinfo[2 * sd] = nc - cinfo[2 * sd + 1];
+      if (cinfo[2 * sd]) cheb_mask_ |= 1u << sd;
+    }
     if (hipMemcpyAsync(d_items_, h_items_, (size_t)std::max(n, 1) * sizeof(Item),
                        hipMemcpyHostToDevice, c_.st) ||
         hipMemcpyAsync(d_nitems_, nn, sizeof(int), hipMemcpyHostToDevice, c_.st) ||
+        (nc && hipMemcpyAsync(d_citems_, h_citems_, (size_t)nc * sizeof(Item),
+                              hipMemcpyHostToDevice, c_.st)) ||
+        hipMemcpyAsync(d_cinfo_, cinfo, 2 * (kChebMaxSteps + 1) * sizeof(int),
+                       hipMemcpyHostToDevice, c_.st) ||
         hipStreamSynchronize(c_.st))
       return CG_E_DEVICE;
     dirty_ = false;
     return CG_OK;
+  }
+
+  // One step: the step kernel, then the Chebyshev step kernel of every s
+  // that a preconditioned solve of this engine has used (a solve at any
+  // other pass is skipped by the Chebyshev kernels; an s with no solve
+  // resident has no items).
+  hipError_t launch_one_step(int k) {
+    hipError_t e = launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st);
+    for (int sd = 1; sd <= kChebMaxSteps && e == hipSuccess; ++sd)
+      if (cheb_mask_ & (1u << sd))
+        e = launch_step_cheb(sd, d_slots_, d_citems_, d_cinfo_, d_step_, k,
+                             std::max(8, cheb_max_blocks_per_cu(sd) * c_.num_cu), c_.st);
+    return e;
   }
 
   static constexpr int kStepRing = 64;
@@ -415,6 +490,13 @@ class Engine {
   State* d_states_ = nullptr;
   Slot* h_slots_ = nullptr;
   State* h_admit_ = nullptr;  // initial state of each slot's solve (pinned)
+  static constexpr int kCoefPerSlot = 16;
+  double* h_coef_ = nullptr;  // Chebyshev coefficients of each slot's solve (pinned)
+  Item* h_citems_ = nullptr;  // Chebyshev items, then cinfo (pinned)
+  Item* d_citems_ = nullptr;
+  int* d_cinfo_ = nullptr;
+  unsigned cheb_mask_ = 0;    // Chebyshev steps s that any admitted solve has used
+  unsigned graph_mask_ = 0;   // ... when the cached chunk was captured
   Item* h_items_ = nullptr;
   int* h_idx_ = nullptr;
   State* h_states_ = nullptr;

@@ -196,11 +196,6 @@ def test_edge_cases(ctx, variant):
 def test_rejections(ctx):
     b = np.ones((8, 8))
     x = np.zeros_like(b)
-    p = cg.make_problem(b, x, 8, 8, precond=4)
-    with pytest.raises(cg.CGError):
-        ctx.cg_solve_batch([p])
-    with pytest.raises(cg.CGError):
-        ctx.cg_submit(p)
     for bad in (9, -1):
         with pytest.raises(cg.CGError):
             ctx.solve(b, x, 8, 8, precond=bad)
@@ -241,3 +236,87 @@ def test_profiled_passes_pipelined(ctx):
     assert st["cheb_precond_w"]["launches"] == m
     assert st["ppcg_pass"]["launches"] == m
     assert st["ppcg_pass"]["bytes"] == m * 136 * n * n
+
+
+# ------------------------------------------------ batches and serving --
+
+MIX = [(300, 190, 4, 0), (513, 257, 8, 1), (1, 1, 2, 0), (64, 1, 1, 1), (100, 100, 0, 1),
+       (130, 70, 2, 1), (1024, 1024, 8, 0), (257, 129, 0, 0), (200, 150, 4, 1),
+       (1, 300, 3, 0), (640, 128, 8, 1), (77, 250, 5, 0)]
+
+
+def mix_problems(seed):
+    rng = np.random.default_rng(seed)
+    return [dict(nx=nx, ny=ny, s=sd, variant=v, b=rng.uniform(-1, 1, (ny, nx)),
+                 tol=1e-8 if k % 2 else 1e-6) for k, (nx, ny, sd, v) in enumerate(MIX)]
+
+
+def make(d, x):
+    return cg.make_problem(d["b"], x, d["nx"], d["ny"], tol=d["tol"], maxit=20000,
+                           variant=d["variant"], precond=d["s"])
+
+
+def test_batch_with_preconditioned_solves_matches_alone(ctx):
+    """Preconditioned solves of both variants and several s side by side with
+    unpreconditioned ones in one batch: each result is bitwise its standalone
+    solve, and the preconditioned ones bitwise the oracle's preconditioned CG
+    in the library's order."""
+    probs = mix_problems(31)
+    xs = [np.zeros_like(d["b"]) for d in probs]
+    say("batch with preconditioned solves:", len(probs))
+    rc, res = ctx.cg_solve_batch([make(d, x) for d, x in zip(probs, xs)])
+    assert rc == cg.CG_OK
+    for d, x, r in zip(probs, xs, res):
+        xa = np.zeros_like(d["b"])
+        rca, ra = ctx.cg_solve(make(d, xa))
+        say("  %dx%d s=%d v%d: batch %d alone %d iterations" % (d["nx"], d["ny"], d["s"],
+                                                                d["variant"], r.iterations,
+                                                                ra.iterations))
+        assert r.status == rca == cg.CG_OK and r.iterations == ra.iterations
+        np.testing.assert_array_equal(x, xa)
+        assert r.rel_res_true == ra.rel_res_true
+        if d["s"] and d["nx"] * d["ny"] <= 300 * 300:
+            o, orho = tile_order(ctx, d["nx"], d["ny"], d["s"], d["variant"])
+            xo, ro = oracle.pcg(d["b"], d["nx"], d["ny"], d["s"], tol=d["tol"], maxit=20000,
+                                mode=MODE_CANONICAL, order=o, order_rho=orho,
+                                variant=d["variant"])
+            assert ro.iterations == r.iterations
+            np.testing.assert_array_equal(x, xo)
+
+
+def test_served_preconditioned_solves_match_alone(ctx):
+    """The same mix served (requests arriving while others run): each result
+    is bitwise its standalone solve; maxit and a zero right-hand side keep
+    their outcomes."""
+    import time
+    probs = mix_problems(32)
+    probs.append(dict(nx=90, ny=70, s=4, variant=1, b=np.zeros((70, 90)), tol=1e-8))
+    xs = [np.zeros_like(d["b"]) for d in probs]
+    tickets = []
+    say("serving preconditioned requests:", len(probs))
+    for k, (d, x) in enumerate(zip(probs, xs)):
+        tickets.append(ctx.cg_submit(make(d, x)))
+        if k % 4 == 3:
+            time.sleep(0.002)
+    xm = np.zeros_like(probs[0]["b"])
+    tm = ctx.cg_submit(cg.make_problem(probs[0]["b"], xm, probs[0]["nx"], probs[0]["ny"],
+                                       tol=1e-14, maxit=5, precond=4, variant=1))
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) + 1 and time.time() < deadline:
+        for t in tickets + [tm]:
+            if t not in out:
+                rc, r = ctx.cg_poll(t)
+                if rc != cg.CG_PENDING:
+                    out[t] = (rc, cg.cg_result.from_buffer_copy(r))
+        time.sleep(0.001)
+    assert len(out) == len(tickets) + 1
+    for d, x, t in zip(probs, xs, tickets):
+        rc, r = out[t]
+        xa = np.zeros_like(d["b"])
+        rca, ra = ctx.cg_solve(make(d, xa))
+        assert rc == rca == cg.CG_OK and r.iterations == ra.iterations
+        np.testing.assert_array_equal(x, xa)
+    assert out[tickets[-1]][1].iterations == 0 and not xs[-1].any()
+    rc, r = out[tm]
+    assert rc == cg.CG_NOT_CONVERGED and r.iterations == 5
