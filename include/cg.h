@@ -228,6 +228,26 @@ int cg_poll(cg_ctx* ctx, uint64_t ticket, cg_result* res);
 
 const char* cg_status_str(int code);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): n small
+ * solves, each bitwise the one cg_solve and cg_solve_batch give, with no
+ * context and no device or pinned-host allocation.  The solves run on the
+ * on-chip solver (one work-group per solve, cg_plan_info.path 2) directly on
+ * the caller's device vectors (mem must be CG_MEM_DEVICE; b, x0 and x hold
+ * nx*ny doubles, row-major, unpadded), on the current HIP device, in `stream`
+ * (hipStream_t, NULL = the null stream); the call returns when they are done.
+ * Every problem must be FP64, 2D, unpreconditioned, constant-coefficient and
+ * fit the on-chip solver: (nx + 1) * ceil(ny / 20) <= 512 (e.g. up to
+ * 100 x 100, or 511 x 20); 1 <= n <= 64.  Anything else is CG_E_INVALID
+ * before any device work.  The library keeps the solves' descriptors and
+ * scalar states in a fixed 64 KiB device array of its own (one per device,
+ * held until the process ends), rewritten whole by every call: calls are
+ * serialised per device within the process, and calls from several processes
+ * each use their own copy.  Returns the worst status, as cg_solve_batch;
+ * results[i] holds each outcome (device_seconds: the call's wall time). */
+int cg_solve_batch_small_noalloc(const cg_problem* probs, int32_t n, void* stream,
+                                 cg_result* results);
+
 /* ---- building blocks, exposed for verification and measurement ---------- */
 
 /* y = A u on the nx-by-ny grid, matrix-free (Section II-B stencil). */

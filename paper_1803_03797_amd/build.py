@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["cg_kernels.hip", "cg_fixed.hip", "cg_runtime.cpp", "cg_serve.cpp", "cg_abi.cpp"]
+SOURCES = ["cg_kernels.hip", "cg_fixed.hip", "cg_noalloc.hip", "cg_runtime.cpp", "cg_serve.cpp",
+           "cg_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

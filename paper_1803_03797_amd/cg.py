@@ -62,7 +62,7 @@ class cg_kstat(C.Structure):
 SYMBOLS = ["cg_create", "cg_destroy", "cg_solve", "cg_solve_batch", "cg_submit", "cg_poll",
            "cg_status_str", "cg_apply", "cg_dot", "cg_plan", "cg_footprint", "cg_validate",
            "cg_tune", "cg_pin_tile", "cg_set_profiling", "cg_kernel_stats", "cg_version",
-           "cg_stream_probe", "cg_mul_probe"]
+           "cg_stream_probe", "cg_mul_probe", "cg_solve_batch_small_noalloc"]
 
 _lib = None
 
@@ -103,6 +103,8 @@ def load():
         "cg_set_profiling": (C.c_int, [P, I]),
         "cg_kernel_stats": (C.c_int, [P, C.POINTER(cg_kstat), I, C.POINTER(I), I]),
         "cg_version": (C.c_char_p, []),
+        "cg_solve_batch_small_noalloc": (C.c_int, [C.POINTER(cg_problem), I, P,
+                                                   C.POINTER(cg_result)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -114,6 +116,18 @@ def load():
 
 def cg_status_str(code):
     return load().cg_status_str(code).decode()
+
+
+def cg_solve_batch_small_noalloc(probs, stream=None):
+    """Small solves with no device allocation (no context; the current HIP
+    device; `stream` a hipStream_t handle or None).  Returns (worst status,
+    results)."""
+    n = len(probs)
+    arr = (cg_problem * n)(*probs)
+    res = (cg_result * n)()
+    rc = _check("cg_solve_batch_small_noalloc",
+                load().cg_solve_batch_small_noalloc(arr, n, stream, res))
+    return rc, list(res)
 
 
 class CGError(RuntimeError):

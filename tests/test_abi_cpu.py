@@ -142,3 +142,23 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(name, "size")] == C.sizeof(py), name
         for f in py._fields_:
             assert got[(name, f[0])] == getattr(py, f[0]).offset, (name, f[0])
+
+
+def test_noalloc_rejects_before_any_device_work():
+    """cg_solve_batch_small_noalloc validates every problem first: host memory,
+    grids too large for the on-chip solver, other precisions, n outside 1..64."""
+    lib = cg.load()
+    ok = _prob(mem=cg.CG_MEM_DEVICE, nx=20, ny=30)
+    bad = [_prob(nx=20, ny=30), _prob(mem=cg.CG_MEM_DEVICE, nx=200, ny=200),
+           _prob(mem=cg.CG_MEM_DEVICE, nx=20, ny=30, precision=1),
+           _prob(mem=cg.CG_MEM_DEVICE, nx=20, ny=30, precond=2),
+           _prob(mem=cg.CG_MEM_DEVICE, nx=20, ny=30, nz=4),
+           _prob(mem=cg.CG_MEM_DEVICE, nx=20, ny=30, kx=3, ky=4),
+           _prob(mem=cg.CG_MEM_DEVICE, nx=512, ny=20)]
+    res = (cg.cg_result * 65)()
+    for p in bad:
+        arr = (cg.cg_problem * 2)(ok, p)
+        assert lib.cg_solve_batch_small_noalloc(arr, 2, None, res) == cg.CG_E_INVALID
+    arr = (cg.cg_problem * 65)(*([ok] * 65))
+    assert lib.cg_solve_batch_small_noalloc(arr, 65, None, res) == cg.CG_E_INVALID
+    assert lib.cg_solve_batch_small_noalloc(arr, 0, None, res) == cg.CG_E_INVALID
