@@ -55,6 +55,19 @@
 #include <omp.h>
 #endif
 
+/* Planted mistakes, for the tests that show the pins catch them (a test
+ * builds a copy of this file with one of them; every real build has
+ * ORACLE_MUTANT 0).  Refinement's inner solve:
+ *   1: the inner vectors kept in binary64;
+ *   2: the inner dot products summed in binary32;
+ *   3: alpha and beta of the inner solve left in binary64.
+ * Residual replacement of the pipelined variant:
+ *   4: w = A r not recomputed;
+ *   5: z = A q not recomputed. */
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
 /* All-core timing build.  Built with -fopenmp (the benchmark's CPU baseline
  * only; the tests use the plain build, in which the pragmas below are inert),
  * the matrix-vector product and the vector updates split their rows over the
@@ -373,6 +386,8 @@ double oracle_dot(int32_t nx, int32_t ny, int32_t mode, const oracle_order* o,
 typedef struct {
   int32_t nx, ny, mode;
   const oracle_order* ord;
+  int32_t rr_period; /* pipelined: residual replacement every rr_period
+                        iterations (0: never) */
 } ctx_t;
 
 static double dot(const ctx_t* c, const double* a, const double* b) {
@@ -556,6 +571,22 @@ static int cg_pipelined(const csr_t* A, const ctx_t* c, const double* b, const d
     axpy(c, n, -alpha, q, r);
     axpy(c, n, -alpha, z, w);
     ++k;
+    if (c->rr_period > 0 && k % c->rr_period == 0) {
+      /* Residual replacement (the attainable-accuracy remedy for pipelined
+       * CG of Cools, Yetkin, Agullo, Giraud and Vanroose): the recurrence
+       * vectors are recomputed from their definitions, q = A p, z = A q,
+       * r = b - A x, w = A r; gamma and delta are then formed from them at
+       * the loop head as always, and the scalar recurrences continue. */
+      spmv(A, p, q);
+#if ORACLE_MUTANT != 5
+      spmv(A, q, z);
+#endif
+      spmv(A, x, nv);
+      for (int64_t i = 0; i < n; ++i) r[i] = b[i] - nv[i];
+#if ORACLE_MUTANT != 4
+      spmv(A, r, w);
+#endif
+    }
   }
 fin:
   finish(A, c, b, x, bb, gamma, res);
@@ -581,9 +612,28 @@ static int order_valid(const oracle_order* o, int32_t nx, int32_t ny) {
 /* Solve A x = b.  variant: 0 classic, 1 pipelined.  mode: 0 sequential,
  * 1 canonical (then ord must describe the order).  x0 may be NULL.
  * Returns the status (also in res). */
+static int cg_any(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
+                  int32_t ny, const double* b, const double* x0, double* x, double tol,
+                  int32_t maxit, int32_t rr_period, oracle_result* res, oracle_history* hist);
+
 int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
               int32_t ny, const double* b, const double* x0, double* x, double tol,
               int32_t maxit, oracle_result* res, oracle_history* hist) {
+  return cg_any(variant, mode, ord, nx, ny, b, x0, x, tol, maxit, 0, res, hist);
+}
+
+/* oracle_cg with residual replacement every rr_period iterations of the
+ * pipelined variant (rr_period >= 1; classic CG ignores it). */
+int oracle_cg_rr(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
+                 int32_t ny, const double* b, const double* x0, double* x, double tol,
+                 int32_t maxit, int32_t rr_period, oracle_result* res) {
+  if (rr_period < 1) return OR_E_INVALID;
+  return cg_any(variant, mode, ord, nx, ny, b, x0, x, tol, maxit, rr_period, res, NULL);
+}
+
+static int cg_any(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
+                  int32_t ny, const double* b, const double* x0, double* x, double tol,
+                  int32_t maxit, int32_t rr_period, oracle_result* res, oracle_history* hist) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0)
     return OR_E_INVALID;
   if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
@@ -591,7 +641,7 @@ int oracle_cg(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx
   csr_t A;
   int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
   if (rc) return rc;
-  ctx_t c = {nx, ny, mode, ord};
+  ctx_t c = {nx, ny, mode, ord, rr_period};
   memset(res, 0, sizeof(*res));
   const double t0 = wall_now();
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, hist)
@@ -765,23 +815,31 @@ int oracle_spmv_vc(int32_t nx, int32_t ny, const double* kx, const double* ky, i
 }
 
 /* Algorithms 1 and 2 on the variable-coefficient operator (the same loops as
- * oracle_cg). */
-int oracle_cg_vc(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny,
-                 const double* kx, const double* ky, const double* b, const double* x0,
-                 double* x, double tol, int32_t maxit, oracle_result* res) {
+ * oracle_cg); rr_period > 0: residual replacement every rr_period iterations
+ * of the pipelined variant, as in oracle_cg_rr. */
+int oracle_cg_vc_rr(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx,
+                    int32_t ny, const double* kx, const double* ky, const double* b,
+                    const double* x0, double* x, double tol, int32_t maxit, int32_t rr_period,
+                    oracle_result* res) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
-      (variant != VARIANT_CLASSIC && variant != VARIANT_PIPELINED))
+      (variant != VARIANT_CLASSIC && variant != VARIANT_PIPELINED) || rr_period < 0)
     return OR_E_INVALID;
   if (mode == MODE_CANONICAL && !order_valid(ord, nx, ny)) return OR_E_INVALID;
   csr_t A;
   int rc = csr_vc_build(&A, nx, ny, kx, ky, mode == MODE_CANONICAL ? 1 : 0);
   if (rc) return rc;
-  ctx_t c = {nx, ny, mode, ord};
+  ctx_t c = {nx, ny, mode, ord, rr_period};
   memset(res, 0, sizeof(*res));
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
   csr_free(&A);
   return rc;
+}
+
+int oracle_cg_vc(int32_t variant, int32_t mode, const oracle_order* ord, int32_t nx, int32_t ny,
+                 const double* kx, const double* ky, const double* b, const double* x0,
+                 double* x, double tol, int32_t maxit, oracle_result* res) {
+  return oracle_cg_vc_rr(variant, mode, ord, nx, ny, kx, ky, b, x0, x, tol, maxit, 0, res);
 }
 
 /* ------------------------------------------ Chebyshev-preconditioned CG -- */
@@ -1041,15 +1099,6 @@ done:
 
 /* ---------------------------------------------------------- refinement -- */
 
-/* Planted mistakes, for the tests that show the refinement pins catch them
- * (a test builds a copy of this file with one of them; every real build has
- * ORACLE_MUTANT 0):
- *   1: the inner vectors kept in binary64;
- *   2: the inner dot products summed in binary32;
- *   3: alpha and beta of the inner solve left in binary64. */
-#ifndef ORACLE_MUTANT
-#define ORACLE_MUTANT 0
-#endif
 #if ORACLE_MUTANT == 1
 typedef double inner_t;
 #define spmv_inner spmv
@@ -1081,7 +1130,9 @@ static double dot_f32_in_f64(int64_t n, const inner_t* a, const inner_t* b) {
  *          s = ||r||; rho = fp32(r * (1/s));
  *   inner: classic CG on A d = rho with FP32 vectors and FP32 stencil/axpy
  *          arithmetic, FP64 dot products, scalars alpha/beta computed in FP64
- *          and rounded to FP32 once; stop when (ri,ri) <= inner_tol^2 (rho,rho);
+ *          and rounded to FP32 once; stop when (ri,ri) <= e^2 (rho,rho) with
+ *          e = max(inner_tol, (tol/2) ||b|| / s) (adaptive: no further than
+ *          the outer tolerance needs);
  *          a breakdown of the inner solve ends it early;
  *   update: x += s * fp64(d).
  * maxit caps the total number of inner iterations; an outer step whose inner
@@ -1127,7 +1178,11 @@ int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, dou
       p[k] = ri[k];
     }
     double gamma = dot_f32_in_f64(n, ri, ri);
-    const double thr_in = (inner_tol * inner_tol) * gamma;
+    /* the inner solve needs to reduce its residual by no more than what is
+     * left to the outer tolerance, (tol ||b||) / ||r||, with a margin of two
+     * for the FP32 arithmetic: the last outer step stops early */
+    const double eff = fmax(inner_tol, (0.5 * tol) * (sqrt(bb) / sc));
+    const double thr_in = (eff * eff) * gamma;
     int32_t kin = 0;
     while (!(gamma <= thr_in) && total < maxit) {
       spmv_inner(&A, p, s);

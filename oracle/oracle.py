@@ -112,6 +112,13 @@ def _load():
     lib.oracle_csr_vc_assemble.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, P, P, P]
     lib.oracle_spmv_vc.restype = C.c_int
     lib.oracle_spmv_vc.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int32, P, P]
+    lib.oracle_cg_rr.restype = C.c_int
+    lib.oracle_cg_rr.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
+                                 P, P, P, C.c_double, C.c_int32, C.c_int32, C.POINTER(_Result)]
+    lib.oracle_cg_vc_rr.restype = C.c_int
+    lib.oracle_cg_vc_rr.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32,
+                                    C.c_int32, P, P, P, P, P, C.c_double, C.c_int32, C.c_int32,
+                                    C.POINTER(_Result)]
     lib.oracle_cg_vc.restype = C.c_int
     lib.oracle_cg_vc.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
                                  P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(_Result)]
@@ -218,17 +225,17 @@ def spmv_vc(u, nx, ny, kx, ky, order=0):
 
 
 def cg_vc(b, nx, ny, kx, ky, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
-          mode=MODE_SEQUENTIAL, order=None):
+          mode=MODE_SEQUENTIAL, order=None, rr_period=0):
     """Solve the variable-coefficient 5-point system (face conductivities kx of
-    shape (ny, nx + 1) and ky of shape (ny + 1, nx))."""
+    shape (ny, nx + 1) and ky of shape (ny + 1, nx)); rr_period as in cg()."""
     kx, ky = _faces(kx, ky, nx, ny)
     b = _vec(b, nx, ny)
     x0a = _vec(x0, nx, ny) if x0 is not None else None
     x = np.zeros_like(b)
     res = _Result()
     o = C.byref(order) if order is not None else None
-    rc = _load().oracle_cg_vc(variant, mode, o, nx, ny, _ptr(kx), _ptr(ky), _ptr(b), _ptr(x0a),
-                              _ptr(x), tol, maxit, C.byref(res))
+    rc = _load().oracle_cg_vc_rr(variant, mode, o, nx, ny, _ptr(kx), _ptr(ky), _ptr(b),
+                                 _ptr(x0a), _ptr(x), tol, maxit, rr_period, C.byref(res))
     if rc < 0:
         raise ValueError("oracle_cg_vc rejected the call: %d" % rc)
     return x, Result(status=res.status, iterations=res.iterations,
@@ -258,9 +265,26 @@ class Result(dict):
 
 
 def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
-       mode=MODE_SEQUENTIAL, order=None, history=0):
+       mode=MODE_SEQUENTIAL, order=None, history=0, rr_period=0):
     """Solve A x = b.  Returns (x, Result); with history=m also returns a dict of
-    the first m records (gamma, r, p, x after 0, 1, ... updates)."""
+    the first m records (gamma, r, p, x after 0, 1, ... updates).  rr_period
+    > 0: the pipelined variant replaces its residuals every rr_period
+    iterations (no history then)."""
+    if rr_period:
+        if history:
+            raise ValueError("no history with residual replacement")
+        b = _vec(b, nx, ny)
+        x0a = _vec(x0, nx, ny) if x0 is not None else None
+        x = np.zeros_like(b)
+        res = _Result()
+        o = C.byref(order) if order is not None else None
+        rc = _load().oracle_cg_rr(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol,
+                                  maxit, rr_period, C.byref(res))
+        if rc < 0:
+            raise ValueError("oracle_cg_rr rejected the call: %d" % rc)
+        return x, Result(status=res.status, iterations=res.iterations,
+                         outer_iterations=res.outer_iterations,
+                         rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
     b = _vec(b, nx, ny)
     x0a = _vec(x0, nx, ny) if x0 is not None else None
     x = np.zeros_like(b)

@@ -501,3 +501,16 @@ def test_refinement_pins_catch_planted_mistakes(tmp_path, mutant):
                                 outer_iterations=res.outer_iterations)
 
     assert not _first_inner_step_pin(refine)
+
+
+def test_refinement_last_inner_solve_stops_at_what_tol_needs():
+    """tol 1e-6, inner tol 1e-4 from x0 = 0: the first inner solve takes the
+    residual to about 1e-4, the second only needs a further factor of about
+    tol / 1e-4 / 2 = 5e-3 (not 1e-4): two outer steps end with a true
+    residual below tol but far above what a second 1e-4 step gives (1e-8)."""
+    nx, ny = 40, 30
+    b = np.random.default_rng(15).standard_normal((ny, nx))
+    x, r = oracle.refine(b, nx, ny, tol=1e-6, inner_tol=1e-4)
+    rt = np.linalg.norm(b.ravel() - sparse_A(nx, ny) @ x.ravel()) / np.linalg.norm(b)
+    assert r.status == oracle.OR_OK and r.outer_iterations == 2
+    assert 1e-8 < rt <= 1e-6
