@@ -97,7 +97,10 @@ typedef struct {
   int32_t maxit;           /* >= 1; FP32-refined: cap on the total inner iterations   */
   cg_variant variant;      /* Algorithm 1 or Algorithm 2                              */
   cg_precision precision;  /* FP64, FP32 inner CG inside FP64 refinement, or fixed    */
-  double inner_tol;        /* refined only: inner stop, relative; 0 = 1e-4            */
+  double inner_tol;        /* refined only: the inner solve stops at the relative
+                              residual max(inner_tol, tol ||b|| / (2 ||b - A x||)),
+                              i.e. no further than the outer tolerance needs;
+                              0 = 1e-4                                            */
   int32_t precond;         /* 0: none; s = 1..8: FP64 CG preconditioned by
                               M^-1 = p_s(A), s steps of Chebyshev semi-iteration on
                               A y = r from y = 0 over [lmax / (2 s^2), lmax], lmax =
@@ -116,7 +119,14 @@ typedef struct {
                               so b, x0 and x hold nx * ny * nz values; FP64, either
                               variant, precond 0, cg_solve only (batches and serving
                               reject it)                                            */
-  int32_t pad_;
+  int32_t rr_period;       /* 0: none.  k > 0 (even): residual replacement in the
+                              pipelined variant (Algorithm 2) every k iterations:
+                              q = A p, z = A q, r = b - A x and w = A r recomputed
+                              from their definitions, after which the iteration
+                              continues (the remedy of Cools et al. for the
+                              accuracy Algorithm 2's recurrences lose); FP64, 2D
+                              (either operator), precond 0, cg_solve only; the
+                              solve runs on the multi-work-group passes        */
   const double* kx;        /* NULL (with ky NULL): the constant-coefficient operators
                               above.  Else the variable-coefficient 5-point operator,
                               the other structured-grid case Section I names beside

@@ -31,7 +31,7 @@ class cg_problem(C.Structure):
                 ("b", C.c_void_p), ("x0", C.c_void_p), ("x", C.c_void_p),
                 ("tol", C.c_double), ("maxit", C.c_int32), ("variant", C.c_int32),
                 ("precision", C.c_int32), ("inner_tol", C.c_double),
-                ("precond", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
+                ("precond", C.c_int32), ("nz", C.c_int32), ("rr_period", C.c_int32),
                 ("kx", C.c_void_p), ("ky", C.c_void_p)]
 
 
@@ -164,11 +164,12 @@ def _numel(v):
 
 def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
                  precision=CG_PREC_FP64, x0=None, inner_tol=0.0, precond=0, nz=0, kx=None,
-                 ky=None):
+                 ky=None, rr_period=0):
     """nz > 1: the 3D 7-point problem on nx x ny x nz (vectors of nx*ny*nz).
     kx, ky: face conductivities of the variable-coefficient operator, ny x
     (nx+1) and (ny+1) x nx, in the memory space of b (the caller keeps them
-    alive until the solve returns)."""
+    alive until the solve returns).  rr_period: residual replacement every
+    rr_period iterations of the pipelined variant (0: none)."""
     pb, mb = _ptr_mem(b)
     px, mx = _ptr_mem(x)
     p0, m0 = _ptr_mem(x0)
@@ -188,7 +189,8 @@ def make_problem(b, x, nx, ny, tol=1e-8, maxit=2000, variant=CG_VARIANT_CLASSIC,
         if v is not None and _numel(v) != n:
             raise ValueError("vector size does not match the %dx%dx%d grid" % (nx, ny, max(nz, 1)))
     p = cg_problem(nx, ny, mb, pb, p0, px, float(tol), int(maxit), int(variant),
-                   int(precision), float(inner_tol), int(precond), int(nz), 0, pkx, pky)
+                   int(precision), float(inner_tol), int(precond), int(nz), int(rr_period), pkx,
+                   pky)
     return p
 
 
@@ -280,12 +282,12 @@ class Context:
         return out.value
 
     def cg_plan(self, nx, ny, variant=CG_VARIANT_CLASSIC, precision=CG_PREC_FP64, precond=0,
-                nz=0, vc=False):
+                nz=0, vc=False, rr_period=0):
         """vc: plan the variable-coefficient operator (the coefficients are not
         read: a placeholder stands for them)."""
         k = C.addressof(_VC_PLACEHOLDER) if vc else None
         p = cg_problem(nx, ny, CG_MEM_DEVICE, None, None, None, 1e-8, 1, variant, precision, 0.0,
-                       precond, nz, 0, k, k)
+                       precond, nz, rr_period, k, k)
         info = cg_plan_info()
         _check("cg_plan", self.lib.cg_plan(self.h, C.byref(p), C.byref(info)))
         return info

@@ -485,8 +485,11 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     const double gamma = sum[0];
     double be = 0.0;
     if (s.kin == 0) {
+      // inner stop: relative residual e = max(inner_tol, (tol/2) ||b|| / s),
+      // no further than the outer tolerance needs (s = ||b - A x||)
+      const double e = fmax(s.inner_tol, (0.5 * s.tol) * (sqrt(s.bb) / s.scale));
       s.gamma0 = gamma;
-      s.thr_in = (s.inner_tol * s.inner_tol) * gamma;
+      s.thr_in = (e * e) * gamma;
       sc.first = 1;
     } else {
       be = gamma / s.gamma;
@@ -839,16 +842,35 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #define CG1_PREFETCH 1
 #endif
 
+#ifndef WALK_PREFETCH
+#define WALK_PREFETCH 1
+#endif
+#ifndef EDGE_MASKED
+#define EDGE_MASKED 0
+#endif
+
 // Loaders for a halo vector that is stored as is.
 template <typename T, int CPL, int OP, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
   const int c = s.c;
-  walk<T, CPL, 1, OP>(
+#if EDGE_MASKED
+  walk<T, CPL, WALK_PREFETCH, OP>(
+      g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
+      [](const Row<T, CPL>& r) { return r; },
+      [=](size_t off) {
+        T v = T(0);
+        if (ea.emask) v = V[off + ea.off];
+        return v;
+      },
+      [=](T v) { return v; }, point, comp);
+#else
+  walk<T, CPL, WALK_PREFETCH, OP>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
       [=](T v) { return ea.emask ? v : T(0); }, point, comp);
+#endif
 }
 
 struct Empty {};
@@ -1176,8 +1198,17 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
       },
       [=](size_t off) {
         RawE v;
+#if EDGE_MASKED
+        v.r = T(0);
+        v.po = T(0);
+        if (ea.emask) {
+          v.r = Rv[off + ea.off];
+          v.po = Po[off + ea.off];
+        }
+#else
         v.r = Rv[off + ea.off];
         v.po = Po[off + ea.off];
+#endif
         return v;
       },
       [=](const RawE& v) { return ea.emask ? (first ? v.r : fma(be, v.po, v.r)) : T(0); },

@@ -74,6 +74,12 @@ int validate(const cg_problem* p) {
   if (p->precond > 0 && p->precision != CG_PREC_FP64) return CG_E_INVALID;
   if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
     return CG_E_INVALID;
+  // residual replacement: the pipelined FP64 2D solve, an even period (x is
+  // brought up to date at even iterations)
+  if (p->rr_period < 0 || (p->rr_period & 1)) return CG_E_INVALID;
+  if (p->rr_period > 0 && (p->variant != CG_VARIANT_PIPELINED || p->precision != CG_PREC_FP64 ||
+                           p->precond != 0 || p->nz > 1))
+    return CG_E_INVALID;
   return CG_OK;
 }
 
@@ -133,7 +139,7 @@ int Ctx::unpinned_rows(const cg_problem* p, int fp32g) const {
 
 bool Ctx::use_wg(const cg_problem* p) const {
   return p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 && !p->kx &&
-         (int64_t)p->nx * p->ny <= wg_max_dof;
+         p->rr_period == 0 && (int64_t)p->nx * p->ny <= wg_max_dof;
 }
 
 // threads of the register-resident solver: rows of nx + 1 (one idle thread
@@ -144,7 +150,7 @@ static int64_t rr_threads_needed(int nx, int ny) {
 
 bool Ctx::use_rr(const cg_problem* p) const {
   return rr_enabled && p->precision == CG_PREC_FP64 && p->precond == 0 && p->nz <= 1 &&
-         !p->kx && rr_threads_needed(p->nx, p->ny) <= kRrThreads;
+         !p->kx && p->rr_period == 0 && rr_threads_needed(p->nx, p->ny) <= kRrThreads;
 }
 
 Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
@@ -157,6 +163,7 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   pl.rr = allow_rr && use_rr(p);
   pl.fixed = p->precision == CG_PREC_FIXED;
   pl.precond = p->precond;
+  pl.rr_period = p->rr_period;
   pl.vc = p->kx != nullptr;
   if (pl.fixed) {
     // one unknown per thread up to 1024 unknowns, then 1024 threads
@@ -232,7 +239,8 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
     // one item per resident work-group (long items amortise the s - 1 halo
     // rows each item recomputes; at least 16 rows)
     const int ngx = (pl.g.pitch + kChebGroupCols - 1) / kChebGroupCols;
-    const int slots = std::max(1, cheb_max_blocks_per_cu(pl.precond) * num_cu);
+    const int slots =
+        std::max(1, cheb_max_blocks_per_cu(pl.precond) * num_cu / std::max(1, cheb_item_div));
     const int nty = std::max(1, slots / ngx);
     int crows = (p->ny + nty - 1) / nty;
     crows = std::max(crows, std::min(p->ny, 16));
@@ -255,6 +263,12 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
     pl.il = n64 + (pl.vc ? 4 : 0);
     pl.g.pitch = pl.width * pl.il;
     pl.g.kcs = pl.width;
+    vec_bytes = round_up((size_t)pl.il * elems * 8, Arena::kAlign);
+  } else if (interleave && classic_interleave && !pl.wg && !pl.refined && !pl.fixed &&
+             p->variant == CG_VARIANT_CLASSIC && !pl.precond && !pl.vc && p->nz <= 1) {
+    // classic FP64 with interleaved rows r, p, p', x, b
+    pl.il = 5;
+    pl.g.pitch = pl.width * pl.il;
     vec_bytes = round_up((size_t)pl.il * elems * 8, Arena::kAlign);
   }
   pl.footprint = vec_bytes + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
@@ -356,8 +370,9 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool chec
 
 bool carve(Ctx& c, Work& w) {
   // an interleaved block holds exactly the vectors carved from it below
-  if (w.pl.il > 1 && (w.pl.variant != CG_VARIANT_PIPELINED ||
-                      w.pl.il != (w.pl.precond ? 10 : 8) + (w.pl.vc ? 4 : 0)))
+  if (w.pl.il > 1 && w.pl.variant == CG_VARIANT_CLASSIC
+          ? (w.pl.il != 5 || w.pl.precond || w.pl.vc || w.pl.refined)
+          : w.pl.il > 1 && w.pl.il != (w.pl.precond ? 10 : 8) + (w.pl.vc ? 4 : 0))
     return false;
   w.mem = (char*)c.arena.alloc(w.pl.footprint);
   if (!w.mem) return false;
@@ -374,6 +389,19 @@ bool carve(Ctx& c, Work& w) {
     double* blk = (double*)take(round_up((size_t)pl.il * pl.width * pl.g.ny * 8, Arena::kAlign));
     int k = 0;
     auto vec = [&]() { return blk + (size_t)(k++) * pl.width; };
+    if (pl.variant == CG_VARIANT_CLASSIC) {
+      // pass 1 streams r, p, p' (adjacent), pass 2 p, r and x
+      w.r = vec();
+      w.pc[0] = vec();
+      w.pc[1] = vec();
+      w.x = vec();
+      w.b = vec();
+      w.part[0] = (double*)take(pl.part);
+      w.part[1] = (double*)take(pl.part);
+      w.S[0] = (State*)take(round_up(sizeof(State), 256));
+      w.S[1] = (State*)take(round_up(sizeof(State), 256));
+      return true;
+    }
     w.b = vec();
     w.x = vec();
     w.r = vec();
@@ -502,6 +530,23 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
       a.w_in = w.w[i & 1];
       a.w_out = w.w[(i + 1) & 1];
     });
+    // residual replacement after iteration i + 1 (even: x is current): q = A p
+    // and z = A q (plain stencil passes, no state), then r = b - A x with its
+    // sums and w = A r with (r,r), (w,r), the sums the next iteration takes
+    if (e == hipSuccess && w.pl.rr_period > 0 && (i + 1) % w.pl.rr_period == 0) {
+      PassArgs a = base_args(w);
+      a.u = w.p;
+      a.y = w.q;
+      e = c.pass(K_APPLY, w.pl.fp32g, a, w.pl.grid, w.check);
+      if (e == hipSuccess) {
+        a.u = w.q;
+        a.y = w.z;
+        e = c.pass(K_APPLY, w.pl.fp32g, a, w.pl.grid, w.check);
+      }
+      if (e == hipSuccess) e = issue(c, w, K_INIT_R, [](PassArgs&) {});
+      if (e == hipSuccess)
+        e = issue(c, w, K_INIT_W, [&](PassArgs& a2) { a2.w_out = w.w[(i + 1) & 1]; });
+    }
   } else {
     // preconditioned: z = M^-1 r first, and the direction is p = z + beta p
     e = hipSuccess;
@@ -559,9 +604,13 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     return CG_OK;
   }
   const Plan& pl = w.pl;
+  // with residual replacement the chunk's passes depend on where in the
+  // replacement period it starts
+  const int rph = pl.rr_period > 0 ? w.i % pl.rr_period : 0;
   GraphKey key{w.mem,
                {pl.g.nx, pl.g.ny, pl.g.rows, pl.grid, pl.variant, pl.refined, iters, w.m & 1,
-                w.i & 1, pl.precond, pl.fp32g, pl.g.plane, pl.vc, pl.cheb_rows}};
+                w.i & 1, pl.precond, pl.fp32g, pl.g.plane, pl.vc, pl.cheb_rows, pl.rr_period,
+                rph}};
   auto it = c.graphs.find(key);
   if (it == c.graphs.end()) {
     hipGraph_t g;
@@ -591,6 +640,8 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
                       ? (w.pl.precond ? 2 : 1)
                   : w.pl.precond ? 3
                                  : 2);
+  // two state passes (K_INIT_R, K_INIT_W) per replacement in the chunk
+  if (pl.rr_period > 0) w.m += 2 * ((w.i + iters) / pl.rr_period - w.i / pl.rr_period);
   w.i += iters;
   return CG_OK;
 }
@@ -1217,6 +1268,8 @@ int Ctx::init(const cg_config* cfg) {
   if (const char* e = getenv("CG_RR")) rr_enabled = atoi(e) != 0;
   if (const char* e = getenv("CG_STEP_CHUNK")) step_chunk = std::max(1, atoi(e));
   if (const char* e = getenv("CG_SERVE_CHUNK")) serve_chunk = std::max(1, atoi(e));
+  if (const char* e = getenv("CG_CHEB_ITEM_DIV")) cheb_item_div = std::max(1, atoi(e));
+  if (const char* e = getenv("CG_CLASSIC_IL")) classic_interleave = atoi(e) != 0;
   load_tune_cache();
   return CG_OK;
 }

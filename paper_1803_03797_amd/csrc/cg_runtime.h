@@ -29,6 +29,7 @@ struct Plan {
   bool vc = false;     // variable-coefficient operator (four coefficient arrays)
   int width = 0;       // padded row length of one vector, in elements
   int il = 1;          // FP64 vectors with interleaved rows (g.pitch = il * width)
+  int rr_period = 0;   // pipelined: residual replacement every rr_period iterations
   bool on_side() const { return rr || fixed; }  // batch: whole solve beside the steps
   cgk::Geo g{};
   int grid = 8;      // work-groups per pass
@@ -46,11 +47,11 @@ struct Pin {
 // iteration and the buffer parities.
 struct GraphKey {
   const void* mem;
-  int v[14];  // nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond,
-              // fp32g, plane, vc, cheb_rows
+  int v[16];  // nx, ny, rows, grid, variant, refined, iters, mpar, ipar, precond,
+              // fp32g, plane, vc, cheb_rows, rr_period, iteration within the period
   bool operator<(const GraphKey& o) const {
     if (mem != o.mem) return mem < o.mem;
-    for (int i = 0; i < 14; ++i)
+    for (int i = 0; i < 16; ++i)
       if (v[i] != o.v[i]) return v[i] < o.v[i];
     return false;
   }
@@ -123,6 +124,8 @@ struct Ctx {
   bool rr_enabled = true;      // register-resident solver for grids that fit it
   int step_chunk = 32;         // batch: steps between harvests
   int serve_chunk = 8;         // serving: steps between admissions
+  int cheb_item_div = 1;       // Chebyshev items per pass: resident work-groups / this
+  bool classic_interleave = false;  // classic FP64 tile passes: interleaved rows
   int step_chunk_for(bool serving) const { return serving ? serve_chunk : step_chunk; }
   size_t engine_bytes() const {  // control block of the multi-solve engine
     return (size_t)max_slots * (sizeof(cgk::Slot) + 2 * 256 * sizeof(cgk::Item) +

@@ -36,11 +36,12 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(nx=10, ny=7, mem=cg.CG_MEM_HOST, b=1, x0=None, x=2, tol=1e-8, maxit=10,
-             variant=0, precision=0, inner_tol=0.0, precond=0, nz=0, kx=None, ky=None)
+             variant=0, precision=0, inner_tol=0.0, precond=0, nz=0, kx=None, ky=None,
+             rr_period=0)
     d.update(kw)
     return cg.cg_problem(d["nx"], d["ny"], d["mem"], d["b"], d["x0"], d["x"], d["tol"],
                          d["maxit"], d["variant"], d["precision"], d["inner_tol"],
-                         d["precond"], d["nz"], 0, d["kx"], d["ky"])
+                         d["precond"], d["nz"], d["rr_period"], d["kx"], d["ky"])
 
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
@@ -59,6 +60,12 @@ def _prob(**kw):
                                  dict(kx=3), dict(ky=4), dict(kx=3, ky=4, nz=2),
                                  dict(kx=3, ky=4, precond=2), dict(kx=3, ky=4, precision=1),
                                  dict(kx=3, ky=4, precision=2),
+                                 # residual replacement: even period, pipelined FP64 2D
+                                 dict(rr_period=3, variant=1), dict(rr_period=-2, variant=1),
+                                 dict(rr_period=2), dict(rr_period=2, variant=1, precision=1),
+                                 dict(rr_period=2, variant=1, precision=2),
+                                 dict(rr_period=2, variant=1, precond=1),
+                                 dict(rr_period=2, variant=1, nz=3),
                                  # padded row stride times 14 interleaved vectors > int32
                                  dict(nx=300_000_000, ny=7, variant=1),
                                  dict(nx=153_391_617, ny=1)])
@@ -83,6 +90,10 @@ def test_validation_accepts():
     for v in (0, 1):
         for nz in (0, 1):
             assert cg.cg_validate(_prob(kx=3, ky=4, variant=v, nz=nz)) == cg.CG_OK
+    # residual replacement: pipelined, 5-point or variable coefficients
+    for rr in (2, 4, 100):
+        assert cg.cg_validate(_prob(rr_period=rr, variant=1)) == cg.CG_OK
+        assert cg.cg_validate(_prob(rr_period=rr, variant=1, kx=3, ky=4)) == cg.CG_OK
     # Chebyshev preconditioner: 1..8 steps, FP64, either variant
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK

@@ -1,0 +1,117 @@
+"""GPU parity of residual replacement in the pipelined CG (cg_problem.rr_period):
+every rr_period iterations the library recomputes q = A p, z = A q (stencil
+passes), r = b - A x and w = A r (the initial-residual passes, with their
+sums), bitwise the oracle's pipelined CG with the same replacement in the
+library's order, on the 5-point and the variable-coefficient operators."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import MODE_CANONICAL
+from paper_1803_03797_amd import cg, workloads
+
+pytestmark = pytest.mark.gpu
+PIPE = cg.CG_VARIANT_PIPELINED
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = cg.Context(device=0, arena_bytes=4 << 30)
+    yield c
+    c.close()
+
+
+def order(ctx, nx, ny, vc=False):
+    info = ctx.cg_plan(nx, ny, PIPE, vc=vc, rr_period=2)
+    assert info.path == 0
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+
+
+@pytest.mark.parametrize("nx,ny", [(300, 200), (129, 67), (513, 257), (40, 30), (1, 77)])
+@pytest.mark.parametrize("period", [2, 4, 10])
+def test_lockstep_bitwise(ctx, nx, ny, period):
+    """Small grids too (they take the multi-work-group passes when replacing)."""
+    b = np.random.default_rng(nx + ny + period).uniform(-1, 1, (ny, nx))
+    o = order(ctx, nx, ny)
+    for m in (1, 6, 40, 71):
+        say("rr lockstep", nx, ny, "period", period, "m", m)
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, nx, ny, tol=0.0, maxit=m, variant=PIPE, rr_period=period)
+        xo, ro = oracle.cg(b, nx, ny, variant=PIPE, tol=0.0, maxit=m, mode=MODE_CANONICAL,
+                           order=o, rr_period=period)
+        # past convergence (the 77-unknown column converges in fewer than 40
+        # iterations) a run with tol = 0 ends in a breakdown on both sides
+        assert rc == ro.status and res.iterations == ro.iterations
+        assert ro.status == cg.CG_BREAKDOWN or ro.iterations == m
+        np.testing.assert_array_equal(x, xo)
+        assert res.rel_res_recursive == ro.rel_res_recursive
+        assert res.rel_res_true == ro.rel_res_true
+
+
+def test_variable_coefficient_attainable_accuracy(ctx, torch):
+    """256 x 256 variable coefficients, tol 1e-12: plain pipelined CG breaks
+    down; with replacement every 50 iterations the solve converges to a true
+    residual of tol, bitwise the oracle's replaced run in the library's order."""
+    n, tol = 256, 1e-12
+    kx, ky = workloads.vc_faces(n, n)
+    b = workloads.vc_rhs(n, n)
+    o = order(ctx, n, n, vc=True)
+    say("vc 256^2 tol 1e-12: plain and replaced")
+    x = np.zeros_like(b)
+    rc0, r0 = ctx.solve(b, x, n, n, tol=tol, maxit=60000, variant=PIPE,
+                        kx=kx, ky=ky)
+    assert rc0 != cg.CG_OK or r0.rel_res_true > 100 * tol
+    x = np.zeros_like(b)
+    rc, r = ctx.solve(b, x, n, n, tol=tol, maxit=60000, variant=PIPE, kx=kx, ky=ky, rr_period=50)
+    xo, ro = oracle.cg_vc(b, n, n, kx, ky, variant=PIPE, tol=tol, maxit=60000,
+                          mode=MODE_CANONICAL, order=o, rr_period=50)
+    say("  replaced: %d iterations, true residual %.2e (oracle %d)" %
+        (r.iterations, r.rel_res_true, ro.iterations))
+    assert rc == cg.CG_OK and r.iterations == ro.iterations
+    assert r.rel_res_true <= 1.5 * tol
+    np.testing.assert_array_equal(x, xo)
+
+
+def test_full_size_lockstep(ctx, torch):
+    """The 4096 x 4096 workload, 40 iterations with a replacement every 8
+    (five replacements, two graph chunks), bitwise against the oracle."""
+    n, m, period = 4096, 40, 8
+    xs = workloads.large_solution(n, n)
+    b = oracle.spmv(xs, n, n, order=0)
+    o = order(ctx, n, n)
+    say("4096^2 rr lockstep")
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    rc, res = ctx.solve(bd, xd, n, n, tol=0.0, maxit=m, variant=PIPE, rr_period=period)
+    xo, ro = oracle.cg(b, n, n, variant=PIPE, tol=0.0, maxit=m, mode=MODE_CANONICAL, order=o,
+                       rr_period=period)
+    assert rc == cg.CG_OK and res.iterations == m
+    np.testing.assert_array_equal(xd.cpu().numpy(), xo)
+
+
+def test_rejections(ctx):
+    b = np.ones((20, 30))
+    x = np.zeros_like(b)
+    for kw in (dict(rr_period=3), dict(rr_period=-2), dict(rr_period=4, variant=0),
+               dict(rr_period=4, variant=PIPE, precision=cg.CG_PREC_FP32_REFINED),
+               dict(rr_period=4, variant=PIPE, precond=2)):
+        with pytest.raises(cg.CGError):
+            ctx.solve(b, x, 30, 20, **kw)
+    p = cg.make_problem(b, x, 30, 20, variant=PIPE, rr_period=4)
+    with pytest.raises(cg.CGError):
+        ctx.cg_solve_batch([p])
+    with pytest.raises(cg.CGError):
+        ctx.cg_submit(p)
