@@ -202,6 +202,18 @@ def headline(args):
                 "kernel": "pcg_pass", "avg_launch_us": round(avg * 1e6, 2),
                 "bytes_per_launch": per_launch, "launches": pk["launches"]}
 
+    # the iteration as a whole: each variant's algorithmic bytes of an
+    # odd/even iteration pair over the summed average times of its passes
+    it_roof = {}
+    for name, ks in (("classic", ("stencil_dot", "stencil_dot", "update_norm", "update_norm_nx")),
+                     ("pipelined", ("pcg_pass", "pcg_pass_nx"))):
+        if all(k in stats and stats[k]["launches"] for k in ks):
+            t = sum(stats[k]["seconds"] / stats[k]["launches"] for k in ks)
+            by = sum(BYTES_PER_DOF[k] for k in ks) * dof
+            it_roof[name] = {"achieved": round(by / t / 1e9, 1),
+                             "frac": round(by / t / 1e9 / HBM_PEAK_GBPS, 4),
+                             "us_per_iteration_pair": round(t * 1e6, 2)}
+
     tol_runs = None
     if args.tol_run:
         tol_runs = {}
@@ -249,6 +261,7 @@ def headline(args):
             v: round(BYTES_PER_ITER[v] * dof * args.iters * args.steps / per_variant[i] / 1e9, 1)
             for i, v in enumerate(("classic", "pipelined"))},
         "roofline": roof,
+        "iteration_roofline": it_roof,
         "kernels": kern,
         "profiled_ms_per_step": round(prof_elapsed / args.steps * 1e3, 3),
         "tol_1e-8": tol_runs,
@@ -333,8 +346,9 @@ def bench_batch(args):
     xs = [torch.zeros_like(b) for b in bs]
     dof = np.array([nx * ny for nx, ny in shapes], dtype=float)
     ctx = cg.Context(device=0, arena_bytes=8 << 30)
+    pc = args.batch_precond
     mk = lambda b, x, s: cg.make_problem(b, x, s[0], s[1], tol=w["tol"], maxit=w["maxit"],
-                                         variant=cg.CG_VARIANT_PIPELINED)
+                                         variant=cg.CG_VARIANT_PIPELINED, precond=pc)
     # warm (graph capture and code paths), then timed
     ctx.cg_solve_batch([mk(b, x, s) for b, x, s in list(zip(bs, xb, shapes))[:8]])
     torch.cuda.synchronize()
@@ -363,17 +377,22 @@ def bench_batch(args):
         cw = 0.0
         for m in order:
             nx, ny = shapes[m]
-            xo, ro = oracle.cg(bs[m].cpu().numpy(), nx, ny, variant=1, tol=w["tol"],
-                               maxit=w["maxit"])
+            if pc:
+                xo, ro = oracle.pcg(bs[m].cpu().numpy(), nx, ny, pc, tol=w["tol"],
+                                    maxit=w["maxit"], variant=1)
+            else:
+                xo, ro = oracle.cg(bs[m].cpu().numpy(), nx, ny, variant=1, tol=w["tol"],
+                                   maxit=w["maxit"])
             cw += nx * ny * ro.iterations
         ct = time.perf_counter() - t
         cpu = {"value": round(cw / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
                "kind": "oracle",
-               "sample": "the %d smallest of the solves, pipelined CG, explicit CSR, single "
-                         "thread (%.1f s)" % (len(order), ct),
+               "sample": "the %d smallest of the solves, pipelined CG%s, explicit CSR, single "
+                         "thread (%.1f s)" % (len(order), " + Chebyshev s=%d" % pc if pc else "",
+                                              ct),
                "extrapolated_batch_seconds": round(work / (cw / ct), 1)}
     emit({"metric": "batch solves/s (pipelined FP64, tol 1e-8, multi-solve step kernel)",
-          "workload": "batch",
+          "workload": "batch", "chebyshev_steps": pc,
           "config": {"workload": "%d solves, sides i.i.d. from {64..1024} per axis, b~U[-1,1]"
                                  % len(shapes), "total_dof": int(dof.sum())},
           "dtype": "f64",
@@ -720,6 +739,19 @@ def bench_vc(args):
                          kernels={k: vv for k, vv in ks.items() if k != "final_check"},
                          tol_1e8=tol_run)
         log("vc", name, json.dumps(out[name]))
+    if not args.fixed_only:
+        # the pipelined variant with residual replacement every rr iterations
+        rr = args.rr_period
+        x3 = torch.zeros_like(b)
+        p3 = cg.make_problem(b, x3, n, n, tol=w["tol"], maxit=w["maxit"], variant=1, kx=kx,
+                             ky=ky, rr_period=rr)
+        t1 = time.perf_counter()
+        rc3, r3 = ctx.cg_solve(p3)
+        dt3 = time.perf_counter() - t1
+        out["pipelined_rr%d" % rr] = dict(tol_1e8=dict(
+            status=cg.cg_status_str(rc3), iterations=r3.iterations, seconds=round(dt3, 4),
+            rel_res_recursive=r3.rel_res_recursive, rel_res_true=r3.rel_res_true))
+        log("vc pipelined rr", json.dumps(out["pipelined_rr%d" % rr]))
     pk = out["pipelined"]["kernels"].get("pcg_pass")
     roof = None
     if pk:
@@ -840,10 +872,10 @@ def bench_serve(args):
     ctx = cg.Context(device=0, arena_bytes=16 << 30)
     dof = np.array([nx * ny for nx, ny, _ in reqs], dtype=float)
 
-    def prob(m, x, precision):
+    def prob(m, x, precision, precond=0):
         nx, ny, tol = reqs[m]
         return cg.make_problem(bs[m], x, nx, ny, tol=tol, maxit=200000, variant=0,
-                               precision=precision, inner_tol=1e-4)
+                               precision=precision, inner_tol=1e-4, precond=precond)
 
     def met(rc, r, m):
         # equal accuracy: every result's true FP64 residual meets its tolerance
@@ -866,16 +898,26 @@ def bench_serve(args):
     cap64 = len(reqs) / (time.perf_counter() - t0)
     log("per-request FP64: %.1f solves/s" % cap64)
 
-    def fifo(arrivals):
-        # one server, FIFO, the measured service times
-        done = 0.0
+    def per_request(arrivals):
+        # per-request FP64 under the same arrivals, measured: one solver
+        # thread takes the requests in arrival order (FIFO) and solves each
+        # alone with cg_solve; latency = completion - arrival
+        xs = [torch.zeros_like(b) for b in bs]
         lat = np.zeros(len(reqs))
+        start = time.perf_counter()
         for m in range(len(reqs)):
-            done = max(done, arrivals[m]) + svc[m]
-            lat[m] = done - arrivals[m]
-        return lat, done
+            dt = arrivals[m] - (time.perf_counter() - start)
+            if dt > 0:
+                time.sleep(dt)
+            ctx.cg_solve(prob(m, xs[m], 0))
+            lat[m] = time.perf_counter() - start - arrivals[m]
+            if (m + 1) % 2000 == 0:
+                log("per-request FP64 under arrivals: %d done" % (m + 1))
+        return lat, time.perf_counter() - start
 
-    def served(precision, arrivals):
+    iters = [0] * len(reqs)
+
+    def served(precision, arrivals, precond=0):
         xs = [torch.zeros_like(b) for b in bs]
         tickets = [None] * len(reqs)
         results = {}
@@ -887,7 +929,7 @@ def bench_serve(args):
                     dt = arrivals[m] - (time.perf_counter() - start)
                     if dt > 0:
                         time.sleep(dt)
-                tickets[m] = ctx.cg_submit(prob(m, xs[m], precision))
+                tickets[m] = ctx.cg_submit(prob(m, xs[m], precision, precond))
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -911,6 +953,7 @@ def bench_serve(args):
                 log("served: %d done" % len(results))
             time.sleep(0.002 if len(reqs) > 1000 else 0.0005)
         th.join()
+        iters[:] = [results[m][1].iterations for m in range(len(reqs))]
         makespan = max(v[2] for v in results.values())
         lat = np.array([results[m][1].latency_seconds for m in range(len(reqs))])
         ok = sum(met(results[m][0], results[m][1], m) for m in range(len(reqs)))
@@ -924,13 +967,19 @@ def bench_serve(args):
     xs_ref, sat_ref = served(cg.CG_PREC_FP32_REFINED, None)
     log("served FP32-refined, saturated", json.dumps(sat_ref))
     xs_64, sat_64 = served(cg.CG_PREC_FP64, None)
+    sat_iters = list(iters)
     log("served FP64, saturated", json.dumps(sat_64))
+    sat_pc = None
+    if args.serve_precond:
+        # the same stream served as Chebyshev-preconditioned classic CG (FP64)
+        _, sat_pc = served(cg.CG_PREC_FP64, None, args.serve_precond)
+        log("served FP64 + Chebyshev s=%d, saturated" % args.serve_precond, json.dumps(sat_pc))
     same = sum(int(torch.equal(a, c)) for a, c in zip(xs_64, x64))
     # latency under Poisson arrivals at fractions of the per-request capacity
     loads = {}
     for frac in args.loads:
         arr = workloads.poisson_arrivals(len(reqs), frac * cap64, seed_item=int(frac * 100))
-        lat64, make64 = fifo(arr)
+        lat64, make64 = per_request(arr)
         entry = {"arrival_rate_per_s": round(frac * cap64, 2),
                  "per_request_fp64": dict(solves_per_s=round(len(reqs) / make64, 2),
                                           p50_ms=round(float(np.median(lat64)) * 1e3, 3),
@@ -940,6 +989,36 @@ def bench_serve(args):
         _, entry["served_fp64"] = served(cg.CG_PREC_FP64, arr)
         loads["%.2f" % frac] = entry
         log("load %.2f:" % frac, json.dumps(entry))
+    # a 1% sample (every 100th request) on the host: the true residual of the
+    # served FP64 and refined solutions with the oracle's explicit CSR
+    # matrix, and the oracle's own solve time (one thread, the iterations
+    # without the CSR assembly: 20 iterations timed, scaled to the iteration
+    # count of the request's served FP64 solve)
+    import oracle
+    sample = list(range(0, len(reqs), 100))
+    host_ok = {"served_fp64": 0, "served_fp32_refined": 0}
+    worst = {"served_fp64": 0.0, "served_fp32_refined": 0.0}
+    cpu_s = 0.0
+    for m in sample:
+        nx, ny, tol = reqs[m]
+        bh = bs[m].cpu().numpy()
+        nb = np.linalg.norm(bh)
+        for name, xs in (("served_fp64", xs_64), ("served_fp32_refined", xs_ref)):
+            xh = xs[m].cpu().numpy()
+            rt = np.linalg.norm(bh - oracle.spmv(xh, nx, ny)) / nb
+            worst[name] = max(worst[name], rt / tol)
+            host_ok[name] += int(rt <= tol * 1.0001)
+        its = sat_iters[m]
+        k = min(20, max(its, 1))
+        _, t, _ = oracle.cg_timed(bh, nx, ny, 0, tol=0.0, maxit=k)
+        cpu_s += t / k * its
+    cpu = None if args.no_cpu else {
+        "value": round(len(sample) / cpu_s, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": "%d requests (every 100th), classic CG, one thread: 20 iterations each timed "
+                  "without the CSR assembly and scaled to the request's iteration count "
+                  "(%.1f s extrapolated)" % (len(sample), cpu_s),
+        "host": host_info()}
+    log("host check:", json.dumps(host_ok), "cpu:", json.dumps(cpu))
     emit({"metric": "served solves/s and p50/p99 latency (FP32-refined vs per-request FP64)",
           "workload": "serve",
           "config": {"workload": "%d requests, sides log-uniform [32,2048] per axis, tol 1e-6 or "
@@ -949,11 +1028,57 @@ def bench_serve(args):
                                      "served_fp32_refined": sat_ref["solves_per_s"],
                                      "served_fp64": sat_64["solves_per_s"]},
           "saturated": {"served_fp32_refined": sat_ref, "served_fp64": sat_64,
-                        "per_request_fp64_met_tolerance": ok64},
+                        "per_request_fp64_met_tolerance": ok64,
+                        "served_fp64_chebyshev_s%d" % args.serve_precond: sat_pc},
           "poisson_loads_x_per_request_capacity": loads,
-          "per_request_latency_model": "FIFO replay of the measured per-request service times",
-          "served_fp64_equals_alone_bitwise": same, "of": len(reqs)})
+          "per_request_latency": "measured: one thread solves the requests one by one in "
+                                 "arrival order (cg_solve each)",
+          "host_csr_check_1pct": {"requests": len(sample), "true_res_le_tol": host_ok,
+                                  "worst_true_res_over_tol": worst},
+          "served_fp64_equals_alone_bitwise": same, "of": len(reqs), "cpu_baseline": cpu})
     ctx.close()
+
+
+# ----------------------------------------------------------------------- tune --
+
+def bench_tune(args):
+    """cg_tune's pick against the unpinned (hand-set) tile shape at 4096^2 and
+    8192^2 for both variants: HIP-event time per iteration of the iteration
+    passes over a fixed-iteration solve, before and after tuning."""
+    torch, cg = setup()
+    names = {0: ("stencil_dot", "update_norm", "update_norm_nx"), 1: ("pcg_pass", "pcg_pass_nx")}
+    out = {}
+    for n in args.tune_sides:
+        ctx = cg.Context(device=0, arena_bytes=96 * n * n + (1 << 30))
+        b = torch.ones((n, n), dtype=torch.float64, device="cuda")
+        for v in (0, 1):
+            def per_iter():
+                x = torch.zeros_like(b)
+                p = cg.make_problem(b, x, n, n, tol=0.0, maxit=64, variant=v)
+                ctx.cg_solve(p)
+                ctx.cg_set_profiling(True)
+                ctx.cg_kernel_stats(reset=True)
+                ctx.cg_solve(p)
+                st = ctx.cg_kernel_stats(reset=True)
+                ctx.cg_set_profiling(False)
+                return sum(st[k]["seconds"] for k in names[v] if k in st) / 64 * 1e6
+
+            def shape():
+                i = ctx.cg_plan(n, n, v)
+                return dict(rows=i.rows, grid=i.grid, cols_per_lane=i.cols_per_lane,
+                            tiles=i.tiles)
+            before = dict(shape(), us_per_iteration=round(per_iter(), 2))
+            t = time.perf_counter()
+            ctx.cg_tune(n, n, v)
+            tt = time.perf_counter() - t
+            after = dict(shape(), us_per_iteration=round(per_iter(), 2))
+            key = "%d^2 %s" % (n, "pipelined" if v else "classic")
+            out[key] = dict(unpinned=before, tuned=after, tune_seconds=round(tt, 1))
+            log("tune", key, json.dumps(out[key]))
+        ctx.close()
+        del b
+    emit({"metric": "autotuner pick vs the unpinned tile shape (us per iteration, HIP events)",
+          "workload": "tune", "results": out})
 
 
 # ---------------------------------------------------------------------- probe --
@@ -992,11 +1117,17 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=48)
-    ap.add_argument("--tol-run", action="store_true", help="also time tol=1e-8 solves")
+    ap.add_argument("--no-tol-run", dest="tol_run", action="store_false",
+                    help="skip the tol=1e-8 solves of the headline workload")
     ap.add_argument("--workload",
-                    choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube", "vc"])
+                    choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube", "vc",
+                             "tune"])
     ap.add_argument("--n-cube", type=int, default=256, help="--workload cube: grid side")
     ap.add_argument("--n-vc", type=int, default=4096, help="--workload vc: grid side")
+    ap.add_argument("--tune-sides", type=int, nargs="+", default=[4096, 8192],
+                    help="--workload tune: grid sides")
+    ap.add_argument("--rr-period", type=int, default=100,
+                    help="--workload vc: residual replacement period of the pipelined tol run")
     ap.add_argument("--fixed-only", action="store_true",
                     help="--workload cube / vc: only the fixed-iteration runs (no tol solves)")
     ap.add_argument("--huge-precond", type=int, default=8,
@@ -1010,6 +1141,10 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=16)
     ap.add_argument("--n-huge", type=int, default=8192)
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.5])
+    ap.add_argument("--batch-precond", type=int, default=0,
+                    help="--workload batch: Chebyshev steps of every solve (0: none)")
+    ap.add_argument("--serve-precond", type=int, default=0,
+                    help="--workload serve: also serve the stream preconditioned with s steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -1032,6 +1167,8 @@ def main():
         return bench_precond(args)
     if args.workload == "cube":
         return bench_cube(args)
+    if args.workload == "tune":
+        return bench_tune(args)
     if args.workload == "vc":
         return bench_vc(args)
     if args.workload == "serve":
