@@ -53,10 +53,18 @@ typedef enum { CG_VARIANT_CLASSIC = 0, CG_VARIANT_PIPELINED = 1 } cg_variant;
  * (nx + 1)(ny + 2) + nx ny <= 20352 (100 x 100 fits; the paper's grids reach
  * 100 x 100; a single row or column up to 5087 or 6782 unknowns); larger
  * grids are CG_E_INVALID.  inner_tol is ignored. */
+/* CG_PREC_AUTO: a size-based precision policy for batches and serving.
+ * Grids of fewer than 20480 unknowns are solved in FP64 (the on-chip solver
+ * and the shortest tile solves, where FP32 vectors buy nothing), larger ones
+ * FP32-refined (CG_PREC_FP32_REFINED: half the bytes per inner iteration);
+ * the result is bitwise that of the precision chosen (outer_iterations > 0
+ * tells a refined one).  2D constant-coefficient problems without
+ * preconditioner or residual replacement only. */
 typedef enum {
   CG_PREC_FP64 = 0,
   CG_PREC_FP32_REFINED = 1,
-  CG_PREC_FIXED = 2
+  CG_PREC_FIXED = 2,
+  CG_PREC_AUTO = 3
 } cg_precision;
 typedef enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 } cg_memspace;
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcg.so")
 
 CG_VARIANT_CLASSIC, CG_VARIANT_PIPELINED = 0, 1
-CG_PREC_FP64, CG_PREC_FP32_REFINED, CG_PREC_FIXED = 0, 1, 2
+CG_PREC_FP64, CG_PREC_FP32_REFINED, CG_PREC_FIXED, CG_PREC_AUTO = 0, 1, 2, 3
 CG_MEM_HOST, CG_MEM_DEVICE = 0, 1
 CG_OK, CG_PENDING, CG_NOT_CONVERGED, CG_BREAKDOWN = 0, 1, 2, 3
 CG_E_INVALID, CG_E_NOMEM, CG_E_DEVICE, CG_E_BUSY, CG_E_TICKET = -1, -2, -3, -4, -5

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/cg.h"
 #include "cg_runtime.h"
@@ -45,24 +46,32 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res) {
   if (!ctx || !res) return CG_E_INVALID;
   int rc = cgr::validate(prob);
   if (rc) return rc;
+  const cg_problem q = cgr::resolve_precision(*prob);
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
-  return c->solve(prob, res);
+  return c->solve(&q, res);
 }
 
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results) {
   if (!ctx || !probs || !results || n < 1) return CG_E_INVALID;
+  std::vector<cg_problem> q;
+  try {
+    q.resize(n);
+  } catch (const std::bad_alloc&) {
+    return CG_E_NOMEM;
+  }
   for (int32_t i = 0; i < n; ++i) {
     int rc = cgr::validate(&probs[i]);
     if (rc) return rc;
     // 3D, variable-coefficient and residual-replacement problems: cg_solve only
     if (probs[i].nz > 1 || probs[i].kx || probs[i].rr_period) return CG_E_INVALID;
+    q[i] = cgr::resolve_precision(probs[i]);
   }
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   if (hipSetDevice(c->device) != hipSuccess) return CG_E_DEVICE;
-  return c->solve_batch(probs, n, results);
+  return c->solve_batch(q.data(), n, results);
 }
 
 int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
@@ -70,7 +79,8 @@ int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
   int rc = cgr::validate(prob);
   if (rc) return rc;
   if (prob->nz > 1 || prob->kx || prob->rr_period) return CG_E_INVALID;  // cg_solve only
-  return cgr_server_submit(C(ctx), prob, ticket);
+  const cg_problem q = cgr::resolve_precision(*prob);
+  return cgr_server_submit(C(ctx), &q, ticket);
 }
 
 int cg_poll(cg_ctx* ctx, uint64_t ticket, cg_result* res) {
@@ -120,7 +130,8 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
     return CG_E_INVALID;
   Ctx* c = C(ctx);
   std::lock_guard<std::recursive_mutex> lk(c->mu);
-  cgr::Plan pl = c->plan(prob);
+  const cg_problem q = cgr::resolve_precision(*prob);
+  cgr::Plan pl = c->plan(&q);
   memset(info, 0, sizeof(*info));
   info->path = pl.fixed ? 3 : pl.rr ? 2 : pl.wg ? 1 : 0;
   info->seg_rows = pl.rr ? cgk::kRrRows : 0;
@@ -144,7 +155,8 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
 
 int cg_footprint(const cg_problem* prob, size_t* bytes) {
   if (!prob || !bytes || prob->nx < 1 || prob->ny < 1) return CG_E_INVALID;
-  *bytes = cgr::footprint_of(prob);
+  const cg_problem q = cgr::resolve_precision(*prob);
+  *bytes = cgr::footprint_of(&q);
   return CG_OK;
 }
 

@@ -284,6 +284,11 @@ hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
 hipError_t launch_gather(const Slot* slots, const int* idx, int n, int step, State* out,
                          hipStream_t s);
 int step_max_blocks_per_cu();
+// The tile passes of preconditioned pipelined CG (K_INIT_WU, K_PPCG) of step
+// *step_base + k, over launch_step's items; other kinds are skipped.
+hipError_t launch_step_ppcg(const Slot* slots, const Item* items, const int* n_items,
+                            const int* step_base, int k, int grid, hipStream_t st);
+int step_ppcg_max_blocks_per_cu();
 // The Chebyshev passes (K_CHEB, K_CHEBW) of step *step_base + k of the
 // resident preconditioned solves with s Chebyshev steps (1 <= s <= 8):
 // work-groups of 512 threads stride over cinfo[2 s] items (Chebyshev item

@@ -2630,8 +2630,10 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
       if (it.t0 == 0 && threadIdx.x == 0) *S.S[(m + 1) & 1] = s;
       continue;
     }
-    // the Chebyshev passes belong to the Chebyshev step kernel
-    if (kind == K_CHEB || kind == K_CHEBW) continue;
+    // the Chebyshev passes belong to the Chebyshev step kernel, the passes of
+    // preconditioned pipelined CG to k_step_ppcg (their bodies would raise
+    // this kernel's register count for every pass)
+    if (kind == K_CHEB || kind == K_CHEBW || kind == K_INIT_WU || kind == K_PPCG) continue;
     if (S.cpl4) {
       switch (kind) {
         case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds, rev); break;
@@ -2649,14 +2651,35 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
         case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds, rev); break;
         case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds, rev); break;
         case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds, rev); break;
-        case K_INIT_WU: step_item<K_INIT_WU, 2>(S, it, m, s, lds, rev); break;
-        case K_PPCG: step_item<K_PPCG, 2>(S, it, m, s, lds, rev); break;
         case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds, rev); break;
         case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds, rev); break;
         case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds, rev); break;
         case K_FINAL: step_item<K_FINAL, 2>(S, it, m, s, lds, rev); break;
       }
     }
+    __syncthreads();  // LDS reuse by the next item
+  }
+}
+
+// The tile passes of preconditioned pipelined CG (K_INIT_WU, K_PPCG) at step
+// *step_base + k, over the same items as k_step; every other pass kind is
+// left to k_step and the Chebyshev step kernel.
+__global__ __launch_bounds__(kGroup) void k_step_ppcg(const Slot* slots, const Item* items,
+                                                     const int* n_items, const int* step_base,
+                                                     int k) {
+  __shared__ double lds[kLdsPerGroup];
+  const int n = __builtin_amdgcn_readfirstlane(*n_items);
+  const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
+  const int rev = step & 1;
+  for (int ii = blockIdx.x; ii < n; ii += gridDim.x) {
+    const Item it = items[rev ? n - 1 - ii : ii];
+    const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
+    const int m = step - S.admit_step;
+    const State s = load_state_uniform(S.S[m & 1]);
+    const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+    if (kind == K_INIT_WU) step_item<K_INIT_WU, 2>(S, it, m, s, lds, rev);
+    else if (kind == K_PPCG) step_item<K_PPCG, 2>(S, it, m, s, lds, rev);
+    else continue;
     __syncthreads();  // LDS reuse by the next item
   }
 }
@@ -2746,6 +2769,21 @@ hipError_t launch_step(const Slot* slots, const Item* items, const int* n_items,
   hipLaunchKernelGGL(k_step, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items, step_base,
                      k);
   return hipGetLastError();
+}
+
+hipError_t launch_step_ppcg(const Slot* slots, const Item* items, const int* n_items,
+                            const int* step_base, int k, int grid, hipStream_t st) {
+  if (grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step_ppcg, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items,
+                     step_base, k);
+  return hipGetLastError();
+}
+
+int step_ppcg_max_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_ppcg, kGroup, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
 }
 
 template <int S>

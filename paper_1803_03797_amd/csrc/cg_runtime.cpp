@@ -46,8 +46,22 @@ static int32_t map_status(int32_t st) {
   }
 }
 
+cg_problem resolve_precision(const cg_problem& p) {
+  cg_problem q = p;
+  if (q.precision == CG_PREC_AUTO)
+    q.precision = (int64_t)q.nx * q.ny < kAutoRefineDof ? CG_PREC_FP64 : CG_PREC_FP32_REFINED;
+  return q;
+}
+
 int validate(const cg_problem* p) {
   if (!p) return CG_E_INVALID;
+  if (p->precision == CG_PREC_AUTO) {
+    // the policy picks FP64 or FP32 refinement: problems both can take
+    if (p->precond != 0 || p->nz > 1 || p->kx || p->ky || p->rr_period != 0)
+      return CG_E_INVALID;
+    const cg_problem q = resolve_precision(*p);
+    return validate(&q);
+  }
   if (p->nx < 1 || p->ny < 1 || p->nz < 0) return CG_E_INVALID;
   if ((int64_t)p->ny * std::max(p->nz, 1) >= (int64_t)1 << 31) return CG_E_INVALID;
   if ((int64_t)p->nx * p->ny * std::max(p->nz, 1) > (int64_t)1 << 31) return CG_E_INVALID;
@@ -264,12 +278,6 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
     pl.g.pitch = pl.width * pl.il;
     pl.g.kcs = pl.width;
     vec_bytes = round_up((size_t)pl.il * elems * 8, Arena::kAlign);
-  } else if (interleave && classic_interleave && !pl.wg && !pl.refined && !pl.fixed &&
-             p->variant == CG_VARIANT_CLASSIC && !pl.precond && !pl.vc && p->nz <= 1) {
-    // classic FP64 with interleaved rows r, p, p', x, b
-    pl.il = 5;
-    pl.g.pitch = pl.width * pl.il;
-    vec_bytes = round_up((size_t)pl.il * elems * 8, Arena::kAlign);
   }
   pl.footprint = vec_bytes + n32 * pl.v32 + 2 * pl.part + 2 * round_up(sizeof(State), 256) +
                  (pl.precond ? 256 : 0);
@@ -370,9 +378,8 @@ hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool chec
 
 bool carve(Ctx& c, Work& w) {
   // an interleaved block holds exactly the vectors carved from it below
-  if (w.pl.il > 1 && w.pl.variant == CG_VARIANT_CLASSIC
-          ? (w.pl.il != 5 || w.pl.precond || w.pl.vc || w.pl.refined)
-          : w.pl.il > 1 && w.pl.il != (w.pl.precond ? 10 : 8) + (w.pl.vc ? 4 : 0))
+  if (w.pl.il > 1 && (w.pl.variant != CG_VARIANT_PIPELINED ||
+                      w.pl.il != (w.pl.precond ? 10 : 8) + (w.pl.vc ? 4 : 0)))
     return false;
   w.mem = (char*)c.arena.alloc(w.pl.footprint);
   if (!w.mem) return false;
@@ -389,19 +396,6 @@ bool carve(Ctx& c, Work& w) {
     double* blk = (double*)take(round_up((size_t)pl.il * pl.width * pl.g.ny * 8, Arena::kAlign));
     int k = 0;
     auto vec = [&]() { return blk + (size_t)(k++) * pl.width; };
-    if (pl.variant == CG_VARIANT_CLASSIC) {
-      // pass 1 streams r, p, p' (adjacent), pass 2 p, r and x
-      w.r = vec();
-      w.pc[0] = vec();
-      w.pc[1] = vec();
-      w.x = vec();
-      w.b = vec();
-      w.part[0] = (double*)take(pl.part);
-      w.part[1] = (double*)take(pl.part);
-      w.S[0] = (State*)take(round_up(sizeof(State), 256));
-      w.S[1] = (State*)take(round_up(sizeof(State), 256));
-      return true;
-    }
     w.b = vec();
     w.x = vec();
     w.r = vec();
@@ -1269,7 +1263,6 @@ int Ctx::init(const cg_config* cfg) {
   if (const char* e = getenv("CG_STEP_CHUNK")) step_chunk = std::max(1, atoi(e));
   if (const char* e = getenv("CG_SERVE_CHUNK")) serve_chunk = std::max(1, atoi(e));
   if (const char* e = getenv("CG_CHEB_ITEM_DIV")) cheb_item_div = std::max(1, atoi(e));
-  if (const char* e = getenv("CG_CLASSIC_IL")) classic_interleave = atoi(e) != 0;
   load_tune_cache();
   return CG_OK;
 }

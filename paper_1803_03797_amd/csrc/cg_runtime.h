@@ -100,6 +100,12 @@ int stage_out(Ctx& c, Work& w, const cg_problem* p, const cgk::State& s);
 void fill_result(const cgk::State& s, cg_result* res, double secs, bool refined);
 
 int validate(const cg_problem* p);
+// CG_PREC_AUTO's choice: FP64 below kAutoRefineDof unknowns, FP32-refined from
+// there (measured in batches of equal requests on the step engine: refinement
+// 0.78x FP64's solves/s at 128^2, 1.21x at 181^2, 1.23-1.35x from 256^2 to
+// 2048^2); any other precision unchanged
+constexpr int64_t kAutoRefineDof = 20480;
+cg_problem resolve_precision(const cg_problem& p);
 size_t footprint_of(const cg_problem* p);
 cgk::Geo make_geo(int nx, int ny, int fp32g, int rows);
 int default_rows(int nx, int ny, int fp32g);
@@ -125,7 +131,6 @@ struct Ctx {
   int step_chunk = 32;         // batch: steps between harvests
   int serve_chunk = 8;         // serving: steps between admissions
   int cheb_item_div = 1;       // Chebyshev items per pass: resident work-groups / this
-  bool classic_interleave = false;  // classic FP64 tile passes: interleaved rows
   int step_chunk_for(bool serving) const { return serving ? serve_chunk : step_chunk; }
   size_t engine_bytes() const {  // control block of the multi-solve engine
     return (size_t)max_slots * (sizeof(cgk::Slot) + 2 * 256 * sizeof(cgk::Item) +

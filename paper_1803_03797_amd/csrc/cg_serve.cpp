@@ -425,6 +425,12 @@ class Engine {
     }
     int* nn = (int*)(h_items_ + max_items_);
     *nn = n;
+    // a preconditioned pipelined solve: its tile passes run in k_step_ppcg
+    // (bit 0 of the mask)
+    for (int i = 0; i < n_; ++i) {
+      Job* j = slot_job_[i];
+      if (j && j->w.pl.precond && j->w.pl.variant == CG_VARIANT_PIPELINED) cheb_mask_ |= 1u;
+    }
     // Chebyshev items, grouped by s (each group's count and offset in cinfo)
     int nc = 0;
     int* cinfo = (int*)(h_citems_ + max_items_);
@@ -455,12 +461,16 @@ class Engine {
     return CG_OK;
   }
 
-  // One step: the step kernel, then the Chebyshev step kernel of every s
-  // that a preconditioned solve of this engine has used (a solve at any
-  // other pass is skipped by the Chebyshev kernels; an s with no solve
+  // One step: the step kernel, the preconditioned pipelined passes' step
+  // kernel once such a solve has been admitted, then the Chebyshev step
+  // kernel of every s that a preconditioned solve of this engine has used
+  // (each kernel skips the solves at passes of the others; an s with no solve
   // resident has no items).
   hipError_t launch_one_step(int k) {
     hipError_t e = launch_step(d_slots_, d_items_, d_nitems_, d_step_, k, grid_, c_.st);
+    if (e == hipSuccess && (cheb_mask_ & 1u))
+      e = launch_step_ppcg(d_slots_, d_items_, d_nitems_, d_step_, k,
+                           std::max(8, step_ppcg_max_blocks_per_cu() * c_.num_cu), c_.st);
     for (int sd = 1; sd <= kChebMaxSteps && e == hipSuccess; ++sd)
       if (cheb_mask_ & (1u << sd))
         e = launch_step_cheb(sd, d_slots_, d_citems_, d_cinfo_, d_step_, k,
@@ -495,7 +505,8 @@ class Engine {
   Item* h_citems_ = nullptr;  // Chebyshev items, then cinfo (pinned)
   Item* d_citems_ = nullptr;
   int* d_cinfo_ = nullptr;
-  unsigned cheb_mask_ = 0;    // Chebyshev steps s that any admitted solve has used
+  unsigned cheb_mask_ = 0;    // bit s: Chebyshev steps s that any admitted solve has used;
+                              // bit 0: a preconditioned pipelined solve was admitted
   unsigned graph_mask_ = 0;   // ... when the cached chunk was captured
   Item* h_items_ = nullptr;
   int* h_idx_ = nullptr;

@@ -47,7 +47,7 @@ def _prob(**kw):
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(tol=-1e-3), dict(tol=1.0),
                                  dict(tol=float("nan")), dict(maxit=0), dict(b=None),
                                  dict(x=None), dict(mem=7), dict(variant=2), dict(precision=5),
-                                 dict(precision=1, inner_tol=1.5), dict(precision=3),
+                                 dict(precision=1, inner_tol=1.5), dict(precision=4),
                                  dict(precision=2, nx=101, ny=101),
                                  dict(precision=2, nx=100, ny=101),
                                  dict(precision=2, nx=1, ny=6783),
@@ -66,6 +66,11 @@ def _prob(**kw):
                                  dict(rr_period=2, variant=1, precision=2),
                                  dict(rr_period=2, variant=1, precond=1),
                                  dict(rr_period=2, variant=1, nz=3),
+                                 # the precision policy: problems FP64 and refined both take
+                                 dict(precision=3, precond=2), dict(precision=3, nz=3),
+                                 dict(precision=3, kx=3, ky=4),
+                                 dict(precision=3, variant=1, rr_period=2),
+                                 dict(precision=3, inner_tol=1.5, nx=300, ny=300),
                                  # padded row stride times 14 interleaved vectors > int32
                                  dict(nx=300_000_000, ny=7, variant=1),
                                  dict(nx=153_391_617, ny=1)])
@@ -90,6 +95,10 @@ def test_validation_accepts():
     for v in (0, 1):
         for nz in (0, 1):
             assert cg.cg_validate(_prob(kx=3, ky=4, variant=v, nz=nz)) == cg.CG_OK
+    # the precision policy: either variant, any size
+    for nx, ny in ((10, 7), (181, 181), (182, 181), (2048, 2048)):
+        assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3)) == cg.CG_OK
+        assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3, variant=1)) == cg.CG_OK
     # residual replacement: pipelined, 5-point or variable coefficients
     for rr in (2, 4, 100):
         assert cg.cg_validate(_prob(rr_period=rr, variant=1)) == cg.CG_OK
@@ -98,6 +107,15 @@ def test_validation_accepts():
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
         assert cg.cg_validate(_prob(precond=s, variant=1)) == cg.CG_OK
+
+
+def test_auto_precision_footprint_follows_its_choice():
+    """Below 20480 unknowns the policy picks FP64, from there FP32 refinement:
+    the footprint is that of the precision chosen."""
+    for nx, ny, chosen in ((143, 143, 0), (128, 160, 1), (4096, 4096, 1), (100, 100, 0),
+                           (181, 181, 1)):
+        assert cg.cg_footprint(_prob(nx=nx, ny=ny, precision=3)) == \
+            cg.cg_footprint(_prob(nx=nx, ny=ny, precision=chosen))
 
 
 def test_footprint_per_unknown():

@@ -270,3 +270,47 @@ def test_serve_rejects_and_unknown_ticket():
         with pytest.raises(cg.CGError) as e:
             ctx.cg_poll(12345)
         assert e.value.code == cg.CG_E_TICKET
+
+
+def test_auto_precision_policy_batch_and_served():
+    """CG_PREC_AUTO: grids below 20480 unknowns solved in FP64, larger ones
+    FP32-refined; in a batch and served, each result is bitwise the solve
+    alone in the precision chosen, and the refined ones meet their tol."""
+    rng = np.random.default_rng(17)
+    shapes = [(100, 100), (143, 143), (144, 143), (300, 200), (64, 64), (513, 257), (17, 3),
+              (181, 181)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny in shapes]
+    with cg.Context(device=0, arena_bytes=2 << 30) as ctx:
+        xs = [np.zeros_like(b) for b in bs]
+        probs = [cg.make_problem(b, x, nx, ny, tol=1e-8, maxit=20000, variant=k % 2,
+                                 precision=cg.CG_PREC_AUTO)
+                 for k, (b, x, (nx, ny)) in enumerate(zip(bs, xs, shapes))]
+        say("auto precision batch")
+        rc, res = ctx.cg_solve_batch(probs)
+        assert rc == cg.CG_OK
+        xv = [np.zeros_like(b) for b in bs]
+        tickets = [ctx.cg_submit(cg.make_problem(b, x, nx, ny, tol=1e-8, maxit=20000,
+                                                 variant=k % 2, precision=cg.CG_PREC_AUTO))
+                   for k, (b, x, (nx, ny)) in enumerate(zip(bs, xv, shapes))]
+        served = {}
+        deadline = time.time() + 60
+        while len(served) < len(tickets) and time.time() < deadline:
+            for t in tickets:
+                if t not in served:
+                    rc2, r2 = ctx.cg_poll(t)
+                    if rc2 != cg.CG_PENDING:
+                        served[t] = (rc2, cg.cg_result.from_buffer_copy(r2))
+            time.sleep(0.001)
+        assert len(served) == len(tickets)
+        for k, ((nx, ny), b, x, r, t) in enumerate(zip(shapes, bs, xs, res, tickets)):
+            chosen = cg.CG_PREC_FP64 if nx * ny < 20480 else cg.CG_PREC_FP32_REFINED
+            xa = np.zeros_like(b)
+            rca, ra = ctx.cg_solve(cg.make_problem(b, xa, nx, ny, tol=1e-8, maxit=20000,
+                                                   variant=k % 2, precision=chosen))
+            assert (r.outer_iterations > 0) == (chosen == cg.CG_PREC_FP32_REFINED)
+            assert r.status == rca == cg.CG_OK and r.iterations == ra.iterations
+            assert r.rel_res_true <= 1e-8 * 1.000001 or chosen == cg.CG_PREC_FP64
+            np.testing.assert_array_equal(x, xa)
+            rcs, rs = served[t]
+            assert rcs == cg.CG_OK and rs.iterations == ra.iterations
+            np.testing.assert_array_equal(xv[k], xa)
