@@ -623,7 +623,7 @@ def bench_cube(args):
     w = workloads.CUBE
     n = args.n_cube
     dof = n ** 3
-    its = w["iterations"]
+    its = args.cube_iters or w["iterations"]
     b = torch.from_numpy(workloads.cube_rhs(n)).cuda()
     ctx = cg.Context(device=0, arena_bytes=64 * dof + (1 << 30))
     x = torch.zeros_like(b)
@@ -969,6 +969,9 @@ def bench_serve(args):
     xs_64, sat_64 = served(cg.CG_PREC_FP64, None)
     sat_iters = list(iters)
     log("served FP64, saturated", json.dumps(sat_64))
+    # the size-based policy: FP64 below 20480 unknowns, FP32-refined above
+    _, sat_auto = served(cg.CG_PREC_AUTO, None)
+    log("served auto precision, saturated", json.dumps(sat_auto))
     sat_pc = None
     if args.serve_precond:
         # the same stream served as Chebyshev-preconditioned classic CG (FP64)
@@ -987,6 +990,7 @@ def bench_serve(args):
                                                        3))}
         _, entry["served_fp32_refined"] = served(cg.CG_PREC_FP32_REFINED, arr)
         _, entry["served_fp64"] = served(cg.CG_PREC_FP64, arr)
+        _, entry["served_auto_precision"] = served(cg.CG_PREC_AUTO, arr)
         loads["%.2f" % frac] = entry
         log("load %.2f:" % frac, json.dumps(entry))
     # a 1% sample (every 100th request) on the host: the true residual of the
@@ -1026,8 +1030,10 @@ def bench_serve(args):
                      "classic CG; refined: inner tol 1e-4": True},
           "saturated_solves_per_s": {"per_request_fp64": round(cap64, 2),
                                      "served_fp32_refined": sat_ref["solves_per_s"],
-                                     "served_fp64": sat_64["solves_per_s"]},
+                                     "served_fp64": sat_64["solves_per_s"],
+                                     "served_auto_precision": sat_auto["solves_per_s"]},
           "saturated": {"served_fp32_refined": sat_ref, "served_fp64": sat_64,
+                        "served_auto_precision": sat_auto,
                         "per_request_fp64_met_tolerance": ok64,
                         "served_fp64_chebyshev_s%d" % args.serve_precond: sat_pc},
           "poisson_loads_x_per_request_capacity": loads,
@@ -1036,6 +1042,46 @@ def bench_serve(args):
           "host_csr_check_1pct": {"requests": len(sample), "true_res_le_tol": host_ok,
                                   "worst_true_res_over_tol": worst},
           "served_fp64_equals_alone_bitwise": same, "of": len(reqs), "cpu_baseline": cpu})
+    ctx.close()
+
+
+# ------------------------------------------------------------------ precision --
+
+def bench_precision(args):
+    """Where FP32 refinement pays on the step engine: batches of k equal
+    requests of side S (b~U[-1,1], tol 1e-8, classic CG), solved in FP64,
+    FP32-refined (inner tol 1e-4) and FP64 with the Chebyshev preconditioner
+    (s = 4); solves/s of each batch and the time of one solve alone."""
+    torch, cg = setup()
+    import numpy as np
+    ctx = cg.Context(device=0, arena_bytes=24 << 30)
+    out = {}
+    for S, k in ((64, 64), (128, 64), (181, 64), (256, 64), (512, 32), (1024, 16), (2048, 8)):
+        rng = np.random.default_rng(S)
+        bs = [torch.from_numpy(rng.uniform(-1, 1, (S, S))).cuda() for _ in range(k)]
+        row = {}
+        for name, prec, pc in (("fp64", 0, 0), ("fp32_refined", 1, 0), ("auto", 3, 0),
+                               ("fp64_chebyshev_s4", 0, 4)):
+            xs = [torch.zeros_like(b) for b in bs]
+            probs = [cg.make_problem(b, x, S, S, tol=1e-8, maxit=200000, precision=prec,
+                                     inner_tol=1e-4, precond=pc) for b, x in zip(bs, xs)]
+            ctx.cg_solve_batch(probs[:2])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, r = ctx.cg_solve_batch(probs)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t
+            t = time.perf_counter()
+            ctx.cg_solve(probs[0])
+            torch.cuda.synchronize()
+            row[name] = dict(solves_per_s=round(k / tb, 2), batch_s=round(tb, 4),
+                             alone_s=round(time.perf_counter() - t, 4), iterations=r[0].iterations,
+                             outer=r[0].outer_iterations, true_res=r[0].rel_res_true,
+                             met_tol=sum(int(q.rel_res_true <= 1e-8 * 1.000001) for q in r))
+        out["%d^2 x %d" % (S, k)] = row
+        log("precision", S, json.dumps(row))
+    emit({"metric": "batch solves/s by precision (step engine, equal requests, tol 1e-8)",
+          "workload": "precision", "results": out})
     ctx.close()
 
 
@@ -1121,8 +1167,10 @@ def main():
                     help="skip the tol=1e-8 solves of the headline workload")
     ap.add_argument("--workload",
                     choices=["small", "batch", "huge", "serve", "fixed", "precond", "cube", "vc",
-                             "tune"])
+                             "tune", "precision"])
     ap.add_argument("--n-cube", type=int, default=256, help="--workload cube: grid side")
+    ap.add_argument("--cube-iters", type=int, default=0,
+                    help="--workload cube: fixed iterations (0: the workload's 500)")
     ap.add_argument("--n-vc", type=int, default=4096, help="--workload vc: grid side")
     ap.add_argument("--tune-sides", type=int, nargs="+", default=[4096, 8192],
                     help="--workload tune: grid sides")
@@ -1167,6 +1215,8 @@ def main():
         return bench_precond(args)
     if args.workload == "cube":
         return bench_cube(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     if args.workload == "tune":
         return bench_tune(args)
     if args.workload == "vc":
