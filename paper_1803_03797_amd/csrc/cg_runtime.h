@@ -102,8 +102,8 @@ void fill_result(const cgk::State& s, cg_result* res, double secs, bool refined)
 int validate(const cg_problem* p);
 // CG_PREC_AUTO's choice: FP64 below kAutoRefineDof unknowns, FP32-refined from
 // there (measured in batches of equal requests on the step engine: refinement
-// 0.78x FP64's solves/s at 128^2, 1.21x at 181^2, 1.23-1.35x from 256^2 to
-// 2048^2); any other precision unchanged
+// 0.81x FP64's solves/s at 128^2, 1.17-1.39x from 181^2 to 2048^2); any other
+// precision unchanged
 constexpr int64_t kAutoRefineDof = 20480;
 cg_problem resolve_precision(const cg_problem& p);
 size_t footprint_of(const cg_problem* p);
