@@ -739,7 +739,7 @@ int oracle_cg3(int32_t variant, int32_t mode, const oracle_order* ord, int32_t n
   csr_t A;
   int rc = csr3_build(&A, nx, ny, nz, mode == MODE_CANONICAL ? 1 : 0);
   if (rc) return rc;
-  ctx_t c = {nx, rows, mode, ord};
+  ctx_t c = {nx, rows, mode, ord, 0};
   memset(res, 0, sizeof(*res));
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
@@ -1042,8 +1042,8 @@ int oracle_pcg(int32_t variant, int32_t mode, const oracle_order* ord,
   csr_t A;
   int rc = csr_build(&A, nx, ny, mode == MODE_CANONICAL ? 1 : 0, 0);
   if (rc) return rc;
-  ctx_t c = {nx, ny, mode, ord};
-  ctx_t c_rho = {nx, ny, mode, ord_rho};
+  ctx_t c = {nx, ny, mode, ord, 0};
+  ctx_t c_rho = {nx, ny, mode, ord_rho, 0};
   memset(res, 0, sizeof(*res));
   if (variant == VARIANT_PIPELINED) {
     rc = ppcg_run(&A, &c, sdeg, &c0, c1, c2, b, x0, x, tol, maxit, res);
@@ -1137,8 +1137,77 @@ static double dot_f32_in_f64(int64_t n, const inner_t* a, const inner_t* b) {
  *   update: x += s * fp64(d).
  * maxit caps the total number of inner iterations; an outer step whose inner
  * solve made no iteration is a breakdown. */
+/* z = M^-1 r in binary32: the Chebyshev recurrence of cheb_apply with the
+ * coefficients rounded to binary32 once and every operation a binary32 one
+ * (d_k = c1 d_(k-1) + c2 r_k with both products rounded). */
+static void cheb_apply_f32(const csr_t* A, int32_t s, float c0, const float* c1,
+                           const float* c2, const float* r, float* z, float* d, float* rk,
+                           float* t) {
+  const int64_t n = A->n;
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = r[i] * c0;
+    z[i] = d[i];
+    rk[i] = r[i];
+  }
+  for (int32_t k = 1; k < s; ++k) {
+    spmv_f32(A, d, t);
+    for (int64_t i = 0; i < n; ++i) {
+      rk[i] = rk[i] - t[i];
+      d[i] = c1[k - 1] * d[i] + c2[k - 1] * rk[i];
+      z[i] = z[i] + d[i];
+    }
+  }
+}
+
+static int refine_any(int32_t nx, int32_t ny, const double* b, const double* x0, double* x,
+                      double tol, double inner_tol, int32_t maxit, int32_t sdeg,
+                      oracle_result* res);
+
+/* Exported z = M^-1 r in binary32 (cheb_apply_f32) for the tests. */
+int oracle_cheb_apply_f32(int32_t nx, int32_t ny, int32_t sdeg, const float* r, float* z) {
+  if (nx < 1 || ny < 1 || sdeg < 1 || sdeg > 64 || !r || !z) return OR_E_INVALID;
+  double c0, c1[64], c2[64];
+  float c1f[64], c2f[64];
+  oracle_cheb_coeffs(nx, ny, sdeg, &c0, c1, c2);
+  for (int32_t k = 0; k + 1 < sdeg; ++k) {
+    c1f[k] = (float)c1[k];
+    c2f[k] = (float)c2[k];
+  }
+  csr_t A;
+  int rc = csr_build(&A, nx, ny, 0, 1);
+  if (rc) return rc;
+  const int64_t n = A.n;
+  float* w = (float*)malloc((size_t)n * 3 * sizeof(float));
+  if (!w) {
+    csr_free(&A);
+    return OR_E_NOMEM;
+  }
+  cheb_apply_f32(&A, sdeg, (float)c0, c1f, c2f, r, z, w, w + n, w + 2 * n);
+  free(w);
+  csr_free(&A);
+  return OR_OK;
+}
+
 int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, double* x,
                   double tol, double inner_tol, int32_t maxit, oracle_result* res) {
+  return refine_any(nx, ny, b, x0, x, tol, inner_tol, maxit, 0, res);
+}
+
+/* Refinement whose inner solve is preconditioned classic CG in binary32 with
+ * M^-1 = p_s(A) (the Chebyshev preconditioner of oracle_pcg, its recurrence in
+ * binary32): z = M^-1 ri, rho = (ri, z) in binary64, p = z + beta p, alpha =
+ * rho / (p, A p) and beta = rho / rho_old computed in binary64 and rounded to
+ * binary32 once; the inner stop test stays on (ri, ri). */
+int oracle_refine_pc(int32_t nx, int32_t ny, const double* b, const double* x0, double* x,
+                     double tol, double inner_tol, int32_t maxit, int32_t sdeg,
+                     oracle_result* res) {
+  if (sdeg < 1 || sdeg > 64) return OR_E_INVALID;
+  return refine_any(nx, ny, b, x0, x, tol, inner_tol, maxit, sdeg, res);
+}
+
+static int refine_any(int32_t nx, int32_t ny, const double* b, const double* x0, double* x,
+                      double tol, double inner_tol, int32_t maxit, int32_t sdeg,
+                      oracle_result* res) {
   if (nx < 1 || ny < 1 || !b || !x || !res || maxit < 1 || !(tol >= 0.0) || tol >= 1.0 ||
       !(inner_tol > 0.0) || inner_tol >= 1.0)
     return OR_E_INVALID;
@@ -1151,12 +1220,24 @@ int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, dou
   inner_t* d = (inner_t*)malloc((size_t)n * sizeof(inner_t));
   inner_t* p = (inner_t*)malloc((size_t)n * sizeof(inner_t));
   inner_t* s = (inner_t*)malloc((size_t)n * sizeof(inner_t));
+  /* preconditioned: z and the Chebyshev recurrence's work vectors */
+  float* zc = sdeg ? (float*)malloc((size_t)n * 4 * sizeof(float)) : NULL;
+  float c0f = 0.0f, c1f[64], c2f[64];
+  if (sdeg) {
+    double c0, c1[64], c2[64];
+    oracle_cheb_coeffs(nx, ny, sdeg, &c0, c1, c2);
+    c0f = (float)c0;
+    for (int32_t k = 0; k + 1 < sdeg; ++k) {
+      c1f[k] = (float)c1[k];
+      c2f[k] = (float)c2[k];
+    }
+  }
   memset(res, 0, sizeof(*res));
   int st = OR_OK;
   int32_t total = 0, outer = 0;
   const double bb = dot_sequential(n, b, b);
   double g = 0.0;
-  if (!r || !ri || !d || !p || !s) { st = OR_E_NOMEM; goto out; }
+  if (!r || !ri || !d || !p || !s || (sdeg && !zc)) { st = OR_E_NOMEM; goto out; }
   if (bb == 0.0) {
     memset(x, 0, (size_t)n * sizeof(double));
     goto out;
@@ -1184,7 +1265,36 @@ int oracle_refine(int32_t nx, int32_t ny, const double* b, const double* x0, dou
     const double eff = fmax(inner_tol, (0.5 * tol) * (sqrt(bb) / sc));
     const double thr_in = (eff * eff) * gamma;
     int32_t kin = 0;
-    while (!(gamma <= thr_in) && total < maxit) {
+#if ORACLE_MUTANT != 1
+    if (sdeg) {
+      /* preconditioned classic CG in binary32, the loop of oracle_pcg */
+      float* z = zc;
+      double rho = 0.0, rho_old = 0.0;
+      while (!(gamma <= thr_in) && total < maxit) {
+        cheb_apply_f32(&A, sdeg, c0f, c1f, c2f, ri, z, zc + n, zc + 2 * n, zc + 3 * n);
+        rho = dot_f32_in_f64(n, ri, z);
+        if (!(rho > 0.0) || !isfinite(rho)) break;
+        if (kin == 0) {
+          for (int64_t k = 0; k < n; ++k) p[k] = z[k];
+        } else {
+          const float bf = (float)(rho / rho_old);
+          for (int64_t k = 0; k < n; ++k) p[k] = z[k] + bf * p[k];
+        }
+        spmv_f32(&A, p, s);
+        const double pi = dot_f32_in_f64(n, p, s);
+        if (!(pi > 0.0) || !isfinite(pi)) break;
+        const float af = (float)(rho / pi);
+        for (int64_t k = 0; k < n; ++k) {
+          d[k] = d[k] + af * p[k];
+          ri[k] = ri[k] - af * s[k];
+        }
+        gamma = dot_f32_in_f64(n, ri, ri);
+        rho_old = rho;
+        ++kin; ++total;
+      }
+    }
+#endif
+    while (!sdeg && !(gamma <= thr_in) && total < maxit) {
       spmv_inner(&A, p, s);
       double pi = dot_f32_in_f64(n, p, s);
       if (!(pi > 0.0) || !isfinite(pi)) break;
@@ -1209,7 +1319,7 @@ out:
   res->status = st;
   res->iterations = total;
   res->outer_iterations = outer;
-  free(r); free(ri); free(d); free(p); free(s);
+  free(r); free(ri); free(d); free(p); free(s); free(zc);
   csr_free(&A);
   return st;
 }

@@ -99,6 +99,11 @@ def _load():
     lib.oracle_refine.restype = C.c_int
     lib.oracle_refine.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
                                   C.c_int32, C.POINTER(_Result)]
+    lib.oracle_cheb_apply_f32.restype = C.c_int
+    lib.oracle_cheb_apply_f32.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P]
+    lib.oracle_refine_pc.restype = C.c_int
+    lib.oracle_refine_pc.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int32, C.POINTER(_Result)]
     lib.oracle_csr3_nnz.restype = C.c_int64
     lib.oracle_csr3_nnz.argtypes = [C.c_int32, C.c_int32, C.c_int32]
     lib.oracle_csr3_assemble.restype = C.c_int64
@@ -372,6 +377,16 @@ def cheb_apply(r, nx, ny, s, mode=MODE_SEQUENTIAL):
     return z
 
 
+def cheb_apply_f32(r, nx, ny, s):
+    """z = M^-1 r in binary32 (r rounded to binary32 first)."""
+    r32 = np.ascontiguousarray(np.asarray(r, dtype=np.float32).reshape(ny, nx))
+    z = np.zeros_like(r32)
+    rc = _load().oracle_cheb_apply_f32(nx, ny, s, r32.ctypes.data, z.ctypes.data)
+    if rc:
+        raise ValueError("oracle_cheb_apply_f32 rejected the call: %d" % rc)
+    return z
+
+
 def pcg(b, nx, ny, s, tol=1e-8, maxit=2000, x0=None, mode=MODE_SEQUENTIAL, order=None,
         order_rho=None, variant=VARIANT_CLASSIC):
     """CG preconditioned by the s-step Chebyshev polynomial in A: classic
@@ -393,14 +408,20 @@ def pcg(b, nx, ny, s, tol=1e-8, maxit=2000, x0=None, mode=MODE_SEQUENTIAL, order
                      rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
 
 
-def refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, maxit=200000, x0=None):
-    """FP32-inner / FP64-outer iterative refinement (see oracle_refine)."""
+def refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, maxit=200000, x0=None, precond=0):
+    """FP32-inner / FP64-outer iterative refinement (see oracle_refine); precond
+    = s > 0: the inner solve preconditioned by s Chebyshev steps in binary32
+    (oracle_refine_pc)."""
     b = _vec(b, nx, ny)
     x0a = _vec(x0, nx, ny) if x0 is not None else None
     x = np.zeros_like(b)
     res = _Result()
-    rc = _load().oracle_refine(nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, inner_tol, maxit,
-                               C.byref(res))
+    if precond:
+        rc = _load().oracle_refine_pc(nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, inner_tol,
+                                      maxit, precond, C.byref(res))
+    else:
+        rc = _load().oracle_refine(nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, inner_tol, maxit,
+                                   C.byref(res))
     if rc < 0:
         raise ValueError("oracle_refine rejected the call: %d" % rc)
     return x, Result(status=res.status, iterations=res.iterations,

@@ -331,3 +331,64 @@ def test_pipelined_single_mode_and_edge_cases():
     assert np.linalg.norm(xp - xc) <= 1e-9 * np.linalg.norm(xc)
     with pytest.raises(ValueError):
         oracle.pcg(b, nx, ny, 4, variant=2)
+
+
+# ------------------------ refinement with a preconditioned binary32 inner solve --
+
+@pytest.mark.parametrize("s", [2, 3, 5, 8])
+def test_binary32_chebyshev_on_eigenvectors(s):
+    """z = M^-1 phi in binary32 equals p_s(lambda) phi to binary32 accuracy
+    (the recurrence's cancellation on the highest modes costs up to about 1e-5
+    relative at s = 8; a wrong coefficient, sign or step costs O(1))."""
+    nx, ny = 24, 17
+    for a, b in ((1, 1), (5, 9), (24, 17), (12, 3)):
+        i = np.arange(nx)[None, :]
+        j = np.arange(ny)[:, None]
+        phi = np.sin(a * np.pi * (i + 1) / (nx + 1)) * np.sin(b * np.pi * (j + 1) / (ny + 1))
+        lam = 4 - 2 * math.cos(a * math.pi / (nx + 1)) - 2 * math.cos(b * math.pi / (ny + 1))
+        phi32 = phi.astype(np.float32)
+        z = oracle.cheb_apply_f32(phi32, nx, ny, s).astype(np.float64)
+        want = p_closed(s, lam, nx, ny) * phi32.astype(np.float64)
+        assert np.abs(z - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def test_binary32_chebyshev_one_step_is_one_rounding():
+    """s = 1: z = fl32(fl32(c0) r), bitwise."""
+    nx, ny = 19, 11
+    r = np.random.default_rng(2).standard_normal((ny, nx)).astype(np.float32)
+    c0, _, _ = oracle.cheb_coeffs(nx, ny, 1)
+    z = oracle.cheb_apply_f32(r, nx, ny, 1)
+    np.testing.assert_array_equal(z, np.float32(c0) * r)
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (40, 25)])
+@pytest.mark.parametrize("s", [2, 4, 8])
+def test_preconditioned_refinement_accuracy(nx, ny, s):
+    b = np.random.default_rng(nx * s).standard_normal((ny, nx))
+    tol = 1e-10
+    x, r = oracle.refine(b, nx, ny, tol=tol, inner_tol=1e-4, precond=s)
+    A = dense_A(nx, ny)
+    rt = np.linalg.norm(b.ravel() - A @ x.ravel()) / np.linalg.norm(b)
+    assert r.status == oracle.OR_OK and rt <= tol and r.outer_iterations >= 2
+    xc = sla.cho_solve(sla.cho_factor(A), b.ravel())
+    w = np.linalg.eigvalsh(A)
+    assert np.linalg.norm(x.ravel() - xc) / np.linalg.norm(xc) <= 2 * tol * w[-1] / w[0]
+
+
+def test_preconditioned_refinement_takes_fewer_inner_iterations():
+    """128^2, tol 1e-10: the preconditioned inner solves take 0.55 / 0.3 / 0.16
+    of the plain ones' iterations at s = 2 / 4 / 8 (the FP64 preconditioned CG
+    ratios), with the same number of outer steps."""
+    n = 128
+    b = np.random.default_rng(3).standard_normal((n, n))
+    x0, r0 = oracle.refine(b, n, n, tol=1e-10, inner_tol=1e-4)
+    for s, ratio in ((2, 0.55), (4, 0.3), (8, 0.16)):
+        x, r = oracle.refine(b, n, n, tol=1e-10, inner_tol=1e-4, precond=s)
+        assert r.status == oracle.OR_OK and r.outer_iterations <= r0.outer_iterations + 1
+        assert r.iterations <= ratio * r0.iterations
+        assert np.linalg.norm(x - x0) <= 1e-8 * np.linalg.norm(x0)
+
+
+def test_preconditioned_refinement_rejects():
+    with pytest.raises(ValueError):
+        oracle.refine(np.ones((4, 4)), 4, 4, precond=65)
