@@ -795,64 +795,93 @@ def bench_huge(args):
     b = torch.from_numpy(workloads.huge_rhs(n, n)).cuda()
     ctx = cg.Context(device=0, arena_bytes=48 * dof + (1 << 30))
     out = {}
-    xr = torch.zeros_like(b)
-    p = cg.make_problem(b, xr, n, n, tol=w["tol"], maxit=w["maxit"],
-                        precision=cg.CG_PREC_FP32_REFINED, inner_tol=w["inner_tol"])
-    ctx.cg_set_profiling(True)
-    ctx.cg_kernel_stats(reset=True)
-    t = time.perf_counter()
-    rc, r = ctx.cg_solve(p)
-    tr = time.perf_counter() - t
-    out["refined"] = dict(status=cg.cg_status_str(rc), seconds=round(tr, 3),
-                          outer=r.outer_iterations, inner=r.iterations,
-                          rel_res_true=r.rel_res_true,
-                          kernels=kern_table(ctx.cg_kernel_stats(reset=True)))
-    log("refined", json.dumps(out["refined"]))
-    x64 = torch.zeros_like(b)
-    p = cg.make_problem(b, x64, n, n, tol=w["tol"], maxit=w["maxit"], variant=0)
-    t = time.perf_counter()
-    rc, r = ctx.cg_solve(p)
-    t64 = time.perf_counter() - t
-    out["fp64_classic"] = dict(status=cg.cg_status_str(rc), seconds=round(t64, 3),
-                               iterations=r.iterations, rel_res_true=r.rel_res_true,
-                               kernels=kern_table(ctx.cg_kernel_stats(reset=True)))
-    log("fp64", json.dumps(out["fp64_classic"]))
-    if args.huge_precond:
-        # the same solve by classic CG preconditioned with s Chebyshev steps
-        xp = torch.zeros_like(b)
-        p = cg.make_problem(b, xp, n, n, tol=w["tol"], maxit=w["maxit"], variant=0,
-                            precond=args.huge_precond)
+
+    def solve(x, **kw):
+        """Timed without profiling (the library replays its graph chunks), then
+        the kernel table from a profiled run of at most 400 iterations (one pass
+        per launch, bracketed by events)."""
+        p = cg.make_problem(b, x, n, n, tol=w["tol"], maxit=w["maxit"], **kw)
         t = time.perf_counter()
         rc, r = ctx.cg_solve(p)
-        tp = time.perf_counter() - t
-        out["fp64_pcg_s%d" % args.huge_precond] = dict(
+        dt = time.perf_counter() - t
+        xs = torch.zeros_like(b)
+        ps = cg.make_problem(b, xs, n, n, tol=w["tol"], maxit=400, **kw)
+        ctx.cg_set_profiling(True)
+        ctx.cg_kernel_stats(reset=True)
+        ctx.cg_solve(ps)
+        kt = kern_table(ctx.cg_kernel_stats(reset=True))
+        ctx.cg_set_profiling(False)
+        del xs
+        return rc, r, dt, kt
+
+    xr = torch.zeros_like(b)
+    rc, r, tr, kt = solve(xr, precision=cg.CG_PREC_FP32_REFINED, inner_tol=w["inner_tol"])
+    out["refined"] = dict(status=cg.cg_status_str(rc), seconds=round(tr, 3),
+                          outer=r.outer_iterations, inner=r.iterations,
+                          rel_res_true=r.rel_res_true, kernels=kt)
+    log("refined", json.dumps(out["refined"]))
+    x64 = torch.zeros_like(b)
+    rc, r, t64, kt = solve(x64, variant=0)
+    out["fp64_classic"] = dict(status=cg.cg_status_str(rc), seconds=round(t64, 3),
+                               iterations=r.iterations, rel_res_true=r.rel_res_true, kernels=kt)
+    log("fp64", json.dumps(out["fp64_classic"]))
+    if args.huge_precond:
+        s_ = args.huge_precond
+        # the same solve by classic CG preconditioned with s Chebyshev steps
+        xp = torch.zeros_like(b)
+        rc, r, tp, kt = solve(xp, variant=0, precond=s_)
+        out["fp64_pcg_s%d" % s_] = dict(
             status=cg.cg_status_str(rc), seconds=round(tp, 3), iterations=r.iterations,
             rel_res_true=r.rel_res_true,
-            rel_err_vs_fp64_classic=((xp - x64).norm() / x64.norm()).item(),
-            kernels=kern_table(ctx.cg_kernel_stats(reset=True)))
-        log("fp64 pcg", json.dumps(out["fp64_pcg_s%d" % args.huge_precond]))
-        del xp
-    ctx.cg_set_profiling(False)
+            rel_err_vs_fp64_classic=((xp - x64).norm() / x64.norm()).item(), kernels=kt)
+        log("fp64 pcg", json.dumps(out["fp64_pcg_s%d" % s_]))
+        # and by the refinement whose FP32 inner solve carries the same
+        # preconditioner (binary32 Chebyshev steps)
+        xq = torch.zeros_like(b)
+        tols = [float(v) for v in str(args.huge_pc_inner_tol).split(",")]
+        itol = tols[0]
+        rc, r, tq, kt = solve(xq, precision=cg.CG_PREC_FP32_REFINED, inner_tol=itol, precond=s_)
+        out["refined_pcg_s%d" % s_] = dict(
+            status=cg.cg_status_str(rc), seconds=round(tq, 3), inner_tol=itol,
+            outer=r.outer_iterations, inner=r.iterations, rel_res_true=r.rel_res_true,
+            rel_err_vs_fp64_classic=((xq - x64).norm() / x64.norm()).item(),
+            speedup_vs_fp64_pcg=round(tp / tq, 3), kernels=kt)
+        log("refined pcg", json.dumps(out["refined_pcg_s%d" % s_]))
+        # further inner tolerances (timed only)
+        sweep = []
+        for itol2 in tols[1:]:
+            xq.zero_()
+            p = cg.make_problem(b, xq, n, n, tol=w["tol"], maxit=w["maxit"],
+                                precision=cg.CG_PREC_FP32_REFINED, inner_tol=itol2, precond=s_)
+            t = time.perf_counter()
+            rc, r = ctx.cg_solve(p)
+            sweep.append(dict(inner_tol=itol2, status=cg.cg_status_str(rc),
+                              seconds=round(time.perf_counter() - t, 3),
+                              outer=r.outer_iterations, inner=r.iterations,
+                              rel_res_true=r.rel_res_true))
+            log("refined pcg sweep", json.dumps(sweep[-1]))
+        if sweep:
+            out["refined_pcg_s%d_inner_tol_sweep" % s_] = sweep
+        del xp, xq
     err = ((xr - x64).norm() / x64.norm()).item()
     kappa = (4 - 4 * math.cos(n * math.pi / (n + 1))) / (4 - 4 * math.cos(math.pi / (n + 1)))
     cpu = None
     if not args.no_cpu:
-        import oracle
         bh = b.cpu().numpy()
         k = 3
-        t = time.perf_counter()
-        oracle.cg(bh, n, n, variant=0, tol=0.0, maxit=k)
-        ct = time.perf_counter() - t
-        cpu = {"value": round(dof * k / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "%d classic iterations at %dx%d (%.1f s incl. CSR assembly); a full "
-                         "solve is extrapolated, not run" % (k, n, n, ct),
+        v1, t1, _ = cpu_rate(bh, n, (0,), k, False)
+        cpu = {"value": round(v1, 5), "unit": "GDOF-iter/s", "cores": 1, "kind": "oracle",
+               "sample": "%d classic iterations at %dx%d, one thread, timed without the CSR "
+                         "assembly (%.1f s); a full solve is extrapolated, not run" % (k, n, n, t1),
+               "host": host_info(),
                "extrapolated_fp64_solve_s": round(dof * out["fp64_classic"]["iterations"] /
-                                                  (dof * k / ct), 0)}
+                                                  (v1 * 1e9), 0)}
     emit({"metric": "8192^2 time to solution, FP32-refined vs FP64 CG (true rel. res 1e-10)",
           "workload": "huge",
           "config": {"workload": "%dx%d, b~N(0,1) seeded, x0=0, outer tol 1e-10 (true FP64 "
-                                 "residual), inner tol 1e-4" % (n, n)},
+                                 "residual), inner tol %g (preconditioned refinement %g)"
+                                 % (n, n, w["inner_tol"],
+                                    float(str(args.huge_pc_inner_tol).split(",")[0]))},
           "results": out, "speedup_refined_vs_fp64": round(t64 / tr, 3),
           "error_refined_vs_fp64": err, "a_priori_bound_2_tol_kappa": 2 * w["tol"] * kappa,
           "cpu_baseline": cpu})
@@ -1178,6 +1207,9 @@ def main():
                     help="--workload vc: residual replacement period of the pipelined tol run")
     ap.add_argument("--fixed-only", action="store_true",
                     help="--workload cube / vc: only the fixed-iteration runs (no tol solves)")
+    ap.add_argument("--huge-pc-inner-tol", default="1e-5",
+                    help="huge: inner tolerance of the preconditioned refinement (a comma "
+                         "list: the first is reported in full, the others timed)")
     ap.add_argument("--huge-precond", type=int, default=8,
                     help="--workload huge: also solve with s Chebyshev steps (0: skip)")
     ap.add_argument("--steps-list", type=int, nargs="*", default=[2, 4, 6, 8],

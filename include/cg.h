@@ -117,8 +117,14 @@ typedef struct {
                               literature Section I builds on): classic CG with
                               z = M^-1 r, or the preconditioned pipelined CG of
                               Ghysels and Vanroose (variant PIPELINED); the stop
-                              test stays on ||r||; FP64; alone, in batches and
-                              served                                               */
+                              test stays on ||r||; FP64 alone, in batches and
+                              served.  With CG_PREC_FP32_REFINED (cg_solve only;
+                              batches and serving: CG_E_INVALID): the inner solve
+                              of the refinement becomes classic CG preconditioned
+                              by the same M^-1 in binary32 (coefficients rounded
+                              once; (r,z) and (p,Ap) summed in binary64, alpha and
+                              beta rounded to binary32 once; the inner stop test on
+                              (r,r)), for either variant                           */
   int32_t nz;              /* 0 or 1: the 2D problem above.  nz > 1: the 3D 7-point
                               Laplacian (centre 6, the six face neighbours -1) on an
                               nx x ny x nz interior grid with zero Dirichlet
@@ -228,7 +234,9 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
  * Solves are admitted in order while their footprint fits the arena and a
  * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
  * worst per-solve status; results[i] holds each outcome.  A breakdown of one
- * solve does not disturb the others. */
+ * solve does not disturb the others.  3D, variable-coefficient and residual-
+ * replacement problems and the preconditioned refinement are CG_E_INVALID
+ * here (cg_solve takes them). */
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
 
 /* Serving: queue one request (non-blocking).  A scheduler thread admits
@@ -238,7 +246,8 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
  * The request's b and x0 are read only once the caller's stream
  * (cg_config.stream) has passed the point of this call; x is written before
  * cg_poll returns the final status.  CG_E_NOMEM if its footprint exceeds
- * arena_bytes; CG_E_DEVICE if the ordering event cannot be recorded. */
+ * arena_bytes; CG_E_DEVICE if the ordering event cannot be recorded;
+ * CG_E_INVALID for the problems cg_solve_batch rejects. */
 int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket);
 /* CG_PENDING, or the final status (then *res is filled and the ticket is
  * released). */

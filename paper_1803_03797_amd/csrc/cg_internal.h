@@ -115,6 +115,9 @@ enum : int32_t {
                   // (stop test, alpha, beta from the three slots); no slots
   K_PPCG,         // preconditioned pipelined fused iteration (n = A m and the eight
                   // updates); slots (r,u), (w,u), (r,r)
+  K_CHEBF,        // refinement, preconditioned inner solve: z = p_s(A) r in FP32
+                  // after the inner stop test on (r,r); slot (r,z) in the tiles
+                  // of K_CHEB
   K_NKINDS
 };
 
@@ -146,6 +149,7 @@ struct PassArgs {
   const double* pc_prev;   //          pass 2: the direction before pc_in
   float* rf;               // refinement: inner residual rho / r_in
   float* df;               //             inner solution d
+  float* zf;               //             preconditioned: z = M^-1 r_in
   const float* pf_in;      //             inner direction ping-pong
   float* pf_out;
   const float* pf_prev;    //             pass 2: the direction before pf_in
@@ -271,9 +275,10 @@ hipError_t launch_solve_fixed_many(const Slot* slots, const int* idx, int n, int
 // `rounds` 32 x 32 -> 64-bit multiply-adds; writes grid * 256 words to sink.
 hipError_t launch_mul_probe(uint64_t* sink, int grid, int rounds, hipStream_t s);
 int pass_max_blocks_per_cu(int kind, int fp32_geometry);
-// Work-groups of the Chebyshev pass with s steps that fit one CU; the pass
-// runs 512-thread work-groups, grid a multiple of 8.
-int cheb_max_blocks_per_cu(int s);
+// Work-groups of the Chebyshev pass with s steps that fit one CU (f32: the
+// binary32 pass of the refinement); the pass runs 512-thread work-groups,
+// grid a multiple of 8.
+int cheb_max_blocks_per_cu(int s, bool f32 = false);
 constexpr int kChebGroupCols = 896;  // columns of one Chebyshev item (7 tiles)
 // Step *step_base + k of every resident solve: work-groups stride over the
 // *n_items items; grid is any positive size.  The base step is read on the

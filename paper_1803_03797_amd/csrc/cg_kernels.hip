@@ -26,6 +26,9 @@
 // the library is built with -ffp-contract=off so nothing else is fused.
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "cg_internal.h"
 
 namespace cgk {
@@ -480,8 +483,41 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     s.kin = 0;
     sc.inv = 1.0 / s.scale;
     return true;
+  } else if constexpr (KIND == K_CHEBF) {
+    // Preconditioned inner solve: the inner stop test on gamma = (r, r) of
+    // the inner residual (the scale pass or pass 2 before this one), before
+    // z = M^-1 r is formed; the threshold as in the unpreconditioned one.
+    if (s.status != ST_RUNNING) return false;
+    const double gamma = sum[0];
+    if (s.kin == 0) {
+      const double e = fmax(s.inner_tol, (0.5 * s.tol) * (sqrt(s.bb) / s.scale));
+      s.gamma0 = gamma;
+      s.thr_in = (e * e) * gamma;
+    }
+    s.gamma = gamma;
+    if (!isfinite(gamma) || gamma <= s.thr_in || s.k >= s.maxit) {
+      s.status = ST_INNER_DONE;
+      return false;
+    }
+    return true;
   } else if constexpr (KIND == K_CG1F) {
     if (s.status != ST_RUNNING) return false;
+    if (s.flags & F_PRECOND) {
+      // the one slot is rho = (r, z) from the Chebyshev pass (which made the
+      // stop test); beta = rho / rho_old with rho kept in delta, p = z + beta p
+      const double rho = sum[0];
+      if (!(rho > 0.0) || !isfinite(rho)) {
+        s.status = ST_INNER_DONE;
+        return false;
+      }
+      double be = 0.0;
+      if (s.kin == 0) sc.first = 1;
+      else be = rho / s.delta;
+      s.delta = rho;
+      s.beta = be;
+      sc.be = be;
+      return true;
+    }
     const double gamma = sum[0];
     double be = 0.0;
     if (s.kin == 0) {
@@ -495,6 +531,7 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
       be = gamma / s.gamma;
     }
     s.gamma = gamma;
+    s.delta = gamma;  // alpha's numerator for pass 2
     if (!isfinite(gamma) || gamma <= s.thr_in || s.k >= s.maxit) {
       s.status = ST_INNER_DONE;
       return false;
@@ -509,7 +546,8 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
       s.status = ST_INNER_DONE;
       return false;
     }
-    s.alpha = s.gamma / pi;
+    // delta: rho = (r, z) preconditioned, else (r, r)
+    s.alpha = s.delta / pi;
     s.k += 1;
     s.kin += 1;
     sc.al = s.alpha;
@@ -534,7 +572,7 @@ constexpr int ndots_in() {  // partial slots the prologue consumes
           KIND == K_REF_SCALE)
              ? 2
          : (KIND == K_CG2 || KIND == K_CG2X || KIND == K_CG1F || KIND == K_CG2F ||
-            KIND == K_CG2FX)
+            KIND == K_CG2FX || KIND == K_CHEBF)
              ? 1
              : 0;
 }
@@ -556,12 +594,13 @@ constexpr int ndots_out() {  // partial slots the body produces
 template <int KIND>
 constexpr bool defers_x() {
   return KIND == K_PCG || KIND == K_PCGX || KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X ||
-         KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_CHEB;
+         KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_CHEB ||
+         KIND == K_CHEBF;
 }
 
 template <int KIND>
 constexpr bool inner_kind() {
-  return KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX;
+  return KIND == K_CG1F || KIND == K_CG2F || KIND == K_CG2FX || KIND == K_CHEBF;
 }
 
 // transition<KIND> plus the deferred-x bookkeeping: sc.xu when this pass ends
@@ -576,7 +615,8 @@ __device__ __forceinline__ bool transition_x(State& s, const double* sum, Sc& sc
   flush = false;
   if constexpr (defers_x<KIND>()) {
     const int k = inner_kind<KIND>() ? s.kin : s.k;
-    if (run && KIND != K_CG1 && KIND != K_CG1F && KIND != K_CHEB && !(k & 1)) {
+    if (run && KIND != K_CG1 && KIND != K_CG1F && KIND != K_CHEB && KIND != K_CHEBF &&
+        !(k & 1)) {
       sc.xu = 1;
       sc.alp = alpha_before;
     }
@@ -1336,7 +1376,7 @@ __device__ __forceinline__ const double* flush_dir(const PassArgs& a) {
 
 template <int KIND>
 __device__ __forceinline__ const float* flush_dir_f32(const PassArgs& a) {
-  if constexpr (KIND == K_CG1F) return a.pf_in;
+  if constexpr (KIND == K_CG1F || KIND == K_CHEBF) return a.pf_in;
   else return a.pf_prev;
 }
 
@@ -1484,7 +1524,7 @@ __global__ __launch_bounds__(kGroup) void k_pass(PassArgs a) {
     if constexpr (DI > 0) {
       // classic pass 1 takes (b,b) too after the initial residual; with the
       // preconditioner its one slot is (r,z) in the Chebyshev pass's tiles
-      const bool pc = KIND == K_CG1 && (s.flags & F_PRECOND);
+      const bool pc = (KIND == K_CG1 || KIND == K_CG1F) && (s.flags & F_PRECOND);
       const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) && !pc ? 2 : 1) : DI;
       const int tin = pc ? a.cheb_tiles : a.g.tiles;
       if (s.status == ST_RUNNING) {
@@ -1575,9 +1615,14 @@ static_assert(kChebGroupTiles * 2 * kWave == kChebWaves * kChebOut, "whole tiles
 static_assert(kChebHaloCols >= kChebMaxSteps - 1, "halo too narrow for the steps");
 static_assert(kChebGroupCols == kChebWaves * kChebOut, "item width known to the host");
 
-struct D2 {
-  double v[2];
+// A lane's two columns, binary64 (the FP64 solves) or binary32 (the inner
+// solve of the refinement), and the matching vector load type.
+template <typename T>
+struct V2 {
+  T v[2];
 };
+template <typename T>
+using Pair = std::conditional_t<sizeof(T) == 8, double2, float2>;
 
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int clcm(int a, int b) { return a / cgcd(a, b) * b; }
@@ -1592,12 +1637,17 @@ __device__ __forceinline__ double dpp0(double v) {
   return __hiloint2double(hi, lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp0(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
 // One wavefront of an item: output columns [cw, cw + 112), rows [y0, y1).
 // Rows are numbered from Jb = y0 - (s - 1); every ring below is indexed by
 // the row modulo its length, and the row loop is expanded over a period that
 // all the lengths divide (one step per template instance), so the rings
 // never move in registers.
-template <int S>
+template <int S, typename T>
 struct ChebRegs {
   static constexpr int H = S - 1;            // stencil steps = halo rows
   static constexpr int L = H > 0 ? H : 1;    // y / r ring length
@@ -1608,54 +1658,55 @@ struct ChebRegs {
   // step ahead beyond, where the registers are needed for the stages
   static constexpr bool RELOAD = S >= 7;
   static constexpr int LR = RELOAD ? 1 : L;
-  D2 d[L][2];    // d_k on rows J-k-2, J-k-1 (slot (row - Jb) mod 2), levels k < H
-  D2 rk[L][2];   // r_k on row J-k-1 (same slots)
-  D2 y[L];       // y on rows J-H .. J-1 (slot (row - Jb) mod L)
-  D2 r0[LR];     // r on the same rows, for (r, z) (RELOAD: unused)
-  D2 rr[2];      // RELOAD: r on rows J-H, J-H+1 (slot (row - Jb) mod 2)
-  D2 ld[PD];     // r loaded for rows J .. J+PD-1 (slot (row - Jb) mod PD)
+  V2<T> d[L][2];    // d_k on rows J-k-2, J-k-1 (slot (row - Jb) mod 2), levels k < H
+  V2<T> rk[L][2];   // r_k on row J-k-1 (same slots)
+  V2<T> y[L];       // y on rows J-H .. J-1 (slot (row - Jb) mod L)
+  V2<T> r0[LR];     // r on the same rows, for (r, z) (RELOAD: unused)
+  V2<T> rr[2];      // RELOAD: r on rows J-H, J-H+1 (slot (row - Jb) mod 2)
+  V2<T> ld[PD];     // r loaded for rows J .. J+PD-1 (slot (row - Jb) mod PD)
   double a0, a1; // (r, z) column sums
 };
 
+template <typename T>
 struct ChebCtx {
-  const double* R;  // r + first column of the lane
-  double* Z;        // z + first column of the lane
+  const T* R;  // r + first column of the lane
+  T* Z;        // z + first column of the lane
   int pitch, ny, y0, Je;
   bool v0, v1, outl;
 };
 
-template <bool MASK>
-__device__ __forceinline__ D2 cheb_load(const ChebCtx& c, int J) {
+template <bool MASK, typename T>
+__device__ __forceinline__ V2<T> cheb_load(const ChebCtx<T>& c, int J) {
   const int jl = min(max(J, 0), c.ny - 1);
-  const double2 t = *reinterpret_cast<const double2*>(c.R + (size_t)jl * c.pitch);
-  D2 o;
+  const Pair<T> t = *reinterpret_cast<const Pair<T>*>(c.R + (size_t)jl * c.pitch);
+  V2<T> o;
   o.v[0] = t.x;
   o.v[1] = t.y;
   if constexpr (MASK) {
     const bool rv = J >= 0 && J < c.ny;
-    o.v[0] = (rv && c.v0) ? o.v[0] : 0.0;
-    o.v[1] = (rv && c.v1) ? o.v[1] : 0.0;
+    o.v[0] = (rv && c.v0) ? o.v[0] : T(0);
+    o.v[1] = (rv && c.v1) ? o.v[1] : T(0);
   }
   return o;
 }
 
 // Step J = J0 + Q of the march; false once the item's rows are exhausted.
-template <int S, bool MASK, int Q>
-__device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, const double* c2,
-                                          double c0, ChebRegs<S>& g, int J0) {
-  using G = ChebRegs<S>;
+template <int S, bool MASK, int Q, typename T>
+__device__ __forceinline__ bool cheb_step(const ChebCtx<T>& c, const T* c1, const T* c2, T c0,
+                                          ChebRegs<S, T>& g, int J0) {
+  using G = ChebRegs<S, T>;
   constexpr int H = G::H, L = G::L, PD = G::PD;
   const int J = J0 + Q;
   if (J >= c.Je) return false;
-  const D2 rin = g.ld[Q % PD];
+  const V2<T> rin = g.ld[Q % PD];
   g.ld[Q % PD] = cheb_load<MASK>(c, J + PD);
-  D2 rrow;
+  V2<T> rrow;
   if constexpr (G::RELOAD) {
     rrow = g.rr[cmod(Q - H, 2)];
     g.rr[cmod(Q - H + 1, 2)] = cheb_load<MASK>(c, J - H + 1);
   }
   // stage 0: d_0 = c0 r, y = d_0 on row J (zero outside the grid already)
-  D2 dn, rn = rin, ynew;
+  V2<T> dn, rn = rin, ynew;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     dn.v[e] = rin.v[e] * c0;
@@ -1666,24 +1717,24 @@ __device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, co
     // stage k on row J - k from level k-1: rows J-k-1 (slot so), J-k
     // (slot sc) and J-k+1 (dn, this step)
     const int so = cmod(Q - (k - 1), 2), sc = so ^ 1;
-    const D2 C = g.d[k - 1][sc], Sv = g.d[k - 1][so], Nv = dn;
-    const double w0 = dpp0<kDppWaveShr1>(C.v[1]);
-    const double e1 = dpp0<kDppWaveShl1>(C.v[0]);
-    const double W[2] = {w0, C.v[0]}, E[2] = {C.v[1], e1};
-    D2 dk, rk;
+    const V2<T> C = g.d[k - 1][sc], Sv = g.d[k - 1][so], Nv = dn;
+    const T w0 = dpp0<kDppWaveShr1>(C.v[1]);
+    const T e1 = dpp0<kDppWaveShl1>(C.v[0]);
+    const T W[2] = {w0, C.v[0]}, E[2] = {C.v[1], e1};
+    V2<T> dk, rk;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const double t = st5(C.v[e], W[e], E[e], Sv.v[e], Nv.v[e]);
+      const T t = st5(C.v[e], W[e], E[e], Sv.v[e], Nv.v[e]);
       rk.v[e] = g.rk[k - 1][sc].v[e] - t;
       dk.v[e] = fma(c1[k - 1], C.v[e], c2[k - 1] * rk.v[e]);
     }
     if constexpr (MASK) {
       const int j = J - k;
       const bool rv = j >= 0 && j < c.ny;
-      dk.v[0] = (rv && c.v0) ? dk.v[0] : 0.0;
-      dk.v[1] = (rv && c.v1) ? dk.v[1] : 0.0;
+      dk.v[0] = (rv && c.v0) ? dk.v[0] : T(0);
+      dk.v[1] = (rv && c.v1) ? dk.v[1] : T(0);
     }
-    D2& yk = g.y[cmod(Q - k, L)];
+    V2<T>& yk = g.y[cmod(Q - k, L)];
 #pragma unroll
     for (int e = 0; e < 2; ++e) yk.v[e] = yk.v[e] + dk.v[e];
     // level k-1's row J-k+1 replaces its row J-k-1 (used just now)
@@ -1694,14 +1745,18 @@ __device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, co
   }
   // row J - H of z is complete (slot Q mod L, which row J takes next)
   constexpr int os = Q % L;
-  const D2 zrow = H > 0 ? g.y[os] : ynew;
+  const V2<T> zrow = H > 0 ? g.y[os] : ynew;
   if constexpr (!G::RELOAD) rrow = H > 0 ? g.r0[os] : rin;
   if (J >= c.y0 + H) {
-    if (c.outl)
-      *reinterpret_cast<double2*>(c.Z + (size_t)(J - H) * c.pitch) =
-          make_double2(zrow.v[0], zrow.v[1]);
-    g.a0 = fma(rrow.v[0], zrow.v[0], g.a0);
-    g.a1 = fma(rrow.v[1], zrow.v[1], g.a1);
+    if (c.outl) {
+      Pair<T> o;
+      o.x = zrow.v[0];
+      o.y = zrow.v[1];
+      *reinterpret_cast<Pair<T>*>(c.Z + (size_t)(J - H) * c.pitch) = o;
+    }
+    // (r, z) in binary64 for both element types
+    g.a0 = fma((double)rrow.v[0], (double)zrow.v[0], g.a0);
+    g.a1 = fma((double)rrow.v[1], (double)zrow.v[1], g.a1);
   }
   if constexpr (H > 0) {
     g.y[os] = ynew;
@@ -1710,31 +1765,34 @@ __device__ __forceinline__ bool cheb_step(const ChebCtx& c, const double* c1, co
   return true;
 }
 
-template <int S, bool MASK, int... Qs>
-__device__ __forceinline__ bool cheb_period(const ChebCtx& c, const double* c1, const double* c2,
-                                            double c0, ChebRegs<S>& g, int J0,
+template <int S, bool MASK, typename T, int... Qs>
+__device__ __forceinline__ bool cheb_period(const ChebCtx<T>& c, const T* c1, const T* c2, T c0,
+                                            ChebRegs<S, T>& g, int J0,
                                             std::integer_sequence<int, Qs...>) {
   return (cheb_step<S, MASK, Qs>(c, c1, c2, c0, g, J0) && ...);
 }
 
-// acc0/acc1 receive the (r, z) column sums of the lane's two columns.
-template <int S, bool MASK>
-__device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, int y1,
-                                           double& acc0, double& acc1) {
-  using G = ChebRegs<S>;
+// R is the input vector, Z the output; ntx the 128-column tiles across the
+// padded row.  acc0/acc1 receive the (r, z) column sums of the lane's two
+// columns.
+template <int S, bool MASK, typename T>
+__device__ __forceinline__ void cheb_march(const PassArgs& a, const T* R, T* Z, int ntx, int cw,
+                                           int y0, int y1, double& acc0, double& acc1) {
+  using G = ChebRegs<S, T>;
   constexpr int H = G::H, L = G::L, PD = G::PD, P = G::P;
   const Geo& gg = a.g;
   const int lane = threadIdx.x & (kWave - 1);
   const int cl = cw - kChebHaloCols + 2 * lane;
-  // the coefficients are uniform: scalar registers
-  const double c0 = uniform(a.cheb[0]);
-  double c1[L], c2[L];
+  // the coefficients are uniform: scalar registers (binary32: each rounded
+  // once from the binary64 coefficient)
+  const T c0 = T(uniform(a.cheb[0]));
+  T c1[L], c2[L];
 #pragma unroll
   for (int k = 0; k < H; ++k) {
-    c1[k] = uniform(a.cheb[1 + k]);
-    c2[k] = uniform(a.cheb[S + k]);
+    c1[k] = T(uniform(a.cheb[1 + k]));
+    c2[k] = T(uniform(a.cheb[S + k]));
   }
-  ChebCtx c;
+  ChebCtx<T> c;
   // columns: the load address is valid for 0 <= cl < the padded row length
   // (a multiple of 128; cl is even, so the pair stays in the row)
   c.v0 = c.v1 = true;
@@ -1742,10 +1800,10 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
   if constexpr (MASK) {
     c.v0 = cl >= 0 && cl < gg.nx;
     c.v1 = cl >= 0 && cl + 1 < gg.nx;
-    lc = (cl >= 0 && cl < gg.ntx * 2 * kWave) ? cl : 0;
+    lc = (cl >= 0 && cl < ntx * 2 * kWave) ? cl : 0;
   }
-  c.R = a.r + lc;
-  c.Z = a.z + cl;
+  c.R = R + lc;
+  c.Z = Z + cl;
   c.pitch = gg.pitch;
   c.ny = gg.ny;
   c.y0 = y0;
@@ -1756,11 +1814,11 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
   for (int k = 0; k < L; ++k)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      g.d[k][0].v[e] = g.d[k][1].v[e] = g.rk[k][0].v[e] = g.rk[k][1].v[e] = 0.0;
-      g.y[k].v[e] = 0.0;
+      g.d[k][0].v[e] = g.d[k][1].v[e] = g.rk[k][0].v[e] = g.rk[k][1].v[e] = T(0);
+      g.y[k].v[e] = T(0);
     }
 #pragma unroll
-  for (int k = 0; k < G::LR; ++k) g.r0[k].v[0] = g.r0[k].v[1] = 0.0;
+  for (int k = 0; k < G::LR; ++k) g.r0[k].v[0] = g.r0[k].v[1] = T(0);
   g.rr[0] = g.rr[1] = g.r0[0];
   g.a0 = g.a1 = 0.0;
   const int Jb = y0 - H;
@@ -1772,13 +1830,31 @@ __device__ __forceinline__ void cheb_march(const PassArgs& a, int cw, int y0, in
   acc1 = g.a1;
 }
 
+// Chebyshev tiles (128 columns) across the padded row: the FP64 tile passes'
+// tiles are 128 columns wide, the FP32 ones (4 columns per lane) 256.
+template <typename T>
+__device__ __forceinline__ int cheb_ntx(const Geo& g) {
+  return sizeof(T) == 8 ? g.ntx : 2 * g.ntx;
+}
+
 // Chebyshev item `it` (ngx items across): each wavefront marches its 112
 // output columns over the item's rows; without PIPE the (r, z) column sums
 // become one partial per 128-column tile (wavefront m folds tile m).
-// `colacc` holds kChebWaves * kChebOut doubles.
-template <int S, bool PIPE>
+// `colacc` holds kChebWaves * kChebOut doubles.  FP64: a.r -> a.z; FP32 (the
+// refinement's inner solve): a.rf -> a.zf.
+template <int S, bool PIPE, typename T = double>
 __device__ __forceinline__ void cheb_item(const PassArgs& a, int it, int ngx, double* colacc) {
   const Geo& g = a.g;
+  const int ntx = cheb_ntx<T>(g);
+  const T* R;
+  T* Z;
+  if constexpr (sizeof(T) == 8) {
+    R = a.r;
+    Z = a.z;
+  } else {
+    R = a.rf;
+    Z = a.zf;
+  }
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
   const int Hc = a.cheb_rows;
   const int gx = it % ngx, ty = it / ngx;
@@ -1788,8 +1864,8 @@ __device__ __forceinline__ void cheb_item(const PassArgs& a, int it, int ngx, do
   if (cw < g.nx) {
     const bool inner = cw >= kChebHaloCols && cw + kChebOut + kChebHaloCols <= g.nx &&
                        y0 >= S - 1 && y1 + (S - 1) <= g.ny;
-    if (inner) cheb_march<S, false>(a, cw, y0, y1, acc0, acc1);
-    else cheb_march<S, true>(a, cw, y0, y1, acc0, acc1);
+    if (inner) cheb_march<S, false>(a, R, Z, ntx, cw, y0, y1, acc0, acc1);
+    else cheb_march<S, true>(a, R, Z, ntx, cw, y0, y1, acc0, acc1);
   }
   // PIPE: no partials, the fused pass sums its dots.  The column sums are
   // still formed: without them the compiler schedules the march of s = 8
@@ -1803,10 +1879,10 @@ __device__ __forceinline__ void cheb_item(const PassArgs& a, int it, int ngx, do
   __syncthreads();
   if (!PIPE && wave < kChebGroupTiles) {
     const int tx = gx * kChebGroupTiles + wave;
-    if (tx < g.ntx) {
+    if (tx < ntx) {
       const double* c = colacc + wave * 2 * kWave + 2 * lane;
       const double v = wave_sum(c[0] + c[1]);
-      if (lane == 0) a.part_out[(size_t)ty * g.ntx + tx] = v;
+      if (lane == 0) a.part_out[(size_t)ty * ntx + tx] = v;
     }
   }
   __syncthreads();
@@ -1857,6 +1933,46 @@ __global__ __launch_bounds__(kChebThreads) void k_cheb(PassArgs a) {
   const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
   const int i0 = (int)(((int64_t)I * xcd) >> 3), i1 = (int)(((int64_t)I * (xcd + 1)) >> 3);
   for (int it = i0 + slot; it < i1; it += nb) cheb_item<S, PIPE>(a, it, ngx, colacc);
+}
+
+// K_CHEBF: z = M^-1 r of the refinement's preconditioned inner solve, in
+// binary32 (a.rf -> a.zf, (r, z) partials per 128-column tile as in K_CHEB).
+// The prologue makes the inner stop test on (r, r) of the inner residual
+// (the scale pass or pass 2 before it) and, when that test ends the inner
+// solve after an odd inner iteration, applies its pending d update instead.
+template <int S>
+__global__ __launch_bounds__(kChebThreads) void k_chebf(PassArgs a) {
+  __shared__ double colacc[kChebWaves * kChebOut];
+  __shared__ double red[4];
+  {
+    State s = load_state_uniform(a.st_in);
+    double sum[1] = {0.0};
+    if (s.status == ST_RUNNING) cross_tile_sum<1>(a.part_in, a.g.tiles, sum, red);
+    sum[0] = uniform(sum[0]);
+    Sc sc;
+    bool flush = false;
+    const bool run = transition_x<K_CHEBF>(s, sum, sc, flush);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = s;
+    if (flush) {
+      if (threadIdx.x < kGroup) {
+        const int G = gridDim.x, b = blockIdx.x;
+        const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+        const int T = a.g.tiles;
+        const int t0 = (int)(((int64_t)T * xcd) >> 3), t1 = (int)(((int64_t)T * (xcd + 1)) >> 3);
+        for (int t = t0 + slot; t < t1; t += nb) run_flush<K_CHEBF, 4>(a, t, sc);
+      }
+      return;
+    }
+    if (!run) return;
+  }
+  const Geo& g = a.g;
+  const int ngx = (cheb_ntx<float>(g) + kChebGroupTiles - 1) / kChebGroupTiles;
+  const int Hc = a.cheb_rows, nty = (g.ny + Hc - 1) / Hc;
+  const int I = ngx * nty;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3, nb = G >> 3;
+  const int i0 = (int)(((int64_t)I * xcd) >> 3), i1 = (int)(((int64_t)I * (xcd + 1)) >> 3);
+  for (int it = i0 + slot; it < i1; it += nb) cheb_item<S, false, float>(a, it, ngx, colacc);
 }
 
 __global__ void k_fill(uint32_t* p, size_t n) {
@@ -2934,6 +3050,21 @@ static hipError_t launch_cheb(const PassArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+static hipError_t launch_chebf(const PassArgs& a, int grid, hipStream_t st) {
+  const dim3 G(grid), B(kChebThreads);
+  switch (a.cheb_s) {
+    case 1: hipLaunchKernelGGL((k_chebf<1>), G, B, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_chebf<2>), G, B, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_chebf<3>), G, B, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_chebf<4>), G, B, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_chebf<5>), G, B, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_chebf<6>), G, B, 0, st, a); break;
+    case 7: hipLaunchKernelGGL((k_chebf<7>), G, B, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_chebf<8>), G, B, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
 template <int KIND>
 static hipError_t launch_kind(int fp32g, const PassArgs& a, int grid, hipStream_t st) {
   if (a.g.plane > 0 || a.g.kc) {
@@ -2994,6 +3125,12 @@ hipError_t launch_pass(int kind, int fp32g, const PassArgs& a, int grid, hipStre
           a.cheb_rows < 1)
         return hipErrorInvalidValue;
       return launch_cheb<true>(a, grid, st);
+    case K_CHEBF:
+      // FP32 geometry (4 columns per lane): the pending-update flush walks its tiles
+      if (!fp32g || a.cheb_s < 1 || a.cheb_s > kChebMaxSteps || !a.cheb || !a.zf || !a.rf ||
+          !a.df || !a.pf_in || a.cheb_rows < 1)
+        return hipErrorInvalidValue;
+      return launch_chebf(a, grid, st);
     case K_INIT_WU:
       if (fp32g || !a.uu || !a.wv || !a.r) return hipErrorInvalidValue;
       hipLaunchKernelGGL((k_pass<K_INIT_WU, 2>), dim3(grid), dim3(kGroup), 0, st, a);
@@ -3052,24 +3189,25 @@ static int occ() {
 }
 
 template <int S>
-static int occ_cheb() {
+static int occ_cheb(bool f32) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cheb<S, false>, kChebThreads, 0) !=
-      hipSuccess)
-    return 1;
+  const hipError_t e =
+      f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_chebf<S>, kChebThreads, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_cheb<S, false>, kChebThreads, 0);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
-int cheb_max_blocks_per_cu(int s) {
+int cheb_max_blocks_per_cu(int s, bool f32) {
   switch (s) {
-    case 1: return occ_cheb<1>();
-    case 2: return occ_cheb<2>();
-    case 3: return occ_cheb<3>();
-    case 4: return occ_cheb<4>();
-    case 5: return occ_cheb<5>();
-    case 6: return occ_cheb<6>();
-    case 7: return occ_cheb<7>();
-    default: return occ_cheb<8>();
+    case 1: return occ_cheb<1>(f32);
+    case 2: return occ_cheb<2>(f32);
+    case 3: return occ_cheb<3>(f32);
+    case 4: return occ_cheb<4>(f32);
+    case 5: return occ_cheb<5>(f32);
+    case 6: return occ_cheb<6>(f32);
+    case 7: return occ_cheb<7>(f32);
+    default: return occ_cheb<8>(f32);
   }
 }
 
@@ -3110,6 +3248,7 @@ size_t pass_algorithmic_bytes(int kind, int64_t dof) {
     case K_DOT: per = 8 * 2; break;
     case K_CHEB: per = 8 * 2; break;            // read r; write z (halo not counted)
     case K_CHEBW: per = 8 * 2; break;           // read w; write m
+    case K_CHEBF: per = 4 * 2; break;           // read r; write z (FP32)
     case K_INIT_WU: per = 8 * 3; break;         // read u, r; write w
     case K_PPCG: per = 8 * 17; break;           // read m x r u w z q s p; write all but m
   }

@@ -85,7 +85,10 @@ int validate(const cg_problem* p) {
     return CG_E_INVALID;
   if (p->precision == CG_PREC_FIXED && !fixed_fits(p->nx, p->ny)) return CG_E_INVALID;
   if (p->precond < 0 || p->precond > kChebMaxSteps) return CG_E_INVALID;
-  if (p->precond > 0 && p->precision != CG_PREC_FP64) return CG_E_INVALID;
+  // the preconditioner: FP64 CG of either variant, or the FP32 inner solve
+  // of the refinement (preconditioned classic CG in binary32)
+  if (p->precond > 0 && p->precision != CG_PREC_FP64 && p->precision != CG_PREC_FP32_REFINED)
+    return CG_E_INVALID;
   if (p->precision == CG_PREC_FP32_REFINED && (!(p->inner_tol >= 0.0) || !(p->inner_tol < 1.0)))
     return CG_E_INVALID;
   // residual replacement: the pipelined FP64 2D solve, an even period (x is
@@ -240,8 +243,8 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   pl.v32 = round_up(elems * 4, Arena::kAlign);
   int n64, n32 = 0;
   if (pl.refined) {
-    n64 = 2;  // b, x
-    n32 = 4;  // rho, d, p, p'
+    n64 = 2;                   // b, x
+    n32 = pl.precond ? 5 : 4;  // rho, d, p, p' (and z)
   } else if (p->variant == CG_VARIANT_PIPELINED) {
     // b, x, r, w, w', z, q, p; preconditioned: b, x, r, u, w, m, z, q, s, p
     n64 = pl.precond ? 10 : 8;
@@ -253,14 +256,15 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
     // one item per resident work-group (long items amortise the s - 1 halo
     // rows each item recomputes; at least 16 rows)
     const int ngx = (pl.g.pitch + kChebGroupCols - 1) / kChebGroupCols;
-    const int slots =
-        std::max(1, cheb_max_blocks_per_cu(pl.precond) * num_cu / std::max(1, cheb_item_div));
+    const int slots = std::max(1, cheb_max_blocks_per_cu(pl.precond, pl.refined) * num_cu /
+                                      std::max(1, cheb_item_div));
     const int nty = std::max(1, slots / ngx);
     int crows = (p->ny + nty - 1) / nty;
     crows = std::max(crows, std::min(p->ny, 16));
     const int ntyc = (p->ny + crows - 1) / crows;
     pl.cheb_rows = crows;
-    pl.cheb_tiles = pl.g.ntx * ntyc;
+    // partials per 128-column tile (the FP32 geometry's tiles are 256 wide)
+    pl.cheb_tiles = (pl.refined ? 2 : 1) * pl.g.ntx * ntyc;
     pl.cheb_grid = (int)round_up((size_t)std::min(ngx * ntyc, slots), 8);
   }
   pl.part = round_up((size_t)ndots_max(p) * std::max(T, pl.cheb_tiles) * 8, Arena::kAlign);
@@ -294,7 +298,7 @@ size_t footprint_of(const cg_problem* p) {
   size_t n64 = fp32g ? 2
                : p->variant == CG_VARIANT_PIPELINED ? (p->precond ? 10 : 8)
                                                     : (p->precond ? 6 : 5);
-  size_t n32 = fp32g ? 4 : 0;
+  size_t n32 = fp32g ? (p->precond ? 5 : 4) : 0;
   const size_t part = round_up((size_t)ndots_max(p) * g.tiles * 8, Arena::kAlign);
   return n64 * v64 + n32 * v32 + 2 * part + 2 * round_up(sizeof(State), 256) +
          (p->precond ? 256 : 0) + (p->kx ? round_up(4 * elems * 8, Arena::kAlign) : 0);
@@ -348,6 +352,7 @@ static const char* kind_name(int kind, int fp32g) {
     case K_REF_UPDATE: return "ref_update";
     case K_CHEB: return "cheb_precond";
     case K_CHEBW: return "cheb_precond_w";
+    case K_CHEBF: return "cheb_precond_f32";
     case K_INIT_WU: return "init_wu";
     case K_PPCG: return "ppcg_pass";
     case K_APPLY: return "apply";
@@ -428,6 +433,10 @@ bool carve(Ctx& c, Work& w) {
     w.df = (float*)take(pl.v32);
     w.pf[0] = (float*)take(pl.v32);
     w.pf[1] = (float*)take(pl.v32);
+    if (pl.precond) {
+      w.zf = (float*)take(pl.v32);
+      w.cheb = (double*)take(256);
+    }
   } else if (pl.variant == CG_VARIANT_PIPELINED) {
     w.r = (double*)take(pl.v64);
     w.w[0] = (double*)take(pl.v64);
@@ -472,6 +481,7 @@ static PassArgs base_args(const Work& w) {
   a.p = w.p;
   a.rf = w.rf;
   a.df = w.df;
+  a.zf = w.zf;
   a.uu = w.u;
   a.sv = w.sv;
   a.mv = w.mv;
@@ -491,7 +501,8 @@ static hipError_t issue(Ctx& c, Work& w, int kind, F mod) {
   a.rev = w.m & 1;
   mod(a);
   w.m++;
-  const int grid = (kind == K_CHEB || kind == K_CHEBW) ? w.pl.cheb_grid : w.pl.grid;
+  const int grid =
+      (kind == K_CHEB || kind == K_CHEBW || kind == K_CHEBF) ? w.pl.cheb_grid : w.pl.grid;
   return c.pass(kind, w.pl.fp32g, a, grid, w.check);
 }
 
@@ -499,10 +510,25 @@ static hipError_t issue_iteration(Ctx& c, Work& w) {
   hipError_t e;
   const int i = w.i;
   if (w.pl.refined) {
-    e = issue(c, w, K_CG1F, [&](PassArgs& a) {
-      a.pf_in = w.pf[i & 1];
-      a.pf_out = w.pf[(i + 1) & 1];
-    });
+    // preconditioned: the inner stop test and z = M^-1 r first (FP32), and
+    // the direction is p = z + beta p
+    e = hipSuccess;
+    if (w.pl.precond)
+      e = issue(c, w, K_CHEBF, [&](PassArgs& a) {
+        a.cheb = w.cheb;
+        a.cheb_s = w.pl.precond;
+        a.cheb_rows = w.pl.cheb_rows;
+        a.pf_in = w.pf[i & 1];  // direction of a pending d update, if the test stops
+      });
+    if (e == hipSuccess)
+      e = issue(c, w, K_CG1F, [&](PassArgs& a) {
+        if (w.pl.precond) {
+          a.rf = w.zf;
+          a.cheb_tiles = w.pl.cheb_tiles;
+        }
+        a.pf_in = w.pf[i & 1];
+        a.pf_out = w.pf[(i + 1) & 1];
+      });
     if (e == hipSuccess)
       e = issue(c, w, (i & 1) ? K_CG2FX : K_CG2F, [&](PassArgs& a) {
         a.pf_in = w.pf[(i + 1) & 1];

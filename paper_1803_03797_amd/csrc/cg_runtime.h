@@ -75,6 +75,7 @@ struct Work {
   double *b = nullptr, *x = nullptr, *r = nullptr, *w[2] = {}, *z = nullptr, *q = nullptr,
          *p = nullptr, *pc[2] = {};
   float *rf = nullptr, *df = nullptr, *pf[2] = {};
+  float* zf = nullptr;  // refinement, preconditioned: z = M^-1 r_in
   double* cheb = nullptr;  // preconditioner coefficients (c0, c1[s-1], c2[s-1])
   double *u = nullptr, *sv = nullptr, *mv = nullptr;  // preconditioned pipelined
   double* kc = nullptr;  // variable coefficients: west, east, south, north arrays

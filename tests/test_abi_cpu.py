@@ -53,7 +53,6 @@ def _prob(**kw):
                                  dict(precision=2, nx=1, ny=6783),
                                  dict(precision=2, nx=5088, ny=1),
                                  dict(precond=-1), dict(precond=9),
-                                 dict(precond=4, precision=1),
                                  dict(precond=4, precision=2),
                                  dict(nz=-1), dict(nz=3, precond=2), dict(nz=3, precision=1),
                                  dict(nz=3, precision=2), dict(nx=2048, ny=2048, nz=1024),
@@ -103,10 +102,13 @@ def test_validation_accepts():
     for rr in (2, 4, 100):
         assert cg.cg_validate(_prob(rr_period=rr, variant=1)) == cg.CG_OK
         assert cg.cg_validate(_prob(rr_period=rr, variant=1, kx=3, ky=4)) == cg.CG_OK
-    # Chebyshev preconditioner: 1..8 steps, FP64, either variant
+    # Chebyshev preconditioner: 1..8 steps, FP64 of either variant or the
+    # FP32 inner solve of the refinement
     for s in range(0, 9):
         assert cg.cg_validate(_prob(precond=s)) == cg.CG_OK
         assert cg.cg_validate(_prob(precond=s, variant=1)) == cg.CG_OK
+        assert cg.cg_validate(_prob(precond=s, precision=1)) == cg.CG_OK
+        assert cg.cg_validate(_prob(precond=s, precision=1, variant=1)) == cg.CG_OK
 
 
 def test_auto_precision_footprint_follows_its_choice():
@@ -120,10 +122,12 @@ def test_auto_precision_footprint_follows_its_choice():
 
 def test_footprint_per_unknown():
     """Resident bytes per unknown: classic 5 FP64 vectors, pipelined 8, refined
-    2 FP64 + 4 FP32, preconditioned classic 6, variable coefficients 4 more
-    (plus padding and small partial/state buffers)."""
+    2 FP64 + 4 FP32, preconditioned classic 6, preconditioned refined 2 FP64 +
+    5 FP32, variable coefficients 4 more (plus padding and small
+    partial/state buffers)."""
     n = 4096
-    for variant, prec, per, pre in ((0, 0, 40, 0), (1, 0, 64, 0), (0, 1, 32, 0), (0, 0, 48, 4)):
+    for variant, prec, per, pre in ((0, 0, 40, 0), (1, 0, 64, 0), (0, 1, 32, 0), (0, 0, 48, 4),
+                                    (0, 1, 36, 4)):
         fp = cg.cg_footprint(_prob(nx=n, ny=n, variant=variant, precision=prec, precond=pre))
         assert per * n * n <= fp <= per * n * n * 1.01 + (1 << 20)
     # variable coefficients: four more FP64 arrays (west, east, south, north)

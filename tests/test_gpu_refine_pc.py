@@ -1,0 +1,220 @@
+"""GPU parity of the refinement with a Chebyshev-preconditioned inner solve
+(precision CG_PREC_FP32_REFINED with precond = s): the inner solve is classic
+CG preconditioned by M^-1 = p_s(A) in binary32 (the binary32 Chebyshev pass,
+then the two FP32 classic passes with p = z + beta p), the outer loop the
+FP64 residual and update of the plain refinement.
+
+The oracle's binary32 inner solve sums its dots in another order and rounds
+its Chebyshev recurrence without fused multiply-adds, so the comparisons are
+at binary32 accuracy for a fixed number of inner iterations and at the
+refinement's FP64 accuracy for converged solves:
+- one and two inner iterations against oracle.refine(precond=s), element by
+  element (the Chebyshev pass, the first direction, beta);
+- converged solves within 1e-9 of the FP64 oracle's solution, with as many
+  outer steps (+-1) and about as many inner iterations as the oracle's;
+- edge cases: a zero right-hand side, an initial guess, the iteration cap,
+  and the batch and serving entry points, which reject the combination."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_03797_amd import cg
+
+pytestmark = pytest.mark.gpu
+
+# one tile, ragged tiles, single rows / columns, several Chebyshev items
+# across and down
+SHAPES = [(1, 1), (2, 2), (64, 1), (1, 300), (100, 100), (130, 70), (300, 190), (513, 257),
+          (1000, 37)]
+STEPS = (1, 2, 4, 8)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    c = cg.Context(device=0, arena_bytes=2 << 30)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb else 1.0)
+
+
+def rhs(nx, ny, seed):
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (ny, nx))
+
+
+def test_plan_of_the_preconditioned_refinement(ctx):
+    """The FP32 geometry (4 columns per lane) and Chebyshev partials per
+    128-column tile: two per pass tile across."""
+    for nx, ny in ((300, 190), (1000, 37), (4096, 4096)):
+        info = ctx.cg_plan(nx, ny, precision=cg.CG_PREC_FP32_REFINED, precond=4)
+        say("plan %dx%d: cols %d pitch %d cheb rows %d tiles %d grid %d" %
+            (nx, ny, info.cols_per_lane, info.pitch, info.cheb_rows, info.cheb_tiles,
+             info.cheb_grid))
+        assert info.path == 0 and info.cols_per_lane == 4
+        assert info.cheb_rows >= 1 and info.cheb_grid >= 8 and info.cheb_grid % 8 == 0
+        assert info.cheb_tiles == (info.pitch // 128) * -(-ny // info.cheb_rows)
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("s", STEPS)
+def test_first_inner_iterations_match_the_oracle(ctx, nx, ny, s):
+    """maxit 1 and 2: x = scale * d after one or two preconditioned binary32
+    inner iterations, element by element against the oracle at binary32
+    accuracy (the Chebyshev pass on every edge and tile of the grid)."""
+    b = rhs(nx, ny, 7 * nx + ny + s)
+    for m in (1, 2):
+        say("refine pc %dx%d s=%d maxit %d" % (nx, ny, s, m))
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, nx, ny, tol=1e-12, maxit=m,
+                            precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-4, precond=s)
+        xo, ro = oracle.refine(b, nx, ny, tol=1e-12, inner_tol=1e-4, maxit=m, precond=s)
+        # (fewer than m when the first iteration already solves the problem)
+        assert res.iterations == ro.iterations <= m
+        assert res.outer_iterations == ro.outer_iterations
+        assert rc == cg.CG_NOT_CONVERGED or (rc == cg.CG_OK and ro.status == 0)
+        scale = np.abs(xo).max()
+        err = np.abs(x - xo).max() / scale
+        say("  max err / max|x| %.2e" % err)
+        assert err <= 2e-5
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 100), (300, 190), (513, 257)])
+@pytest.mark.parametrize("s", (2, 4, 8))
+def test_converged_refinement_parity(ctx, nx, ny, s):
+    """To a true relative residual of 1e-10: as close to the FP64 oracle's
+    solution as the oracle's own preconditioned refinement (within 2x, or
+    1e-9), outer steps within one of the oracle's, inner iterations within
+    10 % of its count.  (Two solutions that meet the same residual tolerance
+    differ by up to about kappa * tol, 4e-6 at 513 x 257; the refinement's
+    last outer step decides where in that range it lands.)"""
+    say("refine pc converged %dx%d s=%d" % (nx, ny, s))
+    b = np.random.default_rng(31 + s).standard_normal((ny, nx))
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-10, maxit=200000,
+                        precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-4, precond=s)
+    xo, ro = oracle.cg(b, nx, ny, tol=1e-10, maxit=200000)
+    xr, rr = oracle.refine(b, nx, ny, tol=1e-10, inner_tol=1e-4, precond=s)
+    say("  outer %d inner %d (oracle %d/%d; plain fp64 %d); err vs fp64 %.2e (oracle's "
+        "refinement %.2e)" % (res.outer_iterations, res.iterations, rr.outer_iterations,
+                               rr.iterations, ro.iterations, rel(x, xo), rel(xr, xo)))
+    assert rc == cg.CG_OK and rr.status == 0
+    assert res.rel_res_true <= 1e-10
+    assert rel(x, xo) <= max(1e-9, 2 * rel(xr, xo))
+    assert abs(res.outer_iterations - rr.outer_iterations) <= 1
+    assert abs(res.iterations - rr.iterations) <= max(3, rr.iterations // 10)
+
+
+def test_converged_refinement_parity_1024(ctx):
+    """1024 x 1024, b ~ N(0,1), s = 8, both variant settings (the inner solve
+    is classic CG for either): within 2e-9 of the FP64 oracle's solution
+    (solutions at the same residual tolerance may differ by up to about
+    2 tol kappa = 8.5e-5 here)."""
+    n = 1024
+    b = np.random.default_rng(1024).standard_normal((n, n))
+    xo, ro = oracle.cg(b, n, n, tol=1e-10, maxit=200000)
+    for variant in (cg.CG_VARIANT_CLASSIC, cg.CG_VARIANT_PIPELINED):
+        say("refine pc 1024^2 s=8 variant %d" % variant)
+        x = np.zeros_like(b)
+        rc, res = ctx.solve(b, x, n, n, tol=1e-10, maxit=200000, variant=variant,
+                            precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-4, precond=8)
+        err = rel(x, xo)
+        say("  outer %d inner %d, fp64 oracle %d; err %.2e"
+            % (res.outer_iterations, res.iterations, ro.iterations, err))
+        assert rc == cg.CG_OK
+        assert res.rel_res_true <= 1e-10
+        assert err <= 2e-9
+        # the preconditioner cuts the inner iterations well below plain CG's
+        assert res.iterations < ro.iterations / 2
+
+
+def test_zero_rhs_initial_guess_and_cap(ctx):
+    nx, ny = 130, 70
+    # zero right-hand side: x = 0, no iteration
+    b = np.zeros((ny, nx))
+    x = np.full_like(b, 3.0)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-10, maxit=1000,
+                        precision=cg.CG_PREC_FP32_REFINED, precond=4)
+    assert rc == cg.CG_OK and res.iterations == 0 and not x.any()
+    # an initial guess: the oracle's refinement from the same guess
+    b = rhs(nx, ny, 5)
+    x0 = rhs(nx, ny, 6)
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-10, maxit=200000, x0=x0,
+                        precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-3, precond=4)
+    xr, rr = oracle.refine(b, nx, ny, tol=1e-10, inner_tol=1e-3, precond=4, x0=x0)
+    xo, _ = oracle.cg(b, nx, ny, tol=1e-10, maxit=200000)
+    say("x0: outer %d inner %d (oracle %d/%d)" % (res.outer_iterations, res.iterations,
+                                                   rr.outer_iterations, rr.iterations))
+    assert rc == cg.CG_OK and res.rel_res_true <= 1e-10
+    assert rel(x, xo) <= max(1e-9, 2 * rel(xr, xo))
+    assert abs(res.outer_iterations - rr.outer_iterations) <= 1
+    # the cap on inner iterations: not converged after exactly maxit of them
+    x = np.zeros_like(b)
+    rc, res = ctx.solve(b, x, nx, ny, tol=1e-12, maxit=25,
+                        precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-6, precond=4)
+    xr, rr = oracle.refine(b, nx, ny, tol=1e-12, inner_tol=1e-6, maxit=25, precond=4)
+    assert rc == cg.CG_NOT_CONVERGED and res.iterations == rr.iterations == 25
+    assert res.outer_iterations == rr.outer_iterations
+    assert np.abs(x - xr).max() <= 2e-5 * np.abs(xr).max()
+
+
+def test_batch_and_serving_reject_the_preconditioned_refinement(ctx, torch):
+    nx, ny = 64, 64
+    b = torch.ones(ny * nx, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    p = cg.make_problem(b, x, nx, ny, precision=cg.CG_PREC_FP32_REFINED, precond=4)
+    arr = (cg.cg_problem * 1)(p)
+    res = (cg.cg_result * 1)()
+    assert ctx.lib.cg_solve_batch(ctx.h, arr, 1, res) == cg.CG_E_INVALID
+    t = C.c_uint64()
+    assert ctx.lib.cg_submit(ctx.h, C.byref(p), C.byref(t)) == cg.CG_E_INVALID
+    # the same request alone is valid
+    rc, r = ctx.cg_solve(p)
+    torch.cuda.synchronize()
+    assert rc == cg.CG_OK and r.rel_res_true <= 1e-8
+
+
+def test_profiled_passes_of_the_preconditioned_refinement(ctx):
+    """Per inner iteration one binary32 Chebyshev pass (8 B per unknown: read
+    r, write z) and the two FP32 classic passes; per outer step the residual,
+    scale and update passes."""
+    n, s = 512, 4
+    b = rhs(n, n, 3)
+    x = np.zeros_like(b)
+    ctx.cg_set_profiling(True)
+    ctx.cg_kernel_stats(reset=True)
+    rc, res = ctx.solve(b, x, n, n, tol=1e-10, maxit=200000,
+                        precision=cg.CG_PREC_FP32_REFINED, inner_tol=1e-4, precond=s)
+    st = ctx.cg_kernel_stats(reset=True)
+    ctx.cg_set_profiling(False)
+    say("profiled: outer %d inner %d; %s" % (res.outer_iterations, res.iterations,
+                                             {k: v["launches"] for k, v in st.items()}))
+    assert rc == cg.CG_OK
+    ch = st["cheb_precond_f32"]
+    # profiled solves run one inner iteration per replayed chunk: each pass
+    # once per inner iteration, plus once in the chunk whose Chebyshev pass
+    # makes the stop test that ends an inner solve (there the later passes'
+    # bodies do not run, but they are launched)
+    it = res.iterations + res.outer_iterations
+    assert ch["launches"] == it
+    assert ch["bytes"] == it * 8 * n * n
+    assert st["stencil_dot_f32"]["launches"] == it
+    assert st["ref_update"]["launches"] == res.outer_iterations
+
