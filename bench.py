@@ -1001,11 +1001,16 @@ def bench_serve(args):
     # the size-based policy: FP64 below 20480 unknowns, FP32-refined above
     _, sat_auto = served(cg.CG_PREC_AUTO, None)
     log("served auto precision, saturated", json.dumps(sat_auto))
-    sat_pc = None
+    sat_pc = sat_pca = None
     if args.serve_precond:
         # the same stream served as Chebyshev-preconditioned classic CG (FP64)
         _, sat_pc = served(cg.CG_PREC_FP64, None, args.serve_precond)
         log("served FP64 + Chebyshev s=%d, saturated" % args.serve_precond, json.dumps(sat_pc))
+        # and by the size-based policy with the preconditioner (refined
+        # requests precondition their FP32 inner solves)
+        _, sat_pca = served(cg.CG_PREC_AUTO, None, args.serve_precond)
+        log("served auto precision + Chebyshev s=%d, saturated" % args.serve_precond,
+            json.dumps(sat_pca))
     same = sum(int(torch.equal(a, c)) for a, c in zip(xs_64, x64))
     # latency under Poisson arrivals at fractions of the per-request capacity
     loads = {}
@@ -1064,7 +1069,8 @@ def bench_serve(args):
           "saturated": {"served_fp32_refined": sat_ref, "served_fp64": sat_64,
                         "served_auto_precision": sat_auto,
                         "per_request_fp64_met_tolerance": ok64,
-                        "served_fp64_chebyshev_s%d" % args.serve_precond: sat_pc},
+                        "served_fp64_chebyshev_s%d" % args.serve_precond: sat_pc,
+                        "served_auto_chebyshev_s%d" % args.serve_precond: sat_pca},
           "poisson_loads_x_per_request_capacity": loads,
           "per_request_latency": "measured: one thread solves the requests one by one in "
                                  "arrival order (cg_solve each)",
@@ -1079,8 +1085,9 @@ def bench_serve(args):
 def bench_precision(args):
     """Where FP32 refinement pays on the step engine: batches of k equal
     requests of side S (b~U[-1,1], tol 1e-8, classic CG), solved in FP64,
-    FP32-refined (inner tol 1e-4) and FP64 with the Chebyshev preconditioner
-    (s = 4); solves/s of each batch and the time of one solve alone."""
+    FP32-refined (inner tol 1e-4), by the size-based policy, and each of these
+    with the Chebyshev preconditioner (s = 4); solves/s of each batch and the
+    time of one solve alone."""
     torch, cg = setup()
     import numpy as np
     ctx = cg.Context(device=0, arena_bytes=24 << 30)
@@ -1090,7 +1097,8 @@ def bench_precision(args):
         bs = [torch.from_numpy(rng.uniform(-1, 1, (S, S))).cuda() for _ in range(k)]
         row = {}
         for name, prec, pc in (("fp64", 0, 0), ("fp32_refined", 1, 0), ("auto", 3, 0),
-                               ("fp64_chebyshev_s4", 0, 4)):
+                               ("fp64_chebyshev_s4", 0, 4), ("fp32_refined_chebyshev_s4", 1, 4),
+                               ("auto_chebyshev_s4", 3, 4)):
             xs = [torch.zeros_like(b) for b in bs]
             probs = [cg.make_problem(b, x, S, S, tol=1e-8, maxit=200000, precision=prec,
                                      inner_tol=1e-4, precond=pc) for b, x in zip(bs, xs)]

@@ -58,8 +58,9 @@ typedef enum { CG_VARIANT_CLASSIC = 0, CG_VARIANT_PIPELINED = 1 } cg_variant;
  * and the shortest tile solves, where FP32 vectors buy nothing), larger ones
  * FP32-refined (CG_PREC_FP32_REFINED: half the bytes per inner iteration);
  * the result is bitwise that of the precision chosen (outer_iterations > 0
- * tells a refined one).  2D constant-coefficient problems without
- * preconditioner or residual replacement only. */
+ * tells a refined one).  2D constant-coefficient problems without residual
+ * replacement only; with precond > 0 the refined ones precondition their
+ * FP32 inner solves. */
 typedef enum {
   CG_PREC_FP64 = 0,
   CG_PREC_FP32_REFINED = 1,
@@ -118,9 +119,9 @@ typedef struct {
                               z = M^-1 r, or the preconditioned pipelined CG of
                               Ghysels and Vanroose (variant PIPELINED); the stop
                               test stays on ||r||; FP64 alone, in batches and
-                              served.  With CG_PREC_FP32_REFINED (cg_solve only;
-                              batches and serving: CG_E_INVALID): the inner solve
-                              of the refinement becomes classic CG preconditioned
+                              served.  With CG_PREC_FP32_REFINED (alone, in batches
+                              and served): the inner solve of the refinement
+                              becomes classic CG preconditioned
                               by the same M^-1 in binary32 (coefficients rounded
                               once; (r,z) and (p,Ap) summed in binary64, alpha and
                               beta rounded to binary32 once; the inner stop test on
@@ -235,8 +236,7 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
  * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
  * worst per-solve status; results[i] holds each outcome.  A breakdown of one
  * solve does not disturb the others.  3D, variable-coefficient and residual-
- * replacement problems and the preconditioned refinement are CG_E_INVALID
- * here (cg_solve takes them). */
+ * replacement problems are CG_E_INVALID here (cg_solve takes them). */
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
 
 /* Serving: queue one request (non-blocking).  A scheduler thread admits

@@ -203,6 +203,7 @@ struct alignas(64) Slot {
   float* rf;
   float* df;
   float* PF[2];      // refinement inner direction ping-pong
+  float* zf;         // refinement, preconditioned: z = M^-1 r_in
   double* part[2];   // per-tile partials, by pass parity
   State* S[2];       // state, by pass parity
 };
@@ -294,13 +295,15 @@ int step_max_blocks_per_cu();
 hipError_t launch_step_ppcg(const Slot* slots, const Item* items, const int* n_items,
                             const int* step_base, int k, int grid, hipStream_t st);
 int step_ppcg_max_blocks_per_cu();
-// The Chebyshev passes (K_CHEB, K_CHEBW) of step *step_base + k of the
-// resident preconditioned solves with s Chebyshev steps (1 <= s <= 8):
-// work-groups of 512 threads stride over cinfo[2 s] items (Chebyshev item
-// ranges) that start at items + cinfo[2 s + 1] (both read on the device);
-// every other solve and pass kind is left to launch_step.
-hipError_t launch_step_cheb(int s, const Slot* slots, const Item* items, const int* cinfo,
-                            const int* step_base, int k, int grid, hipStream_t st);
+// The Chebyshev passes (K_CHEB, K_CHEBW; f32: the refinement's K_CHEBF) of
+// step *step_base + k of the resident preconditioned solves with s Chebyshev
+// steps (1 <= s <= 8): work-groups of 512 threads stride over cinfo[2 s]
+// items (Chebyshev item ranges) that start at items + cinfo[2 s + 1] (both
+// read on the device); every other solve and pass kind is left to
+// launch_step and the other form.
+hipError_t launch_step_cheb(int s, bool f32, const Slot* slots, const Item* items,
+                            const int* cinfo, const int* step_base, int k, int grid,
+                            hipStream_t st);
 hipError_t launch_stream(int pattern, double* const* v, size_t n, double* sink, int grid,
                          hipStream_t s);
 size_t pass_algorithmic_bytes(int kind, int64_t dof);

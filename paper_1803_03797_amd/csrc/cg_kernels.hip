@@ -2610,7 +2610,8 @@ __device__ __forceinline__ bool step_transition(State& s, const double* sum, Sc&
 
 // Kind of the pass after `kind`, given whether its body ran.  Preconditioned
 // (precond != 0): classic CG runs K_CHEB, K_CG1, K_CG2 per iteration; the
-// pipelined variant K_CHEB and K_INIT_WU once, then K_CHEBW, K_PPCG.
+// pipelined variant K_CHEB and K_INIT_WU once, then K_CHEBW, K_PPCG; the
+// refinement's inner solve K_CHEBF, K_CG1F, K_CG2F.
 __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int variant,
                                          int refined, int precond) {
   const int stop = s.status == ST_ZERO_RHS ? K_DONE : K_RESID;
@@ -2627,9 +2628,10 @@ __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int
     case K_CG2: return ran ? (precond ? K_CHEB : K_CG1) : K_RESID;
     case K_RESID: return refined ? K_REF_SCALE : K_FINAL;
     case K_FINAL: return K_DONE;
-    case K_REF_SCALE: return ran ? K_CG1F : K_DONE;
+    case K_REF_SCALE: return ran ? (precond ? K_CHEBF : K_CG1F) : K_DONE;
+    case K_CHEBF: return ran ? K_CG1F : K_REF_UPDATE;
     case K_CG1F: return ran ? K_CG2F : K_REF_UPDATE;
-    case K_CG2F: return ran ? K_CG1F : K_REF_UPDATE;
+    case K_CG2F: return ran ? (precond ? K_CHEBF : K_CG1F) : K_REF_UPDATE;
     case K_REF_UPDATE: return ran ? K_RESID : K_DONE;
   }
   return K_DONE;
@@ -2657,8 +2659,10 @@ __device__ __forceinline__ PassArgs slot_args(const Slot& S, int m, int k0, int 
   a.pc_in = (KIND == K_CG2) ? S.PC[(k0 + 1) & 1] : S.PC[k0 & 1];
   a.pc_out = S.PC[(k0 + 1) & 1];
   a.pc_prev = S.PC[k0 & 1];
-  a.rf = S.rf;
+  // preconditioned inner pass 1 forms p = z + beta p
+  a.rf = (KIND == K_CG1F && S.precond) ? S.zf : S.rf;
   a.df = S.df;
+  a.zf = S.zf;
   a.pf_in = (KIND == K_CG2F) ? S.PF[(kin0 + 1) & 1] : S.PF[kin0 & 1];
   a.pf_out = S.PF[(kin0 + 1) & 1];
   a.pf_prev = S.PF[kin0 & 1];
@@ -2687,7 +2691,7 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   if constexpr (DI > 0) {
     // classic pass 1 also takes (b,b) after the initial residual; with the
     // preconditioner its one slot is (r,z) in the Chebyshev pass's tiles
-    const bool pc = KIND == K_CG1 && (s.flags & F_PRECOND);
+    const bool pc = (KIND == K_CG1 || KIND == K_CG1F) && (s.flags & F_PRECOND);
     const int din = (KIND == K_CG1) ? ((s.flags & F_BB_PENDING) && !pc ? 2 : 1) : DI;
     const int tin = pc ? S.cheb_tiles : T;
     if (s.status == ST_RUNNING || KIND == K_FINAL) {
@@ -2749,7 +2753,9 @@ __global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* 
     // the Chebyshev passes belong to the Chebyshev step kernel, the passes of
     // preconditioned pipelined CG to k_step_ppcg (their bodies would raise
     // this kernel's register count for every pass)
-    if (kind == K_CHEB || kind == K_CHEBW || kind == K_INIT_WU || kind == K_PPCG) continue;
+    if (kind == K_CHEB || kind == K_CHEBW || kind == K_CHEBF || kind == K_INIT_WU ||
+        kind == K_PPCG)
+      continue;
     if (S.cpl4) {
       switch (kind) {
         case K_INIT_R: step_item<K_INIT_R, 4>(S, it, m, s, lds, rev); break;
@@ -2801,13 +2807,16 @@ __global__ __launch_bounds__(kGroup) void k_step_ppcg(const Slot* slots, const I
 }
 
 // The Chebyshev passes of the step engine: for a solve whose state names
-// K_CHEB or K_CHEBW at this step, the item's work-group sums the previous
-// pass's partials, applies the transition of k_cheb and marches Chebyshev
-// items [t0, t1) of the solve exactly as k_cheb does (same items, same
-// partial tiles, hence the same bits); a stop after an odd iteration applies
-// the pending x update on the tiles matching the item's share instead.
-// Solves at any other pass are skipped (k_step runs them).
-template <int S>
+// K_CHEB or K_CHEBW (F32: K_CHEBF) at this step, the item's work-group sums
+// the previous pass's partials, applies the transition of k_cheb (k_chebf)
+// and marches Chebyshev items [t0, t1) of the solve exactly as k_cheb
+// (k_chebf) does (same items, same partial tiles, hence the same bits); a
+// stop after an odd iteration applies the pending x (d) update on the tiles
+// matching the item's share instead.  Solves at any other pass are skipped
+// (k_step and the other form of this kernel run them).  The binary32 form is
+// a kernel of its own so that its march does not add to the registers of the
+// binary64 one.
+template <int S, bool F32>
 __global__ __launch_bounds__(kChebThreads) void k_step_cheb(const Slot* slots, const Item* items,
                                                            const int* cinfo,
                                                            const int* step_base, int k) {
@@ -2823,35 +2832,41 @@ __global__ __launch_bounds__(kChebThreads) void k_step_cheb(const Slot* slots, c
     const int m = step - Sl.admit_step;
     State s = load_state_uniform(Sl.S[m & 1]);
     const int kind = __builtin_amdgcn_readfirstlane(s.kind);
-    if (kind != K_CHEB && kind != K_CHEBW) continue;
+    if (F32 ? kind != K_CHEBF : (kind != K_CHEB && kind != K_CHEBW)) continue;
     const bool pipe = kind == K_CHEBW;
+    constexpr bool f32 = F32;
     const int T = Sl.g.tiles;
     double sum[3] = {0.0, 0.0, 0.0};
     if (s.status == ST_RUNNING) {
       if (pipe) cross_tile_sum<3>(Sl.part[m & 1], T, sum, red);
-      else if (s.flags & F_BB_PENDING) cross_tile_sum<2>(Sl.part[m & 1], T, sum, red);
+      else if (!f32 && (s.flags & F_BB_PENDING)) cross_tile_sum<2>(Sl.part[m & 1], T, sum, red);
       else cross_tile_sum<1>(Sl.part[m & 1], T, sum, red);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) sum[d] = uniform(sum[d]);
-    const int k0 = s.k;
+    const int k0 = s.k, kin0 = s.kin;
     Sc sc;
     bool flush = false;
-    const bool run = pipe ? transition<K_CHEBW>(s, sum, sc)
-                          : transition_x<K_CHEB>(s, sum, sc, flush);
+    bool run;
+    if constexpr (F32) run = transition_x<K_CHEBF>(s, sum, sc, flush);
+    else run = pipe ? transition<K_CHEBW>(s, sum, sc) : transition_x<K_CHEB>(s, sum, sc, flush);
     if (it.t0 == 0 && threadIdx.x == 0) {
       State o = s;
       o.kind = next_kind(kind, run, s, Sl.variant, Sl.refined, Sl.precond);
       *Sl.S[(m + 1) & 1] = o;
     }
-    PassArgs a = slot_args<K_CHEB>(Sl, m, k0, 0);
+    PassArgs a = slot_args<K_CHEB>(Sl, m, k0, kin0);
     if (flush) {
-      // the test stopped the solve after an odd iteration: x update on the
-      // tiles in proportion to this item's share of the Chebyshev items
+      // the test stopped the solve after an odd iteration: x (d) update on
+      // the tiles in proportion to this item's share of the Chebyshev items
       const int I = Sl.cheb_items;
       const int t0 = (int)((int64_t)T * it.t0 / I), t1 = (int)((int64_t)T * it.t1 / I);
-      if (threadIdx.x < kGroup)
-        for (int t = t0; t < t1; ++t) run_flush<K_CHEB, 2>(a, t, sc);
+      if (threadIdx.x < kGroup) {
+        if constexpr (F32)
+          for (int t = t0; t < t1; ++t) run_flush<K_CHEBF, 4>(a, t, sc);
+        else
+          for (int t = t0; t < t1; ++t) run_flush<K_CHEB, 2>(a, t, sc);
+      }
       continue;
     }
     if (!run) continue;
@@ -2863,10 +2878,15 @@ __global__ __launch_bounds__(kChebThreads) void k_step_cheb(const Slot* slots, c
     } else if (Sl.variant == 1) {
       a.z = Sl.u;
     }
-    const int ngx = (Sl.g.ntx + kChebGroupTiles - 1) / kChebGroupTiles;
-    for (int ci = it.t0; ci < it.t1; ++ci) {
-      if (pipe) cheb_item<S, true>(a, ci, ngx, colacc);
-      else cheb_item<S, false>(a, ci, ngx, colacc);
+    if constexpr (F32) {
+      const int ngx = (cheb_ntx<float>(Sl.g) + kChebGroupTiles - 1) / kChebGroupTiles;
+      for (int ci = it.t0; ci < it.t1; ++ci) cheb_item<S, false, float>(a, ci, ngx, colacc);
+    } else {
+      const int ngx = (Sl.g.ntx + kChebGroupTiles - 1) / kChebGroupTiles;
+      for (int ci = it.t0; ci < it.t1; ++ci) {
+        if (pipe) cheb_item<S, true>(a, ci, ngx, colacc);
+        else cheb_item<S, false>(a, ci, ngx, colacc);
+      }
     }
   }
 }
@@ -2903,24 +2923,29 @@ int step_ppcg_max_blocks_per_cu() {
 }
 
 template <int S>
-static void launch_step_cheb_s(const Slot* slots, const Item* items, const int* cinfo,
+static void launch_step_cheb_s(bool f32, const Slot* slots, const Item* items, const int* cinfo,
                                const int* step_base, int k, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_cheb<S>, dim3(grid), dim3(kChebThreads), 0, st, slots, items, cinfo,
-                     step_base, k);
+  if (f32)
+    hipLaunchKernelGGL((k_step_cheb<S, true>), dim3(grid), dim3(kChebThreads), 0, st, slots,
+                       items, cinfo, step_base, k);
+  else
+    hipLaunchKernelGGL((k_step_cheb<S, false>), dim3(grid), dim3(kChebThreads), 0, st, slots,
+                       items, cinfo, step_base, k);
 }
 
-hipError_t launch_step_cheb(int s, const Slot* slots, const Item* items, const int* cinfo,
-                            const int* step_base, int k, int grid, hipStream_t st) {
+hipError_t launch_step_cheb(int s, bool f32, const Slot* slots, const Item* items,
+                            const int* cinfo, const int* step_base, int k, int grid,
+                            hipStream_t st) {
   if (grid < 1) return hipErrorInvalidValue;
   switch (s) {
-    case 1: launch_step_cheb_s<1>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 2: launch_step_cheb_s<2>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 3: launch_step_cheb_s<3>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 4: launch_step_cheb_s<4>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 5: launch_step_cheb_s<5>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 6: launch_step_cheb_s<6>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 7: launch_step_cheb_s<7>(slots, items, cinfo, step_base, k, grid, st); break;
-    case 8: launch_step_cheb_s<8>(slots, items, cinfo, step_base, k, grid, st); break;
+    case 1: launch_step_cheb_s<1>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 2: launch_step_cheb_s<2>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 3: launch_step_cheb_s<3>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 4: launch_step_cheb_s<4>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 5: launch_step_cheb_s<5>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 6: launch_step_cheb_s<6>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 7: launch_step_cheb_s<7>(f32, slots, items, cinfo, step_base, k, grid, st); break;
+    case 8: launch_step_cheb_s<8>(f32, slots, items, cinfo, step_base, k, grid, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -56,9 +56,9 @@ cg_problem resolve_precision(const cg_problem& p) {
 int validate(const cg_problem* p) {
   if (!p) return CG_E_INVALID;
   if (p->precision == CG_PREC_AUTO) {
-    // the policy picks FP64 or FP32 refinement: problems both can take
-    if (p->precond != 0 || p->nz > 1 || p->kx || p->ky || p->rr_period != 0)
-      return CG_E_INVALID;
+    // the policy picks FP64 or FP32 refinement: problems both can take (with
+    // or without the preconditioner)
+    if (p->nz > 1 || p->kx || p->ky || p->rr_period != 0) return CG_E_INVALID;
     const cg_problem q = resolve_precision(*p);
     return validate(&q);
   }

@@ -183,6 +183,7 @@ class Engine {
     S.df = w.df;
     S.PF[0] = w.pf[0];
     S.PF[1] = w.pf[1];
+    S.zf = w.zf;
     S.part[0] = w.part[0];
     S.part[1] = w.part[1];
     S.S[0] = w.S[0];
@@ -398,16 +399,20 @@ class Engine {
   // iterations, so at most 2 maxit + 4 (maxit + 1) passes, plus the final
   // RESID and REF_SCALE.
   // Preconditioned: classic runs three passes per iteration (K_CHEB, K_CG1,
-  // K_CG2), the pipelined variant two (K_CHEBW, K_PPCG).
+  // K_CG2), the pipelined variant two (K_CHEBW, K_PPCG); the refinement's
+  // inner solve three (K_CHEBF, K_CG1F, K_CG2F), ended by K_CHEBF (or by the
+  // K_CG1F after it), i.e. 3 K + 5 passes with the outer ones, at most
+  // 3 maxit + 5 (maxit + 1) plus the final RESID and REF_SCALE.
   static int64_t step_bound(const cg_problem& p, bool refined, int precond) {
     const int64_t m = p.maxit;
-    return refined ? 6 * m + 32 : precond ? 3 * m + 32 : 2 * m + 32;
+    return refined ? (precond ? 8 * m + 32 : 6 * m + 32) : precond ? 3 * m + 32 : 2 * m + 32;
   }
 
-  // Chebyshev items of one pass of a preconditioned solve (as k_cheb numbers
-  // them: groups of kChebGroupCols columns by cheb_rows rows)
+  // Chebyshev items of one pass of a preconditioned solve (as k_cheb and
+  // k_chebf number them: groups of kChebGroupCols columns of the padded row
+  // by cheb_rows rows)
   static int cheb_items_of(const Plan& pl) {
-    const int ngx = (pl.g.ntx * 2 * kWave + kChebGroupCols - 1) / kChebGroupCols;
+    const int ngx = (pl.width + kChebGroupCols - 1) / kChebGroupCols;
     const int nty = (pl.g.ny + pl.cheb_rows - 1) / pl.cheb_rows;
     return ngx * nty;
   }
@@ -429,7 +434,8 @@ class Engine {
     // (bit 0 of the mask)
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
-      if (j && j->w.pl.precond && j->w.pl.variant == CG_VARIANT_PIPELINED) cheb_mask_ |= 1u;
+      if (j && j->w.pl.precond && !j->w.pl.refined && j->w.pl.variant == CG_VARIANT_PIPELINED)
+        cheb_mask_ |= 1u;
     }
     // Chebyshev items, grouped by s (each group's count and offset in cinfo)
     int nc = 0;
@@ -446,7 +452,12 @@ class Engine {
         for (int t = 0; t < I; t += per) h_citems_[nc++] = Item{i, t, std::min(I, t + per), 0};
       }
       cinfo[2 * sd] = nc - cinfo[2 * sd + 1];
-      if (cinfo[2 * sd]) cheb_mask_ |= 1u << sd;
+      // bit s: an FP64 solve with s steps, bit 8 + s: a refined one
+      for (int i = 0; i < n_; ++i) {
+        Job* j = slot_job_[i];
+        if (!j || j->w.pl.on_side() || j->w.pl.precond != sd) continue;
+        cheb_mask_ |= 1u << (j->w.pl.refined ? kChebMaxSteps + sd : sd);
+      }
     }
     if (hipMemcpyAsync(d_items_, h_items_, (size_t)std::max(n, 1) * sizeof(Item),
                        hipMemcpyHostToDevice, c_.st) ||
@@ -472,9 +483,10 @@ class Engine {
       e = launch_step_ppcg(d_slots_, d_items_, d_nitems_, d_step_, k,
                            std::max(8, step_ppcg_max_blocks_per_cu() * c_.num_cu), c_.st);
     for (int sd = 1; sd <= kChebMaxSteps && e == hipSuccess; ++sd)
-      if (cheb_mask_ & (1u << sd))
-        e = launch_step_cheb(sd, d_slots_, d_citems_, d_cinfo_, d_step_, k,
-                             std::max(8, cheb_max_blocks_per_cu(sd) * c_.num_cu), c_.st);
+      for (int f32 = 0; f32 < 2 && e == hipSuccess; ++f32)
+        if (cheb_mask_ & (1u << (f32 ? kChebMaxSteps + sd : sd)))
+          e = launch_step_cheb(sd, f32, d_slots_, d_citems_, d_cinfo_, d_step_, k,
+                               std::max(8, cheb_max_blocks_per_cu(sd, f32) * c_.num_cu), c_.st);
     return e;
   }
 
@@ -505,8 +517,9 @@ class Engine {
   Item* h_citems_ = nullptr;  // Chebyshev items, then cinfo (pinned)
   Item* d_citems_ = nullptr;
   int* d_cinfo_ = nullptr;
-  unsigned cheb_mask_ = 0;    // bit s: Chebyshev steps s that any admitted solve has used;
-                              // bit 0: a preconditioned pipelined solve was admitted
+  unsigned cheb_mask_ = 0;    // bit s (8 + s): Chebyshev steps s that any admitted FP64
+                              // (refined) solve has used; bit 0: a preconditioned
+                              // pipelined solve was admitted
   unsigned graph_mask_ = 0;   // ... when the cached chunk was captured
   Item* h_items_ = nullptr;
   int* h_idx_ = nullptr;

@@ -66,7 +66,7 @@ def _prob(**kw):
                                  dict(rr_period=2, variant=1, precond=1),
                                  dict(rr_period=2, variant=1, nz=3),
                                  # the precision policy: problems FP64 and refined both take
-                                 dict(precision=3, precond=2), dict(precision=3, nz=3),
+                                 dict(precision=3, nz=3),
                                  dict(precision=3, kx=3, ky=4),
                                  dict(precision=3, variant=1, rr_period=2),
                                  dict(precision=3, inner_tol=1.5, nx=300, ny=300),
@@ -94,10 +94,13 @@ def test_validation_accepts():
     for v in (0, 1):
         for nz in (0, 1):
             assert cg.cg_validate(_prob(kx=3, ky=4, variant=v, nz=nz)) == cg.CG_OK
-    # the precision policy: either variant, any size
+    # the precision policy: either variant, any size, with or without the
+    # preconditioner
     for nx, ny in ((10, 7), (181, 181), (182, 181), (2048, 2048)):
-        assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3)) == cg.CG_OK
-        assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3, variant=1)) == cg.CG_OK
+        for pc in (0, 4):
+            assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3, precond=pc)) == cg.CG_OK
+            assert cg.cg_validate(_prob(nx=nx, ny=ny, precision=3, variant=1,
+                                        precond=pc)) == cg.CG_OK
     # residual replacement: pipelined, 5-point or variable coefficients
     for rr in (2, 4, 100):
         assert cg.cg_validate(_prob(rr_period=rr, variant=1)) == cg.CG_OK
@@ -116,8 +119,9 @@ def test_auto_precision_footprint_follows_its_choice():
     the footprint is that of the precision chosen."""
     for nx, ny, chosen in ((143, 143, 0), (128, 160, 1), (4096, 4096, 1), (100, 100, 0),
                            (181, 181, 1)):
-        assert cg.cg_footprint(_prob(nx=nx, ny=ny, precision=3)) == \
-            cg.cg_footprint(_prob(nx=nx, ny=ny, precision=chosen))
+        for pc in (0, 4):
+            assert cg.cg_footprint(_prob(nx=nx, ny=ny, precision=3, precond=pc)) == \
+                cg.cg_footprint(_prob(nx=nx, ny=ny, precision=chosen, precond=pc))
 
 
 def test_footprint_per_unknown():

@@ -12,9 +12,8 @@ refinement's FP64 accuracy for converged solves:
   element (the Chebyshev pass, the first direction, beta);
 - converged solves within 1e-9 of the FP64 oracle's solution, with as many
   outer steps (+-1) and about as many inner iterations as the oracle's;
-- edge cases: a zero right-hand side, an initial guess, the iteration cap,
-  and the batch and serving entry points, which reject the combination."""
-import ctypes as C
+- edge cases: a zero right-hand side, an initial guess, the iteration cap;
+- batches and serving: each result bitwise the solve alone."""
 import sys
 
 import numpy as np
@@ -175,20 +174,116 @@ def test_zero_rhs_initial_guess_and_cap(ctx):
     assert np.abs(x - xr).max() <= 2e-5 * np.abs(xr).max()
 
 
-def test_batch_and_serving_reject_the_preconditioned_refinement(ctx, torch):
-    nx, ny = 64, 64
-    b = torch.ones(ny * nx, dtype=torch.float64, device="cuda")
-    x = torch.zeros_like(b)
-    p = cg.make_problem(b, x, nx, ny, precision=cg.CG_PREC_FP32_REFINED, precond=4)
-    arr = (cg.cg_problem * 1)(p)
-    res = (cg.cg_result * 1)()
-    assert ctx.lib.cg_solve_batch(ctx.h, arr, 1, res) == cg.CG_E_INVALID
-    t = C.c_uint64()
-    assert ctx.lib.cg_submit(ctx.h, C.byref(p), C.byref(t)) == cg.CG_E_INVALID
-    # the same request alone is valid
-    rc, r = ctx.cg_solve(p)
-    torch.cuda.synchronize()
-    assert rc == cg.CG_OK and r.rel_res_true <= 1e-8
+# (nx, ny, s, precision): preconditioned refined requests of several s beside
+# FP64 preconditioned, plain refined and plain FP64 ones
+MIX = [(300, 190, 4, 1), (513, 257, 8, 1), (1, 1, 2, 1), (64, 1, 1, 1), (100, 100, 0, 1),
+       (130, 70, 2, 0), (1024, 1024, 8, 1), (257, 129, 0, 0), (200, 150, 4, 0),
+       (1, 300, 3, 1), (640, 128, 8, 1), (77, 250, 5, 1)]
+
+
+def mix_problems(seed):
+    rng = np.random.default_rng(seed)
+    return [dict(nx=nx, ny=ny, s=sd, prec=pr, b=rng.uniform(-1, 1, (ny, nx)),
+                 tol=1e-10 if k % 2 else 1e-7) for k, (nx, ny, sd, pr) in enumerate(MIX)]
+
+
+def make(d, x, maxit=200000):
+    return cg.make_problem(d["b"], x, d["nx"], d["ny"], tol=d["tol"], maxit=maxit,
+                           precision=d["prec"], inner_tol=1e-4, precond=d["s"])
+
+
+def test_batch_with_preconditioned_refinement_matches_alone(ctx):
+    """Preconditioned refined solves side by side with FP64 preconditioned,
+    plain refined and plain FP64 ones in one batch: each result is bitwise its
+    standalone solve, and the preconditioned refined ones meet their tol."""
+    probs = mix_problems(41)
+    xs = [np.zeros_like(d["b"]) for d in probs]
+    say("batch with preconditioned refined solves:", len(probs))
+    rc, res = ctx.cg_solve_batch([make(d, x) for d, x in zip(probs, xs)])
+    assert rc == cg.CG_OK
+    for d, x, r in zip(probs, xs, res):
+        xa = np.zeros_like(d["b"])
+        rca, ra = ctx.cg_solve(make(d, xa))
+        say("  %dx%d s=%d prec %d: batch %d/%d alone %d/%d iterations, true res %.2e" %
+            (d["nx"], d["ny"], d["s"], d["prec"], r.outer_iterations, r.iterations,
+             ra.outer_iterations, ra.iterations, r.rel_res_true))
+        assert r.status == rca == cg.CG_OK
+        assert (r.iterations, r.outer_iterations) == (ra.iterations, ra.outer_iterations)
+        np.testing.assert_array_equal(x, xa)
+        assert r.rel_res_true == ra.rel_res_true <= d["tol"]
+
+
+def test_served_preconditioned_refinement_matches_alone(ctx):
+    """The same mix served (requests arriving while others run): bitwise the
+    standalone solves; a preconditioned refined request whose inner solves
+    stop after about one iteration (inner tol 0.99) and runs out of
+    iterations ends NOT_CONVERGED without disturbing the others; a zero
+    right-hand side gives x = 0."""
+    import time
+    probs = mix_problems(42)
+    probs.append(dict(nx=90, ny=70, s=4, prec=1, b=np.zeros((70, 90)), tol=1e-8))
+    xs = [np.zeros_like(d["b"]) for d in probs]
+    tickets = []
+    say("serving preconditioned refined requests:", len(probs))
+    for k, (d, x) in enumerate(zip(probs, xs)):
+        tickets.append(ctx.cg_submit(make(d, x)))
+        if k % 4 == 3:
+            time.sleep(0.002)
+    d0 = probs[0]
+    xm = np.zeros_like(d0["b"])
+    tm = ctx.cg_submit(cg.make_problem(d0["b"], xm, d0["nx"], d0["ny"], tol=1e-12, maxit=40,
+                                       precision=1, inner_tol=0.99, precond=4))
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) + 1 and time.time() < deadline:
+        for t in tickets + [tm]:
+            if t not in out:
+                rc, r = ctx.cg_poll(t)
+                if rc != cg.CG_PENDING:
+                    out[t] = (rc, cg.cg_result.from_buffer_copy(r))
+        time.sleep(0.001)
+    assert len(out) == len(tickets) + 1
+    for d, x, t in zip(probs, xs, tickets):
+        rc, r = out[t]
+        xa = np.zeros_like(d["b"])
+        rca, ra = ctx.cg_solve(make(d, xa))
+        assert rc == rca == cg.CG_OK
+        assert (r.iterations, r.outer_iterations) == (ra.iterations, ra.outer_iterations)
+        np.testing.assert_array_equal(x, xa)
+    assert out[tickets[-1]][1].iterations == 0 and not xs[-1].any()
+    rc, r = out[tm]
+    xa = np.zeros_like(d0["b"])
+    rca, ra = ctx.cg_solve(cg.make_problem(d0["b"], xa, d0["nx"], d0["ny"], tol=1e-12,
+                                           maxit=40, precision=1, inner_tol=0.99, precond=4))
+    say("  slow inner: served %d / %d iterations, alone %d / %d" %
+        (r.outer_iterations, r.iterations, ra.outer_iterations, ra.iterations))
+    assert rc == rca == cg.CG_NOT_CONVERGED and r.iterations == ra.iterations == 40
+    np.testing.assert_array_equal(xm, xa)
+
+
+def test_auto_precision_with_the_preconditioner(ctx):
+    """CG_PREC_AUTO with precond = 4 in a batch: below 20480 unknowns FP64
+    PCG, from there the preconditioned refinement; each result bitwise the
+    solve alone in the precision chosen."""
+    rng = np.random.default_rng(19)
+    shapes = [(100, 100), (143, 143), (144, 143), (300, 200), (513, 257), (17, 3)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny in shapes]
+    xs = [np.zeros_like(b) for b in bs]
+    probs = [cg.make_problem(b, x, nx, ny, tol=1e-8, maxit=20000, variant=k % 2,
+                             precision=cg.CG_PREC_AUTO, precond=4)
+             for k, (b, x, (nx, ny)) in enumerate(zip(bs, xs, shapes))]
+    rc, res = ctx.cg_solve_batch(probs)
+    assert rc == cg.CG_OK
+    for k, ((nx, ny), b, x, r) in enumerate(zip(shapes, bs, xs, res)):
+        chosen = cg.CG_PREC_FP64 if nx * ny < 20480 else cg.CG_PREC_FP32_REFINED
+        xa = np.zeros_like(b)
+        rca, ra = ctx.cg_solve(cg.make_problem(b, xa, nx, ny, tol=1e-8, maxit=20000,
+                                               variant=k % 2, precision=chosen, precond=4))
+        say("auto + precond %dx%d: chosen %d, %d/%d iterations" %
+            (nx, ny, chosen, r.outer_iterations, r.iterations))
+        assert (r.outer_iterations > 0) == (chosen == cg.CG_PREC_FP32_REFINED)
+        assert r.status == rca == cg.CG_OK and r.iterations == ra.iterations
+        np.testing.assert_array_equal(x, xa)
 
 
 def test_profiled_passes_of_the_preconditioned_refinement(ctx):
