@@ -178,8 +178,9 @@ typedef struct {
 /* Work layout a problem will use.  Its reduction order is the documented
  * arithmetic contract.  Tile order (paths 0 and 1; cg_dot; an FP64 problem of
  * path 0 or 1 in a batch): tile = 64 lanes x cols_per_lane columns by waves x
- * rows rows; lanes accumulate with fma in row order; xor butterfly; waves in
- * order; tiles in index order through threads2 strided threads.  Column-
+ * rows rows; lanes accumulate with fma in row order (walk_alt = 1: the odd
+ * wavefronts of a tile from their strip's last row up); xor butterfly; waves
+ * in order; tiles in index order through threads2 strided threads.  Column-
  * segment order (path 2, alone and in a batch): thread t of seg_waves*64
  * owns column t mod seg_cols and seg_rows rows of segment t div seg_cols
  * (threads of columns >= nx own nothing); fma in row order; xor butterfly;
@@ -207,6 +208,11 @@ typedef struct {
                                pitch, or pitch times the number of FP64 vectors
                                whose rows the workspace interleaves (pipelined
                                FP64 on path 0)                                     */
+  int32_t walk_alt;         /* tile order: 1 = the odd wavefronts of a tile walk and
+                               sum their strip from its last row up (the classic
+                               variant's 5-point passes: a strip's halo row is then
+                               read by both of its wavefronts at about the same
+                               time); 0 = every wavefront top down                 */
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 

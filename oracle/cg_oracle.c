@@ -109,6 +109,8 @@ typedef struct {
                             (dot_segments: rows, lanes, waves, seg_cols)      */
   int32_t seg_cols;      /* layout 1: threads per row of segments (>= nx; the
                             threads of columns >= nx own nothing)             */
+  int32_t alt;           /* layout 0: 1 = the odd wavefronts of a tile (w = 1,
+                            3, ...) take their strip's rows from the last up */
 } oracle_order;
 
 typedef struct {
@@ -281,7 +283,8 @@ static double butterfly(double* v, int32_t lanes) {
  *   lane l covers columns tx*TW + l*cols_per_lane + e, e < cols_per_lane.
  *   Lane: one accumulator per owned column, starting at +0, updated as
  *     acc_e = fma(a, b, acc_e) over its in-range rows in ascending order
- *     (out-of-range rows/columns are skipped); lane value
+ *     (descending for the odd wavefronts w = 1, 3, ... when alt is set;
+ *     out-of-range rows/columns are skipped); lane value
  *     ((acc_0 + acc_1) + acc_2) + ...
  *   Wavefront: xor butterfly (see butterfly()).
  *   Tile partial: ((wave_0 + wave_1) + wave_2) + ...
@@ -304,7 +307,10 @@ static double dot_canonical(int32_t nx, int32_t ny, const double* a, const doubl
         int64_t j0 = ty * TH + (int64_t)w * R;
         for (int32_t l = 0; l < L; ++l) {
           for (int32_t e = 0; e < cpl; ++e) accs[e] = 0.0;
-          for (int64_t j = j0; j < j0 + R && j < ny; ++j) {
+          const int64_t j1 = (j0 + R < ny) ? j0 + R : ny;
+          const int up = o->alt && (w & 1);
+          for (int64_t i = j0; i < j1; ++i) {
+            const int64_t j = up ? j1 - 1 - (i - j0) : i;
             for (int32_t e = 0; e < cpl; ++e) {
               int64_t c = tx * TW + (int64_t)l * cpl + e;
               if (c < nx) accs[e] = fma(a[j * nx + c], b[j * nx + c], accs[e]);

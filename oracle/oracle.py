@@ -20,7 +20,7 @@ class Order(C.Structure):
     the C file), layout 1 = column segments (dot_segments)."""
     _fields_ = [("cols_per_lane", C.c_int32), ("lanes", C.c_int32), ("waves", C.c_int32),
                 ("rows", C.c_int32), ("threads2", C.c_int32), ("layout", C.c_int32),
-                ("seg_cols", C.c_int32)]
+                ("seg_cols", C.c_int32), ("alt", C.c_int32)]
 
     @classmethod
     def segments(cls, rows, lanes, waves, seg_cols):

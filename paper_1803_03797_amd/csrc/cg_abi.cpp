@@ -146,6 +146,7 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   info->grid = pl.grid;
   info->pitch = pl.width;
   info->row_stride = pl.g.pitch;
+  info->walk_alt = pl.g.alt;
   info->cheb_rows = pl.cheb_rows;
   info->cheb_tiles = pl.cheb_tiles;
   info->cheb_grid = pl.precond ? pl.cheb_grid : 0;

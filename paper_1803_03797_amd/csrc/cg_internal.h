@@ -83,7 +83,8 @@ struct Geo {
   int32_t rows;      // rows per wavefront strip
   int32_t th;        // rows per tile = 4 * rows
   int32_t plane;     // 3D (7-point operator): rows per plane, ny = plane * nz; 2D: 0
-  int32_t pad_;
+  int32_t alt;       // 1: the odd wavefronts of a tile walk their strip from its last
+                     // row up (the 5-point operator only); 0: every wavefront top down
   // variable-coefficient 5-point operator: the west, east, south and north
   // face conductivities of every cell, four arrays laid out like a vector
   // (zero in the padding), kcs elements apart; null otherwise

@@ -724,7 +724,8 @@ __device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
   return e;
 }
 
-// Row walker shared by every stencil body.  For the wavefront's strip it
+// Row walkers shared by every stencil body (walk, which hands the 5-point
+// operators to walk2d).  For the wavefront's strip a walker
 // keeps rows j-1, j, j+1 of the halo vector H and the point data of row j in
 // registers, and issues the loads of halo row j+PD+1 and point row j+PD
 // before it computes row j, so each wavefront keeps PD+1 rows of loads in
@@ -753,31 +754,43 @@ __device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
 // loads the row's four face conductivities (kc: Kc rows of the west, east,
 // south and north arrays that g.kc holds one after the other, each laid out
 // like a vector) PD rows ahead with the point data.
-template <typename T, int CPL, int PD, int OP, class HLoad, class HMake, class ELoad,
+//
+// The walker of the 5-point operators (OP 0, and OP 2 with the row's four
+// face conductivities loaded with the point data).  With g.alt the odd
+// wavefronts of a tile walk their strip from its last row up (S and N keep
+// their meaning: comp still gets rows j-1, j, j+1), so that the row between
+// two wavefronts' strips is loaded by both at about the same time: the
+// second load is a cache hit, where top-down walks put those two loads a
+// whole strip apart.  DYN: up is the caller's (a wavefront-uniform flag);
+// else always top down, with the address arithmetic of a plain forward walk.
+template <bool DYN, typename T, int CPL, int PD, int OP, class HLoad, class HMake, class ELoad,
           class EMake, class Point, class Comp>
-__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
-                                     ELoad eload, EMake emake, Point point, Comp comp) {
+__device__ __forceinline__ void walk2d_dir(const Geo& g, const Strip& s, HLoad hload,
+                                           HMake hmake, ELoad eload, EMake emake, Point point,
+                                           Comp comp, bool up_arg) {
+  static_assert(OP == 0 || OP == 2, "5-point operators only");
   using R = Row<T, CPL>;
   using RawH = decltype(hload((size_t)0));
   using RawE = decltype(eload((size_t)0));
   using B = decltype(point((size_t)0));
-  if (s.j0 >= s.j1) return;
   const size_t P = g.pitch;
-  const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
-  const size_t o0 = (size_t)s.j0 * P;
-  constexpr bool D3 = OP == 1, VC = OP == 2;
-  // 3D: rows j - plane and j + plane (clamped into the grid for the load)
-  const int pl = D3 ? g.plane : 0;
-  auto boff = [&](int r) { return (size_t)max(r - pl, 0) * P; };
-  auto toff = [&](int r) { return (size_t)min(r + pl, g.ny - 1) * P; };
-  RawH qb[D3 ? PD : 1], qt[D3 ? PD : 1];
-  int jp = D3 ? s.j0 % pl : 0;  // row within its plane
-  // variable coefficients: the row's four face conductivities, PD rows ahead
+  const bool up = DYN ? up_arg : false;
+  const int dir = up ? -1 : 1;
+  const int jst = up ? s.j1 - 1 : s.j0;  // first row walked
+  const int jen = up ? s.j0 - 1 : s.j1;  // one past the last, in walk order
+  // halo rows ahead of the walk: down to row j0 - 1 walking up, up to row j1
+  // walking down (when inside the grid); loads of rows past them re-read the
+  // last one, whose value is then ignored
+  const int hlim = up ? max(s.j0 - 1, 0) : min(s.j1, g.ny - 1);
+  auto ahead_ok = [&](int r) { return up ? (r >= s.j0 - 1 && r >= 0) : r <= hlim; };
+  auto ahead_row = [&](int r) { return up ? max(r, hlim) : min(r, hlim); };
+  // point rows ahead of the walk, clamped to the strip's far end
+  auto point_row = [&](int r) { return up ? max(r, s.j0) : min(r, s.j1 - 1); };
   using K = Kc<T, CPL>;
   const size_t kst = (size_t)g.kcs;  // from one coefficient array to the next
   auto kload = [&](size_t off) {
     K k;
-    if constexpr (VC) {
+    if constexpr (OP == 2) {
       const double* c0 = g.kc + off + s.c;
       k.w = ldrow<T, CPL>(c0);
       k.e = ldrow<T, CPL>(c0 + kst);
@@ -786,7 +799,112 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
     }
     return k;
   };
-  K qk[VC ? PD : 1];
+  K qk[OP == 2 ? PD : 1];
+  R hB = zrow<T, CPL>();  // the row behind the walk (row jst - dir)
+  {
+    const int rb = jst - dir;
+    const int rbl = up ? min(rb, g.ny - 1) : max(rb, 0);
+    const R v = hmake(hload((size_t)rbl * P));
+    if (up ? rb < g.ny : rb >= 0) hB = v;
+  }
+  R hC = hmake(hload((size_t)jst * P));
+  T eC = emake(eload((size_t)jst * P));
+  RawH q[PD];   // raw halo rows jst + dir, ..., jst + PD dir
+  RawE qe[PD];
+  bool qv[PD];  // the row exists (inside the grid, not past the strip's halo)
+  B pt[PD];     // point data of rows jst .. jst + (PD - 1) dir
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    const int r = jst + dir * (1 + k);
+    qv[k] = ahead_ok(r);
+    const size_t ro = (size_t)ahead_row(r) * P;
+    q[k] = hload(ro);
+    qe[k] = eload(ro);
+    pt[k] = point((size_t)point_row(jst + dir * k) * P);
+    if constexpr (OP == 2) qk[k] = kload((size_t)point_row(jst + dir * k) * P);
+  }
+  for (int j = jst; j != jen; j += dir) {
+    const size_t o = (size_t)j * P;
+    // loads of the rows needed PD steps from now
+    const int rh = j + dir * (PD + 1);
+    const bool nv = ahead_ok(rh);
+    const size_t ho = (size_t)ahead_row(rh) * P;
+    const RawH hn = hload(ho);
+    const RawE en = eload(ho);
+    const B pn = point((size_t)point_row(j + dir * PD) * P);
+    K kn;
+    if constexpr (OP == 2) kn = kload((size_t)point_row(j + dir * PD) * P);
+    // row j + dir enters the window
+    R hA = hmake(q[0]);
+    T eA = emake(qe[0]);
+    if (!qv[0]) {
+      hA = zrow<T, CPL>();
+      eA = T(0);
+    }
+    R W, E;
+    west_east<T, CPL>(hC, eC, eC, W, E);
+    const R zr = zrow<T, CPL>();
+    // S is row j - 1 and N row j + 1 in either direction
+    if (up) comp(o, hA, hC, hB, W, E, zr, zr, qk[0], pt[0]);
+    else comp(o, hB, hC, hA, W, E, zr, zr, qk[0], pt[0]);
+    hB = hC;
+    hC = hA;
+    eC = eA;
+#pragma unroll
+    for (int k = 0; k + 1 < PD; ++k) {
+      q[k] = q[k + 1];
+      qe[k] = qe[k + 1];
+      qv[k] = qv[k + 1];
+      pt[k] = pt[k + 1];
+      if constexpr (OP == 2) qk[k] = qk[k + 1];
+    }
+    q[PD - 1] = hn;
+    qe[PD - 1] = en;
+    qv[PD - 1] = nv;
+    pt[PD - 1] = pn;
+    if constexpr (OP == 2) qk[PD - 1] = kn;
+  }
+}
+
+// ALT = false: always top down (the passes of pipelined solves, whose plans
+// never set g.alt, and the apply pass, which sums nothing).  One loop serves
+// both directions: measured faster than a loop per direction (stencil_dot
+// 81.7 against 82.9 us at 4096^2, update_norm 141.2 against 144.7 us).
+template <typename T, int CPL, int PD, int OP, bool ALT, class HLoad, class HMake, class ELoad,
+          class EMake, class Point, class Comp>
+__device__ __forceinline__ void walk2d(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
+                                       ELoad eload, EMake emake, Point point, Comp comp) {
+  if (s.j0 >= s.j1) return;
+  walk2d_dir<ALT, T, CPL, PD, OP>(g, s, hload, hmake, eload, emake, point, comp,
+                                  ALT && g.alt && (s.wave & 1));
+}
+
+// The entry point of every body, and the 7-point operator's walker (D3
+// above): top down, the planes below and above loaded with the point data.
+template <typename T, int CPL, int PD, int OP, bool ALT = true, class HLoad, class HMake,
+          class ELoad, class EMake, class Point, class Comp>
+__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
+                                     ELoad eload, EMake emake, Point point, Comp comp) {
+  if constexpr (OP != 1) {
+    walk2d<T, CPL, PD, OP, ALT>(g, s, hload, hmake, eload, emake, point, comp);
+    return;
+  }
+  using R = Row<T, CPL>;
+  using RawH = decltype(hload((size_t)0));
+  using RawE = decltype(eload((size_t)0));
+  using B = decltype(point((size_t)0));
+  if (s.j0 >= s.j1) return;
+  const size_t P = g.pitch;
+  const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
+  const size_t o0 = (size_t)s.j0 * P;
+  constexpr bool D3 = true;
+  // 3D: rows j - plane and j + plane (clamped into the grid for the load)
+  const int pl = D3 ? g.plane : 0;
+  auto boff = [&](int r) { return (size_t)max(r - pl, 0) * P; };
+  auto toff = [&](int r) { return (size_t)min(r + pl, g.ny - 1) * P; };
+  RawH qb[D3 ? PD : 1], qt[D3 ? PD : 1];
+  int jp = D3 ? s.j0 % pl : 0;  // row within its plane
+  const Kc<T, CPL> kz{};
   R hS = zrow<T, CPL>();
   {
     const R v = hmake(hload((size_t)max(s.j0 - 1, 0) * P));
@@ -811,7 +929,6 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qb[k] = hload(boff(rp));
       qt[k] = hload(toff(rp));
     }
-    if constexpr (VC) qk[k] = kload((size_t)rp * P);
   }
   size_t o = o0;
   for (int j = s.j0; j < s.j1; ++j, o += P) {
@@ -828,8 +945,6 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       bn = hload(boff(rp));
       tn = hload(toff(rp));
     }
-    K kn;
-    if constexpr (VC) kn = kload((size_t)rp * P);
     // row j+1 enters the window
     R hN = hmake(q[0]);
     T eN = emake(qe[0]);
@@ -845,11 +960,8 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       const R zr = zrow<T, CPL>();
       const R Bl = j >= pl ? hmake(qb[0]) : zr;
       const R Ab = j + pl < g.ny ? hmake(qt[0]) : zr;
-      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, qk[0], pt[0]);
+      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, kz, pt[0]);
       if (++jp == pl) jp = 0;
-    } else {
-      const R zr = zrow<T, CPL>();
-      comp(o, hS, hC, hN, W, E, zr, zr, qk[0], pt[0]);
     }
     hS = hC;
     hC = hN;
@@ -864,7 +976,6 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
         qb[k] = qb[k + 1];
         qt[k] = qt[k + 1];
       }
-      if constexpr (VC) qk[k] = qk[k + 1];
     }
     q[PD - 1] = hn;
     qe[PD - 1] = en;
@@ -874,7 +985,6 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qb[PD - 1] = bn;
       qt[PD - 1] = tn;
     }
-    if constexpr (VC) qk[PD - 1] = kn;
   }
 }
 
@@ -890,13 +1000,13 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #endif
 
 // Loaders for a halo vector that is stored as is.
-template <typename T, int CPL, int OP, class Point, class Comp>
+template <typename T, int CPL, int OP, bool ALT = true, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
   const int c = s.c;
 #if EDGE_MASKED
-  walk<T, CPL, WALK_PREFETCH, OP>(
+  walk<T, CPL, WALK_PREFETCH, OP, ALT>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; },
       [=](size_t off) {
@@ -906,7 +1016,7 @@ __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T
       },
       [=](T v) { return v; }, point, comp);
 #else
-  walk<T, CPL, WALK_PREFETCH, OP>(
+  walk<T, CPL, WALK_PREFETCH, OP, ALT>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
       [=](T v) { return ea.emask ? v : T(0); }, point, comp);
@@ -961,7 +1071,7 @@ __device__ __forceinline__ void body_apply(const PassArgs& a, int t, double* lv)
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
-  walk_plain<double, CPL, OP>(
+  walk_plain<double, CPL, OP, false>(
       g, s, U, [](size_t) { return Empty{}; },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const R& B3, const R& T3, const auto& kc,
@@ -991,7 +1101,11 @@ __device__ __forceinline__ void body_dot(const PassArgs& a, int t, double* lv) {
 #pragma unroll
   for (int k = 0; k < CPL; ++k) a0[k] = 0.0;
   const int valid = g.nx - s.c;
-  for (int j = s.j0; j < s.j1; ++j) {
+  // rows in the order the stencil passes of the geometry walk them (g.alt:
+  // the odd wavefronts bottom up), so the sums follow the same tile order
+  const bool up = g.alt && (s.wave & 1);
+  for (int i = s.j0; i < s.j1; ++i) {
+    const int j = up ? s.j1 - 1 - (i - s.j0) : i;
     const size_t o = (size_t)j * g.pitch + s.c;
     const R u = ldrow<double, CPL>(a.u + o), y = ldrow<double, CPL>(a.y + o);
 #pragma unroll
@@ -1022,7 +1136,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk_plain<double, CPL, OP>(
+  walk_plain<double, CPL, OP, false>(
       g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
@@ -1085,7 +1199,7 @@ __device__ __forceinline__ void body_init_wu(const PassArgs& a, int t, double* l
   const int valid = g.nx - s.c;
   const double* Rv = a.r;
   double* Wv = a.wv;
-  walk_plain<double, CPL, OP>(
+  walk_plain<double, CPL, OP, false>(
       g, s, a.uu, [=](size_t off) { return ldrow<double, CPL>(Rv + off + s.c); },
       [&](size_t off, const R& hS, const R& hC, const R& hN, const R& W, const R& E,
           const R& B3, const R& T3, const auto& kc,
@@ -1129,7 +1243,7 @@ __device__ __forceinline__ void body_ppcg(const PassArgs& a, int t, const Sc& sc
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = a2[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *U = a.uu, *Wv = a.wv, *Z = a.z, *Q = a.q, *Sv = a.sv, *Pp = a.p;
-  walk_plain<double, CPL, OP>(
+  walk_plain<double, CPL, OP, false>(
       g, s, a.mv,
       [=](size_t off) {
         PpcgRow<CPL> v;
@@ -2731,7 +2845,9 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   }
 }
 
-__global__ __launch_bounds__(kGroup) void k_step(const Slot* slots, const Item* items,
+// At least three waves per SIMD (168 VGPRs, no spill): its largest pass body
+// would otherwise take 174 and two waves.
+__global__ __launch_bounds__(kGroup, 3) void k_step(const Slot* slots, const Item* items,
                                                 const int* n_items, const int* step_base,
                                                 int k) {
   __shared__ double lds[kLdsPerGroup];

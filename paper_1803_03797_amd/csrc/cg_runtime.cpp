@@ -212,6 +212,14 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
   }
   pl.g = make_geo(p->nx, ny, pl.fp32g, rows);
   pl.g.plane = p->nz > 1 ? p->ny : 0;
+  // The classic passes (32-row strips of separate vectors) walk the odd
+  // wavefronts of a tile upward: the row between two wavefronts' strips is
+  // then read by both at about the same time (a cache hit for the second),
+  // not 32 rows apart (measured at 4096^2: stencil_dot 84.1 -> 81.8 us,
+  // update_norm 148.0 -> 141.4 us).  The pipelined pass (8-row strips,
+  // interleaved rows) measured 0.8 % slower so and keeps one direction, as
+  // does the 7-point operator's walker.
+  pl.g.alt = (p->variant == CG_VARIANT_CLASSIC || pl.refined) && p->nz <= 1 ? 1 : 0;
   const int T = pl.g.tiles;
   if (pl.wg) {
     pl.grid = 1;

@@ -43,7 +43,8 @@ def ctx(torch):
 def tile_order(ctx, nx, ny, nz, variant):
     info = ctx.cg_plan(nx, ny, variant=variant, nz=nz)
     assert info.path == 0 and info.cols_per_lane == 2
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt)
 
 
 def rel(a, b):

@@ -44,7 +44,8 @@ def order_of(ctx, nx, ny, variant):
     info = ctx.cg_plan(nx, ny, variant)
     if info.path == 2:
         return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols)
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt)
 
 
 def make(d, x, maxit=20000):

@@ -49,7 +49,8 @@ def order_of(ctx, nx, ny, variant=0):
 
 def tile_order(info):
     """The tile order of the shape (cg_dot and cg_apply use it on every path)."""
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt)
 
 
 def rel(a, b):

@@ -49,7 +49,8 @@ def tile_order(ctx, nx, ny, s, variant=cg.CG_VARIANT_CLASSIC):
     assert info.path == 0 and info.cols_per_lane == 2
     assert info.cheb_rows >= 1 and info.cheb_grid >= 8 and info.cheb_grid % 8 == 0
     assert info.cheb_tiles == (info.pitch // 128) * -(-ny // info.cheb_rows)
-    return (oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2),
+    return (oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                         alt=info.walk_alt),
             oracle.Order(2, info.lanes, 1, info.cheb_rows, info.threads2))
 
 

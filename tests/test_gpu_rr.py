@@ -37,7 +37,8 @@ def ctx(torch):
 def order(ctx, nx, ny, vc=False):
     info = ctx.cg_plan(nx, ny, PIPE, vc=vc, rr_period=2)
     assert info.path == 0
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt)
 
 
 @pytest.mark.parametrize("nx,ny", [(300, 200), (129, 67), (513, 257), (40, 30), (1, 77)])

@@ -31,7 +31,8 @@ def order_of(ctx, nx, ny, variant=0, precision=0):
     info = ctx.cg_plan(nx, ny, variant, precision)
     if info.path == 2:
         return oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols), info
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2), info
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt), info
 
 
 @pytest.mark.parametrize("variant", [0, 1])

@@ -110,7 +110,7 @@ def test_small_workload_against_tile_path(variant, torch):
                 o = (oracle.Order.segments(info.seg_rows, info.lanes, info.seg_waves, info.seg_cols)
                      if info.path == 2 else
                      oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows,
-                                  info.threads2))
+                                  info.threads2, alt=info.walk_alt))
                 x = np.zeros_like(b)
                 rc, res = c.solve(b, x, nx, ny, tol=1e-8, maxit=2000, variant=variant)
                 xo, ro = oracle.cg(b, nx, ny, variant=variant, tol=1e-8, maxit=2000,

@@ -47,7 +47,8 @@ def faces(nx, ny, seed, lo=0.25, hi=4.0):
 def tile_order(ctx, nx, ny, variant):
     info = ctx.cg_plan(nx, ny, variant=variant, vc=True)
     assert info.path == 0 and info.cols_per_lane == 2
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2)
+    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
+                        alt=info.walk_alt)
 
 
 def rel(a, b):

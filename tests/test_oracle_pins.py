@@ -111,7 +111,9 @@ def test_spmv_matches_scipy():
 
 @pytest.mark.parametrize("nx,ny", [(1, 1), (127, 1), (129, 65), (300, 77), (1000, 3)])
 @pytest.mark.parametrize("order", [GPU_LIKE, oracle.Order(4, 64, 4, 8, 256),
-                                   oracle.Order(1, 4, 3, 5, 8), oracle.Order(2, 64, 1, 37, 256)])
+                                   oracle.Order(1, 4, 3, 5, 8), oracle.Order(2, 64, 1, 37, 256),
+                                   oracle.Order(2, 64, 4, 16, 256, alt=1),
+                                   oracle.Order(1, 4, 3, 5, 8, alt=1)])
 def test_canonical_dot_exact_on_integers(nx, ny, order):
     """Integer data: every partial sum is exact, so any correct order returns the
     exact sum; a dropped, repeated or misplaced term would not."""
@@ -125,6 +127,29 @@ def test_canonical_dot_exact_on_integers(nx, ny, order):
     w = np.arange(1, nx * ny + 1, dtype=float).reshape(ny, nx)
     one = np.ones((ny, nx))
     assert oracle.dot(w, one, nx, ny, MODE_CANONICAL, order) == (nx * ny) * (nx * ny + 1) / 2
+
+
+def test_alt_order_sums_odd_wavefronts_upward():
+    """alt = 1: the odd wavefronts of a tile add their strip's rows from the
+    last up, the even ones top down.  One column, two wavefronts of three
+    rows: 1, 1e16, -1e16 top down gives 0 (1 + 1e16 rounds to 1e16), bottom up
+    gives 1."""
+    o0 = oracle.Order(1, 1, 2, 3, 1)
+    o1 = oracle.Order(1, 1, 2, 3, 1, alt=1)
+    one = np.ones((6, 1))
+    odd = np.array([0.0, 0.0, 0.0, 1.0, 1e16, -1e16]).reshape(6, 1)
+    even = np.array([1.0, 1e16, -1e16, 0.0, 0.0, 0.0]).reshape(6, 1)
+    assert oracle.dot(odd, one, 1, 6, MODE_CANONICAL, o0) == 0.0
+    assert oracle.dot(odd, one, 1, 6, MODE_CANONICAL, o1) == 1.0
+    assert oracle.dot(even, one, 1, 6, MODE_CANONICAL, o0) == 0.0
+    assert oracle.dot(even, one, 1, 6, MODE_CANONICAL, o1) == 0.0
+    # a ragged strip (four-row strips, seven rows: the second wavefront holds
+    # three): bottom up from the last row of the grid
+    o4 = oracle.Order(1, 1, 2, 4, 1, alt=1)
+    rag = np.array([0.0, 0.0, 0.0, 0.0, 1.0, 1e16, -1e16]).reshape(7, 1)
+    assert oracle.dot(rag, np.ones((7, 1)), 1, 7, MODE_CANONICAL, o4) == 1.0
+    assert oracle.dot(rag, np.ones((7, 1)), 1, 7, MODE_CANONICAL,
+                      oracle.Order(1, 1, 2, 4, 1)) == 0.0
 
 
 def seg_order(nx, ny, rows, lanes, spare_waves=1, ghosts=1):
