@@ -61,7 +61,7 @@ BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
 PCG_TRAFFIC_BYTES = 1647362579
 # The same for pcg_pass of the variable-coefficient operator at 4096 x 4096
 # (128 algorithmic bytes per unknown: 96 of vectors, 32 of coefficients).
-VC_TRAFFIC_BYTES = 2161748739
+VC_TRAFFIC_BYTES = 2161653028
 # Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
 # iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
 # pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
