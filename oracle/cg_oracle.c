@@ -111,6 +111,8 @@ typedef struct {
                             threads of columns >= nx own nothing)             */
   int32_t alt;           /* layout 0: 1 = the odd wavefronts of a tile (w = 1,
                             3, ...) take their strip's rows from the last up */
+  int32_t plane;         /* layout 2: rows per plane (the 3D grid's ny; the
+                            vectors hold plane * nz rows)                    */
 } oracle_order;
 
 typedef struct {
@@ -379,11 +381,76 @@ static double dot_segments(int32_t nx, int32_t ny, const double* a, const double
   return total;
 }
 
+/* Canonical order of the z-march layout of the 3D operator (layout 2): the
+ * grid is nx x plane x nz, stored as ny = plane * nz rows of nx (row
+ * z * plane + y).  A tile is TW = cols_per_lane * lanes columns by `waves`
+ * consecutive in-plane rows y by `rows` planes z:
+ *   ntx = ceil(nx / TW); nty = ceil(plane / waves); ntz = ceil(nz / rows);
+ *   tile t = (tz * nty + ty) * ntx + tx.
+ *   Wavefront w of tile (tx, ty, tz) owns in-plane row y = ty * waves + w
+ *   (nothing when y >= plane) and planes tz * rows .. tz * rows + rows - 1
+ *   (those < nz); lane l owns columns tx * TW + l * cols_per_lane + e.
+ *   Lane: one accumulator per owned column from +0, acc = fma(a, b, acc)
+ *     over the wavefront's planes in ascending z; lane value
+ *     ((acc_0 + acc_1) + ...); wavefront: xor butterfly; tile partial:
+ *     waves in order; cross-tile: as in dot_canonical. */
+static double dot_zmarch(int32_t nx, int32_t ny, const double* a, const double* b,
+                         const oracle_order* o) {
+  const int32_t cpl = o->cols_per_lane, L = o->lanes, W = o->waves, R = o->rows;
+  const int32_t pl = o->plane, nz = ny / pl;
+  const int32_t TW = cpl * L;
+  const int64_t ntx = (nx + TW - 1) / TW, nty = (pl + W - 1) / W, ntz = (nz + R - 1) / R;
+  const int64_t T = ntx * nty * ntz;
+  double* part = (double*)malloc((size_t)T * sizeof(double));
+  double lane[256], accs[16];
+  for (int64_t tz = 0; tz < ntz; ++tz)
+    for (int64_t ty = 0; ty < nty; ++ty)
+      for (int64_t tx = 0; tx < ntx; ++tx) {
+        double tile = 0.0;
+        for (int32_t w = 0; w < W; ++w) {
+          const int64_t y = ty * W + w;
+          for (int32_t l = 0; l < L; ++l) {
+            for (int32_t e = 0; e < cpl; ++e) accs[e] = 0.0;
+            for (int64_t z = tz * R; y < pl && z < tz * R + R && z < nz; ++z) {
+              const int64_t j = z * pl + y;
+              for (int32_t e = 0; e < cpl; ++e) {
+                const int64_t c = tx * TW + (int64_t)l * cpl + e;
+                if (c < nx) accs[e] = fma(a[j * nx + c], b[j * nx + c], accs[e]);
+              }
+            }
+            double v = accs[0];
+            for (int32_t e = 1; e < cpl; ++e) v = v + accs[e];
+            lane[l] = v;
+          }
+          const double wv = butterfly(lane, L);
+          tile = (w == 0) ? wv : tile + wv;
+        }
+        part[(tz * nty + ty) * ntx + tx] = tile;
+      }
+  const int32_t T2 = o->threads2;
+  double* th = (double*)malloc((size_t)T2 * sizeof(double));
+  for (int32_t t = 0; t < T2; ++t) {
+    double sacc = 0.0;
+    for (int64_t k = t; k < T; k += T2) sacc = sacc + part[k];
+    th[t] = sacc;
+  }
+  double total = 0.0;
+  for (int32_t g = 0; g < T2 / L; ++g) {
+    const double gv = butterfly(th + (int64_t)g * L, L);
+    total = (g == 0) ? gv : total + gv;
+  }
+  free(th);
+  free(part);
+  return total;
+}
+
 /* Exported dot for the tests. */
 double oracle_dot(int32_t nx, int32_t ny, int32_t mode, const oracle_order* o,
                   const double* a, const double* b) {
   if (mode == MODE_CANONICAL)
-    return o->layout == 1 ? dot_segments(nx, ny, a, b, o) : dot_canonical(nx, ny, a, b, o);
+    return o->layout == 1   ? dot_segments(nx, ny, a, b, o)
+           : o->layout == 2 ? dot_zmarch(nx, ny, a, b, o)
+                            : dot_canonical(nx, ny, a, b, o);
   return dot_sequential((int64_t)nx * ny, a, b);
 }
 
@@ -611,8 +678,9 @@ static int order_valid(const oracle_order* o, int32_t nx, int32_t ny) {
   if (o->layout == 1)
     return o->seg_cols >= nx &&
            (int64_t)o->waves * o->lanes >= (int64_t)o->seg_cols * ((ny + o->rows - 1) / o->rows);
-  return o->layout == 0 && o->cols_per_lane >= 1 && o->cols_per_lane <= 16 &&
-         o->threads2 >= o->lanes && o->threads2 % o->lanes == 0;
+  if (o->layout == 2 && !(o->plane >= 1 && ny % o->plane == 0)) return 0;
+  return (o->layout == 0 || o->layout == 2) && o->cols_per_lane >= 1 &&
+         o->cols_per_lane <= 16 && o->threads2 >= o->lanes && o->threads2 % o->lanes == 0;
 }
 
 /* Solve A x = b.  variant: 0 classic, 1 pipelined.  mode: 0 sequential,

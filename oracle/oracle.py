@@ -17,16 +17,24 @@ OR_OK, OR_NOT_CONVERGED, OR_BREAKDOWN, OR_E_INVALID, OR_E_NOMEM = 0, 2, 3, -1, -
 
 class Order(C.Structure):
     """Reduction order of the canonical mode: layout 0 = tiles (dot_canonical in
-    the C file), layout 1 = column segments (dot_segments)."""
+    the C file), layout 1 = column segments (dot_segments), layout 2 = the 3D
+    z-march tiles (dot_zmarch: `waves` in-plane rows by `rows` planes, plane =
+    rows per plane)."""
     _fields_ = [("cols_per_lane", C.c_int32), ("lanes", C.c_int32), ("waves", C.c_int32),
                 ("rows", C.c_int32), ("threads2", C.c_int32), ("layout", C.c_int32),
-                ("seg_cols", C.c_int32), ("alt", C.c_int32)]
+                ("seg_cols", C.c_int32), ("alt", C.c_int32), ("plane", C.c_int32)]
 
     @classmethod
     def segments(cls, rows, lanes, waves, seg_cols):
         """Column-segment order: waves*lanes threads, `rows` rows per thread,
         seg_cols threads per row of segments (those of columns >= nx idle)."""
         return cls(1, lanes, waves, rows, 0, 1, seg_cols)
+
+    @classmethod
+    def zmarch(cls, cols_per_lane, lanes, waves, planes, threads2, plane):
+        """3D z-march order: tiles of `waves` in-plane rows by `planes` planes,
+        each wavefront summing its row over the planes in ascending z."""
+        return cls(cols_per_lane, lanes, waves, planes, threads2, 2, 0, 0, plane)
 
 
 class _Result(C.Structure):

@@ -161,3 +161,67 @@ def test_edge_cases_and_rejections():
     for bad in ((0, 1, 1), (1, 0, 1), (1, 1, 0)):
         with pytest.raises(ValueError):
             oracle.cg3(np.zeros(0), *bad)
+
+
+# --------------------------------------------------- z-march tile order --
+
+ZMARCH = [oracle.Order.zmarch(2, 64, 4, 8, 256, 0), oracle.Order.zmarch(1, 4, 3, 2, 8, 0),
+          oracle.Order.zmarch(2, 64, 4, 64, 256, 0)]
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(1, 1, 2), (7, 5, 3), (130, 7, 5), (37, 40, 23),
+                                      (257, 30, 9)])
+@pytest.mark.parametrize("k", range(len(ZMARCH)))
+def test_zmarch_order_exact_on_integers(nx, ny, nz, k):
+    """Integer data and position weights: every term of the 3D grid is counted
+    exactly once by the z-march order (a dropped, repeated or misplaced row,
+    plane or column would change the exact sum)."""
+    base = ZMARCH[k]
+    o = oracle.Order.zmarch(base.cols_per_lane, base.lanes, base.waves, base.rows,
+                            base.threads2, ny)
+    rows = ny * nz
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    a = rng.integers(-8, 9, size=(rows, nx)).astype(float)
+    b = rng.integers(-8, 9, size=(rows, nx)).astype(float)
+    exact = float(np.sum(a.astype(np.int64) * b.astype(np.int64)))
+    assert oracle.dot(a, b, nx, rows, MODE_CANONICAL, o) == exact
+    w = np.arange(1, nx * rows + 1, dtype=float).reshape(rows, nx)
+    assert oracle.dot(w, np.ones((rows, nx)), nx, rows, MODE_CANONICAL, o) == \
+        (nx * rows) * (nx * rows + 1) / 2
+
+
+def test_zmarch_order_sums_each_row_over_the_planes():
+    """One column, a 2 x 3 (y, z) grid, one tile of two wavefronts (y = 0, 1)
+    over all three planes.  The wavefront of y sums its values in ascending z:
+    y = 0 holding 1, 1e16, -1e16 at z = 0, 1, 2 gives (1 + 1e16) - 1e16 = 0
+    (descending z would give 1).  The tile adds the wavefronts: 1e16 + 1 at
+    y = 0 against -1e16 at y = 1 gives 1e16 - 1e16 = 0, where the stacked-row
+    order (rows z * 2 + y in sequence) cancels 1e16 first and keeps the 1."""
+    o = oracle.Order.zmarch(1, 1, 2, 3, 1, 2)
+    one = np.ones((6, 1))
+    def grid(v):  # v[y][z] -> rows z * 2 + y
+        return np.array([v[y][z] for z in range(3) for y in range(2)]).reshape(6, 1)
+    assert oracle.dot(grid([[1.0, 1e16, -1e16], [0.0, 0.0, 0.0]]), one, 1, 6,
+                      MODE_CANONICAL, o) == 0.0
+    assert oracle.dot(grid([[-1e16, 1e16, 1.0], [0.0, 0.0, 0.0]]), one, 1, 6,
+                      MODE_CANONICAL, o) == 1.0
+    cross = grid([[1e16, 1.0, 0.0], [-1e16, 0.0, 0.0]])
+    assert oracle.dot(cross, one, 1, 6, MODE_CANONICAL, o) == 0.0
+    assert oracle.dot(cross, one, 1, 6, MODE_CANONICAL, oracle.Order(1, 1, 2, 3, 1)) == 1.0
+
+
+def test_zmarch_solves_agree_with_the_tile_order():
+    """CG in the z-march order: the same iterations as in the stacked-row tile
+    order and solutions equal to rounding (two valid summation orders)."""
+    nx, ny, nz = 37, 40, 23
+    b = np.random.default_rng(5).uniform(-1, 1, (ny * nz, nx))
+    for v in (0, 1):
+        x1, r1 = oracle.cg3(b, nx, ny, nz, variant=v, tol=1e-10, mode=MODE_CANONICAL,
+                            order=GPU_LIKE)
+        x2, r2 = oracle.cg3(b, nx, ny, nz, variant=v, tol=1e-10, mode=MODE_CANONICAL,
+                            order=oracle.Order.zmarch(2, 64, 4, 8, 256, ny))
+        assert abs(r1.iterations - r2.iterations) <= 1
+        assert np.linalg.norm(x1 - x2) <= 1e-9 * np.linalg.norm(x1)
+        with pytest.raises(ValueError):
+            oracle.cg3(b, nx, ny, nz, variant=v, mode=MODE_CANONICAL,
+                       order=oracle.Order.zmarch(2, 64, 4, 8, 256, 41))
