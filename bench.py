@@ -62,6 +62,8 @@ PCG_TRAFFIC_BYTES = 1647362579
 # The same for pcg_pass of the variable-coefficient operator at 4096 x 4096
 # (128 algorithmic bytes per unknown: 96 of vectors, 32 of coefficients).
 VC_TRAFFIC_BYTES = 2161653028
+# The same for pcg_pass of the 7-point operator at 256^3 (z-march tiles).
+CUBE_TRAFFIC_BYTES = 1641763806
 # Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
 # iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
 # pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
@@ -664,19 +666,19 @@ def bench_cube(args):
         roof = {"bound": "hbm", "kernel": "pcg_pass (7-point)", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                 "avg_launch_us": pk["avg_us"], "bytes_per_launch": BYTES_PER_DOF["pcg_pass"] * dof,
-                "traffic": None}
+                "traffic": CUBE_TRAFFIC_BYTES if n == 256 else None}
     cpu = None
     if not args.no_cpu:
         import oracle
         bh = b.cpu().numpy()
         k = 4
-        t = time.perf_counter()
         oracle.cg3(bh, n, n, n, variant=0, tol=0.0, maxit=k)
-        ct = time.perf_counter() - t
+        ct = oracle.last_solve_seconds()
         cpu = {"value": round(dof * k / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "host": host_info(),
                "sample": "%d classic iterations of the 3D oracle at %d^3 (explicit 7-point CSR, "
-                         "single thread, %.1f s incl. assembly)" % (k, n, ct)}
+                         "single thread; the iterations timed without the CSR assembly, %.2f s)"
+                         % (k, n, ct)}
     value = (out["classic"]["GDOF_iter_s"] + out["pipelined"]["GDOF_iter_s"]) / 2
     emit({"metric": "CG GDOF-iter/s, 3D 7-point Laplacian %d^3 FP64 (classic + pipelined, %d "
                     "iterations each)" % (n, its),
@@ -766,13 +768,13 @@ def bench_vc(args):
     if not args.no_cpu:
         import oracle
         k = 4
-        t = time.perf_counter()
         oracle.cg_vc(bh, n, n, kxh, kyh, variant=0, tol=0.0, maxit=k)
-        ct = time.perf_counter() - t
+        ct = oracle.last_solve_seconds()
         cpu = {"value": round(dof * k / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "host": host_info(),
                "sample": "%d classic iterations of the variable-coefficient oracle at %d^2 "
-                         "(explicit CSR, single thread, %.1f s incl. assembly)" % (k, n, ct)}
+                         "(explicit CSR, single thread; the iterations timed without the CSR "
+                         "assembly, %.2f s)" % (k, n, ct)}
     value = (out["classic"]["GDOF_iter_s"] + out["pipelined"]["GDOF_iter_s"]) / 2
     emit({"metric": "CG GDOF-iter/s, variable-coefficient 5-point operator %d^2 FP64 (classic "
                     "+ pipelined, %d iterations each)" % (n, its),

@@ -213,6 +213,11 @@ typedef struct {
                                variant's 5-point passes: a strip's halo row is then
                                read by both of its wavefronts at about the same
                                time); 0 = every wavefront top down                 */
+  int32_t walk_z;           /* 1 = the 3D z-march tile order (nz > 1): a tile is 4
+                               consecutive in-plane rows (waves, one per wavefront)
+                               by `rows` planes, tile t = (tz * ceil(ny / 4) + ty) *
+                               tiles across + tx, and each lane sums its row over
+                               the planes in ascending z; 0 = the 2D tile order    */
   size_t footprint;         /* device bytes the solve occupies                       */
 } cg_plan_info;
 

@@ -815,8 +815,10 @@ int oracle_cg3(int32_t variant, int32_t mode, const oracle_order* ord, int32_t n
   if (rc) return rc;
   ctx_t c = {nx, rows, mode, ord, 0};
   memset(res, 0, sizeof(*res));
+  const double t0 = wall_now();
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
+  g_solve_seconds = wall_now() - t0;
   csr_free(&A);
   return rc;
 }
@@ -904,8 +906,10 @@ int oracle_cg_vc_rr(int32_t variant, int32_t mode, const oracle_order* ord, int3
   if (rc) return rc;
   ctx_t c = {nx, ny, mode, ord, rr_period};
   memset(res, 0, sizeof(*res));
+  const double t0 = wall_now();
   rc = (variant == VARIANT_PIPELINED) ? cg_pipelined(&A, &c, b, x0, x, tol, maxit, res, NULL)
                                       : cg_classic(&A, &c, b, x0, x, tol, maxit, res, NULL);
+  g_solve_seconds = wall_now() - t0;
   csr_free(&A);
   return rc;
 }

@@ -346,6 +346,12 @@ def _load_omp():
     return _lib_omp
 
 
+def last_solve_seconds():
+    """Seconds the last solve of this thread spent in its iterations (the CSR
+    assembly excluded): oracle.cg, cg3 and cg_vc."""
+    return _load().oracle_last_solve_seconds()
+
+
 def cg_timed(b, nx, ny, variant=VARIANT_CLASSIC, tol=0.0, maxit=10, all_cores=False):
     """The sequential-mode solve, timed: returns (Result, seconds of the
     iterations without the CSR assembly, threads used).  all_cores: the

@@ -51,7 +51,8 @@ class cg_plan_info(C.Structure):
                 ("tiles", C.c_int32), ("grid", C.c_int32), ("pitch", C.c_int32),
                 ("seg_rows", C.c_int32), ("seg_waves", C.c_int32), ("seg_cols", C.c_int32),
                 ("cheb_rows", C.c_int32), ("cheb_tiles", C.c_int32), ("cheb_grid", C.c_int32),
-                ("row_stride", C.c_int32), ("walk_alt", C.c_int32), ("footprint", C.c_size_t)]
+                ("row_stride", C.c_int32), ("walk_alt", C.c_int32), ("walk_z", C.c_int32),
+                ("footprint", C.c_size_t)]
 
 
 class cg_kstat(C.Structure):

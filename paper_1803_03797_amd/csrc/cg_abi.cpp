@@ -147,6 +147,7 @@ int cg_plan(cg_ctx* ctx, const cg_problem* prob, cg_plan_info* info) {
   info->pitch = pl.width;
   info->row_stride = pl.g.pitch;
   info->walk_alt = pl.g.alt;
+  info->walk_z = pl.g.plane > 0 ? 1 : 0;
   info->cheb_rows = pl.cheb_rows;
   info->cheb_tiles = pl.cheb_tiles;
   info->cheb_grid = pl.precond ? pl.cheb_grid : 0;

@@ -252,9 +252,17 @@ struct Strip {
   int tx, lane, wave;
   int c;       // first column of this lane
   int ct;      // first column of the tile
-  int j0, j1;  // rows of this wavefront's strip; empty when j0 >= j1
+  int j0, j1;  // rows of this wavefront's strip, j0, j0 + js, ... < j1; empty
+               // when j0 >= j1
+  int js;      // row step: 1, or the rows of a plane (3D z-march)
 };
 
+// 2D: tile t = ty * ntx + tx of 4 wavefronts x rows rows; wavefront w walks
+// rows ty * th + w * rows + [0, rows).  3D (g.plane > 0, the z-march): tile
+// t = (tz * nty + ty) * ntx + tx of 4 consecutive in-plane rows (one per
+// wavefront: y = ty * 4 + w) by rows planes; wavefront w walks its row y
+// through planes tz * rows + [0, rows), one plane (g.plane stored rows) per
+// step.
 template <int CPL>
 __device__ __forceinline__ Strip strip_of(const Geo& g, int t) {
   Strip s;
@@ -264,6 +272,19 @@ __device__ __forceinline__ Strip strip_of(const Geo& g, int t) {
   s.wave = (threadIdx.x >> 6) & (kWavesPerTile - 1);
   s.ct = s.tx * (kWave * CPL);
   s.c = s.ct + s.lane * CPL;
+  if (g.plane > 0) {
+    const int pl = g.plane, nz = g.ny / pl;
+    const int y = (ty % g.nty) * kWavesPerTile + s.wave;
+    const int z0 = (ty / g.nty) * g.rows, z1 = min(z0 + g.rows, nz);
+    s.js = pl;
+    s.j0 = s.j1 = 0;
+    if (y < pl) {
+      s.j0 = z0 * pl + y;
+      s.j1 = z1 * pl + y;
+    }
+    return s;
+  }
+  s.js = 1;
   s.j0 = ty * g.th + s.wave * g.rows;
   s.j1 = min(s.j0 + g.rows, g.ny);
   return s;
@@ -742,11 +763,9 @@ __device__ __forceinline__ EdgeAddr edge_addr(const Strip& s, const Geo& g) {
 //   point(off) -> Bundle: the point-wise operands of that row
 //   comp(off, S, C, N, W, E, bundle): row j's arithmetic and stores
 //
-// D3 (the 7-point operator of an nx x (ny / plane) x ... grid stored as
-// g.ny rows of nx, g.plane rows per plane): the walker also loads the halo
-// vector one plane below and above each row (raw, PD rows ahead with the point
-// data) and hands comp hS / hN zeroed at the plane's first / last row, and the
-// rows below / above (zero outside the grid).  In 2D those are zero rows.
+// D3 (the 7-point operator of an nx x g.plane x nz grid stored as g.ny =
+// g.plane * nz rows of nx): the walker marches along z instead (walk below)
+// and hands comp the rows below / above too; in 2D those are zero rows.
 //   comp(off, S, C, N, W, E, below, above, kc, bundle)
 //
 // OP selects the operator: 0 the 5-point stencil, 1 the 7-point one (D3
@@ -879,8 +898,15 @@ __device__ __forceinline__ void walk2d(const Geo& g, const Strip& s, HLoad hload
                                   ALT && g.alt && (s.wave & 1));
 }
 
-// The entry point of every body, and the 7-point operator's walker (D3
-// above): top down, the planes below and above loaded with the point data.
+// The entry point of every body, and the 7-point operator's walker: the
+// z-march (strip_of: the wavefront owns in-plane row y and walks it through
+// its planes).  Plane z - 1 (behind), z and z + 1 (ahead) of row y are the
+// window, as rows j - 1, j, j + 1 are in 2D; rows y - 1 and y + 1 of plane z
+// (the in-plane neighbours) are loaded with the point data, PD planes ahead:
+// they are the rows the tile's neighbouring wavefronts walk at the same step,
+// so they come from the caches instead of HBM.  comp gets S / N = rows y -/+ 1
+// (zero outside the plane) and below / above = planes z -/+ 1 (zero outside
+// the grid).
 template <typename T, int CPL, int PD, int OP, bool ALT = true, class HLoad, class HMake,
           class ELoad, class EMake, class Point, class Comp>
 __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
@@ -895,96 +921,83 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
   using B = decltype(point((size_t)0));
   if (s.j0 >= s.j1) return;
   const size_t P = g.pitch;
-  const int hmax = min(s.j1, g.ny - 1);  // last halo row worth loading
-  const size_t o0 = (size_t)s.j0 * P;
-  constexpr bool D3 = true;
-  // 3D: rows j - plane and j + plane (clamped into the grid for the load)
-  const int pl = D3 ? g.plane : 0;
-  auto boff = [&](int r) { return (size_t)max(r - pl, 0) * P; };
-  auto toff = [&](int r) { return (size_t)min(r + pl, g.ny - 1) * P; };
-  RawH qb[D3 ? PD : 1], qt[D3 ? PD : 1];
-  int jp = D3 ? s.j0 % pl : 0;  // row within its plane
+  const int pl = g.plane, nz = g.ny / pl;
+  const int y = s.j0 % pl;                          // the wavefront's in-plane row
+  const int z0 = s.j0 / pl, z1 = (s.j1 - y) / pl;  // its planes [z0, z1)
+  auto off = [&](int z, int yy) { return ((size_t)z * pl + yy) * P; };
+  // the in-plane neighbours' rows (a row outside the plane is replaced by
+  // row y, whose value is then ignored)
+  const bool has_s = y > 0, has_n = y + 1 < pl;
+  const int ys = has_s ? y - 1 : y, yn = has_n ? y + 1 : y;
+  const int zmax = min(z1, nz - 1);  // last plane worth loading ahead
   const Kc<T, CPL> kz{};
-  R hS = zrow<T, CPL>();
+  R hB = zrow<T, CPL>();  // plane z - 1
   {
-    const R v = hmake(hload((size_t)max(s.j0 - 1, 0) * P));
-    if (s.j0 > 0) hS = v;
+    const R v = hmake(hload(off(max(z0 - 1, 0), y)));
+    if (z0 > 0) hB = v;
   }
-  R hC = hmake(hload(o0));
-  T eC = emake(eload(o0));
-  RawH q[PD];   // raw halo rows j+1 .. j+PD
+  R hC = hmake(hload(off(z0, y)));
+  T eC = emake(eload(off(z0, y)));
+  RawH q[PD];   // raw row y of planes z+1 .. z+PD
   RawE qe[PD];
-  bool qv[PD];  // the row exists (inside the grid, not past the strip's north halo)
-  B pt[PD];     // point data of rows j .. j+PD-1
+  bool qv[PD];  // the plane exists (inside the grid, not past the strip's halo)
+  B pt[PD];     // point data of planes z .. z+PD-1
+  RawH qs[PD], qn[PD];  // rows y - 1, y + 1 of planes z .. z+PD-1
 #pragma unroll
   for (int k = 0; k < PD; ++k) {
-    const int r = s.j0 + 1 + k;
-    qv[k] = r <= hmax;
-    const size_t ro = (size_t)min(r, hmax) * P;
+    const int zr = z0 + 1 + k;
+    qv[k] = zr <= zmax;
+    const size_t ro = off(min(zr, zmax), y);
     q[k] = hload(ro);
     qe[k] = eload(ro);
-    const int rp = min(s.j0 + k, s.j1 - 1);
-    pt[k] = point((size_t)rp * P);
-    if constexpr (D3) {
-      qb[k] = hload(boff(rp));
-      qt[k] = hload(toff(rp));
-    }
+    const int zp = min(z0 + k, z1 - 1);
+    pt[k] = point(off(zp, y));
+    qs[k] = hload(off(zp, ys));
+    qn[k] = hload(off(zp, yn));
   }
-  size_t o = o0;
-  for (int j = s.j0; j < s.j1; ++j, o += P) {
-    // loads of the rows needed PD iterations from now
-    const int rh = j + PD + 1;
-    const bool nv = rh <= hmax;
-    const size_t ho = (size_t)min(rh, hmax) * P;
+  for (int z = z0; z < z1; ++z) {
+    const size_t o = off(z, y);
+    // loads of the planes needed PD steps from now
+    const int zh = z + PD + 1;
+    const bool nv = zh <= zmax;
+    const size_t ho = off(min(zh, zmax), y);
     const RawH hn = hload(ho);
     const RawE en = eload(ho);
-    const int rp = min(j + PD, s.j1 - 1);
-    const B pn = point((size_t)rp * P);
-    RawH bn, tn;
-    if constexpr (D3) {
-      bn = hload(boff(rp));
-      tn = hload(toff(rp));
-    }
-    // row j+1 enters the window
-    R hN = hmake(q[0]);
-    T eN = emake(qe[0]);
+    const int zp = min(z + PD, z1 - 1);
+    const B pn = point(off(zp, y));
+    const RawH sn = hload(off(zp, ys));
+    const RawH nn = hload(off(zp, yn));
+    // plane z + 1 enters the window
+    R hA = hmake(q[0]);
+    T eA = emake(qe[0]);
     if (!qv[0]) {
-      hN = zrow<T, CPL>();
-      eN = T(0);
+      hA = zrow<T, CPL>();
+      eA = T(0);
     }
     R W, E;
     west_east<T, CPL>(hC, eC, eC, W, E);
-    if constexpr (D3) {
-      // in-plane neighbours stop at the plane's edges; the planes below and
-      // above exist for j >= plane and j + plane < ny
-      const R zr = zrow<T, CPL>();
-      const R Bl = j >= pl ? hmake(qb[0]) : zr;
-      const R Ab = j + pl < g.ny ? hmake(qt[0]) : zr;
-      comp(o, jp == 0 ? zr : hS, hC, jp == pl - 1 ? zr : hN, W, E, Bl, Ab, kz, pt[0]);
-      if (++jp == pl) jp = 0;
-    }
-    hS = hC;
-    hC = hN;
-    eC = eN;
+    const R zr = zrow<T, CPL>();
+    const R Sr = has_s ? hmake(qs[0]) : zr;
+    const R Nr = has_n ? hmake(qn[0]) : zr;
+    comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
+    hB = hC;
+    hC = hA;
+    eC = eA;
 #pragma unroll
     for (int k = 0; k + 1 < PD; ++k) {
       q[k] = q[k + 1];
       qe[k] = qe[k + 1];
       qv[k] = qv[k + 1];
       pt[k] = pt[k + 1];
-      if constexpr (D3) {
-        qb[k] = qb[k + 1];
-        qt[k] = qt[k + 1];
-      }
+      qs[k] = qs[k + 1];
+      qn[k] = qn[k + 1];
     }
     q[PD - 1] = hn;
     qe[PD - 1] = en;
     qv[PD - 1] = nv;
     pt[PD - 1] = pn;
-    if constexpr (D3) {
-      qb[PD - 1] = bn;
-      qt[PD - 1] = tn;
-    }
+    qs[PD - 1] = sn;
+    qn[PD - 1] = nn;
   }
 }
 
@@ -1104,7 +1117,7 @@ __device__ __forceinline__ void body_dot(const PassArgs& a, int t, double* lv) {
   // rows in the order the stencil passes of the geometry walk them (g.alt:
   // the odd wavefronts bottom up), so the sums follow the same tile order
   const bool up = g.alt && (s.wave & 1);
-  for (int i = s.j0; i < s.j1; ++i) {
+  for (int i = s.j0; i < s.j1; i += s.js) {
     const int j = up ? s.j1 - 1 - (i - s.j0) : i;
     const size_t o = (size_t)j * g.pitch + s.c;
     const R u = ldrow<double, CPL>(a.u + o), y = ldrow<double, CPL>(a.y + o);
@@ -1451,7 +1464,7 @@ __device__ __forceinline__ void body_flush(const PassArgs& a, int t, const doubl
   const Strip s = strip_of<CPL>(g, t);
   const int valid = g.nx - s.c;
   if (valid <= 0) return;
-  for (int j = s.j0; j < s.j1; ++j) {
+  for (int j = s.j0; j < s.j1; j += s.js) {
     const size_t o = (size_t)j * g.pitch + s.c;
     const R pv = ldrow<double, CPL>(P + o);
     R x = ldrow<double, CPL>(a.x + o);
@@ -1469,7 +1482,7 @@ __device__ __forceinline__ void body_flush_f32(const PassArgs& a, int t, const f
   const Strip s = strip_of<4>(g, t);
   const int valid = g.nx - s.c;
   if (valid <= 0) return;
-  for (int j = s.j0; j < s.j1; ++j) {
+  for (int j = s.j0; j < s.j1; j += s.js) {
     const size_t o = (size_t)j * g.pitch + s.c;
     const R pv = ldrow<float, 4>(P + o);
     R d = ldrow<float, 4>(a.df + o);
@@ -1541,7 +1554,7 @@ __device__ __forceinline__ void body_ref_update(const PassArgs& a, int t, const 
   const Strip s = strip_of<CPL>(g, t);
   const double sc_ = sc.al;
   const int valid = g.nx - s.c;
-  for (int j = s.j0; j < s.j1; ++j) {
+  for (int j = s.j0; j < s.j1; j += s.js) {
     const size_t o = (size_t)j * g.pitch + s.c;
     Row<double, CPL> x = ldrow<double, CPL>(a.x + o);
     const Row<float, CPL> d = ldrow<float, CPL>(a.df + o);

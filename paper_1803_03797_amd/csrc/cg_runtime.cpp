@@ -122,6 +122,29 @@ Geo make_geo(int nx, int ny, int fp32g, int rows) {
   return g;
 }
 
+// 3D z-march tiles (the 7-point operator): 4 in-plane rows, one per
+// wavefront, by zc planes; the stored grid is plane * nz rows.
+Geo make_geo3(int nx, int plane, int nz, int zc) {
+  Geo g = make_geo(nx, plane * nz, 0, 1);
+  g.plane = plane;
+  g.rows = std::max(1, zc);
+  g.th = kWavesPerTile;
+  g.nty = (plane + kWavesPerTile - 1) / kWavesPerTile;
+  g.tiles = g.ntx * g.nty * ((nz + g.rows - 1) / g.rows);
+  return g;
+}
+
+// Planes per z-march strip: about 1024 tiles (4 per CU), at least 8 planes
+// (a strip loads the planes before and after it again, so short strips
+// re-read) and at most 64.
+static int default_planes(int nx, int plane, int nz) {
+  const int ntx = (nx + 2 * kWave - 1) / (2 * kWave);
+  const int nty = (plane + kWavesPerTile - 1) / kWavesPerTile;
+  const int want_ntz = std::max(1, 1024 / std::max(1, ntx * nty));
+  const int zc = (nz + want_ntz - 1) / want_ntz;
+  return std::min(64, std::max(std::min(nz, 8), zc));
+}
+
 int default_rows(int nx, int ny, int fp32g) {
   const int cpl = fp32g ? 4 : 2, tw = kWave * cpl;
   const int ntx = (nx + tw - 1) / tw;
@@ -141,6 +164,7 @@ static int wg_rows(int nx, int ny) {
 
 int Ctx::unpinned_rows(const cg_problem* p, int fp32g) const {
   const int ny = rows_of(p);
+  if (p->nz > 1) return default_planes(p->nx, p->ny, p->nz);
   // pipelined FP64 5-point solves of 16M unknowns and more: about 4096
   // tiles, so that each of the one-per-CU work-groups walks some 16 short
   // ones (pcg_pass at 4096^2 with interleaved rows: 288 us with 8 rows per
@@ -210,8 +234,8 @@ Plan Ctx::plan(const cg_problem* p, bool allow_rr, bool interleave) {
       rows = unpinned_rows(p, pl.fp32g);
     }
   }
-  pl.g = make_geo(p->nx, ny, pl.fp32g, rows);
-  pl.g.plane = p->nz > 1 ? p->ny : 0;
+  // 3D: the z-march tiles, `rows` planes per strip
+  pl.g = p->nz > 1 ? make_geo3(p->nx, p->ny, p->nz, rows) : make_geo(p->nx, ny, pl.fp32g, rows);
   // The classic passes (32-row strips of separate vectors) walk the odd
   // wavefronts of a tile upward: the row between two wavefronts' strips is
   // then read by both at about the same time (a cache hit for the second),
@@ -300,7 +324,7 @@ size_t footprint_of(const cg_problem* p) {
   // same arithmetic as Ctx::plan, without a device (tiling affects only the
   // partial buffers, bounded here by one tile per 2 rows)
   const int fp32g = p->precision == CG_PREC_FP32_REFINED;
-  Geo g = make_geo(p->nx, rows_of(p), fp32g, 1);
+  Geo g = p->nz > 1 ? make_geo3(p->nx, p->ny, p->nz, 1) : make_geo(p->nx, rows_of(p), fp32g, 1);
   const size_t elems = (size_t)g.pitch * rows_of(p);
   const size_t v64 = round_up(elems * 8, Arena::kAlign), v32 = round_up(elems * 4, Arena::kAlign);
   size_t n64 = fp32g ? 2

@@ -109,6 +109,7 @@ constexpr int64_t kAutoRefineDof = 20480;
 cg_problem resolve_precision(const cg_problem& p);
 size_t footprint_of(const cg_problem* p);
 cgk::Geo make_geo(int nx, int ny, int fp32g, int rows);
+cgk::Geo make_geo3(int nx, int plane, int nz, int zc);
 int default_rows(int nx, int ny, int fp32g);
 
 class Server;  // serving scheduler (cg_serve.cpp)

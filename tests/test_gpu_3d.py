@@ -1,8 +1,8 @@
 """GPU parity of both CG variants on the 3D 7-point Laplacian (cg_problem.nz > 1):
-the tile passes with the planes below and above each row, against the 3D
-oracle in the library's tile order (bitwise) and in the textbook order (FP64
-tolerance); at 256^3 (16.8M unknowns) single-mode and finite-termination
-properties."""
+the tile passes marching along z (each wavefront walks one in-plane row through
+its planes), against the 3D oracle in the library's z-march tile order
+(bitwise) and in the textbook order (FP64 tolerance); at 256^3 (16.8M unknowns)
+single-mode and finite-termination properties."""
 import math
 import sys
 
@@ -15,8 +15,8 @@ from paper_1803_03797_amd import cg
 
 pytestmark = pytest.mark.gpu
 
-# single cells and rows, one plane row, ragged tiles, strips crossing planes,
-# several tile columns
+# single cells and rows, one-row planes, tiles ragged in y (rows % 4) and in z
+# (planes % the planes per strip), several tile columns
 SHAPES = [(1, 1, 2), (2, 3, 4), (64, 1, 3), (130, 7, 5), (37, 40, 23), (100, 64, 64),
           (257, 30, 9)]
 VARIANTS = (cg.CG_VARIANT_CLASSIC, cg.CG_VARIANT_PIPELINED)
@@ -41,10 +41,13 @@ def ctx(torch):
 
 
 def tile_order(ctx, nx, ny, nz, variant):
+    """The z-march order of the plan: tiles of `waves` in-plane rows by `rows`
+    planes, each wavefront summing its row over the planes."""
     info = ctx.cg_plan(nx, ny, variant=variant, nz=nz)
-    assert info.path == 0 and info.cols_per_lane == 2
-    return oracle.Order(info.cols_per_lane, info.lanes, info.waves, info.rows, info.threads2,
-                        alt=info.walk_alt)
+    assert info.path == 0 and info.cols_per_lane == 2 and info.walk_z == 1
+    assert info.walk_alt == 0
+    return oracle.Order.zmarch(info.cols_per_lane, info.lanes, info.waves, info.rows,
+                               info.threads2, ny)
 
 
 def rel(a, b):
