@@ -301,25 +301,31 @@ static double dot_canonical(int32_t nx, int32_t ny, const double* a, const doubl
   const int64_t ntx = (nx + TW - 1) / TW, nty = (ny + TH - 1) / TH;
   const int64_t T = ntx * nty;
   double* part = (double*)malloc((size_t)T * sizeof(double));
-  double lane[256], accs[16];
+  /* tiles are independent (each partial is formed alone, then summed in tile
+     order below): the OpenMP build splits them over threads, same bits */
+#pragma omp parallel for schedule(static) collapse(2)
   for (int64_t ty = 0; ty < nty; ++ty) {
     for (int64_t tx = 0; tx < ntx; ++tx) {
+      double lane[256], accs[4096];  /* accs[l * cpl + e]: lane l, column e */
       double tile = 0.0;
       for (int32_t w = 0; w < W; ++w) {
         int64_t j0 = ty * TH + (int64_t)w * R;
-        for (int32_t l = 0; l < L; ++l) {
-          for (int32_t e = 0; e < cpl; ++e) accs[e] = 0.0;
-          const int64_t j1 = (j0 + R < ny) ? j0 + R : ny;
-          const int up = o->alt && (w & 1);
-          for (int64_t i = j0; i < j1; ++i) {
-            const int64_t j = up ? j1 - 1 - (i - j0) : i;
-            for (int32_t e = 0; e < cpl; ++e) {
-              int64_t c = tx * TW + (int64_t)l * cpl + e;
-              if (c < nx) accs[e] = fma(a[j * nx + c], b[j * nx + c], accs[e]);
-            }
+        const int64_t j1 = (j0 + R < ny) ? j0 + R : ny;
+        const int up = o->alt && (w & 1);
+        for (int32_t k = 0; k < TW; ++k) accs[k] = 0.0;
+        /* every lane's accumulators take the wavefront's rows in the same
+           order (the row loop outside the lane loop only makes the memory
+           walk contiguous) */
+        for (int64_t i = j0; i < j1; ++i) {
+          const int64_t j = up ? j1 - 1 - (i - j0) : i;
+          for (int32_t k = 0; k < TW; ++k) {
+            const int64_t c = tx * TW + k;
+            if (c < nx) accs[k] = fma(a[j * nx + c], b[j * nx + c], accs[k]);
           }
-          double v = accs[0];
-          for (int32_t e = 1; e < cpl; ++e) v = v + accs[e];
+        }
+        for (int32_t l = 0; l < L; ++l) {
+          double v = accs[l * cpl];
+          for (int32_t e = 1; e < cpl; ++e) v = v + accs[l * cpl + e];
           lane[l] = v;
         }
         double wv = butterfly(lane, L);
@@ -402,24 +408,25 @@ static double dot_zmarch(int32_t nx, int32_t ny, const double* a, const double* 
   const int64_t ntx = (nx + TW - 1) / TW, nty = (pl + W - 1) / W, ntz = (nz + R - 1) / R;
   const int64_t T = ntx * nty * ntz;
   double* part = (double*)malloc((size_t)T * sizeof(double));
-  double lane[256], accs[16];
+#pragma omp parallel for schedule(static) collapse(3)
   for (int64_t tz = 0; tz < ntz; ++tz)
     for (int64_t ty = 0; ty < nty; ++ty)
       for (int64_t tx = 0; tx < ntx; ++tx) {
+        double lane[256], accs[4096];  /* accs[l * cpl + e]: lane l, column e */
         double tile = 0.0;
         for (int32_t w = 0; w < W; ++w) {
           const int64_t y = ty * W + w;
-          for (int32_t l = 0; l < L; ++l) {
-            for (int32_t e = 0; e < cpl; ++e) accs[e] = 0.0;
-            for (int64_t z = tz * R; y < pl && z < tz * R + R && z < nz; ++z) {
-              const int64_t j = z * pl + y;
-              for (int32_t e = 0; e < cpl; ++e) {
-                const int64_t c = tx * TW + (int64_t)l * cpl + e;
-                if (c < nx) accs[e] = fma(a[j * nx + c], b[j * nx + c], accs[e]);
-              }
+          for (int32_t k = 0; k < TW; ++k) accs[k] = 0.0;
+          for (int64_t z = tz * R; y < pl && z < tz * R + R && z < nz; ++z) {
+            const int64_t j = z * pl + y;
+            for (int32_t k = 0; k < TW; ++k) {
+              const int64_t c = tx * TW + k;
+              if (c < nx) accs[k] = fma(a[j * nx + c], b[j * nx + c], accs[k]);
             }
-            double v = accs[0];
-            for (int32_t e = 1; e < cpl; ++e) v = v + accs[e];
+          }
+          for (int32_t l = 0; l < L; ++l) {
+            double v = accs[l * cpl];
+            for (int32_t e = 1; e < cpl; ++e) v = v + accs[l * cpl + e];
             lane[l] = v;
           }
           const double wv = butterfly(lane, L);

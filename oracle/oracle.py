@@ -278,11 +278,16 @@ class Result(dict):
 
 
 def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
-       mode=MODE_SEQUENTIAL, order=None, history=0, rr_period=0):
+       mode=MODE_SEQUENTIAL, order=None, history=0, rr_period=0, all_cores=False):
     """Solve A x = b.  Returns (x, Result); with history=m also returns a dict of
     the first m records (gamma, r, p, x after 0, 1, ... updates).  rr_period
     > 0: the pipelined variant replaces its residuals every rr_period
-    iterations (no history then)."""
+    iterations (no history then).  all_cores: the OpenMP build, for large
+    canonical-mode solves: its canonical mode gives the same bits (tile
+    partials formed independently and summed in tile order, the SpMV and the
+    axpys element by element); its sequential-mode dots sum per-thread
+    partials, so they differ from the single-thread ones in rounding."""
+    lib = _load_omp() if all_cores else _load()
     if rr_period:
         if history:
             raise ValueError("no history with residual replacement")
@@ -291,8 +296,8 @@ def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
         x = np.zeros_like(b)
         res = _Result()
         o = C.byref(order) if order is not None else None
-        rc = _load().oracle_cg_rr(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol,
-                                  maxit, rr_period, C.byref(res))
+        rc = lib.oracle_cg_rr(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol,
+                              maxit, rr_period, C.byref(res))
         if rc < 0:
             raise ValueError("oracle_cg_rr rejected the call: %d" % rc)
         return x, Result(status=res.status, iterations=res.iterations,
@@ -311,8 +316,8 @@ def cg(b, nx, ny, variant=VARIANT_CLASSIC, tol=1e-8, maxit=2000, x0=None,
                     p=np.zeros((history, n)), x=np.zeros((history, n)))
         h = _History(history, 0, _ptr(hist["gamma"]), _ptr(hist["r"]), _ptr(hist["p"]),
                      _ptr(hist["x"]))
-    rc = _load().oracle_cg(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, maxit,
-                           C.byref(res), C.byref(h) if h is not None else None)
+    rc = lib.oracle_cg(variant, mode, o, nx, ny, _ptr(b), _ptr(x0a), _ptr(x), tol, maxit,
+                       C.byref(res), C.byref(h) if h is not None else None)
     if rc < 0:
         raise ValueError("oracle_cg rejected the call: %d" % rc)
     out = Result(status=res.status, iterations=res.iterations,
@@ -340,6 +345,10 @@ def _load_omp():
         lib.oracle_cg.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32, C.c_int32,
                                   P, P, P, C.c_double, C.c_int32, C.POINTER(_Result),
                                   C.POINTER(_History)]
+        lib.oracle_cg_rr.restype = C.c_int
+        lib.oracle_cg_rr.argtypes = [C.c_int32, C.c_int32, C.POINTER(Order), C.c_int32,
+                                     C.c_int32, P, P, P, C.c_double, C.c_int32, C.c_int32,
+                                     C.POINTER(_Result)]
         lib.oracle_last_solve_seconds.restype = C.c_double
         lib.oracle_threads.restype = C.c_int
         _lib_omp = lib
