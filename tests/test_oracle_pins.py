@@ -539,3 +539,20 @@ def test_refinement_last_inner_solve_stops_at_what_tol_needs():
     rt = np.linalg.norm(b.ravel() - sparse_A(nx, ny) @ x.ravel()) / np.linalg.norm(b)
     assert r.status == oracle.OR_OK and r.outer_iterations == 2
     assert 1e-8 < rt <= 1e-6
+
+
+def test_openmp_build_canonical_mode_gives_the_same_bits():
+    """The OpenMP build's canonical mode (tile partials formed in parallel,
+    then summed in tile order) returns the single-thread build's bits for both
+    variants, in the tile order with and without the alternating walk."""
+    nx, ny = 300, 190
+    b = np.random.default_rng(8).uniform(-1, 1, (ny, nx))
+    for o in (GPU_LIKE, oracle.Order(2, 64, 4, 32, 256, alt=1)):
+        for v in (0, 1):
+            x1, r1 = oracle.cg(b, nx, ny, variant=v, tol=1e-10, maxit=3000,
+                               mode=MODE_CANONICAL, order=o)
+            x2, r2 = oracle.cg(b, nx, ny, variant=v, tol=1e-10, maxit=3000,
+                               mode=MODE_CANONICAL, order=o, all_cores=True)
+            assert r1.iterations == r2.iterations
+            np.testing.assert_array_equal(x1, x2)
+            assert r1.rel_res_true == r2.rel_res_true
