@@ -132,8 +132,7 @@ typedef struct {
                               boundary, the next structured-grid case the paper's
                               Section I names; unknown (i, j, l) at (l ny + j) nx + i,
                               so b, x0 and x hold nx * ny * nz values; FP64, either
-                              variant, precond 0, cg_solve only (batches and serving
-                              reject it)                                            */
+                              variant, precond 0; alone, in batches and served      */
   int32_t rr_period;       /* 0: none.  k > 0 (even): residual replacement in the
                               pipelined variant (Algorithm 2) every k iterations:
                               q = A p, z = A q, r = b - A x and w = A r recomputed
@@ -157,7 +156,9 @@ typedef struct {
                               finite (A is then symmetric positive definite); other
                               values are not checked and make the result undefined
                               (typically CG_BREAKDOWN).  FP64, 2D (nz <= 1), either
-                              variant, precond 0, cg_solve only                    */
+                              variant, precond 0; alone, in batches and served (a
+                              served request's kx and ky are read when it is
+                              admitted, like its b)                                 */
   const double* ky;        /* with kx: the conductivities of the faces between rows,
                               (ny + 1) x nx row-major (kS = ky[j][i], kN = ky[j+1][i];
                               rows 0 and ny are the boundary faces)                */
@@ -246,8 +247,8 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
  * Solves are admitted in order while their footprint fits the arena and a
  * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
  * worst per-solve status; results[i] holds each outcome.  A breakdown of one
- * solve does not disturb the others.  3D, variable-coefficient and residual-
- * replacement problems are CG_E_INVALID here (cg_solve takes them). */
+ * solve does not disturb the others.  Residual-replacement problems are
+ * CG_E_INVALID here (cg_solve takes them). */
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
 
 /* Serving: queue one request (non-blocking).  A scheduler thread admits

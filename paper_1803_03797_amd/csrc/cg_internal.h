@@ -296,6 +296,12 @@ int step_max_blocks_per_cu();
 hipError_t launch_step_ppcg(const Slot* slots, const Item* items, const int* n_items,
                             const int* step_base, int k, int grid, hipStream_t st);
 int step_ppcg_max_blocks_per_cu();
+// Step *step_base + k of the resident solves on the 3D (op 1) or the
+// variable-coefficient (op 2) operator, over the items of launch_step (which
+// skips those solves); grid is any positive size.
+hipError_t launch_step_op(int op, const Slot* slots, const Item* items, const int* n_items,
+                          const int* step_base, int k, int grid, hipStream_t s);
+int step_op_max_blocks_per_cu(int op);
 // The Chebyshev passes (K_CHEB, K_CHEBW; f32: the refinement's K_CHEBF) of
 // step *step_base + k of the resident preconditioned solves with s Chebyshev
 // steps (1 <= s <= 8): work-groups of 512 threads stride over cinfo[2 s]

@@ -1606,19 +1606,19 @@ __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc,
 
 // The body of KIND with the x variant the transition chose (for paths that
 // decide on the device: the single-work-group solver and the step kernel).
-template <int KIND, int CPL>
+template <int KIND, int CPL, int OP = 0>
 __device__ __forceinline__ void run_body_any(const PassArgs& a, int t, const Sc& sc, double* lv) {
   if constexpr (KIND == K_PCG) {
-    if (sc.xu) run_body<K_PCGX, CPL>(a, t, sc, lv);
-    else run_body<K_PCG, CPL>(a, t, sc, lv);
+    if (sc.xu) run_body<K_PCGX, CPL, OP>(a, t, sc, lv);
+    else run_body<K_PCG, CPL, OP>(a, t, sc, lv);
   } else if constexpr (KIND == K_CG2) {
-    if (sc.xu) run_body<K_CG2X, CPL>(a, t, sc, lv);
-    else run_body<K_CG2, CPL>(a, t, sc, lv);
+    if (sc.xu) run_body<K_CG2X, CPL, OP>(a, t, sc, lv);
+    else run_body<K_CG2, CPL, OP>(a, t, sc, lv);
   } else if constexpr (KIND == K_CG2F) {
-    if (sc.xu) run_body<K_CG2FX, CPL>(a, t, sc, lv);
-    else run_body<K_CG2F, CPL>(a, t, sc, lv);
+    if (sc.xu) run_body<K_CG2FX, CPL, OP>(a, t, sc, lv);
+    else run_body<K_CG2F, CPL, OP>(a, t, sc, lv);
   } else {
-    run_body<KIND, CPL>(a, t, sc, lv);
+    run_body<KIND, CPL, OP>(a, t, sc, lv);
   }
 }
 
@@ -2807,7 +2807,7 @@ __device__ __forceinline__ PassArgs slot_args(const Slot& S, int m, int k0, int 
   return a;
 }
 
-template <int KIND, int CPL>
+template <int KIND, int CPL, int OP = 0>
 __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, State s,
                                           double* lds, int rev) {
   constexpr int DI = (KIND == K_FINAL) ? 1 : ndots_in<KIND>();
@@ -2853,9 +2853,15 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   for (int tt = it.t0; tt < it.t1; ++tt, par ^= 1) {
     const int t = rev ? it.t1 - 1 - (tt - it.t0) : tt;
     double lv[3] = {0.0, 0.0, 0.0};
-    run_body_any<KIND, CPL>(a, t, sc, lv);
+    if constexpr (KIND != K_FINAL) run_body_any<KIND, CPL, OP>(a, t, sc, lv);
     if constexpr (DO > 0) tile_partial<DO>(lv, a.part_out, T, t, lds + 8, par);
   }
+}
+
+// The operator of a resident solve: 0 the 5-point stencil, 1 the 7-point one
+// (3D), 2 the variable-coefficient 5-point one.
+__device__ __forceinline__ int slot_op(const Slot& S) {
+  return S.g.plane > 0 ? 1 : S.g.kc ? 2 : 0;
 }
 
 // At least three waves per SIMD (168 VGPRs, no spill): its largest pass body
@@ -2872,6 +2878,8 @@ __global__ __launch_bounds__(kGroup, 3) void k_step(const Slot* slots, const Ite
   for (int ii = blockIdx.x; ii < n; ii += gridDim.x) {
     const Item it = items[rev ? n - 1 - ii : ii];
     const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
+    // the 3D and variable-coefficient solves belong to k_step_op
+    if (slot_op(S) != 0) continue;
     const int m = step - S.admit_step;
     const State s = load_state_uniform(S.S[m & 1]);
     const int kind = __builtin_amdgcn_readfirstlane(s.kind);
@@ -2907,6 +2915,42 @@ __global__ __launch_bounds__(kGroup, 3) void k_step(const Slot* slots, const Ite
         case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds, rev); break;
         case K_FINAL: step_item<K_FINAL, 2>(S, it, m, s, lds, rev); break;
       }
+    }
+    __syncthreads();  // LDS reuse by the next item
+  }
+}
+
+// Step *step_base + k of the resident solves on the operator OP (1: 3D
+// 7-point, 2: variable coefficients; FP64 CG of either variant, no
+// preconditioner), over the same items as k_step, which leaves them alone: a
+// kernel of their own keeps their walkers' registers out of k_step.
+template <int OP>
+__global__ __launch_bounds__(kGroup) void k_step_op(const Slot* slots, const Item* items,
+                                                   const int* n_items, const int* step_base,
+                                                   int k) {
+  __shared__ double lds[kLdsPerGroup];
+  const int n = __builtin_amdgcn_readfirstlane(*n_items);
+  const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
+  const int rev = step & 1;
+  for (int ii = blockIdx.x; ii < n; ii += gridDim.x) {
+    const Item it = items[rev ? n - 1 - ii : ii];
+    const Slot& S = slots[__builtin_amdgcn_readfirstlane(it.slot)];
+    if (slot_op(S) != OP) continue;
+    const int m = step - S.admit_step;
+    const State s = load_state_uniform(S.S[m & 1]);
+    const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+    if (kind == K_DONE) {
+      if (it.t0 == 0 && threadIdx.x == 0) *S.S[(m + 1) & 1] = s;
+      continue;
+    }
+    switch (kind) {
+      case K_INIT_R: step_item<K_INIT_R, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_INIT_W: step_item<K_INIT_W, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_PCG: step_item<K_PCG, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_CG1: step_item<K_CG1, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_CG2: step_item<K_CG2, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_RESID: step_item<K_RESID, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_FINAL: step_item<K_FINAL, 2, OP>(S, it, m, s, lds, rev); break;
     }
     __syncthreads();  // LDS reuse by the next item
   }
@@ -3042,6 +3086,27 @@ hipError_t launch_step_ppcg(const Slot* slots, const Item* items, const int* n_i
   hipLaunchKernelGGL(k_step_ppcg, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items,
                      step_base, k);
   return hipGetLastError();
+}
+
+hipError_t launch_step_op(int op, const Slot* slots, const Item* items, const int* n_items,
+                          const int* step_base, int k, int grid, hipStream_t st) {
+  if (grid < 1 || (op != 1 && op != 2)) return hipErrorInvalidValue;
+  if (op == 1)
+    hipLaunchKernelGGL(k_step_op<1>, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items,
+                       step_base, k);
+  else
+    hipLaunchKernelGGL(k_step_op<2>, dim3(grid), dim3(kGroup), 0, st, slots, items, n_items,
+                       step_base, k);
+  return hipGetLastError();
+}
+
+int step_op_max_blocks_per_cu(int op) {
+  int n = 0;
+  const hipError_t e =
+      op == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_op<1>, kGroup, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_op<2>, kGroup, 0);
+  if (e != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 int step_ppcg_max_blocks_per_cu() {

@@ -164,6 +164,7 @@ class Engine {
     memset(&S, 0, sizeof(S));
     const Work& w = j->w;
     S.g = w.pl.g;
+    S.g.kc = w.kc;  // variable coefficients (null otherwise)
     S.variant = j->p.variant;
     S.refined = w.pl.refined ? 1 : 0;
     S.cpl4 = w.pl.fp32g;
@@ -431,11 +432,15 @@ class Engine {
     int* nn = (int*)(h_items_ + max_items_);
     *nn = n;
     // a preconditioned pipelined solve: its tile passes run in k_step_ppcg
-    // (bit 0 of the mask)
+    // (bit 0 of the mask); a 3D or variable-coefficient solve: its passes run
+    // in k_step_op (bits kOpBit and kOpBit + 1)
     for (int i = 0; i < n_; ++i) {
       Job* j = slot_job_[i];
-      if (j && j->w.pl.precond && !j->w.pl.refined && j->w.pl.variant == CG_VARIANT_PIPELINED)
+      if (!j || j->w.pl.on_side()) continue;
+      if (j->w.pl.precond && !j->w.pl.refined && j->w.pl.variant == CG_VARIANT_PIPELINED)
         cheb_mask_ |= 1u;
+      if (j->w.pl.g.plane > 0) cheb_mask_ |= 1u << kOpBit;
+      if (j->w.pl.vc) cheb_mask_ |= 1u << (kOpBit + 1);
     }
     // Chebyshev items, grouped by s (each group's count and offset in cinfo)
     int nc = 0;
@@ -482,6 +487,10 @@ class Engine {
     if (e == hipSuccess && (cheb_mask_ & 1u))
       e = launch_step_ppcg(d_slots_, d_items_, d_nitems_, d_step_, k,
                            std::max(8, step_ppcg_max_blocks_per_cu() * c_.num_cu), c_.st);
+    for (int op = 1; op <= 2 && e == hipSuccess; ++op)
+      if (cheb_mask_ & (1u << (kOpBit + op - 1)))
+        e = launch_step_op(op, d_slots_, d_items_, d_nitems_, d_step_, k,
+                           std::max(8, step_op_max_blocks_per_cu(op) * c_.num_cu), c_.st);
     for (int sd = 1; sd <= kChebMaxSteps && e == hipSuccess; ++sd)
       for (int f32 = 0; f32 < 2 && e == hipSuccess; ++f32)
         if (cheb_mask_ & (1u << (f32 ? kChebMaxSteps + sd : sd)))
@@ -519,7 +528,9 @@ class Engine {
   int* d_cinfo_ = nullptr;
   unsigned cheb_mask_ = 0;    // bit s (8 + s): Chebyshev steps s that any admitted FP64
                               // (refined) solve has used; bit 0: a preconditioned
-                              // pipelined solve was admitted
+                              // pipelined solve was admitted; bits kOpBit, kOpBit + 1:
+                              // a 3D, a variable-coefficient solve was admitted
+  static constexpr int kOpBit = 2 * kChebMaxSteps + 1;
   unsigned graph_mask_ = 0;   // ... when the cached chunk was captured
   Item* h_items_ = nullptr;
   int* h_idx_ = nullptr;

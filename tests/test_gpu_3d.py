@@ -166,15 +166,67 @@ def test_edge_cases(ctx, variant):
     np.testing.assert_array_equal(x, xo)
 
 
+def _served(ctx, probs):
+    import time
+    tickets = []
+    for k, p in enumerate(probs):
+        tickets.append(ctx.cg_submit(p))
+        if k % 3 == 2:
+            time.sleep(0.002)
+    out = {}
+    deadline = time.time() + 120
+    while len(out) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in out:
+                rc, r = ctx.cg_poll(t)
+                if rc != cg.CG_PENDING:
+                    out[t] = (rc, cg.cg_result.from_buffer_copy(r))
+        time.sleep(0.001)
+    assert len(out) == len(tickets)
+    return [out[t] for t in tickets]
+
+
+def test_batch_and_served_3d_solves_match_alone(ctx):
+    """3D requests of both variants beside 2D ones, batched and served: each
+    result bitwise the solve alone (the 3D ones on their own step kernel,
+    in the same z-march tiles and order), and the 3D ones bitwise the oracle
+    in that order."""
+    rng = np.random.default_rng(41)
+    mix = [(37, 40, 23, 0), (100, 64, 64, 1), (64, 64, 0, 0), (130, 7, 5, 1), (300, 190, 0, 1),
+           (2, 3, 4, 0), (257, 30, 9, 0)]
+    bs = [rng.uniform(-1, 1, (ny * max(nz, 1), nx)) for nx, ny, nz, _ in mix]
+
+    def prob(k, x):
+        nx, ny, nz, v = mix[k]
+        return cg.make_problem(bs[k], x, nx, ny, tol=1e-9, maxit=20000, variant=v, nz=nz)
+    xb = [np.zeros_like(b) for b in bs]
+    say("batch with 3D solves:", len(mix))
+    rc, res = ctx.cg_solve_batch([prob(k, x) for k, x in enumerate(xb)])
+    assert rc == cg.CG_OK
+    xv = [np.zeros_like(b) for b in bs]
+    served = _served(ctx, [prob(k, x) for k, x in enumerate(xv)])
+    for k, (nx, ny, nz, v) in enumerate(mix):
+        xa = np.zeros_like(bs[k])
+        rca, ra = ctx.cg_solve(prob(k, xa))
+        say("  %dx%dx%d v%d: batch %d served %d alone %d iterations" %
+            (nx, ny, nz, v, res[k].iterations, served[k][1].iterations, ra.iterations))
+        assert res[k].status == rca == served[k][0] == cg.CG_OK
+        assert res[k].iterations == served[k][1].iterations == ra.iterations
+        np.testing.assert_array_equal(xb[k], xa)
+        np.testing.assert_array_equal(xv[k], xa)
+        assert res[k].rel_res_true == ra.rel_res_true
+        if nz > 1 and nx * ny * nz <= 40000:
+            o = tile_order(ctx, nx, ny, nz, v)
+            xo, ro = oracle.cg3(bs[k], nx, ny, nz, variant=v, tol=1e-9, maxit=20000,
+                                mode=MODE_CANONICAL, order=o)
+            assert ro.iterations == ra.iterations
+            np.testing.assert_array_equal(xa, xo)
+
+
 def test_rejections(ctx):
     nx, ny, nz = 8, 8, 8
     b = np.ones((ny * nz, nx))
     x = np.zeros_like(b)
-    p = cg.make_problem(b, x, nx, ny, nz=nz)
-    with pytest.raises(cg.CGError):
-        ctx.cg_solve_batch([p])
-    with pytest.raises(cg.CGError):
-        ctx.cg_submit(p)
     for kw in (dict(precond=4), dict(precision=cg.CG_PREC_FP32_REFINED),
                dict(precision=cg.CG_PREC_FIXED)):
         args = dict(nz=nz)

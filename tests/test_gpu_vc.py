@@ -221,16 +221,61 @@ def test_edge_cases(ctx, variant):
     np.testing.assert_array_equal(x, xo)
 
 
+def test_batch_and_served_vc_solves_match_alone(ctx):
+    """Variable-coefficient requests of both variants beside constant-
+    coefficient ones, batched and served: each result bitwise the solve alone
+    (the former on their own step kernel, the coefficients staged at
+    admission), the former bitwise the oracle in the library's order."""
+    import time
+    rng = np.random.default_rng(43)
+    mix = [(300, 190, 1, 0), (130, 70, 1, 1), (64, 64, 0, 0), (513, 257, 1, 1), (100, 100, 0, 1),
+           (17, 3, 1, 0)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny, _, _ in mix]
+    ks = [faces(nx, ny, 50 + k) if vc else (None, None) for k, (nx, ny, vc, _) in enumerate(mix)]
+
+    def prob(k, x):
+        nx, ny, vc, v = mix[k]
+        return cg.make_problem(bs[k], x, nx, ny, tol=1e-9, maxit=20000, variant=v,
+                               kx=ks[k][0], ky=ks[k][1])
+    xb = [np.zeros_like(b) for b in bs]
+    say("batch with variable-coefficient solves:", len(mix))
+    rc, res = ctx.cg_solve_batch([prob(k, x) for k, x in enumerate(xb)])
+    assert rc == cg.CG_OK
+    xv = [np.zeros_like(b) for b in bs]
+    tickets = [ctx.cg_submit(prob(k, x)) for k, x in enumerate(xv)]
+    served = {}
+    deadline = time.time() + 120
+    while len(served) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in served:
+                rc2, r2 = ctx.cg_poll(t)
+                if rc2 != cg.CG_PENDING:
+                    served[t] = (rc2, cg.cg_result.from_buffer_copy(r2))
+        time.sleep(0.001)
+    assert len(served) == len(tickets)
+    for k, (nx, ny, vc, v) in enumerate(mix):
+        xa = np.zeros_like(bs[k])
+        rca, ra = ctx.cg_solve(prob(k, xa))
+        rcs, rs = served[tickets[k]]
+        say("  %dx%d vc=%d v%d: batch %d served %d alone %d iterations" %
+            (nx, ny, vc, v, res[k].iterations, rs.iterations, ra.iterations))
+        assert res[k].status == rca == rcs == cg.CG_OK
+        assert res[k].iterations == rs.iterations == ra.iterations
+        np.testing.assert_array_equal(xb[k], xa)
+        np.testing.assert_array_equal(xv[k], xa)
+        if vc:
+            o = tile_order(ctx, nx, ny, v)
+            xo, ro = oracle.cg_vc(bs[k], nx, ny, ks[k][0], ks[k][1], variant=v, tol=1e-9,
+                                  maxit=20000, mode=MODE_CANONICAL, order=o)
+            assert ro.iterations == ra.iterations
+            np.testing.assert_array_equal(xa, xo)
+
+
 def test_rejections(ctx):
     nx, ny = 16, 12
     kx, ky = faces(nx, ny, 1)
     b = np.ones((ny, nx))
     x = np.zeros_like(b)
-    p = cg.make_problem(b, x, nx, ny, kx=kx, ky=ky)
-    with pytest.raises(cg.CGError):
-        ctx.cg_solve_batch([p])
-    with pytest.raises(cg.CGError):
-        ctx.cg_submit(p)
     for kw in (dict(precond=4), dict(precision=cg.CG_PREC_FP32_REFINED),
                dict(precision=cg.CG_PREC_FIXED)):
         with pytest.raises(cg.CGError):
