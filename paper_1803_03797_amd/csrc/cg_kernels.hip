@@ -255,6 +255,8 @@ struct Strip {
   int j0, j1;  // rows of this wavefront's strip, j0, j0 + js, ... < j1; empty
                // when j0 >= j1
   int js;      // row step: 1, or the rows of a plane (3D z-march)
+  int y;       // 3D: the wavefront's in-plane row (may lie past the plane)
+  int z0, z1;  // 3D: the tile's planes [z0, z1), the same for its wavefronts
 };
 
 // 2D: tile t = ty * ntx + tx of 4 wavefronts x rows rows; wavefront w walks
@@ -277,6 +279,9 @@ __device__ __forceinline__ Strip strip_of(const Geo& g, int t) {
     const int y = (ty % g.nty) * kWavesPerTile + s.wave;
     const int z0 = (ty / g.nty) * g.rows, z1 = min(z0 + g.rows, nz);
     s.js = pl;
+    s.y = y;
+    s.z0 = z0;
+    s.z1 = z1;
     s.j0 = s.j1 = 0;
     if (y < pl) {
       s.j0 = z0 * pl + y;
@@ -285,6 +290,7 @@ __device__ __forceinline__ Strip strip_of(const Geo& g, int t) {
     return s;
   }
   s.js = 1;
+  s.y = s.z0 = s.z1 = 0;
   s.j0 = ty * g.th + s.wave * g.rows;
   s.j1 = min(s.j0 + g.rows, g.ny);
   return s;
@@ -898,40 +904,71 @@ __device__ __forceinline__ void walk2d(const Geo& g, const Strip& s, HLoad hload
                                   ALT && g.alt && (s.wave & 1));
 }
 
-// The entry point of every body, and the 7-point operator's walker: the
-// z-march (strip_of: the wavefront owns in-plane row y and walks it through
-// its planes).  Plane z - 1 (behind), z and z + 1 (ahead) of row y are the
-// window, as rows j - 1, j, j + 1 are in 2D; rows y - 1 and y + 1 of plane z
-// (the in-plane neighbours) are loaded with the point data, PD planes ahead:
-// they are the rows the tile's neighbouring wavefronts walk at the same step,
-// so they come from the caches instead of HBM.  comp gets S / N = rows y -/+ 1
-// (zero outside the plane) and below / above = planes z -/+ 1 (zero outside
-// the grid).
-template <typename T, int CPL, int PD, int OP, bool ALT = true, class HLoad, class HMake,
-          class ELoad, class EMake, class Point, class Comp>
-__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
-                                     ELoad eload, EMake emake, Point point, Comp comp) {
-  if constexpr (OP != 1) {
-    walk2d<T, CPL, PD, OP, ALT>(g, s, hload, hmake, eload, emake, point, comp);
-    return;
-  }
+// The 7-point walker's in-plane neighbours, rows y - 1 and y + 1 of the plane
+// a wavefront is at, are the rows the tile's other wavefronts hold at the
+// same step: each wavefront publishes its row in an LDS exchange buffer,
+// wavefronts 0 and 3 also the tile's outer rows y0 - 1 and y0 + 4, and after
+// one barrier per plane each reads its two neighbours.  The outer-row loads:
+//   ZX_EDGE  issued by wavefronts 0 and 3 only;
+//   ZX_ALL   issued by every wavefront (those of wavefronts 1 and 2 read
+//            their own row and leave it unused), so that the loads of a
+//            step take no branch.
+// Which is faster depends on the pass (measured at 256^3): ZX_EDGE where the
+// halo vector costs two loads a row (classic pass 1) and for the odd
+// pipelined pass, ZX_ALL elsewhere.  Loading the neighbour rows in each
+// wavefront instead (no exchange) ran classic pass 1 at 110.9 us against
+// 88.8.
+constexpr int ZX_EDGE = 1, ZX_ALL = 2;
+
+// The exchange rows: two buffers (alternate planes) of six rows (the tile's
+// outer row y0 - 1, its four rows, its outer row y0 + 4) of one FP64 pair per
+// lane.
+__shared__ double zm_x[2 * (kWavesPerTile + 2) * kWave * 2];
+
+__device__ __forceinline__ void zm_store(double* xb, int slot, int lane, const Row<double, 2>& v) {
+  *reinterpret_cast<double2*>(xb + (slot * kWave + lane) * 2) = make_double2(v.e[0], v.e[1]);
+}
+
+__device__ __forceinline__ Row<double, 2> zm_load(const double* xb, int slot, int lane) {
+  const double2 d = *reinterpret_cast<const double2*>(xb + (slot * kWave + lane) * 2);
+  Row<double, 2> v;
+  v.e[0] = d.x;
+  v.e[1] = d.y;
+  return v;
+}
+
+// The z-march with the exchange (ALLO: the ZX_ALL outer-row loads).  After one
+// barrier per plane every wavefront reads its two neighbours (zero outside
+// the plane).  A wavefront whose row lies past the plane still takes every
+// step (its loads read a valid row, its exchange row is zero, it computes
+// nothing), so the four wavefronts pass the same barriers.
+template <typename T, int CPL, int PD, bool ALLO, class HLoad, class HMake, class ELoad,
+          class EMake, class Point, class Comp>
+__device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
+                                          ELoad eload, EMake emake, Point point, Comp comp) {
+  static_assert(sizeof(T) == 8 && CPL == 2, "the 3D walker exchanges FP64 pairs");
   using R = Row<T, CPL>;
   using RawH = decltype(hload((size_t)0));
   using RawE = decltype(eload((size_t)0));
   using B = decltype(point((size_t)0));
-  if (s.j0 >= s.j1) return;
   const size_t P = g.pitch;
   const int pl = g.plane, nz = g.ny / pl;
-  const int y = s.j0 % pl;                          // the wavefront's in-plane row
-  const int z0 = s.j0 / pl, z1 = (s.j1 - y) / pl;  // its planes [z0, z1)
+  const int w = __builtin_amdgcn_readfirstlane(s.wave);
+  const int z0 = s.z0, z1 = s.z1;
+  const bool live = s.y < pl;
+  const int y = live ? s.y : pl - 1;
   auto off = [&](int z, int yy) { return ((size_t)z * pl + yy) * P; };
-  // the in-plane neighbours' rows (a row outside the plane is replaced by
-  // row y, whose value is then ignored)
-  const bool has_s = y > 0, has_n = y + 1 < pl;
-  const int ys = has_s ? y - 1 : y, yn = has_n ? y + 1 : y;
+  // the outer row this wavefront forms: y0 - 1 (wavefront 0), y0 + 4 (3)
+  const bool outer = w == 0 || w == kWavesPerTile - 1;
+  const int yo = (w == 0) ? s.y - 1 : s.y + 1;
+  const bool has_o = outer && yo >= 0 && yo < pl;
+  const int yoc = has_o ? yo : y;
+  const int oslot = (w == 0) ? 0 : kWavesPerTile + 1;
   const int zmax = min(z1, nz - 1);  // last plane worth loading ahead
   const Kc<T, CPL> kz{};
-  R hB = zrow<T, CPL>();  // plane z - 1
+  const R zr = zrow<T, CPL>();
+  __syncthreads();  // every wavefront has read the previous tile's exchange rows
+  R hB = zr;  // plane z - 1
   {
     const R v = hmake(hload(off(max(z0 - 1, 0), y)));
     if (z0 > 0) hB = v;
@@ -940,20 +977,20 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
   T eC = emake(eload(off(z0, y)));
   RawH q[PD];   // raw row y of planes z+1 .. z+PD
   RawE qe[PD];
-  bool qv[PD];  // the plane exists (inside the grid, not past the strip's halo)
+  bool qv[PD];  // the plane exists (inside the grid, not past the tile's halo)
   B pt[PD];     // point data of planes z .. z+PD-1
-  RawH qs[PD], qn[PD];  // rows y - 1, y + 1 of planes z .. z+PD-1
+  RawH qo[PD];  // the outer row of planes z .. z+PD-1 (wavefronts 0 and 3)
 #pragma unroll
   for (int k = 0; k < PD; ++k) {
-    const int zr = z0 + 1 + k;
-    qv[k] = zr <= zmax;
-    const size_t ro = off(min(zr, zmax), y);
+    const int zr1 = z0 + 1 + k;
+    qv[k] = zr1 <= zmax;
+    const size_t ro = off(min(zr1, zmax), y);
     q[k] = hload(ro);
     qe[k] = eload(ro);
     const int zp = min(z0 + k, z1 - 1);
     pt[k] = point(off(zp, y));
-    qs[k] = hload(off(zp, ys));
-    qn[k] = hload(off(zp, yn));
+    qo[k] = q[k];  // (unused off the outer wavefronts)
+    if (ALLO || outer) qo[k] = hload(off(zp, yoc));
   }
   for (int z = z0; z < z1; ++z) {
     const size_t o = off(z, y);
@@ -965,21 +1002,25 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
     const RawE en = eload(ho);
     const int zp = min(z + PD, z1 - 1);
     const B pn = point(off(zp, y));
-    const RawH sn = hload(off(zp, ys));
-    const RawH nn = hload(off(zp, yn));
+    RawH on = hn;
+    if (ALLO || outer) on = hload(off(zp, yoc));
+    // this plane's rows into the exchange buffer
+    double* xb = zm_x + ((z - z0) & 1) * ((kWavesPerTile + 2) * kWave * 2);
+    zm_store(xb, w + 1, s.lane, live ? hC : zr);
+    if (outer) zm_store(xb, oslot, s.lane, has_o ? hmake(qo[0]) : zr);
     // plane z + 1 enters the window
     R hA = hmake(q[0]);
     T eA = emake(qe[0]);
     if (!qv[0]) {
-      hA = zrow<T, CPL>();
+      hA = zr;
       eA = T(0);
     }
     R W, E;
     west_east<T, CPL>(hC, eC, eC, W, E);
-    const R zr = zrow<T, CPL>();
-    const R Sr = has_s ? hmake(qs[0]) : zr;
-    const R Nr = has_n ? hmake(qn[0]) : zr;
-    comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
+    __syncthreads();
+    const R Sr = zm_load(xb, w, s.lane);
+    const R Nr = zm_load(xb, w + 2, s.lane);
+    if (live) comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
     hB = hC;
     hC = hA;
     eC = eA;
@@ -989,16 +1030,30 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
       qe[k] = qe[k + 1];
       qv[k] = qv[k + 1];
       pt[k] = pt[k + 1];
-      qs[k] = qs[k + 1];
-      qn[k] = qn[k + 1];
+      qo[k] = qo[k + 1];
     }
     q[PD - 1] = hn;
     qe[PD - 1] = en;
     qv[PD - 1] = nv;
     pt[PD - 1] = pn;
-    qs[PD - 1] = sn;
-    qn[PD - 1] = nn;
+    qo[PD - 1] = on;
   }
+}
+
+// The entry point of every body, and the 7-point operator's walker: the
+// z-march (strip_of: the wavefront owns in-plane row y and walks it through
+// the tile's planes).  Plane z - 1 (behind), z and z + 1 (ahead) of row y are
+// the window, as rows j - 1, j, j + 1 are in 2D; ZX picks the form of the
+// outer-row loads.  comp gets S / N = rows y -/+ 1 (zero outside the
+// plane) and below / above = planes z -/+ 1 (zero outside the grid).
+template <typename T, int CPL, int PD, int OP, bool ALT = true, int ZX = ZX_ALL, class HLoad,
+          class HMake, class ELoad, class EMake, class Point, class Comp>
+__device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
+                                     ELoad eload, EMake emake, Point point, Comp comp) {
+  if constexpr (OP != 1)
+    walk2d<T, CPL, PD, OP, ALT>(g, s, hload, hmake, eload, emake, point, comp);
+  else
+    zwalk_xch<T, CPL, PD, ZX == ZX_ALL>(g, s, hload, hmake, eload, emake, point, comp);
 }
 
 #ifndef CG1_PREFETCH
@@ -1013,13 +1068,13 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #endif
 
 // Loaders for a halo vector that is stored as is.
-template <typename T, int CPL, int OP, bool ALT = true, class Point, class Comp>
+template <typename T, int CPL, int OP, bool ALT = true, int ZX = ZX_ALL, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
   const int c = s.c;
 #if EDGE_MASKED
-  walk<T, CPL, WALK_PREFETCH, OP, ALT>(
+  walk<T, CPL, WALK_PREFETCH, OP, ALT, ZX>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; },
       [=](size_t off) {
@@ -1029,7 +1084,7 @@ __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T
       },
       [=](T v) { return v; }, point, comp);
 #else
-  walk<T, CPL, WALK_PREFETCH, OP, ALT>(
+  walk<T, CPL, WALK_PREFETCH, OP, ALT, ZX>(
       g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
       [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
       [=](T v) { return ea.emask ? v : T(0); }, point, comp);
@@ -1149,7 +1204,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk_plain<double, CPL, OP, false>(
+  walk_plain<double, CPL, OP, false, XU ? ZX_ALL : ZX_EDGE>(
       g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
@@ -1349,7 +1404,7 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
     T r, po;
   };
   const EdgeAddr ea = edge_addr<CPL>(s, g);
-  walk<T, CPL, CG1_PREFETCH, OP>(
+  walk<T, CPL, CG1_PREFETCH, OP, true, ZX_EDGE>(
       g, s,
       [=](size_t off) {
         Raw v;
