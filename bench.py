@@ -58,7 +58,7 @@ BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors the library's 134 MB
 # copy kernel gives for the same counters); set to None whenever pcg_pass
 # changes, until the counters are taken again.
-PCG_TRAFFIC_BYTES = 1647362579
+PCG_TRAFFIC_BYTES = 1646594743
 # The same for pcg_pass of the variable-coefficient operator at 4096 x 4096
 # (128 algorithmic bytes per unknown: 96 of vectors, 32 of coefficients).
 VC_TRAFFIC_BYTES = 2161653028
