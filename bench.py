@@ -54,6 +54,7 @@ BYTES_PER_DOF = {"pcg_pass": 96, "pcg_pass_nx": 80, "stencil_dot": 24, "update_n
                  "update_norm_nx": 24}
 # algorithmic bytes per unknown and iteration, averaged over an odd/even pair
 BYTES_PER_ITER = {"classic": 24 + (48 + 24) / 2, "pipelined": (96 + 80) / 2}
+OP_NAMES = {"2d": "", "3d": " on the 7-point operator", "vc": " with variable coefficients"}
 # HBM bytes per pcg_pass launch at 4096 x 4096 from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors the library's 134 MB
 # copy kernel gives for the same counters); set to None whenever pcg_pass
@@ -341,29 +342,46 @@ def bench_batch(args):
 
     from paper_1803_03797_amd import workloads
     w = workloads.BATCH
-    shapes = workloads.batch_shapes(w["count"])[:args.count]
-    bs = [torch.from_numpy(workloads.batch_rhs(m, nx, ny)).cuda()
-          for m, (nx, ny) in enumerate(shapes)]
+    op = args.batch_op
+    pc = args.batch_precond
+    if pc and op != "2d":
+        raise SystemExit("--batch-precond applies to the 5-point operator only")
+    if op == "3d":
+        shapes = workloads.batch_shapes3(w["count"])[:args.count]
+        bs = [torch.from_numpy(workloads.batch_rhs3(m, *s)).cuda() for m, s in enumerate(shapes)]
+        dof = np.array([nx * ny * nz for nx, ny, nz in shapes], dtype=float)
+    else:
+        shapes = workloads.batch_shapes(w["count"])[:args.count]
+        bs = [torch.from_numpy(workloads.batch_rhs(m, nx, ny)).cuda()
+              for m, (nx, ny) in enumerate(shapes)]
+        dof = np.array([nx * ny for nx, ny in shapes], dtype=float)
+    faces = [None] * len(shapes)
+    if op == "vc":
+        faces = [tuple(torch.from_numpy(f).cuda() for f in workloads.batch_faces(m, nx, ny))
+                 for m, (nx, ny) in enumerate(shapes)]
     xb = [torch.zeros_like(b) for b in bs]
     xs = [torch.zeros_like(b) for b in bs]
-    dof = np.array([nx * ny for nx, ny in shapes], dtype=float)
     ctx = cg.Context(device=0, arena_bytes=8 << 30)
-    pc = args.batch_precond
-    mk = lambda b, x, s: cg.make_problem(b, x, s[0], s[1], tol=w["tol"], maxit=w["maxit"],
-                                         variant=cg.CG_VARIANT_PIPELINED, precond=pc)
+
+    def mk(m, x):
+        s, f = shapes[m], faces[m]
+        return cg.make_problem(bs[m], x, s[0], s[1], tol=w["tol"], maxit=w["maxit"],
+                               variant=cg.CG_VARIANT_PIPELINED, precond=pc,
+                               nz=s[2] if op == "3d" else 0,
+                               kx=f[0] if f else None, ky=f[1] if f else None)
     # warm (graph capture and code paths), then timed
-    ctx.cg_solve_batch([mk(b, x, s) for b, x, s in list(zip(bs, xb, shapes))[:8]])
+    ctx.cg_solve_batch([mk(m, xb[m]) for m in range(min(8, len(shapes)))])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, res = ctx.cg_solve_batch([mk(b, x, s) for b, x, s in zip(bs, xb, shapes)])
+    rc, res = ctx.cg_solve_batch([mk(m, xb[m]) for m in range(len(shapes))])
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     its = np.array([r.iterations for r in res], dtype=float)
     log("batched: %.3f s, status %s" % (tb, cg.cg_status_str(rc)))
     t0 = time.perf_counter()
     res1 = []
-    for b, x, s in zip(bs, xs, shapes):
-        rc1, r1 = ctx.cg_solve(mk(b, x, s))
+    for m in range(len(shapes)):
+        rc1, r1 = ctx.cg_solve(mk(m, xs[m]))
         res1.append(r1)
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
@@ -378,30 +396,41 @@ def bench_batch(args):
         t = time.perf_counter()
         cw = 0.0
         for m in order:
-            nx, ny = shapes[m]
+            nx, ny = shapes[m][:2]
             if pc:
                 xo, ro = oracle.pcg(bs[m].cpu().numpy(), nx, ny, pc, tol=w["tol"],
                                     maxit=w["maxit"], variant=1)
+            elif op == "3d":
+                xo, ro = oracle.cg3(bs[m].cpu().numpy(), nx, ny, shapes[m][2], variant=1,
+                                    tol=w["tol"], maxit=w["maxit"])
+            elif op == "vc":
+                xo, ro = oracle.cg_vc(bs[m].cpu().numpy(), nx, ny, faces[m][0].cpu().numpy(),
+                                      faces[m][1].cpu().numpy(), variant=1, tol=w["tol"],
+                                      maxit=w["maxit"])
             else:
                 xo, ro = oracle.cg(bs[m].cpu().numpy(), nx, ny, variant=1, tol=w["tol"],
                                    maxit=w["maxit"])
-            cw += nx * ny * ro.iterations
+            cw += dof[m] * ro.iterations
         ct = time.perf_counter() - t
         cpu = {"value": round(cw / ct / 1e9, 5), "unit": "GDOF-iter/s", "cores": 1,
                "kind": "oracle",
                "sample": "the %d smallest of the solves, pipelined CG%s, explicit CSR, single "
-                         "thread (%.1f s)" % (len(order), " + Chebyshev s=%d" % pc if pc else "",
-                                              ct),
+                         "thread (%.1f s)" % (len(order), " + Chebyshev s=%d" % pc if pc else
+                                              OP_NAMES[op], ct),
                "extrapolated_batch_seconds": round(work / (cw / ct), 1)}
+    recipe = {"2d": "sides i.i.d. from {64..1024} per axis",
+              "3d": "3D grids, sides i.i.d. from {16, 32, 48, 64, 96} per axis",
+              "vc": "sides i.i.d. from {64..1024} per axis, face conductivities "
+                    "i.i.d. U[0.5, 2]"}[op]
+    per_iter = BYTES_PER_ITER["pipelined"] + (32 if op == "vc" else 0)
     emit({"metric": "batch solves/s (pipelined FP64, tol 1e-8, multi-solve step kernel)",
-          "workload": "batch", "chebyshev_steps": pc,
-          "config": {"workload": "%d solves, sides i.i.d. from {64..1024} per axis, b~U[-1,1]"
-                                 % len(shapes), "total_dof": int(dof.sum())},
+          "workload": "batch", "operator": op, "chebyshev_steps": pc,
+          "config": {"workload": "%d solves, %s, b~U[-1,1]" % (len(shapes), recipe),
+                     "total_dof": int(dof.sum())},
           "dtype": "f64",
           "batched": {"seconds": round(tb, 4), "solves_per_s": round(len(shapes) / tb, 2),
                       "GDOF_iter_s": round(work / tb / 1e9, 3),
-                      "algorithmic_GBps": round(BYTES_PER_ITER["pipelined"] * work / tb / 1e9,
-                                                1)},
+                      "algorithmic_GBps": round(per_iter * work / tb / 1e9, 1)},
           "one_by_one": {"seconds": round(ts, 4), "solves_per_s": round(len(shapes) / ts, 2),
                          "GDOF_iter_s": round(work / ts / 1e9, 3)},
           "speedup": round(ts / tb, 3), "status": cg.cg_status_str(rc),
@@ -1231,6 +1260,9 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=16)
     ap.add_argument("--n-huge", type=int, default=8192)
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.5])
+    ap.add_argument("--batch-op", choices=("2d", "3d", "vc"), default="2d",
+                    help="batch workload: the 5-point operator, 3D grids or variable "
+                         "coefficients")
     ap.add_argument("--batch-precond", type=int, default=0,
                     help="--workload batch: Chebyshev steps of every solve (0: none)")
     ap.add_argument("--serve-precond", type=int, default=0,

@@ -81,6 +81,30 @@ def batch_rhs(m: int, nx: int, ny: int):
     return uniform_rhs(nx, ny, generator(2, m))
 
 
+# -- batches of the other operators: 3D grids with sides i.i.d. from
+#    {16, 32, 48, 64, 96} per axis (workload 7), or the 2D batch's grids with
+#    face conductivities i.i.d. uniform[0.5, 2] (workload 8); b ~ U[-1, 1]
+#    per item --
+BATCH3_SIDES = (16, 32, 48, 64, 96)
+
+
+def batch_shapes3(count: int = 256, sides=BATCH3_SIDES):
+    rng = generator(7)
+    n = rng.choice(np.asarray(sides), size=(count, 3))
+    return [(int(a), int(b), int(c)) for a, b, c in n]
+
+
+def batch_rhs3(m: int, nx: int, ny: int, nz: int):
+    """b of item m on an nx x ny x nz grid, as ny*nz rows of nx."""
+    return uniform_rhs(nx, ny * nz, generator(7, m))
+
+
+def batch_faces(m: int, nx: int, ny: int, lo: float = 0.5, hi: float = 2.0):
+    """(kx, ky) of item m: (ny, nx + 1) and (ny + 1, nx), i.i.d. uniform[lo, hi]."""
+    rng = generator(8, m)
+    return rng.uniform(lo, hi, (ny, nx + 1)), rng.uniform(lo, hi, (ny + 1, nx))
+
+
 # -- workload 3: 8192 x 8192, b ~ N(0,1), refinement to 1e-10, inner 1e-4 --
 HUGE = dict(nx=8192, ny=8192, tol=1e-10, inner_tol=1e-4, maxit=200000)
 
