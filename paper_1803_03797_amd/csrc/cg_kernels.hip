@@ -2995,10 +2995,14 @@ __global__ __launch_bounds__(kGroup, 3) void k_step(const Slot* slots, const Ite
 // 7-point, 2: variable coefficients; FP64 CG of either variant, no
 // preconditioner), over the same items as k_step, which leaves them alone: a
 // kernel of their own keeps their walkers' registers out of k_step.
+// The 7-point form fits three waves per SIMD (168 VGPRs, no scratch); the
+// variable-coefficient one would spill at three and keeps two (190 VGPRs).
 template <int OP>
-__global__ __launch_bounds__(kGroup) void k_step_op(const Slot* slots, const Item* items,
-                                                   const int* n_items, const int* step_base,
-                                                   int k) {
+__global__ __launch_bounds__(kGroup, OP == 1 ? 3 : 2) void k_step_op(const Slot* slots,
+                                                                      const Item* items,
+                                                                      const int* n_items,
+                                                                      const int* step_base,
+                                                                      int k) {
   __shared__ double lds[kLdsPerGroup];
   const int n = __builtin_amdgcn_readfirstlane(*n_items);
   const int step = __builtin_amdgcn_readfirstlane(*step_base) + k;
