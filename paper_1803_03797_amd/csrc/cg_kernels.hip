@@ -929,11 +929,11 @@ __device__ __forceinline__ void walk2d(const Geo& g, const Strip& s, HLoad hload
 //   ZX_ALL   issued by every wavefront (those of wavefronts 1 and 2 read
 //            their own row and leave it unused), so that the loads of a
 //            step take no branch.
-// Which is faster depends on the pass (measured at 256^3): ZX_EDGE where the
-// halo vector costs two loads a row (classic pass 1) and for the odd
-// pipelined pass, ZX_ALL elsewhere.  Loading the neighbour rows in each
-// wavefront instead (no exchange) ran classic pass 1 at 110.9 us against
-// 88.8.
+// Which is faster depends on the pass (measured at 256^3): ZX_EDGE for the
+// odd pipelined pass, ZX_ALL for the others; classic pass 1, whose halo
+// vector costs two loads a row, takes zwalk_split below (86.2 -> 79.6 us by
+// rocprofv3 against ZX_EDGE; loading the neighbour rows in each wavefront
+// instead of any exchange ran it at 108.0 us).
 constexpr int ZX_EDGE = 1, ZX_ALL = 2;
 
 // The exchange rows: two buffers (alternate planes) of six rows (the tile's
@@ -1036,6 +1036,123 @@ __device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hl
     __syncthreads();
     const R Sr = zm_load(xb, w, s.lane);
     const R Nr = zm_load(xb, w + 2, s.lane);
+    if (live) comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
+    hB = hC;
+    hC = hA;
+    eC = eA;
+#pragma unroll
+    for (int k = 0; k + 1 < PD; ++k) {
+      q[k] = q[k + 1];
+      qe[k] = qe[k + 1];
+      qv[k] = qv[k + 1];
+      pt[k] = pt[k + 1];
+      qo[k] = qo[k + 1];
+    }
+    q[PD - 1] = hn;
+    qe[PD - 1] = en;
+    qv[PD - 1] = nv;
+    pt[PD - 1] = pn;
+    qo[PD - 1] = on;
+  }
+}
+
+// The raw halves of the tile's outer rows for zwalk_split: two buffers of
+// four rows (row y0 - 1's first and second vector, then row y0 + 4's).
+__shared__ double zm_r[2 * 4 * kWave * 2];
+
+// The z-march of a pass whose halo vector is formed from two vectors (classic
+// pass 1: p = r + beta p_old).  As zwalk_xch, but the tile's two outer rows
+// cost four row loads, one per wavefront: wavefront w loads vector w & 1 of
+// row y0 - 1 (w < 2) or y0 + 4 (w >= 2) and publishes it raw; after the
+// barrier wavefront 0 joins row y0 - 1's halves into its south neighbour and
+// wavefront 3 row y0 + 4's into its north one, with the same arithmetic as
+// hmake.  Every wavefront then issues three row loads a plane (against four
+// for wavefronts 0 and 3 and two for 1 and 2 in zwalk_xch's ZX_EDGE form).
+//   hpart(off, k) -> Row: vector k of the halo sources at offset off
+//   hjoin(a, b)   -> Row: hmake of the raw pair (a, b)
+template <typename T, int CPL, int PD, class HLoad, class HMake, class HPart, class HJoin,
+          class ELoad, class EMake, class Point, class Comp>
+__device__ __forceinline__ void zwalk_split(const Geo& g, const Strip& s, HLoad hload,
+                                            HMake hmake, HPart hpart, HJoin hjoin, ELoad eload,
+                                            EMake emake, Point point, Comp comp) {
+  static_assert(sizeof(T) == 8 && CPL == 2, "the 3D walker exchanges FP64 pairs");
+  using R = Row<T, CPL>;
+  using RawH = decltype(hload((size_t)0));
+  using RawE = decltype(eload((size_t)0));
+  using B = decltype(point((size_t)0));
+  const size_t P = g.pitch;
+  const int pl = g.plane, nz = g.ny / pl;
+  const int w = __builtin_amdgcn_readfirstlane(s.wave);
+  const int z0 = s.z0, z1 = s.z1;
+  const bool live = s.y < pl;
+  const int y = live ? s.y : pl - 1;
+  const int y0 = s.y - w;  // the tile's first in-plane row
+  auto off = [&](int z, int yy) { return ((size_t)z * pl + yy) * P; };
+  // the outer half this wavefront loads (a row outside the plane is replaced
+  // by row y, whose value is then ignored)
+  const int yo = (w < 2) ? y0 - 1 : y0 + kWavesPerTile;
+  const int yoc = (yo >= 0 && yo < pl) ? yo : y;
+  const int part = w & 1;
+  const bool has_s = y0 > 0, has_n = y0 + kWavesPerTile < pl;  // for wavefronts 0 / 3
+  const int zmax = min(z1, nz - 1);  // last plane worth loading ahead
+  const Kc<T, CPL> kz{};
+  const R zr = zrow<T, CPL>();
+  __syncthreads();  // every wavefront has read the previous tile's exchange rows
+  R hB = zr;  // plane z - 1
+  {
+    const R v = hmake(hload(off(max(z0 - 1, 0), y)));
+    if (z0 > 0) hB = v;
+  }
+  R hC = hmake(hload(off(z0, y)));
+  T eC = emake(eload(off(z0, y)));
+  RawH q[PD];   // raw row y of planes z+1 .. z+PD
+  RawE qe[PD];
+  bool qv[PD];  // the plane exists (inside the grid, not past the tile's halo)
+  B pt[PD];     // point data of planes z .. z+PD-1
+  R qo[PD];     // this wavefront's outer half of planes z .. z+PD-1
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    const int zr1 = z0 + 1 + k;
+    qv[k] = zr1 <= zmax;
+    const size_t ro = off(min(zr1, zmax), y);
+    q[k] = hload(ro);
+    qe[k] = eload(ro);
+    const int zp = min(z0 + k, z1 - 1);
+    pt[k] = point(off(zp, y));
+    qo[k] = hpart(off(zp, yoc), part);
+  }
+  for (int z = z0; z < z1; ++z) {
+    const size_t o = off(z, y);
+    // loads of the planes needed PD steps from now
+    const int zh = z + PD + 1;
+    const bool nv = zh <= zmax;
+    const size_t ho = off(min(zh, zmax), y);
+    const RawH hn = hload(ho);
+    const RawE en = eload(ho);
+    const int zp = min(z + PD, z1 - 1);
+    const B pn = point(off(zp, y));
+    const R on = hpart(off(zp, yoc), part);
+    // this plane's rows and outer halves into the exchange buffers
+    const int b = (z - z0) & 1;
+    double* xb = zm_x + b * ((kWavesPerTile + 2) * kWave * 2);
+    double* rb = zm_r + b * (4 * kWave * 2);
+    zm_store(xb, w + 1, s.lane, live ? hC : zr);
+    zm_store(rb, w, s.lane, qo[0]);
+    // plane z + 1 enters the window
+    R hA = hmake(q[0]);
+    T eA = emake(qe[0]);
+    if (!qv[0]) {
+      hA = zr;
+      eA = T(0);
+    }
+    R W, E;
+    west_east<T, CPL>(hC, eC, eC, W, E);
+    __syncthreads();
+    R Sr, Nr;
+    if (w == 0) Sr = has_s ? hjoin(zm_load(rb, 0, s.lane), zm_load(rb, 1, s.lane)) : zr;
+    else Sr = zm_load(xb, w, s.lane);
+    if (w == kWavesPerTile - 1) Nr = has_n ? hjoin(zm_load(rb, 2, s.lane), zm_load(rb, 3, s.lane)) : zr;
+    else Nr = zm_load(xb, w + 2, s.lane);
     if (live) comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
     hB = hC;
     hC = hA;
@@ -1420,20 +1537,34 @@ __device__ __forceinline__ void body_cg1(const PassArgs& a, int t, const Sc& sc,
     T r, po;
   };
   const EdgeAddr ea = edge_addr2<CPL>(s, g);
-  walk<T, CPL, CG1_PREFETCH, OP, true, ZX_EDGE>(
-      g, s,
-      [=](size_t off) {
-        Raw v;
-        v.r = ldrow<T, CPL>(Rv + off + s.c);
-        v.po = ldrow<T, CPL>(Po + off + s.c);  // ignored on the first iteration
-        return v;
-      },
-      [=](const Raw& v) {
-        R h;
+  auto hload = [=](size_t off) {
+    Raw v;
+    v.r = ldrow<T, CPL>(Rv + off + s.c);
+    v.po = ldrow<T, CPL>(Po + off + s.c);  // ignored on the first iteration
+    return v;
+  };
+  auto hmake = [=](const Raw& v) {
+    R h;
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) h.e[k] = first ? v.r.e[k] : fma(be, v.po.e[k], v.r.e[k]);
-        return h;
-      },
+    for (int k = 0; k < CPL; ++k) h.e[k] = first ? v.r.e[k] : fma(be, v.po.e[k], v.r.e[k]);
+    return h;
+  };
+  auto walk_cg1 = [&](auto eload, auto emake, auto point, auto comp) {
+    if constexpr (OP == 1) {
+      auto hpart = [=](size_t off, int k) { return ldrow<T, CPL>((k ? Po : Rv) + off + s.c); };
+      auto hjoin = [=](const R& r, const R& po) {
+        Raw v;
+        v.r = r;
+        v.po = po;
+        return hmake(v);
+      };
+      zwalk_split<T, CPL, CG1_PREFETCH>(g, s, hload, hmake, hpart, hjoin, eload, emake, point,
+                                        comp);
+    } else {
+      walk<T, CPL, CG1_PREFETCH, OP, true>(g, s, hload, hmake, eload, emake, point, comp);
+    }
+  };
+  walk_cg1(
       [=](size_t off) {
         RawE v;
 #if EDGE_MASKED

@@ -102,3 +102,35 @@ def test_model_catches_a_wrong_slot():
         buf[w + 1] = v["y"] if v["live"] else None
     wrong_north = buf[1 + 1]  # wavefront 1 reading slot w + 1: its own row
     assert wrong_north != views[1]["y"] + 1
+
+
+def split_view(ty, w, ny_plane):
+    """The split form of classic pass 1: wavefront w loads vector w & 1 of the
+    tile's outer row y0 - 1 (w < 2) or y0 + 4 (w >= 2), clamped to a row of the
+    plane when that row lies outside it."""
+    y = ty * WAVES + w
+    y0 = y - w
+    yl = y if y < ny_plane else ny_plane - 1
+    yo = y0 - 1 if w < 2 else y0 + WAVES
+    yoc = yo if 0 <= yo < ny_plane else yl
+    return dict(y0=y0, yo=yo, yoc=yoc, part=w & 1)
+
+
+@pytest.mark.parametrize("ny_plane", [1, 2, 3, 4, 5, 7, 8, 9, 13, 40, 64, 257])
+def test_split_outer_rows_model(ny_plane):
+    nty = (ny_plane + WAVES - 1) // WAVES
+    for ty in range(nty):
+        views = [split_view(ty, w, ny_plane) for w in range(WAVES)]
+        y0 = views[0]["y0"]
+        # raw slot w holds (row, vector) = (yoc, part) of wavefront w
+        raw = [(v["yoc"], v["part"]) for v in views]
+        for v in views:
+            assert 0 <= v["yoc"] < ny_plane
+        # wavefront 0 joins slots 0 and 1: both vectors of row y0 - 1, when it exists
+        if y0 > 0:
+            assert raw[0] == (y0 - 1, 0) and raw[1] == (y0 - 1, 1)
+        # wavefront 3 joins slots 2 and 3: both vectors of row y0 + 4, when it exists
+        if y0 + WAVES < ny_plane:
+            assert raw[2] == (y0 + WAVES, 0) and raw[3] == (y0 + WAVES, 1)
+        # every wavefront issues exactly one outer-row load per plane
+        assert len(raw) == WAVES
