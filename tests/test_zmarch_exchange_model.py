@@ -10,7 +10,10 @@ not a multiple of 4, single rows, single planes):
     written by exactly one wavefront per plane;
   - every row a wavefront loads lies inside the plane and every plane inside
     the grid, including the wavefronts past the plane's last row;
-  - the four wavefronts of a tile pass the same number of barriers.
+  - the four wavefronts of a tile pass the same number of barriers;
+  - in the split form of classic pass 1 (one vector row of the outer rows per
+    wavefront), wavefronts 0 and 3 receive both vectors of rows y0 - 1 and
+    y0 + 4, and every wavefront issues one outer load.
 The model follows the walker's index arithmetic step by step (tile ->
 in-plane row, planes of the tile, clamped rows, slot numbers)."""
 import pytest
