@@ -139,8 +139,9 @@ typedef struct {
                               from their definitions, after which the iteration
                               continues (the remedy of Cools et al. for the
                               accuracy Algorithm 2's recurrences lose); FP64, 2D
-                              (either operator), precond 0, cg_solve only; the
-                              solve runs on the multi-work-group passes        */
+                              (either operator), precond 0; alone, in batches and
+                              served (bitwise as alone); the solve runs on the
+                              multi-work-group passes                          */
   const double* kx;        /* NULL (with ky NULL): the constant-coefficient operators
                               above.  Else the variable-coefficient 5-point operator,
                               the other structured-grid case Section I names beside
@@ -247,8 +248,8 @@ int cg_solve(cg_ctx* ctx, const cg_problem* prob, cg_result* res);
  * Solves are admitted in order while their footprint fits the arena and a
  * slot is free.  Each result is bitwise the one cg_solve gives.  Returns the
  * worst per-solve status; results[i] holds each outcome.  A breakdown of one
- * solve does not disturb the others.  Residual-replacement problems are
- * CG_E_INVALID here (cg_solve takes them). */
+ * solve does not disturb the others.  Residual-replacement problems step
+ * through the replacement's four passes on the same engine. */
 int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* results);
 
 /* Serving: queue one request (non-blocking).  A scheduler thread admits
@@ -259,7 +260,7 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
  * (cg_config.stream) has passed the point of this call; x is written before
  * cg_poll returns the final status.  CG_E_NOMEM if its footprint exceeds
  * arena_bytes; CG_E_DEVICE if the ordering event cannot be recorded;
- * CG_E_INVALID for the problems cg_solve_batch rejects. */
+ * CG_E_INVALID for the problems cg_solve rejects. */
 int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket);
 /* CG_PENDING, or the final status (then *res is filled and the ticket is
  * released). */

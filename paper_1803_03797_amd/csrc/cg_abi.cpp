@@ -64,8 +64,6 @@ int cg_solve_batch(cg_ctx* ctx, const cg_problem* probs, int32_t n, cg_result* r
   for (int32_t i = 0; i < n; ++i) {
     int rc = cgr::validate(&probs[i]);
     if (rc) return rc;
-    // residual replacement: cg_solve only
-    if (probs[i].rr_period) return CG_E_INVALID;
     q[i] = cgr::resolve_precision(probs[i]);
   }
   Ctx* c = C(ctx);
@@ -78,7 +76,6 @@ int cg_submit(cg_ctx* ctx, const cg_problem* prob, uint64_t* ticket) {
   if (!ctx || !ticket) return CG_E_INVALID;
   int rc = cgr::validate(prob);
   if (rc) return rc;
-  if (prob->rr_period) return CG_E_INVALID;  // cg_solve only
   const cg_problem q = cgr::resolve_precision(*prob);
   return cgr_server_submit(C(ctx), &q, ticket);
 }

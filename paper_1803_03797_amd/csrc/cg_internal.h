@@ -119,6 +119,8 @@ enum : int32_t {
   K_CHEBF,        // refinement, preconditioned inner solve: z = p_s(A) r in FP32
                   // after the inner stop test on (r,r); slot (r,z) in the tiles
                   // of K_CHEB
+  K_RRQ,          // residual replacement on the step engine: q = A p; no slots
+  K_RRZ,          // residual replacement on the step engine: z = A q; no slots
   K_NKINDS
 };
 
@@ -189,6 +191,7 @@ struct alignas(64) Slot {
   int32_t cheb_rows;   // rows of a Chebyshev item / partial tile
   int32_t cheb_tiles;  // partials of the Chebyshev pass
   int32_t cheb_items;  // Chebyshev items of one pass (the step's items number them)
+  int32_t rr_period;   // pipelined: residual replacement every rr_period iterations; 0 none
   const double* cheb;  // c0, c1[s-1], c2[s-1]
   double* u;           // preconditioned pipelined: u = M^-1 r
   double* sv;          //                           s

@@ -335,6 +335,8 @@ __device__ __forceinline__ bool transition(State& s, const double* sum, Sc& sc) 
     return transition<K_CG2F>(s, sum, sc);
   } else if constexpr (KIND == K_APPLY || KIND == K_DOT || KIND == K_RESID) {
     return true;
+  } else if constexpr (KIND == K_RRQ || KIND == K_RRZ) {
+    return s.status == ST_RUNNING;
   } else if constexpr (KIND == K_INIT_R) {
     return s.status == ST_RUNNING;
   } else if constexpr (KIND == K_INIT_W) {
@@ -1772,13 +1774,15 @@ template <int KIND, int CPL, int OP = 0>
 __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc, double* lv) {
   static_assert(OP == 0 || KIND == K_INIT_R || KIND == K_RESID || KIND == K_INIT_W ||
                     KIND == K_APPLY || KIND == K_DOT || KIND == K_PCG || KIND == K_PCGX ||
-                    KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X,
+                    KIND == K_CG1 || KIND == K_CG2 || KIND == K_CG2X || KIND == K_RRQ ||
+                    KIND == K_RRZ,
                 "no form of this pass for the operator");
   if constexpr (OP != 0) {
     if constexpr (KIND == K_INIT_R) body_residual<CPL, true, OP>(a, t, lv);
     else if constexpr (KIND == K_RESID) body_residual<CPL, false, OP>(a, t, lv);
     else if constexpr (KIND == K_INIT_W) body_apply<CPL, true, OP>(a, t, lv);
-    else if constexpr (KIND == K_APPLY) body_apply<CPL, false, OP>(a, t, lv);
+    else if constexpr (KIND == K_APPLY || KIND == K_RRQ || KIND == K_RRZ)
+      body_apply<CPL, false, OP>(a, t, lv);
     else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
     else if constexpr (KIND == K_PCG) body_pcg<CPL, false, OP>(a, t, sc, lv);
     else if constexpr (KIND == K_PCGX) body_pcg<CPL, true, OP>(a, t, sc, lv);
@@ -1792,7 +1796,8 @@ __device__ __forceinline__ void run_body(const PassArgs& a, int t, const Sc& sc,
   else if constexpr (KIND == K_INIT_W) body_apply<CPL, true>(a, t, lv);
   else if constexpr (KIND == K_INIT_WU) body_init_wu<CPL>(a, t, lv);
   else if constexpr (KIND == K_PPCG) body_ppcg<CPL>(a, t, sc, lv);
-  else if constexpr (KIND == K_APPLY) body_apply<CPL, false>(a, t, lv);
+  else if constexpr (KIND == K_APPLY || KIND == K_RRQ || KIND == K_RRZ)
+    body_apply<CPL, false>(a, t, lv);
   else if constexpr (KIND == K_DOT) body_dot<CPL>(a, t, lv);
   else if constexpr (KIND == K_PCG) body_pcg<CPL, false>(a, t, sc, lv);
   else if constexpr (KIND == K_PCGX) body_pcg<CPL, true>(a, t, sc, lv);
@@ -2942,13 +2947,18 @@ __device__ __forceinline__ bool step_transition(State& s, const double* sum, Sc&
 // pipelined variant K_CHEB and K_INIT_WU once, then K_CHEBW, K_PPCG; the
 // refinement's inner solve K_CHEBF, K_CG1F, K_CG2F.
 __device__ __forceinline__ int next_kind(int kind, bool ran, const State& s, int variant,
-                                         int refined, int precond) {
+                                         int refined, int precond, int rr_period = 0) {
   const int stop = s.status == ST_ZERO_RHS ? K_DONE : K_RESID;
   switch (kind) {
     case K_INIT_R:
       return precond ? K_CHEB : variant == 1 ? K_INIT_W : K_CG1;
     case K_INIT_W: return ran ? K_PCG : K_DONE;
-    case K_PCG: return ran ? K_PCG : stop;
+    // residual replacement after every rr_period-th iteration (even, so x is
+    // current): q = A p, z = A q, then r = b - A x and w = A r with their sums
+    case K_PCG:
+      return !ran ? stop : (rr_period > 0 && s.k % rr_period == 0) ? K_RRQ : K_PCG;
+    case K_RRQ: return ran ? K_RRZ : stop;
+    case K_RRZ: return ran ? K_INIT_R : stop;
     case K_CHEB: return ran ? (variant == 1 ? K_INIT_WU : K_CG1) : stop;
     case K_INIT_WU: return ran ? K_CHEBW : stop;
     case K_CHEBW: return ran ? K_PPCG : stop;
@@ -2995,8 +3005,8 @@ __device__ __forceinline__ PassArgs slot_args(const Slot& S, int m, int k0, int 
   a.pf_in = (KIND == K_CG2F) ? S.PF[(kin0 + 1) & 1] : S.PF[kin0 & 1];
   a.pf_out = S.PF[(kin0 + 1) & 1];
   a.pf_prev = S.PF[kin0 & 1];
-  a.u = nullptr;
-  a.y = nullptr;
+  a.u = (KIND == K_RRQ) ? S.p : (KIND == K_RRZ) ? S.q : nullptr;
+  a.y = (KIND == K_RRQ) ? S.q : (KIND == K_RRZ) ? S.z : nullptr;
   a.rev = 0;
   a.cheb_s = S.precond;
   a.cheb_rows = S.cheb_rows;
@@ -3039,7 +3049,7 @@ __device__ __forceinline__ void step_item(const Slot& S, const Item& it, int m, 
   else run = transition_x<KIND>(s, sum, sc, flush);
   if (it.t0 == 0 && threadIdx.x == 0) {
     State o = s;
-    o.kind = next_kind(KIND, run, s, S.variant, S.refined, S.precond);
+    o.kind = next_kind(KIND, run, s, S.variant, S.refined, S.precond, S.rr_period);
     *S.S[(m + 1) & 1] = o;
   }
   if (!run && !flush) return;
@@ -3112,6 +3122,8 @@ __global__ __launch_bounds__(kGroup, 3) void k_step(const Slot* slots, const Ite
         case K_INIT_R: step_item<K_INIT_R, 2>(S, it, m, s, lds, rev); break;
         case K_INIT_W: step_item<K_INIT_W, 2>(S, it, m, s, lds, rev); break;
         case K_PCG: step_item<K_PCG, 2>(S, it, m, s, lds, rev); break;
+        case K_RRQ: step_item<K_RRQ, 2>(S, it, m, s, lds, rev); break;
+        case K_RRZ: step_item<K_RRZ, 2>(S, it, m, s, lds, rev); break;
         case K_CG1: step_item<K_CG1, 2>(S, it, m, s, lds, rev); break;
         case K_CG2: step_item<K_CG2, 2>(S, it, m, s, lds, rev); break;
         case K_RESID: step_item<K_RESID, 2>(S, it, m, s, lds, rev); break;
@@ -3153,6 +3165,8 @@ __global__ __launch_bounds__(kGroup, OP == 1 ? 3 : 2) void k_step_op(const Slot*
       case K_INIT_R: step_item<K_INIT_R, 2, OP>(S, it, m, s, lds, rev); break;
       case K_INIT_W: step_item<K_INIT_W, 2, OP>(S, it, m, s, lds, rev); break;
       case K_PCG: step_item<K_PCG, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_RRQ: step_item<K_RRQ, 2, OP>(S, it, m, s, lds, rev); break;
+      case K_RRZ: step_item<K_RRZ, 2, OP>(S, it, m, s, lds, rev); break;
       case K_CG1: step_item<K_CG1, 2, OP>(S, it, m, s, lds, rev); break;
       case K_CG2: step_item<K_CG2, 2, OP>(S, it, m, s, lds, rev); break;
       case K_RESID: step_item<K_RESID, 2, OP>(S, it, m, s, lds, rev); break;

@@ -389,6 +389,8 @@ static const char* kind_name(int kind, int fp32g) {
     case K_PPCG: return "ppcg_pass";
     case K_APPLY: return "apply";
     case K_DOT: return "dot";
+    case K_RRQ: return "rr_q";
+    case K_RRZ: return "rr_z";
   }
   return "?";
 }

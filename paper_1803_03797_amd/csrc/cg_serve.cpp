@@ -190,6 +190,7 @@ class Engine {
     S.S[0] = w.S[0];
     S.S[1] = w.S[1];
     S.precond = w.pl.precond;
+    S.rr_period = w.pl.rr_period;
     if (w.pl.precond) {
       S.cheb_rows = w.pl.cheb_rows;
       S.cheb_tiles = w.pl.cheb_tiles;
@@ -406,7 +407,9 @@ class Engine {
   // 3 maxit + 5 (maxit + 1) plus the final RESID and REF_SCALE.
   static int64_t step_bound(const cg_problem& p, bool refined, int precond) {
     const int64_t m = p.maxit;
-    return refined ? (precond ? 8 * m + 32 : 6 * m + 32) : precond ? 3 * m + 32 : 2 * m + 32;
+    // residual replacement adds four passes per rr_period iterations
+    const int64_t rr = p.rr_period > 0 ? 4 * (m / p.rr_period + 1) : 0;
+    return (refined ? (precond ? 8 * m + 32 : 6 * m + 32) : precond ? 3 * m + 32 : 2 * m + 32) + rr;
   }
 
   // Chebyshev items of one pass of a preconditioned solve (as k_cheb and

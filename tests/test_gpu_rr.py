@@ -2,7 +2,8 @@
 every rr_period iterations the library recomputes q = A p, z = A q (stencil
 passes), r = b - A x and w = A r (the initial-residual passes, with their
 sums), bitwise the oracle's pipelined CG with the same replacement in the
-library's order, on the 5-point and the variable-coefficient operators."""
+library's order, on the 5-point and the variable-coefficient operators,
+alone, in batches and served."""
 import sys
 
 import numpy as np
@@ -103,6 +104,62 @@ def test_full_size_lockstep(ctx, torch):
     np.testing.assert_array_equal(xd.cpu().numpy(), xo)
 
 
+def test_batch_and_served_with_replacement_match_alone(ctx):
+    """Pipelined solves with residual replacement (both operators, periods 2 to
+    50, a single column among them) beside plain ones, batched and served on
+    the step engine: each result bitwise the solve alone, and the replaced
+    ones bitwise the oracle's replaced run in the library's order."""
+    import time
+    rng = np.random.default_rng(61)
+    # (nx, ny, rr_period, variable coefficients)
+    mix = [(300, 200, 4, False), (129, 67, 0, False), (513, 257, 10, False),
+           (256, 256, 50, True), (100, 100, 2, False), (40, 30, 6, True), (1, 77, 4, False),
+           (64, 64, 0, True)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny, _, _ in mix]
+    ks = [workloads.vc_faces(nx, ny) if vc else (None, None) for nx, ny, _, vc in mix]
+
+    def prob(k, x):
+        nx, ny, per, vc = mix[k]
+        return cg.make_problem(bs[k], x, nx, ny, tol=1e-10, maxit=20000, variant=PIPE,
+                               rr_period=per, kx=ks[k][0], ky=ks[k][1])
+    xb = [np.zeros_like(b) for b in bs]
+    say("batch with residual replacement:", len(mix))
+    rc, res = ctx.cg_solve_batch([prob(k, x) for k, x in enumerate(xb)])
+    xv = [np.zeros_like(b) for b in bs]
+    tickets = [ctx.cg_submit(prob(k, x)) for k, x in enumerate(xv)]
+    served = {}
+    deadline = time.time() + 120
+    while len(served) < len(tickets) and time.time() < deadline:
+        for t in tickets:
+            if t not in served:
+                rc2, r2 = ctx.cg_poll(t)
+                if rc2 != cg.CG_PENDING:
+                    served[t] = (rc2, cg.cg_result.from_buffer_copy(r2))
+        time.sleep(0.001)
+    assert len(served) == len(tickets)
+    for k, (nx, ny, per, vc) in enumerate(mix):
+        xa = np.zeros_like(bs[k])
+        rca, ra = ctx.cg_solve(prob(k, xa))
+        rcs, rs = served[tickets[k]]
+        say("  %dx%d rr %d vc %d: batch %d served %d alone %d iterations (status %d)" %
+            (nx, ny, per, vc, res[k].iterations, rs.iterations, ra.iterations, rca))
+        assert res[k].status == rca == rcs
+        assert res[k].iterations == rs.iterations == ra.iterations
+        np.testing.assert_array_equal(xb[k], xa)
+        np.testing.assert_array_equal(xv[k], xa)
+        assert res[k].rel_res_true == rs.rel_res_true == ra.rel_res_true
+        if per:
+            o = order(ctx, nx, ny, vc=vc)
+            if vc:
+                xo, ro = oracle.cg_vc(bs[k], nx, ny, ks[k][0], ks[k][1], variant=PIPE, tol=1e-10,
+                                      maxit=20000, mode=MODE_CANONICAL, order=o, rr_period=per)
+            else:
+                xo, ro = oracle.cg(bs[k], nx, ny, variant=PIPE, tol=1e-10, maxit=20000,
+                                   mode=MODE_CANONICAL, order=o, rr_period=per)
+            assert ro.status == rca and ro.iterations == ra.iterations
+            np.testing.assert_array_equal(xa, xo)
+
+
 def test_rejections(ctx):
     b = np.ones((20, 30))
     x = np.zeros_like(b)
@@ -111,8 +168,7 @@ def test_rejections(ctx):
                dict(rr_period=4, variant=PIPE, precond=2)):
         with pytest.raises(cg.CGError):
             ctx.solve(b, x, 30, 20, **kw)
-    p = cg.make_problem(b, x, 30, 20, variant=PIPE, rr_period=4)
-    with pytest.raises(cg.CGError):
-        ctx.cg_solve_batch([p])
-    with pytest.raises(cg.CGError):
-        ctx.cg_submit(p)
+        with pytest.raises(cg.CGError):
+            ctx.cg_solve_batch([cg.make_problem(b, x, 30, 20, **kw)])
+        with pytest.raises(cg.CGError):
+            ctx.cg_submit(cg.make_problem(b, x, 30, 20, **kw))
