@@ -160,6 +160,34 @@ def test_batch_and_served_with_replacement_match_alone(ctx):
             np.testing.assert_array_equal(xa, xo)
 
 
+def test_batch_fixed_iterations_ending_on_a_replacement(ctx):
+    """tol = 0 runs whose last iteration is a replacement point (maxit a
+    multiple of the period) or not: batched, each equals its solve alone in x,
+    status, iterations and both residuals (the recursive one comes from the
+    replaced r when the replacement follows the last iteration)."""
+    rng = np.random.default_rng(67)
+    # (nx, ny, rr_period, maxit)
+    mix = [(300, 200, 4, 40), (129, 67, 10, 71), (40, 30, 2, 6), (513, 257, 10, 40),
+           (1, 77, 4, 8)]
+    bs = [rng.uniform(-1, 1, (ny, nx)) for nx, ny, _, _ in mix]
+
+    def prob(k, x):
+        nx, ny, per, m = mix[k]
+        return cg.make_problem(bs[k], x, nx, ny, tol=0.0, maxit=m, variant=PIPE, rr_period=per)
+    xb = [np.zeros_like(b) for b in bs]
+    say("batch of fixed-iteration replaced solves:", len(mix))
+    rc, res = ctx.cg_solve_batch([prob(k, x) for k, x in enumerate(xb)])
+    for k, (nx, ny, per, m) in enumerate(mix):
+        xa = np.zeros_like(bs[k])
+        rca, ra = ctx.cg_solve(prob(k, xa))
+        say("  %dx%d rr %d maxit %d: batch %d alone %d (status %d)" %
+            (nx, ny, per, m, res[k].iterations, ra.iterations, rca))
+        assert res[k].status == rca and res[k].iterations == ra.iterations
+        np.testing.assert_array_equal(xb[k], xa)
+        assert res[k].rel_res_recursive == ra.rel_res_recursive
+        assert res[k].rel_res_true == ra.rel_res_true
+
+
 def test_rejections(ctx):
     b = np.ones((20, 30))
     x = np.zeros_like(b)
