@@ -401,9 +401,9 @@ static const char* kind_name(int kind, int fp32g) {
 hipError_t Ctx::pass(int kind, int fp32g, const PassArgs& a, int grid, bool check) {
   if (!prof || capturing) return launch_pass(kind, fp32g, a, grid, st);
   hipEvent_t e0 = event(), e1 = event();
-  hipEventRecord(e0, st);
+  (void)hipEventRecord(e0, st);
   hipError_t rc = launch_pass(kind, fp32g, a, grid, st);
-  hipEventRecord(e1, st);
+  (void)hipEventRecord(e1, st);
   // the variable-coefficient operator also reads its four coefficients per
   // unknown in every pass that applies it
   const int64_t dof = (int64_t)a.g.nx * a.g.ny;
@@ -681,10 +681,10 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
     HIPCHK(e2);
     hipGraphExec_t ge;
     hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     HIPCHK(e3);
     if (c.graphs.size() > 64) {
-      for (auto& kv : c.graphs) hipGraphExecDestroy(kv.second);
+      for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
       c.graphs.clear();
     }
     it = c.graphs.emplace(key, ge).first;
@@ -703,7 +703,7 @@ static int run_chunk(Ctx& c, Work& w, int iters) {
 void Ctx::forget_graphs(const void* mem) {
   for (auto it = graphs.begin(); it != graphs.end();) {
     if (it->first.mem == mem) {
-      hipGraphExecDestroy(it->second);
+      (void)hipGraphExecDestroy(it->second);
       it = graphs.erase(it);
     } else {
       ++it;
@@ -901,11 +901,11 @@ static int solve_wg(Ctx& c, Work& w, const cg_problem* p, State& s) {
   if (c.prof) {
     e0 = c.event();
     e1 = c.event();
-    hipEventRecord(e0, c.st);
+    (void)hipEventRecord(e0, c.st);
   }
   HIPCHK(launch_solve_wg(p->variant, a, c.st));
   if (c.prof) {
-    hipEventRecord(e1, c.st);
+    (void)hipEventRecord(e1, c.st);
     c.pending.push_back({e0, e1, "solve_wg", 0.0});
   }
   w.m = 1;
@@ -927,11 +927,11 @@ static int solve_fixed(Ctx& c, Work& w, const cg_problem* p, State& s) {
   if (c.prof) {
     e0 = c.event();
     e1 = c.event();
-    hipEventRecord(e0, c.st);
+    (void)hipEventRecord(e0, c.st);
   }
   HIPCHK(launch_solve_fixed(p->variant, a, w.pl.fx_threads, c.st));
   if (c.prof) {
-    hipEventRecord(e1, c.st);
+    (void)hipEventRecord(e1, c.st);
     c.pending.push_back({e0, e1, "solve_fixed", 0.0});
   }
   w.m = 1;
@@ -946,11 +946,11 @@ static int solve_rr(Ctx& c, Work& w, const cg_problem* p, State& s) {
   if (c.prof) {
     e0 = c.event();
     e1 = c.event();
-    hipEventRecord(e0, c.st);
+    (void)hipEventRecord(e0, c.st);
   }
   HIPCHK(launch_solve_rr(p->variant, a, w.pl.rr_threads, c.st));
   if (c.prof) {
-    hipEventRecord(e1, c.st);
+    (void)hipEventRecord(e1, c.st);
     c.pending.push_back({e0, e1, "solve_rr", 0.0});
   }
   w.m = 1;
@@ -1328,20 +1328,20 @@ int Ctx::init(const cg_config* cfg) {
 }
 
 Ctx::~Ctx() {
-  hipSetDevice(device);
-  if (st) hipStreamSynchronize(st);
-  if (side) hipStreamSynchronize(side);
-  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  (void)hipSetDevice(device);
+  if (st) (void)hipStreamSynchronize(st);
+  if (side) (void)hipStreamSynchronize(side);
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto& pr : pending) {
-    hipEventDestroy(pr.a);
-    hipEventDestroy(pr.b);
+    (void)hipEventDestroy(pr.a);
+    (void)hipEventDestroy(pr.b);
   }
-  for (auto e : ev_free) hipEventDestroy(e);
-  if (user_ev) hipEventDestroy(user_ev);
-  if (host_state) hipHostFree(host_state);
-  if (own_arena) hipFree(own_arena);
-  if (side) hipStreamDestroy(side);
-  if (st) hipStreamDestroy(st);
+  for (auto e : ev_free) (void)hipEventDestroy(e);
+  if (user_ev) (void)hipEventDestroy(user_ev);
+  if (host_state) (void)hipHostFree(host_state);
+  if (own_arena) (void)hipFree(own_arena);
+  if (side) (void)hipStreamDestroy(side);
+  if (st) (void)hipStreamDestroy(st);
 }
 
 }  // namespace cgr

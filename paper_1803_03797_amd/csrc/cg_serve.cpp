@@ -36,7 +36,7 @@ struct Job {
   Job(const Job&) = delete;
   Job& operator=(const Job&) = delete;
   ~Job() {
-    if (ready) hipEventDestroy(ready);
+    if (ready) (void)hipEventDestroy(ready);
   }
   cg_problem p;
   hipEvent_t ready = nullptr;  // served request: the caller's stream at submission
@@ -56,22 +56,22 @@ class Engine {
 
   explicit Engine(Ctx& c, int nslots) : c_(c), n_(std::max(1, nslots)) {}
   ~Engine() {
-    if (rr_pending_) hipStreamSynchronize(c_.side);
-    if (rr_ev_) hipEventDestroy(rr_ev_);
-    if (stage_ev_) hipEventDestroy(stage_ev_);
-    if (h_rr_idx_) hipHostFree(h_rr_idx_);
-    if (graph_) hipGraphExecDestroy(graph_);
+    if (rr_pending_) (void)hipStreamSynchronize(c_.side);
+    if (rr_ev_) (void)hipEventDestroy(rr_ev_);
+    if (stage_ev_) (void)hipEventDestroy(stage_ev_);
+    if (h_rr_idx_) (void)hipHostFree(h_rr_idx_);
+    if (graph_) (void)hipGraphExecDestroy(graph_);
     for (Job* j : slot_job_)
       if (j) c_.arena.release(j->w.mem);
     if (ctrl_) c_.arena.release(ctrl_);
-    if (h_slots_) hipHostFree(h_slots_);
-    if (h_items_) hipHostFree(h_items_);
-    if (h_idx_) hipHostFree(h_idx_);
-    if (h_states_) hipHostFree(h_states_);
-    if (h_admit_) hipHostFree(h_admit_);
-    if (h_coef_) hipHostFree(h_coef_);
-    if (h_citems_) hipHostFree(h_citems_);
-    if (h_step_) hipHostFree(h_step_);
+    if (h_slots_) (void)hipHostFree(h_slots_);
+    if (h_items_) (void)hipHostFree(h_items_);
+    if (h_idx_) (void)hipHostFree(h_idx_);
+    if (h_states_) (void)hipHostFree(h_states_);
+    if (h_admit_) (void)hipHostFree(h_admit_);
+    if (h_coef_) (void)hipHostFree(h_coef_);
+    if (h_citems_) (void)hipHostFree(h_citems_);
+    if (h_step_) (void)hipHostFree(h_step_);
   }
 
   int init() {
@@ -156,7 +156,7 @@ class Engine {
         rc = CG_E_DEVICE;
     }
     if (rc) {
-      hipStreamSynchronize(c_.st);
+      (void)hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
       return rc;
     }
@@ -201,7 +201,7 @@ class Engine {
       S.mv = w.mv;
     }
     if (hipMemcpyAsync(d_slots_ + slot, &S, sizeof(Slot), hipMemcpyHostToDevice, c_.st)) {
-      hipStreamSynchronize(c_.st);
+      (void)hipStreamSynchronize(c_.st);
       c_.arena.release(j->w.mem);
       return CG_E_DEVICE;
     }
@@ -254,7 +254,7 @@ class Engine {
         if (c_.prof) {
           f0 = c_.event();
           f1 = c_.event();
-          hipEventRecord(f0, c_.side);
+          (void)hipEventRecord(f0, c_.side);
         }
         // one launch per run of equal (variant, unknowns per thread)
         for (int g0 = 0; g0 < nf;) {
@@ -266,7 +266,7 @@ class Engine {
           g0 = g1;
         }
         if (c_.prof) {
-          hipEventRecord(f1, c_.side);
+          (void)hipEventRecord(f1, c_.side);
           c_.pending.push_back({f0, f1, "solve_fixed_many", 0.0});
         }
       }
@@ -280,7 +280,7 @@ class Engine {
     if (c_.prof) {
       e0 = c_.event();
       e1 = c_.event();
-      hipEventRecord(e0, c_.st);
+      (void)hipEventRecord(e0, c_.st);
     }
     // the chunk's base step, read by every launch of the chunk on the device
     int* hs = h_step_ + (ring_++ % kStepRing);
@@ -288,7 +288,7 @@ class Engine {
     if (hipMemcpyAsync(d_step_, hs, sizeof(int), hipMemcpyHostToDevice, c_.st)) return CG_E_DEVICE;
     const bool use_graph = c_.graph_chunk > 0 && steps == c_.step_chunk_for(this_is_serving_);
     if (use_graph && (!graph_ || graph_steps_ != steps || graph_mask_ != cheb_mask_)) {
-      if (graph_) hipGraphExecDestroy(graph_);
+      if (graph_) (void)hipGraphExecDestroy(graph_);
       graph_ = nullptr;
       hipGraph_t g;
       if (hipStreamBeginCapture(c_.st, hipStreamCaptureModeThreadLocal)) return CG_E_DEVICE;
@@ -297,7 +297,7 @@ class Engine {
       hipError_t e2 = hipStreamEndCapture(c_.st, &g);
       if (e || e2) return CG_E_DEVICE;
       e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e) {
         graph_ = nullptr;
         return CG_E_DEVICE;
@@ -312,7 +312,7 @@ class Engine {
         if (launch_one_step(k) != hipSuccess) return CG_E_DEVICE;
     }
     if (c_.prof) {
-      hipEventRecord(e1, c_.st);
+      (void)hipEventRecord(e1, c_.st);
       c_.pending.push_back({e0, e1, "batch_steps", 0.0});
     }
     step_ += steps;
@@ -369,7 +369,7 @@ class Engine {
 
   // Fails every resident solve (used after a device error).
   void abandon(std::vector<Job*>& done, int rc) {
-    if (rr_pending_) hipStreamSynchronize(c_.side);
+    if (rr_pending_) (void)hipStreamSynchronize(c_.side);
     rr_pending_ = false;
     rr_new_.clear();
     fx_new_.clear();
