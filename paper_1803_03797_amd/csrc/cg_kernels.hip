@@ -924,24 +924,26 @@ __device__ __forceinline__ void walk2d(const Geo& g, const Strip& s, HLoad hload
 
 // The 7-point walker's in-plane neighbours, rows y - 1 and y + 1 of the plane
 // a wavefront is at, are the rows the tile's other wavefronts hold at the
-// same step: each wavefront publishes its row in an LDS exchange buffer,
-// wavefronts 0 and 3 also the tile's outer rows y0 - 1 and y0 + 4, and after
-// one barrier per plane each reads its two neighbours.  The outer-row loads:
-//   ZX_EDGE  issued by wavefronts 0 and 3 only;
-//   ZX_ALL   issued by every wavefront (those of wavefronts 1 and 2 read
-//            their own row and leave it unused), so that the loads of a
-//            step take no branch.
-// Which is faster depends on the pass (measured at 256^3): ZX_EDGE for the
-// odd pipelined pass, ZX_ALL for the others; classic pass 1, whose halo
-// vector costs two loads a row, takes zwalk_split below (86.2 -> 79.6 us by
-// rocprofv3 against ZX_EDGE; loading the neighbour rows in each wavefront
-// instead of any exchange ran it at 108.0 us).
-constexpr int ZX_EDGE = 1, ZX_ALL = 2;
+// same step: each wavefront publishes its row in an LDS exchange buffer and,
+// after one barrier per plane, reads its two neighbours.  The tile's outer
+// rows y0 - 1 and y0 + 4 come from loads, in one of three forms:
+//   ZX_EDGE  wavefronts 0 and 3 load them whole (zwalk_xch);
+//   ZX_HALF  every wavefront loads half of one, one value per lane
+//            (zwalk_half, halo vectors stored as is);
+//   classic pass 1, whose halo vector is formed from two vectors, splits
+//   them one vector row per wavefront (zwalk_split).
+// Measured at 256^3 (HIP events): ZX_HALF for the passes with one halo
+// vector (update_norm_nx 78.5 -> 73.3 us, pcg_pass 279.2 -> 277.7 us against
+// every wavefront loading a whole outer row), except the odd pipelined pass,
+// which runs 0.7 % faster with ZX_EDGE; zwalk_split took classic pass 1 from
+// 86.2 to 79.6 us (rocprofv3) against ZX_EDGE.  Loading the neighbour rows
+// in each wavefront instead of any exchange ran classic pass 1 at 108.0 us.
+constexpr int ZX_EDGE = 1, ZX_HALF = 2;
 
 // The exchange rows: two buffers (alternate planes) of six rows (the tile's
 // outer row y0 - 1, its four rows, its outer row y0 + 4) of one FP64 pair per
 // lane.
-__shared__ double zm_x[2 * (kWavesPerTile + 2) * kWave * 2];
+__shared__ __align__(16) double zm_x[2 * (kWavesPerTile + 2) * kWave * 2];
 
 __device__ __forceinline__ void zm_store(double* xb, int slot, int lane, const Row<double, 2>& v) {
   *reinterpret_cast<double2*>(xb + (slot * kWave + lane) * 2) = make_double2(v.e[0], v.e[1]);
@@ -955,13 +957,13 @@ __device__ __forceinline__ Row<double, 2> zm_load(const double* xb, int slot, in
   return v;
 }
 
-// The z-march with the exchange (ALLO: the ZX_ALL outer-row loads).  After one
-// barrier per plane every wavefront reads its two neighbours (zero outside
-// the plane).  A wavefront whose row lies past the plane still takes every
+// The z-march with the exchange, the outer rows loaded by wavefronts 0 and 3
+// (ZX_EDGE).  After one barrier per plane every wavefront reads its two
+// neighbours (zero outside the plane).  A wavefront whose row lies past the plane still takes every
 // step (its loads read a valid row, its exchange row is zero, it computes
 // nothing), so the four wavefronts pass the same barriers.
-template <typename T, int CPL, int PD, bool ALLO, class HLoad, class HMake, class ELoad,
-          class EMake, class Point, class Comp>
+template <typename T, int CPL, int PD, class HLoad, class HMake, class ELoad, class EMake,
+          class Point, class Comp>
 __device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
                                           ELoad eload, EMake emake, Point point, Comp comp) {
   static_assert(sizeof(T) == 8 && CPL == 2, "the 3D walker exchanges FP64 pairs");
@@ -1008,7 +1010,7 @@ __device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hl
     const int zp = min(z0 + k, z1 - 1);
     pt[k] = point(off(zp, y));
     qo[k] = q[k];  // (unused off the outer wavefronts)
-    if (ALLO || outer) qo[k] = hload(off(zp, yoc));
+    if (outer) qo[k] = hload(off(zp, yoc));
   }
   for (int z = z0; z < z1; ++z) {
     const size_t o = off(z, y);
@@ -1021,7 +1023,7 @@ __device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hl
     const int zp = min(z + PD, z1 - 1);
     const B pn = point(off(zp, y));
     RawH on = hn;
-    if (ALLO || outer) on = hload(off(zp, yoc));
+    if (outer) on = hload(off(zp, yoc));
     // this plane's rows into the exchange buffer
     double* xb = zm_x + ((z - z0) & 1) * ((kWavesPerTile + 2) * kWave * 2);
     zm_store(xb, w + 1, s.lane, live ? hC : zr);
@@ -1060,7 +1062,7 @@ __device__ __forceinline__ void zwalk_xch(const Geo& g, const Strip& s, HLoad hl
 
 // The raw halves of the tile's outer rows for zwalk_split: two buffers of
 // four rows (row y0 - 1's first and second vector, then row y0 + 4's).
-__shared__ double zm_r[2 * 4 * kWave * 2];
+__shared__ __align__(16) double zm_r[2 * 4 * kWave * 2];
 
 // The z-march of a pass whose halo vector is formed from two vectors (classic
 // pass 1: p = r + beta p_old).  As zwalk_xch, but the tile's two outer rows
@@ -1069,7 +1071,7 @@ __shared__ double zm_r[2 * 4 * kWave * 2];
 // barrier wavefront 0 joins row y0 - 1's halves into its south neighbour and
 // wavefront 3 row y0 + 4's into its north one, with the same arithmetic as
 // hmake.  Every wavefront then issues three row loads a plane (against four
-// for wavefronts 0 and 3 and two for 1 and 2 in zwalk_xch's ZX_EDGE form).
+// for wavefronts 0 and 3 and two for 1 and 2 in zwalk_xch).
 //   hpart(off, k) -> Row: vector k of the halo sources at offset off
 //   hjoin(a, b)   -> Row: hmake of the raw pair (a, b)
 template <typename T, int CPL, int PD, class HLoad, class HMake, class HPart, class HJoin,
@@ -1175,20 +1177,133 @@ __device__ __forceinline__ void zwalk_split(const Geo& g, const Strip& s, HLoad 
   }
 }
 
+// The tile's two outer rows for zwalk_half: two buffers of two rows of the
+// tile's 2 * kWave columns, in column order.
+__shared__ __align__(16) double zm_h[2 * 2 * 2 * kWave];
+
+// The z-march of a pass whose halo vector is stored as is (V).  As
+// zwalk_xch, but the tile's two outer rows cost one half-row load per
+// wavefront: wavefront w loads columns [64 (w & 1), 64 (w & 1) + 64) of the
+// tile's row y0 - 1 (w < 2) or y0 + 4 (w >= 2), one value per lane, into an
+// LDS row buffer; after the barrier wavefronts 0 and 3 read their outer
+// neighbour from it.  Every wavefront issues the same loads, with no branch.
+template <typename T, int CPL, int PD, class HLoad, class ELoad, class EMake, class Point,
+          class Comp>
+__device__ __forceinline__ void zwalk_half(const Geo& g, const Strip& s, const T* V, HLoad hload,
+                                           ELoad eload, EMake emake, Point point, Comp comp) {
+  static_assert(sizeof(T) == 8 && CPL == 2, "the 3D walker exchanges FP64 pairs");
+  using R = Row<T, CPL>;
+  using RawE = decltype(eload((size_t)0));
+  using B = decltype(point((size_t)0));
+  const size_t P = g.pitch;
+  const int pl = g.plane, nz = g.ny / pl;
+  const int w = __builtin_amdgcn_readfirstlane(s.wave);
+  const int z0 = s.z0, z1 = s.z1;
+  const bool live = s.y < pl;
+  const int y = live ? s.y : pl - 1;
+  const int y0 = s.y - w;  // the tile's first in-plane row
+  auto off = [&](int z, int yy) { return ((size_t)z * pl + yy) * P; };
+  // this lane's outer value: a column of the padded row (a row outside the
+  // plane is replaced by row y, whose value is then ignored)
+  const int yo = (w < 2) ? y0 - 1 : y0 + kWavesPerTile;
+  const int yoc = (yo >= 0 && yo < pl) ? yo : y;
+  const int hcol = s.ct + (w & 1) * kWave + s.lane;
+  const int hslot = (w >> 1) * (2 * kWave) + (w & 1) * kWave + s.lane;
+  const bool has_s = y0 > 0, has_n = y0 + kWavesPerTile < pl;  // for wavefronts 0 / 3
+  const int zmax = min(z1, nz - 1);  // last plane worth loading ahead
+  const Kc<T, CPL> kz{};
+  const R zr = zrow<T, CPL>();
+  __syncthreads();  // every wavefront has read the previous tile's exchange rows
+  R hB = zr;  // plane z - 1
+  {
+    const R v = hload(off(max(z0 - 1, 0), y));
+    if (z0 > 0) hB = v;
+  }
+  R hC = hload(off(z0, y));
+  T eC = emake(eload(off(z0, y)));
+  R q[PD];      // row y of planes z+1 .. z+PD
+  RawE qe[PD];
+  bool qv[PD];  // the plane exists (inside the grid, not past the tile's halo)
+  B pt[PD];     // point data of planes z .. z+PD-1
+  T qo[PD];     // this lane's outer value of planes z .. z+PD-1
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    const int zr1 = z0 + 1 + k;
+    qv[k] = zr1 <= zmax;
+    const size_t ro = off(min(zr1, zmax), y);
+    q[k] = hload(ro);
+    qe[k] = eload(ro);
+    const int zp = min(z0 + k, z1 - 1);
+    pt[k] = point(off(zp, y));
+    qo[k] = V[off(zp, yoc) + hcol];
+  }
+  for (int z = z0; z < z1; ++z) {
+    const size_t o = off(z, y);
+    // loads of the planes needed PD steps from now
+    const int zh = z + PD + 1;
+    const bool nv = zh <= zmax;
+    const size_t ho = off(min(zh, zmax), y);
+    const R hn = hload(ho);
+    const RawE en = eload(ho);
+    const int zp = min(z + PD, z1 - 1);
+    const B pn = point(off(zp, y));
+    const T on = V[off(zp, yoc) + hcol];
+    // this plane's rows and outer values into the exchange buffers
+    const int b = (z - z0) & 1;
+    double* xb = zm_x + b * ((kWavesPerTile + 2) * kWave * 2);
+    double* hb = zm_h + b * (2 * 2 * kWave);
+    zm_store(xb, w + 1, s.lane, live ? hC : zr);
+    hb[hslot] = qo[0];
+    // plane z + 1 enters the window
+    R hA = q[0];
+    T eA = emake(qe[0]);
+    if (!qv[0]) {
+      hA = zr;
+      eA = T(0);
+    }
+    R W, E;
+    west_east<T, CPL>(hC, eC, eC, W, E);
+    __syncthreads();
+    R Sr, Nr;
+    if (w == 0) Sr = has_s ? zm_load(hb, 0, s.lane) : zr;
+    else Sr = zm_load(xb, w, s.lane);
+    if (w == kWavesPerTile - 1) Nr = has_n ? zm_load(hb, 1, s.lane) : zr;
+    else Nr = zm_load(xb, w + 2, s.lane);
+    if (live) comp(o, Sr, hC, Nr, W, E, hB, hA, kz, pt[0]);
+    hB = hC;
+    hC = hA;
+    eC = eA;
+#pragma unroll
+    for (int k = 0; k + 1 < PD; ++k) {
+      q[k] = q[k + 1];
+      qe[k] = qe[k + 1];
+      qv[k] = qv[k + 1];
+      pt[k] = pt[k + 1];
+      qo[k] = qo[k + 1];
+    }
+    q[PD - 1] = hn;
+    qe[PD - 1] = en;
+    qv[PD - 1] = nv;
+    pt[PD - 1] = pn;
+    qo[PD - 1] = on;
+  }
+}
+
 // The entry point of every body, and the 7-point operator's walker: the
 // z-march (strip_of: the wavefront owns in-plane row y and walks it through
 // the tile's planes).  Plane z - 1 (behind), z and z + 1 (ahead) of row y are
-// the window, as rows j - 1, j, j + 1 are in 2D; ZX picks the form of the
-// outer-row loads.  comp gets S / N = rows y -/+ 1 (zero outside the
+// the window, as rows j - 1, j, j + 1 are in 2D (ZX_EDGE outer-row loads;
+// walk_plain takes zwalk_half, classic pass 1 zwalk_split).  comp gets S / N = rows y -/+ 1 (zero outside the
 // plane) and below / above = planes z -/+ 1 (zero outside the grid).
-template <typename T, int CPL, int PD, int OP, bool ALT = true, int ZX = ZX_ALL, class HLoad,
+template <typename T, int CPL, int PD, int OP, bool ALT = true, int ZX = ZX_EDGE, class HLoad,
           class HMake, class ELoad, class EMake, class Point, class Comp>
 __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, HMake hmake,
                                      ELoad eload, EMake emake, Point point, Comp comp) {
+  static_assert(OP != 1 || ZX == ZX_EDGE, "ZX_HALF is walk_plain's (it needs the halo vector)");
   if constexpr (OP != 1)
     walk2d<T, CPL, PD, OP, ALT>(g, s, hload, hmake, eload, emake, point, comp);
   else
-    zwalk_xch<T, CPL, PD, ZX == ZX_ALL>(g, s, hload, hmake, eload, emake, point, comp);
+    zwalk_xch<T, CPL, PD>(g, s, hload, hmake, eload, emake, point, comp);
 }
 
 #ifndef CG1_PREFETCH
@@ -1203,7 +1318,7 @@ __device__ __forceinline__ void walk(const Geo& g, const Strip& s, HLoad hload, 
 #endif
 
 // Loaders for a halo vector that is stored as is.
-template <typename T, int CPL, int OP, bool ALT = true, int ZX = ZX_ALL, class Point, class Comp>
+template <typename T, int CPL, int OP, bool ALT = true, int ZX = ZX_HALF, class Point, class Comp>
 __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T* V, Point point,
                                            Comp comp) {
   const EdgeAddr ea = edge_addr<CPL>(s, g);
@@ -1219,10 +1334,17 @@ __device__ __forceinline__ void walk_plain(const Geo& g, const Strip& s, const T
       },
       [=](T v) { return v; }, point, comp);
 #else
-  walk<T, CPL, WALK_PREFETCH, OP, ALT, ZX>(
-      g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
-      [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
-      [=](T v) { return ea.emask ? v : T(0); }, point, comp);
+  if constexpr (OP == 1 && ZX == ZX_HALF) {
+    zwalk_half<T, CPL, WALK_PREFETCH>(
+        g, s, V, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
+        [=](size_t off) { return V[off + ea.off]; }, [=](T v) { return ea.emask ? v : T(0); },
+        point, comp);
+  } else {
+    walk<T, CPL, WALK_PREFETCH, OP, ALT, ZX>(
+        g, s, [=](size_t off) { return ldrow<T, CPL>(V + off + c); },
+        [](const Row<T, CPL>& r) { return r; }, [=](size_t off) { return V[off + ea.off]; },
+        [=](T v) { return ea.emask ? v : T(0); }, point, comp);
+  }
 #endif
 }
 
@@ -1339,7 +1461,7 @@ __device__ __forceinline__ void body_pcg(const PassArgs& a, int t, const Sc& sc,
   for (int k = 0; k < CPL; ++k) a0[k] = a1[k] = 0.0;
   const int valid = g.nx - s.c;
   double *X = a.x, *Rv = a.r, *Z = a.z, *Q = a.q, *Pp = a.p, *Wo = a.w_out;
-  walk_plain<double, CPL, OP, false, XU ? ZX_ALL : ZX_EDGE>(
+  walk_plain<double, CPL, OP, false, XU ? ZX_HALF : ZX_EDGE>(
       g, s, a.w_in,
       [=](size_t off) {
         PcgRow<CPL> v;
