@@ -64,7 +64,7 @@ PCG_TRAFFIC_BYTES = 1646594743
 # (128 algorithmic bytes per unknown: 96 of vectors, 32 of coefficients).
 VC_TRAFFIC_BYTES = 2161653028
 # The same for pcg_pass of the 7-point operator at 256^3 (z-march tiles).
-CUBE_TRAFFIC_BYTES = 1629264775
+CUBE_TRAFFIC_BYTES = 1627106949
 # Fixed point (ALU-bound): exact 50 x 50-bit products per unknown and
 # iteration (classic: p = r + b p, x += a p, r -= a s, (p, s), (r, r);
 # pipelined: the six updates of z, q, p, x, r, w and (r, r), (w, r)), each
