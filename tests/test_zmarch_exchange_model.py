@@ -13,7 +13,10 @@ not a multiple of 4, single rows, single planes):
   - the four wavefronts of a tile pass the same number of barriers;
   - in the split form of classic pass 1 (one vector row of the outer rows per
     wavefront), wavefronts 0 and 3 receive both vectors of rows y0 - 1 and
-    y0 + 4, and every wavefront issues one outer load.
+    y0 + 4, and every wavefront issues one outer load;
+  - in the half-row form (half an outer row per wavefront), every buffer
+    position is written once and wavefronts 0 and 3 read their own columns
+    of rows y0 - 1 and y0 + 4.
 The model follows the walker's index arithmetic step by step (tile ->
 in-plane row, planes of the tile, clamped rows, slot numbers)."""
 import pytest
@@ -137,3 +140,36 @@ def test_split_outer_rows_model(ny_plane):
             assert raw[2] == (y0 + WAVES, 0) and raw[3] == (y0 + WAVES, 1)
         # every wavefront issues exactly one outer-row load per plane
         assert len(raw) == WAVES
+
+
+@pytest.mark.parametrize("ny_plane", [1, 2, 3, 4, 5, 7, 8, 9, 13, 40, 64, 257])
+def test_half_outer_rows_model(ny_plane):
+    """The half-row form: wavefront w loads columns 64 (w & 1) + lane of row
+    y0 - 1 (w < 2) or y0 + 4 (w >= 2) into buffer position
+    128 (w >> 1) + 64 (w & 1) + lane; wavefronts 0 and 3 then read their lane's
+    two columns 2 lane, 2 lane + 1 from rows 0 and 1 of the buffer."""
+    lanes, tile_cols = 64, 128
+    nty = (ny_plane + WAVES - 1) // WAVES
+    for ty in range(nty):
+        buf = [None] * (2 * tile_cols)
+        for w in range(WAVES):
+            y = ty * WAVES + w
+            y0 = y - w
+            yl = y if y < ny_plane else ny_plane - 1
+            yo = y0 - 1 if w < 2 else y0 + WAVES
+            yoc = yo if 0 <= yo < ny_plane else yl
+            assert 0 <= yoc < ny_plane
+            for lane in range(lanes):
+                col = (w & 1) * lanes + lane
+                slot = (w >> 1) * tile_cols + (w & 1) * lanes + lane
+                assert buf[slot] is None
+                buf[slot] = (yoc, col)
+        assert None not in buf
+        y0 = ty * WAVES
+        for lane in range(lanes):
+            s0, s1 = buf[2 * lane], buf[2 * lane + 1]
+            n0, n1 = buf[tile_cols + 2 * lane], buf[tile_cols + 2 * lane + 1]
+            if y0 > 0:
+                assert s0 == (y0 - 1, 2 * lane) and s1 == (y0 - 1, 2 * lane + 1)
+            if y0 + WAVES < ny_plane:
+                assert n0 == (y0 + WAVES, 2 * lane) and n1 == (y0 + WAVES, 2 * lane + 1)
